@@ -1,0 +1,635 @@
+"""FP64 reference implementation (oracle) of the method of "Effective and General
+Distance Computation for Approximate Nearest Neighbor Search".
+
+TEST INFRASTRUCTURE ONLY -- see the package docstring.  Plain, slow and written
+to be checked against the paper by eye.  Every floating-point step is FP64
+unless the step *is* a rounding to a storage format.
+
+What is computed (paper section in brackets):
+
+* exact KNN under the squared Euclidean distance            [Sec. II-A]
+* PCA rotation: centring, covariance, eigenvectors as rows  [Sec. IV-B, Thm. 1]
+* IVF lists by k-means, probe the N_probe nearest centroids [Sec. II-A, IVF]
+* the pruned refinement: per block of candidates, per stage of Delta_d
+  dimensions, the partial (PCA-projected) squared distance dis'_s is tested
+  with the learned linear classifier  m_s * dis'_s + beta_s > tau  and the
+  candidate is pruned, else refined; the result queue keeps the K best and tau
+  is its K-th distance                                       [Sec. V-A, V-B; Alg. 2 loop]
+* calibration: logistic regression per stage on (dis', tau) features with
+  KNN pairs as label 0 and pairs met in a query process as label 1, then the
+  bias is moved to reach a target recall of label 0          [Sec. V-A "Parameter
+  Learning", "Adaptive Adjustment"; Sec. VII-A implementation details]
+
+Readings of points the paper leaves open are listed in the design notes; the
+ones that change results are repeated next to the code that takes them.
+
+Parity status: every function here is pinned by tests under ``tests/`` that
+check it against closed forms, invariants, brute force or library routines
+(never against its own formula retyped).  Values printed in the paper's figures
+and tables cannot be reproduced (their datasets are absent): those are parity
+unpinned and no function here claims them.
+"""
+from __future__ import annotations
+
+import heapq
+import math
+
+import numpy as np
+
+# --------------------------------------------------------------------------------------
+# Counter-based random keys (SplitMix64, Steele, Lea & Flood, OOPSLA 2014).  Random
+# choices the method makes during fit (PCA sample, k-means init/sample, the label-1
+# subsample, the calibration sample) are "the m items with the smallest keys", keys
+# being SplitMix64 outputs of a counter.  The GPU library implements the same
+# published generator on its own.
+# --------------------------------------------------------------------------------------
+_M64 = (1 << 64) - 1
+TAG_PCA, TAG_KMEANS_INIT, TAG_KMEANS_SAMPLE, TAG_NEG, TAG_CALIB = 1, 2, 3, 4, 5
+
+
+def splitmix64(x):
+    """SplitMix64 output for state ``x`` (uint64 array): add the golden gamma, then the
+    two xor-shift-multiply rounds and a final xor-shift."""
+    x = np.asarray(x, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = x + np.uint64(0x9E3779B97F4A7C15)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        z = z ^ (z >> np.uint64(31))
+    return z
+
+
+def ctr_key(seed: int, tag: int, idx) -> np.ndarray:
+    """key = splitmix64(splitmix64(seed + tag) + idx)  (all mod 2^64)."""
+    base = splitmix64(np.uint64((seed + tag) & _M64))
+    with np.errstate(over="ignore"):
+        return splitmix64(base + np.asarray(idx, dtype=np.uint64))
+
+
+def select_by_key(n: int, m: int, seed: int, tag: int) -> np.ndarray:
+    """Indices of the ``m`` smallest keys among 0..n-1 (ties by index), ascending index order."""
+    if m >= n:
+        return np.arange(n, dtype=np.int64)
+    keys = ctr_key(seed, tag, np.arange(n, dtype=np.uint64))
+    order = np.lexsort((np.arange(n), keys))
+    return np.sort(order[:m]).astype(np.int64)
+
+
+# --------------------------------------------------------------------------------------
+# Exact KNN  [Sec. II-A]: K smallest dis(p, q) = ||p - q||^2, ties by id.
+# --------------------------------------------------------------------------------------
+
+def sq_dist_direct(X: np.ndarray, q: np.ndarray) -> np.ndarray:
+    """||x - q||^2 for each row x of X, summed term by term in FP64."""
+    d = np.asarray(X, dtype=np.float64) - np.asarray(q, dtype=np.float64)[None, :]
+    return np.einsum("ij,ij->i", d, d)
+
+
+def topk_lex(dist: np.ndarray, ids: np.ndarray, k: int):
+    """The k smallest (dist, id) pairs in lexicographic order."""
+    order = np.lexsort((ids, dist))[:k]
+    return ids[order], dist[order]
+
+
+def bruteforce_knn(X: np.ndarray, Q: np.ndarray, k: int, chunk: int = 256):
+    """Exact K nearest neighbours of every query row, FP64.
+
+    Distances are screened with the algebraic expansion ||x||^2 + ||q||^2 - 2<x,q>
+    (one matrix product), then every point whose screened distance lies within a
+    safe margin of the screened K-th distance is recomputed term by term, and the
+    answer is taken from the recomputed values.  The margin (1e-10 of the norms'
+    scale) is orders of magnitude above the FP64 error of the expansion for D<=4096,
+    so the result equals the term-by-term definition.
+
+    Returns ids (nq, k) int64 padded with -1 and dists (nq, k) float64 padded with inf.
+    """
+    X = np.asarray(X, dtype=np.float64)
+    Q = np.asarray(Q, dtype=np.float64)
+    n = X.shape[0]
+    nq = Q.shape[0]
+    kk = min(k, n)
+    ids_out = np.full((nq, k), -1, dtype=np.int64)
+    d_out = np.full((nq, k), np.inf)
+    xn = np.einsum("ij,ij->i", X, X)
+    all_ids = np.arange(n, dtype=np.int64)
+    for s in range(0, nq, chunk):
+        Qc = Q[s:s + chunk]
+        qn = np.einsum("ij,ij->i", Qc, Qc)
+        approx = xn[None, :] + qn[:, None] - 2.0 * (Qc @ X.T)
+        for r in range(Qc.shape[0]):
+            a = approx[r]
+            if kk == 0:
+                continue
+            kth = np.partition(a, kk - 1)[kk - 1]
+            margin = 1e-10 * (xn.max() + qn[r]) + 1e-300
+            cand = np.nonzero(a <= kth + margin)[0]
+            exact = sq_dist_direct(X[cand], Qc[r])
+            i, d = topk_lex(exact, all_ids[cand], kk)
+            ids_out[s + r, :kk] = i
+            d_out[s + r, :kk] = d
+    return ids_out, d_out
+
+
+# --------------------------------------------------------------------------------------
+# PCA rotation  [Sec. IV-B Thm. 1 and its Remark; centring per the footnote of Sec. IV-B]
+# --------------------------------------------------------------------------------------
+
+def pca_fit(X: np.ndarray, pca_sample: int = 1_000_000, seed: int = 0) -> dict:
+    """mu = mean of the PCA sample, C = (1/#P) sum (x-mu)(x-mu)^T, and R whose rows are the
+    eigenvectors of C ordered by eigenvalue, largest first.
+
+    Readings: the sample P is all rows when n <= pca_sample, otherwise the pca_sample rows
+    with the smallest SplitMix64 keys; eigenvalue ties keep the solver's index order; each
+    eigenvector is signed so that its largest-magnitude component is positive (first such
+    component on ties).  The eigen-decomposition itself is a library routine (LAPACK syevd).
+    """
+    X = np.asarray(X)
+    n, D = X.shape
+    rows = select_by_key(n, pca_sample, seed, TAG_PCA) if n > pca_sample else None
+    P = np.asarray(X if rows is None else X[rows], dtype=np.float64)
+    mu = P.mean(axis=0)
+    Pc = P - mu[None, :]
+    C = (Pc.T @ Pc) / P.shape[0]
+    lam, V = np.linalg.eigh(C)                 # ascending
+    order = np.lexsort((np.arange(D), -lam))   # descending, index tie-break
+    lam, V = lam[order], V[:, order]
+    for j in range(D):
+        v = V[:, j]
+        i = int(np.argmax(np.abs(v)))          # first index of the largest magnitude
+        if v[i] < 0:
+            V[:, j] = -v
+    return dict(mu=mu, cov=C, lam=lam, R=np.ascontiguousarray(V.T))
+
+
+def rotate(X: np.ndarray, mu: np.ndarray, R: np.ndarray) -> np.ndarray:
+    """x_D = R (x - mu)  [Eq. (1): the rotation preserves ||x - q||^2]."""
+    return (np.asarray(X, dtype=np.float64) - mu[None, :]) @ R.T
+
+
+# --------------------------------------------------------------------------------------
+# Storage formats.  The paper stores FP32 (Sec. VII-A); lower-precision storage is a
+# deployment choice.  Reading: a stored value is the FP64 rotated value rounded to FP32
+# (round to nearest even), then, for FP16/BF16, rounded again (nearest even) to the
+# narrow format.  Every distance "exact" for a stored vector is exact for its stored value.
+# --------------------------------------------------------------------------------------
+
+def _bf16_round_f32(a32: np.ndarray) -> np.ndarray:
+    """Round float32 values to bfloat16 (nearest, ties to even) and widen back to float32."""
+    u = a32.astype(np.float32).view(np.uint32).astype(np.uint64)
+    lsb = (u >> np.uint64(16)) & np.uint64(1)
+    u = (u + np.uint64(0x7FFF) + lsb) & np.uint64(0xFFFF0000)
+    return u.astype(np.uint32).view(np.float32)
+
+
+def round_storage(y: np.ndarray, dtype: str) -> np.ndarray:
+    """Stored value of FP64 ``y`` for storage ``dtype`` in {'f32', 'f16', 'bf16'}, as FP64."""
+    y32 = np.asarray(y, dtype=np.float64).astype(np.float32)
+    if dtype == "f32":
+        out = y32
+    elif dtype == "f16":
+        out = y32.astype(np.float16).astype(np.float32)
+    elif dtype == "bf16":
+        out = _bf16_round_f32(y32)
+    else:
+        raise ValueError(dtype)
+    return out.astype(np.float64)
+
+
+# --------------------------------------------------------------------------------------
+# IVF  [Sec. II-A "Inverted File-Based"]: k-means buckets, probe the nearest centroids.
+# --------------------------------------------------------------------------------------
+
+def nearest_centroid(Y: np.ndarray, C: np.ndarray, chunk: int = 8192) -> np.ndarray:
+    """argmin_j ||y - c_j||^2 per row (ties to the lower j).  Screened through the
+    expansion, then every centroid within a safe margin of the screened minimum is
+    recomputed term by term (same argument as in ``bruteforce_knn``)."""
+    Y = np.asarray(Y, dtype=np.float64)
+    C = np.asarray(C, dtype=np.float64)
+    cn = np.einsum("ij,ij->i", C, C)
+    out = np.empty(Y.shape[0], dtype=np.int64)
+    jj = np.arange(C.shape[0])
+    for s in range(0, Y.shape[0], chunk):
+        Yc = Y[s:s + chunk]
+        yn = np.einsum("ij,ij->i", Yc, Yc)
+        a = cn[None, :] + yn[:, None] - 2.0 * (Yc @ C.T)
+        amin = a.min(axis=1)
+        margin = 1e-10 * (cn.max() + yn) + 1e-300
+        close = a <= (amin + margin)[:, None]
+        out[s:s + Yc.shape[0]] = np.argmax(close, axis=1)      # single close centroid
+        for r in np.nonzero(close.sum(axis=1) > 1)[0]:         # several: recompute exactly
+            cand = np.nonzero(close[r])[0]
+            ex = sq_dist_direct(C[cand], Yc[r])
+            best = np.lexsort((jj[cand], ex))[0]
+            out[s + r] = cand[best]
+    return out
+
+
+def kmeans(Y: np.ndarray, nlist: int, iters: int = 25, seed: int = 0, train_per_list: int = 256):
+    """Lloyd's k-means.  Readings: training set = all rows if n <= train_per_list * nlist,
+    else that many rows with the smallest SplitMix64 keys; initial centroids = the nlist
+    training rows with the smallest keys (in ascending row order); assignment ties go to
+    the lower centroid index; an empty cluster keeps its previous centroid; after the
+    iterations every row of Y is assigned once more."""
+    Y = np.asarray(Y, dtype=np.float64)
+    n = Y.shape[0]
+    cap = train_per_list * nlist
+    train = Y if n <= cap else Y[select_by_key(n, cap, seed, TAG_KMEANS_SAMPLE)]
+    init = select_by_key(train.shape[0], nlist, seed, TAG_KMEANS_INIT)
+    C = train[init].copy()
+    for _ in range(iters):
+        a = nearest_centroid(train, C)
+        for j in range(nlist):
+            members = train[a == j]
+            if members.shape[0]:
+                C[j] = members.mean(axis=0)
+    return C, nearest_centroid(Y, C)
+
+
+def build_lists(assign: np.ndarray, nlist: int):
+    """List j holds the ids assigned to centroid j in ascending id order.
+    Returns (offsets[nlist+1], ids in list order)."""
+    assign = np.asarray(assign, dtype=np.int64)
+    ids = np.lexsort((np.arange(assign.shape[0]), assign)).astype(np.int64)
+    counts = np.bincount(assign, minlength=nlist)
+    off = np.zeros(nlist + 1, dtype=np.int64)
+    off[1:] = np.cumsum(counts)
+    return off, ids
+
+
+def probe_order(qrot: np.ndarray, C: np.ndarray, nprobe: int):
+    """The nprobe centroids nearest to the rotated query, ascending by (distance, list id).
+    Also returns the smallest relative gap between consecutive distances among the first
+    nprobe+1 (a near tie there can reorder or swap probed lists under other rounding)."""
+    d = sq_dist_direct(C, qrot)
+    order = np.lexsort((np.arange(C.shape[0]), d))
+    top = order[:nprobe]
+    ds = d[order[:min(nprobe + 1, C.shape[0])]]
+    if ds.shape[0] > 1:
+        gap = np.abs(np.diff(ds)) / np.maximum(np.abs(ds[1:]), 1e-300)
+        margin = float(gap.min())
+    else:
+        margin = math.inf
+    return top.astype(np.int64), d[top], margin
+
+
+# --------------------------------------------------------------------------------------
+# Stages  [Sec. IV-D Alg. 2: dimensions are added Delta_d at a time; Sec. V-B
+# "Incremental Correction": one classifier per stage until d = D]
+# --------------------------------------------------------------------------------------
+
+def stage_bounds(D: int, delta_d: int = 32) -> np.ndarray:
+    """d_s = min(s * Delta_d, D) for s = 1..S, S = ceil(D / Delta_d).  Stages 1..S-1 are
+    tested; at stage S all D dimensions are summed, so the value is the exact distance."""
+    S = -(-D // delta_d)
+    return np.minimum(np.arange(1, S + 1) * delta_d, D).astype(np.int64)
+
+
+def partial_dists(Yc: np.ndarray, qrot: np.ndarray, bounds: np.ndarray) -> np.ndarray:
+    """e_s = sum_{i < d_s} (q'_i - y_i)^2 for every row and stage (FP64): the PCA
+    partial distance dis' over the first d_s projected dimensions [Sec. V-B]."""
+    diff = np.asarray(Yc, dtype=np.float64) - qrot[None, :]
+    sq = diff * diff
+    cs = np.cumsum(sq, axis=1)
+    return cs[:, bounds - 1]
+
+
+def _rel(a, b, c):
+    return np.abs(a) + np.abs(b) + np.abs(c) + 1e-300
+
+
+def search_one(qrot, Y, list_off, list_ids, probes, k, m, beta, bounds, B=256, L=0,
+               prune=True, collect_neg=None):
+    """Canonical block-synchronous pruned refinement for one rotated query.
+
+    The paper's refinement updates tau after every candidate [Sec. I: result queue Q with
+    threshold tau].  Reading for parallel hardware: candidates are taken in probe order,
+    each list in blocks of B consecutive stored positions (blocks never span lists); every
+    candidate of block b is tested against tau_b = the tau in force after block b-1-L
+    (+inf if there is none or the queue held fewer than K).  B = 1, L = 0 is the paper's
+    sequential rule.  A candidate is pruned at the first tested stage s with
+    tau_b < inf and m_s * e_s + beta_s > tau_b (strict, Sec. V-A classifier), otherwise its
+    exact distance e_S joins the block's survivors; after the block the queue becomes the
+    K smallest (dis, id) of queue and survivors, and tau its K-th distance.
+
+    Returns (ids, dists, stop_counts, margin):
+      stop_counts[s] = candidates whose last scanned stage is s (0-based, S-1 = refined);
+      margin = smallest relative distance of any decision quantity to its threshold.
+    If ``collect_neg`` is a list, (id, tau_b, e_1..e_S) of every candidate with tau_b
+    finite and dis > tau_b is appended to it (label-1 pool of the calibration).
+    """
+    S = bounds.shape[0]
+    T_d = np.zeros(0)
+    T_i = np.zeros(0, dtype=np.int64)
+    tau_hist = []
+    stop_counts = np.zeros(S, dtype=np.int64)
+    margin = math.inf
+    b = 0
+    for lst in probes:
+        lo, hi = int(list_off[lst]), int(list_off[lst + 1])
+        for s0 in range(lo, hi, B):
+            ids = list_ids[s0:min(s0 + B, hi)]
+            j = b - 1 - L
+            tau_b = tau_hist[j] if j >= 0 else math.inf
+            e = partial_dists(Y[ids], qrot, bounds)          # (nb, S)
+            stop = np.full(ids.shape[0], S - 1, dtype=np.int64)
+            if prune and math.isfinite(tau_b) and S > 1:
+                lhs = e[:, :S - 1] * m[None, :] + beta[None, :]   # (nb, S-1)
+                hit = lhs > tau_b
+                any_hit = hit.any(axis=1)
+                first = np.where(any_hit, hit.argmax(axis=1), S - 1)
+                stop = first
+                # decision margins of every evaluated test (stages <= stop)
+                evaluated = np.arange(S - 1)[None, :] <= first[:, None]
+                rel = np.abs(lhs - tau_b) / _rel(e[:, :S - 1] * m[None, :], beta[None, :], tau_b)
+                if evaluated.any():
+                    margin = min(margin, float(rel[evaluated].min()))
+            np.add.at(stop_counts, stop, 1)
+            surv = stop == S - 1
+            sd = e[surv, S - 1]
+            si = ids[surv]
+            if collect_neg is not None and math.isfinite(tau_b):
+                neg = sd > tau_b
+                es = e[surv]
+                for r in np.nonzero(neg)[0]:
+                    collect_neg.append((int(si[r]), tau_b, es[r]))
+            # merge: K smallest of queue and survivors by (dis, id)
+            all_d = np.concatenate([T_d, sd])
+            all_i = np.concatenate([T_i, si])
+            order = np.lexsort((all_i, all_d))
+            if order.shape[0] > k:
+                dk, dk1 = all_d[order[k - 1]], all_d[order[k]]
+                margin = min(margin, float(abs(dk1 - dk) / max(abs(dk1), 1e-300)))
+            order = order[:k]
+            T_d, T_i = all_d[order], all_i[order]
+            tau_hist.append(float(T_d[k - 1]) if T_d.shape[0] == k else math.inf)
+            b += 1
+    if T_d.shape[0] > 1:
+        gaps = np.abs(np.diff(T_d)) / np.maximum(np.abs(T_d[1:]), 1e-300)
+        margin = min(margin, float(gaps.min()))
+    ids_out = np.full(k, -1, dtype=np.int64)
+    d_out = np.full(k, np.inf)
+    ids_out[:T_i.shape[0]] = T_i
+    d_out[:T_d.shape[0]] = T_d
+    return ids_out, d_out, stop_counts, margin
+
+
+def search_sequential(qrot, Y, list_off, list_ids, probes, k, m, beta, bounds):
+    """The paper's per-candidate refinement, coded separately: a binary max-heap Q of the
+    K best (dis, id); tau = its root once it holds K entries; each candidate walks the
+    stages and is pruned at the first stage with m_s e_s + beta_s > tau, otherwise enters
+    Q when (dis, id) is smaller than the root [Sec. I refinement; Alg. 2 stage loop;
+    Sec. V-A classifier].  Equals ``search_one`` with B = 1, L = 0."""
+    heap = []   # entries (-dis, -id): the root is the largest (dis, id)
+    q = np.asarray(qrot, dtype=np.float64)
+    S = bounds.shape[0]
+    for lst in probes:
+        for pos in range(int(list_off[lst]), int(list_off[lst + 1])):
+            x = int(list_ids[pos])
+            tau = -heap[0][0] if len(heap) == k else math.inf
+            acc = 0.0
+            lo = 0
+            pruned = False
+            for s in range(S):
+                hi = int(bounds[s])
+                for i in range(lo, hi):
+                    t = q[i] - Y[x, i]
+                    acc += t * t
+                lo = hi
+                if s < S - 1 and tau != math.inf and m[s] * acc + beta[s] > tau:
+                    pruned = True
+                    break
+            if pruned:
+                continue
+            item = (-acc, -x)
+            if len(heap) < k:
+                heapq.heappush(heap, item)
+            elif (acc, x) < (-heap[0][0], -heap[0][1]):
+                heapq.heapreplace(heap, item)
+    res = sorted((-a, -b) for a, b in heap)
+    ids = np.full(k, -1, dtype=np.int64)
+    ds = np.full(k, np.inf)
+    for i, (d, x) in enumerate(res):
+        ids[i], ds[i] = x, d
+    return ids, ds
+
+
+# --------------------------------------------------------------------------------------
+# Logistic regression  [Sec. V-A "Parameter Learning": linear classifier on (dis', tau),
+# cross-entropy loss].  Reading: the paper trains with SGD and reports that other linear
+# models give similar outcomes; the oracle takes the exact minimiser of the same
+# cross-entropy (plus a 1e-8 ridge) by Newton's method (IRLS).
+# --------------------------------------------------------------------------------------
+
+def irls_logistic(F: np.ndarray, y: np.ndarray, ridge: float = 1e-8, max_iter: int = 100,
+                  tol: float = 1e-12):
+    """Minimise mean BCE(sigmoid(w0 + w.f), y) + ridge/2 * |w|^2 (w without intercept) on
+    standardised features; returns (b, w) in the original feature units."""
+    F = np.asarray(F, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    mean = F.mean(axis=0)
+    std = F.std(axis=0)
+    std[std == 0] = 1.0
+    Z = np.hstack([np.ones((F.shape[0], 1)), (F - mean) / std])
+    n, p = Z.shape
+    w = np.zeros(p)
+    reg = np.full(p, ridge)
+    reg[0] = 0.0
+    for _ in range(max_iter):
+        t = Z @ w
+        pr = 0.5 * (1.0 + np.tanh(0.5 * t))          # sigmoid, overflow-free
+        g = Z.T @ (pr - y) / n + reg * w
+        W = pr * (1.0 - pr)
+        H = (Z * W[:, None]).T @ Z / n + np.diag(reg) + 1e-300 * np.eye(p)
+        step = np.linalg.solve(H, g)
+        w = w - step
+        if np.max(np.abs(step)) < tol:
+            break
+    wf = w[1:] / std
+    b = w[0] - float(np.dot(w[1:], mean / std))
+    return b, wf
+
+
+def classifier_to_correction(b: float, w1: float, w2: float):
+    """sign(w1 dis' + w2 tau + b) > 0  <=>  m dis' + beta > tau  with m = -w1/w2,
+    beta = -b/w2 when w2 < 0 [Sec. V-A, linear model].  Reading: if w2 >= 0 or m <= 0 the
+    classifier has no usable orientation and m falls back to 1."""
+    if w2 < 0:
+        m = -w1 / w2
+        if m > 0:
+            return m, -b / w2
+    return 1.0, 0.0
+
+
+# --------------------------------------------------------------------------------------
+# Target-recall adjustment  [Sec. V-A "Adaptive Adjustment": move beta to beta' so that the
+# recall of label 0 reaches r].  Reading: alpha = 1 - r is the probability that a true
+# neighbour is pruned at ANY stage (joint), so beta_s = the (k*+1)-th smallest residual
+# g_s = tau - m_s e_s of stage s, with k* the largest k whose joint false-prune fraction
+# F(k) = (1/n0) #{ j : exists s, g_s(j) < g_s^(k+1) } is <= alpha.  The binary search the
+# paper mentions is exact here because F is monotone in k.  Per-stage (Bonferroni) mode
+# gives every test stage alpha / S_t instead.
+# --------------------------------------------------------------------------------------
+
+def joint_false_prune(G: np.ndarray, Gs: np.ndarray, k: int) -> float:
+    """F(k) for residual matrix G (n0, S_t) and its column-sorted copy Gs."""
+    thr = Gs[k, :]
+    return float(np.mean((G < thr[None, :]).any(axis=1)))
+
+
+def beta_for_alpha(G: np.ndarray, alpha: float, mode: str = "joint") -> np.ndarray:
+    G = np.asarray(G, dtype=np.float64)
+    n0, St = G.shape
+    if alpha <= 0.0 or n0 == 0:
+        return np.full(St, -np.inf)
+    Gs = np.sort(G, axis=0)
+    if mode == "bonferroni":
+        k = min(int(math.floor(alpha * n0 / St)), n0 - 1)
+        return Gs[k, :].copy()
+    lo, hi = 0, n0 - 1                    # F(0) = 0 <= alpha always
+    while lo < hi:
+        mid = (lo + hi + 1) // 2
+        if joint_false_prune(G, Gs, mid) <= alpha:
+            lo = mid
+        else:
+            hi = mid - 1
+    return Gs[lo, :].copy()
+
+
+# --------------------------------------------------------------------------------------
+# Calibration  [Sec. V-A; Sec. VII-A implementation details: training queries, their KNN as
+# label 0, items met "through a query process" as label 1, BCE training, target recall]
+# --------------------------------------------------------------------------------------
+
+def calibrate(Y, list_off, list_ids, centroids, mu, R, calib, bounds, calib_k=10, calib_nprobe=8,
+              B=256, L=0, seed=0, max_neg=50):
+    """Per test stage: m_s from logistic regression on label 0 = (e_s, tau_q) of the K_c
+    true neighbours of every calibration query (tau_q = its K_c-th distance) and label 1 =
+    up to ``max_neg`` (e_s, tau_b) per query drawn (smallest SplitMix64 keys of
+    query_index * 2^32 + id) from the candidates of an unpruned canonical IVF search
+    (calib_nprobe, B, L) whose exact distance exceeds the block's finite tau_b.
+    Returns dict(m, G) with G the (n0, S_t) residual matrix g_s(j) = tau_j - m_s e_s(j)."""
+    Y = np.asarray(Y, dtype=np.float64)
+    S = bounds.shape[0]
+    St = S - 1
+    Qr = rotate(calib, mu, R)
+    knn_ids, knn_d = bruteforce_knn(Y, Qr, calib_k)
+    pos_e, pos_tau, neg_e, neg_tau = [], [], [], []
+    zeros_m = np.zeros(St)
+    for qi in range(Qr.shape[0]):
+        tau_q = knn_d[qi, calib_k - 1]
+        e = partial_dists(Y[knn_ids[qi]], Qr[qi], bounds)
+        pos_e.append(e[:, :St])
+        pos_tau.append(np.full(calib_k, tau_q))
+        probes, _, _ = probe_order(Qr[qi], centroids, calib_nprobe)
+        pool = []
+        search_one(Qr[qi], Y, list_off, list_ids, probes, calib_k, zeros_m, zeros_m, bounds,
+                   B=B, L=L, prune=False, collect_neg=pool)
+        if pool:
+            idx = np.array([p[0] for p in pool], dtype=np.uint64)
+            keys = ctr_key(seed, TAG_NEG, (np.uint64(qi) << np.uint64(32)) + idx)
+            take = np.lexsort((idx, keys))[:max_neg]
+            for t in take:
+                neg_e.append(pool[t][2][:St])
+                neg_tau.append(pool[t][1])
+    pos_e = np.vstack(pos_e)
+    pos_tau = np.concatenate(pos_tau)
+    neg_e = np.vstack(neg_e) if neg_e else np.zeros((0, St))
+    neg_tau = np.asarray(neg_tau, dtype=np.float64)
+    m = np.ones(St)
+    lr = []
+    for s in range(St):
+        F = np.vstack([np.column_stack([pos_e[:, s], pos_tau]), np.column_stack([neg_e[:, s], neg_tau])])
+        lab = np.concatenate([np.zeros(pos_e.shape[0]), np.ones(neg_e.shape[0])])
+        if neg_e.shape[0] == 0:
+            lr.append((0.0, 0.0, 0.0))
+            continue
+        b, w = irls_logistic(F, lab)
+        m[s], _ = classifier_to_correction(b, w[0], w[1])
+        lr.append((b, w[0], w[1]))
+    G = pos_tau[:, None] - pos_e * m[None, :]
+    return dict(m=m, G=G, pos_e=pos_e, pos_tau=pos_tau, neg_e=neg_e, neg_tau=neg_tau, lr=lr,
+                knn_ids=knn_ids, knn_d=knn_d)
+
+
+# --------------------------------------------------------------------------------------
+# End-to-end fit and search
+# --------------------------------------------------------------------------------------
+
+def fit(base, calib, nlist, delta_d=32, storage="f32", kmeans_iters=25, calib_k=10,
+        calib_nprobe=None, B=256, L=0, seed=0, pca_sample=1_000_000, max_neg=50):
+    """Projection + IVF lists + calibrated correction table for ``base``."""
+    base = np.asarray(base)
+    D = base.shape[1]
+    pca = pca_fit(base, pca_sample, seed)
+    Y = round_storage(rotate(base, pca["mu"], pca["R"]), storage)
+    C, assign = kmeans(Y, nlist, kmeans_iters, seed)
+    off, ids = build_lists(assign, nlist)
+    bounds = stage_bounds(D, delta_d)
+    if calib_nprobe is None:
+        calib_nprobe = int(min(max(1, nlist // 8), 64))
+    cal = calibrate(Y, off, ids, C, pca["mu"], pca["R"], calib, bounds, calib_k, calib_nprobe,
+                    B, L, seed, max_neg)
+    return dict(mu=pca["mu"], R=pca["R"], lam=pca["lam"], cov=pca["cov"], Y=Y, centroids=C,
+                assign=assign, list_off=off, list_ids=ids, bounds=bounds, m=cal["m"], G=cal["G"],
+                calib=cal, storage=storage, delta_d=delta_d, B=B, L=L)
+
+
+def search(index, queries, k, nprobe, alpha, mode="learned", B=None, L=None, calib_mode="joint"):
+    """Search every query; mode in {'learned', 'lossless', 'none'}.
+    Returns ids (nq, k), dists (nq, k), stop_counts (nq, S), margin (nq,)."""
+    B = index["B"] if B is None else B
+    L = index["L"] if L is None else L
+    bounds = index["bounds"]
+    St = bounds.shape[0] - 1
+    if mode == "learned":
+        m = index["m"]
+        beta = beta_for_alpha(index["G"], alpha, calib_mode)
+        prune = alpha > 0
+    elif mode == "lossless":
+        m, beta, prune = np.ones(St), np.zeros(St), True
+    elif mode == "none":
+        m, beta, prune = np.ones(St), np.zeros(St), False
+    else:
+        raise ValueError(mode)
+    Qr = rotate(queries, index["mu"], index["R"])
+    nq = Qr.shape[0]
+    ids = np.full((nq, k), -1, dtype=np.int64)
+    ds = np.full((nq, k), np.inf)
+    stops = np.zeros((nq, bounds.shape[0]), dtype=np.int64)
+    margins = np.full(nq, math.inf)
+    probes_all = np.zeros((nq, nprobe), dtype=np.int64)
+    for qi in range(nq):
+        probes, _, pm = probe_order(Qr[qi], index["centroids"], nprobe)
+        probes_all[qi] = probes
+        i, d, st, mg = search_one(Qr[qi], index["Y"], index["list_off"], index["list_ids"], probes,
+                                  k, m, beta, bounds, B, L, prune)
+        ids[qi], ds[qi], stops[qi], margins[qi] = i, d, st, min(mg, pm)
+    return dict(ids=ids, dists=ds, stops=stops, margin=margins, probes=probes_all, qrot=Qr, m=m,
+                beta=beta)
+
+
+def recall_at(ids: np.ndarray, gt: np.ndarray, k: int = 10) -> float:
+    """recall@k = |T ∩ G| / k averaged over queries [Sec. VII-A evaluation metrics]."""
+    hits = 0
+    for a, g in zip(ids[:, :k], gt[:, :k]):
+        hits += len(set(a.tolist()) & set(g.tolist()))
+    return hits / (k * ids.shape[0])
+
+
+def false_prune_rate(index, queries, k, alpha, calib_mode="joint"):
+    """Held-out check of the calibration: the fraction of (query, true K-NN) pairs that the
+    stage tests would prune at the query's final tau (its K-th true distance), i.e. the
+    label-0 miss rate the target recall r = 1 - alpha bounds [Sec. V-A].  Also returns the
+    per-query miss counts for a query-level bootstrap."""
+    bounds = index["bounds"]
+    St = bounds.shape[0] - 1
+    m = index["m"]
+    beta = beta_for_alpha(index["G"], alpha, calib_mode)
+    Qr = rotate(queries, index["mu"], index["R"])
+    knn_ids, knn_d = bruteforce_knn(index["Y"], Qr, k)
+    per_q = np.zeros(Qr.shape[0])
+    for qi in range(Qr.shape[0]):
+        tau = knn_d[qi, k - 1]
+        e = partial_dists(index["Y"][knn_ids[qi]], Qr[qi], bounds)[:, :St]
+        per_q[qi] = np.count_nonzero((e * m[None, :] + beta[None, :] > tau).any(axis=1))
+    return float(per_q.sum() / (k * Qr.shape[0])), per_q

@@ -1,0 +1,410 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix (CPU only).
+
+Each test checks an oracle function against something other than itself: a closed
+form, a published value, an invariant, a library routine or brute force on a tiny
+input.  Paper references are to sections, equations, theorems and algorithms.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.optimize
+import scipy.spatial.distance as ssd
+
+import oracle as O
+import synthdata
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ----------------------------------------------------------------------------- generator
+
+def test_splitmix64_published_outputs():
+    """SplitMix64 (Steele, Lea, Flood 2014) first outputs for seed 0."""
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "splitmix64.txt")) if l.strip() and l[0] != "#"]
+    gamma = 0x9E3779B97F4A7C15
+    for idx, hexv in rows:
+        state = (int(idx) * gamma) % (1 << 64)
+        assert int(O.splitmix64(np.uint64(state))) == int(hexv, 16)
+
+
+def test_select_by_key_is_smallest_keys():
+    keys = O.ctr_key(5, O.TAG_PCA, np.arange(1000, dtype=np.uint64))
+    sel = O.select_by_key(1000, 37, 5, O.TAG_PCA)
+    brute = sorted(range(1000), key=lambda i: (int(keys[i]), i))[:37]
+    assert sorted(brute) == sel.tolist()
+
+
+# ----------------------------------------------------------------------------- exact KNN
+
+def test_bruteforce_matches_library_distance_sort():
+    """Exact KNN [Sec. II-A] vs scipy's squared-Euclidean distance matrix + a full sort."""
+    rng = np.random.default_rng(1)
+    X = rng.standard_normal((700, 24)).astype(np.float32)
+    Q = rng.standard_normal((9, 24)).astype(np.float32)
+    X[5] = X[3]                                # an exact duplicate: tie broken by id
+    Q[0] = X[3]
+    ids, d = O.bruteforce_knn(X, Q, 12)
+    Dm = ssd.cdist(Q.astype(np.float64), X.astype(np.float64), "sqeuclidean")
+    for r in range(Q.shape[0]):
+        ref = sorted(range(X.shape[0]), key=lambda i: (Dm[r, i], i))[:12]
+        assert ids[r].tolist() == ref
+        np.testing.assert_allclose(d[r], Dm[r, ref], rtol=1e-12, atol=1e-12)
+    assert ids[0, 0] == 3 and ids[0, 1] == 5 and d[0, 0] == 0.0
+
+
+def test_bruteforce_pads_when_k_exceeds_n():
+    X = np.eye(3, dtype=np.float32)
+    ids, d = O.bruteforce_knn(X, np.zeros((1, 3), np.float32), 5)
+    assert ids[0, 3:].tolist() == [-1, -1] and np.isinf(d[0, 3:]).all()
+    assert ids[0, :3].tolist() == [0, 1, 2]
+
+
+# ----------------------------------------------------------------------------- PCA (Thm. 1)
+
+def test_pca_closed_form_2d():
+    """Covariance [[2,1],[1,2]] -> eigenvalues 3, 1 and eigenvectors (1,1)/sqrt2, (1,-1)/sqrt2."""
+    lines = [l for l in open(os.path.join(GOLDEN, "pca_2d.txt")) if l.strip() and l[0] != "#"]
+    P = np.array([[float(v) for v in l.split()] for l in lines])
+    p = O.pca_fit(P)
+    s = 1 / math.sqrt(2)
+    np.testing.assert_allclose(p["mu"], [10, -5], atol=1e-14)
+    np.testing.assert_allclose(p["lam"], [3, 1], atol=1e-13)
+    np.testing.assert_allclose(p["R"], [[s, s], [s, -s]], atol=1e-13)
+
+
+def test_pca_covariance_matches_library(small_workload):
+    """C = (1/n) sum (x-mu)(x-mu)^T  (population covariance of the centred data)."""
+    X = small_workload["base"][:2000]
+    p = O.pca_fit(X)
+    np.testing.assert_allclose(p["cov"], np.cov(X.astype(np.float64).T, bias=True), rtol=1e-10,
+                               atol=1e-13)
+
+
+def test_pca_rotation_orthogonal_and_diagonalising(small_workload):
+    p = O.pca_fit(small_workload["base"])
+    R, C, lam = p["R"], p["cov"], p["lam"]
+    assert np.abs(R @ R.T - np.eye(R.shape[0])).max() <= 1e-12
+    RC = R @ C @ R.T
+    off = RC - np.diag(np.diag(RC))
+    assert np.abs(off).max() <= 1e-10 * lam[0]
+    np.testing.assert_allclose(np.diag(RC), lam, rtol=1e-9, atol=1e-12)
+    assert np.all(np.diff(lam) <= 0)
+    # sign rule: the largest-magnitude component of every row is positive
+    assert np.all(R[np.arange(R.shape[0]), np.abs(R).argmax(axis=1)] > 0)
+
+
+def test_pca_recovers_generating_spectrum(small_workload):
+    """Data are Q diag(sqrt(1/i)) z: sample eigenvalues ~ 1/i and leading eigenvectors ~ the
+    columns of Q (closed form of the generating covariance)."""
+    w = small_workload
+    p = O.pca_fit(w["base"])
+    n = w["base"].shape[0]
+    rel = np.abs(p["lam"][:16] - w["lam"][:16]) / w["lam"][:16]
+    assert rel.max() <= 3 * math.sqrt(2 / n) * 3
+    for i in range(3):
+        assert abs(float(p["R"][i] @ w["rot"][:, i])) >= 0.99
+
+
+def test_theorem1_pca_minimises_residual_variance(small_workload):
+    """Thm. 1 (Ky Fan): for every d, the variance left in dims d+1..D after the PCA rotation
+    is no larger than after any other orthogonal rotation (20 Haar draws)."""
+    X = small_workload["base"][:3000].astype(np.float64)
+    p = O.pca_fit(X)
+    Xc = X - p["mu"]
+    tail_pca = np.cumsum(np.var(Xc @ p["R"].T, axis=0)[::-1])[::-1]
+    rng = np.random.default_rng(11)
+    for _ in range(20):
+        Rr = synthdata.haar_rotation(X.shape[1], rng)
+        tail_r = np.cumsum(np.var(Xc @ Rr, axis=0)[::-1])[::-1]
+        assert np.all(tail_pca <= tail_r * (1 + 1e-9) + 1e-12)
+
+
+# ----------------------------------------------------------------------------- Eq. (1)
+
+def test_eq1_rotation_invariance_full_stage(small_workload):
+    """Eq. (1): ||x - q||^2 = ||R x - R q||^2, so the last stage's partial distance e_S of the
+    rotated vectors is the exact distance in the original coordinates."""
+    w = small_workload
+    p = O.pca_fit(w["base"])
+    Y = O.rotate(w["base"][:500], p["mu"], p["R"])
+    bounds = O.stage_bounds(128, 32)
+    for qi in range(5):
+        q = w["queries"][qi]
+        e = O.partial_dists(Y, O.rotate(q[None], p["mu"], p["R"])[0], bounds)
+        exact = O.sq_dist_direct(w["base"][:500], q)
+        np.testing.assert_allclose(e[:, -1], exact, rtol=1e-12)
+        # partial distances of squares never decrease and never exceed the exact one
+        assert np.all(np.diff(e, axis=1) >= 0)
+
+
+def test_stage_bounds_ragged():
+    assert O.stage_bounds(128, 32).tolist() == [32, 64, 96, 128]
+    assert O.stage_bounds(100, 32).tolist() == [32, 64, 96, 100]
+    assert O.stage_bounds(20, 32).tolist() == [20]
+
+
+# ----------------------------------------------------------------------------- storage rounding
+
+def test_storage_rounding_matches_library_and_definition():
+    import torch
+    rng = np.random.default_rng(3)
+    y = rng.standard_normal(5000) * 10
+    y32 = y.astype(np.float32)
+    np.testing.assert_array_equal(O.round_storage(y, "f32"), y32.astype(np.float64))
+    np.testing.assert_array_equal(O.round_storage(y, "f16"),
+                                  torch.from_numpy(y32).to(torch.float16).double().numpy())
+    np.testing.assert_array_equal(O.round_storage(y, "bf16"),
+                                  torch.from_numpy(y32).to(torch.bfloat16).double().numpy())
+    # ties to even on the bfloat16 grid near 1 (spacing 2^-7)
+    assert O.round_storage(np.array([1 + 2 ** -8]), "bf16")[0] == 1.0
+    assert O.round_storage(np.array([1 + 3 * 2 ** -8]), "bf16")[0] == 1 + 2 ** -6
+
+
+# ----------------------------------------------------------------------------- IVF
+
+def test_kmeans_two_clumps_closed_form():
+    rng = np.random.default_rng(2)
+    a = rng.standard_normal((50, 4)) * 0.01 + 10
+    b = rng.standard_normal((70, 4)) * 0.01 - 10
+    Y = np.vstack([a, b])
+    C, assign = O.kmeans(Y, 2, iters=5, seed=1)
+    got = sorted(map(tuple, np.round(C, 9)))
+    want = sorted(map(tuple, np.round([a.mean(0), b.mean(0)], 9)))
+    np.testing.assert_allclose(got, want, atol=1e-9)
+    assert len(set(assign[:50])) == 1 and len(set(assign[50:])) == 1
+
+
+def test_kmeans_assignment_is_nearest(small_index):
+    ix = small_index
+    Dm = ssd.cdist(ix["Y"][:2000], ix["centroids"], "sqeuclidean")
+    ref = np.array([min(range(Dm.shape[1]), key=lambda j: (Dm[i, j], j)) for i in range(2000)])
+    np.testing.assert_array_equal(ix["assign"][:2000], ref)
+    off, ids = ix["list_off"], ix["list_ids"]
+    assert off[-1] == ix["Y"].shape[0]
+    for j in range(0, 64, 7):
+        mem = ids[off[j]:off[j + 1]]
+        assert np.all(np.diff(mem) > 0) and np.all(ix["assign"][mem] == j)
+
+
+def test_probe_order_matches_library(small_index, small_workload):
+    ix = small_index
+    qr = O.rotate(small_workload["queries"][:4], ix["mu"], ix["R"])
+    for q in qr:
+        top, d, _ = O.probe_order(q, ix["centroids"], 8)
+        Dm = ssd.cdist(q[None], ix["centroids"], "sqeuclidean")[0]
+        ref = sorted(range(64), key=lambda j: (Dm[j], j))[:8]
+        assert top.tolist() == ref
+
+
+# ----------------------------------------------------------------------------- search semantics
+
+def _probed_bruteforce(ix, qr, probes, k):
+    cand = np.concatenate([ix["list_ids"][ix["list_off"][p]:ix["list_off"][p + 1]] for p in probes])
+    d = ssd.cdist(qr[None], ix["Y"][cand], "sqeuclidean")[0]
+    order = sorted(range(cand.shape[0]), key=lambda i: (d[i], cand[i]))[:k]
+    return cand[order], d[order]
+
+
+@pytest.mark.parametrize("mode", ["none", "lossless"])
+def test_zero_pruning_and_lossless_reproduce_bruteforce(small_index, small_workload, mode):
+    """No pruning, and the lossless partial-distance exit (m=1, beta=0: e_s <= dis, so
+    e_s > tau implies dis > tau by Eq. (1)), both equal exact KNN over the probed lists."""
+    ix = small_index
+    r = O.search(ix, small_workload["queries"][:20], 10, 8, 0.0, mode=mode)
+    for qi in range(20):
+        ids, d = _probed_bruteforce(ix, r["qrot"][qi], r["probes"][qi], 10)
+        assert r["ids"][qi].tolist() == ids.tolist()
+        np.testing.assert_allclose(r["dists"][qi], d, rtol=1e-12)
+
+
+def test_alpha_zero_and_all_lists_is_exact_knn(small_index, small_workload):
+    ix = small_index
+    Q = small_workload["queries"][:10]
+    r = O.search(ix, Q, 10, 64, 0.0, mode="learned")
+    gt, gd = O.bruteforce_knn(ix["Y"], r["qrot"], 10)
+    np.testing.assert_array_equal(r["ids"], gt)
+    np.testing.assert_allclose(r["dists"], gd, rtol=1e-12)
+
+
+def test_lossless_prunes_something(small_index, small_workload):
+    r = O.search(small_index, small_workload["queries"][:10], 10, 8, 0.0, mode="lossless")
+    assert r["stops"][:, :-1].sum() > 0
+
+
+def test_block_of_one_equals_sequential_heap(small_index, small_workload):
+    """B = 1, L = 0 block-synchronous search == the paper's per-candidate refinement with a
+    binary max-heap (coded separately), on a learned table that prunes."""
+    ix = small_index
+    beta = O.beta_for_alpha(ix["G"], 0.1)
+    qr = O.rotate(small_workload["queries"][:6], ix["mu"], ix["R"])
+    for q in qr:
+        probes, _, _ = O.probe_order(q, ix["centroids"], 3)
+        a_ids, a_d, stops, _ = O.search_one(q, ix["Y"], ix["list_off"], ix["list_ids"], probes, 10,
+                                            ix["m"], beta, ix["bounds"], B=1, L=0)
+        b_ids, b_d = O.search_sequential(q, ix["Y"], ix["list_off"], ix["list_ids"], probes, 10,
+                                         ix["m"], beta, ix["bounds"])
+        assert stops[:-1].sum() > 0
+        assert a_ids.tolist() == b_ids.tolist()
+        np.testing.assert_allclose(a_d, b_d, rtol=1e-12)
+
+
+def test_lag_beyond_block_count_disables_pruning(small_index, small_workload):
+    """tau_b is +inf when block b-1-L does not exist, so a lag longer than the whole scan
+    reproduces the unpruned result."""
+    ix = small_index
+    r1 = O.search(ix, small_workload["queries"][:8], 10, 8, 0.2, L=10_000)
+    r0 = O.search(ix, small_workload["queries"][:8], 10, 8, 0.0, mode="none")
+    np.testing.assert_array_equal(r1["ids"], r0["ids"])
+    assert r1["stops"][:, :-1].sum() == 0
+
+
+def test_returned_distances_are_exact_for_stored_vectors(small_index, small_workload):
+    ix = small_index
+    r = O.search(ix, small_workload["queries"][:20], 10, 8, 0.1)
+    for qi in range(20):
+        exact = O.sq_dist_direct(ix["Y"][r["ids"][qi]], r["qrot"][qi])
+        np.testing.assert_allclose(r["dists"][qi], exact, rtol=1e-12)
+        assert np.all(np.diff(r["dists"][qi]) >= 0)
+
+
+def test_topk_merge_matches_full_sort(small_index, small_workload):
+    """With B larger than every list the queue is one merge of all survivors: a full sort."""
+    ix = small_index
+    q = O.rotate(small_workload["queries"][:1], ix["mu"], ix["R"])[0]
+    probes, _, _ = O.probe_order(q, ix["centroids"], 1)
+    ids, d, _, _ = O.search_one(q, ix["Y"], ix["list_off"], ix["list_ids"], probes, 25,
+                                ix["m"], ix["m"] * 0, ix["bounds"], B=1 << 20, prune=False)
+    ref_ids, ref_d = _probed_bruteforce(ix, q, probes, 25)
+    assert ids.tolist() == ref_ids.tolist()
+
+
+def test_empty_lists_and_short_candidate_sets_pad():
+    Y = np.array([[0.0, 0.0], [1.0, 0.0]])
+    off = np.array([0, 0, 2])
+    lids = np.array([0, 1])
+    ids, d, _, _ = O.search_one(np.zeros(2), Y, off, lids, np.array([0, 1]), 4, np.ones(0),
+                                np.zeros(0), np.array([2]), B=256)
+    assert ids.tolist() == [0, 1, -1, -1] and np.isinf(d[2:]).all()
+
+
+# ----------------------------------------------------------------------------- calibration
+
+def test_irls_matches_library_optimiser():
+    """IRLS (Newton) minimiser == scipy BFGS minimiser of the same penalised cross-entropy."""
+    rng = np.random.default_rng(4)
+    F = rng.standard_normal((400, 2)) * [3.0, 1.0] + [5.0, 2.0]
+    logit = 0.8 * F[:, 0] - 1.5 * F[:, 1] + 0.3
+    y = (rng.random(400) < 1 / (1 + np.exp(-logit))).astype(float)
+    b, w = O.irls_logistic(F, y)
+
+    def loss(v):
+        t = v[0] + F @ v[1:]
+        return np.mean(np.logaddexp(0, t) - y * t) + 0.5e-8 * np.sum((v[1:] * F.std(0)) ** 2)
+
+    ref = scipy.optimize.minimize(loss, np.zeros(3), method="BFGS", options=dict(gtol=1e-12)).x
+    np.testing.assert_allclose([b, *w], ref, rtol=2e-5, atol=2e-5)
+    # stationarity by central finite differences of the loss
+    h = 1e-6
+    g = [(loss(np.array([b, *w]) + h * e) - loss(np.array([b, *w]) - h * e)) / (2 * h) for e in np.eye(3)]
+    assert np.max(np.abs(g)) < 1e-7
+
+
+def test_classifier_to_correction_is_the_same_decision():
+    """sign(w1 e + w2 tau + b) == [m e + beta > tau] on a grid (Sec. V-A linear model)."""
+    b, w1, w2 = 0.7, 1.3, -2.1
+    m, beta = O.classifier_to_correction(b, w1, w2)
+    for e in np.linspace(0, 5, 21):
+        for tau in np.linspace(0.1, 5, 17):
+            assert (w1 * e + w2 * tau + b > 0) == (m * e + beta > tau)
+    assert O.classifier_to_correction(0.0, 1.0, 0.5) == (1.0, 0.0)
+
+
+def test_beta_single_stage_is_plain_quantile():
+    """One test stage: the joint rule reduces to the (floor(alpha n0)+1)-th smallest residual."""
+    g = np.random.default_rng(5).standard_normal((1000, 1))
+    for a in [0.001, 0.005, 0.05, 0.1, 0.37]:
+        assert O.beta_for_alpha(g, a)[0] == np.sort(g[:, 0])[int(math.floor(a * 1000))]
+
+
+def test_beta_joint_bruteforce_small():
+    """k* by enumerating every k on n0 <= 50, and F(k*) <= alpha < F(k*+1)."""
+    rng = np.random.default_rng(6)
+    for trial in range(20):
+        n0, St = int(rng.integers(5, 50)), int(rng.integers(1, 5))
+        G = rng.standard_normal((n0, St))
+        for a in [0.01, 0.05, 0.1, 0.3]:
+            beta = O.beta_for_alpha(G, a)
+
+            def frac(k):
+                thr = [sorted(G[:, s])[k] for s in range(St)]
+                return sum(any(G[j, s] < thr[s] for s in range(St)) for j in range(n0)) / n0
+            ks = [k for k in range(n0) if frac(k) <= a]
+            kstar = max(ks)
+            assert beta.tolist() == [sorted(G[:, s])[kstar] for s in range(St)]
+            # with these betas the calibration set's joint false-prune fraction is frac(k*)
+            pruned = (G < beta[None, :]).any(axis=1).mean()
+            assert pruned == frac(kstar) <= a
+            if kstar + 1 < n0:
+                assert frac(kstar + 1) > a
+    assert np.all(np.isneginf(O.beta_for_alpha(G, 0.0)))
+
+
+def test_bonferroni_split():
+    """Per-stage target r_i = 1 - (1-r)/(D/Delta_d) -> each stage gets alpha/S_t."""
+    G = np.random.default_rng(8).standard_normal((2000, 4))
+    beta = O.beta_for_alpha(G, 0.1, "bonferroni")
+    k = int(math.floor(0.1 * 2000 / 4))
+    assert beta.tolist() == np.sort(G, axis=0)[k].tolist()
+
+
+def test_calibration_labels(small_index):
+    cal = small_index["calib"]
+    # label 0: the K_c true neighbours of each calibration query, tau = their K_c-th distance
+    assert cal["pos_e"].shape == (1000 * 10, 3)
+    np.testing.assert_array_equal(cal["pos_tau"].reshape(1000, 10), np.repeat(cal["knn_d"][:, 9:10], 10, 1))
+    # label 1: at most 50 per query, every one met with a finite tau_b and dis > tau_b
+    assert 0 < cal["neg_e"].shape[0] <= 50 * 1000
+    assert np.all(np.isfinite(cal["neg_tau"]))
+    m = small_index["m"]
+    assert np.all(m > 0)
+
+
+def test_heldout_false_prune_rate_matches_significance(small_index, small_workload):
+    """On fresh validation queries the fraction of true neighbours the stage tests would prune
+    (at the query's final tau) matches alpha [Sec. V-A target recall r = 1 - alpha]: alpha lies
+    in a 99% query-level bootstrap interval, widened by sqrt(2) because calibration and
+    validation are two independent query samples of the same size."""
+    rng = np.random.default_rng(9)
+    for a in [0.05, 0.1]:
+        rate, per_q = O.false_prune_rate(small_index, small_workload["val"], 10, a)
+        boots = np.array([per_q[rng.integers(0, per_q.shape[0], per_q.shape[0])].mean() / 10
+                          for _ in range(2000)])
+        lo, hi = np.quantile(boots, [0.005, 0.995])
+        half = (hi - lo) / 2 * math.sqrt(2)
+        assert abs(rate - a) <= half, (a, rate, half)
+
+
+def test_learned_pruning_scans_fewer_dims_and_keeps_recall(small_index, small_workload):
+    ix = small_index
+    Q = small_workload["queries"]
+    r0 = O.search(ix, Q, 10, 8, 0.0, mode="none")
+    r1 = O.search(ix, Q, 10, 8, 0.1)
+    S = r1["stops"].shape[1]
+    scanned = (r1["stops"] * np.arange(1, S + 1)).sum() / (r1["stops"].sum() * S)
+    assert scanned < 0.6
+    same = np.mean([len(set(a) & set(b)) / 10 for a, b in zip(r0["ids"], r1["ids"])])
+    assert same >= 0.9
+
+
+def test_rotate_orientation_gives_principal_coordinates(small_workload):
+    """y = R (x - mu): the rotated coordinates are uncorrelated and their variances are the
+    eigenvalues, largest first (a transposed R would still preserve distances but not this)."""
+    X = small_workload["base"]
+    p = O.pca_fit(X)
+    Y = O.rotate(X, p["mu"], p["R"])
+    cov = np.cov(Y.T, bias=True)
+    np.testing.assert_allclose(np.diag(cov), p["lam"], rtol=1e-9, atol=1e-12)
+    assert np.abs(cov - np.diag(np.diag(cov))).max() <= 1e-9 * p["lam"][0]
+    np.testing.assert_allclose(Y.mean(axis=0), 0, atol=1e-9)
