@@ -1,0 +1,201 @@
+/*
+ * ddc.h -- C ABI of the MI355X (gfx950) library for data-driven, PCA-based,
+ * incrementally pruned distance comparison inside an IVF nearest-neighbour
+ * search ("Effective and General Distance Computation for Approximate Nearest
+ * Neighbor Search").
+ *
+ * Problem (Sec. II-A): a set S of n points in R^D, a query q, the K points of S
+ * with the smallest squared Euclidean distance dis(p, q) = ||p - q||^2.  Candidates
+ * come from an inverted file (IVF, Sec. II-A): k-means lists, the N_probe lists
+ * whose centroids are nearest to q are scanned.  Each candidate is compared with
+ * the running K-th distance tau of the result queue (Sec. I) through the
+ * data-driven correction of Sec. V-A applied incrementally (Sec. V-B): after every
+ * block of Delta_d PCA-rotated dimensions (Sec. IV-B, Thm. 1; Alg. 2's loop) the
+ * partial distance e_s is tested with  m_s * e_s + beta_s > tau  and the candidate
+ * is pruned, otherwise refined to its exact distance.
+ *
+ * Conventions shared by every call:
+ *  - Pointers are plain host or device addresses as stated per argument; no
+ *    call keeps a caller pointer after it returns (device entry points keep them
+ *    until the work queued on the given stream has finished).
+ *  - Matrices are row-major, float32 unless stated.  Distances are squared L2
+ *    in the caller's original coordinates (rotation invariance, Eq. (1)).
+ *  - Results are ascending by (dist, id); a query with fewer than k candidates
+ *    is padded with id -1 and dist +INFINITY.
+ *  - Errors: every entry point returns a ddc_status; argument validation happens
+ *    before the first HIP call; on error the output buffers are unspecified and
+ *    ddc_last_error() describes the failure (thread-local text, valid until the
+ *    next call on the same thread).  No C++ exception crosses this boundary.
+ *  - Threads: an index is immutable after fit/import, except ddc_calibrate,
+ *    which replaces the correction table and must not overlap searches on the
+ *    same index.  Concurrent searches on one index are allowed.
+ */
+#ifndef DDC_H
+#define DDC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ddc_index ddc_index; /* opaque, library-owned; freed only by ddc_free */
+
+typedef enum {
+  DDC_OK = 0,
+  DDC_EINVAL = -1,  /* bad argument (checked before any device call) */
+  DDC_ENOMEM = -2,  /* device or host allocation failed */
+  DDC_EDEVICE = -3, /* a HIP call failed */
+  DDC_EIO = -4,     /* file error in save/load */
+  DDC_EBUSY = -5,
+  DDC_EUNSUP = -6   /* valid request this build does not implement */
+} ddc_status;
+
+/* Storage format of the rotated base vectors (the paper stores FP32, Sec. VII-A). */
+typedef enum { DDC_F32 = 0, DDC_F16 = 1, DDC_BF16 = 2 } ddc_dtype;
+
+/* Input precision of the query-rotation matrix product (FP32 accumulation either way). */
+typedef enum { DDC_ROT_F32 = 0, DDC_ROT_BF16 = 1 } ddc_rot;
+
+/* Distance correction used by the stage tests.
+ *  LEARNED : m_s * e_s + beta_s(alpha) > tau with the calibrated table (Sec. V-A, V-B)
+ *  LOSSLESS: m_s = 1, beta_s = 0 -- e_s <= dis always (sums of squares, Eq. (1)), so
+ *            the result equals NONE exactly (classic partial-distance early exit)
+ *  NONE    : no test; every candidate is refined (full-D scan)                        */
+typedef enum { DDC_CORR_LEARNED = 0, DDC_CORR_LOSSLESS = 1, DDC_CORR_NONE = 2 } ddc_corr;
+
+/* How the target recall r = 1 - alpha of label 0 (true neighbours) is split over
+ * the test stages (Sec. V-A "Adaptive Adjustment"):
+ *  JOINT      : alpha bounds the probability that a true neighbour is pruned at ANY stage
+ *  BONFERRONI : every stage gets alpha / S_t (per-stage target r_i = 1-(1-r)/(D/Delta_d)) */
+typedef enum { DDC_CALIB_JOINT = 0, DDC_CALIB_BONFERRONI = 1 } ddc_calib_mode;
+
+typedef struct {
+  int32_t nlist;          /* IVF lists (k-means centroids); paper: 4096 (Sec. VII-A) */
+  int32_t delta_d;        /* dims per stage, Delta_d (Alg. 2); 32; must be a multiple of 32 */
+  int32_t block_b;        /* tau refresh block B, candidates; multiple of 64, 64..1024; 256 */
+  int32_t lag_l;          /* tau lag L in blocks; 0 (only 0 is implemented on the GPU) */
+  int32_t kmeans_iters;   /* Lloyd iterations; 25 */
+  int32_t kmeans_train_per_list; /* k-means trains on <= this * nlist rows; 256 */
+  int32_t calib_k;        /* K_c of the label-0 pairs (KNN of each calibration query); 10 */
+  int32_t calib_nprobe;   /* N_probe of the label-1 query process; 0 = min(max(1,nlist/8),64) */
+  int32_t calib_max_neg;  /* label-1 pairs kept per calibration query; 50 */
+  ddc_dtype storage;      /* base storage format; DDC_F32 */
+  ddc_rot rotation;       /* query rotation precision; DDC_ROT_F32 */
+  int64_t pca_sample;     /* PCA rows: all if n <= this, else a SplitMix64 sample; 1,000,000 */
+  uint64_t seed;          /* SplitMix64 seed of every random choice in fit; 0 */
+} ddc_fit_params;
+
+/* Artifacts of a fitted index, host memory, for ddc_import / ddc_export.
+ * Sizes: D = dim, S = ceil(D / delta_d) stages, S_t = S - 1 test stages. */
+typedef struct {
+  int64_t n;              /* base vectors */
+  int32_t dim;            /* D */
+  int32_t nlist;
+  int32_t delta_d;
+  int32_t block_b;
+  int32_t lag_l;
+  ddc_dtype storage;
+  ddc_rot rotation;
+  double *mu;             /* [D]        centring mean (Sec. IV-B footnote) */
+  double *rot;            /* [D x D]    R, rows = eigenvectors, largest eigenvalue first */
+  double *lam;            /* [D]        eigenvalues (export only; may be NULL on import) */
+  float *centroids;       /* [nlist x D] IVF centroids in the rotated frame */
+  int32_t *assign;        /* [n]        list of every base vector; lists keep ids ascending */
+  float *y;               /* [n x D]    stored rotated base: values exactly representable in
+                                         `storage` (import rounds anything else to nearest even) */
+  int64_t n0;             /* label-0 calibration pairs */
+  double *m;              /* [S_t]      per-stage slope m_s (Sec. V-A: m = -w1/w2) */
+  double *resid;          /* [n0 x S_t] residuals g_s(j) = tau_j - m_s e_s(j) of the label-0 pairs */
+} ddc_artifacts;
+
+typedef struct {
+  int64_t n;
+  int32_t dim, dim_padded, nlist, delta_d, n_stages, n_test_stages, block_b, lag_l;
+  ddc_dtype storage;
+  ddc_rot rotation;
+  int64_t n0;
+  int64_t packed_bytes;   /* device bytes of the packed base */
+  int64_t total_tiles;    /* 64-vector tiles over all lists */
+} ddc_index_info;
+
+/* Per-call counters of the scan (sums over all queries of the call). */
+typedef struct {
+  int64_t candidates;        /* candidates met in probed lists */
+  int64_t refined;           /* candidates that reached the last stage (exact distance) */
+  int64_t stage_slices;      /* sum over candidates of stages read (one stage = Delta_d dims) */
+  int64_t bytes_touched;     /* algorithmic bytes of base data read by the scan */
+  int64_t stage_stop[64];    /* candidates whose last stage read was s (0-based; S-1 = refined) */
+} ddc_search_stats;
+
+/* Fills *p with the defaults listed above. */
+ddc_status ddc_fit_params_default(ddc_fit_params *p);
+
+/* Fit an index on the GPU (Sec. IV-B PCA, Sec. II-A IVF, Sec. V-A/V-B calibration).
+ *  base  : host [n x dim] float32, finite.   calib: host [n_calib x dim] float32 training
+ *  queries held out from base (Sec. VII-A: training queries are removed from the data).
+ *  Requires n >= nlist, 1 <= dim <= 4096, n_calib >= 1.  *out = NULL on failure. */
+ddc_status ddc_fit(const float *base, int64_t n, int32_t dim, const float *calib,
+                   int64_t n_calib, const ddc_fit_params *p, ddc_index **out);
+
+/* Build an index from artifacts (e.g. another implementation's fit).  Every array
+ * in `a` is read, none is kept.  resid/m may be NULL with n0 = 0 (then only LOSSLESS and
+ * NONE searches, or a later ddc_calibrate, are possible). */
+ddc_status ddc_import(const ddc_artifacts *a, ddc_index **out);
+
+/* Copy the artifacts out.  The caller allocates every array of `a` with the sizes from
+ * ddc_index_info (y may be NULL to skip the base).  lam is filled when known. */
+ddc_status ddc_export(const ddc_index *ix, ddc_artifacts *a);
+
+ddc_status ddc_index_get_info(const ddc_index *ix, ddc_index_info *info);
+
+/* Re-run the calibration of Sec. V-A on new training queries (e.g. ~100 out-of-distribution
+ * queries, Sec. V-C) and replace the index's correction table.  calib: host [n_calib x dim]. */
+ddc_status ddc_calibrate(ddc_index *ix, const float *calib, int64_t n_calib, int32_t calib_k,
+                         int32_t calib_nprobe, int32_t calib_max_neg, uint64_t seed);
+
+/* The correction table for a significance alpha = 1 - r (target recall r of label 0):
+ * m_out[S_t] = m_s, beta_out[S_t] = beta_s(alpha) (FP64, -INFINITY when alpha = 0). */
+ddc_status ddc_correction(const ddc_index *ix, double significance, ddc_calib_mode mode,
+                          double *m_out, double *beta_out);
+
+/* Search, host buffers.  queries: [nq x dim]; ids/dists: [nq x k].
+ * 1 <= k <= 256, 1 <= nprobe <= nlist, 0 <= significance < 1 (0: no learned pruning). */
+ddc_status ddc_search(const ddc_index *ix, const float *queries, int64_t nq, int32_t k,
+                      int32_t nprobe, double significance, ddc_corr mode, int64_t *ids,
+                      float *dists, ddc_search_stats *stats);
+
+/* Search with a K and an N_probe per query (host buffers).  k[nq], nprobe[nq];
+ * results of query i at out_offsets[i] .. out_offsets[i] + k[i] (caller-built CSR with
+ * out_offsets[i+1] - out_offsets[i] >= k[i]); ids/dists sized out_offsets[nq]. */
+ddc_status ddc_search_var(const ddc_index *ix, const float *queries, int64_t nq, const int32_t *k,
+                          const int32_t *nprobe, double significance, ddc_corr mode,
+                          const int64_t *out_offsets, int64_t *ids, float *dists,
+                          ddc_search_stats *stats);
+
+/* Search on device buffers, queued on `hip_stream` (a hipStream_t; NULL = default stream),
+ * no host synchronisation.  d_queries [nq x dim]; d_k / d_nprobe: per-query arrays or NULL
+ * to use k_all / nprobe_all; k_max / nprobe_max bound them; d_out_offsets: CSR as in
+ * ddc_search_var or NULL for dense [nq x k_all]; d_ids int64 / d_dists float32 outputs;
+ * d_counters: NULL or device int64[4 + 64] receiving ddc_search_stats' fields (added to). */
+ddc_status ddc_search_device(const ddc_index *ix, const float *d_queries, int64_t nq,
+                             const int32_t *d_k, int32_t k_all, int32_t k_max,
+                             const int32_t *d_nprobe, int32_t nprobe_all, int32_t nprobe_max,
+                             double significance, ddc_corr mode, const int64_t *d_out_offsets,
+                             int64_t *d_ids, float *d_dists, int64_t *d_counters,
+                             void *hip_stream);
+
+/* Intermediates of the first two hot-path steps for parity checks (host buffers):
+ * q_rot [nq x dim] = R (q - mu) as the search computes it; probes [nq x nprobe] in probe
+ * order (ascending centroid distance, then list id). */
+ddc_status ddc_debug_intermediates(const ddc_index *ix, const float *queries, int64_t nq,
+                                   int32_t nprobe, float *q_rot, int32_t *probes);
+
+void ddc_free(ddc_index *ix);
+const char *ddc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DDC_H */

@@ -1,0 +1,271 @@
+"""ctypes binding of include/ddc.h (argument marshalling only; every step runs in libddc.so)."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+_LOCK = threading.Lock()
+
+DTYPE = {"f32": 0, "f16": 1, "bf16": 2}
+ROT = {"f32": 0, "bf16": 1}
+CORR = {"learned": 0, "lossless": 1, "none": 2}
+CALIB = {"joint": 0, "bonferroni": 1}
+STATUS = {0: "DDC_OK", -1: "DDC_EINVAL", -2: "DDC_ENOMEM", -3: "DDC_EDEVICE", -4: "DDC_EIO",
+          -5: "DDC_EBUSY", -6: "DDC_EUNSUP"}
+
+SYMBOLS = ["ddc_fit_params_default", "ddc_fit", "ddc_import", "ddc_export", "ddc_index_get_info",
+           "ddc_calibrate", "ddc_correction", "ddc_search", "ddc_search_var", "ddc_search_device",
+           "ddc_debug_intermediates", "ddc_free", "ddc_last_error"]
+
+
+class FitParams(C.Structure):
+    _fields_ = [("nlist", C.c_int32), ("delta_d", C.c_int32), ("block_b", C.c_int32),
+                ("lag_l", C.c_int32), ("kmeans_iters", C.c_int32),
+                ("kmeans_train_per_list", C.c_int32), ("calib_k", C.c_int32),
+                ("calib_nprobe", C.c_int32), ("calib_max_neg", C.c_int32), ("storage", C.c_int),
+                ("rotation", C.c_int), ("pca_sample", C.c_int64), ("seed", C.c_uint64)]
+
+
+class Artifacts(C.Structure):
+    _fields_ = [("n", C.c_int64), ("dim", C.c_int32), ("nlist", C.c_int32), ("delta_d", C.c_int32),
+                ("block_b", C.c_int32), ("lag_l", C.c_int32), ("storage", C.c_int),
+                ("rotation", C.c_int), ("mu", C.c_void_p), ("rot", C.c_void_p), ("lam", C.c_void_p),
+                ("centroids", C.c_void_p), ("assign", C.c_void_p), ("y", C.c_void_p),
+                ("n0", C.c_int64), ("m", C.c_void_p), ("resid", C.c_void_p)]
+
+
+class IndexInfo(C.Structure):
+    _fields_ = [("n", C.c_int64), ("dim", C.c_int32), ("dim_padded", C.c_int32),
+                ("nlist", C.c_int32), ("delta_d", C.c_int32), ("n_stages", C.c_int32),
+                ("n_test_stages", C.c_int32), ("block_b", C.c_int32), ("lag_l", C.c_int32),
+                ("storage", C.c_int), ("rotation", C.c_int), ("n0", C.c_int64),
+                ("packed_bytes", C.c_int64), ("total_tiles", C.c_int64)]
+
+
+class SearchStats(C.Structure):
+    _fields_ = [("candidates", C.c_int64), ("refined", C.c_int64), ("stage_slices", C.c_int64),
+                ("bytes_touched", C.c_int64), ("stage_stop", C.c_int64 * 64)]
+
+    def as_dict(self):
+        return dict(candidates=self.candidates, refined=self.refined, stage_slices=self.stage_slices,
+                    bytes_touched=self.bytes_touched, stage_stop=list(self.stage_stop))
+
+
+class DdcError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def lib_path() -> str:
+    return os.path.join(_HERE, "libddc.so")
+
+
+def load_library():
+    """Load libddc.so; raises if it is missing (there is no fallback path)."""
+    global _LIB
+    with _LOCK:
+        if _LIB is not None:
+            return _LIB
+        p = lib_path()
+        if not os.path.exists(p):
+            raise RuntimeError(f"{p} is not built; run __graft_entry__.build() (hipcc, gfx950)")
+        lib = C.CDLL(p)
+        vp, i64, i32, f64 = C.c_void_p, C.c_int64, C.c_int32, C.c_double
+        st = C.c_int
+        lib.ddc_last_error.restype = C.c_char_p
+        lib.ddc_fit_params_default.argtypes = [C.POINTER(FitParams)]
+        lib.ddc_fit.argtypes = [vp, i64, i32, vp, i64, C.POINTER(FitParams), C.POINTER(vp)]
+        lib.ddc_import.argtypes = [C.POINTER(Artifacts), C.POINTER(vp)]
+        lib.ddc_export.argtypes = [vp, C.POINTER(Artifacts)]
+        lib.ddc_index_get_info.argtypes = [vp, C.POINTER(IndexInfo)]
+        lib.ddc_calibrate.argtypes = [vp, vp, i64, i32, i32, i32, C.c_uint64]
+        lib.ddc_correction.argtypes = [vp, f64, C.c_int, vp, vp]
+        lib.ddc_search.argtypes = [vp, vp, i64, i32, i32, f64, C.c_int, vp, vp, C.POINTER(SearchStats)]
+        lib.ddc_search_var.argtypes = [vp, vp, i64, vp, vp, f64, C.c_int, vp, vp, vp,
+                                       C.POINTER(SearchStats)]
+        lib.ddc_search_device.argtypes = [vp, vp, i64, vp, i32, i32, vp, i32, i32, f64, C.c_int, vp,
+                                          vp, vp, vp, vp]
+        lib.ddc_debug_intermediates.argtypes = [vp, vp, i64, i32, vp, vp]
+        lib.ddc_free.argtypes = [vp]
+        lib.ddc_free.restype = None
+        for name in SYMBOLS:
+            if name not in ("ddc_free", "ddc_last_error"):
+                getattr(lib, name).restype = st
+        _LIB = lib
+        return lib
+
+
+def _check(rc):
+    if rc != 0:
+        msg = load_library().ddc_last_error().decode(errors="replace")
+        raise DdcError(rc, msg)
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def default_params(**kw) -> FitParams:
+    p = FitParams()
+    _check(load_library().ddc_fit_params_default(C.byref(p)))
+    for k, v in kw.items():
+        if k == "storage":
+            v = DTYPE[v] if isinstance(v, str) else v
+        if k == "rotation":
+            v = ROT[v] if isinstance(v, str) else v
+        if not hasattr(p, k):
+            raise TypeError(f"unknown fit parameter {k}")
+        setattr(p, k, v)
+    return p
+
+
+class Index:
+    """A fitted index living on the current GPU."""
+
+    def __init__(self, handle):
+        self._h = C.c_void_p(handle)
+
+    # -- construction ------------------------------------------------------------------
+    @classmethod
+    def fit(cls, base, calib, **params) -> "Index":
+        base, calib = _f32(base), _f32(calib)
+        p = default_params(**params)
+        h = C.c_void_p()
+        _check(load_library().ddc_fit(_ptr(base), base.shape[0], base.shape[1], _ptr(calib),
+                                      calib.shape[0], C.byref(p), C.byref(h)))
+        return cls(h.value)
+
+    @classmethod
+    def from_artifacts(cls, art: dict) -> "Index":
+        """art: mu, R (rows = eigenvectors), centroids, assign, y (stored rotated base), and
+        optionally m, resid (label-0 residual matrix), lam, storage, rotation, delta_d, block_b."""
+        mu = np.ascontiguousarray(art["mu"], np.float64)
+        R = np.ascontiguousarray(art["R"], np.float64)
+        cent = _f32(art["centroids"])
+        assign = np.ascontiguousarray(art["assign"], np.int32)
+        y = _f32(art["y"])
+        a = Artifacts()
+        a.n, a.dim = y.shape
+        a.nlist = cent.shape[0]
+        a.delta_d = int(art.get("delta_d", 32))
+        a.block_b = int(art.get("block_b", 256))
+        a.lag_l = int(art.get("lag_l", 0))
+        st = art.get("storage", "f32")
+        a.storage = DTYPE[st] if isinstance(st, str) else st
+        rt = art.get("rotation", "f32")
+        a.rotation = ROT[rt] if isinstance(rt, str) else rt
+        keep = [mu, R, cent, assign, y]
+        a.mu, a.rot, a.centroids, a.assign, a.y = (_ptr(x) for x in keep)
+        lam = art.get("lam")
+        if lam is not None:
+            lam = np.ascontiguousarray(lam, np.float64)
+            keep.append(lam)
+            a.lam = _ptr(lam)
+        if art.get("resid") is not None:
+            m = np.ascontiguousarray(art["m"], np.float64)
+            G = np.ascontiguousarray(art["resid"], np.float64)
+            keep += [m, G]
+            a.m, a.resid, a.n0 = _ptr(m), _ptr(G), G.shape[0]
+        h = C.c_void_p()
+        _check(load_library().ddc_import(C.byref(a), C.byref(h)))
+        return cls(h.value)
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            load_library().ddc_free(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    # -- inspection --------------------------------------------------------------------
+    def info(self) -> dict:
+        i = IndexInfo()
+        _check(load_library().ddc_index_get_info(self._h, C.byref(i)))
+        return {f: getattr(i, f) for f, _ in IndexInfo._fields_}
+
+    def export(self, with_base: bool = True) -> dict:
+        inf = self.info()
+        n, D, nl, St, n0 = inf["n"], inf["dim"], inf["nlist"], inf["n_test_stages"], inf["n0"]
+        out = dict(mu=np.zeros(D), R=np.zeros((D, D)), lam=np.full(D, np.nan),
+                   centroids=np.zeros((nl, D), np.float32), assign=np.zeros(n, np.int32),
+                   y=np.zeros((n, D), np.float32) if with_base else None,
+                   m=np.zeros(St), resid=np.zeros((n0, St)))
+        a = Artifacts()
+        a.mu, a.rot, a.lam = _ptr(out["mu"]), _ptr(out["R"]), _ptr(out["lam"])
+        a.centroids, a.assign, a.y = _ptr(out["centroids"]), _ptr(out["assign"]), _ptr(out["y"])
+        a.m, a.resid = _ptr(out["m"]), _ptr(out["resid"])
+        _check(load_library().ddc_export(self._h, C.byref(a)))
+        out.update(delta_d=a.delta_d, block_b=a.block_b, storage=a.storage, rotation=a.rotation)
+        return out
+
+    def correction(self, alpha: float, mode: str = "joint"):
+        St = self.info()["n_test_stages"]
+        m, b = np.zeros(St), np.zeros(St)
+        _check(load_library().ddc_correction(self._h, alpha, CALIB[mode], _ptr(m), _ptr(b)))
+        return m, b
+
+    def calibrate(self, calib, calib_k=10, calib_nprobe=0, max_neg=50, seed=0):
+        calib = _f32(calib)
+        _check(load_library().ddc_calibrate(self._h, _ptr(calib), calib.shape[0], calib_k,
+                                            calib_nprobe, max_neg, seed))
+
+    # -- search ------------------------------------------------------------------------
+    def search(self, queries, k: int, nprobe: int, alpha: float, mode: str = "learned"):
+        q = _f32(queries)
+        nq = q.shape[0]
+        ids = np.empty((nq, k), np.int64)
+        d = np.empty((nq, k), np.float32)
+        st = SearchStats()
+        _check(load_library().ddc_search(self._h, _ptr(q), nq, k, nprobe, alpha, CORR[mode],
+                                         _ptr(ids), _ptr(d), C.byref(st)))
+        return ids, d, st.as_dict()
+
+    def search_var(self, queries, k, nprobe, alpha: float, mode: str = "learned"):
+        q = _f32(queries)
+        k = np.ascontiguousarray(k, np.int32)
+        nprobe = np.ascontiguousarray(nprobe, np.int32)
+        off = np.zeros(q.shape[0] + 1, np.int64)
+        off[1:] = np.cumsum(k)
+        ids = np.empty(off[-1], np.int64)
+        d = np.empty(off[-1], np.float32)
+        st = SearchStats()
+        _check(load_library().ddc_search_var(self._h, _ptr(q), q.shape[0], _ptr(k), _ptr(nprobe),
+                                             alpha, CORR[mode], _ptr(off), _ptr(ids), _ptr(d),
+                                             C.byref(st)))
+        return ids, d, off, st.as_dict()
+
+    def search_device(self, d_queries, nq, k_all, nprobe_all, alpha, mode, d_ids, d_dists,
+                      d_counters=0, stream=0, d_k=0, k_max=0, d_nprobe=0, nprobe_max=0,
+                      d_offsets=0):
+        """Device pointers (ints, e.g. torch tensors' data_ptr()) and a hipStream_t handle."""
+        _check(load_library().ddc_search_device(
+            self._h, d_queries, nq, d_k or None, k_all, k_max, d_nprobe or None, nprobe_all,
+            nprobe_max, alpha, CORR[mode], d_offsets or None, d_ids, d_dists, d_counters or None,
+            stream or None))
+
+    def debug_intermediates(self, queries, nprobe: int):
+        q = _f32(queries)
+        D = self.info()["dim"]
+        qr = np.empty((q.shape[0], D), np.float32)
+        pr = np.empty((q.shape[0], nprobe), np.int32)
+        _check(load_library().ddc_debug_intermediates(self._h, _ptr(q), q.shape[0], nprobe,
+                                                      _ptr(qr), _ptr(pr)))
+        return qr, pr

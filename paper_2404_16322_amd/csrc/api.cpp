@@ -1,0 +1,1019 @@
+// Host runtime behind include/ddc.h: index construction (GPU fit or import), the search
+// pipeline (rotation GEMM -> coarse GEMM -> probe selection -> pruned scan), calibration.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <numeric>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "ddc.h"
+#include "ddc_internal.h"
+#include "host_math.h"
+
+using namespace ddc;
+
+// ---------------------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------------------
+static thread_local std::string g_err;
+
+static ddc_status set_err(ddc_status st, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+struct DdcError : std::runtime_error {
+  ddc_status st;
+  DdcError(ddc_status s, const std::string &m) : std::runtime_error(m), st(s) {}
+};
+
+#define HIPC(expr)                                                                          \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess)                                                                   \
+      throw DdcError(e_ == hipErrorOutOfMemory ? DDC_ENOMEM : DDC_EDEVICE,                  \
+                     std::string(#expr) + ": " + hipGetErrorString(e_));                    \
+  } while (0)
+
+#define GUARD_BEGIN try {
+#define GUARD_END                                                        \
+  }                                                                      \
+  catch (const DdcError &e) { return set_err(e.st, "%s", e.what()); }   \
+  catch (const std::bad_alloc &) { return set_err(DDC_ENOMEM, "host allocation failed"); } \
+  catch (const std::exception &e) { return set_err(DDC_EDEVICE, "%s", e.what()); }
+
+// ---------------------------------------------------------------------------------------
+// device memory
+// ---------------------------------------------------------------------------------------
+struct DevBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  explicit DevBuf(size_t b) { alloc(b); }
+  DevBuf(const DevBuf &) = delete;
+  DevBuf &operator=(const DevBuf &) = delete;
+  DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  void alloc(size_t b) {
+    release();
+    if (b) HIPC(hipMalloc(&p, b));
+    bytes = b;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  ~DevBuf() { release(); }
+  template <class T> T *as() const { return reinterpret_cast<T *>(p); }
+};
+
+struct DeviceGuard {
+  int prev = 0;
+  explicit DeviceGuard(int dev) {
+    (void)hipGetDevice(&prev);
+    if (prev != dev) HIPC(hipSetDevice(dev));
+  }
+  ~DeviceGuard() { (void)hipSetDevice(prev); }
+};
+
+struct StreamHolder {
+  hipStream_t s = nullptr;
+  StreamHolder() { HIPC(hipStreamCreateWithFlags(&s, hipStreamNonBlocking)); }
+  ~StreamHolder() {
+    if (s) (void)hipStreamDestroy(s);
+  }
+};
+
+static void set_pool_retain(int dev) {
+  static std::mutex mtx;
+  static std::vector<int> done;
+  std::lock_guard<std::mutex> lk(mtx);
+  if (std::find(done.begin(), done.end(), dev) != done.end()) return;
+  hipMemPool_t pool;
+  if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+    uint64_t thr = std::numeric_limits<uint64_t>::max();
+    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+  }
+  done.push_back(dev);
+}
+
+// stream-ordered scratch (returned to the pool when the stream reaches the free)
+struct AsyncBuf {
+  void *p = nullptr;
+  hipStream_t s = nullptr;
+  AsyncBuf(size_t bytes, hipStream_t st) : s(st) {
+    if (bytes) HIPC(hipMallocAsync(&p, bytes, st));
+  }
+  ~AsyncBuf() {
+    if (p) (void)hipFreeAsync(p, s);
+  }
+  template <class T> T *as() const { return reinterpret_cast<T *>(p); }
+};
+
+// ---------------------------------------------------------------------------------------
+// index
+// ---------------------------------------------------------------------------------------
+struct ddc_index {
+  int device = 0;
+  int64_t n = 0;
+  int D = 0, Dp = 0, NB = 0, nlist = 0, delta_d = 32, S = 0, St = 0, B = 256, L = 0;
+  ddc_dtype storage = DDC_F32;
+  ddc_rot rot = DDC_ROT_F32;
+  std::vector<double> mu, R, lam;
+  std::vector<float> cent;          // nlist x D
+  std::vector<int32_t> assign;      // n
+  std::vector<int32_t> list_len, tile_off;
+  std::vector<int64_t> id_to_slot;  // n
+  int64_t total_tiles = 0;
+  std::vector<double> m, resid;     // St ; n0 x St
+  int64_t n0 = 0;
+  std::mutex beta_mtx;
+  std::map<std::pair<double, int>, std::vector<double>> beta_cache;
+  DevBuf d_R32, d_mu32, d_cent, d_cnorm, d_tile_off, d_list_len, d_ids, d_base, d_R64, d_mu64;
+
+  int store() const { return storage == DDC_F32 ? ST_F32 : storage == DDC_F16 ? ST_F16 : ST_BF16; }
+  int esize() const { return storage == DDC_F32 ? 4 : 2; }
+};
+
+static int stage_count(int D, int dd) { return (D + dd - 1) / dd; }
+
+// Lists keep ids ascending; list j occupies ceil(len_j / 64) tiles starting at tile_off[j].
+static void build_lists(ddc_index *ix, std::vector<int64_t> &slot_row) {
+  const int nl = ix->nlist;
+  ix->list_len.assign(nl, 0);
+  for (int64_t i = 0; i < ix->n; ++i) ix->list_len[ix->assign[i]]++;
+  ix->tile_off.assign(nl + 1, 0);
+  for (int j = 0; j < nl; ++j) ix->tile_off[j + 1] = ix->tile_off[j] + (ix->list_len[j] + kTile - 1) / kTile;
+  ix->total_tiles = ix->tile_off[nl];
+  slot_row.assign((size_t)ix->total_tiles * kTile, -1);
+  ix->id_to_slot.assign(ix->n, -1);
+  std::vector<int32_t> fill(nl, 0);
+  for (int64_t i = 0; i < ix->n; ++i) {
+    const int j = ix->assign[i];
+    const int64_t slot = (int64_t)ix->tile_off[j] * kTile + fill[j]++;
+    slot_row[slot] = i;
+    ix->id_to_slot[i] = slot;
+  }
+}
+
+// Upload rotation, centroids, list tables and pack the rotated base Y (device, n x Dp).
+static void upload_index(ddc_index *ix, const float *d_Y, hipStream_t s) {
+  const int D = ix->D, Dp = ix->Dp;
+  std::vector<float> R32((size_t)Dp * Dp, 0.f), mu32(Dp, 0.f);
+  for (int i = 0; i < D; ++i) {
+    mu32[i] = (float)ix->mu[i];
+    for (int j = 0; j < D; ++j) R32[(size_t)i * Dp + j] = (float)ix->R[(size_t)i * D + j];
+  }
+  ix->d_R32.alloc(R32.size() * 4);
+  ix->d_mu32.alloc(mu32.size() * 4);
+  HIPC(hipMemcpy(ix->d_R32.p, R32.data(), R32.size() * 4, hipMemcpyHostToDevice));
+  HIPC(hipMemcpy(ix->d_mu32.p, mu32.data(), mu32.size() * 4, hipMemcpyHostToDevice));
+  ix->d_R64.alloc((size_t)D * D * 8);
+  ix->d_mu64.alloc((size_t)D * 8);
+  HIPC(hipMemcpy(ix->d_R64.p, ix->R.data(), (size_t)D * D * 8, hipMemcpyHostToDevice));
+  HIPC(hipMemcpy(ix->d_mu64.p, ix->mu.data(), (size_t)D * 8, hipMemcpyHostToDevice));
+
+  std::vector<float> cp((size_t)ix->nlist * Dp, 0.f), cn(ix->nlist);
+  for (int j = 0; j < ix->nlist; ++j) {
+    double s2 = 0.0;
+    for (int d = 0; d < D; ++d) {
+      const float v = ix->cent[(size_t)j * D + d];
+      cp[(size_t)j * Dp + d] = v;
+      s2 += (double)v * v;
+    }
+    cn[j] = (float)s2;
+  }
+  ix->d_cent.alloc(cp.size() * 4);
+  ix->d_cnorm.alloc(cn.size() * 4);
+  HIPC(hipMemcpy(ix->d_cent.p, cp.data(), cp.size() * 4, hipMemcpyHostToDevice));
+  HIPC(hipMemcpy(ix->d_cnorm.p, cn.data(), cn.size() * 4, hipMemcpyHostToDevice));
+
+  std::vector<int64_t> slot_row;
+  build_lists(ix, slot_row);
+  std::vector<int32_t> ids(slot_row.size());
+  for (size_t i = 0; i < slot_row.size(); ++i) ids[i] = (int32_t)slot_row[i];
+  ix->d_tile_off.alloc(ix->tile_off.size() * 4);
+  ix->d_list_len.alloc(ix->list_len.size() * 4);
+  ix->d_ids.alloc(std::max<size_t>(ids.size(), 1) * 4);
+  HIPC(hipMemcpy(ix->d_tile_off.p, ix->tile_off.data(), ix->tile_off.size() * 4, hipMemcpyHostToDevice));
+  HIPC(hipMemcpy(ix->d_list_len.p, ix->list_len.data(), ix->list_len.size() * 4, hipMemcpyHostToDevice));
+  if (!ids.empty()) HIPC(hipMemcpy(ix->d_ids.p, ids.data(), ids.size() * 4, hipMemcpyHostToDevice));
+  DevBuf d_slot(std::max<size_t>(slot_row.size(), 1) * 8);
+  if (!slot_row.empty())
+    HIPC(hipMemcpy(d_slot.p, slot_row.data(), slot_row.size() * 8, hipMemcpyHostToDevice));
+  const size_t packed = (size_t)ix->total_tiles * ix->NB * kTile * kBlockDims * ix->esize();
+  ix->d_base.alloc(std::max<size_t>(packed, 16));
+  launch_pack(d_Y, Dp, D, ix->NB, d_slot.as<int64_t>(), ix->total_tiles, ix->d_base.p, ix->store(), s);
+  HIPC(hipGetLastError());
+  HIPC(hipStreamSynchronize(s));
+}
+
+static bool all_finite(const float *x, int64_t cnt) {
+  for (int64_t i = 0; i < cnt; ++i)
+    if (!std::isfinite(x[i])) return false;
+  return true;
+}
+
+// ---------------------------------------------------------------------------------------
+// calibration (Sec. V-A): label 0 = the calib_k nearest stored vectors of every training
+// query (tau = K_c-th distance), label 1 = candidates met by an unpruned canonical IVF search
+// with a finite tau_b and dis > tau_b (<= max_neg per query, smallest SplitMix64 keys).
+// Per test stage a logistic regression on (e_s, tau) gives m_s; the residuals
+// g_s = tau - m_s e_s of the label-0 pairs are kept for the target-recall adjustment.
+// ---------------------------------------------------------------------------------------
+static void run_calibration(ddc_index *ix, const float *calib, int64_t nc, int kc, int nprobe_c,
+                            int max_neg, uint64_t seed, hipStream_t s) {
+  const int D = ix->D, Dp = ix->Dp, St = ix->St;
+  DevBuf d_c((size_t)nc * D * 4);
+  HIPC(hipMemcpyAsync(d_c.p, calib, (size_t)nc * D * 4, hipMemcpyHostToDevice, s));
+  DevBuf d_q64((size_t)nc * D * 8);
+  launch_rotate64(d_c.as<float>(), nc, D, ix->d_mu64.as<double>(), ix->d_R64.as<double>(),
+                  d_q64.as<double>(), s);
+
+  // -- exact K_c-NN: FP32 unpruned scan over all lists for a candidate superset, FP64 refine
+  const int kp = std::min(kMaxK, std::max(4 * kc, kc + 32));
+  DevBuf d_q32((size_t)nc * Dp * 4);
+  {
+    GemmArgs g{};
+    g.A = d_c.as<float>(); g.lda = D; g.mu = ix->d_mu32.as<float>();
+    g.B = ix->d_R32.as<float>(); g.ldb = Dp; g.C = d_q32.as<float>(); g.ldc = Dp;
+    g.M = nc; g.N = Dp; g.K = D; g.mode = 0; g.prec = 0;
+    launch_gemm(g, s);
+  }
+  std::vector<int32_t> iota((size_t)nc * ix->nlist);
+  for (int64_t q = 0; q < nc; ++q)
+    for (int j = 0; j < ix->nlist; ++j) iota[(size_t)q * ix->nlist + j] = j;
+  DevBuf d_all((size_t)nc * ix->nlist * 4);
+  HIPC(hipMemcpyAsync(d_all.p, iota.data(), iota.size() * 4, hipMemcpyHostToDevice, s));
+  DevBuf d_cid((size_t)nc * kp * 8), d_cd((size_t)nc * kp * 4);
+  {
+    ScanArgs a{};
+    a.qrot = d_q32.as<float>(); a.q_stride = Dp;
+    a.probes = d_all.as<int32_t>(); a.p_stride = ix->nlist; a.nprobe_all = ix->nlist;
+    a.k_all = kp; a.tile_off = ix->d_tile_off.as<int32_t>(); a.list_len = ix->d_list_len.as<int32_t>();
+    a.base = ix->d_base.p; a.ids = ix->d_ids.as<int32_t>();
+    a.out_ids = d_cid.as<int64_t>(); a.out_d = d_cd.as<float>();
+    a.nq = (int32_t)nc; a.nblocks = ix->NB; a.block_b = ix->B; a.prune = 0; a.nlist = ix->nlist;
+    launch_scan(a, ix->store(), s);
+  }
+  std::vector<int64_t> cid((size_t)nc * kp);
+  std::vector<float> cd((size_t)nc * kp);
+  HIPC(hipMemcpyAsync(cid.data(), d_cid.p, cid.size() * 8, hipMemcpyDeviceToHost, s));
+  HIPC(hipMemcpyAsync(cd.data(), d_cd.p, cd.size() * 4, hipMemcpyDeviceToHost, s));
+  HIPC(hipStreamSynchronize(s));
+  std::vector<int64_t> cslot(cid.size());
+  for (size_t i = 0; i < cid.size(); ++i) cslot[i] = cid[i] >= 0 ? ix->id_to_slot[cid[i]] : -1;
+  DevBuf d_cs(cslot.size() * 8), d_c64(cslot.size() * 8);
+  HIPC(hipMemcpyAsync(d_cs.p, cslot.data(), cslot.size() * 8, hipMemcpyHostToDevice, s));
+  launch_refine64(d_q64.as<double>(), D, ix->d_base.p, ix->store(), ix->NB, d_cs.as<int64_t>(), kp,
+                  nc, d_c64.as<double>(), s);
+  std::vector<double> c64(cslot.size());
+  HIPC(hipMemcpyAsync(c64.data(), d_c64.p, c64.size() * 8, hipMemcpyDeviceToHost, s));
+  std::vector<double> q64((size_t)nc * D);
+  HIPC(hipMemcpyAsync(q64.data(), d_q64.p, q64.size() * 8, hipMemcpyDeviceToHost, s));
+  HIPC(hipStreamSynchronize(s));
+
+  std::vector<int32_t> pair_q;
+  std::vector<int64_t> pair_slot;
+  std::vector<double> pair_tau;
+  std::vector<int64_t> all_slots;  // for the rare full-FP64 fallback
+  for (int64_t q = 0; q < nc; ++q) {
+    std::vector<std::pair<double, int64_t>> c;  // (d64, id)
+    for (int t = 0; t < kp; ++t)
+      if (cid[q * kp + t] >= 0) c.push_back({c64[q * kp + t], cid[q * kp + t]});
+    std::sort(c.begin(), c.end());
+    const int got = (int)c.size();
+    bool exact = got >= kc;
+    if (exact && got == kp) {
+      // any vector outside the FP32 superset has FP32 distance >= the last one kept
+      double qn = 0;
+      for (int d = 0; d < D; ++d) qn += q64[q * D + d] * q64[q * D + d];
+      const double last32 = cd[q * kp + kp - 1];
+      exact = c[kc - 1].first * (1.0 + 1e-3) + 1e-6 * qn < last32;
+    }
+    if (!exact && got < std::min<int64_t>(kc, ix->n)) exact = got == ix->n;
+    if (!exact) {
+      // FP64 over every stored vector for this query
+      if (all_slots.empty())
+        for (int64_t i = 0; i < ix->n; ++i) all_slots.push_back(ix->id_to_slot[i]);
+      DevBuf d_as(all_slots.size() * 8), d_ad(all_slots.size() * 8);
+      HIPC(hipMemcpyAsync(d_as.p, all_slots.data(), all_slots.size() * 8, hipMemcpyHostToDevice, s));
+      launch_refine64(d_q64.as<double>() + q * D, D, ix->d_base.p, ix->store(), ix->NB,
+                      d_as.as<int64_t>(), (int32_t)all_slots.size(), 1, d_ad.as<double>(), s);
+      std::vector<double> ad(all_slots.size());
+      HIPC(hipMemcpyAsync(ad.data(), d_ad.p, ad.size() * 8, hipMemcpyDeviceToHost, s));
+      HIPC(hipStreamSynchronize(s));
+      c.clear();
+      for (int64_t i = 0; i < ix->n; ++i) c.push_back({ad[i], i});
+      std::partial_sort(c.begin(), c.begin() + std::min<int64_t>(kc, ix->n), c.end());
+    }
+    const int take = std::min<int>(kc, (int)c.size());
+    if (take < kc) throw DdcError(DDC_EINVAL, "calibration needs at least calib_k base vectors");
+    const double tau = c[kc - 1].first;
+    for (int t = 0; t < kc; ++t) {
+      pair_q.push_back((int32_t)q);
+      pair_slot.push_back(ix->id_to_slot[c[t].second]);
+      pair_tau.push_back(tau);
+    }
+  }
+  const int64_t n0 = (int64_t)pair_q.size();
+
+  // -- label 1: probes (FP64 centroid distances, ascending by (d, list)), FP64 canonical search
+  DevBuf d_cd64((size_t)nc * ix->nlist * 8);
+  launch_cdist64(d_q64.as<double>(), nc, D, ix->d_cent.as<float>(), Dp, ix->nlist, d_cd64.as<double>(), s);
+  std::vector<double> cd64((size_t)nc * ix->nlist);
+  HIPC(hipMemcpyAsync(cd64.data(), d_cd64.p, cd64.size() * 8, hipMemcpyDeviceToHost, s));
+  HIPC(hipStreamSynchronize(s));
+  std::vector<int32_t> probes((size_t)nc * nprobe_c);
+  {
+    std::vector<int32_t> ord(ix->nlist);
+    for (int64_t q = 0; q < nc; ++q) {
+      std::iota(ord.begin(), ord.end(), 0);
+      const double *row = &cd64[(size_t)q * ix->nlist];
+      std::partial_sort(ord.begin(), ord.begin() + nprobe_c, ord.end(), [&](int a, int b) {
+        return row[a] < row[b] || (row[a] == row[b] && a < b);
+      });
+      for (int p = 0; p < nprobe_c; ++p) probes[(size_t)q * nprobe_c + p] = ord[p];
+    }
+  }
+  DevBuf d_pr(probes.size() * 4), d_ns((size_t)nc * max_neg * 8), d_nt((size_t)nc * max_neg * 8);
+  HIPC(hipMemcpyAsync(d_pr.p, probes.data(), probes.size() * 4, hipMemcpyHostToDevice, s));
+  {
+    NegArgs a{};
+    a.qrot = d_q64.as<double>(); a.D = D; a.probes = d_pr.as<int32_t>(); a.nprobe = nprobe_c;
+    a.tile_off = ix->d_tile_off.as<int32_t>(); a.list_len = ix->d_list_len.as<int32_t>();
+    a.base = ix->d_base.p; a.store = ix->store(); a.nblocks = ix->NB; a.ids = ix->d_ids.as<int32_t>();
+    a.k = kc; a.block_b = ix->B; a.max_neg = max_neg;
+    a.key_base = splitmix64(seed + TAG_NEG); a.nq = nc;
+    a.neg_slot = d_ns.as<int64_t>(); a.neg_tau = d_nt.as<double>();
+    launch_negatives64(a, s);
+  }
+  std::vector<int64_t> ns((size_t)nc * max_neg);
+  std::vector<double> nt((size_t)nc * max_neg);
+  HIPC(hipMemcpyAsync(ns.data(), d_ns.p, ns.size() * 8, hipMemcpyDeviceToHost, s));
+  HIPC(hipMemcpyAsync(nt.data(), d_nt.p, nt.size() * 8, hipMemcpyDeviceToHost, s));
+  HIPC(hipStreamSynchronize(s));
+  for (int64_t q = 0; q < nc; ++q)
+    for (int t = 0; t < max_neg; ++t) {
+      const int64_t sl = ns[q * max_neg + t];
+      if (sl < 0) continue;
+      pair_q.push_back((int32_t)q);
+      pair_slot.push_back(sl);
+      pair_tau.push_back(nt[q * max_neg + t]);
+    }
+  const int64_t npairs = (int64_t)pair_q.size();
+  const int64_t n1 = npairs - n0;
+
+  // -- features e_s at every test stage (FP64)
+  std::vector<int32_t> send(St);
+  for (int t = 0; t < St; ++t) send[t] = ((t + 1) * ix->delta_d) / kBlockDims;
+  std::vector<double> feat((size_t)npairs * std::max(St, 1));
+  if (St > 0) {
+    DevBuf d_pq(npairs * 4), d_ps(npairs * 8), d_se(St * 4), d_f((size_t)npairs * St * 8);
+    HIPC(hipMemcpyAsync(d_pq.p, pair_q.data(), npairs * 4, hipMemcpyHostToDevice, s));
+    HIPC(hipMemcpyAsync(d_ps.p, pair_slot.data(), npairs * 8, hipMemcpyHostToDevice, s));
+    HIPC(hipMemcpyAsync(d_se.p, send.data(), St * 4, hipMemcpyHostToDevice, s));
+    launch_features64(d_q64.as<double>(), D, ix->d_base.p, ix->store(), ix->NB, d_pq.as<int32_t>(),
+                      d_ps.as<int64_t>(), npairs, d_se.as<int32_t>(), St, d_f.as<double>(), s);
+    HIPC(hipMemcpyAsync(feat.data(), d_f.p, (size_t)npairs * St * 8, hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+  }
+  HIPC(hipGetLastError());
+
+  // -- per stage logistic regression -> m_s ; residuals of label 0
+  std::vector<double> m(St, 1.0);
+  for (int t = 0; t < St && n1 > 0; ++t) {
+    std::vector<double> F((size_t)npairs * 2), y(npairs);
+    for (int64_t p = 0; p < npairs; ++p) {
+      F[2 * p] = feat[(size_t)p * St + t];
+      F[2 * p + 1] = pair_tau[p];
+      y[p] = p < n0 ? 0.0 : 1.0;
+    }
+    double b, w1, w2;
+    logistic_fit(F, y, b, w1, w2);
+    if (w2 < 0 && -w1 / w2 > 0) m[t] = -w1 / w2;
+  }
+  std::vector<double> G((size_t)n0 * St);
+  for (int64_t j = 0; j < n0; ++j)
+    for (int t = 0; t < St; ++t) G[(size_t)j * St + t] = pair_tau[j] - m[t] * feat[(size_t)j * St + t];
+  {
+    std::lock_guard<std::mutex> lk(ix->beta_mtx);
+    ix->m = m;
+    ix->resid = G;
+    ix->n0 = n0;
+    ix->beta_cache.clear();
+  }
+}
+
+static std::vector<double> get_beta(ddc_index *ix, double alpha, int mode) {
+  std::lock_guard<std::mutex> lk(ix->beta_mtx);
+  auto key = std::make_pair(alpha, mode);
+  auto it = ix->beta_cache.find(key);
+  if (it != ix->beta_cache.end()) return it->second;
+  auto b = beta_for_alpha(ix->resid, ix->n0, ix->St, alpha, mode);
+  ix->beta_cache[key] = b;
+  return b;
+}
+
+// ---------------------------------------------------------------------------------------
+// search pipeline
+// ---------------------------------------------------------------------------------------
+static void search_device(ddc_index *ix, const float *d_q, int64_t nq, const int32_t *d_k, int k_all,
+                          int k_max, const int32_t *d_np, int np_all, int np_max, double alpha,
+                          ddc_corr mode, const int64_t *d_off, int64_t *d_ids, float *d_d,
+                          int64_t *d_ctr, hipStream_t s, float *qrot_out = nullptr,
+                          int32_t *probes_out = nullptr) {
+  const int Dp = ix->Dp, D = ix->D;
+  ScanArgs a{};
+  a.prune = 0;
+  if (ix->St > 0) {
+    std::vector<double> mm(ix->St), bb(ix->St);
+    if (mode == DDC_CORR_LEARNED && alpha > 0) {
+      mm = ix->m;
+      bb = get_beta(ix, alpha, DDC_CALIB_JOINT);
+      a.prune = 1;
+    } else if (mode == DDC_CORR_LOSSLESS) {
+      std::fill(mm.begin(), mm.end(), 1.0);
+      std::fill(bb.begin(), bb.end(), 0.0);
+      a.prune = 1;
+    }
+    if (a.prune)
+      for (int t = 0; t < ix->St; ++t) {
+        const int b = ((t + 1) * ix->delta_d) / kBlockDims - 1;
+        a.test_after[b] = 1;
+        a.m[b] = (float)mm[t];
+        a.beta[b] = (float)bb[t];
+      }
+  }
+  const int64_t chunk = 32768;
+  for (int64_t q0 = 0; q0 < nq; q0 += chunk) {
+    const int64_t nqc = std::min(chunk, nq - q0);
+    AsyncBuf qrot((size_t)nqc * Dp * 4, s), cdist((size_t)nqc * ix->nlist * 4, s),
+        probes((size_t)nqc * np_max * 4, s);
+    GemmArgs g{};
+    g.A = d_q + q0 * D; g.lda = D; g.mu = ix->d_mu32.as<float>();
+    g.B = ix->d_R32.as<float>(); g.ldb = Dp; g.C = qrot.as<float>(); g.ldc = Dp;
+    g.M = nqc; g.N = Dp; g.K = D; g.mode = 0; g.prec = ix->rot == DDC_ROT_BF16 ? 1 : 0;
+    launch_gemm(g, s);
+    GemmArgs c{};
+    c.A = qrot.as<float>(); c.lda = Dp; c.mu = nullptr; c.B = ix->d_cent.as<float>(); c.ldb = Dp;
+    c.bias = ix->d_cnorm.as<float>(); c.C = cdist.as<float>(); c.ldc = ix->nlist;
+    c.M = nqc; c.N = ix->nlist; c.K = Dp; c.mode = 1; c.prec = 0;
+    launch_gemm(c, s);
+    launch_select(cdist.as<float>(), ix->nlist, ix->nlist, d_np ? d_np + q0 : nullptr, np_all, np_max,
+                  probes.as<int32_t>(), np_max, nqc, s);
+    if (qrot_out) {
+      HIPC(hipMemcpy2DAsync(qrot_out + q0 * D, D * 4, qrot.p, Dp * 4, D * 4, nqc,
+                            hipMemcpyDeviceToHost, s));
+      HIPC(hipMemcpyAsync(probes_out + q0 * np_max, probes.p, (size_t)nqc * np_max * 4,
+                          hipMemcpyDeviceToHost, s));
+      HIPC(hipStreamSynchronize(s));
+      continue;
+    }
+    a.qrot = qrot.as<float>(); a.q_stride = Dp;
+    a.probes = probes.as<int32_t>(); a.p_stride = np_max;
+    a.nprobe = d_np ? d_np + q0 : nullptr; a.nprobe_all = np_all;
+    a.k = d_k ? d_k + q0 : nullptr; a.k_all = k_all;
+    a.out_off = d_off ? d_off + q0 : nullptr;
+    a.tile_off = ix->d_tile_off.as<int32_t>(); a.list_len = ix->d_list_len.as<int32_t>();
+    a.base = ix->d_base.p; a.ids = ix->d_ids.as<int32_t>();
+    a.out_ids = d_off ? d_ids : d_ids + q0 * k_all;
+    a.out_d = d_off ? d_d : d_d + q0 * k_all;
+    a.counters = d_ctr;
+    a.nq = (int32_t)nqc; a.nblocks = ix->NB; a.block_b = ix->B; a.nlist = ix->nlist;
+    launch_scan(a, ix->store(), s);
+    (void)k_max;
+  }
+  HIPC(hipGetLastError());
+}
+
+static void stats_from_counters(const ddc_index *ix, const int64_t *c, ddc_search_stats *st) {
+  std::memset(st, 0, sizeof *st);
+  st->candidates = c[0];
+  st->refined = c[1];
+  st->stage_slices = c[2];
+  st->bytes_touched = c[2] * (int64_t)kBlockDims * ix->esize();
+  for (int i = 0; i < 64; ++i) st->stage_stop[i] = c[4 + i];
+}
+
+// ---------------------------------------------------------------------------------------
+// validation helpers
+// ---------------------------------------------------------------------------------------
+static ddc_status check_search_args(const ddc_index *ix, int64_t nq, double alpha, ddc_corr mode) {
+  if (!ix) return set_err(DDC_EINVAL, "index is NULL");
+  if (nq < 0) return set_err(DDC_EINVAL, "nq must be >= 0");
+  if (!(alpha >= 0.0 && alpha < 1.0)) return set_err(DDC_EINVAL, "significance must be in [0, 1)");
+  if (mode != DDC_CORR_LEARNED && mode != DDC_CORR_LOSSLESS && mode != DDC_CORR_NONE)
+    return set_err(DDC_EINVAL, "unknown correction mode %d", (int)mode);
+  if (mode == DDC_CORR_LEARNED && alpha > 0 && ix->St > 0 && ix->n0 == 0)
+    return set_err(DDC_EINVAL, "index has no calibrated correction table (use LOSSLESS/NONE or calibrate)");
+  return DDC_OK;
+}
+
+static ddc_status check_k_np(const ddc_index *ix, int k, int np) {
+  if (k < 1 || k > kMaxK) return set_err(DDC_EINVAL, "k must be in [1, %d], got %d", kMaxK, k);
+  if (np < 1 || np > ix->nlist) return set_err(DDC_EINVAL, "nprobe must be in [1, nlist=%d], got %d", ix->nlist, np);
+  if (np > 4096) return set_err(DDC_EUNSUP, "nprobe > 4096 is not supported");
+  return DDC_OK;
+}
+
+static ddc_status check_params(const ddc_fit_params *p, int64_t n, int dim) {
+  if (!p) return set_err(DDC_EINVAL, "params is NULL");
+  if (dim < 1 || dim > kMaxBlocks * kBlockDims) return set_err(DDC_EINVAL, "dim must be in [1, 4096]");
+  if (p->nlist < 1 || p->nlist > 65536) return set_err(DDC_EINVAL, "nlist must be in [1, 65536]");
+  if (n < p->nlist) return set_err(DDC_EINVAL, "need n >= nlist");
+  if (p->delta_d < kBlockDims || p->delta_d % kBlockDims) return set_err(DDC_EINVAL, "delta_d must be a positive multiple of 32");
+  if (p->block_b < 64 || p->block_b > 1024 || p->block_b % 64) return set_err(DDC_EINVAL, "block_b must be a multiple of 64 in [64, 1024]");
+  if (p->lag_l != 0) return set_err(DDC_EUNSUP, "only lag_l = 0 is implemented");
+  if (p->kmeans_iters < 0 || p->kmeans_train_per_list < 1) return set_err(DDC_EINVAL, "bad k-means parameters");
+  if (p->calib_k < 1 || p->calib_k > 64) return set_err(DDC_EINVAL, "calib_k must be in [1, 64]");
+  if (p->calib_nprobe < 0 || p->calib_nprobe > p->nlist) return set_err(DDC_EINVAL, "calib_nprobe must be in [0, nlist]");
+  if (p->calib_max_neg < 1 || p->calib_max_neg > 256) return set_err(DDC_EINVAL, "calib_max_neg must be in [1, 256]");
+  if (p->storage != DDC_F32 && p->storage != DDC_F16 && p->storage != DDC_BF16) return set_err(DDC_EINVAL, "bad storage");
+  if (p->rotation != DDC_ROT_F32 && p->rotation != DDC_ROT_BF16) return set_err(DDC_EINVAL, "bad rotation");
+  if (p->pca_sample < 2) return set_err(DDC_EINVAL, "pca_sample must be >= 2");
+  return DDC_OK;
+}
+
+static void init_sizes(ddc_index *ix, int64_t n, int D, int nlist, int dd, int B, int L, ddc_dtype st,
+                       ddc_rot rot) {
+  ix->n = n; ix->D = D; ix->nlist = nlist; ix->delta_d = dd; ix->B = B; ix->L = L;
+  ix->storage = st; ix->rot = rot;
+  ix->NB = (D + kBlockDims - 1) / kBlockDims;
+  ix->Dp = ix->NB * kBlockDims;
+  ix->S = stage_count(D, dd);
+  ix->St = ix->S - 1;
+  (void)hipGetDevice(&ix->device);
+  set_pool_retain(ix->device);
+}
+
+// ---------------------------------------------------------------------------------------
+// ABI
+// ---------------------------------------------------------------------------------------
+extern "C" {
+
+const char *ddc_last_error(void) { return g_err.c_str(); }
+
+ddc_status ddc_fit_params_default(ddc_fit_params *p) {
+  if (!p) return set_err(DDC_EINVAL, "params is NULL");
+  std::memset(p, 0, sizeof *p);
+  p->nlist = 4096; p->delta_d = 32; p->block_b = 256; p->lag_l = 0;
+  p->kmeans_iters = 25; p->kmeans_train_per_list = 256;
+  p->calib_k = 10; p->calib_nprobe = 0; p->calib_max_neg = 50;
+  p->storage = DDC_F32; p->rotation = DDC_ROT_F32;
+  p->pca_sample = 1000000; p->seed = 0;
+  return DDC_OK;
+}
+
+void ddc_free(ddc_index *ix) {
+  if (!ix) return;
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  (void)hipSetDevice(ix->device);
+  delete ix;
+  (void)hipSetDevice(prev);
+}
+
+ddc_status ddc_index_get_info(const ddc_index *ix, ddc_index_info *info) {
+  if (!ix || !info) return set_err(DDC_EINVAL, "NULL argument");
+  std::memset(info, 0, sizeof *info);
+  info->n = ix->n; info->dim = ix->D; info->dim_padded = ix->Dp; info->nlist = ix->nlist;
+  info->delta_d = ix->delta_d; info->n_stages = ix->S; info->n_test_stages = ix->St;
+  info->block_b = ix->B; info->lag_l = ix->L; info->storage = ix->storage; info->rotation = ix->rot;
+  info->n0 = ix->n0; info->packed_bytes = (int64_t)ix->d_base.bytes; info->total_tiles = ix->total_tiles;
+  return DDC_OK;
+}
+
+ddc_status ddc_import(const ddc_artifacts *a, ddc_index **out) {
+  if (!out) return set_err(DDC_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!a) return set_err(DDC_EINVAL, "artifacts is NULL");
+  if (a->n < 1 || a->dim < 1 || a->dim > kMaxBlocks * kBlockDims) return set_err(DDC_EINVAL, "bad n/dim");
+  if (a->nlist < 1 || a->nlist > 65536) return set_err(DDC_EINVAL, "nlist must be in [1, 65536]");
+  if (a->delta_d < kBlockDims || a->delta_d % kBlockDims) return set_err(DDC_EINVAL, "delta_d must be a positive multiple of 32");
+  if (a->block_b < 64 || a->block_b > 1024 || a->block_b % 64) return set_err(DDC_EINVAL, "block_b must be a multiple of 64 in [64, 1024]");
+  if (a->lag_l != 0) return set_err(DDC_EUNSUP, "only lag_l = 0 is implemented");
+  if (a->storage != DDC_F32 && a->storage != DDC_F16 && a->storage != DDC_BF16) return set_err(DDC_EINVAL, "bad storage");
+  if (a->rotation != DDC_ROT_F32 && a->rotation != DDC_ROT_BF16) return set_err(DDC_EINVAL, "bad rotation");
+  if (!a->mu || !a->rot || !a->centroids || !a->assign || !a->y) return set_err(DDC_EINVAL, "missing artifact array");
+  const int D = a->dim;
+  const int St = stage_count(D, a->delta_d) - 1;
+  if (a->n0 < 0 || (a->n0 > 0 && (!a->m || !a->resid))) return set_err(DDC_EINVAL, "bad correction table");
+  for (int64_t i = 0; i < a->n; ++i)
+    if (a->assign[i] < 0 || a->assign[i] >= a->nlist) return set_err(DDC_EINVAL, "assign out of range at %lld", (long long)i);
+  if (!all_finite(a->y, a->n * D) || !all_finite(a->centroids, (int64_t)a->nlist * D))
+    return set_err(DDC_EINVAL, "non-finite values in y or centroids");
+  GUARD_BEGIN
+  std::unique_ptr<ddc_index> ix(new ddc_index);
+  init_sizes(ix.get(), a->n, D, a->nlist, a->delta_d, a->block_b, a->lag_l, a->storage, a->rotation);
+  ix->mu.assign(a->mu, a->mu + D);
+  ix->R.assign(a->rot, a->rot + (size_t)D * D);
+  if (a->lam) ix->lam.assign(a->lam, a->lam + D);
+  ix->cent.assign(a->centroids, a->centroids + (size_t)a->nlist * D);
+  ix->assign.assign(a->assign, a->assign + a->n);
+  if (a->n0 > 0) {
+    ix->m.assign(a->m, a->m + St);
+    ix->resid.assign(a->resid, a->resid + (size_t)a->n0 * St);
+    ix->n0 = a->n0;
+  }
+  StreamHolder sh;
+  DevBuf d_Y((size_t)a->n * ix->Dp * 4);
+  HIPC(hipMemset2DAsync(d_Y.p, ix->Dp * 4, 0, ix->Dp * 4, a->n, sh.s));
+  HIPC(hipMemcpy2DAsync(d_Y.p, ix->Dp * 4, a->y, D * 4, D * 4, a->n, hipMemcpyHostToDevice, sh.s));
+  launch_round_storage(d_Y.as<float>(), a->n * ix->Dp, ix->store(), sh.s);
+  upload_index(ix.get(), d_Y.as<float>(), sh.s);
+  *out = ix.release();
+  return DDC_OK;
+  GUARD_END
+}
+
+ddc_status ddc_export(const ddc_index *ixc, ddc_artifacts *a) {
+  if (!ixc || !a) return set_err(DDC_EINVAL, "NULL argument");
+  ddc_index *ix = const_cast<ddc_index *>(ixc);
+  if (!a->mu || !a->rot || !a->centroids || !a->assign) return set_err(DDC_EINVAL, "missing output array");
+  if (ix->n0 > 0 && (!a->m || !a->resid)) return set_err(DDC_EINVAL, "missing m/resid output");
+  GUARD_BEGIN
+  DeviceGuard dg(ix->device);
+  const int D = ix->D;
+  a->n = ix->n; a->dim = D; a->nlist = ix->nlist; a->delta_d = ix->delta_d; a->block_b = ix->B;
+  a->lag_l = ix->L; a->storage = ix->storage; a->rotation = ix->rot; a->n0 = ix->n0;
+  std::copy(ix->mu.begin(), ix->mu.end(), a->mu);
+  std::copy(ix->R.begin(), ix->R.end(), a->rot);
+  if (a->lam && !ix->lam.empty()) std::copy(ix->lam.begin(), ix->lam.end(), a->lam);
+  std::copy(ix->cent.begin(), ix->cent.end(), a->centroids);
+  std::copy(ix->assign.begin(), ix->assign.end(), a->assign);
+  if (ix->n0 > 0) {
+    std::copy(ix->m.begin(), ix->m.end(), a->m);
+    std::copy(ix->resid.begin(), ix->resid.end(), a->resid);
+  }
+  if (a->y) {
+    const size_t per = (size_t)ix->NB * kTile * kBlockDims;
+    std::vector<unsigned char> packed(ix->d_base.bytes);
+    HIPC(hipMemcpy(packed.data(), ix->d_base.p, packed.size(), hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < ix->n; ++i) {
+      const int64_t slot = ix->id_to_slot[i];
+      const int64_t tile = slot / kTile;
+      const int v = (int)(slot % kTile);
+      for (int d = 0; d < D; ++d) {
+        const size_t idx = tile * per + ((size_t)(d / kBlockDims) * kTile + v) * kBlockDims + d % kBlockDims;
+        float x;
+        if (ix->storage == DDC_F32) {
+          std::memcpy(&x, &packed[idx * 4], 4);
+        } else {
+          uint16_t h;
+          std::memcpy(&h, &packed[idx * 2], 2);
+          if (ix->storage == DDC_BF16) {
+            const uint32_t u = (uint32_t)h << 16;
+            std::memcpy(&x, &u, 4);
+          } else {
+            // IEEE binary16 -> binary32
+            const uint32_t sgn = (uint32_t)(h >> 15) << 31, ex = (h >> 10) & 31, man = h & 1023;
+            uint32_t u;
+            if (ex == 0) {
+              if (man == 0) u = sgn;
+              else {
+                int e = -1;
+                uint32_t mm = man;
+                do { ++e; mm <<= 1; } while (!(mm & 1024));
+                u = sgn | ((uint32_t)(127 - 15 - e) << 23) | ((mm & 1023) << 13);
+              }
+            } else if (ex == 31) u = sgn | 0x7F800000u | (man << 13);
+            else u = sgn | ((ex + 112) << 23) | (man << 13);
+            std::memcpy(&x, &u, 4);
+          }
+        }
+        a->y[(size_t)i * D + d] = x;
+      }
+    }
+  }
+  return DDC_OK;
+  GUARD_END
+}
+
+ddc_status ddc_correction(const ddc_index *ixc, double alpha, ddc_calib_mode mode, double *m_out,
+                          double *beta_out) {
+  if (!ixc || !m_out || !beta_out) return set_err(DDC_EINVAL, "NULL argument");
+  if (!(alpha >= 0.0 && alpha < 1.0)) return set_err(DDC_EINVAL, "significance must be in [0, 1)");
+  if (mode != DDC_CALIB_JOINT && mode != DDC_CALIB_BONFERRONI) return set_err(DDC_EINVAL, "bad calibration mode");
+  if (ixc->n0 == 0 && ixc->St > 0) return set_err(DDC_EINVAL, "index has no correction table");
+  GUARD_BEGIN
+  ddc_index *ix = const_cast<ddc_index *>(ixc);
+  auto b = get_beta(ix, alpha, mode);
+  for (int t = 0; t < ix->St; ++t) { m_out[t] = ix->m[t]; beta_out[t] = b[t]; }
+  return DDC_OK;
+  GUARD_END
+}
+
+ddc_status ddc_search_device(const ddc_index *ixc, const float *d_queries, int64_t nq,
+                             const int32_t *d_k, int32_t k_all, int32_t k_max,
+                             const int32_t *d_nprobe, int32_t nprobe_all, int32_t nprobe_max,
+                             double significance, ddc_corr mode, const int64_t *d_out_offsets,
+                             int64_t *d_ids, float *d_dists, int64_t *d_counters, void *hip_stream) {
+  ddc_status st = check_search_args(ixc, nq, significance, mode);
+  if (st != DDC_OK) return st;
+  if (nq > 0 && (!d_queries || !d_ids || !d_dists)) return set_err(DDC_EINVAL, "NULL buffer");
+  if (!d_k && (st = check_k_np(ixc, k_all, 1)) != DDC_OK) return st;
+  if (d_k && (k_max < 1 || k_max > kMaxK)) return set_err(DDC_EINVAL, "k_max must be in [1, %d]", kMaxK);
+  if (d_k && !d_out_offsets) return set_err(DDC_EINVAL, "per-query k needs out_offsets");
+  const int npm = d_nprobe ? nprobe_max : nprobe_all;
+  if ((st = check_k_np(ixc, 1, npm)) != DDC_OK) return st;
+  if (nq == 0) return DDC_OK;
+  GUARD_BEGIN
+  ddc_index *ix = const_cast<ddc_index *>(ixc);
+  DeviceGuard dg(ix->device);
+  search_device(ix, d_queries, nq, d_k, k_all, d_k ? k_max : k_all, d_nprobe, nprobe_all, npm,
+                significance, mode, d_out_offsets, d_ids, d_dists, d_counters,
+                reinterpret_cast<hipStream_t>(hip_stream));
+  return DDC_OK;
+  GUARD_END
+}
+
+static ddc_status search_host(const ddc_index *ixc, const float *queries, int64_t nq,
+                              const int32_t *k, int32_t k_all, const int32_t *np, int32_t np_all,
+                              double alpha, ddc_corr mode, const int64_t *offs, int64_t *ids,
+                              float *dists, ddc_search_stats *stats) {
+  ddc_index *ix = const_cast<ddc_index *>(ixc);
+  int kmax = k_all, npmax = np_all;
+  int64_t total = nq * (int64_t)k_all;
+  if (k) {
+    kmax = 0;
+    npmax = 0;
+    for (int64_t i = 0; i < nq; ++i) {
+      ddc_status st = check_k_np(ix, k[i], np[i]);
+      if (st != DDC_OK) return st;
+      if (offs[i + 1] - offs[i] < k[i] || offs[i] < 0) return set_err(DDC_EINVAL, "out_offsets too small for k at %lld", (long long)i);
+      kmax = std::max(kmax, k[i]);
+      npmax = std::max(npmax, np[i]);
+    }
+    total = offs[nq];
+  }
+  if (!all_finite(queries, nq * ix->D)) return set_err(DDC_EINVAL, "non-finite query values");
+  if (nq == 0) {
+    if (stats) std::memset(stats, 0, sizeof *stats);
+    return DDC_OK;
+  }
+  GUARD_BEGIN
+  DeviceGuard dg(ix->device);
+  StreamHolder sh;
+  DevBuf d_q((size_t)nq * ix->D * 4), d_ids(total * 8), d_d(total * 4), d_ctr(kMaxCounters * 8);
+  DevBuf d_k, d_np, d_off;
+  HIPC(hipMemcpyAsync(d_q.p, queries, (size_t)nq * ix->D * 4, hipMemcpyHostToDevice, sh.s));
+  HIPC(hipMemsetAsync(d_ctr.p, 0, kMaxCounters * 8, sh.s));
+  if (k) {
+    d_k.alloc(nq * 4); d_np.alloc(nq * 4); d_off.alloc((nq + 1) * 8);
+    HIPC(hipMemcpyAsync(d_k.p, k, nq * 4, hipMemcpyHostToDevice, sh.s));
+    HIPC(hipMemcpyAsync(d_np.p, np, nq * 4, hipMemcpyHostToDevice, sh.s));
+    HIPC(hipMemcpyAsync(d_off.p, offs, (nq + 1) * 8, hipMemcpyHostToDevice, sh.s));
+  }
+  // slots of the CSR not covered by any query's k keep the padding values
+  if (k) {
+    std::vector<int64_t> pad_i(total, -1);
+    std::vector<float> pad_d(total, INFINITY);
+    HIPC(hipMemcpyAsync(d_ids.p, pad_i.data(), total * 8, hipMemcpyHostToDevice, sh.s));
+    HIPC(hipMemcpyAsync(d_d.p, pad_d.data(), total * 4, hipMemcpyHostToDevice, sh.s));
+    HIPC(hipStreamSynchronize(sh.s));
+  }
+  search_device(ix, d_q.as<float>(), nq, k ? d_k.as<int32_t>() : nullptr, k_all, kmax,
+                k ? d_np.as<int32_t>() : nullptr, np_all, npmax, alpha, mode,
+                k ? d_off.as<int64_t>() : nullptr, d_ids.as<int64_t>(), d_d.as<float>(),
+                d_ctr.as<int64_t>(), sh.s);
+  HIPC(hipMemcpyAsync(ids, d_ids.p, total * 8, hipMemcpyDeviceToHost, sh.s));
+  HIPC(hipMemcpyAsync(dists, d_d.p, total * 4, hipMemcpyDeviceToHost, sh.s));
+  int64_t ctr[kMaxCounters];
+  HIPC(hipMemcpyAsync(ctr, d_ctr.p, sizeof ctr, hipMemcpyDeviceToHost, sh.s));
+  HIPC(hipStreamSynchronize(sh.s));
+  if (stats) stats_from_counters(ix, ctr, stats);
+  return DDC_OK;
+  GUARD_END
+}
+
+ddc_status ddc_search(const ddc_index *ix, const float *queries, int64_t nq, int32_t k, int32_t nprobe,
+                      double significance, ddc_corr mode, int64_t *ids, float *dists,
+                      ddc_search_stats *stats) {
+  ddc_status st = check_search_args(ix, nq, significance, mode);
+  if (st != DDC_OK) return st;
+  if ((st = check_k_np(ix, k, nprobe)) != DDC_OK) return st;
+  if (nq > 0 && (!queries || !ids || !dists)) return set_err(DDC_EINVAL, "NULL buffer");
+  return search_host(ix, queries, nq, nullptr, k, nullptr, nprobe, significance, mode, nullptr, ids,
+                     dists, stats);
+}
+
+ddc_status ddc_search_var(const ddc_index *ix, const float *queries, int64_t nq, const int32_t *k,
+                          const int32_t *nprobe, double significance, ddc_corr mode,
+                          const int64_t *out_offsets, int64_t *ids, float *dists,
+                          ddc_search_stats *stats) {
+  ddc_status st = check_search_args(ix, nq, significance, mode);
+  if (st != DDC_OK) return st;
+  if (nq > 0 && (!queries || !k || !nprobe || !out_offsets || !ids || !dists))
+    return set_err(DDC_EINVAL, "NULL buffer");
+  return search_host(ix, queries, nq, k, 0, nprobe, 0, significance, mode, out_offsets, ids, dists,
+                     stats);
+}
+
+ddc_status ddc_debug_intermediates(const ddc_index *ixc, const float *queries, int64_t nq,
+                                   int32_t nprobe, float *q_rot, int32_t *probes) {
+  if (!ixc) return set_err(DDC_EINVAL, "index is NULL");
+  ddc_status st = check_k_np(ixc, 1, nprobe);
+  if (st != DDC_OK) return st;
+  if (nq < 0 || (nq > 0 && (!queries || !q_rot || !probes))) return set_err(DDC_EINVAL, "bad buffers");
+  if (!all_finite(queries, nq * ixc->D)) return set_err(DDC_EINVAL, "non-finite query values");
+  if (nq == 0) return DDC_OK;
+  GUARD_BEGIN
+  ddc_index *ix = const_cast<ddc_index *>(ixc);
+  DeviceGuard dg(ix->device);
+  StreamHolder sh;
+  DevBuf d_q((size_t)nq * ix->D * 4);
+  HIPC(hipMemcpyAsync(d_q.p, queries, (size_t)nq * ix->D * 4, hipMemcpyHostToDevice, sh.s));
+  search_device(ix, d_q.as<float>(), nq, nullptr, 1, 1, nullptr, nprobe, nprobe, 0.0, DDC_CORR_NONE,
+                nullptr, nullptr, nullptr, nullptr, sh.s, q_rot, probes);
+  HIPC(hipStreamSynchronize(sh.s));
+  return DDC_OK;
+  GUARD_END
+}
+
+ddc_status ddc_calibrate(ddc_index *ix, const float *calib, int64_t n_calib, int32_t calib_k,
+                         int32_t calib_nprobe, int32_t calib_max_neg, uint64_t seed) {
+  if (!ix || !calib) return set_err(DDC_EINVAL, "NULL argument");
+  if (n_calib < 1) return set_err(DDC_EINVAL, "n_calib must be >= 1");
+  if (calib_k < 1 || calib_k > 64 || calib_k > ix->n) return set_err(DDC_EINVAL, "calib_k must be in [1, min(64, n)]");
+  if (calib_nprobe < 0 || calib_nprobe > ix->nlist) return set_err(DDC_EINVAL, "calib_nprobe must be in [0, nlist]");
+  if (calib_max_neg < 1 || calib_max_neg > 256) return set_err(DDC_EINVAL, "calib_max_neg must be in [1, 256]");
+  if (!all_finite(calib, n_calib * ix->D)) return set_err(DDC_EINVAL, "non-finite calibration values");
+  const int npc = calib_nprobe ? calib_nprobe : std::min(std::max(1, ix->nlist / 8), 64);
+  GUARD_BEGIN
+  DeviceGuard dg(ix->device);
+  StreamHolder sh;
+  run_calibration(ix, calib, n_calib, calib_k, npc, calib_max_neg, seed, sh.s);
+  return DDC_OK;
+  GUARD_END
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------------------
+// fit
+// ---------------------------------------------------------------------------------------
+static void gather_rows(const float *src, int64_t ld, const std::vector<int64_t> &rows, int cols,
+                        float *dst, int64_t ldd, hipStream_t s) {
+  if (rows.empty()) return;
+  DevBuf d_r(rows.size() * 8);
+  HIPC(hipMemcpyAsync(d_r.p, rows.data(), rows.size() * 8, hipMemcpyHostToDevice, s));
+  launch_gather_rows(src, ld, d_r.as<int64_t>(), (int64_t)rows.size(), cols, dst, ldd, s);
+  HIPC(hipStreamSynchronize(s));
+}
+
+static void kmeans_assign(const float *d_Y, int64_t n, int Dp, const float *d_C, int nlist,
+                          float *d_cn, unsigned long long *d_key, int32_t *d_assign, hipStream_t s) {
+  launch_row_norms(d_C, Dp, nlist, Dp, d_cn, s);
+  HIPC(hipMemsetAsync(d_key, 0xFF, n * 8, s));
+  GemmArgs g{};
+  g.A = d_Y; g.lda = Dp; g.mu = nullptr; g.B = d_C; g.ldb = Dp; g.bias = d_cn; g.key64 = d_key;
+  g.M = n; g.N = nlist; g.K = Dp; g.mode = 2; g.prec = 0;
+  launch_gemm(g, s);
+  launch_decode_argmin(d_key, n, d_assign, s);
+}
+
+extern "C" ddc_status ddc_fit(const float *base, int64_t n, int32_t dim, const float *calib,
+                              int64_t n_calib, const ddc_fit_params *p, ddc_index **out) {
+  if (!out) return set_err(DDC_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!base || !calib) return set_err(DDC_EINVAL, "NULL base or calib");
+  ddc_status st = check_params(p, n, dim);
+  if (st != DDC_OK) return st;
+  if (n_calib < 1) return set_err(DDC_EINVAL, "n_calib must be >= 1");
+  if (p->calib_k > n) return set_err(DDC_EINVAL, "calib_k > n");
+  if (!all_finite(base, n * dim) || !all_finite(calib, n_calib * dim))
+    return set_err(DDC_EINVAL, "non-finite input values");
+  GUARD_BEGIN
+  std::unique_ptr<ddc_index> ix(new ddc_index);
+  init_sizes(ix.get(), n, dim, p->nlist, p->delta_d, p->block_b, p->lag_l, p->storage, p->rotation);
+  const int D = dim, Dp = ix->Dp, nlist = p->nlist;
+  StreamHolder sh;
+  hipStream_t s = sh.s;
+  DevBuf d_X((size_t)n * D * 4);
+  HIPC(hipMemcpyAsync(d_X.p, base, (size_t)n * D * 4, hipMemcpyHostToDevice, s));
+
+  // F1: FP64 mean and covariance of the PCA sample
+  std::vector<int64_t> rows;
+  int64_t nrows = n;
+  DevBuf d_rows;
+  if (n > p->pca_sample) {
+    rows = select_by_key(n, p->pca_sample, p->seed, TAG_PCA);
+    nrows = (int64_t)rows.size();
+    d_rows.alloc(rows.size() * 8);
+    HIPC(hipMemcpyAsync(d_rows.p, rows.data(), rows.size() * 8, hipMemcpyHostToDevice, s));
+  }
+  const int nparts_m = (int)std::min<int64_t>(256, std::max<int64_t>(1, nrows / 1024));
+  DevBuf d_mpart((size_t)nparts_m * D * 8), d_mu64((size_t)D * 8);
+  launch_mean64(d_X.as<float>(), n, D, d_rows.as<int64_t>(), nrows, d_mpart.as<double>(), nparts_m,
+                d_mu64.as<double>(), s);
+  const int ntile = (D + 63) / 64;
+  const int tiles = ntile * (ntile + 1) / 2;
+  int nparts_c = (int)std::max<int64_t>(1, std::min<int64_t>(nrows / 256, 2048 / std::max(1, tiles)));
+  nparts_c = std::max(1, std::min(nparts_c, (int)std::max<int64_t>(1, (int64_t)(1u << 30) / ((int64_t)ntile * ntile * 64 * 64 * 8))));
+  DevBuf d_cpart((size_t)nparts_c * ntile * ntile * 64 * 64 * 8), d_cov((size_t)D * D * 8);
+  launch_cov64(d_X.as<float>(), n, D, d_rows.as<int64_t>(), nrows, d_mu64.as<double>(),
+               d_cpart.as<double>(), nparts_c, d_cov.as<double>(), s);
+  std::vector<double> cov((size_t)D * D);
+  ix->mu.resize(D);
+  HIPC(hipMemcpyAsync(cov.data(), d_cov.p, cov.size() * 8, hipMemcpyDeviceToHost, s));
+  HIPC(hipMemcpyAsync(ix->mu.data(), d_mu64.p, (size_t)D * 8, hipMemcpyDeviceToHost, s));
+  HIPC(hipStreamSynchronize(s));
+  HIPC(hipGetLastError());
+  d_cpart.release();
+
+  // F2: eigenvectors (rows of R, largest eigenvalue first)
+  if (!sym_eig_desc(cov, D, ix->lam, ix->R)) throw DdcError(DDC_EDEVICE, "eigen-decomposition did not converge");
+
+  // F3: rotate the base on the matrix cores, round to the storage format
+  std::vector<float> R32((size_t)Dp * Dp, 0.f), mu32(Dp, 0.f);
+  for (int i = 0; i < D; ++i) {
+    mu32[i] = (float)ix->mu[i];
+    for (int j = 0; j < D; ++j) R32[(size_t)i * Dp + j] = (float)ix->R[(size_t)i * D + j];
+  }
+  DevBuf d_R(R32.size() * 4), d_m32(mu32.size() * 4);
+  HIPC(hipMemcpyAsync(d_R.p, R32.data(), R32.size() * 4, hipMemcpyHostToDevice, s));
+  HIPC(hipMemcpyAsync(d_m32.p, mu32.data(), mu32.size() * 4, hipMemcpyHostToDevice, s));
+  DevBuf d_Y((size_t)n * Dp * 4);
+  {
+    GemmArgs g{};
+    g.A = d_X.as<float>(); g.lda = D; g.mu = d_m32.as<float>(); g.B = d_R.as<float>(); g.ldb = Dp;
+    g.C = d_Y.as<float>(); g.ldc = Dp; g.M = n; g.N = Dp; g.K = D; g.mode = 0; g.prec = 0;
+    launch_gemm(g, s);
+  }
+  launch_round_storage(d_Y.as<float>(), n * Dp, ix->store(), s);
+  d_X.release();
+
+  // F4: k-means (Lloyd) on the stored values
+  const int64_t cap = (int64_t)p->kmeans_train_per_list * nlist;
+  std::vector<int64_t> trows;
+  const float *d_T = d_Y.as<float>();
+  int64_t ntr = n;
+  DevBuf d_train;
+  if (n > cap) {
+    trows = select_by_key(n, cap, p->seed, TAG_KMEANS_SAMPLE);
+    ntr = (int64_t)trows.size();
+    d_train.alloc((size_t)ntr * Dp * 4);
+    gather_rows(d_Y.as<float>(), Dp, trows, Dp, d_train.as<float>(), Dp, s);
+    d_T = d_train.as<float>();
+  }
+  const std::vector<int64_t> init = select_by_key(ntr, nlist, p->seed, TAG_KMEANS_INIT);
+  DevBuf d_C((size_t)nlist * Dp * 4), d_cn((size_t)nlist * 4), d_key((size_t)n * 8),
+      d_as((size_t)n * 4), d_off((size_t)(nlist + 1) * 4), d_mem((size_t)ntr * 4);
+  gather_rows(d_T, Dp, init, Dp, d_C.as<float>(), Dp, s);
+  std::vector<int32_t> asg(ntr), off(nlist + 1), mem(ntr), fill(nlist);
+  for (int it = 0; it < p->kmeans_iters; ++it) {
+    kmeans_assign(d_T, ntr, Dp, d_C.as<float>(), nlist, d_cn.as<float>(),
+                  d_key.as<unsigned long long>(), d_as.as<int32_t>(), s);
+    HIPC(hipMemcpyAsync(asg.data(), d_as.p, ntr * 4, hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    std::fill(off.begin(), off.end(), 0);
+    for (int64_t i = 0; i < ntr; ++i) off[asg[i] + 1]++;
+    for (int j = 0; j < nlist; ++j) off[j + 1] += off[j];
+    for (int j = 0; j < nlist; ++j) fill[j] = off[j];
+    for (int64_t i = 0; i < ntr; ++i) mem[fill[asg[i]]++] = (int32_t)i;
+    HIPC(hipMemcpyAsync(d_off.p, off.data(), off.size() * 4, hipMemcpyHostToDevice, s));
+    HIPC(hipMemcpyAsync(d_mem.p, mem.data(), ntr * 4, hipMemcpyHostToDevice, s));
+    launch_centroid_update(d_T, Dp, D, d_off.as<int32_t>(), d_mem.as<int32_t>(), nlist,
+                           d_C.as<float>(), Dp, s);
+  }
+  d_train.release();
+  kmeans_assign(d_Y.as<float>(), n, Dp, d_C.as<float>(), nlist, d_cn.as<float>(),
+                d_key.as<unsigned long long>(), d_as.as<int32_t>(), s);
+  ix->assign.resize(n);
+  std::vector<float> cpad((size_t)nlist * Dp);
+  HIPC(hipMemcpyAsync(ix->assign.data(), d_as.p, n * 4, hipMemcpyDeviceToHost, s));
+  HIPC(hipMemcpyAsync(cpad.data(), d_C.p, cpad.size() * 4, hipMemcpyDeviceToHost, s));
+  HIPC(hipStreamSynchronize(s));
+  HIPC(hipGetLastError());
+  ix->cent.resize((size_t)nlist * D);
+  for (int j = 0; j < nlist; ++j)
+    for (int d = 0; d < D; ++d) ix->cent[(size_t)j * D + d] = cpad[(size_t)j * Dp + d];
+  d_key.release();
+
+  upload_index(ix.get(), d_Y.as<float>(), s);
+  d_Y.release();
+
+  // F5: calibration of the correction table
+  const int npc = p->calib_nprobe ? p->calib_nprobe : std::min(std::max(1, nlist / 8), 64);
+  run_calibration(ix.get(), calib, n_calib, p->calib_k, npc, p->calib_max_neg, p->seed, s);
+  *out = ix.release();
+  return DDC_OK;
+  GUARD_END
+}

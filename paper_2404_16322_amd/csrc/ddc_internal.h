@@ -1,0 +1,124 @@
+// Internal declarations shared by the HIP kernel files and the host runtime.
+// Not part of the public ABI (include/ddc.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ddc {
+
+// Dimension blocks of the packed base are 32 wide; a stage (Delta_d) is a whole
+// number of blocks.  Vectors are grouped in tiles of 64 (one wavefront).
+constexpr int kBlockDims = 32;
+constexpr int kTile = 64;
+constexpr int kMaxBlocks = 128;      // D <= 4096
+constexpr int kMaxK = 256;
+constexpr int kScanThreads = 256;    // 4 wavefronts per query
+constexpr int kMaxCounters = 4 + 64; // candidates, refined, stage_slices, unused, stop[64]
+
+enum StoreType : int { ST_F32 = 0, ST_F16 = 1, ST_BF16 = 2 };
+
+// Arguments of the pruned scan (A3) + top-K merge (A4) + finalize (A5) kernel.
+struct ScanArgs {
+  const float *qrot;       // [nq x q_stride] rotated queries, zero beyond D
+  int64_t q_stride;
+  const int32_t *probes;   // [nq x p_stride] list ids in probe order
+  int32_t p_stride;
+  const int32_t *nprobe;   // per query, or NULL -> nprobe_all
+  int32_t nprobe_all;
+  const int32_t *k;        // per query, or NULL -> k_all
+  int32_t k_all;
+  const int64_t *out_off;  // CSR result offsets, or NULL -> q * k_all
+  const int32_t *tile_off; // [nlist + 1] first tile of each list
+  const int32_t *list_len; // [nlist]
+  const void *base;        // packed tiles: [tile][block][64 vectors][32 dims]
+  const int32_t *ids;      // [tiles * 64] original id of each stored slot (-1 = padding)
+  int64_t *out_ids;
+  float *out_d;
+  int64_t *counters;       // NULL or [kMaxCounters] (added to)
+  int32_t nq, nblocks, block_b, prune, nlist;
+  float m[kMaxBlocks];     // per 32-dim block: slope of the test after this block
+  float beta[kMaxBlocks];  //                   bias of the test after this block
+  int8_t test_after[kMaxBlocks]; // 1 if a stage test follows block b
+};
+
+void launch_scan(const ScanArgs &a, int store, hipStream_t s);
+
+// C[M x N] = (A - mu)[M x K] * B[N x K]^T on MFMA, FP32 accumulation.
+//   mode 0: out[m][n] = acc                      (query / base rotation)
+//   mode 1: out[m][n] = bias[n] - 2 acc          (coarse: ||c||^2 - 2 <q', c>)
+//   mode 2: argmin over n of bias[n] - 2 acc per row -> atomicMin into key64[m]
+// A, B row-major with leading dims lda, ldb (elements); K is padded by zero-filling.
+// prec 0 = FP32 MFMA, 1 = BF16 MFMA (inputs rounded to nearest even bfloat16).
+struct GemmArgs {
+  const float *A; int64_t lda;
+  const float *mu;        // [K] or NULL
+  const float *B; int64_t ldb;
+  const float *bias;      // [N] (modes 1, 2)
+  float *C; int64_t ldc;  // modes 0, 1
+  unsigned long long *key64; // mode 2
+  int64_t M; int32_t N, K;
+  int32_t mode, prec;
+};
+void launch_gemm(const GemmArgs &g, hipStream_t s);
+
+// Probe selection (A2): the nprobe smallest of dist[q][0..nlist) by (value, index),
+// ascending, written to probes[q][0..nprobe).
+void launch_select(const float *dist, int64_t ld, int32_t nlist, const int32_t *nprobe,
+                   int32_t nprobe_all, int32_t nprobe_max, int32_t *probes, int32_t p_stride,
+                   int64_t nq, hipStream_t s);
+
+// ---- fit-side kernels (k_fit.hip) ----
+// FP64 column means of X[rows] (rows = NULL -> all n): out mu[D].
+void launch_mean64(const float *X, int64_t n, int32_t D, const int64_t *rows, int64_t nrows,
+                   double *partial, int32_t nparts, double *mu, hipStream_t s);
+// FP64 covariance (1/nrows) sum (x-mu)(x-mu)^T, deterministic (fixed partial order).
+void launch_cov64(const float *X, int64_t n, int32_t D, const int64_t *rows, int64_t nrows,
+                  const double *mu, double *partial, int32_t nparts, double *cov, hipStream_t s);
+// Round FP32 rows to the storage format and back (values become exactly representable).
+void launch_round_storage(float *Y, int64_t count, int store, hipStream_t s);
+// Per-cluster FP64 means in a fixed order: members[off[j]..off[j+1]) of Y rows.
+void launch_centroid_update(const float *Y, int64_t ldy, int32_t D, const int32_t *off,
+                            const int32_t *members, int32_t nlist, float *C, int64_t ldc,
+                            hipStream_t s);
+void launch_row_norms(const float *C, int64_t ldc, int32_t rows, int32_t D, float *out,
+                      hipStream_t s);
+// dst[r] = src[rows[r]] (row copies, `cols` floats each)
+void launch_gather_rows(const float *src, int64_t ld, const int64_t *rows, int64_t nrows, int32_t cols,
+                        float *dst, int64_t ldd, hipStream_t s);
+void launch_decode_argmin(const unsigned long long *key64, int64_t n, int32_t *assign,
+                          hipStream_t s);
+// Pack rotated rows into [tile][block][64][32] storage tiles; slot_row[t*64+v] = row or -1.
+void launch_pack(const float *Y, int64_t ldy, int32_t D, int32_t nblocks, const int64_t *slot_row,
+                 int64_t total_tiles, void *base, int store, hipStream_t s);
+
+// ---- calibration kernels (k_calib.hip), FP64 ----
+void launch_rotate64(const float *Q, int64_t nq, int32_t D, const double *mu, const double *R,
+                     double *out, hipStream_t s);
+// Exact FP64 squared distances of rows `cand[q][0..nc)` of the packed base to q'.
+void launch_refine64(const double *qrot, int32_t D, const void *base, int store, int32_t nblocks,
+                     const int64_t *slots, int32_t nc, int64_t nq, double *out, hipStream_t s);
+// FP64 partial distances e_s after every test stage for (query, slot) pairs.
+void launch_features64(const double *qrot, int32_t D, const void *base, int store, int32_t nblocks,
+                       const int32_t *pair_q, const int64_t *pair_slot, int64_t npairs,
+                       const int32_t *stage_end_block, int32_t n_test, double *out, hipStream_t s);
+// FP64 centroid distances for probe ordering of calibration queries.
+void launch_cdist64(const double *qrot, int64_t nq, int32_t D, const float *cent, int64_t ldc,
+                    int32_t nlist, double *out, hipStream_t s);
+// Unpruned canonical IVF search in FP64 collecting label-1 candidates (dis > tau_b, tau_b finite),
+// keeping the max_neg with the smallest SplitMix64 keys per query.
+struct NegArgs {
+  const double *qrot; int32_t D;
+  const int32_t *probes; int32_t nprobe;
+  const int32_t *tile_off; const int32_t *list_len;
+  const void *base; int store; int32_t nblocks;
+  const int32_t *ids;
+  int32_t k, block_b, max_neg;
+  unsigned long long key_base;   // splitmix64(seed + tag)
+  int64_t nq;
+  int64_t *neg_slot;   // [nq x max_neg] stored slot or -1
+  double *neg_tau;     // [nq x max_neg]
+};
+void launch_negatives64(const NegArgs &a, hipStream_t s);
+
+}  // namespace ddc

@@ -1,0 +1,291 @@
+// Host numerics of the fit.  See host_math.h.
+#include "host_math.h"
+
+#include <algorithm>
+#include <cmath>
+#include <limits>
+#include <numeric>
+
+namespace ddc {
+
+uint64_t splitmix64(uint64_t x) {
+  uint64_t z = x + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+uint64_t ctr_key(uint64_t seed, uint64_t tag, uint64_t i) { return splitmix64(splitmix64(seed + tag) + i); }
+
+std::vector<int64_t> select_by_key(int64_t n, int64_t m, uint64_t seed, uint64_t tag) {
+  std::vector<int64_t> idx(n);
+  std::iota(idx.begin(), idx.end(), 0);
+  if (m >= n) return idx;
+  const uint64_t base = splitmix64(seed + tag);
+  std::vector<uint64_t> key(n);
+  for (int64_t i = 0; i < n; ++i) key[i] = splitmix64(base + (uint64_t)i);
+  auto less = [&](int64_t a, int64_t b) { return key[a] < key[b] || (key[a] == key[b] && a < b); };
+  std::nth_element(idx.begin(), idx.begin() + m, idx.end(), less);
+  idx.resize(m);
+  std::sort(idx.begin(), idx.end());
+  return idx;
+}
+
+// ---------------------------------------------------------------------------------------
+// Symmetric eigenproblem.  Householder: for column k, reflect the sub-column x = A[k+1:, k]
+// onto alpha e_1 with H = I - 2 v v^T (v = x - alpha e_1 normalised); A <- H A H updates the
+// trailing block as A' -= 2 (v w^T + w v^T), w = A'v - (v^T A' v) v.  Accumulated
+// Q = H_0 H_1 ... gives A = Q T Q^T.  Then the tridiagonal T is diagonalised by implicit
+// QL sweeps (Givens rotations chasing the bulge from the bottom), each rotation also
+// applied to the columns of Q.
+// ---------------------------------------------------------------------------------------
+static void tridiagonalise(std::vector<double> &A, int n, std::vector<double> &Q,
+                           std::vector<double> &d, std::vector<double> &e) {
+  Q.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) Q[(size_t)i * n + i] = 1.0;
+  std::vector<double> v(n), p(n), w(n);
+  for (int k = 0; k + 2 < n; ++k) {
+    const int m = n - k - 1;  // length of the sub-column
+    double nrm = 0.0;
+    for (int i = 0; i < m; ++i) {
+      const double x = A[(size_t)(k + 1 + i) * n + k];
+      nrm += x * x;
+    }
+    nrm = std::sqrt(nrm);
+    if (nrm == 0.0) continue;
+    const double x0 = A[(size_t)(k + 1) * n + k];
+    const double alpha = x0 > 0 ? -nrm : nrm;
+    for (int i = 0; i < m; ++i) v[i] = A[(size_t)(k + 1 + i) * n + k];
+    v[0] -= alpha;
+    double vn = 0.0;
+    for (int i = 0; i < m; ++i) vn += v[i] * v[i];
+    vn = std::sqrt(vn);
+    if (vn == 0.0) continue;
+    for (int i = 0; i < m; ++i) v[i] /= vn;
+    // p = A' v on the trailing block (rows/cols k+1..n-1)
+    for (int i = 0; i < m; ++i) {
+      const double *row = &A[(size_t)(k + 1 + i) * n + k + 1];
+      double s = 0.0;
+      for (int j = 0; j < m; ++j) s += row[j] * v[j];
+      p[i] = s;
+    }
+    double K = 0.0;
+    for (int i = 0; i < m; ++i) K += v[i] * p[i];
+    for (int i = 0; i < m; ++i) w[i] = p[i] - K * v[i];
+    for (int i = 0; i < m; ++i) {
+      double *row = &A[(size_t)(k + 1 + i) * n + k + 1];
+      const double vi = v[i], wi = w[i];
+      for (int j = 0; j < m; ++j) row[j] -= 2.0 * (vi * w[j] + wi * v[j]);
+    }
+    A[(size_t)(k + 1) * n + k] = alpha;
+    A[(size_t)k * n + k + 1] = alpha;
+    for (int i = 1; i < m; ++i) {
+      A[(size_t)(k + 1 + i) * n + k] = 0.0;
+      A[(size_t)k * n + k + 1 + i] = 0.0;
+    }
+    // Q[:, k+1:] <- Q[:, k+1:] (I - 2 v v^T)
+    for (int r = 0; r < n; ++r) {
+      double *row = &Q[(size_t)r * n + k + 1];
+      double s = 0.0;
+      for (int j = 0; j < m; ++j) s += row[j] * v[j];
+      s *= 2.0;
+      for (int j = 0; j < m; ++j) row[j] -= s * v[j];
+    }
+  }
+  d.resize(n);
+  e.assign(n, 0.0);
+  for (int i = 0; i < n; ++i) d[i] = A[(size_t)i * n + i];
+  for (int i = 0; i + 1 < n; ++i) e[i] = A[(size_t)(i + 1) * n + i];  // e[i] couples i, i+1
+}
+
+static bool tridiag_ql(std::vector<double> &d, std::vector<double> &e, int n, std::vector<double> &Q) {
+  // Q is row-major n x n; rotations act on its columns.  Work on the transpose for locality.
+  std::vector<double> Qt((size_t)n * n);
+  for (int r = 0; r < n; ++r)
+    for (int c = 0; c < n; ++c) Qt[(size_t)c * n + r] = Q[(size_t)r * n + c];
+  const double eps = std::numeric_limits<double>::epsilon();
+  for (int l = 0; l < n; ++l) {
+    int iter = 0;
+    for (;;) {
+      int m = l;
+      for (; m + 1 < n; ++m) {
+        const double dd = std::fabs(d[m]) + std::fabs(d[m + 1]);
+        if (std::fabs(e[m]) <= eps * dd) break;
+      }
+      if (m == l) break;
+      if (++iter > 60) return false;
+      // shift from the leading 2x2 block of the unreduced segment
+      double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
+      double r = std::hypot(g, 1.0);
+      g = d[m] - d[l] + e[l] / (g + (g >= 0 ? r : -r));
+      double s = 1.0, c = 1.0, p = 0.0;
+      int i = m - 1;
+      bool deflated = false;
+      for (; i >= l; --i) {
+        const double f = s * e[i];
+        const double b = c * e[i];
+        r = std::hypot(f, g);
+        e[i + 1] = r;
+        if (r == 0.0) {
+          d[i + 1] -= p;
+          e[m] = 0.0;
+          deflated = true;
+          break;
+        }
+        s = f / r;
+        c = g / r;
+        g = d[i + 1] - p;
+        r = (d[i] - g) * s + 2.0 * c * b;
+        p = s * r;
+        d[i + 1] = g + p;
+        g = c * r - b;
+        double *ci = &Qt[(size_t)i * n];
+        double *cj = &Qt[(size_t)(i + 1) * n];
+        for (int k = 0; k < n; ++k) {
+          const double fk = cj[k];
+          cj[k] = s * ci[k] + c * fk;
+          ci[k] = c * ci[k] - s * fk;
+        }
+      }
+      if (deflated) continue;
+      d[l] -= p;
+      e[l] = g;
+      e[m] = 0.0;
+    }
+  }
+  for (int r = 0; r < n; ++r)
+    for (int c = 0; c < n; ++c) Q[(size_t)r * n + c] = Qt[(size_t)c * n + r];
+  return true;
+}
+
+bool sym_eig_desc(const std::vector<double> &Ain, int n, std::vector<double> &lam,
+                  std::vector<double> &vecs) {
+  std::vector<double> A = Ain, Q, d, e;
+  tridiagonalise(A, n, Q, d, e);
+  if (!tridiag_ql(d, e, n, Q)) return false;
+  std::vector<int> order(n);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return d[a] > d[b]; });
+  lam.resize(n);
+  vecs.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    const int c = order[i];
+    lam[i] = d[c];
+    int arg = 0;
+    double best = -1.0;
+    for (int j = 0; j < n; ++j) {
+      const double a = std::fabs(Q[(size_t)j * n + c]);
+      if (a > best) { best = a; arg = j; }
+    }
+    const double sgn = Q[(size_t)arg * n + c] < 0 ? -1.0 : 1.0;
+    for (int j = 0; j < n; ++j) vecs[(size_t)i * n + j] = sgn * Q[(size_t)j * n + c];
+  }
+  return true;
+}
+
+// ---------------------------------------------------------------------------------------
+void logistic_fit(const std::vector<double> &F, const std::vector<double> &y, double &b, double &w1,
+                  double &w2) {
+  const size_t n = y.size();
+  double mean[2] = {0, 0}, sd[2] = {0, 0};
+  for (size_t i = 0; i < n; ++i) { mean[0] += F[2 * i]; mean[1] += F[2 * i + 1]; }
+  mean[0] /= n; mean[1] /= n;
+  for (size_t i = 0; i < n; ++i) {
+    sd[0] += (F[2 * i] - mean[0]) * (F[2 * i] - mean[0]);
+    sd[1] += (F[2 * i + 1] - mean[1]) * (F[2 * i + 1] - mean[1]);
+  }
+  for (int j = 0; j < 2; ++j) {
+    sd[j] = std::sqrt(sd[j] / n);
+    if (sd[j] == 0) sd[j] = 1.0;
+  }
+  const double ridge = 1e-8;
+  double w[3] = {0, 0, 0};
+  for (int it = 0; it < 100; ++it) {
+    double g[3] = {0, 0, 0}, H[3][3] = {{0}};
+    for (size_t i = 0; i < n; ++i) {
+      const double z[3] = {1.0, (F[2 * i] - mean[0]) / sd[0], (F[2 * i + 1] - mean[1]) / sd[1]};
+      const double t = w[0] + w[1] * z[1] + w[2] * z[2];
+      const double pr = 0.5 * (1.0 + std::tanh(0.5 * t));
+      const double r = pr - y[i], wt = pr * (1.0 - pr);
+      for (int a = 0; a < 3; ++a) {
+        g[a] += z[a] * r;
+        for (int c = 0; c < 3; ++c) H[a][c] += wt * z[a] * z[c];
+      }
+    }
+    for (int a = 0; a < 3; ++a) {
+      g[a] /= n;
+      for (int c = 0; c < 3; ++c) H[a][c] /= n;
+    }
+    for (int a = 1; a < 3; ++a) { g[a] += ridge * w[a]; H[a][a] += ridge; }
+    // solve H x = g (Gaussian elimination with partial pivoting)
+    double M[3][4];
+    for (int a = 0; a < 3; ++a) {
+      for (int c = 0; c < 3; ++c) M[a][c] = H[a][c];
+      M[a][3] = g[a];
+    }
+    for (int col = 0; col < 3; ++col) {
+      int piv = col;
+      for (int r = col + 1; r < 3; ++r)
+        if (std::fabs(M[r][col]) > std::fabs(M[piv][col])) piv = r;
+      if (piv != col)
+        for (int c = 0; c < 4; ++c) std::swap(M[col][c], M[piv][c]);
+      const double dv = M[col][col] != 0 ? M[col][col] : 1e-300;
+      for (int r = col + 1; r < 3; ++r) {
+        const double f = M[r][col] / dv;
+        for (int c = col; c < 4; ++c) M[r][c] -= f * M[col][c];
+      }
+    }
+    double x[3];
+    for (int r = 2; r >= 0; --r) {
+      double s = M[r][3];
+      for (int c = r + 1; c < 3; ++c) s -= M[r][c] * x[c];
+      x[r] = s / (M[r][r] != 0 ? M[r][r] : 1e-300);
+    }
+    double mx = 0;
+    for (int a = 0; a < 3; ++a) {
+      w[a] -= x[a];
+      mx = std::max(mx, std::fabs(x[a]));
+    }
+    if (mx < 1e-12) break;
+  }
+  w1 = w[1] / sd[0];
+  w2 = w[2] / sd[1];
+  b = w[0] - w[1] * mean[0] / sd[0] - w[2] * mean[1] / sd[1];
+}
+
+std::vector<double> beta_for_alpha(const std::vector<double> &G, int64_t n0, int st, double alpha,
+                                   int mode) {
+  std::vector<double> beta(st, -std::numeric_limits<double>::infinity());
+  if (alpha <= 0.0 || n0 == 0 || st == 0) return beta;
+  std::vector<double> Gs((size_t)n0 * st);
+  for (int s = 0; s < st; ++s) {
+    std::vector<double> col(n0);
+    for (int64_t j = 0; j < n0; ++j) col[j] = G[(size_t)j * st + s];
+    std::sort(col.begin(), col.end());
+    for (int64_t j = 0; j < n0; ++j) Gs[(size_t)j * st + s] = col[j];
+  }
+  int64_t k;
+  if (mode == 1) {
+    k = std::min<int64_t>((int64_t)std::floor(alpha * (double)n0 / st), n0 - 1);
+  } else {
+    auto frac = [&](int64_t kk) {
+      int64_t cnt = 0;
+      for (int64_t j = 0; j < n0; ++j) {
+        for (int s = 0; s < st; ++s) {
+          if (G[(size_t)j * st + s] < Gs[(size_t)kk * st + s]) { ++cnt; break; }
+        }
+      }
+      return (double)cnt / (double)n0;
+    };
+    int64_t lo = 0, hi = n0 - 1;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi + 1) / 2;
+      if (frac(mid) <= alpha) lo = mid; else hi = mid - 1;
+    }
+    k = lo;
+  }
+  for (int s = 0; s < st; ++s) beta[s] = Gs[(size_t)k * st + s];
+  return beta;
+}
+
+}  // namespace ddc
