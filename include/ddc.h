@@ -192,6 +192,15 @@ ddc_status ddc_search_device(const ddc_index *ix, const float *d_queries, int64_
 ddc_status ddc_debug_intermediates(const ddc_index *ix, const float *queries, int64_t nq,
                                    int32_t nprobe, float *q_rot, int32_t *probes);
 
+/* Per-kernel timing of the search pipeline with HIP events recorded on the launch stream
+ * around every kernel of every later search on this index (enable = 1) or none (0).
+ * Kernels: 0 query rotation (A1), 1 coarse centroid distances (A2), 2 probe selection (A2),
+ * 3 pruned scan + top-K merge + finalize (A3-A5).  ddc_get_kernel_timing waits for the
+ * recorded events, adds their elapsed times to ms_total[4] and counts to launches[4]
+ * (both caller arrays, overwritten), and clears the record when reset != 0. */
+ddc_status ddc_set_kernel_timing(ddc_index *ix, int enable);
+ddc_status ddc_get_kernel_timing(ddc_index *ix, double *ms_total, int64_t *launches, int reset);
+
 void ddc_free(ddc_index *ix);
 const char *ddc_last_error(void);
 

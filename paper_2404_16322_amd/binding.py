@@ -20,7 +20,8 @@ STATUS = {0: "DDC_OK", -1: "DDC_EINVAL", -2: "DDC_ENOMEM", -3: "DDC_EDEVICE", -4
 
 SYMBOLS = ["ddc_fit_params_default", "ddc_fit", "ddc_import", "ddc_export", "ddc_index_get_info",
            "ddc_calibrate", "ddc_correction", "ddc_search", "ddc_search_var", "ddc_search_device",
-           "ddc_debug_intermediates", "ddc_free", "ddc_last_error"]
+           "ddc_debug_intermediates", "ddc_set_kernel_timing", "ddc_get_kernel_timing", "ddc_free",
+           "ddc_last_error"]
 
 
 class FitParams(C.Structure):
@@ -92,6 +93,8 @@ def load_library():
         lib.ddc_search_device.argtypes = [vp, vp, i64, vp, i32, i32, vp, i32, i32, f64, C.c_int, vp,
                                           vp, vp, vp, vp]
         lib.ddc_debug_intermediates.argtypes = [vp, vp, i64, i32, vp, vp]
+        lib.ddc_set_kernel_timing.argtypes = [vp, C.c_int]
+        lib.ddc_get_kernel_timing.argtypes = [vp, vp, vp, C.c_int]
         lib.ddc_free.argtypes = [vp]
         lib.ddc_free.restype = None
         for name in SYMBOLS:
@@ -260,6 +263,16 @@ class Index:
             self._h, d_queries, nq, d_k or None, k_all, k_max, d_nprobe or None, nprobe_all,
             nprobe_max, alpha, CORR[mode], d_offsets or None, d_ids, d_dists, d_counters or None,
             stream or None))
+
+    def set_kernel_timing(self, enable: bool):
+        _check(load_library().ddc_set_kernel_timing(self._h, int(enable)))
+
+    def kernel_timing(self, reset: bool = True):
+        """(ms_total[4], launches[4]) for rotation, coarse, select, scan since the last reset."""
+        ms = np.zeros(4)
+        n = np.zeros(4, np.int64)
+        _check(load_library().ddc_get_kernel_timing(self._h, _ptr(ms), _ptr(n), int(reset)))
+        return ms, n
 
     def debug_intermediates(self, queries, nprobe: int):
         q = _f32(queries)

@@ -146,6 +146,14 @@ struct ddc_index {
   std::mutex beta_mtx;
   std::map<std::pair<double, int>, std::vector<double>> beta_cache;
   DevBuf d_R32, d_mu32, d_cent, d_cnorm, d_tile_off, d_list_len, d_ids, d_base, d_R64, d_mu64;
+  // optional per-kernel event timing
+  bool timing = false;
+  std::mutex timing_mtx;
+  struct Mark { int kernel; hipEvent_t a, b; };
+  std::vector<Mark> marks;
+  ~ddc_index() {
+    for (auto &m : marks) { (void)hipEventDestroy(m.a); (void)hipEventDestroy(m.b); }
+  }
 
   int store() const { return storage == DDC_F32 ? ST_F32 : storage == DDC_F16 ? ST_F16 : ST_BF16; }
   int esize() const { return storage == DDC_F32 ? 4 : 2; }
@@ -270,6 +278,7 @@ static void run_calibration(ddc_index *ix, const float *calib, int64_t nc, int k
     a.base = ix->d_base.p; a.ids = ix->d_ids.as<int32_t>();
     a.out_ids = d_cid.as<int64_t>(); a.out_d = d_cd.as<float>();
     a.nq = (int32_t)nc; a.nblocks = ix->NB; a.block_b = ix->B; a.prune = 0; a.nlist = ix->nlist;
+    a.k_max = kp;
     launch_scan(a, ix->store(), s);
   }
   std::vector<int64_t> cid((size_t)nc * kp);
@@ -434,6 +443,18 @@ static std::vector<double> get_beta(ddc_index *ix, double alpha, int mode) {
 // ---------------------------------------------------------------------------------------
 // search pipeline
 // ---------------------------------------------------------------------------------------
+template <class F> static void timed(ddc_index *ix, int kernel, hipStream_t s, F &&launch) {
+  if (!ix->timing) { launch(); return; }
+  ddc_index::Mark m{kernel, nullptr, nullptr};
+  HIPC(hipEventCreate(&m.a));
+  HIPC(hipEventCreate(&m.b));
+  HIPC(hipEventRecord(m.a, s));
+  launch();
+  HIPC(hipEventRecord(m.b, s));
+  std::lock_guard<std::mutex> lk(ix->timing_mtx);
+  ix->marks.push_back(m);
+}
+
 static void search_device(ddc_index *ix, const float *d_q, int64_t nq, const int32_t *d_k, int k_all,
                           int k_max, const int32_t *d_np, int np_all, int np_max, double alpha,
                           ddc_corr mode, const int64_t *d_off, int64_t *d_ids, float *d_d,
@@ -470,14 +491,16 @@ static void search_device(ddc_index *ix, const float *d_q, int64_t nq, const int
     g.A = d_q + q0 * D; g.lda = D; g.mu = ix->d_mu32.as<float>();
     g.B = ix->d_R32.as<float>(); g.ldb = Dp; g.C = qrot.as<float>(); g.ldc = Dp;
     g.M = nqc; g.N = Dp; g.K = D; g.mode = 0; g.prec = ix->rot == DDC_ROT_BF16 ? 1 : 0;
-    launch_gemm(g, s);
+    timed(ix, 0, s, [&] { launch_gemm(g, s); });
     GemmArgs c{};
     c.A = qrot.as<float>(); c.lda = Dp; c.mu = nullptr; c.B = ix->d_cent.as<float>(); c.ldb = Dp;
     c.bias = ix->d_cnorm.as<float>(); c.C = cdist.as<float>(); c.ldc = ix->nlist;
     c.M = nqc; c.N = ix->nlist; c.K = Dp; c.mode = 1; c.prec = 0;
-    launch_gemm(c, s);
-    launch_select(cdist.as<float>(), ix->nlist, ix->nlist, d_np ? d_np + q0 : nullptr, np_all, np_max,
-                  probes.as<int32_t>(), np_max, nqc, s);
+    timed(ix, 1, s, [&] { launch_gemm(c, s); });
+    timed(ix, 2, s, [&] {
+      launch_select(cdist.as<float>(), ix->nlist, ix->nlist, d_np ? d_np + q0 : nullptr, np_all,
+                    np_max, probes.as<int32_t>(), np_max, nqc, s);
+    });
     if (qrot_out) {
       HIPC(hipMemcpy2DAsync(qrot_out + q0 * D, D * 4, qrot.p, Dp * 4, D * 4, nqc,
                             hipMemcpyDeviceToHost, s));
@@ -497,8 +520,8 @@ static void search_device(ddc_index *ix, const float *d_q, int64_t nq, const int
     a.out_d = d_off ? d_d : d_d + q0 * k_all;
     a.counters = d_ctr;
     a.nq = (int32_t)nqc; a.nblocks = ix->NB; a.block_b = ix->B; a.nlist = ix->nlist;
-    launch_scan(a, ix->store(), s);
-    (void)k_max;
+    a.k_max = k_max;
+    timed(ix, 3, s, [&] { launch_scan(a, ix->store(), s); });
   }
   HIPC(hipGetLastError());
 }
@@ -843,6 +866,34 @@ ddc_status ddc_debug_intermediates(const ddc_index *ixc, const float *queries, i
   search_device(ix, d_q.as<float>(), nq, nullptr, 1, 1, nullptr, nprobe, nprobe, 0.0, DDC_CORR_NONE,
                 nullptr, nullptr, nullptr, nullptr, sh.s, q_rot, probes);
   HIPC(hipStreamSynchronize(sh.s));
+  return DDC_OK;
+  GUARD_END
+}
+
+ddc_status ddc_set_kernel_timing(ddc_index *ix, int enable) {
+  if (!ix) return set_err(DDC_EINVAL, "index is NULL");
+  std::lock_guard<std::mutex> lk(ix->timing_mtx);
+  ix->timing = enable != 0;
+  return DDC_OK;
+}
+
+ddc_status ddc_get_kernel_timing(ddc_index *ix, double *ms_total, int64_t *launches, int reset) {
+  if (!ix || !ms_total || !launches) return set_err(DDC_EINVAL, "NULL argument");
+  GUARD_BEGIN
+  DeviceGuard dg(ix->device);
+  std::lock_guard<std::mutex> lk(ix->timing_mtx);
+  for (int i = 0; i < 4; ++i) { ms_total[i] = 0.0; launches[i] = 0; }
+  for (auto &m : ix->marks) {
+    HIPC(hipEventSynchronize(m.b));
+    float ms = 0.f;
+    HIPC(hipEventElapsedTime(&ms, m.a, m.b));
+    ms_total[m.kernel] += ms;
+    launches[m.kernel] += 1;
+  }
+  if (reset) {
+    for (auto &m : ix->marks) { (void)hipEventDestroy(m.a); (void)hipEventDestroy(m.b); }
+    ix->marks.clear();
+  }
   return DDC_OK;
   GUARD_END
 }

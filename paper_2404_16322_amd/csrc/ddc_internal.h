@@ -36,7 +36,7 @@ struct ScanArgs {
   int64_t *out_ids;
   float *out_d;
   int64_t *counters;       // NULL or [kMaxCounters] (added to)
-  int32_t nq, nblocks, block_b, prune, nlist;
+  int32_t nq, nblocks, block_b, prune, nlist, k_max;
   float m[kMaxBlocks];     // per 32-dim block: slope of the test after this block
   float beta[kMaxBlocks];  //                   bias of the test after this block
   int8_t test_after[kMaxBlocks]; // 1 if a stage test follows block b

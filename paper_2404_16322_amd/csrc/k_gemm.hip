@@ -54,29 +54,41 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(GemmArgs g) {
 
   for (int k0 = 0; k0 < g.K; k0 += BK) {
     // stage A (minus mu) and B tiles: 64 rows x 32 k, 8 elements per thread each
+    const bool vec = (g.lda % 4 == 0) && (g.ldb % 4 == 0) && (k0 + BK <= g.K);
 #pragma unroll
     for (int it = 0; it < 2; ++it) {
       const int e = tid + it * 256;       // 0..511 -> (row, k4)
       const int r = e >> 3;
       const int kc = (e & 7) * 4;
-      float av[4], bv[4];
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int k = k0 + kc + t;
-        const int64_t gm = m0 + r;
-        const int gn = n0 + r;
-        float x = 0.f, y = 0.f;
-        if (k < g.K) {
-          if (gm < g.M) x = g.A[gm * g.lda + k] - (g.mu ? g.mu[k] : 0.f);
-          if (gn < g.N) y = g.B[(int64_t)gn * g.ldb + k];
+      const int64_t gm = m0 + r;
+      const int gn = n0 + r;
+      float4 av = make_float4(0.f, 0.f, 0.f, 0.f), bv = av;
+      if (vec) {
+        if (gm < g.M) {
+          av = *reinterpret_cast<const float4 *>(g.A + gm * g.lda + k0 + kc);
+          if (g.mu) {
+            const float4 mv = *reinterpret_cast<const float4 *>(g.mu + k0 + kc);
+            av.x -= mv.x; av.y -= mv.y; av.z -= mv.z; av.w -= mv.w;
+          }
         }
-        av[t] = x; bv[t] = y;
-      }
+        if (gn < g.N) bv = *reinterpret_cast<const float4 *>(g.B + (int64_t)gn * g.ldb + k0 + kc);
+      } else {
+        float ta[4], tb[4];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        As[r * LDA + kc + t] = av[t];
-        Bs[r * LDA + kc + t] = bv[t];
+        for (int t = 0; t < 4; ++t) {
+          const int k = k0 + kc + t;
+          float x = 0.f, y = 0.f;
+          if (k < g.K) {
+            if (gm < g.M) x = g.A[gm * g.lda + k] - (g.mu ? g.mu[k] : 0.f);
+            if (gn < g.N) y = g.B[(int64_t)gn * g.ldb + k];
+          }
+          ta[t] = x; tb[t] = y;
+        }
+        av = make_float4(ta[0], ta[1], ta[2], ta[3]);
+        bv = make_float4(tb[0], tb[1], tb[2], tb[3]);
       }
+      *reinterpret_cast<float4 *>(&As[r * LDA + kc]) = av;
+      *reinterpret_cast<float4 *>(&Bs[r * LDA + kc]) = bv;
     }
     __syncthreads();
     if (g.prec == 0) {
@@ -164,41 +176,73 @@ void launch_gemm(const GemmArgs &g, hipStream_t s) {
 // ------------------------------------------------------------------------------------
 constexpr int kSelThreads = 256;
 
+__device__ inline int wave_incl_scan(int v) {
+  const int lane = __lane_id();
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t = __shfl_up(v, o);
+    if (lane >= o) v += t;
+  }
+  return v;
+}
+
+// Exclusive prefix of one int per thread over the workgroup, in thread order; also the total.
+__device__ inline int block_excl_scan(int v, int *wsum, int &total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int inc = wave_incl_scan(v);
+  if (lane == 63) wsum[wave] = inc;
+  __syncthreads();
+  int before = 0;
+  total = 0;
+#pragma unroll
+  for (int w = 0; w < kSelThreads / 64; ++w) {
+    const int x = wsum[w];
+    if (w < wave) before += x;
+    total += x;
+  }
+  __syncthreads();
+  return before + inc - v;
+}
+
 __global__ __launch_bounds__(kSelThreads) void select_kernel(const float *dist, int64_t ld,
                                                              int32_t nlist, const int32_t *nprobe,
                                                              int32_t nprobe_all, int32_t *probes,
                                                              int32_t p_stride) {
   extern __shared__ __align__(16) unsigned char smem[];
   int32_t *hist = reinterpret_cast<int32_t *>(smem);           // [256]
-  int32_t *scan = hist + 256;                                    // [kSelThreads + 1]
-  int32_t *sh = scan + kSelThreads + 1;                          // [4] misc
-  uint32_t *sel_k = reinterpret_cast<uint32_t *>(sh + 4);        // [np]
-  int32_t *sel_j = reinterpret_cast<int32_t *>(sel_k + p_stride);  // [np]
+  int32_t *wsum = hist + 256;                                    // [4]
+  int32_t *sh = wsum + 4;                                        // [4]
+  uint32_t *sel_k = reinterpret_cast<uint32_t *>(sh + 4);        // [p_stride]
+  int32_t *sel_j = reinterpret_cast<int32_t *>(sel_k + p_stride);  // [p_stride]
 
   const int64_t q = blockIdx.x;
   const int tid = threadIdx.x;
   const int np = nprobe ? nprobe[q] : nprobe_all;
   const float *row = dist + q * ld;
-  auto key_of = [&](int j) -> uint32_t { return f32_order_key(row[j]); };
 
+  // radix select (8 bits per pass, most significant first) of the np-th smallest key
   uint32_t prefix = 0, mask = 0;
-  int kk = np;  // rank (1-based) of the threshold among items matching the prefix
+  int kk = np;
   for (int shift = 24; shift >= 0; shift -= 8) {
     hist[tid] = 0;
     __syncthreads();
     for (int j = tid; j < nlist; j += kSelThreads) {
-      const uint32_t u = key_of(j);
+      const uint32_t u = f32_order_key(row[j]);
       if ((u & mask) == prefix) atomicAdd(&hist[(u >> shift) & 255], 1);
     }
     __syncthreads();
-    if (tid == 0) {
-      int cum = 0, d = 0;
-      for (d = 0; d < 256; ++d) {
-        if (cum + hist[d] >= kk) break;
-        cum += hist[d];
+    if (tid < 64) {   // one wavefront finds the bucket holding rank kk
+      const int h0 = hist[4 * tid], h1 = hist[4 * tid + 1], h2 = hist[4 * tid + 2], h3 = hist[4 * tid + 3];
+      const int inc = wave_incl_scan(h0 + h1 + h2 + h3);
+      const int exc = inc - (h0 + h1 + h2 + h3);
+      if (exc < kk && kk <= inc) {
+        int c = exc, d = 4 * tid;
+        if (c + h0 < kk) { c += h0; ++d;
+          if (c + h1 < kk) { c += h1; ++d;
+            if (c + h2 < kk) { c += h2; ++d; } } }
+        sh[0] = d;
+        sh[1] = kk - c;
       }
-      sh[0] = d;
-      sh[1] = kk - cum;
     }
     __syncthreads();
     prefix |= (uint32_t)sh[0] << shift;
@@ -206,37 +250,22 @@ __global__ __launch_bounds__(kSelThreads) void select_kernel(const float *dist, 
     kk = sh[1];
     __syncthreads();
   }
-  // prefix = threshold key; take every key < prefix and the first kk (by index) == prefix.
+  // prefix = threshold key; take every key < prefix and the first kk (by index) == prefix,
+  // in index order via exclusive scans over contiguous per-thread index ranges.
   const int chunk = (nlist + kSelThreads - 1) / kSelThreads;
   const int jb = tid * chunk, je = min(nlist, jb + chunk);
   int nless = 0, neq = 0;
   for (int j = jb; j < je; ++j) {
-    const uint32_t u = key_of(j);
+    const uint32_t u = f32_order_key(row[j]);
     nless += u < prefix;
     neq += u == prefix;
   }
-  // exclusive scans of nless and neq over threads (in index order)
-  scan[tid] = nless;
-  __syncthreads();
-  if (tid == 0) {
-    int c = 0;
-    for (int t = 0; t < kSelThreads; ++t) { const int v = scan[t]; scan[t] = c; c += v; }
-    scan[kSelThreads] = c;
-  }
-  __syncthreads();
-  int pl = scan[tid];
-  const int total_less = scan[kSelThreads];
-  __syncthreads();
-  scan[tid] = neq;
-  __syncthreads();
-  if (tid == 0) {
-    int c = 0;
-    for (int t = 0; t < kSelThreads; ++t) { const int v = scan[t]; scan[t] = c; c += v; }
-  }
-  __syncthreads();
-  int pe = scan[tid];
+  int total_less;
+  int pl = block_excl_scan(nless, wsum, total_less);
+  int total_eq;
+  int pe = block_excl_scan(neq, wsum, total_eq);
   for (int j = jb; j < je; ++j) {
-    const uint32_t u = key_of(j);
+    const uint32_t u = f32_order_key(row[j]);
     if (u < prefix) {
       sel_k[pl] = u; sel_j[pl] = j; ++pl;
     } else if (u == prefix) {
@@ -245,7 +274,7 @@ __global__ __launch_bounds__(kSelThreads) void select_kernel(const float *dist, 
     }
   }
   __syncthreads();
-  // rank sort by (key, index)
+  // rank sort of the np selected by (key, index)
   for (int i = tid; i < np; i += kSelThreads) {
     const uint32_t u = sel_k[i];
     const int j = sel_j[i];
@@ -262,7 +291,7 @@ void launch_select(const float *dist, int64_t ld, int32_t nlist, const int32_t *
                    int32_t nprobe_all, int32_t nprobe_max, int32_t *probes, int32_t p_stride,
                    int64_t nq, hipStream_t s) {
   if (nq <= 0) return;
-  const size_t smem = (256 + kSelThreads + 1 + 4) * 4 + (size_t)p_stride * 8;
+  const size_t smem = (256 + 4 + 4) * 4 + (size_t)p_stride * 8;
   hipLaunchKernelGGL(select_kernel, dim3((unsigned)nq), dim3(kSelThreads), smem, s, dist, ld, nlist,
                      nprobe, nprobe_all, probes, p_stride);
   (void)nprobe_max;

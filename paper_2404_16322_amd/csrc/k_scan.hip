@@ -88,87 +88,111 @@ __device__ inline unsigned long long lane_mask_lt() {
 
 }  // namespace
 
+// Per-wavefront LDS: rotated query, two result queues (double buffer), the block's
+// survivors and two alive lists of the staged scan.
+struct WaveLds {
+  size_t q, td, ti, sd, si, ac, ae, bytes;
+};
+__host__ __device__ inline size_t align16(size_t b) { return (b + 15) & ~(size_t)15; }
+__host__ __device__ inline WaveLds wave_lds(int Dp, int kmax, int block_b) {
+  WaveLds w;
+  size_t o = 0;
+  w.q = o; o += align16((size_t)Dp * 4);
+  w.td = o; o += align16((size_t)2 * kmax * 4);
+  w.ti = o; o += align16((size_t)2 * kmax * 4);
+  w.sd = o; o += align16((size_t)block_b * 4);
+  w.si = o; o += align16((size_t)block_b * 4);
+  w.ac = o; o += align16((size_t)2 * block_b * 2);
+  w.ae = o; o += align16((size_t)2 * block_b * 4);
+  w.bytes = o;
+  return w;
+}
+
+// One wavefront per query, four queries per workgroup; the waves never synchronise with
+// each other, so a query's block chain (scan -> merge -> next tau) runs without barriers.
 template <int ST>
-__global__ __launch_bounds__(kScanThreads) void scan_kernel(ScanArgs a) {
+__global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4, 8))) void scan_kernel(ScanArgs a) {
   using S = Store<ST>;
   constexpr int EPL = 16 / S::kBytes;          // elements per lane load
   constexpr int G = kBlockDims / EPL;          // lanes per vector slice
   constexpr int CPW = 64 / G;                  // slices per wavefront load
-  constexpr int MAXCH = kTile / CPW;           // loads to cover a tile
-  constexpr int SLICE = kBlockDims * S::kBytes;          // bytes per vector slice
-  constexpr int64_t BLOCK_BYTES = (int64_t)kTile * SLICE;  // bytes per tile block
+  constexpr int MAXCH = 64 / CPW;              // loads per group: one 64-vector tile
+  constexpr int GROUP = CPW * MAXCH;           // candidates per load group
+  constexpr int SLICE = kBlockDims * S::kBytes;            // bytes per vector slice
+  constexpr int64_t BLOCK_BYTES = (int64_t)kTile * SLICE;  // bytes per tile dim-block
 
   extern __shared__ __align__(16) unsigned char smem[];
-  const int q = blockIdx.x;
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = tid >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int q = blockIdx.x * (kScanThreads / 64) + wave;
+  if (q >= a.nq) return;   // whole wavefront; no workgroup barrier follows
   const int g = lane % G;
   const int sub = lane / G;
   const int nb = a.nblocks;
   const int Dp = nb * kBlockDims;
-
-  // LDS carve-up
-  float *s_q = reinterpret_cast<float *>(smem);                       // [Dp]
-  float *s_td = s_q + Dp;                                             // [2][kMaxK]
-  int32_t *s_ti = reinterpret_cast<int32_t *>(s_td + 2 * kMaxK);      // [2][kMaxK]
-  float *s_sd = reinterpret_cast<float *>(s_ti + 2 * kMaxK);          // [block_b]
-  int32_t *s_si = reinterpret_cast<int32_t *>(s_sd + a.block_b);      // [block_b]
-  uint16_t *s_ac = reinterpret_cast<uint16_t *>(s_si + a.block_b);    // [4][2][64] alive cand
-  float *s_ae = reinterpret_cast<float *>(s_ac + 4 * 2 * 64);         // [4][2][64] alive e
-  int32_t *s_ctr = reinterpret_cast<int32_t *>(s_ae + 4 * 2 * 64);    // [2] survivor counts
-  int32_t *s_stat = s_ctr + 2;                                        // [3 + 64]
+  const int B = a.block_b;
+  const int KM = a.k_max;
+  const WaveLds L = wave_lds(Dp, KM, B);
+  unsigned char *wl = smem + (size_t)wave * L.bytes;
+  float *s_q = reinterpret_cast<float *>(wl + L.q);
+  float *s_td = reinterpret_cast<float *>(wl + L.td);
+  int32_t *s_ti = reinterpret_cast<int32_t *>(wl + L.ti);
+  float *s_sd = reinterpret_cast<float *>(wl + L.sd);
+  int32_t *s_si = reinterpret_cast<int32_t *>(wl + L.si);
+  uint16_t *s_ac = reinterpret_cast<uint16_t *>(wl + L.ac);
+  float *s_ae = reinterpret_cast<float *>(wl + L.ae);
 
   const int K = a.k ? a.k[q] : a.k_all;
   const int np = a.nprobe ? a.nprobe[q] : a.nprobe_all;
   const float *qg = a.qrot + (int64_t)q * a.q_stride;
-  for (int i = tid; i < Dp; i += kScanThreads) s_q[i] = qg[i];
-  if (tid < 2) s_ctr[tid] = 0;
-  for (int i = tid; i < 3 + 64; i += kScanThreads) s_stat[i] = 0;
-  __syncthreads();
+  for (int i = lane; i < Dp; i += 64) s_q[i] = qg[i];
+  __builtin_amdgcn_wave_barrier();
 
-  // queried lane-private stats
-  int st_cand = 0, st_ref = 0, st_slices = 0;
+  // statistics (wave-uniform, flushed once when counters are requested)
+  int64_t st_cand = 0, st_ref = 0, st_slices = 0;
+  unsigned long long *ctr = reinterpret_cast<unsigned long long *>(a.counters);
 
-  int tin = 0;         // active queue buffer
-  int tn = 0;          // queue size
+  int tin = 0, tn = 0;
   float tau = INFINITY;
   int32_t tau_id = 0x7FFFFFFF;
-  int par = 0;         // survivor-counter parity
   const bool prune = a.prune != 0;
-  const uint16_t *no16 = nullptr;
-  (void)no16;
+  const bool leader = g == 0;
+  const unsigned long long lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
 
   for (int p = 0; p < np; ++p) {
     const int lst = a.probes[(int64_t)q * a.p_stride + p];
     if (lst < 0 || lst >= a.nlist) continue;  // never follow an invalid list id
     const int len = a.list_len[lst];
-    const int64_t tile0 = a.tile_off[lst];
-    for (int bs = 0; bs < len; bs += a.block_b) {
-      const int blen = min(a.block_b, len - bs);
-      const int ntiles = (blen + kTile - 1) / kTile;
-      const bool finite = tn == K;   // tau_b < inf
-      for (int t = wave; t < ntiles; t += 4) {
-        const int64_t tile = tile0 + (bs / kTile) + t;
-        const int cnt = min(kTile, blen - t * kTile);
-        const unsigned char *tb = reinterpret_cast<const unsigned char *>(a.base) +
-                                  tile * (int64_t)nb * BLOCK_BYTES;
-        if (!prune || !finite) {
-          // ---- every candidate of the tile, every block (no test can prune) ----
+    const unsigned char *lbase = reinterpret_cast<const unsigned char *>(a.base) +
+                                 (int64_t)a.tile_off[lst] * nb * BLOCK_BYTES;  // wave-uniform
+    const int32_t *lids = a.ids + (int64_t)a.tile_off[lst] * kTile;
+    for (int bs = 0; bs < len; bs += B) {
+      const int blen = min(B, len - bs);
+      const unsigned char *bbase = lbase + (int64_t)(bs / kTile) * nb * BLOCK_BYTES;
+      const int32_t *bids = lids + bs;
+      int ns = 0;   // survivors of this block (wave-uniform)
+      if (!prune || tn < K) {
+        // ---- no test can prune: every candidate, every dim block ----
+        for (int t0 = 0; t0 < blen; t0 += GROUP) {
+          const int cnt = min(GROUP, blen - t0);
+          const int nch = (cnt + CPW - 1) / CPW;
           float acc[MAXCH];
 #pragma unroll
           for (int c = 0; c < MAXCH; ++c) acc[c] = 0.f;
-          const int nch = (cnt + CPW - 1) / CPW;
           for (int b = 0; b < nb; ++b) {
             float qv[EPL];
 #pragma unroll
             for (int e = 0; e < EPL; ++e) qv[e] = s_q[b * kBlockDims + g * EPL + e];
             uint4 v[MAXCH];
 #pragma unroll
-            for (int c = 0; c < MAXCH; ++c)
-              if (c < nch)
-                v[c] = *reinterpret_cast<const uint4 *>(tb + b * BLOCK_BYTES +
-                                                        (c * CPW + sub) * SLICE + g * 16);
+            for (int c = 0; c < MAXCH; ++c) {
+              if (c < nch) {
+                const int slot = t0 + c * CPW + sub;   // < 64-aligned tile padding
+                const uint32_t off = (uint32_t)((slot / kTile) * nb + b) * (uint32_t)BLOCK_BYTES +
+                                     (uint32_t)((slot % kTile) * SLICE + g * 16);
+                v[c] = *reinterpret_cast<const uint4 *>(bbase + off);
+              }
+            }
 #pragma unroll
             for (int c = 0; c < MAXCH; ++c) {
               if (c < nch) {
@@ -186,49 +210,54 @@ __global__ __launch_bounds__(kScanThreads) void scan_kernel(ScanArgs a) {
           for (int c = 0; c < MAXCH; ++c) {
             if (c < nch) {
               const float dis = group_sum<G>(acc[c]);
-              const int slot = c * CPW + sub;
-              if (g == 0 && slot < cnt) {
-                const int32_t id = a.ids[tile * kTile + slot];
-                if (tn < K || lex_less(dis, id, tau, tau_id)) {
-                  const int pos = atomicAdd(&s_ctr[par], 1);
-                  s_sd[pos] = dis;
-                  s_si[pos] = id;
-                }
+              const int slot = t0 + c * CPW + sub;
+              bool keep = false;
+              int32_t id = 0;
+              if (leader && slot < blen) {
+                id = bids[slot];
+                keep = tn < K || lex_less(dis, id, tau, tau_id);
               }
+              const unsigned long long bal = __ballot(keep);
+              if (keep) {
+                const int pos = ns + __popcll(bal & lt);
+                s_sd[pos] = dis;
+                s_si[pos] = id;
+              }
+              ns += __popcll(bal);
             }
           }
-          if (lane == 0) {
-            st_cand += cnt; st_ref += cnt; st_slices += cnt * nb;
-            atomicAdd(&s_stat[3 + min(nb - 1, 63)], cnt);
-          }
-        } else {
-          // ---- staged scan with per-stage tests and wavefront compaction ----
-          uint16_t *ac = s_ac + wave * 128;
-          float *ae = s_ae + wave * 128;
-          int cur = 0;
-          int nalive = cnt;
-          if (lane == 0) st_cand += cnt;
-          for (int b = 0; b < nb && nalive > 0; ++b) {
-            const bool last = b == nb - 1;
-            const bool test = a.test_after[b] != 0;
-            const float mb = a.m[b], bb = a.beta[b];
-            float qv[EPL];
+        }
+        st_cand += blen; st_ref += blen; st_slices += (int64_t)blen * nb;
+        if (ctr && lane == 0) atomicAdd(&ctr[4 + min(nb - 1, 63)], (unsigned long long)blen);
+      } else {
+        // ---- staged scan: test after every stage, compact the survivors ----
+        int cur = 0;
+        int nalive = blen;
+        st_cand += blen;
+        for (int b = 0; b < nb && nalive > 0; ++b) {
+          const bool last = b == nb - 1;
+          const bool test = a.test_after[b] != 0;
+          const float mb = a.m[b], bb = a.beta[b];
+          float qv[EPL];
 #pragma unroll
-            for (int e = 0; e < EPL; ++e) qv[e] = s_q[b * kBlockDims + g * EPL + e];
-            const int nch = (nalive + CPW - 1) / CPW;
+          for (int e = 0; e < EPL; ++e) qv[e] = s_q[b * kBlockDims + g * EPL + e];
+          int nnext = 0;
+          int pruned = 0;
+          for (int t0 = 0; t0 < nalive; t0 += GROUP) {
+            const int nch = (min(GROUP, nalive - t0) + CPW - 1) / CPW;
             uint4 v[MAXCH];
             int cand[MAXCH];
 #pragma unroll
             for (int c = 0; c < MAXCH; ++c) {
               if (c < nch) {
-                const int slot = c * CPW + sub;
-                const int cd = slot < nalive ? (b == 0 ? slot : (int)ac[cur * 64 + slot]) : 0;
+                const int idx = t0 + c * CPW + sub;
+                const int cd = idx < nalive ? (b == 0 ? idx : (int)s_ac[cur * B + idx]) : 0;
                 cand[c] = cd;
-                v[c] = *reinterpret_cast<const uint4 *>(tb + b * BLOCK_BYTES + cd * SLICE + g * 16);
+                const uint32_t off = (uint32_t)((cd / kTile) * nb + b) * (uint32_t)BLOCK_BYTES +
+                                     (uint32_t)((cd % kTile) * SLICE + g * 16);
+                v[c] = *reinterpret_cast<const uint4 *>(bbase + off);
               }
             }
-            int nnext = 0;
-            int pruned_here = 0;
 #pragma unroll
             for (int c = 0; c < MAXCH; ++c) {
               if (c < nch) {
@@ -241,68 +270,64 @@ __global__ __launch_bounds__(kScanThreads) void scan_kernel(ScanArgs a) {
                   part = fmaf(d, d, part);
                 }
                 part = group_sum<G>(part);
-                const int slot = c * CPW + sub;
-                const bool valid = slot < nalive;
-                const float eprev = (b == 0 || !valid) ? 0.f : ae[cur * 64 + slot];
-                const float ev = eprev + part;
+                const int idx = t0 + c * CPW + sub;
+                const bool valid = leader && idx < nalive;
+                const float ev = (b == 0 || !valid) ? part : s_ae[cur * B + idx] + part;
                 bool keep = valid;
                 if (test && valid) keep = !(fmaf(mb, ev, bb) > tau);
-                const bool leader = g == 0;
                 if (last) {
-                  if (leader && keep) {
-                    const int32_t id = a.ids[tile * kTile + cand[c]];
-                    if (lex_less(ev, id, tau, tau_id)) {
-                      const int pos = atomicAdd(&s_ctr[par], 1);
-                      s_sd[pos] = ev;
-                      s_si[pos] = id;
-                    }
+                  int32_t id = 0;
+                  bool take = false;
+                  if (keep) {
+                    id = bids[cand[c]];
+                    take = lex_less(ev, id, tau, tau_id);
                   }
+                  const unsigned long long bal = __ballot(take);
+                  if (take) {
+                    const int pos = ns + __popcll(bal & lt);
+                    s_sd[pos] = ev;
+                    s_si[pos] = id;
+                  }
+                  ns += __popcll(bal);
                 } else {
-                  const unsigned long long bal = __ballot(leader && keep);
-                  const int pos = nnext + __popcll(bal & lane_mask_lt());
-                  if (leader && keep) {
-                    ac[(cur ^ 1) * 64 + pos] = (uint16_t)cand[c];
-                    ae[(cur ^ 1) * 64 + pos] = ev;
+                  const unsigned long long bal = __ballot(keep);
+                  if (keep) {
+                    const int pos = nnext + __popcll(bal & lt);
+                    s_ac[(cur ^ 1) * B + pos] = (uint16_t)cand[c];
+                    s_ae[(cur ^ 1) * B + pos] = ev;
                   }
                   nnext += __popcll(bal);
                 }
-                pruned_here += __popcll(__ballot(leader && valid && !keep));
+                pruned += __popcll(__ballot(valid && !keep));
               }
-            }
-            if (lane == 0) {
-              st_slices += nalive;
-              if (last) {
-                st_ref += nalive - pruned_here;
-                atomicAdd(&s_stat[3 + min(b, 63)], nalive - pruned_here);
-              }
-              if (pruned_here) atomicAdd(&s_stat[3 + min(b, 63)], pruned_here);
-            }
-            __builtin_amdgcn_wave_barrier();
-            if (!last) {
-              nalive = nnext;
-              cur ^= 1;
             }
           }
+          st_slices += nalive;
+          if (last) st_ref += nalive - pruned;
+          if (ctr && lane == 0) {
+            const int fin = last ? nalive : pruned;   // last block: every remaining one stops here
+            if (fin) atomicAdd(&ctr[4 + min(b, 63)], (unsigned long long)fin);
+          }
+          __builtin_amdgcn_wave_barrier();
+          if (!last) { nalive = nnext; cur ^= 1; }
         }
       }
-      __syncthreads();  // survivors of the block complete
-      const int ns = s_ctr[par];
+      __builtin_amdgcn_wave_barrier();
       if (ns > 0) {
-        // ---- merge: queue (sorted, tn) + survivors (ns, unsorted) -> K smallest ----
-        const float *td = s_td + tin * kMaxK;
-        const int32_t *ti = s_ti + tin * kMaxK;
-        float *od = s_td + (tin ^ 1) * kMaxK;
-        int32_t *oi = s_ti + (tin ^ 1) * kMaxK;
-        for (int i = tid; i < tn + ns; i += kScanThreads) {
+        // ---- merge: queue (sorted, tn) + survivors (ns) -> K smallest by (dis, id) ----
+        const float *td = s_td + tin * KM;
+        const int32_t *ti = s_ti + tin * KM;
+        float *od = s_td + (tin ^ 1) * KM;
+        int32_t *oi = s_ti + (tin ^ 1) * KM;
+        for (int i = lane; i < tn + ns; i += 64) {
           float d;
           int32_t id;
           int rank;
           if (i < tn) {
-            d = td[i]; id = ti[i];
-            rank = i;
+            d = td[i]; id = ti[i]; rank = i;
           } else {
             d = s_sd[i - tn]; id = s_si[i - tn];
-            int lo = 0, hi = tn;           // queue entries smaller than (d, id)
+            int lo = 0, hi = tn;
             while (lo < hi) {
               const int mid = (lo + hi) >> 1;
               if (lex_less(td[mid], ti[mid], d, id)) lo = mid + 1; else hi = mid;
@@ -312,53 +337,39 @@ __global__ __launch_bounds__(kScanThreads) void scan_kernel(ScanArgs a) {
           for (int j = 0; j < ns; ++j) rank += lex_less(s_sd[j], s_si[j], d, id) ? 1 : 0;
           if (rank < K) { od[rank] = d; oi[rank] = id; }
         }
-      }
-      if (tid == 0) s_ctr[par ^ 1] = 0;
-      __syncthreads();  // merge complete
-      if (ns > 0) {
+        __builtin_amdgcn_wave_barrier();
         tin ^= 1;
         tn = min(K, tn + ns);
+        if (tn == K) {
+          tau = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(s_td[tin * KM + K - 1])));
+          tau_id = __builtin_amdgcn_readfirstlane(s_ti[tin * KM + K - 1]);
+        }
       }
-      if (tn == K) {
-        tau = s_td[tin * kMaxK + K - 1];
-        tau_id = s_ti[tin * kMaxK + K - 1];
-      }
-      par ^= 1;
     }
   }
 
   // ---- finalize: ascending (dis, id), original ids, padding ----
   const int64_t off = a.out_off ? a.out_off[q] : (int64_t)q * a.k_all;
-  for (int i = tid; i < K; i += kScanThreads) {
+  for (int i = lane; i < K; i += 64) {
     const bool have = i < tn;
-    a.out_ids[off + i] = have ? (int64_t)s_ti[tin * kMaxK + i] : (int64_t)-1;
-    a.out_d[off + i] = have ? s_td[tin * kMaxK + i] : INFINITY;
+    a.out_ids[off + i] = have ? (int64_t)s_ti[tin * KM + i] : (int64_t)-1;
+    a.out_d[off + i] = have ? s_td[tin * KM + i] : INFINITY;
   }
-  if (a.counters) {
-    if (lane == 0) {
-      atomicAdd(&s_stat[0], st_cand);
-      atomicAdd(&s_stat[1], st_ref);
-      atomicAdd(&s_stat[2], st_slices);
-    }
-    __syncthreads();
-    for (int i = tid; i < 3 + 64; i += kScanThreads) {
-      const int v = s_stat[i];
-      if (v) atomicAdd(reinterpret_cast<unsigned long long *>(&a.counters[i < 3 ? i : i + 1]),
-                       (unsigned long long)v);
-    }
+  if (ctr && lane == 0) {
+    atomicAdd(&ctr[0], (unsigned long long)st_cand);
+    atomicAdd(&ctr[1], (unsigned long long)st_ref);
+    atomicAdd(&ctr[2], (unsigned long long)st_slices);
   }
 }
 
-size_t scan_smem_bytes(int nblocks, int block_b) {
-  const size_t Dp = (size_t)nblocks * kBlockDims;
-  return Dp * 4 + 2 * kMaxK * 8 + (size_t)block_b * 8 + 4 * 2 * 64 * 2 + 4 * 2 * 64 * 4 +
-         (2 + 3 + 64) * 4;
+size_t scan_smem_bytes(int nblocks, int kmax, int block_b) {
+  return 4 * wave_lds(nblocks * kBlockDims, kmax, block_b).bytes;
 }
 
 void launch_scan(const ScanArgs &a, int store, hipStream_t s) {
   if (a.nq <= 0) return;
-  const size_t smem = scan_smem_bytes(a.nblocks, a.block_b);
-  dim3 grid((unsigned)a.nq), block(kScanThreads);
+  const size_t smem = scan_smem_bytes(a.nblocks, a.k_max, a.block_b);
+  dim3 grid((unsigned)((a.nq + 3) / 4)), block(kScanThreads);
   switch (store) {
     case ST_F32: hipLaunchKernelGGL(scan_kernel<ST_F32>, grid, block, smem, s, a); break;
     case ST_F16: hipLaunchKernelGGL(scan_kernel<ST_F16>, grid, block, smem, s, a); break;

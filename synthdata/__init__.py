@@ -111,14 +111,16 @@ WORKLOADS = {
 
 
 def make_workload(name: str, n: int | None = None, nq: int | None = None,
-                  n_calib: int | None = None, n_val: int | None = None) -> dict:
+                  n_calib: int | None = None, n_val: int | None = None,
+                  spread: tuple | None = None) -> dict:
     """Build a workload.  Sizes default to the full configuration; smaller
     sizes draw from the same distribution (same rotation and mixture), so a
     reduced case is a prefix-free sample of the same data source.
 
     Returns dict(base, queries, calib, val) as float32 C-contiguous arrays plus
     the recipe (``spec``) and, for the Gaussian case, the true spectrum and
-    rotation (``lam``, ``rot``) for closed-form checks.
+    rotation (``lam``, ``rot``) for closed-form checks.  ``spread`` overrides the
+    mixture's (between-component, within-component) per-coordinate std.
     """
     spec = dict(WORKLOADS[name])
     n = spec["n"] if n is None else n
@@ -136,7 +138,8 @@ def make_workload(name: str, n: int | None = None, nq: int | None = None,
     else:
         lam = _power_spectrum(D, spec["expo"])
         if kind == "sift":
-            mix = Mixture(D, spec["comps"], lam, centre=127.5, mean_std=30.0, within_std=15.0,
+            ms, ws = spread or (21.0, 24.0)
+            mix = Mixture(D, spec["comps"], lam, centre=127.5, mean_std=ms, within_std=ws,
                           seed_rot=sd(STREAM_ROT), seed_mix=sd(STREAM_MIX))
 
             def gen(cnt, stream):
