@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <limits>
 #include <map>
@@ -120,6 +121,15 @@ struct AsyncBuf {
   AsyncBuf(size_t bytes, hipStream_t st) : s(st) {
     if (bytes) HIPC(hipMallocAsync(&p, bytes, st));
   }
+  AsyncBuf(const AsyncBuf &) = delete;
+  AsyncBuf &operator=(AsyncBuf &&o) noexcept {
+    if (this != &o) {
+      if (p) (void)hipFreeAsync(p, s);
+      p = o.p; s = o.s; o.p = nullptr;
+    }
+    return *this;
+  }
+  AsyncBuf(AsyncBuf &&o) noexcept : p(o.p), s(o.s) { o.p = nullptr; }
   ~AsyncBuf() {
     if (p) (void)hipFreeAsync(p, s);
   }
@@ -155,6 +165,8 @@ struct ddc_index {
     for (auto &m : marks) { (void)hipEventDestroy(m.a); (void)hipEventDestroy(m.b); }
   }
 
+  // result-invariant launch knobs (environment DDC_QUERY_ORDER / DDC_XCD_SWIZZLE = 0 or 1)
+  int query_order = 1, xcd_swizzle = 1;
   int store() const { return storage == DDC_F32 ? ST_F32 : storage == DDC_F16 ? ST_F16 : ST_BF16; }
   int esize() const { return storage == DDC_F32 ? 4 : 2; }
 };
@@ -519,6 +531,16 @@ static void search_device(ddc_index *ix, const float *d_q, int64_t nq, const int
     a.out_ids = d_off ? d_ids : d_ids + q0 * k_all;
     a.out_d = d_off ? d_d : d_d + q0 * k_all;
     a.counters = d_ctr;
+    AsyncBuf ord_hist(0, s), ord_rank(0, s), ord(0, s);
+    if (ix->query_order) {
+      ord_hist = AsyncBuf((size_t)(ix->nlist + 1) * 4, s);
+      ord_rank = AsyncBuf((size_t)nqc * 4, s);
+      ord = AsyncBuf((size_t)nqc * 4, s);
+      launch_query_order(probes.as<int32_t>(), np_max, nqc, ix->nlist, ord_hist.as<int32_t>(),
+                         ord_rank.as<int32_t>(), ord.as<int32_t>(), s);
+      a.order = ord.as<int32_t>();
+    }
+    a.xcd_swizzle = ix->xcd_swizzle;
     a.nq = (int32_t)nqc; a.nblocks = ix->NB; a.block_b = ix->B; a.nlist = ix->nlist;
     a.k_max = k_max;
     timed(ix, 3, s, [&] { launch_scan(a, ix->store(), s); });
@@ -584,6 +606,8 @@ static void init_sizes(ddc_index *ix, int64_t n, int D, int nlist, int dd, int B
   ix->St = ix->S - 1;
   (void)hipGetDevice(&ix->device);
   set_pool_retain(ix->device);
+  if (const char *e = getenv("DDC_QUERY_ORDER")) ix->query_order = atoi(e) != 0;
+  if (const char *e = getenv("DDC_XCD_SWIZZLE")) ix->xcd_swizzle = atoi(e) != 0;
 }
 
 // ---------------------------------------------------------------------------------------

@@ -36,6 +36,8 @@ struct ScanArgs {
   int64_t *out_ids;
   float *out_d;
   int64_t *counters;       // NULL or [kMaxCounters] (added to)
+  const int32_t *order;    // NULL or [nq]: wave slot -> query (results do not depend on it)
+  int32_t xcd_swizzle;     // 1: workgroup w runs slot range of XCD (w mod 8), contiguous per XCD
   int32_t nq, nblocks, block_b, prune, nlist, k_max;
   float m[kMaxBlocks];     // per 32-dim block: slope of the test after this block
   float beta[kMaxBlocks];  //                   bias of the test after this block
@@ -43,6 +45,11 @@ struct ScanArgs {
 };
 
 void launch_scan(const ScanArgs &a, int store, hipStream_t s);
+
+// Query order for cache locality: queries grouped by their first probed list (counting sort,
+// order within a group arbitrary).  hist: [nlist + 1] scratch, rank: [nq] scratch.
+void launch_query_order(const int32_t *probes, int32_t p_stride, int64_t nq, int32_t nlist,
+                        int32_t *hist, int32_t *rank, int32_t *order, hipStream_t s);
 
 // C[M x N] = (A - mu)[M x K] * B[N x K]^T on MFMA, FP32 accumulation.
 //   mode 0: out[m][n] = acc                      (query / base rotation)

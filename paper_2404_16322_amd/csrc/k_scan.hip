@@ -60,21 +60,49 @@ template <> struct Store<ST_BF16> {
   }
 };
 
-// Sum over aligned groups of G lanes with DPP moves (every lane of the group gets the sum).
+// Lane exchanges inside aligned groups of 8 lanes (DPP, no LDS traffic).
 __device__ inline float dpp_xor1(float v) {  // quad_perm [1,0,3,2]
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));
 }
 __device__ inline float dpp_xor2(float v) {  // quad_perm [2,3,0,1]
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, false));
 }
-__device__ inline float dpp_half_mirror(float v) {  // lane i <- lane 7-i within 8
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x141, 0xF, 0xF, false));
+__device__ inline float dpp_xor4(float v) {  // row_shl:4 into banks 0,2 and row_shr:4 into banks 1,3
+  const int x = __float_as_int(v);
+  int r = __builtin_amdgcn_update_dpp(x, x, 0x104, 0xF, 0x5, false);
+  r = __builtin_amdgcn_update_dpp(r, x, 0x114, 0xF, 0xA, false);
+  return __int_as_float(r);
 }
-template <int G> __device__ inline float group_sum(float v) {
-  v += dpp_xor1(v);
-  v += dpp_xor2(v);
-  if (G == 8) v += dpp_half_mirror(v);
-  return v;
+
+// Transposed group reduction: lane j of every aligned group of G lanes (G = 4 or 8) holds
+// G partial sums p[0..G-1]; on return it holds the group-wide sum of p[j].  Each halving
+// step keeps the half of the values selected by one bit of j and adds the partner's copy.
+template <int G> __device__ inline float transpose_sum(const float (&p)[G], int j) {
+  float q[4];
+  if constexpr (G == 8) {
+    const bool hi = (j & 4) != 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const float send = hi ? p[i] : p[i + 4];
+      const float keep = hi ? p[i + 4] : p[i];
+      q[i] = keep + dpp_xor4(send);
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) q[i] = p[i];
+  }
+  float r[2];
+  const bool h1 = (j & 2) != 0;
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const float send = h1 ? q[i] : q[i + 2];
+    const float keep = h1 ? q[i + 2] : q[i];
+    r[i] = keep + dpp_xor2(send);
+  }
+  const bool h0 = (j & 1) != 0;
+  const float send = h0 ? r[0] : r[1];
+  const float keep = h0 ? r[1] : r[0];
+  return keep + dpp_xor1(send);
 }
 
 __device__ inline bool lex_less(float d, int32_t id, float td, int32_t tid) {
@@ -110,7 +138,7 @@ __host__ __device__ inline WaveLds wave_lds(int Dp, int kmax, int block_b) {
 
 // One wavefront per query, four queries per workgroup; the waves never synchronise with
 // each other, so a query's block chain (scan -> merge -> next tau) runs without barriers.
-template <int ST>
+template <int ST, bool PRUNE>
 __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4, 8))) void scan_kernel(ScanArgs a) {
   using S = Store<ST>;
   constexpr int EPL = 16 / S::kBytes;          // elements per lane load
@@ -124,8 +152,16 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
   extern __shared__ __align__(16) unsigned char smem[];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int q = blockIdx.x * (kScanThreads / 64) + wave;
-  if (q >= a.nq) return;   // whole wavefront; no workgroup barrier follows
+  int wg = blockIdx.x;
+  if (a.xcd_swizzle) {
+    // consecutive workgroups land on XCDs 0..7 in turn: give each XCD a contiguous range
+    const int n = gridDim.x, x = wg % 8, r = wg / 8;
+    const int per = n / 8, rem = n % 8;
+    wg = x * per + min(x, rem) + r;
+  }
+  const int slot = wg * (kScanThreads / 64) + wave;
+  if (slot >= a.nq) return;   // whole wavefront; no workgroup barrier follows
+  const int q = a.order ? a.order[slot] : slot;
   const int g = lane % G;
   const int sub = lane / G;
   const int nb = a.nblocks;
@@ -155,8 +191,6 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
   int tin = 0, tn = 0;
   float tau = INFINITY;
   int32_t tau_id = 0x7FFFFFFF;
-  const bool prune = a.prune != 0;
-  const bool leader = g == 0;
   const unsigned long long lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
 
   for (int p = 0; p < np; ++p) {
@@ -171,66 +205,58 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
       const unsigned char *bbase = lbase + (int64_t)(bs / kTile) * nb * BLOCK_BYTES;
       const int32_t *bids = lids + bs;
       int ns = 0;   // survivors of this block (wave-uniform)
-      if (!prune || tn < K) {
+      // In a load group, chunk c, lane (sub, g) reads dims [g*EPL, g*EPL+EPL) of candidate
+      // t0 + c*CPW + sub; after transpose_sum the lane owns candidate t0 + g*CPW + sub.
+      if (!PRUNE || tn < K) {
         // ---- no test can prune: every candidate, every dim block ----
+        // Slots past blen inside the last tile are zero padding: loads stay in bounds.
         for (int t0 = 0; t0 < blen; t0 += GROUP) {
-          const int cnt = min(GROUP, blen - t0);
-          const int nch = (cnt + CPW - 1) / CPW;
           float acc[MAXCH];
 #pragma unroll
           for (int c = 0; c < MAXCH; ++c) acc[c] = 0.f;
+          const uint32_t tile_off = (uint32_t)(t0 / kTile) * nb * (uint32_t)BLOCK_BYTES;
           for (int b = 0; b < nb; ++b) {
             float qv[EPL];
 #pragma unroll
             for (int e = 0; e < EPL; ++e) qv[e] = s_q[b * kBlockDims + g * EPL + e];
+            const unsigned char *bp = bbase + tile_off + b * BLOCK_BYTES + g * 16;
             uint4 v[MAXCH];
 #pragma unroll
-            for (int c = 0; c < MAXCH; ++c) {
-              if (c < nch) {
-                const int slot = t0 + c * CPW + sub;   // < 64-aligned tile padding
-                const uint32_t off = (uint32_t)((slot / kTile) * nb + b) * (uint32_t)BLOCK_BYTES +
-                                     (uint32_t)((slot % kTile) * SLICE + g * 16);
-                v[c] = *reinterpret_cast<const uint4 *>(bbase + off);
-              }
-            }
+            for (int c = 0; c < MAXCH; ++c)
+              v[c] = *reinterpret_cast<const uint4 *>(bp + (uint32_t)((c * CPW + sub) * SLICE));
 #pragma unroll
             for (int c = 0; c < MAXCH; ++c) {
-              if (c < nch) {
-                float f[EPL];
-                S::unpack(v[c], f);
+              float f[EPL];
+              S::unpack(v[c], f);
 #pragma unroll
-                for (int e = 0; e < EPL; ++e) {
-                  const float d = f[e] - qv[e];
-                  acc[c] = fmaf(d, d, acc[c]);
-                }
+              for (int e = 0; e < EPL; ++e) {
+                const float d = f[e] - qv[e];
+                acc[c] = fmaf(d, d, acc[c]);
               }
             }
           }
-#pragma unroll
-          for (int c = 0; c < MAXCH; ++c) {
-            if (c < nch) {
-              const float dis = group_sum<G>(acc[c]);
-              const int slot = t0 + c * CPW + sub;
-              bool keep = false;
-              int32_t id = 0;
-              if (leader && slot < blen) {
-                id = bids[slot];
-                keep = tn < K || lex_less(dis, id, tau, tau_id);
-              }
-              const unsigned long long bal = __ballot(keep);
-              if (keep) {
-                const int pos = ns + __popcll(bal & lt);
-                s_sd[pos] = dis;
-                s_si[pos] = id;
-              }
-              ns += __popcll(bal);
-            }
+          const float dis = transpose_sum<G>(acc, g);
+          const int slot = t0 + g * CPW + sub;
+          bool keep = false;
+          int32_t id = 0;
+          if (slot < blen) {
+            id = bids[slot];
+            keep = tn < K || lex_less(dis, id, tau, tau_id);
           }
+          const unsigned long long bal = __ballot(keep);
+          if (keep) {
+            const int pos = ns + __popcll(bal & lt);
+            s_sd[pos] = dis;
+            s_si[pos] = id;
+          }
+          ns += __popcll(bal);
         }
         st_cand += blen; st_ref += blen; st_slices += (int64_t)blen * nb;
         if (ctr && lane == 0) atomicAdd(&ctr[4 + min(nb - 1, 63)], (unsigned long long)blen);
-      } else {
+      } else if (PRUNE) {
         // ---- staged scan: test after every stage, compact the survivors ----
+        // Lanes past the live count read the group's first live candidate (same cache
+        // line, always in bounds) and are masked out of every decision.
         int cur = 0;
         int nalive = blen;
         st_cand += blen;
@@ -241,66 +267,67 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
           float qv[EPL];
 #pragma unroll
           for (int e = 0; e < EPL; ++e) qv[e] = s_q[b * kBlockDims + g * EPL + e];
+          const unsigned char *bp = bbase + b * BLOCK_BYTES + g * 16;
+          const uint16_t *alive = s_ac + cur * B;
+          const float *alive_e = s_ae + cur * B;
           int nnext = 0;
           int pruned = 0;
           for (int t0 = 0; t0 < nalive; t0 += GROUP) {
-            const int nch = (min(GROUP, nalive - t0) + CPW - 1) / CPW;
+            const int first = b == 0 ? t0 : (int)alive[t0];
             uint4 v[MAXCH];
-            int cand[MAXCH];
 #pragma unroll
             for (int c = 0; c < MAXCH; ++c) {
-              if (c < nch) {
-                const int idx = t0 + c * CPW + sub;
-                const int cd = idx < nalive ? (b == 0 ? idx : (int)s_ac[cur * B + idx]) : 0;
-                cand[c] = cd;
-                const uint32_t off = (uint32_t)((cd / kTile) * nb + b) * (uint32_t)BLOCK_BYTES +
-                                     (uint32_t)((cd % kTile) * SLICE + g * 16);
-                v[c] = *reinterpret_cast<const uint4 *>(bbase + off);
-              }
+              const int idx = t0 + c * CPW + sub;
+              const int cd = idx < nalive ? (b == 0 ? idx : (int)alive[idx]) : first;
+              const uint32_t off = (uint32_t)(cd / kTile) * nb * (uint32_t)BLOCK_BYTES +
+                                   (uint32_t)((cd % kTile) * SLICE);
+              v[c] = *reinterpret_cast<const uint4 *>(bp + off);
             }
+            float part[MAXCH];
 #pragma unroll
             for (int c = 0; c < MAXCH; ++c) {
-              if (c < nch) {
-                float f[EPL];
-                S::unpack(v[c], f);
-                float part = 0.f;
+              float f[EPL];
+              S::unpack(v[c], f);
+              float acc = 0.f;
 #pragma unroll
-                for (int e = 0; e < EPL; ++e) {
-                  const float d = f[e] - qv[e];
-                  part = fmaf(d, d, part);
-                }
-                part = group_sum<G>(part);
-                const int idx = t0 + c * CPW + sub;
-                const bool valid = leader && idx < nalive;
-                const float ev = (b == 0 || !valid) ? part : s_ae[cur * B + idx] + part;
-                bool keep = valid;
-                if (test && valid) keep = !(fmaf(mb, ev, bb) > tau);
-                if (last) {
-                  int32_t id = 0;
-                  bool take = false;
-                  if (keep) {
-                    id = bids[cand[c]];
-                    take = lex_less(ev, id, tau, tau_id);
-                  }
-                  const unsigned long long bal = __ballot(take);
-                  if (take) {
-                    const int pos = ns + __popcll(bal & lt);
-                    s_sd[pos] = ev;
-                    s_si[pos] = id;
-                  }
-                  ns += __popcll(bal);
-                } else {
-                  const unsigned long long bal = __ballot(keep);
-                  if (keep) {
-                    const int pos = nnext + __popcll(bal & lt);
-                    s_ac[(cur ^ 1) * B + pos] = (uint16_t)cand[c];
-                    s_ae[(cur ^ 1) * B + pos] = ev;
-                  }
-                  nnext += __popcll(bal);
-                }
-                pruned += __popcll(__ballot(valid && !keep));
+              for (int e = 0; e < EPL; ++e) {
+                const float d = f[e] - qv[e];
+                acc = fmaf(d, d, acc);
               }
+              part[c] = acc;
             }
+            const float tot = transpose_sum<G>(part, g);
+            const int idx = t0 + g * CPW + sub;
+            const bool valid = idx < nalive;
+            const int ci = min(idx, B - 1);
+            const int cand = b == 0 ? idx : (int)alive[ci];
+            const float ev = b == 0 ? tot : alive_e[ci] + tot;
+            bool keep = valid;
+            if (test) keep = keep && !(fmaf(mb, ev, bb) > tau);
+            if (last) {
+              int32_t id = 0;
+              bool take = false;
+              if (keep) {
+                id = bids[cand];
+                take = lex_less(ev, id, tau, tau_id);
+              }
+              const unsigned long long bal = __ballot(take);
+              if (take) {
+                const int pos = ns + __popcll(bal & lt);
+                s_sd[pos] = ev;
+                s_si[pos] = id;
+              }
+              ns += __popcll(bal);
+            } else {
+              const unsigned long long bal = __ballot(keep);
+              if (keep) {
+                const int pos = nnext + __popcll(bal & lt);
+                s_ac[(cur ^ 1) * B + pos] = (uint16_t)cand;
+                s_ae[(cur ^ 1) * B + pos] = ev;
+              }
+              nnext += __popcll(bal);
+            }
+            pruned += __popcll(__ballot(valid && !keep));
           }
           st_slices += nalive;
           if (last) st_ref += nalive - pruned;
@@ -362,6 +389,54 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
   }
 }
 
+__global__ void fill_i32_kernel(int32_t *p, int64_t n, int32_t v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void order_hist_kernel(const int32_t *probes, int32_t p_stride, int64_t nq, int32_t *hist,
+                                  int32_t *rank) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < nq) rank[q] = atomicAdd(&hist[probes[q * p_stride] + 1], 1);
+}
+
+__global__ void order_scan_kernel(int32_t *hist, int32_t nlist) {
+  // exclusive prefix over hist[1..nlist] in place (hist[0] = 0), one workgroup
+  __shared__ int32_t part[256];
+  const int t = threadIdx.x;
+  const int chunk = (nlist + 255) / 256;
+  const int b = 1 + t * chunk, e = min(nlist + 1, b + chunk);
+  int s = 0;
+  for (int i = b; i < e; ++i) s += hist[i];
+  part[t] = s;
+  __syncthreads();
+  if (t == 0) {
+    int c = 0;
+    for (int i = 0; i < 256; ++i) { const int v = part[i]; part[i] = c; c += v; }
+  }
+  __syncthreads();
+  int c = part[t];
+  for (int i = b; i < e; ++i) { const int v = hist[i]; hist[i] = c; c += v; }
+}
+
+__global__ void order_scatter_kernel(const int32_t *probes, int32_t p_stride, int64_t nq,
+                                     const int32_t *hist, const int32_t *rank, int32_t *order) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < nq) order[hist[probes[q * p_stride] + 1] + rank[q]] = (int32_t)q;
+}
+
+void launch_query_order(const int32_t *probes, int32_t p_stride, int64_t nq, int32_t nlist,
+                        int32_t *hist, int32_t *rank, int32_t *order, hipStream_t s) {
+  if (nq <= 0) return;
+  hipLaunchKernelGGL(fill_i32_kernel, dim3((nlist + 256) / 256), dim3(256), 0, s, hist,
+                     (int64_t)nlist + 1, 0);
+  const unsigned g = (unsigned)((nq + 255) / 256);
+  hipLaunchKernelGGL(order_hist_kernel, dim3(g), dim3(256), 0, s, probes, p_stride, nq, hist, rank);
+  hipLaunchKernelGGL(order_scan_kernel, dim3(1), dim3(256), 0, s, hist, nlist);
+  hipLaunchKernelGGL(order_scatter_kernel, dim3(g), dim3(256), 0, s, probes, p_stride, nq, hist, rank,
+                     order);
+}
+
 size_t scan_smem_bytes(int nblocks, int kmax, int block_b) {
   return 4 * wave_lds(nblocks * kBlockDims, kmax, block_b).bytes;
 }
@@ -370,10 +445,20 @@ void launch_scan(const ScanArgs &a, int store, hipStream_t s) {
   if (a.nq <= 0) return;
   const size_t smem = scan_smem_bytes(a.nblocks, a.k_max, a.block_b);
   dim3 grid((unsigned)((a.nq + 3) / 4)), block(kScanThreads);
+  const bool p = a.prune != 0;
   switch (store) {
-    case ST_F32: hipLaunchKernelGGL(scan_kernel<ST_F32>, grid, block, smem, s, a); break;
-    case ST_F16: hipLaunchKernelGGL(scan_kernel<ST_F16>, grid, block, smem, s, a); break;
-    default: hipLaunchKernelGGL(scan_kernel<ST_BF16>, grid, block, smem, s, a); break;
+    case ST_F32:
+      if (p) hipLaunchKernelGGL((scan_kernel<ST_F32, true>), grid, block, smem, s, a);
+      else hipLaunchKernelGGL((scan_kernel<ST_F32, false>), grid, block, smem, s, a);
+      break;
+    case ST_F16:
+      if (p) hipLaunchKernelGGL((scan_kernel<ST_F16, true>), grid, block, smem, s, a);
+      else hipLaunchKernelGGL((scan_kernel<ST_F16, false>), grid, block, smem, s, a);
+      break;
+    default:
+      if (p) hipLaunchKernelGGL((scan_kernel<ST_BF16, true>), grid, block, smem, s, a);
+      else hipLaunchKernelGGL((scan_kernel<ST_BF16, false>), grid, block, smem, s, a);
+      break;
   }
 }
 
