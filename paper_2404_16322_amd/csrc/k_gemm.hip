@@ -171,10 +171,16 @@ void launch_gemm(const GemmArgs &g, hipStream_t s) {
 }
 
 // ------------------------------------------------------------------------------------
-// Probe selection: radix select of the nprobe-th smallest (value, index) key, ordered
-// gather, then a rank sort of the selected items.  One workgroup per query.
+// Probe selection: the nprobe smallest (distance, list) pairs of a query, ascending.
+// One wavefront per query (four per workgroup).  Radix select on the order-preserving
+// 32-bit key of the distance, whose first 8-bit digit starts at the highest bit where the
+// row's smallest and largest keys differ (so the first histogram is spread over the whole
+// range); passes stop once the bucket holding the remaining rank has at most kExtra keys,
+// or on the last digit (then every key in it is equal and index order decides).  The
+// chosen keys are rank-sorted by (key, index).
 // ------------------------------------------------------------------------------------
 constexpr int kSelThreads = 256;
+constexpr int kExtra = 64;
 
 __device__ inline int wave_incl_scan(int v) {
   const int lane = __lane_id();
@@ -186,114 +192,159 @@ __device__ inline int wave_incl_scan(int v) {
   return v;
 }
 
-// Exclusive prefix of one int per thread over the workgroup, in thread order; also the total.
-__device__ inline int block_excl_scan(int v, int *wsum, int &total) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int inc = wave_incl_scan(v);
-  if (lane == 63) wsum[wave] = inc;
-  __syncthreads();
-  int before = 0;
-  total = 0;
+__device__ inline uint32_t wave_min_u32(uint32_t v) {
 #pragma unroll
-  for (int w = 0; w < kSelThreads / 64; ++w) {
-    const int x = wsum[w];
-    if (w < wave) before += x;
-    total += x;
-  }
-  __syncthreads();
-  return before + inc - v;
+  for (int o = 32; o > 0; o >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, o));
+  return v;
 }
+__device__ inline uint32_t wave_max_u32(uint32_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, o));
+  return v;
+}
+
+__host__ __device__ inline size_t select_wave_lds(int p_stride) { return 256 * 4 + (size_t)(p_stride + kExtra) * 8; }
 
 __global__ __launch_bounds__(kSelThreads) void select_kernel(const float *dist, int64_t ld,
                                                              int32_t nlist, const int32_t *nprobe,
                                                              int32_t nprobe_all, int32_t *probes,
-                                                             int32_t p_stride) {
+                                                             int32_t p_stride, int64_t nq) {
   extern __shared__ __align__(16) unsigned char smem[];
-  int32_t *hist = reinterpret_cast<int32_t *>(smem);           // [256]
-  int32_t *wsum = hist + 256;                                    // [4]
-  int32_t *sh = wsum + 4;                                        // [4]
-  uint32_t *sel_k = reinterpret_cast<uint32_t *>(sh + 4);        // [p_stride]
-  int32_t *sel_j = reinterpret_cast<int32_t *>(sel_k + p_stride);  // [p_stride]
-
-  const int64_t q = blockIdx.x;
-  const int tid = threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t q = (int64_t)blockIdx.x * (kSelThreads / 64) + wave;
+  if (q >= nq) return;
+  unsigned char *wl = smem + (size_t)wave * select_wave_lds(p_stride);
+  int32_t *hist = reinterpret_cast<int32_t *>(wl);
+  uint32_t *sel_k = reinterpret_cast<uint32_t *>(wl + 256 * 4);
+  int32_t *sel_j = reinterpret_cast<int32_t *>(sel_k + p_stride + kExtra);
   const int np = nprobe ? nprobe[q] : nprobe_all;
   const float *row = dist + q * ld;
+  const unsigned long long lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
 
-  // radix select (8 bits per pass, most significant first) of the np-th smallest key
-  uint32_t prefix = 0, mask = 0;
-  int kk = np;
-  for (int shift = 24; shift >= 0; shift -= 8) {
-    hist[tid] = 0;
-    __syncthreads();
-    for (int j = tid; j < nlist; j += kSelThreads) {
+  uint32_t kmin = 0xFFFFFFFFu, kmax = 0u;
+  for (int j = lane; j < nlist; j += 64) {
+    const uint32_t u = f32_order_key(row[j]);
+    kmin = min(kmin, u);
+    kmax = max(kmax, u);
+  }
+  kmin = wave_min_u32(kmin);
+  kmax = wave_max_u32(kmax);
+  // keys share the bits above `top`; digits are taken below it
+  int top = kmin == kmax ? -1 : 31 - __clz((int)(kmin ^ kmax));
+  uint32_t prefix = top >= 31 ? 0u : (kmin & ~((2u << top) - 1u));
+  uint32_t mask = top >= 31 ? 0u : ~((2u << top) - 1u);
+  if (top < 0) { prefix = kmin; mask = 0xFFFFFFFFu; }
+  int kk = np;          // rank still to place inside the current region
+  int shift = top - 7;  // low bit of the current digit (may go negative: clamp below)
+  int dig = 0;          // bucket of the remaining rank
+  bool boundary_ties = top < 0;  // the region holds a single key value
+  while (top >= 0) {
+    const int sh = max(shift, 0);
+    const int width = top - sh + 1;   // <= 8 bits
+    const uint32_t dmask = (1u << width) - 1u;
+    for (int i = lane; i < 256; i += 64) hist[i] = 0;
+    __builtin_amdgcn_wave_barrier();
+    for (int j = lane; j < nlist; j += 64) {
       const uint32_t u = f32_order_key(row[j]);
-      if ((u & mask) == prefix) atomicAdd(&hist[(u >> shift) & 255], 1);
+      if ((u & mask) == prefix) atomicAdd(&hist[(u >> sh) & dmask], 1);
     }
-    __syncthreads();
-    if (tid < 64) {   // one wavefront finds the bucket holding rank kk
-      const int h0 = hist[4 * tid], h1 = hist[4 * tid + 1], h2 = hist[4 * tid + 2], h3 = hist[4 * tid + 3];
-      const int inc = wave_incl_scan(h0 + h1 + h2 + h3);
-      const int exc = inc - (h0 + h1 + h2 + h3);
-      if (exc < kk && kk <= inc) {
-        int c = exc, d = 4 * tid;
-        if (c + h0 < kk) { c += h0; ++d;
-          if (c + h1 < kk) { c += h1; ++d;
-            if (c + h2 < kk) { c += h2; ++d; } } }
-        sh[0] = d;
-        sh[1] = kk - c;
+    __builtin_amdgcn_wave_barrier();
+    const int h0 = hist[4 * lane], h1 = hist[4 * lane + 1], h2 = hist[4 * lane + 2], h3 = hist[4 * lane + 3];
+    const int inc = wave_incl_scan(h0 + h1 + h2 + h3);
+    const int exc = inc - (h0 + h1 + h2 + h3);
+    int d = 0, before = 0, inb = 0;
+    if (exc < kk && kk <= inc) {
+      int c = exc, dd = 4 * lane;
+      int hv = h0;
+      if (c + h0 < kk) { c += h0; ++dd; hv = h1;
+        if (c + h1 < kk) { c += h1; ++dd; hv = h2;
+          if (c + h2 < kk) { c += h2; ++dd; hv = h3; } } }
+      d = dd; before = c; inb = hv;
+    }
+    const unsigned long long owner = __ballot(exc < kk && kk <= inc);
+    const int src = __ffsll((long long)owner) - 1;
+    d = __shfl(d, src); before = __shfl(before, src); inb = __shfl(inb, src);
+    dig = d;
+    // narrow the region to the bucket holding the remaining rank
+    const uint32_t region_lo = prefix | ((uint32_t)d << sh);
+    if (sh == 0) {
+      prefix = region_lo;
+      mask = 0xFFFFFFFFu;
+      kk -= before;
+      boundary_ties = true;
+      break;
+    }
+    if (inb <= kExtra) {
+      // finalize with the bucket's keys as extra candidates: region = [region_lo, +2^sh)
+      prefix = region_lo;
+      mask |= dmask << sh;
+      kk -= before;
+      break;
+    }
+    prefix = region_lo;
+    mask |= dmask << sh;
+    kk -= before;
+    top = sh - 1;
+    shift = top - 7;
+  }
+  // gather: every key below the region, then the region's keys (all of them when it is a
+  // small bucket; the first kk in index order when it is a single value)
+  const uint32_t region_lo = prefix;
+  int nsel = 0;
+  for (int j0 = 0; j0 < nlist; j0 += 64) {
+    const int j = j0 + lane;
+    const uint32_t u = j < nlist ? f32_order_key(row[j]) : 0xFFFFFFFFu;
+    const bool below = j < nlist && u < region_lo;
+    const bool inreg = j < nlist && (u & mask) == prefix;
+    bool take = below;
+    if (!boundary_ties) take = take || inreg;
+    const unsigned long long bt = __ballot(take);
+    if (take) {
+      const int pos = nsel + __popcll(bt & lt);
+      sel_k[pos] = u;
+      sel_j[pos] = j;
+    }
+    nsel += __popcll(bt);
+  }
+  if (boundary_ties) {
+    int taken = 0;
+    for (int j0 = 0; j0 < nlist && taken < kk; j0 += 64) {
+      const int j = j0 + lane;
+      const uint32_t u = j < nlist ? f32_order_key(row[j]) : 0u;
+      const bool inreg = j < nlist && u == prefix;
+      const unsigned long long bt = __ballot(inreg);
+      const int r = __popcll(bt & lt);
+      if (inreg && taken + r < kk) {
+        sel_k[nsel + taken + r] = u;
+        sel_j[nsel + taken + r] = j;
       }
+      taken = min(kk, taken + __popcll(bt));
     }
-    __syncthreads();
-    prefix |= (uint32_t)sh[0] << shift;
-    mask |= 255u << shift;
-    kk = sh[1];
-    __syncthreads();
+    nsel += taken;
   }
-  // prefix = threshold key; take every key < prefix and the first kk (by index) == prefix,
-  // in index order via exclusive scans over contiguous per-thread index ranges.
-  const int chunk = (nlist + kSelThreads - 1) / kSelThreads;
-  const int jb = tid * chunk, je = min(nlist, jb + chunk);
-  int nless = 0, neq = 0;
-  for (int j = jb; j < je; ++j) {
-    const uint32_t u = f32_order_key(row[j]);
-    nless += u < prefix;
-    neq += u == prefix;
-  }
-  int total_less;
-  int pl = block_excl_scan(nless, wsum, total_less);
-  int total_eq;
-  int pe = block_excl_scan(neq, wsum, total_eq);
-  for (int j = jb; j < je; ++j) {
-    const uint32_t u = f32_order_key(row[j]);
-    if (u < prefix) {
-      sel_k[pl] = u; sel_j[pl] = j; ++pl;
-    } else if (u == prefix) {
-      if (pe < kk) { sel_k[total_less + pe] = u; sel_j[total_less + pe] = j; }
-      ++pe;
-    }
-  }
-  __syncthreads();
-  // rank sort of the np selected by (key, index)
-  for (int i = tid; i < np; i += kSelThreads) {
+  __builtin_amdgcn_wave_barrier();
+  // rank sort by (key, index); the first np ranks are the probes
+  for (int i = lane; i < nsel; i += 64) {
     const uint32_t u = sel_k[i];
     const int j = sel_j[i];
     int r = 0;
-    for (int t = 0; t < np; ++t) {
+    for (int t = 0; t < nsel; ++t) {
       const uint32_t v = sel_k[t];
       r += (v < u) || (v == u && sel_j[t] < j);
     }
-    probes[q * p_stride + r] = j;
+    if (r < np) probes[q * p_stride + r] = j;
   }
+  (void)dig;
 }
 
 void launch_select(const float *dist, int64_t ld, int32_t nlist, const int32_t *nprobe,
                    int32_t nprobe_all, int32_t nprobe_max, int32_t *probes, int32_t p_stride,
                    int64_t nq, hipStream_t s) {
   if (nq <= 0) return;
-  const size_t smem = (256 + 4 + 4) * 4 + (size_t)p_stride * 8;
-  hipLaunchKernelGGL(select_kernel, dim3((unsigned)nq), dim3(kSelThreads), smem, s, dist, ld, nlist,
-                     nprobe, nprobe_all, probes, p_stride);
+  const size_t smem = 4 * select_wave_lds(p_stride);
+  hipLaunchKernelGGL(select_kernel, dim3((unsigned)((nq + 3) / 4)), dim3(kSelThreads), smem, s, dist,
+                     ld, nlist, nprobe, nprobe_all, probes, p_stride, nq);
   (void)nprobe_max;
 }
 

@@ -259,3 +259,54 @@ def test_gpu_fit_pca_and_index_against_oracle():
     ids, d, _ = g.search(w["queries"], 10, 8, 0.1)
     ora = O.search(ix, w["queries"], 10, 8, 0.1)
     _assert_ok(check_search(ids, d, ora, ix))
+
+
+# ------------------------------------------------------------------------------ probe selection edges
+
+def _probe_index(centroids, D=32, n=200, seed=0):
+    """An index whose lists hold a few random vectors, for probe-selection checks."""
+    from paper_2404_16322_amd import Index
+    rng = np.random.default_rng(seed)
+    nl = centroids.shape[0]
+    y = rng.standard_normal((n, D)).astype(np.float32)
+    assign = rng.integers(0, nl, size=n).astype(np.int32)
+    return Index.from_artifacts(dict(mu=np.zeros(D), R=np.eye(D), centroids=centroids.astype(np.float32),
+                                     assign=assign, y=y))
+
+
+def _oracle_probes(q, C, nprobe):
+    d = O.sq_dist_direct(C, q)
+    return np.lexsort((np.arange(C.shape[0]), d))[:nprobe], d
+
+
+@pytest.mark.parametrize("nl,nprobe", [(64, 8), (64, 64), (5000, 100), (5000, 4096), (300, 1)])
+def test_probe_selection_ties_and_sizes(nl, nprobe):
+    rng = np.random.default_rng(nl + nprobe)
+    C = rng.standard_normal((nl, 32)).astype(np.float32)
+    C[10:20] = C[3]          # exact duplicates: equal distances, ordered by list id
+    C[40] = C[3]
+    g = _probe_index(C)
+    Q = rng.standard_normal((50, 32)).astype(np.float32)
+    Q[0] = C[3]              # the duplicated centroid itself: distance 0 ten times over
+    _, probes = g.debug_intermediates(Q, nprobe)
+    C64 = C.astype(np.float64)
+    for qi in range(Q.shape[0]):
+        ref, d = _oracle_probes(Q[qi].astype(np.float64), C64, nprobe)
+        if probes[qi].tolist() == ref.tolist():
+            continue
+        # only near ties between different centroids may reorder
+        ds = np.sort(d)[:nprobe + 1]
+        gaps = np.abs(np.diff(ds)) / np.maximum(ds[1:], 1e-30)
+        gaps = gaps[gaps > 0]
+        assert gaps.size and gaps.min() < TOL, (qi, probes[qi][:12], ref[:12])
+        assert sorted(probes[qi].tolist()) == sorted(set(probes[qi].tolist()))
+    dup = [j for j in probes[0].tolist() if j in {3, 40} | set(range(10, 20))]
+    assert dup == sorted(dup) and dup[:min(12, nprobe)] == [3, *range(10, 20), 40][:min(12, nprobe)]
+
+
+def test_probe_selection_all_equal_distances():
+    C = np.ones((300, 32), np.float32)
+    g = _probe_index(C)
+    _, probes = g.debug_intermediates(np.zeros((3, 32), np.float32), 70)
+    for row in probes:
+        assert row.tolist() == list(range(70))
