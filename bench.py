@@ -62,6 +62,67 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
+def serve_phase(ix, w, offered_qps, seconds, alpha, nlist, seed=0, n_streams=4, max_batch=2048,
+                budget=4 << 30):
+    """Open-loop load: requests of U{1..256} queries (drawn from the query set) arrive as a
+    Poisson process at `offered_qps` queries/s; every query has its own K ~ U{10..100} and
+    nprobe ~ U{16..128}.  Latency = completion seen on the host - scheduled arrival, so a
+    producer running late never hides queueing delay."""
+    import threading
+    from paper_2404_16322_amd import Server
+    rng = np.random.default_rng(1000 + seed)
+    mean_req = 128.5
+    n_req = max(1, int(offered_qps / mean_req * seconds))
+    sizes = rng.integers(1, 257, size=n_req)
+    gaps = rng.exponential(mean_req / offered_qps, size=n_req)
+    Q = w["queries"]
+    reqs = []
+    for nqr in sizes:
+        rows = rng.integers(0, Q.shape[0], size=nqr)
+        reqs.append((np.ascontiguousarray(Q[rows]), rng.integers(10, 101, size=nqr).astype(np.int32),
+                     rng.integers(16, min(128, nlist) + 1, size=nqr).astype(np.int32)))
+    srv = Server(ix, n_streams=n_streams, max_batch=max_batch, hbm_budget_bytes=budget, alpha=alpha)
+    sched = np.cumsum(gaps)
+    tickets = [None] * n_req
+    t_sched = [0] * n_req
+    start = time.monotonic_ns() + 20_000_000
+
+    def producer():
+        for i, (q, k, npb) in enumerate(reqs):
+            t = start + int(sched[i] * 1e9)
+            t_sched[i] = t
+            while time.monotonic_ns() < t:
+                pass
+            tickets[i] = srv.submit(q, k, npb)
+
+    th = threading.Thread(target=producer)
+    th.start()
+    lat = []
+    i = 0
+    while i < n_req:
+        if tickets[i] is None:
+            time.sleep(0.0002)
+            continue
+        r = srv.poll(tickets[i])
+        if r is None:
+            time.sleep(0.0001)
+            continue
+        lat.append((r[3] - t_sched[i]) * 1e-6)
+        i += 1
+    th.join()
+    end = time.monotonic_ns()
+    st = srv.stats()
+    srv.close()
+    lat = np.sort(np.asarray(lat))
+    total_q = int(sizes.sum())
+    return dict(offered_qps=round(offered_qps, 1), achieved_qps=round(total_q / ((end - start) * 1e-9), 1),
+                requests=n_req, queries=total_q, p50_ms=round(float(np.percentile(lat, 50)), 3),
+                p99_ms=round(float(np.percentile(lat, 99)), 3), max_ms=round(float(lat[-1]), 3),
+                server_p50_ms=round(st["p50_ms"], 3), server_p99_ms=round(st["p99_ms"], 3),
+                max_concurrent_batches=st["max_concurrent"], budget_peak_bytes=st["budget_peak_bytes"],
+                n_streams=n_streams, max_batch=max_batch, hbm_budget_bytes=budget)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -73,6 +134,9 @@ def main():
     ap.add_argument("--alpha", type=float, default=0.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=48)
+    ap.add_argument("--serve-rates", default="0.25,0.5",
+                    help="offered load of the serving phase, fractions of the measured peak QPS")
+    ap.add_argument("--serve-seconds", type=float, default=3.0)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -243,6 +307,13 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
 
+    # ---- serving: open-loop Poisson arrivals, continuous batching --------------------------
+    serve = []
+    rates = [float(x) for x in args.serve_rates.split(",") if x.strip()] if args.serve_seconds > 0 else []
+    for frac in rates:
+        serve.append(serve_phase(ix, w, qps * frac, args.serve_seconds, alpha, nlist, seed=len(serve)))
+        log(f"[bench] serve {serve[-1]}")
+
     # ---- CPU oracle baseline (bounded sample) --------------------------------------------
     cpu = None
     if not args.no_cpu_baseline:
@@ -289,6 +360,9 @@ def main():
                        "scanned_dim_ratio": round(slices / max(1, candidates * S), 4),
                        "bytes_vs_full_d": round(slices * slice_bytes / max(1, full_bytes_per_launch), 4)},
         "roofline": roofline,
+        "serve": serve,
+        "serve_p50_ms": serve[-1]["p50_ms"] if serve else None,
+        "serve_p99_ms": serve[-1]["p99_ms"] if serve else None,
         "cpu_baseline": cpu,
         "fit_s": round(fit_s, 2),
         "sweep": sweep,

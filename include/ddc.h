@@ -201,6 +201,44 @@ ddc_status ddc_debug_intermediates(const ddc_index *ix, const float *queries, in
 ddc_status ddc_set_kernel_timing(ddc_index *ix, int enable);
 ddc_status ddc_get_kernel_timing(ddc_index *ix, double *ms_total, int64_t *launches, int reset);
 
+/* ---- continuous-batching server --------------------------------------------------------
+ * A scheduler thread admits queued requests into micro-batches on n_streams HIP streams while
+ * the device bytes of all batches in flight (queries, results, search scratch) stay within
+ * hbm_budget_bytes; batches on different streams overlap on the GPU and a request arriving
+ * while others run starts as soon as a stream and budget are free.  Every query keeps its own
+ * K and N_probe; its result is the same as searching it alone (ddc_search_var).  The index
+ * must outlive the server.  Slot buffers for max_batch queries are allocated at creation. */
+typedef struct ddc_server ddc_server;
+typedef struct {
+  int32_t n_streams;        /* concurrent micro-batches, 1..16 */
+  int32_t max_batch;        /* queries per micro-batch and per request, 1..65536 */
+  int64_t hbm_budget_bytes; /* device bytes all in-flight batches may use */
+  double significance;      /* alpha of every request, [0, 1) */
+  ddc_corr mode;
+} ddc_server_params;
+typedef struct {
+  int64_t requests_done, queries_done, rejected;
+  double qps;               /* queries_done / (last completion - first submission), s^-1 */
+  double p50_ms, p99_ms, max_ms; /* request latency: submission -> results on the host */
+  int64_t budget_peak_bytes;     /* most device bytes in flight at once */
+  int32_t max_concurrent;        /* most batches in flight at once */
+} ddc_server_stats;
+
+ddc_status ddc_server_create(const ddc_index *ix, const ddc_server_params *p, ddc_server **out);
+/* Queue nq queries (host [nq x dim], copied) with per-query k[nq] (1..256) and nprobe[nq]
+ * (1..min(nlist, 4096)); returns at once with a ticket.  DDC_EBUSY when the request alone needs
+ * more device memory than the budget (it is never admitted). */
+ddc_status ddc_server_submit(ddc_server *s, const float *queries, int32_t nq, const int32_t *k,
+                             const int32_t *nprobe, uint64_t *ticket);
+/* *done = 1 and results copied (ids/dists sized sum(k), query-major, each query ascending,
+ * padded) once the request finished, else *done = 0.  t_done_ns (nullable): CLOCK_MONOTONIC
+ * time at which the server saw the results on the host.  A finished ticket is forgotten. */
+ddc_status ddc_server_poll(ddc_server *s, uint64_t ticket, int64_t *ids, float *dists, int *done,
+                           uint64_t *t_done_ns);
+ddc_status ddc_server_get_stats(ddc_server *s, ddc_server_stats *st);
+/* Finishes every queued request, then frees the server. */
+void ddc_server_destroy(ddc_server *s);
+
 void ddc_free(ddc_index *ix);
 const char *ddc_last_error(void);
 

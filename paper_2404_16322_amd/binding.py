@@ -21,7 +21,8 @@ STATUS = {0: "DDC_OK", -1: "DDC_EINVAL", -2: "DDC_ENOMEM", -3: "DDC_EDEVICE", -4
 SYMBOLS = ["ddc_fit_params_default", "ddc_fit", "ddc_import", "ddc_export", "ddc_index_get_info",
            "ddc_calibrate", "ddc_correction", "ddc_search", "ddc_search_var", "ddc_search_device",
            "ddc_debug_intermediates", "ddc_set_kernel_timing", "ddc_get_kernel_timing", "ddc_free",
-           "ddc_last_error"]
+           "ddc_last_error", "ddc_server_create", "ddc_server_submit", "ddc_server_poll",
+           "ddc_server_get_stats", "ddc_server_destroy"]
 
 
 class FitParams(C.Structure):
@@ -55,6 +56,17 @@ class SearchStats(C.Structure):
     def as_dict(self):
         return dict(candidates=self.candidates, refined=self.refined, stage_slices=self.stage_slices,
                     bytes_touched=self.bytes_touched, stage_stop=list(self.stage_stop))
+
+
+class ServerParams(C.Structure):
+    _fields_ = [("n_streams", C.c_int32), ("max_batch", C.c_int32), ("hbm_budget_bytes", C.c_int64),
+                ("significance", C.c_double), ("mode", C.c_int)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("requests_done", C.c_int64), ("queries_done", C.c_int64), ("rejected", C.c_int64),
+                ("qps", C.c_double), ("p50_ms", C.c_double), ("p99_ms", C.c_double),
+                ("max_ms", C.c_double), ("budget_peak_bytes", C.c_int64), ("max_concurrent", C.c_int32)]
 
 
 class DdcError(RuntimeError):
@@ -95,10 +107,16 @@ def load_library():
         lib.ddc_debug_intermediates.argtypes = [vp, vp, i64, i32, vp, vp]
         lib.ddc_set_kernel_timing.argtypes = [vp, C.c_int]
         lib.ddc_get_kernel_timing.argtypes = [vp, vp, vp, C.c_int]
+        lib.ddc_server_create.argtypes = [vp, C.POINTER(ServerParams), C.POINTER(vp)]
+        lib.ddc_server_submit.argtypes = [vp, vp, i32, vp, vp, C.POINTER(C.c_uint64)]
+        lib.ddc_server_poll.argtypes = [vp, C.c_uint64, vp, vp, C.POINTER(C.c_int), C.POINTER(C.c_uint64)]
+        lib.ddc_server_get_stats.argtypes = [vp, C.POINTER(ServerStats)]
+        lib.ddc_server_destroy.argtypes = [vp]
+        lib.ddc_server_destroy.restype = None
         lib.ddc_free.argtypes = [vp]
         lib.ddc_free.restype = None
         for name in SYMBOLS:
-            if name not in ("ddc_free", "ddc_last_error"):
+            if name not in ("ddc_free", "ddc_last_error", "ddc_server_destroy"):
                 getattr(lib, name).restype = st
         _LIB = lib
         return lib
@@ -282,3 +300,58 @@ class Index:
         _check(load_library().ddc_debug_intermediates(self._h, _ptr(q), q.shape[0], nprobe,
                                                       _ptr(qr), _ptr(pr)))
         return qr, pr
+
+
+class Server:
+    """Continuous-batching search server on an index (the index must outlive it)."""
+
+    def __init__(self, index: Index, n_streams=4, max_batch=1024, hbm_budget_bytes=2 << 30,
+                 alpha=0.05, mode="learned"):
+        p = ServerParams(n_streams, max_batch, hbm_budget_bytes, alpha, CORR[mode])
+        h = C.c_void_p()
+        _check(load_library().ddc_server_create(index.handle, C.byref(p), C.byref(h)))
+        self._h = h
+        self._index = index
+        self._nres = {}
+
+    def submit(self, queries, k, nprobe) -> int:
+        q = _f32(queries)
+        k = np.ascontiguousarray(k, np.int32)
+        nprobe = np.ascontiguousarray(nprobe, np.int32)
+        t = C.c_uint64()
+        _check(load_library().ddc_server_submit(self._h, _ptr(q), q.shape[0], _ptr(k), _ptr(nprobe),
+                                                C.byref(t)))
+        self._nres[t.value] = (int(k.sum()), k.copy())
+        return t.value
+
+    def poll(self, ticket: int):
+        """None while running, else (ids, dists, offsets, t_done_ns) for the request."""
+        nres, k = self._nres[ticket]
+        ids = np.empty(nres, np.int64)
+        d = np.empty(nres, np.float32)
+        done = C.c_int(0)
+        tdone = C.c_uint64(0)
+        _check(load_library().ddc_server_poll(self._h, ticket, _ptr(ids), _ptr(d), C.byref(done),
+                                              C.byref(tdone)))
+        if not done.value:
+            return None
+        del self._nres[ticket]
+        off = np.zeros(k.shape[0] + 1, np.int64)
+        off[1:] = np.cumsum(k)
+        return ids, d, off, tdone.value
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(load_library().ddc_server_get_stats(self._h, C.byref(st)))
+        return {f: getattr(st, f) for f, _ in ServerStats._fields_}
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            load_library().ddc_server_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -21,15 +21,13 @@
 #include "ddc.h"
 #include "ddc_internal.h"
 #include "host_math.h"
+#include "runtime.h"
 
 using namespace ddc;
 
-// ---------------------------------------------------------------------------------------
-// errors
-// ---------------------------------------------------------------------------------------
 static thread_local std::string g_err;
 
-static ddc_status set_err(ddc_status st, const char *fmt, ...) {
+ddc_status ddc::set_err(ddc_status st, const char *fmt, ...) {
   char buf[512];
   va_list ap;
   va_start(ap, fmt);
@@ -38,138 +36,6 @@ static ddc_status set_err(ddc_status st, const char *fmt, ...) {
   g_err = buf;
   return st;
 }
-
-struct DdcError : std::runtime_error {
-  ddc_status st;
-  DdcError(ddc_status s, const std::string &m) : std::runtime_error(m), st(s) {}
-};
-
-#define HIPC(expr)                                                                          \
-  do {                                                                                      \
-    hipError_t e_ = (expr);                                                                 \
-    if (e_ != hipSuccess)                                                                   \
-      throw DdcError(e_ == hipErrorOutOfMemory ? DDC_ENOMEM : DDC_EDEVICE,                  \
-                     std::string(#expr) + ": " + hipGetErrorString(e_));                    \
-  } while (0)
-
-#define GUARD_BEGIN try {
-#define GUARD_END                                                        \
-  }                                                                      \
-  catch (const DdcError &e) { return set_err(e.st, "%s", e.what()); }   \
-  catch (const std::bad_alloc &) { return set_err(DDC_ENOMEM, "host allocation failed"); } \
-  catch (const std::exception &e) { return set_err(DDC_EDEVICE, "%s", e.what()); }
-
-// ---------------------------------------------------------------------------------------
-// device memory
-// ---------------------------------------------------------------------------------------
-struct DevBuf {
-  void *p = nullptr;
-  size_t bytes = 0;
-  DevBuf() = default;
-  explicit DevBuf(size_t b) { alloc(b); }
-  DevBuf(const DevBuf &) = delete;
-  DevBuf &operator=(const DevBuf &) = delete;
-  DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
-  void alloc(size_t b) {
-    release();
-    if (b) HIPC(hipMalloc(&p, b));
-    bytes = b;
-  }
-  void release() {
-    if (p) (void)hipFree(p);
-    p = nullptr;
-    bytes = 0;
-  }
-  ~DevBuf() { release(); }
-  template <class T> T *as() const { return reinterpret_cast<T *>(p); }
-};
-
-struct DeviceGuard {
-  int prev = 0;
-  explicit DeviceGuard(int dev) {
-    (void)hipGetDevice(&prev);
-    if (prev != dev) HIPC(hipSetDevice(dev));
-  }
-  ~DeviceGuard() { (void)hipSetDevice(prev); }
-};
-
-struct StreamHolder {
-  hipStream_t s = nullptr;
-  StreamHolder() { HIPC(hipStreamCreateWithFlags(&s, hipStreamNonBlocking)); }
-  ~StreamHolder() {
-    if (s) (void)hipStreamDestroy(s);
-  }
-};
-
-static void set_pool_retain(int dev) {
-  static std::mutex mtx;
-  static std::vector<int> done;
-  std::lock_guard<std::mutex> lk(mtx);
-  if (std::find(done.begin(), done.end(), dev) != done.end()) return;
-  hipMemPool_t pool;
-  if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
-    uint64_t thr = std::numeric_limits<uint64_t>::max();
-    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
-  }
-  done.push_back(dev);
-}
-
-// stream-ordered scratch (returned to the pool when the stream reaches the free)
-struct AsyncBuf {
-  void *p = nullptr;
-  hipStream_t s = nullptr;
-  AsyncBuf(size_t bytes, hipStream_t st) : s(st) {
-    if (bytes) HIPC(hipMallocAsync(&p, bytes, st));
-  }
-  AsyncBuf(const AsyncBuf &) = delete;
-  AsyncBuf &operator=(AsyncBuf &&o) noexcept {
-    if (this != &o) {
-      if (p) (void)hipFreeAsync(p, s);
-      p = o.p; s = o.s; o.p = nullptr;
-    }
-    return *this;
-  }
-  AsyncBuf(AsyncBuf &&o) noexcept : p(o.p), s(o.s) { o.p = nullptr; }
-  ~AsyncBuf() {
-    if (p) (void)hipFreeAsync(p, s);
-  }
-  template <class T> T *as() const { return reinterpret_cast<T *>(p); }
-};
-
-// ---------------------------------------------------------------------------------------
-// index
-// ---------------------------------------------------------------------------------------
-struct ddc_index {
-  int device = 0;
-  int64_t n = 0;
-  int D = 0, Dp = 0, NB = 0, nlist = 0, delta_d = 32, S = 0, St = 0, B = 256, L = 0;
-  ddc_dtype storage = DDC_F32;
-  ddc_rot rot = DDC_ROT_F32;
-  std::vector<double> mu, R, lam;
-  std::vector<float> cent;          // nlist x D
-  std::vector<int32_t> assign;      // n
-  std::vector<int32_t> list_len, tile_off;
-  std::vector<int64_t> id_to_slot;  // n
-  int64_t total_tiles = 0;
-  std::vector<double> m, resid;     // St ; n0 x St
-  int64_t n0 = 0;
-  std::mutex beta_mtx;
-  std::map<std::pair<double, int>, std::vector<double>> beta_cache;
-  DevBuf d_R32, d_mu32, d_cent, d_cnorm, d_tile_off, d_list_len, d_ids, d_base, d_R64, d_mu64;
-  // optional per-kernel event timing
-  bool timing = false;
-  std::mutex timing_mtx;
-  struct Mark { int kernel; hipEvent_t a, b; };
-  std::vector<Mark> marks;
-  ~ddc_index() {
-    for (auto &m : marks) { (void)hipEventDestroy(m.a); (void)hipEventDestroy(m.b); }
-  }
-
-  // result-invariant launch knobs (environment DDC_QUERY_ORDER / DDC_XCD_SWIZZLE = 0 or 1)
-  int query_order = 1, xcd_swizzle = 1;
-  int store() const { return storage == DDC_F32 ? ST_F32 : storage == DDC_F16 ? ST_F16 : ST_BF16; }
-  int esize() const { return storage == DDC_F32 ? 4 : 2; }
-};
 
 static int stage_count(int D, int dd) { return (D + dd - 1) / dd; }
 
@@ -467,11 +333,16 @@ template <class F> static void timed(ddc_index *ix, int kernel, hipStream_t s, F
   ix->marks.push_back(m);
 }
 
-static void search_device(ddc_index *ix, const float *d_q, int64_t nq, const int32_t *d_k, int k_all,
-                          int k_max, const int32_t *d_np, int np_all, int np_max, double alpha,
-                          ddc_corr mode, const int64_t *d_off, int64_t *d_ids, float *d_d,
-                          int64_t *d_ctr, hipStream_t s, float *qrot_out = nullptr,
-                          int32_t *probes_out = nullptr) {
+size_t ddc::search_scratch_bytes(const ddc_index *ix, int64_t nq, int np_max) {
+  const int64_t c = std::min<int64_t>(nq, 32768);
+  return (size_t)c * ix->Dp * 4 + (size_t)c * ix->nlist * 4 + (size_t)c * np_max * 4 +
+         (size_t)(ix->nlist + 1) * 4 + (size_t)c * 8 + 4096;
+}
+
+void ddc::search_device(ddc_index *ix, const float *d_q, int64_t nq, const int32_t *d_k, int k_all,
+                        int k_max, const int32_t *d_np, int np_all, int np_max, double alpha,
+                        ddc_corr mode, const int64_t *d_off, int64_t *d_ids, float *d_d,
+                        int64_t *d_ctr, hipStream_t s, float *qrot_out, int32_t *probes_out) {
   const int Dp = ix->Dp, D = ix->D;
   ScanArgs a{};
   a.prune = 0;

@@ -42,7 +42,8 @@ def test_exports_every_declared_symbol(lib):
 def test_struct_layouts_match_the_c_compiler(tmp_path):
     """sizeof / offsetof of every ABI struct, as gcc lays out include/ddc.h, equal ctypes'."""
     structs = {"ddc_fit_params": B.FitParams, "ddc_artifacts": B.Artifacts,
-               "ddc_index_info": B.IndexInfo, "ddc_search_stats": B.SearchStats}
+               "ddc_index_info": B.IndexInfo, "ddc_search_stats": B.SearchStats,
+               "ddc_server_params": B.ServerParams, "ddc_server_stats": B.ServerStats}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "ddc.h"', "int main(void){"]
     for cname, cls in structs.items():
         lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
@@ -129,3 +130,16 @@ def test_import_rejects_bad_artifacts_without_device(lib):
 def test_correction_rejects_bad_significance(lib):
     m = np.zeros(4)
     assert lib.ddc_correction(None, 0.1, 0, m.ctypes.data, m.ctypes.data) == -1
+
+
+def test_server_rejects_bad_arguments_without_device(lib):
+    out = C.c_void_p()
+    p = B.ServerParams(4, 256, 1 << 30, 0.05, 0)
+    assert lib.ddc_server_create(None, C.byref(p), C.byref(out)) == -1
+    assert out.value is None
+    t = C.c_uint64()
+    assert lib.ddc_server_submit(None, None, 1, None, None, C.byref(t)) == -1
+    done = C.c_int()
+    assert lib.ddc_server_poll(None, 1, None, None, C.byref(done), None) == -1
+    st = B.ServerStats()
+    assert lib.ddc_server_get_stats(None, C.byref(st)) == -1
