@@ -115,7 +115,10 @@ def bruteforce_knn(X: np.ndarray, Q: np.ndarray, k: int, chunk: int = 256):
     for s in range(0, nq, chunk):
         Qc = Q[s:s + chunk]
         qn = np.einsum("ij,ij->i", Qc, Qc)
-        approx = xn[None, :] + qn[:, None] - 2.0 * (Qc @ X.T)
+        approx = Qc @ X.T                  # screened ||x||^2 + ||q||^2 - 2 <x, q>, in place
+        approx *= -2.0
+        approx += xn[None, :]
+        approx += qn[:, None]
         for r in range(Qc.shape[0]):
             a = approx[r]
             if kk == 0:
@@ -211,7 +214,10 @@ def nearest_centroid(Y: np.ndarray, C: np.ndarray, chunk: int = 8192) -> np.ndar
     for s in range(0, Y.shape[0], chunk):
         Yc = Y[s:s + chunk]
         yn = np.einsum("ij,ij->i", Yc, Yc)
-        a = cn[None, :] + yn[:, None] - 2.0 * (Yc @ C.T)
+        a = Yc @ C.T                      # screened ||y||^2 + ||c||^2 - 2 <y, c>, in place
+        a *= -2.0
+        a += cn[None, :]
+        a += yn[:, None]
         amin = a.min(axis=1)
         margin = 1e-10 * (cn.max() + yn) + 1e-300
         close = a <= (amin + margin)[:, None]
