@@ -31,6 +31,27 @@ HBM_PEAK_GBS = 8000.0
 NPROBES = [16, 24, 32, 48, 64, 96, 128]
 ALPHAS = [0.001, 0.005, 0.01, 0.02, 0.05, 0.1]
 
+DESCR = {"sift": "integer 0-255 mixture", "gist": "power-law mixture",
+         "embed": "unit-normalised mixture", "gauss": "Gaussian"}
+
+# name -> data set, index and search settings.  "serve": ("frac", [...]) offers fractions of the
+# measured peak QPS, ("abs", [...]) absolute queries/s.
+CONFIGS = {
+    # 1M x 128 integer descriptors, FP32, IVF 4096, 10,000 queries, K = 10 (the headline)
+    "sift1m": dict(data="sift1m", nlist=4096, storage="f32", rotation="f32", k=10, nprobes=NPROBES,
+                   serve=("frac", [0.25, 0.5])),
+    # 1M x 960, stored BF16 (or FP16), query rotation on BF16 MFMA, 1,000 queries, K = 100,
+    # nprobe 64; per-result distance error against FP64 on the original data
+    "gist1m": dict(data="gist1m", nlist=4096, storage="bf16", rotation="bf16", k=100, nprobes=[64],
+                   error_vs_fp64=True, serve=None),
+    "gist1m-f16": dict(data="gist1m", nlist=4096, storage="f16", rotation="bf16", k=100, nprobes=[64],
+                       error_vs_fp64=True, serve=None),
+    # 5M x 256 unit-normalised FP16, IVF 16384: serving at absolute Poisson rates
+    "embed256": dict(data="embed256", nlist=16384, storage="f16", rotation="f32", k=10,
+                     nprobes=[16, 32, 48, 64, 96, 128], fit=dict(kmeans_train_per_list=64, kmeans_iters=10),
+                     serve=("abs", [5e3, 1e4, 2e4, 3.5e4, 5e4]), gt_queries=2000),
+}
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -129,13 +150,14 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="sift1m")
-    ap.add_argument("--k", type=int, default=10)
+    ap.add_argument("--k", type=int, default=0, help="K (default: the workload's)")
     ap.add_argument("--nprobe", type=int, default=0, help="fix the operating point (skip sweep)")
     ap.add_argument("--alpha", type=float, default=0.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=48)
-    ap.add_argument("--serve-rates", default="0.25,0.5",
-                    help="offered load of the serving phase, fractions of the measured peak QPS")
+    ap.add_argument("--serve-rates", default="",
+                    help="offered loads of the serving phase (override; fractions of the peak QPS "
+                         "or absolute queries/s, as the workload defines)")
     ap.add_argument("--serve-seconds", type=float, default=3.0)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (HBM counter calibration)")
@@ -152,16 +174,18 @@ def main():
 
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
+    cfg = CONFIGS[args.workload]
     t0 = time.time()
-    w = synthdata.make_workload(args.workload)
+    w = synthdata.make_workload(cfg["data"], nq=cfg.get("gt_queries"))
     spec = w["spec"]
     nq, D = w["queries"].shape
     log(f"[bench] workload {args.workload}: n={w['base'].shape[0]} D={D} nq={nq} "
         f"({time.time() - t0:.1f}s)")
 
     t0 = time.time()
-    nlist = 4096
-    ix = Index.fit(w["base"], w["calib"], nlist=nlist, seed=spec["cfg"])
+    nlist = cfg["nlist"]
+    ix = Index.fit(w["base"], w["calib"], nlist=nlist, seed=spec["cfg"], storage=cfg["storage"],
+                   rotation=cfg["rotation"], **cfg.get("fit", {}))
     torch.cuda.synchronize()
     fit_s = time.time() - t0
     info = ix.info()
@@ -175,7 +199,7 @@ def main():
     torch.cuda.empty_cache()
     log(f"[bench] FP64 ground truth {time.time() - t0:.1f}s")
 
-    k = args.k
+    k = args.k or cfg["k"]
     q_dev = torch.from_numpy(w["queries"]).to(dev)
     ids_dev = torch.empty((nq, k), dtype=torch.int64, device=dev)
     d_dev = torch.empty((nq, k), dtype=torch.float32, device=dev)
@@ -206,7 +230,7 @@ def main():
     if args.nprobe:
         points = [(args.nprobe, args.alpha)]
     else:
-        points = [(p, a) for p in NPROBES for a in ALPHAS]
+        points = [(p, a) for p in cfg["nprobes"] for a in ALPHAS]
     best = None
     for p, a in points:
         r = recall(p, a, "learned")
@@ -215,7 +239,7 @@ def main():
         if r >= 0.95 and (best is None or ms < best[2]):
             best = (p, a, ms, r)
     full_best = None
-    for p in (NPROBES if not args.nprobe else [args.nprobe]):
+    for p in (cfg["nprobes"] if not args.nprobe else [args.nprobe]):
         r = recall(p, 0.0, "none")
         ms = timed(p, 0.0, "none", 2)
         sweep.append(dict(nprobe=p, alpha=0.0, recall=r, qps=nq / ms * 1e3, mode="none"))
@@ -231,6 +255,31 @@ def main():
     log(f"[bench] operating point nprobe={nprobe} alpha={alpha} recall@10={rec:.4f}; "
         f"full-D nprobe={full_best[0]} recall@10={full_best[3]:.4f}")
 
+    # ---- per-result distance error against FP64 on the original data ----------------------
+    dist_err = None
+    if cfg.get("error_vs_fp64"):
+        run(nprobe, alpha, "learned")
+        stream.synchronize()
+        ids_np = ids_dev.cpu().numpy()
+        d_np = d_dev.cpu().numpy().astype(np.float64)
+        valid = ids_np >= 0
+        base32 = torch.from_numpy(w["base"]).to(dev)
+        q64 = torch.from_numpy(w["queries"]).to(dev, torch.float64)
+        rel = []
+        for s0 in range(0, nq, 100):
+            idx = torch.from_numpy(np.where(valid[s0:s0 + 100], ids_np[s0:s0 + 100], 0)).to(dev)
+            x = base32[idx].to(torch.float64)                       # (b, k, D)
+            dt = ((x - q64[s0:s0 + 100, None, :]) ** 2).sum(-1).cpu().numpy()
+            e = np.abs(d_np[s0:s0 + 100] - dt) / np.maximum(dt, 1e-30)
+            rel.append(e[valid[s0:s0 + 100]])
+        rel = np.concatenate(rel)
+        dist_err = dict(what="|returned FP32 distance - FP64 distance of the original vector| / FP64",
+                        median=float(np.median(rel)), p99=float(np.percentile(rel, 99)),
+                        max=float(rel.max()), results=int(rel.size))
+        del base32, q64
+        torch.cuda.empty_cache()
+        log(f"[bench] distance error vs FP64: {dist_err}")
+
     # ---- work counters of one launch at the operating point ---------------------------
     ctr.zero_()
     run(nprobe, alpha, "learned", counters=True)
@@ -239,7 +288,7 @@ def main():
     candidates, refined, slices = int(c[0]), int(c[1]), int(c[2])
     esize = {0: 4, 1: 2, 2: 2}[info["storage"]]
     slice_bytes = 32 * esize
-    S = info["n_stages"]
+    NB = info["dim_padded"] // 32      # 32-dim blocks the scan counts
     # algorithmic bytes of one scan launch: base slices read + ids of refined candidates +
     # list table entries + rotated queries + outputs
     scan_bytes = (slices * slice_bytes + refined * 4 + nq * nprobe * 12 + nq * info["dim_padded"] * 4
@@ -297,7 +346,7 @@ def main():
             traffic = None
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
-                    kernel="scan_kernel<f32>", bytes_per_launch=int(scan_bytes),
+                    kernel=f"scan_kernel<{cfg['storage']}, pruned>", bytes_per_launch=int(scan_bytes),
                     kernel_ms=round(scan_ms, 4))
 
     if args.copy_probe:
@@ -309,9 +358,14 @@ def main():
 
     # ---- serving: open-loop Poisson arrivals, continuous batching --------------------------
     serve = []
-    rates = [float(x) for x in args.serve_rates.split(",") if x.strip()] if args.serve_seconds > 0 else []
-    for frac in rates:
-        serve.append(serve_phase(ix, w, qps * frac, args.serve_seconds, alpha, nlist, seed=len(serve)))
+    rates = []
+    if args.serve_seconds > 0 and cfg.get("serve"):
+        kind, vals = cfg["serve"]
+        if args.serve_rates:
+            vals = [float(x) for x in args.serve_rates.split(",") if x.strip()]
+        rates = [qps * v for v in vals] if kind == "frac" else list(vals)
+    for rate in rates:
+        serve.append(serve_phase(ix, w, rate, args.serve_seconds, alpha, nlist, seed=len(serve)))
         log(f"[bench] serve {serve[-1]}")
 
     # ---- CPU oracle baseline (bounded sample) --------------------------------------------
@@ -344,8 +398,9 @@ def main():
         "vs_baseline": None,
         "dtype": {0: "f32", 1: "f16", 2: "bf16"}[info["storage"]],
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {w['base'].shape[0]} x {D} integer 0-255 mixture "
-                               f"of {spec.get('comps')} Gaussians, IVF {nlist}",
+        "config": {"workload": f"{args.workload}: {w['base'].shape[0]} x {D} {DESCR[spec['kind']]}, "
+                               f"{spec.get('comps')} Gaussian components, IVF {nlist}, storage "
+                               f"{cfg['storage']}, rotation {cfg['rotation']}",
                    "queries_per_step": nq, "k": k, "nprobe": nprobe, "significance": alpha,
                    "recall_at_10": round(rec, 4), "parallelism": "single GPU"},
         "full_d_scan": {"qps": round(full_qps, 1), "nprobe": full_best[0],
@@ -357,9 +412,10 @@ def main():
                       "coarse": round(kms[1] / max(1, kn[1]), 4),
                       "select": round(kms[2] / max(1, kn[2]), 4), "scan": round(scan_ms, 4)},
         "scan_stats": {"candidates": candidates, "refined": refined,
-                       "scanned_dim_ratio": round(slices / max(1, candidates * S), 4),
+                       "scanned_dim_ratio": round(slices / max(1, candidates * NB), 4),
                        "bytes_vs_full_d": round(slices * slice_bytes / max(1, full_bytes_per_launch), 4)},
         "roofline": roofline,
+        "distance_error_vs_fp64": dist_err,
         "serve": serve,
         "serve_p50_ms": serve[-1]["p50_ms"] if serve else None,
         "serve_p99_ms": serve[-1]["p99_ms"] if serve else None,

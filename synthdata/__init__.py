@@ -75,15 +75,18 @@ class Mixture:
         jitter = rng.lognormal(0.0, 0.5, size=(n_comp, D))
         self.scales = b * np.sqrt(lam[None, :] * jitter)   # in the rotated frame
 
-    def sample(self, n: int, seed: int) -> np.ndarray:
+    def sample(self, n: int, seed: int, post=None, dtype=np.float64) -> np.ndarray:
+        """n points; `post` (optional) maps every FP64 chunk before it is stored as `dtype`
+        (the random draws do not depend on either)."""
         rng = np.random.default_rng(seed)
         comp = rng.integers(0, self.n_comp, size=n)
-        out = np.empty((n, self.D), dtype=np.float64)
+        out = np.empty((n, self.D), dtype=dtype)
         chunk = 1 << 16
         for s in range(0, n, chunk):
             c = comp[s:s + chunk]
             z = rng.standard_normal((c.shape[0], self.D))
-            out[s:s + c.shape[0]] = self.means[c] + (z * self.scales[c]) @ self.rot.T
+            x = self.means[c] + (z * self.scales[c]) @ self.rot.T
+            out[s:s + c.shape[0]] = post(x) if post is not None else x
         return out
 
 
@@ -142,21 +145,20 @@ def make_workload(name: str, n: int | None = None, nq: int | None = None,
             mix = Mixture(D, spec["comps"], lam, centre=127.5, mean_std=ms, within_std=ws,
                           seed_rot=sd(STREAM_ROT), seed_mix=sd(STREAM_MIX))
 
-            def gen(cnt, stream):
-                x = mix.sample(cnt, sd(stream))
-                return np.rint(np.clip(x, 0.0, 255.0)).astype(np.float32)   # rint = half-even
+            def gen(cnt, stream):   # clip to [0, 255], round half-even
+                return mix.sample(cnt, sd(stream), post=lambda x: np.rint(np.clip(x, 0.0, 255.0)),
+                                  dtype=np.float32)
         elif kind == "gist":
             mix = Mixture(D, spec["comps"], lam, centre=0.0, mean_std=0.6, within_std=0.4,
                           seed_rot=sd(STREAM_ROT), seed_mix=sd(STREAM_MIX))
-            gen = lambda cnt, stream: mix.sample(cnt, sd(stream)).astype(np.float32)
+            gen = lambda cnt, stream: mix.sample(cnt, sd(stream), dtype=np.float32)
         elif kind == "embed":
             mix = Mixture(D, spec["comps"], lam, centre=0.0, mean_std=0.6, within_std=0.4,
                           seed_rot=sd(STREAM_ROT), seed_mix=sd(STREAM_MIX))
 
-            def gen(cnt, stream):
-                x = mix.sample(cnt, sd(stream))
-                x /= np.linalg.norm(x, axis=1, keepdims=True)
-                return x.astype(np.float32)
+            def gen(cnt, stream):   # unit-normalised after sampling
+                return mix.sample(cnt, sd(stream), post=lambda x: x / np.linalg.norm(x, axis=1, keepdims=True),
+                                  dtype=np.float32)
         else:
             raise ValueError(kind)
     out["base"] = np.ascontiguousarray(gen(n, STREAM_BASE))
