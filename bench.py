@@ -316,6 +316,23 @@ def main():
     scan_ms = kms[3] / max(1, kn[3])
     qps = nq / ms_step * 1e3
 
+    # every launch shape of the scan at the operating point (results are bit-identical)
+    chosen = ix.scan_variant(nq, k, nprobe)
+    variants = {}
+    for wv, la in ((1, 0), (1, 1), (4, 0), (4, 1)):
+        ix.set_launch(waves_per_query=wv, lookahead=la)
+        run(nprobe, alpha, "learned")
+        stream.synchronize()
+        ix.set_kernel_timing(True)
+        for _ in range(max(3, args.steps // 2)):
+            run(nprobe, alpha, "learned")
+        stream.synchronize()
+        ix.set_kernel_timing(False)
+        vms, vn = ix.kernel_timing(reset=True)
+        variants[f"waves{wv}{'_lookahead' if la else ''}"] = round(vms[3] / max(1, vn[3]), 4)
+    ix.set_launch(waves_per_query=0, lookahead=-1)
+    log(f"[bench] scan variants (ms): {variants}; tuned choice {chosen}")
+
     # full-D scan at its own operating point, same protocol
     for _ in range(args.warmup):
         run(full_best[0], 0.0, "none")
@@ -346,7 +363,8 @@ def main():
             traffic = None
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
-                    kernel=f"scan_kernel<{cfg['storage']}, pruned>", bytes_per_launch=int(scan_bytes),
+                    kernel=f"scan_kernel<{cfg['storage']}, pruned, lookahead={chosen[1]}, "
+                           f"waves={chosen[0]}>", bytes_per_launch=int(scan_bytes),
                     kernel_ms=round(scan_ms, 4))
 
     if args.copy_probe:
@@ -408,6 +426,8 @@ def main():
                         "scan_kernel_ms": round(full_scan_ms, 4),
                         "scan_achieved_GBs": round(full_scan_bytes / (full_scan_ms * 1e-3) / 1e9, 1)},
         "speedup_vs_full_d": round(qps / full_qps, 3),
+        "scan_variant_ms": variants,
+        "scan_variant_tuned": {"waves_per_query": chosen[0], "lookahead": chosen[1]},
         "kernel_ms": {"rotation": round(kms[0] / max(1, kn[0]), 4),
                       "coarse": round(kms[1] / max(1, kn[1]), 4),
                       "select": round(kms[2] / max(1, kn[2]), 4), "scan": round(scan_ms, 4)},

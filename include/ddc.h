@@ -201,6 +201,27 @@ ddc_status ddc_debug_intermediates(const ddc_index *ix, const float *queries, in
 ddc_status ddc_set_kernel_timing(ddc_index *ix, int enable);
 ddc_status ddc_get_kernel_timing(ddc_index *ix, double *ms_total, int64_t *launches, int reset);
 
+/* Launch shape of the pruned scan (A3-A5).  None of these changes any result bit (every
+ * candidate's partial distances are summed in the same order in every variant); they only
+ * trade occupancy, latency and bytes read.  waves_per_query: 1 (one wavefront runs a query's
+ * whole scan, four queries per workgroup) or 4 (a workgroup per query, the tiles of every
+ * candidate block split over its four wavefronts), 0 = tuned.  lookahead: 0 (one dim block
+ * per dependent load), 1 (when few candidates are alive, one load covers up to 8 consecutive
+ * dim blocks of each), -1 = tuned.  query_order: group queries with the same first list;
+ * xcd_swizzle: give each XCD a contiguous query range (0 or 1 each).  Tuned values are picked
+ * per (queries, N_probe, K, pruned or not) size class on the first search of that class by
+ * timing each candidate on the actual launch (that search synchronises its stream once); a
+ * stream that is capturing a graph gets a fixed rule instead.  Defaults: 0, -1, 1, 1. */
+typedef struct {
+  int32_t waves_per_query, lookahead, query_order, xcd_swizzle;
+} ddc_launch_params;
+ddc_status ddc_set_launch(ddc_index *ix, const ddc_launch_params *p);
+ddc_status ddc_get_launch(const ddc_index *ix, ddc_launch_params *p);
+/* The scan variant a search of nq queries with this K, N_probe and mode runs: waves (1 or 4)
+ * and lookahead (0 or 1).  A size class not tuned yet reports the fixed rule's choice. */
+ddc_status ddc_scan_variant(ddc_index *ix, int64_t nq, int32_t k_max, int32_t nprobe_max,
+                            ddc_corr mode, int32_t *waves, int32_t *lookahead);
+
 /* ---- continuous-batching server --------------------------------------------------------
  * A scheduler thread admits queued requests into micro-batches on n_streams HIP streams while
  * the device bytes of all batches in flight (queries, results, search scratch) stay within

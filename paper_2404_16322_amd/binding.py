@@ -22,7 +22,8 @@ SYMBOLS = ["ddc_fit_params_default", "ddc_fit", "ddc_import", "ddc_export", "ddc
            "ddc_calibrate", "ddc_correction", "ddc_search", "ddc_search_var", "ddc_search_device",
            "ddc_debug_intermediates", "ddc_set_kernel_timing", "ddc_get_kernel_timing", "ddc_free",
            "ddc_last_error", "ddc_server_create", "ddc_server_submit", "ddc_server_poll",
-           "ddc_server_get_stats", "ddc_server_destroy"]
+           "ddc_server_get_stats", "ddc_server_destroy", "ddc_set_launch", "ddc_get_launch",
+           "ddc_scan_variant"]
 
 
 class FitParams(C.Structure):
@@ -69,6 +70,11 @@ class ServerStats(C.Structure):
                 ("max_ms", C.c_double), ("budget_peak_bytes", C.c_int64), ("max_concurrent", C.c_int32)]
 
 
+class LaunchParams(C.Structure):
+    _fields_ = [("waves_per_query", C.c_int32), ("lookahead", C.c_int32),
+                ("query_order", C.c_int32), ("xcd_swizzle", C.c_int32)]
+
+
 class DdcError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"{STATUS.get(status, status)}: {msg}")
@@ -107,6 +113,10 @@ def load_library():
         lib.ddc_debug_intermediates.argtypes = [vp, vp, i64, i32, vp, vp]
         lib.ddc_set_kernel_timing.argtypes = [vp, C.c_int]
         lib.ddc_get_kernel_timing.argtypes = [vp, vp, vp, C.c_int]
+        lib.ddc_set_launch.argtypes = [vp, C.POINTER(LaunchParams)]
+        lib.ddc_get_launch.argtypes = [vp, C.POINTER(LaunchParams)]
+        lib.ddc_scan_variant.argtypes = [vp, i64, i32, i32, C.c_int, C.POINTER(C.c_int32),
+                                         C.POINTER(C.c_int32)]
         lib.ddc_server_create.argtypes = [vp, C.POINTER(ServerParams), C.POINTER(vp)]
         lib.ddc_server_submit.argtypes = [vp, vp, i32, vp, vp, C.POINTER(C.c_uint64)]
         lib.ddc_server_poll.argtypes = [vp, C.c_uint64, vp, vp, C.POINTER(C.c_int), C.POINTER(C.c_uint64)]
@@ -281,6 +291,28 @@ class Index:
             self._h, d_queries, nq, d_k or None, k_all, k_max, d_nprobe or None, nprobe_all,
             nprobe_max, alpha, CORR[mode], d_offsets or None, d_ids, d_dists, d_counters or None,
             stream or None))
+
+    def set_launch(self, waves_per_query: int | None = None, lookahead: int | None = None,
+                   query_order: int | None = None, xcd_swizzle: int | None = None):
+        """Result-invariant launch shape of the scan; None keeps the current value
+        (waves_per_query 0 and lookahead -1 mean tuned per size class)."""
+        cur = self.launch()
+        lp = LaunchParams(*(cur[k] if v is None else int(v) for k, v in
+                            (("waves_per_query", waves_per_query), ("lookahead", lookahead),
+                             ("query_order", query_order), ("xcd_swizzle", xcd_swizzle))))
+        _check(load_library().ddc_set_launch(self._h, C.byref(lp)))
+
+    def launch(self) -> dict:
+        lp = LaunchParams()
+        _check(load_library().ddc_get_launch(self._h, C.byref(lp)))
+        return {k: getattr(lp, k) for k, _ in LaunchParams._fields_}
+
+    def scan_variant(self, nq: int, k: int, nprobe: int, mode: str = "learned") -> tuple:
+        """(waves per query, lookahead) a search of this shape runs (tuned or fixed rule)."""
+        w, la = C.c_int32(), C.c_int32()
+        _check(load_library().ddc_scan_variant(self._h, nq, k, nprobe, CORR[mode], C.byref(w),
+                                               C.byref(la)))
+        return w.value, la.value
 
     def set_kernel_timing(self, enable: bool):
         _check(load_library().ddc_set_kernel_timing(self._h, int(enable)))

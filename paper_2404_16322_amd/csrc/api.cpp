@@ -25,6 +25,82 @@
 
 using namespace ddc;
 
+// ---- scan launch shape: fixed rule, or timed once per size class --------------------
+static int ceil_log2(int64_t v) {
+  int r = 0;
+  while ((int64_t(1) << r) < v) ++r;
+  return r;
+}
+
+static std::array<int, 4> tune_class(int64_t nq, int np_max, int k_max, int prune) {
+  return {ceil_log2(std::max<int64_t>(nq, 1)), ceil_log2(std::max(np_max, 1)),
+          ceil_log2(std::max(k_max, 1)), prune};
+}
+
+// Without measurements: a workgroup per query while the batch leaves the chip's wave slots
+// mostly empty, and multi-block loads once vectors span eight or more dim blocks.
+static std::pair<int, int> fixed_variant(const ddc_index *ix, int64_t nq, int prune) {
+  return {nq < 4096 ? 4 : 1, prune && ix->NB >= 8 ? 1 : 0};
+}
+
+static std::pair<int, int> forced_or(const ddc_index *ix, std::pair<int, int> v, int prune) {
+  if (ix->waves_per_query) v.first = ix->waves_per_query;
+  if (ix->lookahead >= 0) v.second = ix->lookahead;
+  if (!prune) v.second = 0;
+  return v;
+}
+
+// Sets a.waves_per_query / a.lookahead.  An untuned class is timed on this very launch (each
+// candidate twice, counters off; every candidate writes the same results), then cached.
+static void choose_variant(ddc_index *ix, ScanArgs &a, int np_max, hipStream_t s) {
+  const auto key = tune_class(a.nq, np_max, a.k_max, a.prune);
+  std::pair<int, int> v = fixed_variant(ix, a.nq, a.prune);
+  const bool need_w = ix->waves_per_query == 0, need_l = a.prune && ix->lookahead < 0;
+  if (need_w || need_l) {
+    std::lock_guard<std::mutex> lk(ix->tune_mtx);
+    auto it = ix->tuned.find(key);
+    if (it != ix->tuned.end()) {
+      v = it->second;
+    } else {
+      hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+      HIPC(hipStreamIsCapturing(s, &cs));
+      if (cs == hipStreamCaptureStatusNone) {
+        std::vector<std::pair<int, int>> cand;
+        for (int w : {1, 4})
+          for (int l : {0, 1}) {
+            auto c = forced_or(ix, {w, l}, a.prune);
+            if (std::find(cand.begin(), cand.end(), c) == cand.end()) cand.push_back(c);
+          }
+        hipEvent_t e0, e1;
+        HIPC(hipEventCreate(&e0));
+        HIPC(hipEventCreate(&e1));
+        ScanArgs t = a;
+        t.counters = nullptr;
+        float best = INFINITY;
+        for (auto c : cand) {
+          t.waves_per_query = c.first;
+          t.lookahead = c.second;
+          for (int rep = 0; rep < 2; ++rep) {
+            HIPC(hipEventRecord(e0, s));
+            launch_scan(t, ix->store(), s);
+            HIPC(hipEventRecord(e1, s));
+            HIPC(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIPC(hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best) { best = ms; v = c; }
+          }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        ix->tuned[key] = v;
+      }
+    }
+  }
+  v = forced_or(ix, v, a.prune);
+  a.waves_per_query = v.first;
+  a.lookahead = v.second;
+}
+
 static thread_local std::string g_err;
 
 ddc_status ddc::set_err(ddc_status st, const char *fmt, ...) {
@@ -157,6 +233,7 @@ static void run_calibration(ddc_index *ix, const float *calib, int64_t nc, int k
     a.out_ids = d_cid.as<int64_t>(); a.out_d = d_cd.as<float>();
     a.nq = (int32_t)nc; a.nblocks = ix->NB; a.block_b = ix->B; a.prune = 0; a.nlist = ix->nlist;
     a.k_max = kp;
+    a.waves_per_query = fixed_variant(ix, nc, 0).first;
     launch_scan(a, ix->store(), s);
   }
   std::vector<int64_t> cid((size_t)nc * kp);
@@ -414,6 +491,7 @@ void ddc::search_device(ddc_index *ix, const float *d_q, int64_t nq, const int32
     a.xcd_swizzle = ix->xcd_swizzle;
     a.nq = (int32_t)nqc; a.nblocks = ix->NB; a.block_b = ix->B; a.nlist = ix->nlist;
     a.k_max = k_max;
+    choose_variant(ix, a, np_max, s);
     timed(ix, 3, s, [&] { launch_scan(a, ix->store(), s); });
   }
   HIPC(hipGetLastError());
@@ -477,8 +555,6 @@ static void init_sizes(ddc_index *ix, int64_t n, int D, int nlist, int dd, int B
   ix->St = ix->S - 1;
   (void)hipGetDevice(&ix->device);
   set_pool_retain(ix->device);
-  if (const char *e = getenv("DDC_QUERY_ORDER")) ix->query_order = atoi(e) != 0;
-  if (const char *e = getenv("DDC_XCD_SWIZZLE")) ix->xcd_swizzle = atoi(e) != 0;
 }
 
 // ---------------------------------------------------------------------------------------
@@ -791,6 +867,49 @@ ddc_status ddc_get_kernel_timing(ddc_index *ix, double *ms_total, int64_t *launc
   }
   return DDC_OK;
   GUARD_END
+}
+
+ddc_status ddc_set_launch(ddc_index *ix, const ddc_launch_params *p) {
+  if (!ix || !p) return set_err(DDC_EINVAL, "NULL argument");
+  if (p->waves_per_query != 0 && p->waves_per_query != 1 && p->waves_per_query != 4)
+    return set_err(DDC_EINVAL, "waves_per_query must be 0, 1 or 4");
+  if (p->lookahead < -1 || p->lookahead > 1) return set_err(DDC_EINVAL, "lookahead must be -1, 0 or 1");
+  if ((p->query_order != 0 && p->query_order != 1) || (p->xcd_swizzle != 0 && p->xcd_swizzle != 1))
+    return set_err(DDC_EINVAL, "query_order and xcd_swizzle must be 0 or 1");
+  std::lock_guard<std::mutex> lk(ix->tune_mtx);
+  ix->tuned.clear();   // a choice tuned under other forced knobs may not be the best now
+  ix->waves_per_query = p->waves_per_query;
+  ix->lookahead = p->lookahead;
+  ix->query_order = p->query_order;
+  ix->xcd_swizzle = p->xcd_swizzle;
+  return DDC_OK;
+}
+
+ddc_status ddc_get_launch(const ddc_index *ix, ddc_launch_params *p) {
+  if (!ix || !p) return set_err(DDC_EINVAL, "NULL argument");
+  p->waves_per_query = ix->waves_per_query;
+  p->lookahead = ix->lookahead;
+  p->query_order = ix->query_order;
+  p->xcd_swizzle = ix->xcd_swizzle;
+  return DDC_OK;
+}
+
+ddc_status ddc_scan_variant(ddc_index *ix, int64_t nq, int32_t k_max, int32_t nprobe_max,
+                            ddc_corr mode, int32_t *waves, int32_t *lookahead) {
+  if (!ix || !waves || !lookahead) return set_err(DDC_EINVAL, "NULL argument");
+  if (nq < 1 || k_max < 1 || nprobe_max < 1) return set_err(DDC_EINVAL, "sizes must be >= 1");
+  const int prune = ix->St > 0 && mode != DDC_CORR_NONE;
+  const int64_t nqc = std::min<int64_t>(nq, 32768);
+  std::pair<int, int> v = fixed_variant(ix, nqc, prune);
+  {
+    std::lock_guard<std::mutex> lk(ix->tune_mtx);
+    auto it = ix->tuned.find(tune_class(nqc, nprobe_max, k_max, prune));
+    if (it != ix->tuned.end()) v = it->second;
+  }
+  v = forced_or(ix, v, prune);
+  *waves = v.first;
+  *lookahead = v.second;
+  return DDC_OK;
 }
 
 ddc_status ddc_calibrate(ddc_index *ix, const float *calib, int64_t n_calib, int32_t calib_k,

@@ -15,6 +15,7 @@ constexpr int kMaxBlocks = 128;      // D <= 4096
 constexpr int kMaxK = 256;
 constexpr int kScanThreads = 256;    // 4 wavefronts per query
 constexpr int kMaxCounters = 4 + 64; // candidates, refined, stage_slices, unused, stop[64]
+constexpr size_t kMaxLds = 160 * 1024;  // LDS per workgroup on gfx950
 
 enum StoreType : int { ST_F32 = 0, ST_F16 = 1, ST_BF16 = 2 };
 
@@ -38,6 +39,8 @@ struct ScanArgs {
   int64_t *counters;       // NULL or [kMaxCounters] (added to)
   const int32_t *order;    // NULL or [nq]: wave slot -> query (results do not depend on it)
   int32_t xcd_swizzle;     // 1: workgroup w runs slot range of XCD (w mod 8), contiguous per XCD
+  int32_t waves_per_query; // 1 or 4 (result-invariant)
+  int32_t lookahead;       // 0 or 1: multi-stage loads when few candidates survive (result-invariant)
   int32_t nq, nblocks, block_b, prune, nlist, k_max;
   float m[kMaxBlocks];     // per 32-dim block: slope of the test after this block
   float beta[kMaxBlocks];  //                   bias of the test after this block

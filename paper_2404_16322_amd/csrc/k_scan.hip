@@ -1,6 +1,6 @@
 // Pruned candidate scan, top-K merge and finalize for IVF search on gfx950.
 //
-// Method (one workgroup of 4 wavefronts per query):
+// Method (one wavefront, or a workgroup of four, per query):
 //  * candidates are taken list by list in probe order, each list in blocks of B
 //    stored positions; all candidates of a block are tested against the same
 //    threshold tau_b, the K-th distance of the result queue after the previous block
@@ -22,6 +22,8 @@
 
 #include <hip/hip_fp16.h>
 #include <math.h>
+
+#include <stdexcept>
 
 namespace ddc {
 
@@ -116,42 +118,56 @@ __device__ inline unsigned long long lane_mask_lt() {
 
 }  // namespace
 
-// Per-wavefront LDS: rotated query, two result queues (double buffer), the block's
-// survivors and two alive lists of the staged scan.
-struct WaveLds {
-  size_t q, td, ti, sd, si, ac, ae, bytes;
+// LDS: per query (shared by its W waves) the rotated query, two result queues (double
+// buffer), the block's survivors and two survivor counters; per wave two alive lists of the
+// staged scan and the per-dim-block test table (m, beta; beta = -inf where no test follows).
+struct Lds {
+  size_t q, td, ti, sd, si, cnt, query_bytes;
+  size_t ac, ae, mb, wave_bytes;
 };
 __host__ __device__ inline size_t align16(size_t b) { return (b + 15) & ~(size_t)15; }
-__host__ __device__ inline WaveLds wave_lds(int Dp, int kmax, int block_b) {
-  WaveLds w;
+__host__ __device__ inline Lds lds_layout(int Dp, int kmax, int block_b, int W) {
+  Lds l;
   size_t o = 0;
-  w.q = o; o += align16((size_t)Dp * 4);
-  w.td = o; o += align16((size_t)2 * kmax * 4);
-  w.ti = o; o += align16((size_t)2 * kmax * 4);
-  w.sd = o; o += align16((size_t)block_b * 4);
-  w.si = o; o += align16((size_t)block_b * 4);
-  w.ac = o; o += align16((size_t)2 * block_b * 2);
-  w.ae = o; o += align16((size_t)2 * block_b * 4);
-  w.bytes = o;
-  return w;
+  l.q = o; o += align16((size_t)Dp * 4);
+  l.td = o; o += align16((size_t)2 * kmax * 4);
+  l.ti = o; o += align16((size_t)2 * kmax * 4);
+  l.sd = o; o += align16((size_t)block_b * 4);
+  l.si = o; o += align16((size_t)block_b * 4);
+  l.cnt = o; o += 16;
+  l.query_bytes = o;
+  const int seg = W == 1 ? block_b : kTile;   // candidates one wave scans per segment
+  o = 0;
+  l.ac = o; o += align16((size_t)2 * seg * 2);
+  l.ae = o; o += align16((size_t)2 * seg * 4);
+  l.mb = o; o += align16((size_t)2 * (Dp / kBlockDims) * 4);
+  l.wave_bytes = o;
+  return l;
+}
+__host__ __device__ inline size_t scan_lds_bytes(int Dp, int kmax, int block_b, int W) {
+  const Lds l = lds_layout(Dp, kmax, block_b, W);
+  return (size_t)(4 / W) * l.query_bytes + 4 * l.wave_bytes;
 }
 
-// One wavefront per query, four queries per workgroup; the waves never synchronise with
-// each other, so a query's block chain (scan -> merge -> next tau) runs without barriers.
-template <int ST, bool PRUNE>
+// W waves per query (W = 1: four queries per workgroup, no workgroup barrier at all; W = 4:
+// one query per workgroup, each block's tiles split over the four waves, survivors merged
+// by the workgroup between two barriers).  LOOK enables the multi-stage look-ahead.
+template <int ST, bool PRUNE, bool LOOK, int W>
 __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4, 8))) void scan_kernel(ScanArgs a) {
   using S = Store<ST>;
   constexpr int EPL = 16 / S::kBytes;          // elements per lane load
   constexpr int G = kBlockDims / EPL;          // lanes per vector slice
   constexpr int CPW = 64 / G;                  // slices per wavefront load
   constexpr int MAXCH = 64 / CPW;              // loads per group: one 64-vector tile
-  constexpr int GROUP = CPW * MAXCH;           // candidates per load group
+  constexpr int GROUP = CPW * MAXCH;           // candidates per load group (64)
   constexpr int SLICE = kBlockDims * S::kBytes;            // bytes per vector slice
   constexpr int64_t BLOCK_BYTES = (int64_t)kTile * SLICE;  // bytes per tile dim-block
+  constexpr int QPW = 4 / W;                   // queries per workgroup
 
   extern __shared__ __align__(16) unsigned char smem[];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int qs = wave / W, wsub = wave % W;    // query slot in the workgroup, wave within query
   int wg = blockIdx.x;
   if (a.xcd_swizzle) {
     // consecutive workgroups land on XCDs 0..7 in turn: give each XCD a contiguous range
@@ -159,8 +175,8 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
     const int per = n / 8, rem = n % 8;
     wg = x * per + min(x, rem) + r;
   }
-  const int slot = wg * (kScanThreads / 64) + wave;
-  if (slot >= a.nq) return;   // whole wavefront; no workgroup barrier follows
+  const int slot = wg * QPW + qs;
+  if (slot >= a.nq) return;   // W = 4: the whole workgroup leaves together
   const int q = a.order ? a.order[slot] : slot;
   const int g = lane % G;
   const int sub = lane / G;
@@ -168,30 +184,65 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
   const int Dp = nb * kBlockDims;
   const int B = a.block_b;
   const int KM = a.k_max;
-  const WaveLds L = wave_lds(Dp, KM, B);
-  unsigned char *wl = smem + (size_t)wave * L.bytes;
-  float *s_q = reinterpret_cast<float *>(wl + L.q);
-  float *s_td = reinterpret_cast<float *>(wl + L.td);
-  int32_t *s_ti = reinterpret_cast<int32_t *>(wl + L.ti);
-  float *s_sd = reinterpret_cast<float *>(wl + L.sd);
-  int32_t *s_si = reinterpret_cast<int32_t *>(wl + L.si);
+  const int SEG = W == 1 ? B : kTile;
+  const Lds L = lds_layout(Dp, KM, B, W);
+  unsigned char *ql = smem + (size_t)qs * L.query_bytes;
+  unsigned char *wl = smem + (size_t)QPW * L.query_bytes + (size_t)wave * L.wave_bytes;
+  float *s_q = reinterpret_cast<float *>(ql + L.q);
+  float *s_td = reinterpret_cast<float *>(ql + L.td);
+  int32_t *s_ti = reinterpret_cast<int32_t *>(ql + L.ti);
+  float *s_sd = reinterpret_cast<float *>(ql + L.sd);
+  int32_t *s_si = reinterpret_cast<int32_t *>(ql + L.si);
+  int32_t *s_cnt = reinterpret_cast<int32_t *>(ql + L.cnt);
   uint16_t *s_ac = reinterpret_cast<uint16_t *>(wl + L.ac);
   float *s_ae = reinterpret_cast<float *>(wl + L.ae);
+  float *s_mb = reinterpret_cast<float *>(wl + L.mb);
 
   const int K = a.k ? a.k[q] : a.k_all;
   const int np = a.nprobe ? a.nprobe[q] : a.nprobe_all;
   const float *qg = a.qrot + (int64_t)q * a.q_stride;
-  for (int i = lane; i < Dp; i += 64) s_q[i] = qg[i];
-  __builtin_amdgcn_wave_barrier();
+  const int qt = wsub * 64 + lane;             // thread index within the query's waves
+  for (int i = qt; i < Dp; i += 64 * W) s_q[i] = qg[i];
+  if (qt < 2) s_cnt[qt] = 0;
+  if (PRUNE && LOOK) {
+    for (int i = 0; i < nb; ++i) {   // uniform index: scalar reads of the kernel arguments
+      const bool t = a.test_after[i] != 0;
+      const float mv = t ? a.m[i] : 0.f, bv = t ? a.beta[i] : -INFINITY;
+      if (lane == 0) { s_mb[2 * i] = mv; s_mb[2 * i + 1] = bv; }
+    }
+  }
+  if (W > 1) __syncthreads(); else __builtin_amdgcn_wave_barrier();
 
   // statistics (wave-uniform, flushed once when counters are requested)
   int64_t st_cand = 0, st_ref = 0, st_slices = 0;
   unsigned long long *ctr = reinterpret_cast<unsigned long long *>(a.counters);
 
-  int tin = 0, tn = 0;
+  int tin = 0, tn = 0, par = 0;
   float tau = INFINITY;
   int32_t tau_id = 0x7FFFFFFF;
   const unsigned long long lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  int ns = 0;   // W = 1: survivors of the current block (wave-uniform)
+
+  // append the lanes with `take` to the block's survivor list
+  auto append = [&](bool take, float ev, int32_t id) {
+    const unsigned long long bal = __ballot(take);
+    const int cnt = __popcll(bal);
+    if (cnt == 0) return;
+    int base;
+    if (W == 1) {
+      base = ns;
+      ns += cnt;
+    } else {
+      int b0 = 0;
+      if (lane == 0) b0 = atomicAdd(&s_cnt[par], cnt);
+      base = __shfl(b0, 0);
+    }
+    if (take) {
+      const int pos = base + __popcll(bal & lt);
+      s_sd[pos] = ev;
+      s_si[pos] = id;
+    }
+  };
 
   for (int p = 0; p < np; ++p) {
     const int lst = a.probes[(int64_t)q * a.p_stride + p];
@@ -202,15 +253,17 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
     const int32_t *lids = a.ids + (int64_t)a.tile_off[lst] * kTile;
     for (int bs = 0; bs < len; bs += B) {
       const int blen = min(B, len - bs);
-      const unsigned char *bbase = lbase + (int64_t)(bs / kTile) * nb * BLOCK_BYTES;
-      const int32_t *bids = lids + bs;
-      int ns = 0;   // survivors of this block (wave-uniform)
+      ns = 0;
+      for (int s0 = (W == 1 ? 0 : wsub * kTile); s0 < blen; s0 += (W == 1 ? blen : W * kTile)) {
+      const int slen = W == 1 ? blen : min(kTile, blen - s0);
+      const unsigned char *bbase = lbase + (int64_t)((bs + s0) / kTile) * nb * BLOCK_BYTES;
+      const int32_t *bids = lids + bs + s0;
       // In a load group, chunk c, lane (sub, g) reads dims [g*EPL, g*EPL+EPL) of candidate
       // t0 + c*CPW + sub; after transpose_sum the lane owns candidate t0 + g*CPW + sub.
       if (!PRUNE || tn < K) {
         // ---- no test can prune: every candidate, every dim block ----
-        // Slots past blen inside the last tile are zero padding: loads stay in bounds.
-        for (int t0 = 0; t0 < blen; t0 += GROUP) {
+        // Slots past slen inside the last tile are zero padding: loads stay in bounds.
+        for (int t0 = 0; t0 < slen; t0 += GROUP) {
           float acc[MAXCH];
 #pragma unroll
           for (int c = 0; c < MAXCH; ++c) acc[c] = 0.f;
@@ -236,31 +289,119 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
             }
           }
           const float dis = transpose_sum<G>(acc, g);
-          const int slot = t0 + g * CPW + sub;
+          const int sl = t0 + g * CPW + sub;
           bool keep = false;
           int32_t id = 0;
-          if (slot < blen) {
-            id = bids[slot];
+          if (sl < slen) {
+            id = bids[sl];
             keep = tn < K || lex_less(dis, id, tau, tau_id);
           }
-          const unsigned long long bal = __ballot(keep);
-          if (keep) {
-            const int pos = ns + __popcll(bal & lt);
-            s_sd[pos] = dis;
-            s_si[pos] = id;
-          }
-          ns += __popcll(bal);
+          append(keep, dis, id);
         }
-        st_cand += blen; st_ref += blen; st_slices += (int64_t)blen * nb;
-        if (ctr && lane == 0) atomicAdd(&ctr[4 + min(nb - 1, 63)], (unsigned long long)blen);
+        st_cand += slen; st_ref += slen; st_slices += (int64_t)slen * nb;
+        if (ctr && lane == 0) atomicAdd(&ctr[4 + min(nb - 1, 63)], (unsigned long long)slen);
       } else if (PRUNE) {
         // ---- staged scan: test after every stage, compact the survivors ----
         // Lanes past the live count read the group's first live candidate (same cache
         // line, always in bounds) and are masked out of every decision.
         int cur = 0;
-        int nalive = blen;
-        st_cand += blen;
-        for (int b = 0; b < nb && nalive > 0; ++b) {
+        int nalive = slen;
+        st_cand += slen;
+        int b = 0;
+        while (b < nb && nalive > 0) {
+          int L = 1;
+          if (LOOK && nb - b > 1) {
+            // Look-ahead: when the live candidates fit in MAXCH / L load slots, every slot
+            // loads one (candidate, stage) pair of L consecutive stages, so L dependent loads
+            // become one.  Decisions are still taken stage by stage; bytes past a
+            // candidate's stopping stage are read but not counted as algorithmic.
+            const int ch = (nalive + CPW - 1) / CPW;
+            if (ch * 8 <= MAXCH) L = 8;
+            else if (ch * 4 <= MAXCH) L = 4;
+            else if (ch * 2 <= MAXCH) L = 2;
+          }
+          if (LOOK && L > 1) {
+            const int Le = min(L, nb - b);
+            const int lgL = L == 8 ? 3 : (L == 4 ? 2 : 1);
+            const uint16_t *alive = s_ac + cur * SEG;
+            const float *alive_e = s_ae + cur * SEG;
+            const int first = b == 0 ? 0 : (int)alive[0];
+            uint4 v[MAXCH];
+#pragma unroll
+            for (int c = 0; c < MAXCH; ++c) {
+              const int idx = (c >> lgL) * CPW + sub;
+              const int cd = idx < nalive ? (b == 0 ? idx : (int)alive[idx]) : first;
+              const int bb = min(b + (c & (L - 1)), nb - 1);
+              const uint32_t off = (uint32_t)((cd / kTile) * nb + bb) * (uint32_t)BLOCK_BYTES +
+                                   (uint32_t)((cd % kTile) * SLICE + g * 16);
+              v[c] = *reinterpret_cast<const uint4 *>(bbase + off);
+            }
+            float part[MAXCH];
+#pragma unroll
+            for (int c = 0; c < MAXCH; ++c) {
+              const int bb = min(b + (c & (L - 1)), nb - 1);
+              float f[EPL];
+              S::unpack(v[c], f);
+              float acc = 0.f;
+#pragma unroll
+              for (int e = 0; e < EPL; ++e) {
+                const float d = f[e] - s_q[bb * kBlockDims + g * EPL + e];
+                acc = fmaf(d, d, acc);
+              }
+              part[c] = acc;
+            }
+            const float tot = transpose_sum<G>(part, g);  // lane g: slot g = (candidate g >> lgL, stage g & (L-1))
+            const int my_cc = g >> lgL, my_ss = g & (L - 1);
+            const int idx = my_cc * CPW + sub;
+            const bool valid = idx < nalive;
+            const int ci = min(idx, SEG - 1);
+            const int cand = b == 0 ? idx : (int)alive[ci];
+            // running partial distance, added one stage at a time in stage order: the same
+            // rounding as the one-stage path, so the variant changes no result bit
+            float ev = my_ss == 0 ? (b == 0 ? tot : alive_e[ci] + tot) : tot;
+            for (int j = 1; j < L; ++j) {
+              const float prev = __shfl_up(ev, 1);
+              if (my_ss == j) ev = prev + ev;
+            }
+            bool prune = false;
+            if (valid && my_ss < Le) {
+              const int bb = b + my_ss;
+              prune = fmaf(s_mb[2 * bb], ev, s_mb[2 * bb + 1]) > tau;
+            }
+            const unsigned long long pm = __ballot(prune);
+            const uint32_t bits = (uint32_t)(pm >> (sub * G + my_cc * L)) & ((1u << L) - 1u);
+            const int firstp = bits ? __builtin_ctz(bits) : Le;
+            st_slices += __popcll(__ballot(valid && my_ss < Le && my_ss <= firstp));
+            const bool writer = valid && my_ss == Le - 1;
+            const bool survive = writer && bits == 0;
+            if (ctr && writer && bits) atomicAdd(&ctr[4 + min(b + firstp, 63)], 1ull);
+            if (b + Le == nb) {
+              // the window reached the last stage: survivors carry their exact distance
+              if (ctr && survive) atomicAdd(&ctr[4 + min(nb - 1, 63)], 1ull);
+              st_ref += __popcll(__ballot(survive));
+              int32_t id = 0;
+              bool take = false;
+              if (survive) {
+                id = bids[cand];
+                take = lex_less(ev, id, tau, tau_id);
+              }
+              append(take, ev, id);
+              __builtin_amdgcn_wave_barrier();
+              nalive = 0;
+            } else {
+              const unsigned long long bal = __ballot(survive);
+              if (survive) {
+                const int pos = __popcll(bal & lt);
+                s_ac[(cur ^ 1) * SEG + pos] = (uint16_t)cand;
+                s_ae[(cur ^ 1) * SEG + pos] = ev;
+              }
+              __builtin_amdgcn_wave_barrier();
+              nalive = __popcll(bal);
+              cur ^= 1;
+            }
+            b += Le;
+            continue;
+          }
           const bool last = b == nb - 1;
           const bool test = a.test_after[b] != 0;
           const float mb = a.m[b], bb = a.beta[b];
@@ -268,8 +409,8 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
 #pragma unroll
           for (int e = 0; e < EPL; ++e) qv[e] = s_q[b * kBlockDims + g * EPL + e];
           const unsigned char *bp = bbase + b * BLOCK_BYTES + g * 16;
-          const uint16_t *alive = s_ac + cur * B;
-          const float *alive_e = s_ae + cur * B;
+          const uint16_t *alive = s_ac + cur * SEG;
+          const float *alive_e = s_ae + cur * SEG;
           int nnext = 0;
           int pruned = 0;
           for (int t0 = 0; t0 < nalive; t0 += GROUP) {
@@ -299,7 +440,7 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
             const float tot = transpose_sum<G>(part, g);
             const int idx = t0 + g * CPW + sub;
             const bool valid = idx < nalive;
-            const int ci = min(idx, B - 1);
+            const int ci = min(idx, SEG - 1);
             const int cand = b == 0 ? idx : (int)alive[ci];
             const float ev = b == 0 ? tot : alive_e[ci] + tot;
             bool keep = valid;
@@ -311,19 +452,13 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
                 id = bids[cand];
                 take = lex_less(ev, id, tau, tau_id);
               }
-              const unsigned long long bal = __ballot(take);
-              if (take) {
-                const int pos = ns + __popcll(bal & lt);
-                s_sd[pos] = ev;
-                s_si[pos] = id;
-              }
-              ns += __popcll(bal);
+              append(take, ev, id);
             } else {
               const unsigned long long bal = __ballot(keep);
               if (keep) {
                 const int pos = nnext + __popcll(bal & lt);
-                s_ac[(cur ^ 1) * B + pos] = (uint16_t)cand;
-                s_ae[(cur ^ 1) * B + pos] = ev;
+                s_ac[(cur ^ 1) * SEG + pos] = (uint16_t)cand;
+                s_ae[(cur ^ 1) * SEG + pos] = ev;
               }
               nnext += __popcll(bal);
             }
@@ -337,16 +472,26 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
           }
           __builtin_amdgcn_wave_barrier();
           if (!last) { nalive = nnext; cur ^= 1; }
+          b += 1;
         }
       }
-      __builtin_amdgcn_wave_barrier();
+      }  // segments
+      // ---- merge: queue (sorted, tn) + survivors (ns) -> K smallest by (dis, id) ----
+      int mt, mstep;
+      if (W == 1) {
+        __builtin_amdgcn_wave_barrier();
+        mt = lane; mstep = 64;
+      } else {
+        __syncthreads();                       // every wave's survivors are in LDS
+        ns = s_cnt[par];
+        mt = qt; mstep = 64 * W;
+      }
       if (ns > 0) {
-        // ---- merge: queue (sorted, tn) + survivors (ns) -> K smallest by (dis, id) ----
         const float *td = s_td + tin * KM;
         const int32_t *ti = s_ti + tin * KM;
         float *od = s_td + (tin ^ 1) * KM;
         int32_t *oi = s_ti + (tin ^ 1) * KM;
-        for (int i = lane; i < tn + ns; i += 64) {
+        for (int i = mt; i < tn + ns; i += mstep) {
           float d;
           int32_t id;
           int rank;
@@ -364,7 +509,15 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
           for (int j = 0; j < ns; ++j) rank += lex_less(s_sd[j], s_si[j], d, id) ? 1 : 0;
           if (rank < K) { od[rank] = d; oi[rank] = id; }
         }
+      }
+      if (W == 1) {
         __builtin_amdgcn_wave_barrier();
+      } else {
+        if (qt == 0) s_cnt[par ^ 1] = 0;       // the next block's counter (unused until then)
+        __syncthreads();
+        par ^= 1;
+      }
+      if (ns > 0) {
         tin ^= 1;
         tn = min(K, tn + ns);
         if (tn == K) {
@@ -377,7 +530,7 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
 
   // ---- finalize: ascending (dis, id), original ids, padding ----
   const int64_t off = a.out_off ? a.out_off[q] : (int64_t)q * a.k_all;
-  for (int i = lane; i < K; i += 64) {
+  for (int i = qt; i < K; i += 64 * W) {
     const bool have = i < tn;
     a.out_ids[off + i] = have ? (int64_t)s_ti[tin * KM + i] : (int64_t)-1;
     a.out_d[off + i] = have ? s_td[tin * KM + i] : INFINITY;
@@ -437,28 +590,32 @@ void launch_query_order(const int32_t *probes, int32_t p_stride, int64_t nq, int
                      order);
 }
 
-size_t scan_smem_bytes(int nblocks, int kmax, int block_b) {
-  return 4 * wave_lds(nblocks * kBlockDims, kmax, block_b).bytes;
+template <int ST, bool P, bool LK, int W>
+static void launch_variant(const ScanArgs &a, hipStream_t s) {
+  const size_t smem = scan_lds_bytes(a.nblocks * kBlockDims, a.k_max, a.block_b, W);
+  if (smem > kMaxLds) throw std::runtime_error("scan: LDS request exceeds 160 KiB");
+  const int qpw = 4 / W;
+  hipLaunchKernelGGL((scan_kernel<ST, P, LK, W>), dim3((unsigned)((a.nq + qpw - 1) / qpw)),
+                     dim3(kScanThreads), smem, s, a);
+}
+
+template <int ST> static void launch_store(const ScanArgs &a, hipStream_t s) {
+  const bool w4 = a.waves_per_query == 4;
+  if (!a.prune) {
+    if (w4) launch_variant<ST, false, false, 4>(a, s); else launch_variant<ST, false, false, 1>(a, s);
+  } else if (a.lookahead) {
+    if (w4) launch_variant<ST, true, true, 4>(a, s); else launch_variant<ST, true, true, 1>(a, s);
+  } else {
+    if (w4) launch_variant<ST, true, false, 4>(a, s); else launch_variant<ST, true, false, 1>(a, s);
+  }
 }
 
 void launch_scan(const ScanArgs &a, int store, hipStream_t s) {
   if (a.nq <= 0) return;
-  const size_t smem = scan_smem_bytes(a.nblocks, a.k_max, a.block_b);
-  dim3 grid((unsigned)((a.nq + 3) / 4)), block(kScanThreads);
-  const bool p = a.prune != 0;
   switch (store) {
-    case ST_F32:
-      if (p) hipLaunchKernelGGL((scan_kernel<ST_F32, true>), grid, block, smem, s, a);
-      else hipLaunchKernelGGL((scan_kernel<ST_F32, false>), grid, block, smem, s, a);
-      break;
-    case ST_F16:
-      if (p) hipLaunchKernelGGL((scan_kernel<ST_F16, true>), grid, block, smem, s, a);
-      else hipLaunchKernelGGL((scan_kernel<ST_F16, false>), grid, block, smem, s, a);
-      break;
-    default:
-      if (p) hipLaunchKernelGGL((scan_kernel<ST_BF16, true>), grid, block, smem, s, a);
-      else hipLaunchKernelGGL((scan_kernel<ST_BF16, false>), grid, block, smem, s, a);
-      break;
+    case ST_F32: launch_store<ST_F32>(a, s); break;
+    case ST_F16: launch_store<ST_F16>(a, s); break;
+    default: launch_store<ST_BF16>(a, s); break;
   }
 }
 

@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <limits>
+#include <array>
 #include <map>
 #include <mutex>
 #include <new>
@@ -153,8 +154,10 @@ struct ddc_index {
     for (auto &m : marks) { (void)hipEventDestroy(m.a); (void)hipEventDestroy(m.b); }
   }
 
-  // result-invariant launch knobs (environment DDC_QUERY_ORDER / DDC_XCD_SWIZZLE = 0 or 1)
-  int query_order = 1, xcd_swizzle = 1;
+  // result-invariant launch knobs of the scan (0 / -1 = tuned per size class)
+  int waves_per_query = 0, lookahead = -1, query_order = 1, xcd_swizzle = 1;
+  std::mutex tune_mtx;
+  std::map<std::array<int, 4>, std::pair<int, int>> tuned;  // class -> (waves, lookahead)
   int store() const {
     return storage == DDC_F32 ? ddc::ST_F32 : storage == DDC_F16 ? ddc::ST_F16 : ddc::ST_BF16;
   }

@@ -1,0 +1,113 @@
+"""Launch-shape variants of the scan (one wavefront or a workgroup of four per query, with and
+without multi-block look-ahead loads) return bit-identical results, which match the oracle;
+the tuner picks one of them per size class."""
+import numpy as np
+import pytest
+
+import oracle as O
+from parity_util import artifacts, check_search, oracle_index, workload
+
+pytestmark = pytest.mark.gpu
+
+VARIANTS = [(1, 0), (1, 1), (4, 0), (4, 1)]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+
+
+def _index(ix):
+    from paper_2404_16322_amd import Index
+    return Index.from_artifacts(artifacts(ix))
+
+
+def _all_variants(g, run):
+    out = []
+    for w, la in VARIANTS:
+        g.set_launch(waves_per_query=w, lookahead=la)
+        out.append(run())
+    g.set_launch(waves_per_query=0, lookahead=-1)
+    return out
+
+
+def _assert_identical(results):
+    first = results[0]
+    for r in results[1:]:
+        for a, b in zip(first, r):
+            if isinstance(a, np.ndarray):
+                np.testing.assert_array_equal(a, b)
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+@pytest.mark.parametrize("mode,alpha", [("learned", 0.1), ("lossless", 0.0), ("none", 0.0)])
+def test_variants_bitwise_identical_d128(storage, mode, alpha):
+    ix = oracle_index(storage=storage, n_calib=300)
+    w = workload("gauss128")
+    g = _index(ix)
+    Q = w["queries"]
+    res = _all_variants(g, lambda: g.search(Q, 10, 8, alpha, mode=mode)[:2])
+    _assert_identical(res)
+    ora = O.search(ix, Q, 10, 8, alpha, mode=mode)
+    r = check_search(res[0][0], res[0][1], ora, ix)
+    assert not r["bad"], r["bad"][:5]
+
+
+@pytest.fixture(scope="module")
+def wide():
+    # 960-d: 30 dim blocks, so look-ahead windows of 8 blocks occur
+    w = workload("gist1m", n=12000, nq=120, n_calib=200, n_val=0)
+    ix = O.fit(w["base"], w["calib"], nlist=32, delta_d=32, storage="bf16", kmeans_iters=10,
+               calib_k=10, calib_nprobe=6, B=256, seed=7)
+    ix["centroids"] = ix["centroids"].astype(np.float32).astype(np.float64)
+    return w, ix
+
+
+@pytest.mark.parametrize("k,nprobe", [(10, 6), (100, 4)])
+def test_variants_bitwise_identical_d960(wide, k, nprobe):
+    w, ix = wide
+    g = _index(ix)
+    Q = w["queries"]
+    res = _all_variants(g, lambda: g.search(Q, k, nprobe, 0.1)[:2])
+    _assert_identical(res)
+    ora = O.search(ix, Q, k, nprobe, 0.1)
+    r = check_search(res[0][0], res[0][1], ora, ix)
+    print(f"d960: {r['same']}/{r['nq']} identical, {r['excused']} excused")
+    assert not r["bad"], r["bad"][:5]
+    assert r["excused"] <= 0.05 * r["nq"] + 1
+
+
+def test_variants_per_query_k_nprobe_and_counters():
+    ix = oracle_index()
+    w = workload("gauss128")
+    g = _index(ix)
+    Q = w["queries"][:150]
+    rng = np.random.default_rng(3)
+    ks = rng.integers(1, 120, Q.shape[0]).astype(np.int32)
+    nps = rng.integers(1, 20, Q.shape[0]).astype(np.int32)
+    res = _all_variants(g, lambda: g.search_var(Q, ks, nps, 0.2))
+    _assert_identical([r[:3] for r in res])
+    # work counters describe the algorithm, not the launch: identical in every variant
+    for r in res[1:]:
+        for key in ("candidates", "refined", "stage_slices"):
+            assert r[3][key] == res[0][3][key], key
+
+
+def test_tuner_picks_a_variant_and_caches_it():
+    ix = oracle_index()
+    w = workload("gauss128")
+    g = _index(ix)
+    assert g.launch() == dict(waves_per_query=0, lookahead=-1, query_order=1, xcd_swizzle=1)
+    ids0, d0, _ = g.search(w["queries"], 10, 8, 0.1)
+    v = g.scan_variant(w["queries"].shape[0], 10, 8)
+    assert v in VARIANTS
+    ids1, d1, _ = g.search(w["queries"], 10, 8, 0.1)
+    np.testing.assert_array_equal(ids0, ids1)
+    np.testing.assert_array_equal(d0, d1)
+    g.set_launch(waves_per_query=4, lookahead=0, query_order=0, xcd_swizzle=0)
+    assert g.scan_variant(1000, 10, 8) == (4, 0)
+    assert g.scan_variant(1000, 10, 8, mode="none") == (4, 0)
+    ids2, d2, _ = g.search(w["queries"], 10, 8, 0.1)
+    np.testing.assert_array_equal(ids0, ids2)
+    np.testing.assert_array_equal(d0, d2)
