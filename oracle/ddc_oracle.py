@@ -199,6 +199,82 @@ def round_storage(y: np.ndarray, dtype: str) -> np.ndarray:
 
 
 # --------------------------------------------------------------------------------------
+# FP8 pre-stage codes.  Not in the paper (it stores FP32 only, Sec. VII-A); the paper's
+# argument that the learned correction absorbs whatever error the estimate carries
+# (Sec. V-A, V-B) is what makes a coarser first test usable.  Format: OCP 8-bit floating
+# point E4M3 (OFP8 spec v1.0): sign, 4 exponent bits with bias 7, 3 mantissa bits,
+# subnormals, no infinities, S.1111.111 = NaN, largest finite 448.  The leading `lead`
+# rotated dims of every stored vector are coded with one scale per (list, tile of 64
+# consecutive list positions): s = max |y| over the tile / 448 in FP32 (1 if the tile is all
+# zero), code = E4M3 round-to-nearest-even of fp32(y / s) with saturation to +-448, decoded
+# value = fp32(value(code) * s).  Reading: the code is an integer decided by FP32 values,
+# so every step that decides it is taken in FP32 (division and product correctly rounded).
+# --------------------------------------------------------------------------------------
+FP8_MAX = 448.0
+FP8_TILE = 64
+
+
+def fp8_e4m3_value(code: int) -> float:
+    """Value of one E4M3 code by the format's definition (NaN for S.1111.111)."""
+    code = int(code) & 0xFF
+    sign = -1.0 if code & 0x80 else 1.0
+    e = (code >> 3) & 0xF
+    m = code & 0x7
+    if e == 0xF and m == 0x7:
+        return math.nan
+    if e == 0:
+        return sign * m * 2.0 ** -9              # subnormal: m/8 * 2^(1-7)
+    return sign * (1.0 + m / 8.0) * 2.0 ** (e - 7)
+
+
+FP8_TABLE = np.array([fp8_e4m3_value(c) for c in range(256)], dtype=np.float64)
+
+
+def fp8_e4m3_encode(v: np.ndarray) -> np.ndarray:
+    """E4M3 code of every FP32 value: nearest finite value, ties to the even mantissa,
+    magnitudes beyond 448 saturate to 448; the sign bit is the sign bit of v."""
+    v = np.asarray(v, dtype=np.float32).astype(np.float64)   # exact
+    a = np.abs(v)
+    code = np.zeros(v.shape, dtype=np.int64)
+    sub = a < 2.0 ** -6
+    # subnormal range: grid 2^-9, code = number of grid steps (8 steps = smallest normal)
+    code[sub] = np.rint(a[sub] / 2.0 ** -9).astype(np.int64)
+    nrm = ~sub
+    if nrm.any():
+        _, ex = np.frexp(a[nrm])                  # a = f * 2^ex, f in [0.5, 1)
+        e = ex.astype(np.int64) - 1                # a in [2^e, 2^(e+1))
+        e = np.minimum(e, 8)
+        n = np.rint(a[nrm] / np.ldexp(1.0, e - 3)).astype(np.int64)   # in [8, 16]
+        code[nrm] = ((e + 7) << 3) + (n - 8)       # n = 16 carries into the next exponent
+    code = np.minimum(code, 0x7E)                  # saturate (0x7F would be NaN)
+    code |= np.where(np.signbit(v), 0x80, 0)
+    return code.astype(np.uint8)
+
+
+def fp8_encode_lead(Y: np.ndarray, list_off: np.ndarray, list_ids: np.ndarray, lead: int = 64):
+    """Codes of the leading ``lead`` dims of every stored vector (rows of Y by id), with
+    one scale per (list, 64-position tile).  Returns dict(lead, codes (n, lead) uint8,
+    scale (n,) float32 = the scale of the vector's tile, dec (n, lead) FP64 decoded)."""
+    Y = np.asarray(Y, dtype=np.float64)
+    n = Y.shape[0]
+    codes = np.zeros((n, lead), dtype=np.uint8)
+    scale = np.ones(n, dtype=np.float32)
+    dec = np.zeros((n, lead), dtype=np.float64)
+    for j in range(list_off.shape[0] - 1):
+        lo, hi = int(list_off[j]), int(list_off[j + 1])
+        for t0 in range(lo, hi, FP8_TILE):
+            ids = list_ids[t0:min(t0 + FP8_TILE, hi)]
+            a = Y[ids, :lead].astype(np.float32)
+            amax = np.float32(np.abs(a).max())
+            s = np.float32(amax / np.float32(FP8_MAX)) if amax > 0 else np.float32(1.0)
+            c = fp8_e4m3_encode(a / s)                                # FP32 division
+            codes[ids] = c
+            scale[ids] = s
+            dec[ids] = (FP8_TABLE[c].astype(np.float32) * s).astype(np.float64)  # FP32 product
+    return dict(lead=lead, codes=codes, scale=scale, dec=dec)
+
+
+# --------------------------------------------------------------------------------------
 # IVF  [Sec. II-A "Inverted File-Based"]: k-means buckets, probe the nearest centroids.
 # --------------------------------------------------------------------------------------
 
@@ -304,7 +380,7 @@ def _rel(a, b, c):
 
 
 def search_one(qrot, Y, list_off, list_ids, probes, k, m, beta, bounds, B=256, L=0,
-               prune=True, collect_neg=None):
+               prune=True, collect_neg=None, pre=None):
     """Canonical block-synchronous pruned refinement for one rotated query.
 
     The paper's refinement updates tau after every candidate [Sec. I: result queue Q with
@@ -322,12 +398,17 @@ def search_one(qrot, Y, list_off, list_ids, probes, k, m, beta, bounds, B=256, L
       margin = smallest relative distance of any decision quantity to its threshold.
     If ``collect_neg`` is a list, (id, tau_b, e_1..e_S) of every candidate with tau_b
     finite and dis > tau_b is appended to it (label-1 pool of the calibration).
+    ``pre`` = (dec, m0, beta0) adds the FP8 pre-stage: before stage 1 every tested
+    candidate's e_0 = sum over the coded lead dims of (q'_i - dec_i)^2 is tested with
+    m0 e_0 + beta0 > tau_b; survivors restart at dim 0 on the stored values.  Then
+    stop_counts has S + 1 entries, entry 0 counting the candidates the pre-stage pruned.
     """
     S = bounds.shape[0]
     T_d = np.zeros(0)
     T_i = np.zeros(0, dtype=np.int64)
     tau_hist = []
-    stop_counts = np.zeros(S, dtype=np.int64)
+    P = 1 if pre is not None else 0
+    stop_counts = np.zeros(S + P, dtype=np.int64)
     margin = math.inf
     b = 0
     for lst in probes:
@@ -338,6 +419,16 @@ def search_one(qrot, Y, list_off, list_ids, probes, k, m, beta, bounds, B=256, L
             tau_b = tau_hist[j] if j >= 0 else math.inf
             e = partial_dists(Y[ids], qrot, bounds)          # (nb, S)
             stop = np.full(ids.shape[0], S - 1, dtype=np.int64)
+            pre_hit = np.zeros(ids.shape[0], dtype=bool)
+            if prune and pre is not None and math.isfinite(tau_b):
+                dec, m0, beta0 = pre
+                lead = dec.shape[1]
+                e0 = partial_dists(dec[ids], qrot[:lead], np.array([lead]))[:, 0]
+                lhs0 = m0 * e0 + beta0
+                pre_hit = lhs0 > tau_b
+                rel0 = np.abs(lhs0 - tau_b) / _rel(m0 * e0, np.full_like(e0, beta0), tau_b)
+                if rel0.size:
+                    margin = min(margin, float(rel0.min()))
             if prune and math.isfinite(tau_b) and S > 1:
                 lhs = e[:, :S - 1] * m[None, :] + beta[None, :]   # (nb, S-1)
                 hit = lhs > tau_b
@@ -345,12 +436,14 @@ def search_one(qrot, Y, list_off, list_ids, probes, k, m, beta, bounds, B=256, L
                 first = np.where(any_hit, hit.argmax(axis=1), S - 1)
                 stop = first
                 # decision margins of every evaluated test (stages <= stop)
-                evaluated = np.arange(S - 1)[None, :] <= first[:, None]
+                evaluated = (np.arange(S - 1)[None, :] <= first[:, None]) & ~pre_hit[:, None]
                 rel = np.abs(lhs - tau_b) / _rel(e[:, :S - 1] * m[None, :], beta[None, :], tau_b)
                 if evaluated.any():
                     margin = min(margin, float(rel[evaluated].min()))
-            np.add.at(stop_counts, stop, 1)
-            surv = stop == S - 1
+            np.add.at(stop_counts, stop[~pre_hit] + P, 1)
+            if P:
+                stop_counts[0] += int(pre_hit.sum())
+            surv = (stop == S - 1) & ~pre_hit
             sd = e[surv, S - 1]
             si = ids[surv]
             if collect_neg is not None and math.isfinite(tau_b):
@@ -379,12 +472,12 @@ def search_one(qrot, Y, list_off, list_ids, probes, k, m, beta, bounds, B=256, L
     return ids_out, d_out, stop_counts, margin
 
 
-def search_sequential(qrot, Y, list_off, list_ids, probes, k, m, beta, bounds):
+def search_sequential(qrot, Y, list_off, list_ids, probes, k, m, beta, bounds, pre=None):
     """The paper's per-candidate refinement, coded separately: a binary max-heap Q of the
     K best (dis, id); tau = its root once it holds K entries; each candidate walks the
     stages and is pruned at the first stage with m_s e_s + beta_s > tau, otherwise enters
     Q when (dis, id) is smaller than the root [Sec. I refinement; Alg. 2 stage loop;
-    Sec. V-A classifier].  Equals ``search_one`` with B = 1, L = 0."""
+    Sec. V-A classifier].  Equals ``search_one`` with B = 1, L = 0 (``pre`` as there)."""
     heap = []   # entries (-dis, -id): the root is the largest (dis, id)
     q = np.asarray(qrot, dtype=np.float64)
     S = bounds.shape[0]
@@ -392,6 +485,14 @@ def search_sequential(qrot, Y, list_off, list_ids, probes, k, m, beta, bounds):
         for pos in range(int(list_off[lst]), int(list_off[lst + 1])):
             x = int(list_ids[pos])
             tau = -heap[0][0] if len(heap) == k else math.inf
+            if pre is not None and tau != math.inf:
+                dec, m0, beta0 = pre
+                e0 = 0.0
+                for i in range(dec.shape[1]):
+                    t = q[i] - dec[x, i]
+                    e0 += t * t
+                if m0 * e0 + beta0 > tau:
+                    continue
             acc = 0.0
             lo = 0
             pruned = False
@@ -507,15 +608,18 @@ def beta_for_alpha(G: np.ndarray, alpha: float, mode: str = "joint") -> np.ndarr
 # --------------------------------------------------------------------------------------
 
 def calibrate(Y, list_off, list_ids, centroids, mu, R, calib, bounds, calib_k=10, calib_nprobe=8,
-              B=256, L=0, seed=0, max_neg=50):
+              B=256, L=0, seed=0, max_neg=50, pre_dec=None):
     """Per test stage: m_s from logistic regression on label 0 = (e_s, tau_q) of the K_c
     true neighbours of every calibration query (tau_q = its K_c-th distance) and label 1 =
     up to ``max_neg`` (e_s, tau_b) per query drawn (smallest SplitMix64 keys of
     query_index * 2^32 + id) from the candidates of an unpruned canonical IVF search
     (calib_nprobe, B, L) whose exact distance exceeds the block's finite tau_b.
-    Returns dict(m, G) with G the (n0, S_t) residual matrix g_s(j) = tau_j - m_s e_s(j)."""
+    Returns dict(m, G) with G the (n0, S_t) residual matrix g_s(j) = tau_j - m_s e_s(j).
+    With ``pre_dec`` (decoded FP8 lead dims, rows by id) the pre-stage is one more test
+    stage, first in m and G, whose feature e_0 is taken over the decoded values."""
     Y = np.asarray(Y, dtype=np.float64)
     S = bounds.shape[0]
+    P = 1 if pre_dec is not None else 0
     St = S - 1
     Qr = rotate(calib, mu, R)
     knn_ids, knn_d = bruteforce_knn(Y, Qr, calib_k)
@@ -524,7 +628,11 @@ def calibrate(Y, list_off, list_ids, centroids, mu, R, calib, bounds, calib_k=10
     for qi in range(Qr.shape[0]):
         tau_q = knn_d[qi, calib_k - 1]
         e = partial_dists(Y[knn_ids[qi]], Qr[qi], bounds)
-        pos_e.append(e[:, :St])
+        if pre_dec is not None:
+            lead = pre_dec.shape[1]
+            e0 = partial_dists(pre_dec[knn_ids[qi]], Qr[qi][:lead], np.array([lead]))
+            e = np.hstack([e0, e])
+        pos_e.append(e[:, :St + P])
         pos_tau.append(np.full(calib_k, tau_q))
         probes, _, _ = probe_order(Qr[qi], centroids, calib_nprobe)
         pool = []
@@ -535,15 +643,20 @@ def calibrate(Y, list_off, list_ids, centroids, mu, R, calib, bounds, calib_k=10
             keys = ctr_key(seed, TAG_NEG, (np.uint64(qi) << np.uint64(32)) + idx)
             take = np.lexsort((idx, keys))[:max_neg]
             for t in take:
-                neg_e.append(pool[t][2][:St])
+                en = pool[t][2][:St]
+                if pre_dec is not None:
+                    lead = pre_dec.shape[1]
+                    e0 = partial_dists(pre_dec[[pool[t][0]]], Qr[qi][:lead], np.array([lead]))[0]
+                    en = np.concatenate([e0, en])
+                neg_e.append(en)
                 neg_tau.append(pool[t][1])
     pos_e = np.vstack(pos_e)
     pos_tau = np.concatenate(pos_tau)
-    neg_e = np.vstack(neg_e) if neg_e else np.zeros((0, St))
+    neg_e = np.vstack(neg_e) if neg_e else np.zeros((0, St + P))
     neg_tau = np.asarray(neg_tau, dtype=np.float64)
-    m = np.ones(St)
+    m = np.ones(St + P)
     lr = []
-    for s in range(St):
+    for s in range(St + P):
         F = np.vstack([np.column_stack([pos_e[:, s], pos_tau]), np.column_stack([neg_e[:, s], neg_tau])])
         lab = np.concatenate([np.zeros(pos_e.shape[0]), np.ones(neg_e.shape[0])])
         if neg_e.shape[0] == 0:
@@ -562,8 +675,9 @@ def calibrate(Y, list_off, list_ids, centroids, mu, R, calib, bounds, calib_k=10
 # --------------------------------------------------------------------------------------
 
 def fit(base, calib, nlist, delta_d=32, storage="f32", kmeans_iters=25, calib_k=10,
-        calib_nprobe=None, B=256, L=0, seed=0, pca_sample=1_000_000, max_neg=50):
-    """Projection + IVF lists + calibrated correction table for ``base``."""
+        calib_nprobe=None, B=256, L=0, seed=0, pca_sample=1_000_000, max_neg=50, fp8_lead=0):
+    """Projection + IVF lists + calibrated correction table for ``base``; ``fp8_lead`` = 64
+    adds the FP8 pre-stage over the leading 64 rotated dims."""
     base = np.asarray(base)
     D = base.shape[1]
     pca = pca_fit(base, pca_sample, seed)
@@ -573,11 +687,12 @@ def fit(base, calib, nlist, delta_d=32, storage="f32", kmeans_iters=25, calib_k=
     bounds = stage_bounds(D, delta_d)
     if calib_nprobe is None:
         calib_nprobe = int(min(max(1, nlist // 8), 64))
+    pre = fp8_encode_lead(Y, off, ids, fp8_lead) if fp8_lead else None
     cal = calibrate(Y, off, ids, C, pca["mu"], pca["R"], calib, bounds, calib_k, calib_nprobe,
-                    B, L, seed, max_neg)
+                    B, L, seed, max_neg, pre_dec=pre["dec"] if pre else None)
     return dict(mu=pca["mu"], R=pca["R"], lam=pca["lam"], cov=pca["cov"], Y=Y, centroids=C,
                 assign=assign, list_off=off, list_ids=ids, bounds=bounds, m=cal["m"], G=cal["G"],
-                calib=cal, storage=storage, delta_d=delta_d, B=B, L=L)
+                calib=cal, storage=storage, delta_d=delta_d, B=B, L=L, pre=pre)
 
 
 def search(index, queries, k, nprobe, alpha, mode="learned", B=None, L=None, calib_mode="joint"):
@@ -587,11 +702,17 @@ def search(index, queries, k, nprobe, alpha, mode="learned", B=None, L=None, cal
     L = index["L"] if L is None else L
     bounds = index["bounds"]
     St = bounds.shape[0] - 1
+    pre_ix = index.get("pre")
+    pre = None
     if mode == "learned":
         m = index["m"]
         beta = beta_for_alpha(index["G"], alpha, calib_mode)
         prune = alpha > 0
+        if pre_ix is not None:     # the pre-stage is the first test stage of the table
+            pre = (pre_ix["dec"], float(m[0]), float(beta[0]))
+            m, beta = m[1:], beta[1:]
     elif mode == "lossless":
+        # the FP8 estimate is not a lower bound of the stored-value distance: no pre-stage
         m, beta, prune = np.ones(St), np.zeros(St), True
     elif mode == "none":
         m, beta, prune = np.ones(St), np.zeros(St), False
@@ -601,14 +722,14 @@ def search(index, queries, k, nprobe, alpha, mode="learned", B=None, L=None, cal
     nq = Qr.shape[0]
     ids = np.full((nq, k), -1, dtype=np.int64)
     ds = np.full((nq, k), np.inf)
-    stops = np.zeros((nq, bounds.shape[0]), dtype=np.int64)
+    stops = np.zeros((nq, bounds.shape[0] + (1 if pre is not None and prune else 0)), dtype=np.int64)
     margins = np.full(nq, math.inf)
     probes_all = np.zeros((nq, nprobe), dtype=np.int64)
     for qi in range(nq):
         probes, _, pm = probe_order(Qr[qi], index["centroids"], nprobe)
         probes_all[qi] = probes
         i, d, st, mg = search_one(Qr[qi], index["Y"], index["list_off"], index["list_ids"], probes,
-                                  k, m, beta, bounds, B, L, prune)
+                                  k, m, beta, bounds, B, L, prune, pre=pre if prune else None)
         ids[qi], ds[qi], stops[qi], margins[qi] = i, d, st, min(mg, pm)
     return dict(ids=ids, dists=ds, stops=stops, margin=margins, probes=probes_all, qrot=Qr, m=m,
                 beta=beta)
@@ -631,11 +752,16 @@ def false_prune_rate(index, queries, k, alpha, calib_mode="joint"):
     St = bounds.shape[0] - 1
     m = index["m"]
     beta = beta_for_alpha(index["G"], alpha, calib_mode)
+    pre = index.get("pre")
     Qr = rotate(queries, index["mu"], index["R"])
     knn_ids, knn_d = bruteforce_knn(index["Y"], Qr, k)
     per_q = np.zeros(Qr.shape[0])
     for qi in range(Qr.shape[0]):
         tau = knn_d[qi, k - 1]
         e = partial_dists(index["Y"][knn_ids[qi]], Qr[qi], bounds)[:, :St]
+        if pre is not None:
+            lead = pre["lead"]
+            e0 = partial_dists(pre["dec"][knn_ids[qi]], Qr[qi][:lead], np.array([lead]))
+            e = np.hstack([e0, e])
         per_q[qi] = np.count_nonzero((e * m[None, :] + beta[None, :] > tau).any(axis=1))
     return float(per_q.sum() / (k * Qr.shape[0])), per_q

@@ -408,3 +408,126 @@ def test_rotate_orientation_gives_principal_coordinates(small_workload):
     np.testing.assert_allclose(np.diag(cov), p["lam"], rtol=1e-9, atol=1e-12)
     assert np.abs(cov - np.diag(np.diag(cov))).max() <= 1e-9 * p["lam"][0]
     np.testing.assert_allclose(Y.mean(axis=0), 0, atol=1e-9)
+
+
+# ----------------------------------------------------------------------------- FP8 pre-stage
+
+def _finite_codes():
+    return [c for c in range(256) if not math.isnan(O.fp8_e4m3_value(c))]
+
+
+def test_fp8_e4m3_published_values():
+    """Code values against the OFP8 specification's E4M3 table (golden fixture)."""
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "fp8_e4m3.txt")) if l.strip() and l[0] != "#"]
+    for hexc, val in rows:
+        v = O.fp8_e4m3_value(int(hexc, 16))
+        if val == "nan":
+            assert math.isnan(v)
+        else:
+            assert v == float(val) and math.copysign(1, v) == math.copysign(1, float(val))
+    fin = [O.fp8_e4m3_value(c) for c in _finite_codes()]
+    assert len(fin) == 254 and max(fin) == 448.0 and min(fin) == -448.0
+    pos = sorted({v for v in fin if v > 0})
+    assert len(pos) == 126 and pos[0] == 2.0 ** -9       # strictly increasing magnitudes
+
+
+def test_fp8_encode_is_nearest_ties_to_even_with_saturation():
+    """Brute force over all finite codes: nearest value, ties to the even code (even
+    mantissa), magnitudes beyond 448 clamp to 448."""
+    codes = np.array(_finite_codes())
+    vals = np.array([O.fp8_e4m3_value(c) for c in codes])
+    rng = np.random.default_rng(5)
+    v = np.concatenate([
+        rng.standard_normal(3000) * 10.0 ** rng.uniform(-4, 3, 3000),
+        # exact midpoints between neighbouring positive values (ties)
+        (np.sort(vals[vals > 0])[:-1] + np.sort(vals[vals > 0])[1:]) / 2,
+        -(np.sort(vals[vals > 0])[:-1] + np.sort(vals[vals > 0])[1:]) / 2,
+        [0.0, -0.0, 448.0, 463.9, 464.0, 465.0, 1e6, -1e6, 2.0 ** -10, 2.0 ** -10 * 3, 2.0 ** -6],
+    ]).astype(np.float32)
+    got = O.fp8_e4m3_encode(v)
+    for x, c in zip(v.astype(np.float64), got):
+        xc = min(max(x, -448.0), 448.0)
+        err = np.abs(vals - xc)
+        best = err.min()
+        cands = codes[err == best]
+        if len(cands) > 1:
+            cands = [c2 for c2 in cands if c2 % 2 == 0 or (c2 & 0x7F) == 0]
+        if xc == 0.0:
+            assert c in (0x00, 0x80) and (c == 0x80) == bool(np.signbit(x))
+            continue
+        assert int(c) in [int(t) for t in cands], (x, c, cands)
+
+
+def test_fp8_lead_codes_per_list_tile(small_index):
+    """Every (list, 64-position tile) has scale max|y|/448 (FP32); its largest element codes
+    to +-448; decoded values are within half an E4M3 step of the stored values."""
+    ix = small_index
+    pre = O.fp8_encode_lead(ix["Y"], ix["list_off"], ix["list_ids"], 64)
+    Y = ix["Y"][:, :64]
+    for j in range(ix["list_off"].shape[0] - 1):
+        lo, hi = int(ix["list_off"][j]), int(ix["list_off"][j + 1])
+        for t0 in range(lo, hi, 64):
+            ids = ix["list_ids"][t0:min(t0 + 64, hi)]
+            s = pre["scale"][ids]
+            assert np.all(s == s[0])
+            amax = np.abs(Y[ids]).max()
+            assert abs(float(s[0]) - amax / 448) <= 2.0 ** -23 * amax / 448
+            assert np.any((pre["codes"][ids] & 0x7F) == 0x7E)
+    v = Y / pre["scale"][:, None].astype(np.float64)
+    a = np.abs(v)
+    step = np.where(a < 2.0 ** -6, 2.0 ** -9, 2.0 ** (np.floor(np.log2(np.maximum(a, 1e-300))) - 3))
+    decv = pre["dec"] / pre["scale"][:, None].astype(np.float64)
+    assert np.all(np.abs(decv - v) <= step / 2 * (1 + 1e-6) + 1e-12)
+
+
+@pytest.fixture(scope="module")
+def fp8_index(small_workload):
+    w = small_workload
+    return O.fit(w["base"], w["calib"], nlist=64, kmeans_iters=25, calib_k=10, calib_nprobe=8,
+                 seed=7, fp8_lead=64)
+
+
+def test_fp8_prestage_block_of_one_equals_sequential(fp8_index, small_workload):
+    ix = fp8_index
+    St = ix["bounds"].shape[0] - 1
+    assert ix["m"].shape == (St + 1,) and ix["G"].shape[1] == St + 1
+    beta = O.beta_for_alpha(ix["G"], 0.1)
+    pre = (ix["pre"]["dec"], ix["m"][0], beta[0])
+    for qv in small_workload["queries"][:12]:
+        qr = O.rotate(qv[None], ix["mu"], ix["R"])[0]
+        probes, _, _ = O.probe_order(qr, ix["centroids"], 8)
+        a = O.search_one(qr, ix["Y"], ix["list_off"], ix["list_ids"], probes, 10, ix["m"][1:],
+                         beta[1:], ix["bounds"], B=1, L=0, pre=pre)
+        b = O.search_sequential(qr, ix["Y"], ix["list_off"], ix["list_ids"], probes, 10, ix["m"][1:],
+                                beta[1:], ix["bounds"], pre=pre)
+        assert a[0].tolist() == b[0].tolist()
+        np.testing.assert_array_equal(a[1], b[1])
+
+
+def test_fp8_prestage_prunes_and_lossless_ignores_it(fp8_index, small_index, small_workload):
+    Q = small_workload["queries"]
+    r = O.search(fp8_index, Q, 10, 8, 0.1)
+    assert r["stops"].shape[1] == fp8_index["bounds"].shape[0] + 1
+    assert r["stops"][:, 0].sum() > 0                   # the pre-stage prunes candidates
+    # lossless / none never use the FP8 estimate: identical to the index without codes
+    for mode in ("lossless", "none"):
+        a = O.search(fp8_index, Q, 10, 8, 0.0, mode=mode)
+        b = O.search(small_index, Q, 10, 8, 0.0, mode=mode)
+        assert a["ids"].tolist() == b["ids"].tolist()
+    # every returned distance is the exact distance of the stored (not FP8) vector
+    for qi in range(20):
+        ok = r["ids"][qi] >= 0
+        ex = O.sq_dist_direct(fp8_index["Y"][r["ids"][qi][ok]], r["qrot"][qi])
+        np.testing.assert_allclose(r["dists"][qi][ok], ex, rtol=1e-12)
+
+
+def test_fp8_heldout_false_prune_rate_matches_significance(fp8_index, small_workload):
+    """The joint calibration covers the pre-stage too: held-out miss rate matches alpha."""
+    rng = np.random.default_rng(9)
+    for a in [0.05, 0.1]:
+        rate, per_q = O.false_prune_rate(fp8_index, small_workload["val"], 10, a)
+        boots = np.array([per_q[rng.integers(0, per_q.shape[0], per_q.shape[0])].mean() / 10
+                          for _ in range(2000)])
+        lo, hi = np.quantile(boots, [0.005, 0.995])
+        half = (hi - lo) / 2 * math.sqrt(2)
+        assert abs(rate - a) <= half, (a, rate, half)
