@@ -46,6 +46,12 @@ CONFIGS = {
                    error_vs_fp64=True, serve=None),
     "gist1m-f16": dict(data="gist1m", nlist=4096, storage="f16", rotation="bf16", k=100, nprobes=[64],
                        error_vs_fp64=True, serve=None),
+    # 2M x 768 unit-normalised FP16 with the FP8 E4M3 pre-stage over the leading 64 dims;
+    # a step is 4 launches of 4,096 queries, each query with its own nprobe ~ U{8..256} and
+    # K ~ U{10, 50, 100}
+    "embed768": dict(data="embed768", nlist=4096, storage="f16", rotation="bf16", fp8=64,
+                     uneven=dict(batches=4, batch=4096, nprobe=(8, 256), k=(10, 50, 100)),
+                     fit=dict(kmeans_train_per_list=64, kmeans_iters=10), serve=None),
     # 5M x 256 unit-normalised FP16, IVF 16384: serving at absolute Poisson rates
     "embed256": dict(data="embed256", nlist=16384, storage="f16", rotation="f32", k=10,
                      nprobes=[16, 32, 48, 64, 96, 128], fit=dict(kmeans_train_per_list=64, kmeans_iters=10),
@@ -176,7 +182,9 @@ def main():
     dev = torch.device("cuda:0")
     cfg = CONFIGS[args.workload]
     t0 = time.time()
-    w = synthdata.make_workload(cfg["data"], nq=cfg.get("gt_queries"))
+    uneven = cfg.get("uneven")
+    nq_total = uneven["batches"] * uneven["batch"] if uneven else cfg.get("gt_queries")
+    w = synthdata.make_workload(cfg["data"], nq=nq_total)
     spec = w["spec"]
     nq, D = w["queries"].shape
     log(f"[bench] workload {args.workload}: n={w['base'].shape[0]} D={D} nq={nq} "
@@ -185,7 +193,7 @@ def main():
     t0 = time.time()
     nlist = cfg["nlist"]
     ix = Index.fit(w["base"], w["calib"], nlist=nlist, seed=spec["cfg"], storage=cfg["storage"],
-                   rotation=cfg["rotation"], **cfg.get("fit", {}))
+                   rotation=cfg["rotation"], fp8_lead_dims=cfg.get("fp8", 0), **cfg.get("fit", {}))
     torch.cuda.synchronize()
     fit_s = time.time() - t0
     info = ix.info()
@@ -199,16 +207,45 @@ def main():
     torch.cuda.empty_cache()
     log(f"[bench] FP64 ground truth {time.time() - t0:.1f}s")
 
-    k = args.k or cfg["k"]
     q_dev = torch.from_numpy(w["queries"]).to(dev)
-    ids_dev = torch.empty((nq, k), dtype=torch.int64, device=dev)
-    d_dev = torch.empty((nq, k), dtype=torch.float32, device=dev)
-    ctr = torch.zeros(68, dtype=torch.int64, device=dev)
+    ctr = torch.zeros(70, dtype=torch.int64, device=dev)
     stream = torch.cuda.Stream(device=dev)
+    if uneven:
+        # per-query K and nprobe, results in CSR order; one step = `batches` launches
+        ks, nps = synthdata.uneven_requests(nq, 1000 * spec["cfg"] + 9, *uneven["nprobe"], uneven["k"])
+        off = np.zeros(nq + 1, np.int64)
+        off[1:] = np.cumsum(ks)
+        k = int(ks.max())
+        k_dev, np_dev = torch.from_numpy(ks).to(dev), torch.from_numpy(nps).to(dev)
+        off_dev = torch.from_numpy(off).to(dev)
+        ids_dev = torch.empty(int(off[-1]), dtype=torch.int64, device=dev)
+        d_dev = torch.empty(int(off[-1]), dtype=torch.float32, device=dev)
+        bsz = uneven["batch"]
+        launches = uneven["batches"]
+        first10 = off[:-1, None] + np.arange(10)[None, :]
+    else:
+        k = args.k or cfg["k"]
+        ids_dev = torch.empty((nq, k), dtype=torch.int64, device=dev)
+        d_dev = torch.empty((nq, k), dtype=torch.float32, device=dev)
+        launches = 1
 
     def run(nprobe, alpha, mode, counters=False):
-        ix.search_device(q_dev.data_ptr(), nq, k, nprobe, alpha, mode, ids_dev.data_ptr(),
-                         d_dev.data_ptr(), ctr.data_ptr() if counters else 0, stream.cuda_stream)
+        cp = ctr.data_ptr() if counters else 0
+        if not uneven:
+            ix.search_device(q_dev.data_ptr(), nq, k, nprobe, alpha, mode, ids_dev.data_ptr(),
+                             d_dev.data_ptr(), cp, stream.cuda_stream)
+            return
+        for b in range(launches):
+            s0 = b * bsz
+            ix.search_device(q_dev.data_ptr() + s0 * D * 4, bsz, 0, 0, alpha, mode,
+                             ids_dev.data_ptr(), d_dev.data_ptr(), cp, stream.cuda_stream,
+                             d_k=k_dev.data_ptr() + s0 * 4, k_max=k,
+                             d_nprobe=np_dev.data_ptr() + s0 * 4, nprobe_max=int(nps.max()),
+                             d_offsets=off_dev.data_ptr() + s0 * 8)
+
+    def result_ids():
+        a = ids_dev.cpu().numpy()
+        return a[first10] if uneven else a
 
     def timed(nprobe, alpha, mode, reps):
         with torch.cuda.stream(stream):
@@ -223,14 +260,17 @@ def main():
     def recall(nprobe, alpha, mode):
         run(nprobe, alpha, mode)
         stream.synchronize()
-        return recall_at_10(ids_dev.cpu().numpy(), gt)
+        return recall_at_10(result_ids(), gt)
 
     # ---- operating points ---------------------------------------------------------
     sweep = []
+    nprobe_list = ["per-query"] if uneven else cfg["nprobes"]
     if args.nprobe:
         points = [(args.nprobe, args.alpha)]
+    elif uneven and args.alpha:
+        points = [("per-query", args.alpha)]
     else:
-        points = [(p, a) for p in cfg["nprobes"] for a in ALPHAS]
+        points = [(p, a) for p in nprobe_list for a in ALPHAS]
     best = None
     for p, a in points:
         r = recall(p, a, "learned")
@@ -239,7 +279,7 @@ def main():
         if r >= 0.95 and (best is None or ms < best[2]):
             best = (p, a, ms, r)
     full_best = None
-    for p in (cfg["nprobes"] if not args.nprobe else [args.nprobe]):
+    for p in (nprobe_list if not args.nprobe else [args.nprobe]):
         r = recall(p, 0.0, "none")
         ms = timed(p, 0.0, "none", 2)
         sweep.append(dict(nprobe=p, alpha=0.0, recall=r, qps=nq / ms * 1e3, mode="none"))
@@ -286,14 +326,21 @@ def main():
     stream.synchronize()
     c = ctr.cpu().numpy()
     candidates, refined, slices = int(c[0]), int(c[1]), int(c[2])
+    pre_reads, pre_pruned = int(c[68]), int(c[69])
     esize = {0: 4, 1: 2, 2: 2}[info["storage"]]
     slice_bytes = 32 * esize
     NB = info["dim_padded"] // 32      # 32-dim blocks the scan counts
-    # algorithmic bytes of one scan launch: base slices read + ids of refined candidates +
-    # list table entries + rotated queries + outputs
-    scan_bytes = (slices * slice_bytes + refined * 4 + nq * nprobe * 12 + nq * info["dim_padded"] * 4
-                  + nq * k * 12)
-    full_bytes_per_launch = candidates * info["dim_padded"] * esize
+    probe_entries = int(nps.sum()) if uneven else nq * nprobe
+    out_entries = int(off[-1]) if uneven else nq * k
+
+    def launch_bytes(sl, ref, pre, probes):
+        """Algorithmic bytes of one scan launch: base slices read + FP8 slices read + ids of
+        refined candidates + list table entries + rotated queries + outputs."""
+        return (sl * slice_bytes + pre * 64 + ref * 4 + probes * 12 + nq * info["dim_padded"] * 4
+                + out_entries * 12) / launches
+
+    scan_bytes = launch_bytes(slices, refined, pre_reads, probe_entries)
+    full_bytes_per_launch = candidates * info["dim_padded"] * esize / launches
 
     # ---- timed region -----------------------------------------------------------------
     for _ in range(args.warmup):
@@ -317,7 +364,7 @@ def main():
     qps = nq / ms_step * 1e3
 
     # every launch shape of the scan at the operating point (results are bit-identical)
-    chosen = ix.scan_variant(nq, k, nprobe)
+    chosen = ix.scan_variant(bsz, k, int(nps.max())) if uneven else ix.scan_variant(nq, k, nprobe)
     variants = {}
     for wv, la in ((1, 0), (1, 1), (4, 0), (4, 1)):
         ix.set_launch(waves_per_query=wv, lookahead=la)
@@ -346,9 +393,31 @@ def main():
     run(full_best[0], 0.0, "none", counters=True)
     stream.synchronize()
     fc = ctr.cpu().numpy()
-    full_scan_bytes = int(fc[2]) * slice_bytes + int(fc[1]) * 4 + nq * full_best[0] * 12 + \
-        nq * info["dim_padded"] * 4 + nq * k * 12
+    full_scan_bytes = launch_bytes(int(fc[2]), int(fc[1]), 0,
+                                   probe_entries if uneven else nq * full_best[0])
     full_scan_ms = fkms[3] / max(1, fkn[3])
+
+    # the same index without the FP8 pre-stage (re-imported, recalibrated on the same queries)
+    no_pre = None
+    if cfg.get("fp8"):
+        e = ix.export()
+        art = dict(e, fp8_lead_dims=0, resid=None, m=None)
+        ix_main = ix
+        ix = Index.from_artifacts(art)
+        ix.calibrate(w["calib"], seed=spec["cfg"])
+        r_np = recall(nprobe, alpha, "learned")
+        for _ in range(args.warmup):
+            run(nprobe, alpha, "learned")
+        ms_np = timed(nprobe, alpha, "learned", args.steps)
+        ctr.zero_()
+        run(nprobe, alpha, "learned", counters=True)
+        stream.synchronize()
+        nc = ctr.cpu().numpy()
+        no_pre = dict(qps=round(nq / ms_np * 1e3, 1), recall_at_10=round(r_np, 4),
+                      scanned_dim_ratio=round(int(nc[2]) / max(1, int(nc[0]) * NB), 4))
+        ix.close()
+        ix = ix_main
+        log(f"[bench] without the FP8 pre-stage: {no_pre}")
 
     achieved = scan_bytes / (scan_ms * 1e-3) / 1e9
     traffic = None
@@ -395,9 +464,16 @@ def main():
                    centroids=e["centroids"].astype(np.float64), m=e["m"], G=e["resid"], B=256, L=0,
                    bounds=oracle.stage_bounds(D, 32))
         oix["list_off"], oix["list_ids"] = oracle.build_lists(e["assign"], nlist)
+        if e.get("fp8_lead_dims"):
+            oix["pre"] = oracle.fp8_encode_lead(oix["Y"], oix["list_off"], oix["list_ids"],
+                                                e["fp8_lead_dims"])
         sample = w["queries"][:args.cpu_sample]
         t0 = time.time()
-        oracle.search(oix, sample, k, nprobe, alpha)
+        if uneven:
+            for i in range(sample.shape[0]):
+                oracle.search(oix, sample[i:i + 1], int(ks[i]), int(nps[i]), alpha)
+        else:
+            oracle.search(oix, sample, k, nprobe, alpha)
         cpu_s = time.time() - t0
         cpu = dict(value=round(sample.shape[0] / cpu_s, 3), unit="queries/s", cores=1, kind="oracle",
                    sample=f"first {sample.shape[0]} of the {nq} queries, same index/nprobe/alpha, "
@@ -420,20 +496,26 @@ def main():
                                f"{spec.get('comps')} Gaussian components, IVF {nlist}, storage "
                                f"{cfg['storage']}, rotation {cfg['rotation']}",
                    "queries_per_step": nq, "k": k, "nprobe": nprobe, "significance": alpha,
-                   "recall_at_10": round(rec, 4), "parallelism": "single GPU"},
+                   "recall_at_10": round(rec, 4), "parallelism": "single GPU",
+                   **({"launches_per_step": launches, "queries_per_launch": bsz,
+                       "k": f"per query U{set(uneven['k'])}", "nprobe": "per query U{%d..%d}" % uneven["nprobe"],
+                       "fp8_prestage_dims": cfg.get("fp8", 0)} if uneven else {})},
         "full_d_scan": {"qps": round(full_qps, 1), "nprobe": full_best[0],
                         "recall_at_10": round(full_best[3], 4), "ms_per_step": round(full_ms, 4),
                         "scan_kernel_ms": round(full_scan_ms, 4),
                         "scan_achieved_GBs": round(full_scan_bytes / (full_scan_ms * 1e-3) / 1e9, 1)},
         "speedup_vs_full_d": round(qps / full_qps, 3),
+        "without_fp8_prestage": no_pre,
         "scan_variant_ms": variants,
         "scan_variant_tuned": {"waves_per_query": chosen[0], "lookahead": chosen[1]},
         "kernel_ms": {"rotation": round(kms[0] / max(1, kn[0]), 4),
                       "coarse": round(kms[1] / max(1, kn[1]), 4),
                       "select": round(kms[2] / max(1, kn[2]), 4), "scan": round(scan_ms, 4)},
-        "scan_stats": {"candidates": candidates, "refined": refined,
+        "scan_stats": {"candidates": candidates, "refined": refined, "prestage_reads": pre_reads,
+                       "prestage_pruned": pre_pruned,
                        "scanned_dim_ratio": round(slices / max(1, candidates * NB), 4),
-                       "bytes_vs_full_d": round(slices * slice_bytes / max(1, full_bytes_per_launch), 4)},
+                       "bytes_vs_full_d": round((slices * slice_bytes + pre_reads * 64) / launches
+                                                / max(1, full_bytes_per_launch), 4)},
         "roofline": roofline,
         "distance_error_vs_fp64": dist_err,
         "serve": serve,

@@ -83,12 +83,16 @@ typedef struct {
   int32_t calib_max_neg;  /* label-1 pairs kept per calibration query; 50 */
   ddc_dtype storage;      /* base storage format; DDC_F32 */
   ddc_rot rotation;       /* query rotation precision; DDC_ROT_F32 */
+  int32_t fp8_lead_dims;  /* 0, or 64: FP8 E4M3 codes of the leading 64 rotated dims (one scale
+                             per list tile of 64 vectors) give a first test stage over 64 dims
+                             before the stored-precision stages (needs dim >= 64); 0 */
   int64_t pca_sample;     /* PCA rows: all if n <= this, else a SplitMix64 sample; 1,000,000 */
   uint64_t seed;          /* SplitMix64 seed of every random choice in fit; 0 */
 } ddc_fit_params;
 
 /* Artifacts of a fitted index, host memory, for ddc_import / ddc_export.
- * Sizes: D = dim, S = ceil(D / delta_d) stages, S_t = S - 1 test stages. */
+ * Sizes: D = dim, S = ceil(D / delta_d) stages, T = S - 1 test stages, plus one (first in
+ * m and resid) when fp8_lead_dims = 64. */
 typedef struct {
   int64_t n;              /* base vectors */
   int32_t dim;            /* D */
@@ -98,6 +102,7 @@ typedef struct {
   int32_t lag_l;
   ddc_dtype storage;
   ddc_rot rotation;
+  int32_t fp8_lead_dims;  /* 0 or 64 (import encodes the codes from y) */
   double *mu;             /* [D]        centring mean (Sec. IV-B footnote) */
   double *rot;            /* [D x D]    R, rows = eigenvectors, largest eigenvalue first */
   double *lam;            /* [D]        eigenvalues (export only; may be NULL on import) */
@@ -106,8 +111,10 @@ typedef struct {
   float *y;               /* [n x D]    stored rotated base: values exactly representable in
                                          `storage` (import rounds anything else to nearest even) */
   int64_t n0;             /* label-0 calibration pairs */
-  double *m;              /* [S_t]      per-stage slope m_s (Sec. V-A: m = -w1/w2) */
-  double *resid;          /* [n0 x S_t] residuals g_s(j) = tau_j - m_s e_s(j) of the label-0 pairs */
+  double *m;              /* [T]        per-stage slope m_s (Sec. V-A: m = -w1/w2) */
+  double *resid;          /* [n0 x T]   residuals g_s(j) = tau_j - m_s e_s(j) of the label-0 pairs */
+  uint8_t *codes8;        /* [n x 64]   export only, may be NULL: FP8 codes of vector i (by id) */
+  float *scale8;          /* [n]        export only, may be NULL: decode scale of vector i's tile */
 } ddc_artifacts;
 
 typedef struct {
@@ -118,6 +125,7 @@ typedef struct {
   int64_t n0;
   int64_t packed_bytes;   /* device bytes of the packed base */
   int64_t total_tiles;    /* 64-vector tiles over all lists */
+  int32_t fp8_lead_dims;  /* 0 or 64; n_test_stages counts the FP8 pre-stage when 64 */
 } ddc_index_info;
 
 /* Per-call counters of the scan (sums over all queries of the call). */
@@ -127,6 +135,8 @@ typedef struct {
   int64_t stage_slices;      /* sum over candidates of stages read (one stage = Delta_d dims) */
   int64_t bytes_touched;     /* algorithmic bytes of base data read by the scan */
   int64_t stage_stop[64];    /* candidates whose last stage read was s (0-based; S-1 = refined) */
+  int64_t prestage_reads;    /* candidates whose 64-byte FP8 slice was read (tested) */
+  int64_t prestage_pruned;   /* candidates the FP8 pre-stage pruned (not in stage_stop) */
 } ddc_search_stats;
 
 /* Fills *p with the defaults listed above. */
@@ -156,7 +166,8 @@ ddc_status ddc_calibrate(ddc_index *ix, const float *calib, int64_t n_calib, int
                          int32_t calib_nprobe, int32_t calib_max_neg, uint64_t seed);
 
 /* The correction table for a significance alpha = 1 - r (target recall r of label 0):
- * m_out[S_t] = m_s, beta_out[S_t] = beta_s(alpha) (FP64, -INFINITY when alpha = 0). */
+ * m_out[T] = m_s, beta_out[T] = beta_s(alpha) (FP64, -INFINITY when alpha = 0); T as in
+ * ddc_index_info.n_test_stages (the FP8 pre-stage first when present). */
 ddc_status ddc_correction(const ddc_index *ix, double significance, ddc_calib_mode mode,
                           double *m_out, double *beta_out);
 
@@ -178,7 +189,8 @@ ddc_status ddc_search_var(const ddc_index *ix, const float *queries, int64_t nq,
  * no host synchronisation.  d_queries [nq x dim]; d_k / d_nprobe: per-query arrays or NULL
  * to use k_all / nprobe_all; k_max / nprobe_max bound them; d_out_offsets: CSR as in
  * ddc_search_var or NULL for dense [nq x k_all]; d_ids int64 / d_dists float32 outputs;
- * d_counters: NULL or device int64[4 + 64] receiving ddc_search_stats' fields (added to). */
+ * d_counters: NULL or device int64[4 + 64 + 2] (added to): candidates, refined, stage
+ * slices, unused, stage_stop[64], prestage_reads, prestage_pruned. */
 ddc_status ddc_search_device(const ddc_index *ix, const float *d_queries, int64_t nq,
                              const int32_t *d_k, int32_t k_all, int32_t k_max,
                              const int32_t *d_nprobe, int32_t nprobe_all, int32_t nprobe_max,

@@ -31,15 +31,17 @@ class FitParams(C.Structure):
                 ("lag_l", C.c_int32), ("kmeans_iters", C.c_int32),
                 ("kmeans_train_per_list", C.c_int32), ("calib_k", C.c_int32),
                 ("calib_nprobe", C.c_int32), ("calib_max_neg", C.c_int32), ("storage", C.c_int),
-                ("rotation", C.c_int), ("pca_sample", C.c_int64), ("seed", C.c_uint64)]
+                ("rotation", C.c_int), ("fp8_lead_dims", C.c_int32), ("pca_sample", C.c_int64),
+                ("seed", C.c_uint64)]
 
 
 class Artifacts(C.Structure):
     _fields_ = [("n", C.c_int64), ("dim", C.c_int32), ("nlist", C.c_int32), ("delta_d", C.c_int32),
                 ("block_b", C.c_int32), ("lag_l", C.c_int32), ("storage", C.c_int),
-                ("rotation", C.c_int), ("mu", C.c_void_p), ("rot", C.c_void_p), ("lam", C.c_void_p),
-                ("centroids", C.c_void_p), ("assign", C.c_void_p), ("y", C.c_void_p),
-                ("n0", C.c_int64), ("m", C.c_void_p), ("resid", C.c_void_p)]
+                ("rotation", C.c_int), ("fp8_lead_dims", C.c_int32), ("mu", C.c_void_p),
+                ("rot", C.c_void_p), ("lam", C.c_void_p), ("centroids", C.c_void_p),
+                ("assign", C.c_void_p), ("y", C.c_void_p), ("n0", C.c_int64), ("m", C.c_void_p),
+                ("resid", C.c_void_p), ("codes8", C.c_void_p), ("scale8", C.c_void_p)]
 
 
 class IndexInfo(C.Structure):
@@ -47,16 +49,18 @@ class IndexInfo(C.Structure):
                 ("nlist", C.c_int32), ("delta_d", C.c_int32), ("n_stages", C.c_int32),
                 ("n_test_stages", C.c_int32), ("block_b", C.c_int32), ("lag_l", C.c_int32),
                 ("storage", C.c_int), ("rotation", C.c_int), ("n0", C.c_int64),
-                ("packed_bytes", C.c_int64), ("total_tiles", C.c_int64)]
+                ("packed_bytes", C.c_int64), ("total_tiles", C.c_int64), ("fp8_lead_dims", C.c_int32)]
 
 
 class SearchStats(C.Structure):
     _fields_ = [("candidates", C.c_int64), ("refined", C.c_int64), ("stage_slices", C.c_int64),
-                ("bytes_touched", C.c_int64), ("stage_stop", C.c_int64 * 64)]
+                ("bytes_touched", C.c_int64), ("stage_stop", C.c_int64 * 64),
+                ("prestage_reads", C.c_int64), ("prestage_pruned", C.c_int64)]
 
     def as_dict(self):
         return dict(candidates=self.candidates, refined=self.refined, stage_slices=self.stage_slices,
-                    bytes_touched=self.bytes_touched, stage_stop=list(self.stage_stop))
+                    bytes_touched=self.bytes_touched, stage_stop=list(self.stage_stop),
+                    prestage_reads=self.prestage_reads, prestage_pruned=self.prestage_pruned)
 
 
 class ServerParams(C.Structure):
@@ -179,7 +183,8 @@ class Index:
     @classmethod
     def from_artifacts(cls, art: dict) -> "Index":
         """art: mu, R (rows = eigenvectors), centroids, assign, y (stored rotated base), and
-        optionally m, resid (label-0 residual matrix), lam, storage, rotation, delta_d, block_b."""
+        optionally m, resid (label-0 residual matrix), lam, storage, rotation, delta_d, block_b,
+        fp8_lead_dims (0 or 64; the codes are encoded from y on import)."""
         mu = np.ascontiguousarray(art["mu"], np.float64)
         R = np.ascontiguousarray(art["R"], np.float64)
         cent = _f32(art["centroids"])
@@ -195,6 +200,7 @@ class Index:
         a.storage = DTYPE[st] if isinstance(st, str) else st
         rt = art.get("rotation", "f32")
         a.rotation = ROT[rt] if isinstance(rt, str) else rt
+        a.fp8_lead_dims = int(art.get("fp8_lead_dims", 0))
         keep = [mu, R, cent, assign, y]
         a.mu, a.rot, a.centroids, a.assign, a.y = (_ptr(x) for x in keep)
         lam = art.get("lam")
@@ -243,8 +249,13 @@ class Index:
         a.mu, a.rot, a.lam = _ptr(out["mu"]), _ptr(out["R"]), _ptr(out["lam"])
         a.centroids, a.assign, a.y = _ptr(out["centroids"]), _ptr(out["assign"]), _ptr(out["y"])
         a.m, a.resid = _ptr(out["m"]), _ptr(out["resid"])
+        if inf["fp8_lead_dims"]:
+            out["codes8"] = np.zeros((n, inf["fp8_lead_dims"]), np.uint8)
+            out["scale8"] = np.zeros(n, np.float32)
+            a.codes8, a.scale8 = _ptr(out["codes8"]), _ptr(out["scale8"])
         _check(load_library().ddc_export(self._h, C.byref(a)))
-        out.update(delta_d=a.delta_d, block_b=a.block_b, storage=a.storage, rotation=a.rotation)
+        out.update(delta_d=a.delta_d, block_b=a.block_b, storage=a.storage, rotation=a.rotation,
+                   fp8_lead_dims=a.fp8_lead_dims)
         return out
 
     def correction(self, alpha: float, mode: str = "joint"):

@@ -182,6 +182,12 @@ static void upload_index(ddc_index *ix, const float *d_Y, hipStream_t s) {
   const size_t packed = (size_t)ix->total_tiles * ix->NB * kTile * kBlockDims * ix->esize();
   ix->d_base.alloc(std::max<size_t>(packed, 16));
   launch_pack(d_Y, Dp, D, ix->NB, d_slot.as<int64_t>(), ix->total_tiles, ix->d_base.p, ix->store(), s);
+  if (ix->fp8) {
+    ix->d_base8.alloc(std::max<size_t>((size_t)ix->total_tiles * kTile * kFp8Lead, 16));
+    ix->d_scale8.alloc(std::max<size_t>((size_t)ix->total_tiles * 4, 16));
+    launch_encode_fp8(ix->d_base.p, ix->store(), ix->NB, ix->total_tiles, ix->d_base8.as<uint8_t>(),
+                      ix->d_scale8.as<float>(), s);
+  }
   HIPC(hipGetLastError());
   HIPC(hipStreamSynchronize(s));
 }
@@ -344,28 +350,44 @@ static void run_calibration(ddc_index *ix, const float *calib, int64_t nc, int k
   const int64_t npairs = (int64_t)pair_q.size();
   const int64_t n1 = npairs - n0;
 
-  // -- features e_s at every test stage (FP64)
-  std::vector<int32_t> send(St);
+  // -- features e_s at every test stage (FP64); with FP8 codes column 0 is the pre-stage's
+  // e_0 over the decoded lead dims, then the stored-precision stages
+  const int P = ix->P(), Tt = ix->Tt();
+  std::vector<int32_t> send(std::max(St, 1));
   for (int t = 0; t < St; ++t) send[t] = ((t + 1) * ix->delta_d) / kBlockDims;
-  std::vector<double> feat((size_t)npairs * std::max(St, 1));
-  if (St > 0) {
-    DevBuf d_pq(npairs * 4), d_ps(npairs * 8), d_se(St * 4), d_f((size_t)npairs * St * 8);
+  std::vector<double> feat((size_t)npairs * std::max(Tt, 1));
+  if (Tt > 0) {
+    DevBuf d_pq(npairs * 4), d_ps(npairs * 8), d_se(std::max(St, 1) * 4),
+        d_f((size_t)npairs * Tt * 8), d_f8(P ? (size_t)npairs * 8 : 8);
     HIPC(hipMemcpyAsync(d_pq.p, pair_q.data(), npairs * 4, hipMemcpyHostToDevice, s));
     HIPC(hipMemcpyAsync(d_ps.p, pair_slot.data(), npairs * 8, hipMemcpyHostToDevice, s));
-    HIPC(hipMemcpyAsync(d_se.p, send.data(), St * 4, hipMemcpyHostToDevice, s));
-    launch_features64(d_q64.as<double>(), D, ix->d_base.p, ix->store(), ix->NB, d_pq.as<int32_t>(),
-                      d_ps.as<int64_t>(), npairs, d_se.as<int32_t>(), St, d_f.as<double>(), s);
-    HIPC(hipMemcpyAsync(feat.data(), d_f.p, (size_t)npairs * St * 8, hipMemcpyDeviceToHost, s));
+    HIPC(hipMemcpyAsync(d_se.p, send.data(), std::max(St, 1) * 4, hipMemcpyHostToDevice, s));
+    if (St > 0)
+      launch_features64(d_q64.as<double>(), D, ix->d_base.p, ix->store(), ix->NB, d_pq.as<int32_t>(),
+                        d_ps.as<int64_t>(), npairs, d_se.as<int32_t>(), St, d_f.as<double>(), s);
+    std::vector<double> f8(P ? npairs : 0);
+    if (P) {
+      launch_features8(d_q64.as<double>(), D, ix->d_base8.as<uint8_t>(), ix->d_scale8.as<float>(),
+                       d_pq.as<int32_t>(), d_ps.as<int64_t>(), npairs, d_f8.as<double>(), 1, s);
+      HIPC(hipMemcpyAsync(f8.data(), d_f8.p, (size_t)npairs * 8, hipMemcpyDeviceToHost, s));
+    }
+    std::vector<double> fs((size_t)npairs * St);
+    if (St > 0)
+      HIPC(hipMemcpyAsync(fs.data(), d_f.p, (size_t)npairs * St * 8, hipMemcpyDeviceToHost, s));
     HIPC(hipStreamSynchronize(s));
+    for (int64_t p = 0; p < npairs; ++p) {
+      if (P) feat[(size_t)p * Tt] = f8[p];
+      for (int t = 0; t < St; ++t) feat[(size_t)p * Tt + P + t] = fs[(size_t)p * St + t];
+    }
   }
   HIPC(hipGetLastError());
 
   // -- per stage logistic regression -> m_s ; residuals of label 0
-  std::vector<double> m(St, 1.0);
-  for (int t = 0; t < St && n1 > 0; ++t) {
+  std::vector<double> m(Tt, 1.0);
+  for (int t = 0; t < Tt && n1 > 0; ++t) {
     std::vector<double> F((size_t)npairs * 2), y(npairs);
     for (int64_t p = 0; p < npairs; ++p) {
-      F[2 * p] = feat[(size_t)p * St + t];
+      F[2 * p] = feat[(size_t)p * Tt + t];
       F[2 * p + 1] = pair_tau[p];
       y[p] = p < n0 ? 0.0 : 1.0;
     }
@@ -373,9 +395,9 @@ static void run_calibration(ddc_index *ix, const float *calib, int64_t nc, int k
     logistic_fit(F, y, b, w1, w2);
     if (w2 < 0 && -w1 / w2 > 0) m[t] = -w1 / w2;
   }
-  std::vector<double> G((size_t)n0 * St);
+  std::vector<double> G((size_t)n0 * Tt);
   for (int64_t j = 0; j < n0; ++j)
-    for (int t = 0; t < St; ++t) G[(size_t)j * St + t] = pair_tau[j] - m[t] * feat[(size_t)j * St + t];
+    for (int t = 0; t < Tt; ++t) G[(size_t)j * Tt + t] = pair_tau[j] - m[t] * feat[(size_t)j * Tt + t];
   {
     std::lock_guard<std::mutex> lk(ix->beta_mtx);
     ix->m = m;
@@ -390,7 +412,7 @@ static std::vector<double> get_beta(ddc_index *ix, double alpha, int mode) {
   auto key = std::make_pair(alpha, mode);
   auto it = ix->beta_cache.find(key);
   if (it != ix->beta_cache.end()) return it->second;
-  auto b = beta_for_alpha(ix->resid, ix->n0, ix->St, alpha, mode);
+  auto b = beta_for_alpha(ix->resid, ix->n0, ix->Tt(), alpha, mode);
   ix->beta_cache[key] = b;
   return b;
 }
@@ -423,13 +445,17 @@ void ddc::search_device(ddc_index *ix, const float *d_q, int64_t nq, const int32
   const int Dp = ix->Dp, D = ix->D;
   ScanArgs a{};
   a.prune = 0;
-  if (ix->St > 0) {
-    std::vector<double> mm(ix->St), bb(ix->St);
+  const int P = ix->P(), Tt = ix->Tt();
+  if (Tt > 0) {
+    std::vector<double> mm(Tt), bb(Tt);
+    bool pre = false;
     if (mode == DDC_CORR_LEARNED && alpha > 0) {
       mm = ix->m;
       bb = get_beta(ix, alpha, DDC_CALIB_JOINT);
       a.prune = 1;
-    } else if (mode == DDC_CORR_LOSSLESS) {
+      pre = P != 0;
+    } else if (mode == DDC_CORR_LOSSLESS && ix->St > 0) {
+      // the FP8 estimate is no lower bound of the stored-value distance: no pre-stage here
       std::fill(mm.begin(), mm.end(), 1.0);
       std::fill(bb.begin(), bb.end(), 0.0);
       a.prune = 1;
@@ -438,9 +464,16 @@ void ddc::search_device(ddc_index *ix, const float *d_q, int64_t nq, const int32
       for (int t = 0; t < ix->St; ++t) {
         const int b = ((t + 1) * ix->delta_d) / kBlockDims - 1;
         a.test_after[b] = 1;
-        a.m[b] = (float)mm[t];
-        a.beta[b] = (float)bb[t];
+        a.m[b] = (float)mm[P + t];
+        a.beta[b] = (float)bb[P + t];
       }
+    if (pre) {
+      a.pre = 1;
+      a.pre_m = (float)mm[0];
+      a.pre_beta = (float)bb[0];
+      a.base8 = ix->d_base8.as<uint8_t>();
+      a.scale8 = ix->d_scale8.as<float>();
+    }
   }
   const int64_t chunk = 32768;
   for (int64_t q0 = 0; q0 < nq; q0 += chunk) {
@@ -502,8 +535,10 @@ static void stats_from_counters(const ddc_index *ix, const int64_t *c, ddc_searc
   st->candidates = c[0];
   st->refined = c[1];
   st->stage_slices = c[2];
-  st->bytes_touched = c[2] * (int64_t)kBlockDims * ix->esize();
+  st->bytes_touched = c[2] * (int64_t)kBlockDims * ix->esize() + c[kCtrPreReads] * kFp8Lead;
   for (int i = 0; i < 64; ++i) st->stage_stop[i] = c[4 + i];
+  st->prestage_reads = c[kCtrPreReads];
+  st->prestage_pruned = c[kCtrPrePruned];
 }
 
 // ---------------------------------------------------------------------------------------
@@ -515,7 +550,7 @@ static ddc_status check_search_args(const ddc_index *ix, int64_t nq, double alph
   if (!(alpha >= 0.0 && alpha < 1.0)) return set_err(DDC_EINVAL, "significance must be in [0, 1)");
   if (mode != DDC_CORR_LEARNED && mode != DDC_CORR_LOSSLESS && mode != DDC_CORR_NONE)
     return set_err(DDC_EINVAL, "unknown correction mode %d", (int)mode);
-  if (mode == DDC_CORR_LEARNED && alpha > 0 && ix->St > 0 && ix->n0 == 0)
+  if (mode == DDC_CORR_LEARNED && alpha > 0 && ix->Tt() > 0 && ix->n0 == 0)
     return set_err(DDC_EINVAL, "index has no calibrated correction table (use LOSSLESS/NONE or calibrate)");
   return DDC_OK;
 }
@@ -542,13 +577,15 @@ static ddc_status check_params(const ddc_fit_params *p, int64_t n, int dim) {
   if (p->storage != DDC_F32 && p->storage != DDC_F16 && p->storage != DDC_BF16) return set_err(DDC_EINVAL, "bad storage");
   if (p->rotation != DDC_ROT_F32 && p->rotation != DDC_ROT_BF16) return set_err(DDC_EINVAL, "bad rotation");
   if (p->pca_sample < 2) return set_err(DDC_EINVAL, "pca_sample must be >= 2");
+  if (p->fp8_lead_dims != 0 && p->fp8_lead_dims != kFp8Lead) return set_err(DDC_EINVAL, "fp8_lead_dims must be 0 or 64");
+  if (p->fp8_lead_dims && dim < kFp8Lead) return set_err(DDC_EINVAL, "the FP8 pre-stage needs dim >= 64");
   return DDC_OK;
 }
 
 static void init_sizes(ddc_index *ix, int64_t n, int D, int nlist, int dd, int B, int L, ddc_dtype st,
-                       ddc_rot rot) {
+                       ddc_rot rot, int fp8) {
   ix->n = n; ix->D = D; ix->nlist = nlist; ix->delta_d = dd; ix->B = B; ix->L = L;
-  ix->storage = st; ix->rot = rot;
+  ix->storage = st; ix->rot = rot; ix->fp8 = fp8;
   ix->NB = (D + kBlockDims - 1) / kBlockDims;
   ix->Dp = ix->NB * kBlockDims;
   ix->S = stage_count(D, dd);
@@ -588,7 +625,8 @@ ddc_status ddc_index_get_info(const ddc_index *ix, ddc_index_info *info) {
   if (!ix || !info) return set_err(DDC_EINVAL, "NULL argument");
   std::memset(info, 0, sizeof *info);
   info->n = ix->n; info->dim = ix->D; info->dim_padded = ix->Dp; info->nlist = ix->nlist;
-  info->delta_d = ix->delta_d; info->n_stages = ix->S; info->n_test_stages = ix->St;
+  info->delta_d = ix->delta_d; info->n_stages = ix->S; info->n_test_stages = ix->Tt();
+  info->fp8_lead_dims = ix->fp8;
   info->block_b = ix->B; info->lag_l = ix->L; info->storage = ix->storage; info->rotation = ix->rot;
   info->n0 = ix->n0; info->packed_bytes = (int64_t)ix->d_base.bytes; info->total_tiles = ix->total_tiles;
   return DDC_OK;
@@ -606,8 +644,10 @@ ddc_status ddc_import(const ddc_artifacts *a, ddc_index **out) {
   if (a->storage != DDC_F32 && a->storage != DDC_F16 && a->storage != DDC_BF16) return set_err(DDC_EINVAL, "bad storage");
   if (a->rotation != DDC_ROT_F32 && a->rotation != DDC_ROT_BF16) return set_err(DDC_EINVAL, "bad rotation");
   if (!a->mu || !a->rot || !a->centroids || !a->assign || !a->y) return set_err(DDC_EINVAL, "missing artifact array");
+  if (a->fp8_lead_dims != 0 && a->fp8_lead_dims != kFp8Lead) return set_err(DDC_EINVAL, "fp8_lead_dims must be 0 or 64");
+  if (a->fp8_lead_dims && a->dim < kFp8Lead) return set_err(DDC_EINVAL, "the FP8 pre-stage needs dim >= 64");
   const int D = a->dim;
-  const int St = stage_count(D, a->delta_d) - 1;
+  const int Tt = stage_count(D, a->delta_d) - 1 + (a->fp8_lead_dims ? 1 : 0);
   if (a->n0 < 0 || (a->n0 > 0 && (!a->m || !a->resid))) return set_err(DDC_EINVAL, "bad correction table");
   for (int64_t i = 0; i < a->n; ++i)
     if (a->assign[i] < 0 || a->assign[i] >= a->nlist) return set_err(DDC_EINVAL, "assign out of range at %lld", (long long)i);
@@ -615,15 +655,16 @@ ddc_status ddc_import(const ddc_artifacts *a, ddc_index **out) {
     return set_err(DDC_EINVAL, "non-finite values in y or centroids");
   GUARD_BEGIN
   std::unique_ptr<ddc_index> ix(new ddc_index);
-  init_sizes(ix.get(), a->n, D, a->nlist, a->delta_d, a->block_b, a->lag_l, a->storage, a->rotation);
+  init_sizes(ix.get(), a->n, D, a->nlist, a->delta_d, a->block_b, a->lag_l, a->storage, a->rotation,
+             a->fp8_lead_dims);
   ix->mu.assign(a->mu, a->mu + D);
   ix->R.assign(a->rot, a->rot + (size_t)D * D);
   if (a->lam) ix->lam.assign(a->lam, a->lam + D);
   ix->cent.assign(a->centroids, a->centroids + (size_t)a->nlist * D);
   ix->assign.assign(a->assign, a->assign + a->n);
   if (a->n0 > 0) {
-    ix->m.assign(a->m, a->m + St);
-    ix->resid.assign(a->resid, a->resid + (size_t)a->n0 * St);
+    ix->m.assign(a->m, a->m + Tt);
+    ix->resid.assign(a->resid, a->resid + (size_t)a->n0 * Tt);
     ix->n0 = a->n0;
   }
   StreamHolder sh;
@@ -647,6 +688,18 @@ ddc_status ddc_export(const ddc_index *ixc, ddc_artifacts *a) {
   const int D = ix->D;
   a->n = ix->n; a->dim = D; a->nlist = ix->nlist; a->delta_d = ix->delta_d; a->block_b = ix->B;
   a->lag_l = ix->L; a->storage = ix->storage; a->rotation = ix->rot; a->n0 = ix->n0;
+  a->fp8_lead_dims = ix->fp8;
+  if (ix->fp8 && (a->codes8 || a->scale8)) {
+    std::vector<uint8_t> c8((size_t)ix->total_tiles * kTile * kFp8Lead);
+    std::vector<float> s8(ix->total_tiles);
+    HIPC(hipMemcpy(c8.data(), ix->d_base8.p, c8.size(), hipMemcpyDeviceToHost));
+    HIPC(hipMemcpy(s8.data(), ix->d_scale8.p, s8.size() * 4, hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < ix->n; ++i) {
+      const int64_t slot = ix->id_to_slot[i];
+      if (a->codes8) std::memcpy(a->codes8 + (size_t)i * kFp8Lead, &c8[(size_t)slot * kFp8Lead], kFp8Lead);
+      if (a->scale8) a->scale8[i] = s8[slot / kTile];
+    }
+  }
   std::copy(ix->mu.begin(), ix->mu.end(), a->mu);
   std::copy(ix->R.begin(), ix->R.end(), a->rot);
   if (a->lam && !ix->lam.empty()) std::copy(ix->lam.begin(), ix->lam.end(), a->lam);
@@ -705,11 +758,11 @@ ddc_status ddc_correction(const ddc_index *ixc, double alpha, ddc_calib_mode mod
   if (!ixc || !m_out || !beta_out) return set_err(DDC_EINVAL, "NULL argument");
   if (!(alpha >= 0.0 && alpha < 1.0)) return set_err(DDC_EINVAL, "significance must be in [0, 1)");
   if (mode != DDC_CALIB_JOINT && mode != DDC_CALIB_BONFERRONI) return set_err(DDC_EINVAL, "bad calibration mode");
-  if (ixc->n0 == 0 && ixc->St > 0) return set_err(DDC_EINVAL, "index has no correction table");
+  if (ixc->n0 == 0 && ixc->Tt() > 0) return set_err(DDC_EINVAL, "index has no correction table");
   GUARD_BEGIN
   ddc_index *ix = const_cast<ddc_index *>(ixc);
   auto b = get_beta(ix, alpha, mode);
-  for (int t = 0; t < ix->St; ++t) { m_out[t] = ix->m[t]; beta_out[t] = b[t]; }
+  for (int t = 0; t < ix->Tt(); ++t) { m_out[t] = ix->m[t]; beta_out[t] = b[t]; }
   return DDC_OK;
   GUARD_END
 }
@@ -898,7 +951,7 @@ ddc_status ddc_scan_variant(ddc_index *ix, int64_t nq, int32_t k_max, int32_t np
                             ddc_corr mode, int32_t *waves, int32_t *lookahead) {
   if (!ix || !waves || !lookahead) return set_err(DDC_EINVAL, "NULL argument");
   if (nq < 1 || k_max < 1 || nprobe_max < 1) return set_err(DDC_EINVAL, "sizes must be >= 1");
-  const int prune = ix->St > 0 && mode != DDC_CORR_NONE;
+  const int prune = mode == DDC_CORR_LEARNED ? ix->Tt() > 0 : (mode == DDC_CORR_LOSSLESS && ix->St > 0);
   const int64_t nqc = std::min<int64_t>(nq, 32768);
   std::pair<int, int> v = fixed_variant(ix, nqc, prune);
   {
@@ -967,7 +1020,8 @@ extern "C" ddc_status ddc_fit(const float *base, int64_t n, int32_t dim, const f
     return set_err(DDC_EINVAL, "non-finite input values");
   GUARD_BEGIN
   std::unique_ptr<ddc_index> ix(new ddc_index);
-  init_sizes(ix.get(), n, dim, p->nlist, p->delta_d, p->block_b, p->lag_l, p->storage, p->rotation);
+  init_sizes(ix.get(), n, dim, p->nlist, p->delta_d, p->block_b, p->lag_l, p->storage, p->rotation,
+             p->fp8_lead_dims);
   const int D = dim, Dp = ix->Dp, nlist = p->nlist;
   StreamHolder sh;
   hipStream_t s = sh.s;

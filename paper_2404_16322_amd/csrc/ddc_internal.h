@@ -14,7 +14,10 @@ constexpr int kTile = 64;
 constexpr int kMaxBlocks = 128;      // D <= 4096
 constexpr int kMaxK = 256;
 constexpr int kScanThreads = 256;    // 4 wavefronts per query
-constexpr int kMaxCounters = 4 + 64; // candidates, refined, stage_slices, unused, stop[64]
+// counters: candidates, refined, stage_slices, unused, stop[64], pre-stage reads, pre-stage prunes
+constexpr int kCtrPreReads = 4 + 64, kCtrPrePruned = 4 + 64 + 1;
+constexpr int kMaxCounters = 4 + 64 + 2;
+constexpr int kFp8Lead = 64;          // dims covered by the FP8 pre-stage
 constexpr size_t kMaxLds = 160 * 1024;  // LDS per workgroup on gfx950
 
 enum StoreType : int { ST_F32 = 0, ST_F16 = 1, ST_BF16 = 2 };
@@ -39,6 +42,10 @@ struct ScanArgs {
   int64_t *counters;       // NULL or [kMaxCounters] (added to)
   const int32_t *order;    // NULL or [nq]: wave slot -> query (results do not depend on it)
   int32_t xcd_swizzle;     // 1: workgroup w runs slot range of XCD (w mod 8), contiguous per XCD
+  const uint8_t *base8;    // FP8 pre-stage codes: per tile 64 vectors x 64 B (NULL if none)
+  const float *scale8;     // per tile decode scale
+  int32_t pre;             // 1: run the FP8 pre-stage test m * e_0 + beta > tau first
+  float pre_m, pre_beta;
   int32_t waves_per_query; // 1 or 4 (result-invariant)
   int32_t lookahead;       // 0 or 1: multi-stage loads when few candidates survive (result-invariant)
   int32_t nq, nblocks, block_b, prune, nlist, k_max;
@@ -109,6 +116,15 @@ void launch_rotate64(const float *Q, int64_t nq, int32_t D, const double *mu, co
 void launch_refine64(const double *qrot, int32_t D, const void *base, int store, int32_t nblocks,
                      const int64_t *slots, int32_t nc, int64_t nq, double *out, hipStream_t s);
 // FP64 partial distances e_s after every test stage for (query, slot) pairs.
+// FP8 E4M3 codes of the leading 64 dims of every packed tile, one scale per tile
+// (max |y| / 448); codes: [tiles x 64 vectors x 64] bytes, scale: [tiles].
+void launch_encode_fp8(const void *base, int store, int32_t nblocks, int64_t total_tiles,
+                       uint8_t *codes, float *scale, hipStream_t s);
+// FP64 pre-stage feature e_0 = sum_{i<64} (q_i - dec_i)^2 of (query, packed slot) pairs,
+// dec = fp32(value(code) * scale).
+void launch_features8(const double *qrot, int32_t D, const uint8_t *codes, const float *scale,
+                      const int32_t *pair_q, const int64_t *pair_slot, int64_t npairs, double *out,
+                      int64_t out_stride, hipStream_t s);
 void launch_features64(const double *qrot, int32_t D, const void *base, int store, int32_t nblocks,
                        const int32_t *pair_q, const int64_t *pair_slot, int64_t npairs,
                        const int32_t *stage_end_block, int32_t n_test, double *out, hipStream_t s);

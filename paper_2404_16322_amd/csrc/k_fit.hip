@@ -233,4 +233,90 @@ void launch_pack(const float *Y, int64_t ldy, int32_t D, int32_t nblocks, const 
                      nblocks, slot_row, base, store);
 }
 
+// ---- FP8 E4M3 (OCP OFP8 v1.0: bias 7, no infinities, largest finite 448) ----------
+// Round to nearest, ties to even mantissa, saturating at +-448; sign from the sign bit.
+__device__ inline uint32_t e4m3_rne_sat(float v) {
+  const uint32_t sign = (__float_as_uint(v) >> 24) & 0x80u;
+  const float a = fabsf(v);
+  uint32_t code;
+  if (!(a < 464.f)) {
+    code = 0x7Eu;                                   // beyond halfway to 480: clamp to 448
+  } else if (a < 0.015625f) {
+    code = (uint32_t)rintf(a * 512.f);              // below 2^-6: subnormal steps of 2^-9
+  } else {
+    const int e = (int)((__float_as_uint(a) >> 23) & 0xFFu) - 127;   // a in [2^e, 2^(e+1))
+    const uint32_t n = (uint32_t)rintf(ldexpf(a, 3 - e));           // 8 .. 16
+    code = (uint32_t)(e + 7) * 8u + n - 8u;                          // 16 carries into e + 1
+  }
+  return min(code, 0x7Eu) | sign;
+}
+
+__device__ inline float packed_value(const void *base, int store, int32_t nblocks, int64_t tile,
+                                     int v, int dim) {
+  const int64_t idx = ((tile * nblocks + dim / kBlockDims) * kTile + v) * kBlockDims + dim % kBlockDims;
+  if (store == ST_F32) return reinterpret_cast<const float *>(base)[idx];
+  if (store == ST_F16) return __half2float(reinterpret_cast<const __half *>(base)[idx]);
+  return __uint_as_float((uint32_t)reinterpret_cast<const unsigned short *>(base)[idx] << 16);
+}
+
+// One wavefront per tile, lane = vector slot (padding slots hold zeros).
+__global__ void encode_fp8_kernel(const void *base, int store, int32_t nblocks, uint8_t *codes,
+                                  float *scale) {
+  const int64_t t = blockIdx.x;
+  const int v = threadIdx.x;
+  float amax = 0.f;
+  for (int d = 0; d < kFp8Lead; ++d) amax = fmaxf(amax, fabsf(packed_value(base, store, nblocks, t, v, d)));
+  for (int o = 32; o > 0; o >>= 1) amax = fmaxf(amax, __shfl_xor(amax, o));
+  const float sc = amax > 0.f ? amax / 448.f : 1.f;
+  uint32_t *out = reinterpret_cast<uint32_t *>(codes + (t * kTile + v) * kFp8Lead);
+  for (int d = 0; d < kFp8Lead; d += 4) {
+    uint32_t w = 0;
+    for (int e = 0; e < 4; ++e)
+      w |= e4m3_rne_sat(packed_value(base, store, nblocks, t, v, d + e) / sc) << (8 * e);
+    out[d / 4] = w;
+  }
+  if (v == 0) scale[t] = sc;
+}
+
+void launch_encode_fp8(const void *base, int store, int32_t nblocks, int64_t total_tiles,
+                       uint8_t *codes, float *scale, hipStream_t s) {
+  if (total_tiles <= 0) return;
+  hipLaunchKernelGGL(encode_fp8_kernel, dim3((unsigned)total_tiles), dim3(kTile), 0, s, base, store,
+                     nblocks, codes, scale);
+}
+
+// Value of an E4M3 code from the format's fields (exact in FP32).
+__device__ inline float e4m3_value(uint32_t c) {
+  const float sgn = (c & 0x80u) ? -1.f : 1.f;
+  const uint32_t e = (c >> 3) & 0xFu, m = c & 7u;
+  if (e == 0) return sgn * (float)m * 0.001953125f;            // m * 2^-9
+  return sgn * ldexpf(1.f + (float)m * 0.125f, (int)e - 7);
+}
+
+__global__ void features8_kernel(const double *qrot, int32_t D, const uint8_t *codes,
+                                 const float *scale, const int32_t *pair_q, const int64_t *pair_slot,
+                                 int64_t npairs, double *out, int64_t out_stride) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npairs) return;
+  const int64_t slot = pair_slot[p];
+  const double *q = qrot + (int64_t)pair_q[p] * D;
+  const float sc = scale[slot / kTile];
+  const uint8_t *c = codes + slot * kFp8Lead;
+  double acc = 0.0;
+  for (int i = 0; i < kFp8Lead; ++i) {
+    const float dec = e4m3_value(c[i]) * sc;
+    const double d = q[i] - (double)dec;
+    acc += d * d;
+  }
+  out[p * out_stride] = acc;
+}
+
+void launch_features8(const double *qrot, int32_t D, const uint8_t *codes, const float *scale,
+                      const int32_t *pair_q, const int64_t *pair_slot, int64_t npairs, double *out,
+                      int64_t out_stride, hipStream_t s) {
+  if (npairs <= 0) return;
+  hipLaunchKernelGGL(features8_kernel, dim3((unsigned)((npairs + 255) / 256)), dim3(256), 0, s, qrot,
+                     D, codes, scale, pair_q, pair_slot, npairs, out, out_stride);
+}
+
 }  // namespace ddc

@@ -107,6 +107,14 @@ template <int G> __device__ inline float transpose_sum(const float (&p)[G], int 
   return keep + dpp_xor1(send);
 }
 
+// Four FP8 E4M3 codes (byte k of w = element k) -> four floats, exact (gfx950 converts
+// the OCP E4M3 format in hardware, two codes per instruction).
+__device__ inline void e4m3x4_to_f32(uint32_t w, float *f) {
+  const auto lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)w, false);
+  const auto hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)w, true);
+  f[0] = lo[0]; f[1] = lo[1]; f[2] = hi[0]; f[3] = hi[1];
+}
+
 __device__ inline bool lex_less(float d, int32_t id, float td, int32_t tid) {
   return d < td || (d == td && id < tid);
 }
@@ -151,8 +159,9 @@ __host__ __device__ inline size_t scan_lds_bytes(int Dp, int kmax, int block_b, 
 
 // W waves per query (W = 1: four queries per workgroup, no workgroup barrier at all; W = 4:
 // one query per workgroup, each block's tiles split over the four waves, survivors merged
-// by the workgroup between two barriers).  LOOK enables the multi-stage look-ahead.
-template <int ST, bool PRUNE, bool LOOK, int W>
+// by the workgroup between two barriers).  LOOK enables the multi-stage look-ahead; PRE the
+// FP8 pre-stage over the leading 64 dims before the first stage.
+template <int ST, bool PRUNE, bool LOOK, int W, bool PRE>
 __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4, 8))) void scan_kernel(ScanArgs a) {
   using S = Store<ST>;
   constexpr int EPL = 16 / S::kBytes;          // elements per lane load
@@ -214,7 +223,7 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
   if (W > 1) __syncthreads(); else __builtin_amdgcn_wave_barrier();
 
   // statistics (wave-uniform, flushed once when counters are requested)
-  int64_t st_cand = 0, st_ref = 0, st_slices = 0;
+  int64_t st_cand = 0, st_ref = 0, st_slices = 0, st_pre = 0, st_pre_pruned = 0;
   unsigned long long *ctr = reinterpret_cast<unsigned long long *>(a.counters);
 
   int tin = 0, tn = 0, par = 0;
@@ -307,6 +316,61 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
         int cur = 0;
         int nalive = slen;
         st_cand += slen;
+        bool listed = false;   // the alive list holds pre-stage survivors (partial sums restart at 0)
+        if (PRE) {
+          // ---- FP8 pre-stage: one 64-byte code slice per candidate, decoded with the tile's
+          // scale; survivors go to the alive list and the stages start over at dim 0 ----
+          constexpr int G8 = 4, CPW8 = 16, CH8 = 4;   // 16 codes per lane, 16 candidates per load
+          const int g8 = lane & 3, sub8 = lane >> 2;
+          float q8[16];
+#pragma unroll
+          for (int e = 0; e < 16; ++e) q8[e] = s_q[g8 * 16 + e];
+          const int tile0 = a.tile_off[lst] + (bs + s0) / kTile;   // wave-uniform
+          int nn = 0;
+          for (int t0 = 0; t0 < slen; t0 += kTile) {
+            const int tile = tile0 + t0 / kTile;
+            const float sc = a.scale8[tile];
+            const unsigned char *p8 = a.base8 + (int64_t)tile * (kTile * kFp8Lead) + g8 * 16;
+            uint4 v[CH8];
+#pragma unroll
+            for (int c = 0; c < CH8; ++c)
+              v[c] = *reinterpret_cast<const uint4 *>(p8 + (c * CPW8 + sub8) * 64);
+            float part[CH8];
+#pragma unroll
+            for (int c = 0; c < CH8; ++c) {
+              const uint32_t w[4] = {v[c].x, v[c].y, v[c].z, v[c].w};
+              float acc = 0.f;
+#pragma unroll
+              for (int i = 0; i < 4; ++i) {
+                float f[4];
+                e4m3x4_to_f32(w[i], f);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                  const float d = f[e] * sc - q8[4 * i + e];
+                  acc = fmaf(d, d, acc);
+                }
+              }
+              part[c] = acc;
+            }
+            const float e0 = transpose_sum<G8>(part, g8);
+            const int idx = t0 + g8 * CPW8 + sub8;
+            const bool valid = idx < slen;
+            const bool prune = valid && fmaf(a.pre_m, e0, a.pre_beta) > tau;
+            const bool keep = valid && !prune;
+            const unsigned long long bal = __ballot(keep);
+            if (keep) {
+              const int pos = nn + __popcll(bal & lt);
+              s_ac[pos] = (uint16_t)idx;
+              s_ae[pos] = 0.f;
+            }
+            nn += __popcll(bal);
+            st_pre_pruned += __popcll(__ballot(prune));
+          }
+          st_pre += slen;
+          __builtin_amdgcn_wave_barrier();
+          nalive = nn;
+          listed = true;
+        }
         int b = 0;
         while (b < nb && nalive > 0) {
           int L = 1;
@@ -325,12 +389,13 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
             const int lgL = L == 8 ? 3 : (L == 4 ? 2 : 1);
             const uint16_t *alive = s_ac + cur * SEG;
             const float *alive_e = s_ae + cur * SEG;
-            const int first = b == 0 ? 0 : (int)alive[0];
+            const bool direct = b == 0 && !listed;
+            const int first = direct ? 0 : (int)alive[0];
             uint4 v[MAXCH];
 #pragma unroll
             for (int c = 0; c < MAXCH; ++c) {
               const int idx = (c >> lgL) * CPW + sub;
-              const int cd = idx < nalive ? (b == 0 ? idx : (int)alive[idx]) : first;
+              const int cd = idx < nalive ? (direct ? idx : (int)alive[idx]) : first;
               const int bb = min(b + (c & (L - 1)), nb - 1);
               const uint32_t off = (uint32_t)((cd / kTile) * nb + bb) * (uint32_t)BLOCK_BYTES +
                                    (uint32_t)((cd % kTile) * SLICE + g * 16);
@@ -355,10 +420,10 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
             const int idx = my_cc * CPW + sub;
             const bool valid = idx < nalive;
             const int ci = min(idx, SEG - 1);
-            const int cand = b == 0 ? idx : (int)alive[ci];
+            const int cand = direct ? idx : (int)alive[ci];
             // running partial distance, added one stage at a time in stage order: the same
             // rounding as the one-stage path, so the variant changes no result bit
-            float ev = my_ss == 0 ? (b == 0 ? tot : alive_e[ci] + tot) : tot;
+            float ev = my_ss == 0 ? (direct ? tot : alive_e[ci] + tot) : tot;
             for (int j = 1; j < L; ++j) {
               const float prev = __shfl_up(ev, 1);
               if (my_ss == j) ev = prev + ev;
@@ -411,15 +476,16 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
           const unsigned char *bp = bbase + b * BLOCK_BYTES + g * 16;
           const uint16_t *alive = s_ac + cur * SEG;
           const float *alive_e = s_ae + cur * SEG;
+          const bool direct = b == 0 && !listed;
           int nnext = 0;
           int pruned = 0;
           for (int t0 = 0; t0 < nalive; t0 += GROUP) {
-            const int first = b == 0 ? t0 : (int)alive[t0];
+            const int first = direct ? t0 : (int)alive[t0];
             uint4 v[MAXCH];
 #pragma unroll
             for (int c = 0; c < MAXCH; ++c) {
               const int idx = t0 + c * CPW + sub;
-              const int cd = idx < nalive ? (b == 0 ? idx : (int)alive[idx]) : first;
+              const int cd = idx < nalive ? (direct ? idx : (int)alive[idx]) : first;
               const uint32_t off = (uint32_t)(cd / kTile) * nb * (uint32_t)BLOCK_BYTES +
                                    (uint32_t)((cd % kTile) * SLICE);
               v[c] = *reinterpret_cast<const uint4 *>(bp + off);
@@ -441,8 +507,8 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
             const int idx = t0 + g * CPW + sub;
             const bool valid = idx < nalive;
             const int ci = min(idx, SEG - 1);
-            const int cand = b == 0 ? idx : (int)alive[ci];
-            const float ev = b == 0 ? tot : alive_e[ci] + tot;
+            const int cand = direct ? idx : (int)alive[ci];
+            const float ev = direct ? tot : alive_e[ci] + tot;
             bool keep = valid;
             if (test) keep = keep && !(fmaf(mb, ev, bb) > tau);
             if (last) {
@@ -539,6 +605,10 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
     atomicAdd(&ctr[0], (unsigned long long)st_cand);
     atomicAdd(&ctr[1], (unsigned long long)st_ref);
     atomicAdd(&ctr[2], (unsigned long long)st_slices);
+    if (PRE) {
+      atomicAdd(&ctr[kCtrPreReads], (unsigned long long)st_pre);
+      atomicAdd(&ctr[kCtrPrePruned], (unsigned long long)st_pre_pruned);
+    }
   }
 }
 
@@ -590,12 +660,12 @@ void launch_query_order(const int32_t *probes, int32_t p_stride, int64_t nq, int
                      order);
 }
 
-template <int ST, bool P, bool LK, int W>
+template <int ST, bool P, bool LK, int W, bool PRE = false>
 static void launch_variant(const ScanArgs &a, hipStream_t s) {
   const size_t smem = scan_lds_bytes(a.nblocks * kBlockDims, a.k_max, a.block_b, W);
   if (smem > kMaxLds) throw std::runtime_error("scan: LDS request exceeds 160 KiB");
   const int qpw = 4 / W;
-  hipLaunchKernelGGL((scan_kernel<ST, P, LK, W>), dim3((unsigned)((a.nq + qpw - 1) / qpw)),
+  hipLaunchKernelGGL((scan_kernel<ST, P, LK, W, PRE>), dim3((unsigned)((a.nq + qpw - 1) / qpw)),
                      dim3(kScanThreads), smem, s, a);
 }
 
@@ -603,6 +673,12 @@ template <int ST> static void launch_store(const ScanArgs &a, hipStream_t s) {
   const bool w4 = a.waves_per_query == 4;
   if (!a.prune) {
     if (w4) launch_variant<ST, false, false, 4>(a, s); else launch_variant<ST, false, false, 1>(a, s);
+  } else if (a.pre) {
+    if (a.lookahead) {
+      if (w4) launch_variant<ST, true, true, 4, true>(a, s); else launch_variant<ST, true, true, 1, true>(a, s);
+    } else {
+      if (w4) launch_variant<ST, true, false, 4, true>(a, s); else launch_variant<ST, true, false, 1, true>(a, s);
+    }
   } else if (a.lookahead) {
     if (w4) launch_variant<ST, true, true, 4>(a, s); else launch_variant<ST, true, true, 1>(a, s);
   } else {
