@@ -675,9 +675,11 @@ def calibrate(Y, list_off, list_ids, centroids, mu, R, calib, bounds, calib_k=10
 # --------------------------------------------------------------------------------------
 
 def fit(base, calib, nlist, delta_d=32, storage="f32", kmeans_iters=25, calib_k=10,
-        calib_nprobe=None, B=256, L=0, seed=0, pca_sample=1_000_000, max_neg=50, fp8_lead=0):
+        calib_nprobe=None, B=256, L=0, seed=0, pca_sample=1_000_000, max_neg=50, fp8_lead=0,
+        calib_k_extra=()):
     """Projection + IVF lists + calibrated correction table for ``base``; ``fp8_lead`` = 64
-    adds the FP8 pre-stage over the leading 64 rotated dims."""
+    adds the FP8 pre-stage over the leading 64 rotated dims.  ``calib_k_extra`` adds one
+    table per further K_c (see ``table_for_k``)."""
     base = np.asarray(base)
     D = base.shape[1]
     pca = pca_fit(base, pca_sample, seed)
@@ -688,11 +690,31 @@ def fit(base, calib, nlist, delta_d=32, storage="f32", kmeans_iters=25, calib_k=
     if calib_nprobe is None:
         calib_nprobe = int(min(max(1, nlist // 8), 64))
     pre = fp8_encode_lead(Y, off, ids, fp8_lead) if fp8_lead else None
-    cal = calibrate(Y, off, ids, C, pca["mu"], pca["R"], calib, bounds, calib_k, calib_nprobe,
-                    B, L, seed, max_neg, pre_dec=pre["dec"] if pre else None)
+    tables = []
+    for kc in [calib_k, *calib_k_extra]:
+        cal = calibrate(Y, off, ids, C, pca["mu"], pca["R"], calib, bounds, kc, calib_nprobe,
+                        B, L, seed, max_neg, pre_dec=pre["dec"] if pre else None)
+        tables.append(dict(kc=kc, m=cal["m"], G=cal["G"], calib=cal))
+    cal = tables[0]["calib"]
     return dict(mu=pca["mu"], R=pca["R"], lam=pca["lam"], cov=pca["cov"], Y=Y, centroids=C,
                 assign=assign, list_off=off, list_ids=ids, bounds=bounds, m=cal["m"], G=cal["G"],
-                calib=cal, storage=storage, delta_d=delta_d, B=B, L=L, pre=pre)
+                calib=cal, storage=storage, delta_d=delta_d, B=B, L=L, pre=pre,
+                tables=tables if len(tables) > 1 else None)
+
+
+def table_for_k(index, k):
+    """(m, G) of the correction table a search with K uses.  Reading: the paper trains with
+    the K nearest neighbours as label 0 and its threshold tau is the K-th distance; an index
+    calibrated at several K_c applies the table of the largest K_c <= K (the smallest K_c's
+    table when K is below all of them), so the label-0 semantics match the search's K."""
+    tabs = index.get("tables")
+    if not tabs:
+        return index["m"], index["G"]
+    best = tabs[0]
+    for t in tabs:
+        if t["kc"] <= k and t["kc"] >= best["kc"]:
+            best = t
+    return best["m"], best["G"]
 
 
 def search(index, queries, k, nprobe, alpha, mode="learned", B=None, L=None, calib_mode="joint"):
@@ -705,8 +727,8 @@ def search(index, queries, k, nprobe, alpha, mode="learned", B=None, L=None, cal
     pre_ix = index.get("pre")
     pre = None
     if mode == "learned":
-        m = index["m"]
-        beta = beta_for_alpha(index["G"], alpha, calib_mode)
+        m, G = table_for_k(index, k)
+        beta = beta_for_alpha(G, alpha, calib_mode)
         prune = alpha > 0
         if pre_ix is not None:     # the pre-stage is the first test stage of the table
             pre = (pre_ix["dec"], float(m[0]), float(beta[0]))
@@ -750,8 +772,8 @@ def false_prune_rate(index, queries, k, alpha, calib_mode="joint"):
     per-query miss counts for a query-level bootstrap."""
     bounds = index["bounds"]
     St = bounds.shape[0] - 1
-    m = index["m"]
-    beta = beta_for_alpha(index["G"], alpha, calib_mode)
+    m, G = table_for_k(index, k)
+    beta = beta_for_alpha(G, alpha, calib_mode)
     pre = index.get("pre")
     Qr = rotate(queries, index["mu"], index["R"])
     knn_ids, knn_d = bruteforce_knn(index["Y"], Qr, k)

@@ -531,3 +531,34 @@ def test_fp8_heldout_false_prune_rate_matches_significance(fp8_index, small_work
         lo, hi = np.quantile(boots, [0.005, 0.995])
         half = (hi - lo) / 2 * math.sqrt(2)
         assert abs(rate - a) <= half, (a, rate, half)
+
+
+# ----------------------------------------------------------------------------- tables per K_c
+
+@pytest.fixture(scope="module")
+def multi_k_index(small_workload):
+    w = small_workload
+    return O.fit(w["base"], w["calib"], nlist=64, kmeans_iters=25, calib_k=10, calib_nprobe=8,
+                 seed=7, calib_k_extra=(50,))
+
+
+def test_table_for_k_picks_largest_calibrated_k_not_above(multi_k_index):
+    ix = multi_k_index
+    t10, t50 = ix["tables"]
+    assert t10["kc"] == 10 and t50["kc"] == 50
+    assert t10["G"].shape[0] == 1000 * 10 and t50["G"].shape[0] == 1000 * 50
+    for k, want in [(1, t10), (10, t10), (49, t10), (50, t50), (100, t50)]:
+        m, G = O.table_for_k(ix, k)
+        assert m is want["m"] and G is want["G"]
+
+
+def test_table_at_k50_holds_significance_at_k50(multi_k_index, small_workload):
+    """Label 0 = the K nearest with tau = the K-th distance: the K_c = 50 table reaches alpha
+    for K = 50 searches on held-out queries (99% bootstrap interval, widened by sqrt 2)."""
+    rng = np.random.default_rng(11)
+    for a in [0.05, 0.1]:
+        rate, per_q = O.false_prune_rate(multi_k_index, small_workload["val"], 50, a)
+        boots = np.array([per_q[rng.integers(0, per_q.shape[0], per_q.shape[0])].mean() / 50
+                          for _ in range(2000)])
+        lo, hi = np.quantile(boots, [0.005, 0.995])
+        assert abs(rate - a) <= (hi - lo) / 2 * math.sqrt(2), (a, rate)
