@@ -401,7 +401,7 @@ def main():
     no_pre = None
     if cfg.get("fp8"):
         e = ix.export()
-        art = dict(e, fp8_lead_dims=0, resid=None, m=None)
+        art = dict(e, fp8_lead_dims=0, resid=None, m=None, tables=None)
         ix_main = ix
         ix = Index.from_artifacts(art)
         ix.calibrate(w["calib"], seed=spec["cfg"])
@@ -464,6 +464,8 @@ def main():
                    centroids=e["centroids"].astype(np.float64), m=e["m"], G=e["resid"], B=256, L=0,
                    bounds=oracle.stage_bounds(D, 32))
         oix["list_off"], oix["list_ids"] = oracle.build_lists(e["assign"], nlist)
+        if len(e["tables"]) > 1:
+            oix["tables"] = [dict(kc=t["kc"], m=t["m"], G=t["resid"]) for t in e["tables"]]
         if e.get("fp8_lead_dims"):
             oix["pre"] = oracle.fp8_encode_lead(oix["Y"], oix["list_off"], oix["list_ids"],
                                                 e["fp8_lead_dims"])

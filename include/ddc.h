@@ -78,9 +78,12 @@ typedef struct {
   int32_t lag_l;          /* tau lag L in blocks; 0 (only 0 is implemented on the GPU) */
   int32_t kmeans_iters;   /* Lloyd iterations; 25 */
   int32_t kmeans_train_per_list; /* k-means trains on <= this * nlist rows; 256 */
-  int32_t calib_k;        /* K_c of the label-0 pairs (KNN of each calibration query); 10 */
+  int32_t calib_k;        /* K_c of the label-0 pairs (KNN of each calibration query), 1..256; 10 */
   int32_t calib_nprobe;   /* N_probe of the label-1 query process; 0 = min(max(1,nlist/8),64) */
   int32_t calib_max_neg;  /* label-1 pairs kept per calibration query; 50 */
+  int32_t calib_k_extra[3]; /* further K_c values, ascending above calib_k, 0 = unused: one
+                             correction table per K_c; a search with K uses the table of the
+                             largest K_c <= K (calib_k's when K is smaller); {0, 0, 0} */
   ddc_dtype storage;      /* base storage format; DDC_F32 */
   ddc_rot rotation;       /* query rotation precision; DDC_ROT_F32 */
   int32_t fp8_lead_dims;  /* 0, or 64: FP8 E4M3 codes of the leading 64 rotated dims (one scale
@@ -110,9 +113,12 @@ typedef struct {
   int32_t *assign;        /* [n]        list of every base vector; lists keep ids ascending */
   float *y;               /* [n x D]    stored rotated base: values exactly representable in
                                          `storage` (import rounds anything else to nearest even) */
-  int64_t n0;             /* label-0 calibration pairs */
-  double *m;              /* [T]        per-stage slope m_s (Sec. V-A: m = -w1/w2) */
-  double *resid;          /* [n0 x T]   residuals g_s(j) = tau_j - m_s e_s(j) of the label-0 pairs */
+  int32_t n_tables;       /* correction tables, 0..4 (0: none) */
+  int32_t table_k[4];     /* their calibration K_c, ascending */
+  int64_t table_n0[4];    /* their label-0 pairs */
+  double *m;              /* [n_tables x T] per-stage slope m_s (Sec. V-A: m = -w1/w2) */
+  double *resid;          /* [sum n0 x T] residuals g_s(j) = tau_j - m_s e_s(j) of the label-0
+                             pairs, table after table */
   uint8_t *codes8;        /* [n x 64]   export only, may be NULL: FP8 codes of vector i (by id) */
   float *scale8;          /* [n]        export only, may be NULL: decode scale of vector i's tile */
 } ddc_artifacts;
@@ -122,10 +128,12 @@ typedef struct {
   int32_t dim, dim_padded, nlist, delta_d, n_stages, n_test_stages, block_b, lag_l;
   ddc_dtype storage;
   ddc_rot rotation;
-  int64_t n0;
+  int64_t n0;             /* label-0 pairs over all correction tables */
   int64_t packed_bytes;   /* device bytes of the packed base */
   int64_t total_tiles;    /* 64-vector tiles over all lists */
   int32_t fp8_lead_dims;  /* 0 or 64; n_test_stages counts the FP8 pre-stage when 64 */
+  int32_t n_tables;       /* correction tables and their calibration K_c */
+  int32_t table_k[4];
 } ddc_index_info;
 
 /* Per-call counters of the scan (sums over all queries of the call). */
@@ -150,8 +158,8 @@ ddc_status ddc_fit(const float *base, int64_t n, int32_t dim, const float *calib
                    int64_t n_calib, const ddc_fit_params *p, ddc_index **out);
 
 /* Build an index from artifacts (e.g. another implementation's fit).  Every array
- * in `a` is read, none is kept.  resid/m may be NULL with n0 = 0 (then only LOSSLESS and
- * NONE searches, or a later ddc_calibrate, are possible). */
+ * in `a` is read, none is kept.  resid/m may be NULL with n_tables = 0 (then only LOSSLESS
+ * and NONE searches, or a later ddc_calibrate, are possible). */
 ddc_status ddc_import(const ddc_artifacts *a, ddc_index **out);
 
 /* Copy the artifacts out.  The caller allocates every array of `a` with the sizes from
@@ -160,15 +168,22 @@ ddc_status ddc_export(const ddc_index *ix, ddc_artifacts *a);
 
 ddc_status ddc_index_get_info(const ddc_index *ix, ddc_index_info *info);
 
+/* Write the index to a file (its artifacts: rotation, centroids, lists, stored base,
+ * correction tables; FP8 codes are re-encoded on load) / build an index from such a file.
+ * DDC_EIO on any file error, a foreign or truncated file, or a checksum mismatch. */
+ddc_status ddc_save(const ddc_index *ix, const char *path);
+ddc_status ddc_load(const char *path, ddc_index **out);
+
 /* Re-run the calibration of Sec. V-A on new training queries (e.g. ~100 out-of-distribution
- * queries, Sec. V-C) and replace the index's correction table.  calib: host [n_calib x dim]. */
+ * queries, Sec. V-C) and replace the index's correction tables: one table at K_c = calib_k,
+ * or, with calib_k = 0, one at every K_c the index has now.  calib: host [n_calib x dim]. */
 ddc_status ddc_calibrate(ddc_index *ix, const float *calib, int64_t n_calib, int32_t calib_k,
                          int32_t calib_nprobe, int32_t calib_max_neg, uint64_t seed);
 
-/* The correction table for a significance alpha = 1 - r (target recall r of label 0):
- * m_out[T] = m_s, beta_out[T] = beta_s(alpha) (FP64, -INFINITY when alpha = 0); T as in
- * ddc_index_info.n_test_stages (the FP8 pre-stage first when present). */
-ddc_status ddc_correction(const ddc_index *ix, double significance, ddc_calib_mode mode,
+/* The correction a search with K uses for a significance alpha = 1 - r (target recall r of
+ * label 0): m_out[T] = m_s, beta_out[T] = beta_s(alpha) (FP64, -INFINITY when alpha = 0); T as
+ * in ddc_index_info.n_test_stages (the FP8 pre-stage first when present). */
+ddc_status ddc_correction(const ddc_index *ix, int32_t k, double significance, ddc_calib_mode mode,
                           double *m_out, double *beta_out);
 
 /* Search, host buffers.  queries: [nq x dim]; ids/dists: [nq x k].

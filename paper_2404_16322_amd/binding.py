@@ -23,14 +23,15 @@ SYMBOLS = ["ddc_fit_params_default", "ddc_fit", "ddc_import", "ddc_export", "ddc
            "ddc_debug_intermediates", "ddc_set_kernel_timing", "ddc_get_kernel_timing", "ddc_free",
            "ddc_last_error", "ddc_server_create", "ddc_server_submit", "ddc_server_poll",
            "ddc_server_get_stats", "ddc_server_destroy", "ddc_set_launch", "ddc_get_launch",
-           "ddc_scan_variant"]
+           "ddc_scan_variant", "ddc_save", "ddc_load"]
 
 
 class FitParams(C.Structure):
     _fields_ = [("nlist", C.c_int32), ("delta_d", C.c_int32), ("block_b", C.c_int32),
                 ("lag_l", C.c_int32), ("kmeans_iters", C.c_int32),
                 ("kmeans_train_per_list", C.c_int32), ("calib_k", C.c_int32),
-                ("calib_nprobe", C.c_int32), ("calib_max_neg", C.c_int32), ("storage", C.c_int),
+                ("calib_nprobe", C.c_int32), ("calib_max_neg", C.c_int32),
+                ("calib_k_extra", C.c_int32 * 3), ("storage", C.c_int),
                 ("rotation", C.c_int), ("fp8_lead_dims", C.c_int32), ("pca_sample", C.c_int64),
                 ("seed", C.c_uint64)]
 
@@ -40,7 +41,8 @@ class Artifacts(C.Structure):
                 ("block_b", C.c_int32), ("lag_l", C.c_int32), ("storage", C.c_int),
                 ("rotation", C.c_int), ("fp8_lead_dims", C.c_int32), ("mu", C.c_void_p),
                 ("rot", C.c_void_p), ("lam", C.c_void_p), ("centroids", C.c_void_p),
-                ("assign", C.c_void_p), ("y", C.c_void_p), ("n0", C.c_int64), ("m", C.c_void_p),
+                ("assign", C.c_void_p), ("y", C.c_void_p), ("n_tables", C.c_int32),
+                ("table_k", C.c_int32 * 4), ("table_n0", C.c_int64 * 4), ("m", C.c_void_p),
                 ("resid", C.c_void_p), ("codes8", C.c_void_p), ("scale8", C.c_void_p)]
 
 
@@ -49,7 +51,8 @@ class IndexInfo(C.Structure):
                 ("nlist", C.c_int32), ("delta_d", C.c_int32), ("n_stages", C.c_int32),
                 ("n_test_stages", C.c_int32), ("block_b", C.c_int32), ("lag_l", C.c_int32),
                 ("storage", C.c_int), ("rotation", C.c_int), ("n0", C.c_int64),
-                ("packed_bytes", C.c_int64), ("total_tiles", C.c_int64), ("fp8_lead_dims", C.c_int32)]
+                ("packed_bytes", C.c_int64), ("total_tiles", C.c_int64), ("fp8_lead_dims", C.c_int32),
+                ("n_tables", C.c_int32), ("table_k", C.c_int32 * 4)]
 
 
 class SearchStats(C.Structure):
@@ -108,7 +111,7 @@ def load_library():
         lib.ddc_export.argtypes = [vp, C.POINTER(Artifacts)]
         lib.ddc_index_get_info.argtypes = [vp, C.POINTER(IndexInfo)]
         lib.ddc_calibrate.argtypes = [vp, vp, i64, i32, i32, i32, C.c_uint64]
-        lib.ddc_correction.argtypes = [vp, f64, C.c_int, vp, vp]
+        lib.ddc_correction.argtypes = [vp, i32, f64, C.c_int, vp, vp]
         lib.ddc_search.argtypes = [vp, vp, i64, i32, i32, f64, C.c_int, vp, vp, C.POINTER(SearchStats)]
         lib.ddc_search_var.argtypes = [vp, vp, i64, vp, vp, f64, C.c_int, vp, vp, vp,
                                        C.POINTER(SearchStats)]
@@ -117,6 +120,8 @@ def load_library():
         lib.ddc_debug_intermediates.argtypes = [vp, vp, i64, i32, vp, vp]
         lib.ddc_set_kernel_timing.argtypes = [vp, C.c_int]
         lib.ddc_get_kernel_timing.argtypes = [vp, vp, vp, C.c_int]
+        lib.ddc_save.argtypes = [vp, C.c_char_p]
+        lib.ddc_load.argtypes = [C.c_char_p, C.POINTER(vp)]
         lib.ddc_set_launch.argtypes = [vp, C.POINTER(LaunchParams)]
         lib.ddc_get_launch.argtypes = [vp, C.POINTER(LaunchParams)]
         lib.ddc_scan_variant.argtypes = [vp, i64, i32, i32, C.c_int, C.POINTER(C.c_int32),
@@ -158,6 +163,8 @@ def default_params(**kw) -> FitParams:
             v = DTYPE[v] if isinstance(v, str) else v
         if k == "rotation":
             v = ROT[v] if isinstance(v, str) else v
+        if k == "calib_k_extra":
+            v = (C.c_int32 * 3)(*(list(v) + [0, 0, 0])[:3])
         if not hasattr(p, k):
             raise TypeError(f"unknown fit parameter {k}")
         setattr(p, k, v)
@@ -208,14 +215,29 @@ class Index:
             lam = np.ascontiguousarray(lam, np.float64)
             keep.append(lam)
             a.lam = _ptr(lam)
-        if art.get("resid") is not None:
-            m = np.ascontiguousarray(art["m"], np.float64)
-            G = np.ascontiguousarray(art["resid"], np.float64)
+        tabs = art.get("tables")
+        if tabs is None and art.get("resid") is not None:
+            tabs = [dict(kc=int(art.get("calib_k", 1)), m=art["m"], resid=art["resid"])]
+        if tabs:
+            m = np.ascontiguousarray(np.vstack([np.atleast_2d(t["m"]) for t in tabs]), np.float64)
+            G = np.ascontiguousarray(np.vstack([t["resid"] for t in tabs]), np.float64)
             keep += [m, G]
-            a.m, a.resid, a.n0 = _ptr(m), _ptr(G), G.shape[0]
+            a.m, a.resid, a.n_tables = _ptr(m), _ptr(G), len(tabs)
+            for i, t in enumerate(tabs):
+                a.table_k[i] = int(t["kc"])
+                a.table_n0[i] = t["resid"].shape[0]
         h = C.c_void_p()
         _check(load_library().ddc_import(C.byref(a), C.byref(h)))
         return cls(h.value)
+
+    @classmethod
+    def load(cls, path: str) -> "Index":
+        h = C.c_void_p()
+        _check(load_library().ddc_load(os.fsencode(path), C.byref(h)))
+        return cls(h.value)
+
+    def save(self, path: str):
+        _check(load_library().ddc_save(self._h, os.fsencode(path)))
 
     def close(self):
         if self._h is not None and self._h.value:
@@ -236,7 +258,9 @@ class Index:
     def info(self) -> dict:
         i = IndexInfo()
         _check(load_library().ddc_index_get_info(self._h, C.byref(i)))
-        return {f: getattr(i, f) for f, _ in IndexInfo._fields_}
+        out = {f: getattr(i, f) for f, _ in IndexInfo._fields_}
+        out["table_k"] = list(i.table_k)[:i.n_tables]
+        return out
 
     def export(self, with_base: bool = True) -> dict:
         inf = self.info()
@@ -248,20 +272,30 @@ class Index:
         a = Artifacts()
         a.mu, a.rot, a.lam = _ptr(out["mu"]), _ptr(out["R"]), _ptr(out["lam"])
         a.centroids, a.assign, a.y = _ptr(out["centroids"]), _ptr(out["assign"]), _ptr(out["y"])
-        a.m, a.resid = _ptr(out["m"]), _ptr(out["resid"])
+        nt = inf["n_tables"]
+        m_all, r_all = np.zeros((max(nt, 1), St)), np.zeros((n0, St))
+        a.m, a.resid = _ptr(m_all), _ptr(r_all)
         if inf["fp8_lead_dims"]:
             out["codes8"] = np.zeros((n, inf["fp8_lead_dims"]), np.uint8)
             out["scale8"] = np.zeros(n, np.float32)
             a.codes8, a.scale8 = _ptr(out["codes8"]), _ptr(out["scale8"])
         _check(load_library().ddc_export(self._h, C.byref(a)))
+        tabs, r0 = [], 0
+        for t in range(nt):
+            n0t = a.table_n0[t]
+            tabs.append(dict(kc=a.table_k[t], m=m_all[t].copy(), resid=r_all[r0:r0 + n0t].copy()))
+            r0 += n0t
+        if tabs:
+            out["m"], out["resid"], out["calib_k"] = tabs[0]["m"], tabs[0]["resid"], tabs[0]["kc"]
         out.update(delta_d=a.delta_d, block_b=a.block_b, storage=a.storage, rotation=a.rotation,
-                   fp8_lead_dims=a.fp8_lead_dims)
+                   fp8_lead_dims=a.fp8_lead_dims, tables=tabs)
         return out
 
-    def correction(self, alpha: float, mode: str = "joint"):
+    def correction(self, alpha: float, mode: str = "joint", k: int = 1):
+        """(m, beta) of the correction table a search with this K uses."""
         St = self.info()["n_test_stages"]
         m, b = np.zeros(St), np.zeros(St)
-        _check(load_library().ddc_correction(self._h, alpha, CALIB[mode], _ptr(m), _ptr(b)))
+        _check(load_library().ddc_correction(self._h, k, alpha, CALIB[mode], _ptr(m), _ptr(b)))
         return m, b
 
     def calibrate(self, calib, calib_k=10, calib_nprobe=0, max_neg=50, seed=0):
@@ -387,6 +421,15 @@ class Server:
         st = ServerStats()
         _check(load_library().ddc_server_get_stats(self._h, C.byref(st)))
         return {f: getattr(st, f) for f, _ in ServerStats._fields_}
+
+    @classmethod
+    def load(cls, path: str) -> "Index":
+        h = C.c_void_p()
+        _check(load_library().ddc_load(os.fsencode(path), C.byref(h)))
+        return cls(h.value)
+
+    def save(self, path: str):
+        _check(load_library().ddc_save(self._h, os.fsencode(path)))
 
     def close(self):
         if self._h is not None and self._h.value:

@@ -205,8 +205,8 @@ static bool all_finite(const float *x, int64_t cnt) {
 // Per test stage a logistic regression on (e_s, tau) gives m_s; the residuals
 // g_s = tau - m_s e_s of the label-0 pairs are kept for the target-recall adjustment.
 // ---------------------------------------------------------------------------------------
-static void run_calibration(ddc_index *ix, const float *calib, int64_t nc, int kc, int nprobe_c,
-                            int max_neg, uint64_t seed, hipStream_t s) {
+static ddc_index::Table run_calibration(ddc_index *ix, const float *calib, int64_t nc, int kc,
+                                        int nprobe_c, int max_neg, uint64_t seed, hipStream_t s) {
   const int D = ix->D, Dp = ix->Dp, St = ix->St;
   DevBuf d_c((size_t)nc * D * 4);
   HIPC(hipMemcpyAsync(d_c.p, calib, (size_t)nc * D * 4, hipMemcpyHostToDevice, s));
@@ -398,23 +398,76 @@ static void run_calibration(ddc_index *ix, const float *calib, int64_t nc, int k
   std::vector<double> G((size_t)n0 * Tt);
   for (int64_t j = 0; j < n0; ++j)
     for (int t = 0; t < Tt; ++t) G[(size_t)j * Tt + t] = pair_tau[j] - m[t] * feat[(size_t)j * Tt + t];
-  {
-    std::lock_guard<std::mutex> lk(ix->beta_mtx);
-    ix->m = m;
-    ix->resid = G;
-    ix->n0 = n0;
-    ix->beta_cache.clear();
-  }
+  ddc_index::Table tab;
+  tab.kc = kc;
+  tab.m = m;
+  tab.resid = G;
+  tab.n0 = n0;
+  return tab;
 }
 
-static std::vector<double> get_beta(ddc_index *ix, double alpha, int mode) {
+static void set_tables(ddc_index *ix, std::vector<ddc_index::Table> t) {
+  std::sort(t.begin(), t.end(), [](const ddc_index::Table &a, const ddc_index::Table &b) { return a.kc < b.kc; });
   std::lock_guard<std::mutex> lk(ix->beta_mtx);
-  auto key = std::make_pair(alpha, mode);
+  ix->tables = std::move(t);
+  ix->beta_cache.clear();
+  ix->tab_cache.clear();
+}
+
+// The table a search with K uses: the last (largest K_c) with K_c <= K, else the first.
+static int table_for_k(const ddc_index *ix, int k) {
+  int t = 0;
+  for (int i = 1; i < (int)ix->tables.size(); ++i)
+    if (ix->tables[i].kc <= k) t = i;
+  return t;
+}
+
+static std::vector<double> beta_locked(ddc_index *ix, double alpha, int mode, int t) {
+  auto key = std::make_tuple(alpha, mode, t);
   auto it = ix->beta_cache.find(key);
   if (it != ix->beta_cache.end()) return it->second;
-  auto b = beta_for_alpha(ix->resid, ix->n0, ix->Tt(), alpha, mode);
+  const auto &tb = ix->tables[t];
+  auto b = beta_for_alpha(tb.resid, tb.n0, ix->Tt(), alpha, mode);
   ix->beta_cache[key] = b;
   return b;
+}
+
+static std::vector<double> get_beta(ddc_index *ix, double alpha, int mode, int t) {
+  std::lock_guard<std::mutex> lk(ix->beta_mtx);
+  return beta_locked(ix, alpha, mode, t);
+}
+
+// Device copy of every table for one (alpha, correction mode): [ntab][NB + 1][2] (m, beta) per
+// dim block (beta = -inf where no test follows; entry NB = the FP8 pre-stage).
+static std::shared_ptr<DevBuf> device_tables(ddc_index *ix, double alpha, ddc_corr mode, int *ntab) {
+  std::lock_guard<std::mutex> lk(ix->beta_mtx);
+  const bool lossless = mode == DDC_CORR_LOSSLESS;
+  const auto key = std::make_pair(lossless ? -1.0 : alpha, (int)mode);
+  const int nt = lossless ? 1 : (int)ix->tables.size();
+  *ntab = nt;
+  auto it = ix->tab_cache.find(key);
+  if (it != ix->tab_cache.end()) return it->second;
+  const int NB = ix->NB, P = ix->P();
+  std::vector<float> h((size_t)nt * (NB + 1) * 2);
+  for (int t = 0; t < nt; ++t) {
+    float *row = &h[(size_t)t * (NB + 1) * 2];
+    for (int b = 0; b <= NB; ++b) { row[2 * b] = 0.f; row[2 * b + 1] = -INFINITY; }
+    std::vector<double> mm(ix->Tt(), 1.0), bb(ix->Tt(), 0.0);
+    if (!lossless) {
+      mm = ix->tables[t].m;
+      bb = beta_locked(ix, alpha, DDC_CALIB_JOINT, t);
+    }
+    for (int j = 0; j < ix->St; ++j) {
+      const int b = ((j + 1) * ix->delta_d) / kBlockDims - 1;
+      row[2 * b] = (float)mm[P + j];
+      row[2 * b + 1] = (float)bb[P + j];
+    }
+    if (P && !lossless) { row[2 * NB] = (float)mm[0]; row[2 * NB + 1] = (float)bb[0]; }
+  }
+  auto buf = std::make_shared<DevBuf>(h.size() * 4);
+  HIPC(hipMemcpy(buf->p, h.data(), h.size() * 4, hipMemcpyHostToDevice));
+  ix->tab_cache[key] = buf;
+  return buf;
 }
 
 // ---------------------------------------------------------------------------------------
@@ -445,32 +498,18 @@ void ddc::search_device(ddc_index *ix, const float *d_q, int64_t nq, const int32
   const int Dp = ix->Dp, D = ix->D;
   ScanArgs a{};
   a.prune = 0;
-  const int P = ix->P(), Tt = ix->Tt();
-  if (Tt > 0) {
-    std::vector<double> mm(Tt), bb(Tt);
-    bool pre = false;
-    if (mode == DDC_CORR_LEARNED && alpha > 0) {
-      mm = ix->m;
-      bb = get_beta(ix, alpha, DDC_CALIB_JOINT);
-      a.prune = 1;
-      pre = P != 0;
-    } else if (mode == DDC_CORR_LOSSLESS && ix->St > 0) {
-      // the FP8 estimate is no lower bound of the stored-value distance: no pre-stage here
-      std::fill(mm.begin(), mm.end(), 1.0);
-      std::fill(bb.begin(), bb.end(), 0.0);
-      a.prune = 1;
-    }
-    if (a.prune)
-      for (int t = 0; t < ix->St; ++t) {
-        const int b = ((t + 1) * ix->delta_d) / kBlockDims - 1;
-        a.test_after[b] = 1;
-        a.m[b] = (float)mm[P + t];
-        a.beta[b] = (float)bb[P + t];
-      }
-    if (pre) {
+  std::shared_ptr<DevBuf> tabs;   // keeps the device tables alive for this call
+  const bool learned = mode == DDC_CORR_LEARNED && alpha > 0 && ix->Tt() > 0;
+  // LOSSLESS tests e_s > tau with the stored values only: the FP8 estimate is no lower bound
+  const bool lossless = mode == DDC_CORR_LOSSLESS && ix->St > 0;
+  if (learned || lossless) {
+    a.prune = 1;
+    tabs = device_tables(ix, alpha, mode, &a.ntab);
+    a.tab = tabs->as<float>();
+    for (int t = 0; t < a.ntab; ++t) a.tab_k[t] = lossless ? 1 : ix->tables[t].kc;
+    for (int j = 0; j < ix->St; ++j) a.test_after[((j + 1) * ix->delta_d) / kBlockDims - 1] = 1;
+    if (learned && ix->P()) {
       a.pre = 1;
-      a.pre_m = (float)mm[0];
-      a.pre_beta = (float)bb[0];
       a.base8 = ix->d_base8.as<uint8_t>();
       a.scale8 = ix->d_scale8.as<float>();
     }
@@ -550,7 +589,7 @@ static ddc_status check_search_args(const ddc_index *ix, int64_t nq, double alph
   if (!(alpha >= 0.0 && alpha < 1.0)) return set_err(DDC_EINVAL, "significance must be in [0, 1)");
   if (mode != DDC_CORR_LEARNED && mode != DDC_CORR_LOSSLESS && mode != DDC_CORR_NONE)
     return set_err(DDC_EINVAL, "unknown correction mode %d", (int)mode);
-  if (mode == DDC_CORR_LEARNED && alpha > 0 && ix->Tt() > 0 && ix->n0 == 0)
+  if (mode == DDC_CORR_LEARNED && alpha > 0 && ix->Tt() > 0 && ix->tables.empty())
     return set_err(DDC_EINVAL, "index has no calibrated correction table (use LOSSLESS/NONE or calibrate)");
   return DDC_OK;
 }
@@ -571,7 +610,14 @@ static ddc_status check_params(const ddc_fit_params *p, int64_t n, int dim) {
   if (p->block_b < 64 || p->block_b > 1024 || p->block_b % 64) return set_err(DDC_EINVAL, "block_b must be a multiple of 64 in [64, 1024]");
   if (p->lag_l != 0) return set_err(DDC_EUNSUP, "only lag_l = 0 is implemented");
   if (p->kmeans_iters < 0 || p->kmeans_train_per_list < 1) return set_err(DDC_EINVAL, "bad k-means parameters");
-  if (p->calib_k < 1 || p->calib_k > 64) return set_err(DDC_EINVAL, "calib_k must be in [1, 64]");
+  if (p->calib_k < 1 || p->calib_k > kMaxK) return set_err(DDC_EINVAL, "calib_k must be in [1, 256]");
+  for (int i = 0, prev = p->calib_k; i < kMaxTables - 1; ++i) {
+    const int e = p->calib_k_extra[i];
+    if (e == 0) continue;
+    if (e <= prev || e > kMaxK) return set_err(DDC_EINVAL, "calib_k_extra must ascend above calib_k, <= 256");
+    if (i > 0 && p->calib_k_extra[i - 1] == 0) return set_err(DDC_EINVAL, "calib_k_extra: zeros only at the end");
+    prev = e;
+  }
   if (p->calib_nprobe < 0 || p->calib_nprobe > p->nlist) return set_err(DDC_EINVAL, "calib_nprobe must be in [0, nlist]");
   if (p->calib_max_neg < 1 || p->calib_max_neg > 256) return set_err(DDC_EINVAL, "calib_max_neg must be in [1, 256]");
   if (p->storage != DDC_F32 && p->storage != DDC_F16 && p->storage != DDC_BF16) return set_err(DDC_EINVAL, "bad storage");
@@ -597,6 +643,43 @@ static void init_sizes(ddc_index *ix, int64_t n, int D, int nlist, int dd, int B
 // ---------------------------------------------------------------------------------------
 // ABI
 // ---------------------------------------------------------------------------------------
+// ---- index file: "DDCINDEX", version, sizes, then the artifact arrays (little-endian, as
+// in memory), then a 64-bit FNV-1a checksum of everything before it --------------------------
+namespace {
+constexpr char kMagic[8] = {'D', 'D', 'C', 'I', 'N', 'D', 'E', 'X'};
+constexpr uint32_t kFileVersion = 1;
+
+struct Fnv {
+  uint64_t h = 1469598103934665603ull;
+  void add(const void *p, size_t n) {
+    const unsigned char *c = static_cast<const unsigned char *>(p);
+    for (size_t i = 0; i < n; ++i) { h ^= c[i]; h *= 1099511628211ull; }
+  }
+};
+
+struct Writer {
+  FILE *f;
+  Fnv sum;
+  void put(const void *p, size_t n) {
+    if (n && fwrite(p, 1, n, f) != n) throw DdcError(DDC_EIO, "write failed");
+    sum.add(p, n);
+  }
+  template <class T> void val(T v) { put(&v, sizeof v); }
+};
+
+struct Reader {
+  FILE *f;
+  Fnv sum;
+  void get(void *p, size_t n) {
+    if (n && fread(p, 1, n, f) != n) throw DdcError(DDC_EIO, "file truncated");
+    sum.add(p, n);
+  }
+  template <class T> T val() { T v; get(&v, sizeof v); return v; }
+};
+
+struct FileCloser { FILE *f; ~FileCloser() { if (f) fclose(f); } };
+}  // namespace
+
 extern "C" {
 
 const char *ddc_last_error(void) { return g_err.c_str(); }
@@ -628,7 +711,9 @@ ddc_status ddc_index_get_info(const ddc_index *ix, ddc_index_info *info) {
   info->delta_d = ix->delta_d; info->n_stages = ix->S; info->n_test_stages = ix->Tt();
   info->fp8_lead_dims = ix->fp8;
   info->block_b = ix->B; info->lag_l = ix->L; info->storage = ix->storage; info->rotation = ix->rot;
-  info->n0 = ix->n0; info->packed_bytes = (int64_t)ix->d_base.bytes; info->total_tiles = ix->total_tiles;
+  info->n0 = ix->n0_total(); info->packed_bytes = (int64_t)ix->d_base.bytes; info->total_tiles = ix->total_tiles;
+  info->n_tables = (int32_t)ix->tables.size();
+  for (size_t t = 0; t < ix->tables.size(); ++t) info->table_k[t] = ix->tables[t].kc;
   return DDC_OK;
 }
 
@@ -648,7 +733,12 @@ ddc_status ddc_import(const ddc_artifacts *a, ddc_index **out) {
   if (a->fp8_lead_dims && a->dim < kFp8Lead) return set_err(DDC_EINVAL, "the FP8 pre-stage needs dim >= 64");
   const int D = a->dim;
   const int Tt = stage_count(D, a->delta_d) - 1 + (a->fp8_lead_dims ? 1 : 0);
-  if (a->n0 < 0 || (a->n0 > 0 && (!a->m || !a->resid))) return set_err(DDC_EINVAL, "bad correction table");
+  if (a->n_tables < 0 || a->n_tables > kMaxTables) return set_err(DDC_EINVAL, "n_tables must be in [0, 4]");
+  for (int t = 0; t < a->n_tables; ++t) {
+    if (a->table_n0[t] < 1 || a->table_k[t] < 1 || (t > 0 && a->table_k[t] <= a->table_k[t - 1]))
+      return set_err(DDC_EINVAL, "bad correction table %d (n0 >= 1, K_c ascending)", t);
+  }
+  if (a->n_tables > 0 && (!a->m || !a->resid)) return set_err(DDC_EINVAL, "missing m/resid");
   for (int64_t i = 0; i < a->n; ++i)
     if (a->assign[i] < 0 || a->assign[i] >= a->nlist) return set_err(DDC_EINVAL, "assign out of range at %lld", (long long)i);
   if (!all_finite(a->y, a->n * D) || !all_finite(a->centroids, (int64_t)a->nlist * D))
@@ -662,10 +752,17 @@ ddc_status ddc_import(const ddc_artifacts *a, ddc_index **out) {
   if (a->lam) ix->lam.assign(a->lam, a->lam + D);
   ix->cent.assign(a->centroids, a->centroids + (size_t)a->nlist * D);
   ix->assign.assign(a->assign, a->assign + a->n);
-  if (a->n0 > 0) {
-    ix->m.assign(a->m, a->m + Tt);
-    ix->resid.assign(a->resid, a->resid + (size_t)a->n0 * Tt);
-    ix->n0 = a->n0;
+  {
+    std::vector<ddc_index::Table> tabs(a->n_tables);
+    size_t roff = 0;
+    for (int t = 0; t < a->n_tables; ++t) {
+      tabs[t].kc = a->table_k[t];
+      tabs[t].n0 = a->table_n0[t];
+      tabs[t].m.assign(a->m + (size_t)t * Tt, a->m + (size_t)(t + 1) * Tt);
+      tabs[t].resid.assign(a->resid + roff * Tt, a->resid + (roff + a->table_n0[t]) * Tt);
+      roff += a->table_n0[t];
+    }
+    set_tables(ix.get(), std::move(tabs));
   }
   StreamHolder sh;
   DevBuf d_Y((size_t)a->n * ix->Dp * 4);
@@ -682,12 +779,13 @@ ddc_status ddc_export(const ddc_index *ixc, ddc_artifacts *a) {
   if (!ixc || !a) return set_err(DDC_EINVAL, "NULL argument");
   ddc_index *ix = const_cast<ddc_index *>(ixc);
   if (!a->mu || !a->rot || !a->centroids || !a->assign) return set_err(DDC_EINVAL, "missing output array");
-  if (ix->n0 > 0 && (!a->m || !a->resid)) return set_err(DDC_EINVAL, "missing m/resid output");
+  if (!ix->tables.empty() && (!a->m || !a->resid)) return set_err(DDC_EINVAL, "missing m/resid output");
   GUARD_BEGIN
   DeviceGuard dg(ix->device);
   const int D = ix->D;
   a->n = ix->n; a->dim = D; a->nlist = ix->nlist; a->delta_d = ix->delta_d; a->block_b = ix->B;
-  a->lag_l = ix->L; a->storage = ix->storage; a->rotation = ix->rot; a->n0 = ix->n0;
+  a->lag_l = ix->L; a->storage = ix->storage; a->rotation = ix->rot;
+  a->n_tables = (int32_t)ix->tables.size();
   a->fp8_lead_dims = ix->fp8;
   if (ix->fp8 && (a->codes8 || a->scale8)) {
     std::vector<uint8_t> c8((size_t)ix->total_tiles * kTile * kFp8Lead);
@@ -705,9 +803,16 @@ ddc_status ddc_export(const ddc_index *ixc, ddc_artifacts *a) {
   if (a->lam && !ix->lam.empty()) std::copy(ix->lam.begin(), ix->lam.end(), a->lam);
   std::copy(ix->cent.begin(), ix->cent.end(), a->centroids);
   std::copy(ix->assign.begin(), ix->assign.end(), a->assign);
-  if (ix->n0 > 0) {
-    std::copy(ix->m.begin(), ix->m.end(), a->m);
-    std::copy(ix->resid.begin(), ix->resid.end(), a->resid);
+  {
+    size_t roff = 0;
+    for (size_t t = 0; t < ix->tables.size(); ++t) {
+      const auto &tb = ix->tables[t];
+      a->table_k[t] = tb.kc;
+      a->table_n0[t] = tb.n0;
+      std::copy(tb.m.begin(), tb.m.end(), a->m + t * ix->Tt());
+      std::copy(tb.resid.begin(), tb.resid.end(), a->resid + roff * ix->Tt());
+      roff += (size_t)tb.n0;
+    }
   }
   if (a->y) {
     const size_t per = (size_t)ix->NB * kTile * kBlockDims;
@@ -753,16 +858,111 @@ ddc_status ddc_export(const ddc_index *ixc, ddc_artifacts *a) {
   GUARD_END
 }
 
-ddc_status ddc_correction(const ddc_index *ixc, double alpha, ddc_calib_mode mode, double *m_out,
-                          double *beta_out) {
+
+ddc_status ddc_save(const ddc_index *ixc, const char *path) {
+  if (!ixc || !path) return set_err(DDC_EINVAL, "NULL argument");
+  GUARD_BEGIN
+  ddc_index *ix = const_cast<ddc_index *>(ixc);
+  const int D = ix->D, T = ix->Tt();
+  const int64_t n = ix->n, n0 = ix->n0_total();
+  const int nt = (int)ix->tables.size();
+  std::vector<double> mu(D), R((size_t)D * D), lam(D), m((size_t)std::max(nt, 1) * T), resid((size_t)n0 * T);
+  std::vector<float> cent((size_t)ix->nlist * D), y((size_t)n * D);
+  std::vector<int32_t> assign(n);
+  ddc_artifacts a{};
+  a.mu = mu.data(); a.rot = R.data(); a.lam = lam.data(); a.centroids = cent.data();
+  a.assign = assign.data(); a.y = y.data(); a.m = m.data(); a.resid = resid.data();
+  const ddc_status st = ddc_export(ixc, &a);
+  if (st != DDC_OK) return st;
+  FileCloser fc{fopen(path, "wb")};
+  if (!fc.f) return set_err(DDC_EIO, "cannot open %s for writing", path);
+  Writer w{fc.f};
+  w.put(kMagic, 8);
+  w.val<uint32_t>(kFileVersion);
+  w.val<int64_t>(n);
+  for (int32_t v : {D, ix->nlist, ix->delta_d, ix->B, ix->L, (int32_t)ix->storage, (int32_t)ix->rot, ix->fp8, nt})
+    w.val<int32_t>(v);
+  for (int t = 0; t < kMaxTables; ++t) w.val<int32_t>(t < nt ? a.table_k[t] : 0);
+  for (int t = 0; t < kMaxTables; ++t) w.val<int64_t>(t < nt ? a.table_n0[t] : 0);
+  const uint8_t has_lam = ix->lam.empty() ? 0 : 1;
+  w.val<uint8_t>(has_lam);
+  w.put(mu.data(), mu.size() * 8);
+  w.put(R.data(), R.size() * 8);
+  if (has_lam) w.put(lam.data(), lam.size() * 8);
+  w.put(cent.data(), cent.size() * 4);
+  w.put(assign.data(), assign.size() * 4);
+  w.put(y.data(), y.size() * 4);
+  w.put(m.data(), (size_t)nt * T * 8);
+  w.put(resid.data(), resid.size() * 8);
+  const uint64_t h = w.sum.h;
+  if (fwrite(&h, 1, 8, fc.f) != 8) throw DdcError(DDC_EIO, "write failed");
+  if (fflush(fc.f) != 0) throw DdcError(DDC_EIO, "write failed");
+  return DDC_OK;
+  GUARD_END
+}
+
+ddc_status ddc_load(const char *path, ddc_index **out) {
+  if (!out) return set_err(DDC_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!path) return set_err(DDC_EINVAL, "path is NULL");
+  GUARD_BEGIN
+  FileCloser fc{fopen(path, "rb")};
+  if (!fc.f) return set_err(DDC_EIO, "cannot open %s", path);
+  Reader r{fc.f};
+  char magic[8];
+  r.get(magic, 8);
+  if (std::memcmp(magic, kMagic, 8) != 0) return set_err(DDC_EIO, "%s is not an index file", path);
+  if (r.val<uint32_t>() != kFileVersion) return set_err(DDC_EIO, "unsupported index file version");
+  ddc_artifacts a{};
+  a.n = r.val<int64_t>();
+  a.dim = r.val<int32_t>(); a.nlist = r.val<int32_t>(); a.delta_d = r.val<int32_t>();
+  a.block_b = r.val<int32_t>(); a.lag_l = r.val<int32_t>();
+  a.storage = (ddc_dtype)r.val<int32_t>(); a.rotation = (ddc_rot)r.val<int32_t>();
+  a.fp8_lead_dims = r.val<int32_t>(); a.n_tables = r.val<int32_t>();
+  for (int t = 0; t < kMaxTables; ++t) a.table_k[t] = r.val<int32_t>();
+  int64_t n0 = 0;
+  for (int t = 0; t < kMaxTables; ++t) { a.table_n0[t] = r.val<int64_t>(); n0 += a.table_n0[t]; }
+  // sizes are checked before any allocation they decide
+  if (a.n < 1 || a.n > (int64_t(1) << 40) || a.dim < 1 || a.dim > kMaxBlocks * kBlockDims ||
+      a.nlist < 1 || a.nlist > 65536 || a.delta_d < kBlockDims || a.n_tables < 0 ||
+      a.n_tables > kMaxTables || n0 < 0 || n0 > (int64_t(1) << 36))
+    return set_err(DDC_EIO, "corrupt index file header");
+  const int D = a.dim;
+  const int T = (D + a.delta_d - 1) / a.delta_d - 1 + (a.fp8_lead_dims ? 1 : 0);
+  const uint8_t has_lam = r.val<uint8_t>();
+  std::vector<double> mu(D), R((size_t)D * D), lam(has_lam ? D : 0), m((size_t)a.n_tables * T),
+      resid((size_t)n0 * T);
+  std::vector<float> cent((size_t)a.nlist * D), y((size_t)a.n * D);
+  std::vector<int32_t> assign(a.n);
+  r.get(mu.data(), mu.size() * 8);
+  r.get(R.data(), R.size() * 8);
+  if (has_lam) r.get(lam.data(), lam.size() * 8);
+  r.get(cent.data(), cent.size() * 4);
+  r.get(assign.data(), assign.size() * 4);
+  r.get(y.data(), y.size() * 4);
+  r.get(m.data(), m.size() * 8);
+  r.get(resid.data(), resid.size() * 8);
+  const uint64_t want = r.sum.h;
+  uint64_t got = 0;
+  if (fread(&got, 1, 8, fc.f) != 8 || got != want) return set_err(DDC_EIO, "index file checksum mismatch");
+  a.mu = mu.data(); a.rot = R.data(); a.lam = has_lam ? lam.data() : nullptr; a.centroids = cent.data();
+  a.assign = assign.data(); a.y = y.data(); a.m = m.data(); a.resid = resid.data();
+  return ddc_import(&a, out);
+  GUARD_END
+}
+
+ddc_status ddc_correction(const ddc_index *ixc, int32_t k, double alpha, ddc_calib_mode mode,
+                          double *m_out, double *beta_out) {
   if (!ixc || !m_out || !beta_out) return set_err(DDC_EINVAL, "NULL argument");
   if (!(alpha >= 0.0 && alpha < 1.0)) return set_err(DDC_EINVAL, "significance must be in [0, 1)");
   if (mode != DDC_CALIB_JOINT && mode != DDC_CALIB_BONFERRONI) return set_err(DDC_EINVAL, "bad calibration mode");
-  if (ixc->n0 == 0 && ixc->Tt() > 0) return set_err(DDC_EINVAL, "index has no correction table");
+  if (k < 1 || k > kMaxK) return set_err(DDC_EINVAL, "k must be in [1, %d]", kMaxK);
+  if (ixc->tables.empty()) return set_err(DDC_EINVAL, "index has no correction table");
   GUARD_BEGIN
   ddc_index *ix = const_cast<ddc_index *>(ixc);
-  auto b = get_beta(ix, alpha, mode);
-  for (int t = 0; t < ix->Tt(); ++t) { m_out[t] = ix->m[t]; beta_out[t] = b[t]; }
+  const int t = table_for_k(ix, k);
+  auto b = get_beta(ix, alpha, mode, t);
+  for (int j = 0; j < ix->Tt(); ++j) { m_out[j] = ix->tables[t].m[j]; beta_out[j] = b[j]; }
   return DDC_OK;
   GUARD_END
 }
@@ -969,7 +1169,8 @@ ddc_status ddc_calibrate(ddc_index *ix, const float *calib, int64_t n_calib, int
                          int32_t calib_nprobe, int32_t calib_max_neg, uint64_t seed) {
   if (!ix || !calib) return set_err(DDC_EINVAL, "NULL argument");
   if (n_calib < 1) return set_err(DDC_EINVAL, "n_calib must be >= 1");
-  if (calib_k < 1 || calib_k > 64 || calib_k > ix->n) return set_err(DDC_EINVAL, "calib_k must be in [1, min(64, n)]");
+  if (calib_k < 0 || calib_k > kMaxK || calib_k > ix->n) return set_err(DDC_EINVAL, "calib_k must be in [0, min(256, n)]");
+  if (calib_k == 0 && ix->tables.empty()) return set_err(DDC_EINVAL, "calib_k = 0 needs existing tables");
   if (calib_nprobe < 0 || calib_nprobe > ix->nlist) return set_err(DDC_EINVAL, "calib_nprobe must be in [0, nlist]");
   if (calib_max_neg < 1 || calib_max_neg > 256) return set_err(DDC_EINVAL, "calib_max_neg must be in [1, 256]");
   if (!all_finite(calib, n_calib * ix->D)) return set_err(DDC_EINVAL, "non-finite calibration values");
@@ -977,7 +1178,12 @@ ddc_status ddc_calibrate(ddc_index *ix, const float *calib, int64_t n_calib, int
   GUARD_BEGIN
   DeviceGuard dg(ix->device);
   StreamHolder sh;
-  run_calibration(ix, calib, n_calib, calib_k, npc, calib_max_neg, seed, sh.s);
+  std::vector<int> kcs;
+  if (calib_k) kcs.push_back(calib_k);
+  else for (auto &t : ix->tables) kcs.push_back(t.kc);
+  std::vector<ddc_index::Table> tabs;
+  for (int kc : kcs) tabs.push_back(run_calibration(ix, calib, n_calib, kc, npc, calib_max_neg, seed, sh.s));
+  set_tables(ix, std::move(tabs));
   return DDC_OK;
   GUARD_END
 }
@@ -1016,6 +1222,8 @@ extern "C" ddc_status ddc_fit(const float *base, int64_t n, int32_t dim, const f
   if (st != DDC_OK) return st;
   if (n_calib < 1) return set_err(DDC_EINVAL, "n_calib must be >= 1");
   if (p->calib_k > n) return set_err(DDC_EINVAL, "calib_k > n");
+  for (int i = 0; i < kMaxTables - 1; ++i)
+    if (p->calib_k_extra[i] > n) return set_err(DDC_EINVAL, "calib_k_extra > n");
   if (!all_finite(base, n * dim) || !all_finite(calib, n_calib * dim))
     return set_err(DDC_EINVAL, "non-finite input values");
   GUARD_BEGIN
@@ -1131,7 +1339,12 @@ extern "C" ddc_status ddc_fit(const float *base, int64_t n, int32_t dim, const f
 
   // F5: calibration of the correction table
   const int npc = p->calib_nprobe ? p->calib_nprobe : std::min(std::max(1, nlist / 8), 64);
-  run_calibration(ix.get(), calib, n_calib, p->calib_k, npc, p->calib_max_neg, p->seed, s);
+  std::vector<ddc_index::Table> tabs;
+  tabs.push_back(run_calibration(ix.get(), calib, n_calib, p->calib_k, npc, p->calib_max_neg, p->seed, s));
+  for (int i = 0; i < kMaxTables - 1 && p->calib_k_extra[i]; ++i)
+    tabs.push_back(run_calibration(ix.get(), calib, n_calib, p->calib_k_extra[i], npc, p->calib_max_neg,
+                                   p->seed, s));
+  set_tables(ix.get(), std::move(tabs));
   *out = ix.release();
   return DDC_OK;
   GUARD_END

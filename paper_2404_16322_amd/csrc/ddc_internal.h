@@ -18,6 +18,7 @@ constexpr int kScanThreads = 256;    // 4 wavefronts per query
 constexpr int kCtrPreReads = 4 + 64, kCtrPrePruned = 4 + 64 + 1;
 constexpr int kMaxCounters = 4 + 64 + 2;
 constexpr int kFp8Lead = 64;          // dims covered by the FP8 pre-stage
+constexpr int kMaxTables = 4;         // correction tables (calibration K_c values) per index
 constexpr size_t kMaxLds = 160 * 1024;  // LDS per workgroup on gfx950
 
 enum StoreType : int { ST_F32 = 0, ST_F16 = 1, ST_BF16 = 2 };
@@ -44,13 +45,16 @@ struct ScanArgs {
   int32_t xcd_swizzle;     // 1: workgroup w runs slot range of XCD (w mod 8), contiguous per XCD
   const uint8_t *base8;    // FP8 pre-stage codes: per tile 64 vectors x 64 B (NULL if none)
   const float *scale8;     // per tile decode scale
-  int32_t pre;             // 1: run the FP8 pre-stage test m * e_0 + beta > tau first
-  float pre_m, pre_beta;
+  int32_t pre;             // 1: run the FP8 pre-stage test first
   int32_t waves_per_query; // 1 or 4 (result-invariant)
   int32_t lookahead;       // 0 or 1: multi-stage loads when few candidates survive (result-invariant)
   int32_t nq, nblocks, block_b, prune, nlist, k_max;
-  float m[kMaxBlocks];     // per 32-dim block: slope of the test after this block
-  float beta[kMaxBlocks];  //                   bias of the test after this block
+  // Correction tables [ntab][nblocks + 1][2] = (m, beta) of the test after dim block b
+  // (beta = -inf, m = 0 where none follows); entry nblocks is the FP8 pre-stage.  A query
+  // with K uses the last table t with tab_k[t] <= K (table 0 when none).
+  const float *tab;
+  int32_t ntab;
+  int32_t tab_k[kMaxTables];
   int8_t test_after[kMaxBlocks]; // 1 if a stage test follows block b
 };
 

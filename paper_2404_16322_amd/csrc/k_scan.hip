@@ -148,7 +148,7 @@ __host__ __device__ inline Lds lds_layout(int Dp, int kmax, int block_b, int W) 
   o = 0;
   l.ac = o; o += align16((size_t)2 * seg * 2);
   l.ae = o; o += align16((size_t)2 * seg * 4);
-  l.mb = o; o += align16((size_t)2 * (Dp / kBlockDims) * 4);
+  l.mb = o; o += align16((size_t)2 * (Dp / kBlockDims + 1) * 4);
   l.wave_bytes = o;
   return l;
 }
@@ -207,18 +207,19 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
   float *s_ae = reinterpret_cast<float *>(wl + L.ae);
   float *s_mb = reinterpret_cast<float *>(wl + L.mb);
 
-  const int K = a.k ? a.k[q] : a.k_all;
+  const int K = __builtin_amdgcn_readfirstlane(a.k ? a.k[q] : a.k_all);
   const int np = a.nprobe ? a.nprobe[q] : a.nprobe_all;
   const float *qg = a.qrot + (int64_t)q * a.q_stride;
   const int qt = wsub * 64 + lane;             // thread index within the query's waves
   for (int i = qt; i < Dp; i += 64 * W) s_q[i] = qg[i];
   if (qt < 2) s_cnt[qt] = 0;
-  if (PRUNE && LOOK) {
-    for (int i = 0; i < nb; ++i) {   // uniform index: scalar reads of the kernel arguments
-      const bool t = a.test_after[i] != 0;
-      const float mv = t ? a.m[i] : 0.f, bv = t ? a.beta[i] : -INFINITY;
-      if (lane == 0) { s_mb[2 * i] = mv; s_mb[2 * i + 1] = bv; }
-    }
+  if (PRUNE) {
+    // this query's correction table (by its K) into the wave's LDS
+    int tsel = 0;
+    for (int t = 1; t < a.ntab; ++t)
+      if (K >= a.tab_k[t]) tsel = t;
+    const float *tq = a.tab + (size_t)tsel * (nb + 1) * 2;
+    for (int i = lane; i < 2 * (nb + 1); i += 64) s_mb[i] = tq[i];
   }
   if (W > 1) __syncthreads(); else __builtin_amdgcn_wave_barrier();
 
@@ -355,7 +356,7 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
             const float e0 = transpose_sum<G8>(part, g8);
             const int idx = t0 + g8 * CPW8 + sub8;
             const bool valid = idx < slen;
-            const bool prune = valid && fmaf(a.pre_m, e0, a.pre_beta) > tau;
+            const bool prune = valid && fmaf(s_mb[2 * nb], e0, s_mb[2 * nb + 1]) > tau;
             const bool keep = valid && !prune;
             const unsigned long long bal = __ballot(keep);
             if (keep) {
@@ -469,7 +470,7 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
           }
           const bool last = b == nb - 1;
           const bool test = a.test_after[b] != 0;
-          const float mb = a.m[b], bb = a.beta[b];
+          const float mb = s_mb[2 * b], bb = s_mb[2 * b + 1];
           float qv[EPL];
 #pragma unroll
           for (int e = 0; e < EPL; ++e) qv[e] = s_q[b * kBlockDims + g * EPL + e];

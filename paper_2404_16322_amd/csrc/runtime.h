@@ -9,6 +9,8 @@
 #include <limits>
 #include <array>
 #include <map>
+#include <tuple>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <stdexcept>
@@ -140,10 +142,18 @@ struct ddc_index {
   std::vector<int32_t> list_len, tile_off;
   std::vector<int64_t> id_to_slot;  // n
   int64_t total_tiles = 0;
-  std::vector<double> m, resid;     // St ; n0 x St
-  int64_t n0 = 0;
+  // correction tables, ascending calibration K_c; a search with K uses the last with
+  // kc <= K (the first when none): m [Tt], resid [n0 x Tt] (label-0 residuals)
+  struct Table { int kc = 1; std::vector<double> m, resid; int64_t n0 = 0; };
+  std::vector<Table> tables;
+  int64_t n0_total() const {
+    int64_t t = 0;
+    for (auto &x : tables) t += x.n0;
+    return t;
+  }
   std::mutex beta_mtx;
-  std::map<std::pair<double, int>, std::vector<double>> beta_cache;
+  std::map<std::tuple<double, int, int>, std::vector<double>> beta_cache;   // (alpha, mode, table)
+  std::map<std::pair<double, int>, std::shared_ptr<ddc::DevBuf>> tab_cache; // device tables
   ddc::DevBuf d_R32, d_mu32, d_cent, d_cnorm, d_tile_off, d_list_len, d_ids, d_base, d_R64, d_mu64;
   int fp8 = 0;                      // FP8 pre-stage lead dims (0 or 64)
   ddc::DevBuf d_base8, d_scale8;    // its codes (tiles x 64 x 64 B) and per-tile scales

@@ -233,7 +233,7 @@ ddc_status ddc_server_create(const ddc_index *ixc, const ddc_server_params *p, d
   if (!(p->significance >= 0.0 && p->significance < 1.0)) return set_err(DDC_EINVAL, "significance must be in [0, 1)");
   if (p->mode != DDC_CORR_LEARNED && p->mode != DDC_CORR_LOSSLESS && p->mode != DDC_CORR_NONE)
     return set_err(DDC_EINVAL, "unknown correction mode");
-  if (p->mode == DDC_CORR_LEARNED && p->significance > 0 && ixc->St > 0 && ixc->n0 == 0)
+  if (p->mode == DDC_CORR_LEARNED && p->significance > 0 && ixc->Tt() > 0 && ixc->tables.empty())
     return set_err(DDC_EINVAL, "index has no calibrated correction table");
   ddc_index *ix = const_cast<ddc_index *>(ixc);
   std::unique_ptr<ddc_server> s(new ddc_server);

@@ -44,6 +44,8 @@ def artifacts(ix, with_table=True):
         art["fp8_lead_dims"] = ix["pre"]["lead"]
     if with_table:
         art.update(m=ix["m"], resid=ix["G"])
+        if ix.get("tables"):
+            art["tables"] = [dict(kc=t["kc"], m=t["m"], resid=t["G"]) for t in ix["tables"]]
     return art
 
 

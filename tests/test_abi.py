@@ -129,7 +129,7 @@ def test_import_rejects_bad_artifacts_without_device(lib):
 
 def test_correction_rejects_bad_significance(lib):
     m = np.zeros(4)
-    assert lib.ddc_correction(None, 0.1, 0, m.ctypes.data, m.ctypes.data) == -1
+    assert lib.ddc_correction(None, 10, 0.1, 0, m.ctypes.data, m.ctypes.data) == -1
 
 
 def test_server_rejects_bad_arguments_without_device(lib):
@@ -143,3 +143,29 @@ def test_server_rejects_bad_arguments_without_device(lib):
     assert lib.ddc_server_poll(None, 1, None, None, C.byref(done), None) == -1
     st = B.ServerStats()
     assert lib.ddc_server_get_stats(None, C.byref(st)) == -1
+
+
+def test_load_rejects_missing_and_foreign_files_without_device(lib, tmp_path):
+    out = C.c_void_p()
+    assert lib.ddc_load(str(tmp_path / "none.ddc").encode(), C.byref(out)) == -4
+    f = tmp_path / "foreign.ddc"
+    f.write_bytes(b"NOTANIDX" + bytes(64))
+    assert lib.ddc_load(str(f).encode(), C.byref(out)) == -4
+    assert b"not an index file" in lib.ddc_last_error()
+    f.write_bytes(b"DDCINDEX" + (1).to_bytes(4, "little") + bytes(10))
+    assert lib.ddc_load(str(f).encode(), C.byref(out)) == -4      # truncated header
+    assert out.value is None
+    assert lib.ddc_save(None, b"x") == -1
+
+
+def test_fit_rejects_bad_table_and_fp8_parameters_without_device(lib):
+    base = np.zeros((100, 16), np.float32)
+    cal = np.zeros((10, 16), np.float32)
+    out = C.c_void_p()
+    for kw in [dict(calib_k_extra=(5, 0, 0)), dict(calib_k_extra=(20, 15, 0)),
+               dict(calib_k_extra=(0, 20, 0)), dict(calib_k_extra=(300, 0, 0)),
+               dict(fp8_lead_dims=32), dict(fp8_lead_dims=64)]:
+        p = B.default_params(nlist=4, **kw)
+        rc = lib.ddc_fit(base.ctypes.data, 100, 16, cal.ctypes.data, 10, C.byref(p), C.byref(out))
+        assert rc == -1, kw
+        assert out.value is None
