@@ -44,7 +44,7 @@ import numpy as np
 # published generator on its own.
 # --------------------------------------------------------------------------------------
 _M64 = (1 << 64) - 1
-TAG_PCA, TAG_KMEANS_INIT, TAG_KMEANS_SAMPLE, TAG_NEG, TAG_CALIB = 1, 2, 3, 4, 5
+TAG_PCA, TAG_KMEANS_INIT, TAG_KMEANS_SAMPLE, TAG_NEG, TAG_CALIB, TAG_HAAR = 1, 2, 3, 4, 5, 6
 
 
 def splitmix64(x):
@@ -162,6 +162,32 @@ def pca_fit(X: np.ndarray, pca_sample: int = 1_000_000, seed: int = 0) -> dict:
         if v[i] < 0:
             V[:, j] = -v
     return dict(mu=mu, cov=C, lam=lam, R=np.ascontiguousarray(V.T))
+
+
+def gaussian_by_key(count: int, seed: int, tag: int) -> np.ndarray:
+    """``count`` standard normals by the Box-Muller transform (Box & Muller 1958) of pairs of
+    SplitMix64 counter keys: u1 = (key(2i) >> 11 + 1) 2^-53 in (0, 1], u2 = (key(2i+1) >> 11)
+    2^-53 in [0, 1); z(2i) = r cos(2 pi u2), z(2i+1) = r sin(2 pi u2), r = sqrt(-2 ln u1)."""
+    npair = (count + 1) // 2
+    k = ctr_key(seed, tag, np.arange(2 * npair, dtype=np.uint64))
+    u1 = ((k[0::2] >> np.uint64(11)).astype(np.float64) + 1.0) * 2.0 ** -53
+    u2 = (k[1::2] >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    r = np.sqrt(-2.0 * np.log(u1))
+    z = np.empty(2 * npair)
+    z[0::2] = r * np.cos(2.0 * math.pi * u2)
+    z[1::2] = r * np.sin(2.0 * math.pi * u2)
+    return z[:count]
+
+
+def haar_rotation(D: int, seed: int) -> np.ndarray:
+    """A Haar-distributed random rotation (the random projection of the ablation against
+    PCA, Sec. III / IV-B): Q of the QR factorisation of a D x D matrix of standard normals
+    (row-major from ``gaussian_by_key``), each column's sign flipped so that the triangular
+    factor has a positive diagonal (Mezzadri 2007).  Returned with the rotated axes as rows."""
+    Z = gaussian_by_key(D * D, seed, TAG_HAAR).reshape(D, D)
+    Q, T = np.linalg.qr(Z)
+    Q = Q * np.where(np.diag(T) < 0, -1.0, 1.0)[None, :]
+    return np.ascontiguousarray(Q.T)
 
 
 def rotate(X: np.ndarray, mu: np.ndarray, R: np.ndarray) -> np.ndarray:
@@ -674,15 +700,33 @@ def calibrate(Y, list_off, list_ids, centroids, mu, R, calib, bounds, calib_k=10
 # End-to-end fit and search
 # --------------------------------------------------------------------------------------
 
+def ads_table(bounds: np.ndarray, D: int, eps0: float = 2.1):
+    """The random-projection test of ADSampling (Sec. III "Distance Correction") in this
+    code's test form.  With a random rotation, dis' = (D / d) e_d estimates dis; the test
+    dis' > (1 + eps)^2 tau (squared distances) with eps = eps0 / sqrt(d) (reading: the
+    failure bound 2 exp(-c0 d eps^2) of its lemma held at the level 2 exp(-c0 eps0^2)) is
+    m_s e_s + beta_s > tau with m_s = (D / d_s) / (1 + eps0 / sqrt(d_s))^2, beta_s = 0."""
+    d = np.asarray(bounds[:-1], dtype=np.float64)
+    m = (D / d) / (1.0 + eps0 / np.sqrt(d)) ** 2
+    return m, np.zeros_like(m)
+
+
 def fit(base, calib, nlist, delta_d=32, storage="f32", kmeans_iters=25, calib_k=10,
         calib_nprobe=None, B=256, L=0, seed=0, pca_sample=1_000_000, max_neg=50, fp8_lead=0,
-        calib_k_extra=()):
+        calib_k_extra=(), projection="pca"):
     """Projection + IVF lists + calibrated correction table for ``base``; ``fp8_lead`` = 64
     adds the FP8 pre-stage over the leading 64 rotated dims.  ``calib_k_extra`` adds one
-    table per further K_c (see ``table_for_k``)."""
+    table per further K_c (see ``table_for_k``).  ``projection`` = "haar" replaces the PCA
+    rotation by ``haar_rotation(D, seed)`` (centring and everything after it unchanged)."""
     base = np.asarray(base)
     D = base.shape[1]
     pca = pca_fit(base, pca_sample, seed)
+    if projection == "haar":
+        Rh = haar_rotation(D, seed)
+        pca = dict(mu=pca["mu"], cov=pca["cov"], R=Rh,
+                   lam=np.einsum("ij,jk,ik->i", Rh, pca["cov"], Rh))   # variance along each axis
+    elif projection != "pca":
+        raise ValueError(projection)
     Y = round_storage(rotate(base, pca["mu"], pca["R"]), storage)
     C, assign = kmeans(Y, nlist, kmeans_iters, seed)
     off, ids = build_lists(assign, nlist)
@@ -718,7 +762,8 @@ def table_for_k(index, k):
 
 
 def search(index, queries, k, nprobe, alpha, mode="learned", B=None, L=None, calib_mode="joint"):
-    """Search every query; mode in {'learned', 'lossless', 'none'}.
+    """Search every query; mode in {'learned', 'lossless', 'none', 'ads'} ('ads': the
+    ADSampling test of ``ads_table`` with index["ads_eps0"], default 2.1).
     Returns ids (nq, k), dists (nq, k), stop_counts (nq, S), margin (nq,)."""
     B = index["B"] if B is None else B
     L = index["L"] if L is None else L
@@ -736,6 +781,9 @@ def search(index, queries, k, nprobe, alpha, mode="learned", B=None, L=None, cal
     elif mode == "lossless":
         # the FP8 estimate is not a lower bound of the stored-value distance: no pre-stage
         m, beta, prune = np.ones(St), np.zeros(St), True
+    elif mode == "ads":
+        m, beta = ads_table(bounds, index["Y"].shape[1], index.get("ads_eps0", 2.1))
+        prune = True
     elif mode == "none":
         m, beta, prune = np.ones(St), np.zeros(St), False
     else:

@@ -562,3 +562,55 @@ def test_table_at_k50_holds_significance_at_k50(multi_k_index, small_workload):
                           for _ in range(2000)])
         lo, hi = np.quantile(boots, [0.005, 0.995])
         assert abs(rate - a) <= (hi - lo) / 2 * math.sqrt(2), (a, rate)
+
+
+# ----------------------------------------------------------------------------- random-rotation ablation
+
+def test_gaussian_by_key_is_standard_normal():
+    import scipy.stats as st
+    z = O.gaussian_by_key(20000, 3, O.TAG_HAAR)
+    assert st.kstest(z, "norm").pvalue > 0.01
+    assert abs(z.mean()) < 0.03 and abs(z.std() - 1) < 0.03
+
+
+def test_haar_rotation_orthogonal_and_sign_symmetric():
+    """Orthogonal to rounding; with the sign fix every entry is symmetric about zero (QR
+    without it leaves the first entry of the first column of one sign)."""
+    R = O.haar_rotation(64, 5)
+    assert np.abs(R @ R.T - np.eye(64)).max() < 1e-12
+    r00 = np.array([O.haar_rotation(4, s)[0, 0] for s in range(2000)])
+    assert 0.45 < (r00 > 0).mean() < 0.55 and abs(r00.mean()) < 0.03
+    # E[R_ij^2] = 1/D for a uniformly random rotation
+    sq = np.mean([O.haar_rotation(8, s) ** 2 for s in range(400)], axis=0)
+    assert np.abs(sq - 1 / 8).max() < 0.03
+
+
+def test_scaled_partial_distance_unbiased_under_random_rotation():
+    """Isotropic data, random rotation: (D/d) e_d estimates the distance without bias (the
+    premise of the ADSampling test), per stage within 2%."""
+    rng = np.random.default_rng(0)
+    X = rng.standard_normal((1000, 128))
+    Q = rng.standard_normal((400, 128))
+    R = O.haar_rotation(128, 7)
+    Y, Qr = X @ R.T, Q @ R.T
+    b = O.stage_bounds(128, 32)
+    e = np.concatenate([O.partial_dists(Y, q, b) for q in Qr])
+    est = (e[:, :-1] * (128 / b[:-1])[None, :]).mean(axis=0)
+    assert np.all(np.abs(est / e[:, -1].mean() - 1) < 0.02)
+
+
+def test_ads_test_is_safe_on_isotropic_data_and_exact_for_large_eps(small_workload):
+    rng = np.random.default_rng(1)
+    X = rng.standard_normal((6000, 128)).astype(np.float32)
+    C = rng.standard_normal((12000, 128)).astype(np.float32)
+    ix = O.fit(X, C[:200], nlist=16, kmeans_iters=5, calib_k=10, calib_nprobe=4, seed=3,
+               projection="haar")
+    Q = C[1000:1040]
+    a = O.search(ix, Q, 10, 16, 0.0, mode="ads")
+    n = O.search(ix, Q, 10, 16, 0.0, mode="none")
+    assert a["stops"][:, :-1].sum() > 0                         # it prunes
+    miss = np.mean([len(set(x) - set(y)) for x, y in zip(n["ids"], a["ids"])]) / 10
+    assert miss < 0.01                                          # and rarely wrongly
+    big = dict(ix, ads_eps0=1e6)
+    b = O.search(big, Q, 10, 16, 0.0, mode="ads")
+    assert b["ids"].tolist() == n["ids"].tolist() and b["stops"][:, :-1].sum() == 0
