@@ -62,8 +62,15 @@ typedef enum { DDC_ROT_F32 = 0, DDC_ROT_BF16 = 1 } ddc_rot;
  *  LEARNED : m_s * e_s + beta_s(alpha) > tau with the calibrated table (Sec. V-A, V-B)
  *  LOSSLESS: m_s = 1, beta_s = 0 -- e_s <= dis always (sums of squares, Eq. (1)), so
  *            the result equals NONE exactly (classic partial-distance early exit)
- *  NONE    : no test; every candidate is refined (full-D scan)                        */
-typedef enum { DDC_CORR_LEARNED = 0, DDC_CORR_LOSSLESS = 1, DDC_CORR_NONE = 2 } ddc_corr;
+ *  NONE    : no test; every candidate is refined (full-D scan)
+ *  ADS     : the random-projection test of ADSampling (Sec. III): prune iff
+ *            (D / d_s) e_s > (1 + eps0 / sqrt(d_s))^2 tau, eps0 set by ddc_set_ads_epsilon
+ *            (2.1 by default); meant for a DDC_PROJ_HAAR index; significance is ignored   */
+typedef enum { DDC_CORR_LEARNED = 0, DDC_CORR_LOSSLESS = 1, DDC_CORR_NONE = 2, DDC_CORR_ADS = 3 } ddc_corr;
+
+/* Rotation learned by the fit: PCA (Sec. IV-B, Thm. 1) or, for the ablation of Sec. III /
+ * IV-B, a Haar-distributed random rotation drawn from the fit seed. */
+typedef enum { DDC_PROJ_PCA = 0, DDC_PROJ_HAAR = 1 } ddc_proj;
 
 /* How the target recall r = 1 - alpha of label 0 (true neighbours) is split over
  * the test stages (Sec. V-A "Adaptive Adjustment"):
@@ -86,6 +93,7 @@ typedef struct {
                              largest K_c <= K (calib_k's when K is smaller); {0, 0, 0} */
   ddc_dtype storage;      /* base storage format; DDC_F32 */
   ddc_rot rotation;       /* query rotation precision; DDC_ROT_F32 */
+  ddc_proj projection;    /* DDC_PROJ_PCA */
   int32_t fp8_lead_dims;  /* 0, or 64: FP8 E4M3 codes of the leading 64 rotated dims (one scale
                              per list tile of 64 vectors) give a first test stage over 64 dims
                              before the stored-precision stages (needs dim >= 64); 0 */
@@ -227,6 +235,9 @@ ddc_status ddc_debug_intermediates(const ddc_index *ix, const float *queries, in
  * (both caller arrays, overwritten), and clears the record when reset != 0. */
 ddc_status ddc_set_kernel_timing(ddc_index *ix, int enable);
 ddc_status ddc_get_kernel_timing(ddc_index *ix, double *ms_total, int64_t *launches, int reset);
+
+/* eps0 of the DDC_CORR_ADS test (> 0; 2.1 by default, the value the paper uses for it). */
+ddc_status ddc_set_ads_epsilon(ddc_index *ix, double eps0);
 
 /* Launch shape of the pruned scan (A3-A5).  None of these changes any result bit (every
  * candidate's partial distances are summed in the same order in every variant); they only

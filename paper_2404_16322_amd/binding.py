@@ -13,7 +13,8 @@ _LOCK = threading.Lock()
 
 DTYPE = {"f32": 0, "f16": 1, "bf16": 2}
 ROT = {"f32": 0, "bf16": 1}
-CORR = {"learned": 0, "lossless": 1, "none": 2}
+CORR = {"learned": 0, "lossless": 1, "none": 2, "ads": 3}
+PROJ = {"pca": 0, "haar": 1}
 CALIB = {"joint": 0, "bonferroni": 1}
 STATUS = {0: "DDC_OK", -1: "DDC_EINVAL", -2: "DDC_ENOMEM", -3: "DDC_EDEVICE", -4: "DDC_EIO",
           -5: "DDC_EBUSY", -6: "DDC_EUNSUP"}
@@ -23,7 +24,7 @@ SYMBOLS = ["ddc_fit_params_default", "ddc_fit", "ddc_import", "ddc_export", "ddc
            "ddc_debug_intermediates", "ddc_set_kernel_timing", "ddc_get_kernel_timing", "ddc_free",
            "ddc_last_error", "ddc_server_create", "ddc_server_submit", "ddc_server_poll",
            "ddc_server_get_stats", "ddc_server_destroy", "ddc_set_launch", "ddc_get_launch",
-           "ddc_scan_variant", "ddc_save", "ddc_load"]
+           "ddc_scan_variant", "ddc_save", "ddc_load", "ddc_set_ads_epsilon"]
 
 
 class FitParams(C.Structure):
@@ -32,7 +33,8 @@ class FitParams(C.Structure):
                 ("kmeans_train_per_list", C.c_int32), ("calib_k", C.c_int32),
                 ("calib_nprobe", C.c_int32), ("calib_max_neg", C.c_int32),
                 ("calib_k_extra", C.c_int32 * 3), ("storage", C.c_int),
-                ("rotation", C.c_int), ("fp8_lead_dims", C.c_int32), ("pca_sample", C.c_int64),
+                ("rotation", C.c_int), ("projection", C.c_int), ("fp8_lead_dims", C.c_int32),
+                ("pca_sample", C.c_int64),
                 ("seed", C.c_uint64)]
 
 
@@ -120,6 +122,7 @@ def load_library():
         lib.ddc_debug_intermediates.argtypes = [vp, vp, i64, i32, vp, vp]
         lib.ddc_set_kernel_timing.argtypes = [vp, C.c_int]
         lib.ddc_get_kernel_timing.argtypes = [vp, vp, vp, C.c_int]
+        lib.ddc_set_ads_epsilon.argtypes = [vp, f64]
         lib.ddc_save.argtypes = [vp, C.c_char_p]
         lib.ddc_load.argtypes = [C.c_char_p, C.POINTER(vp)]
         lib.ddc_set_launch.argtypes = [vp, C.POINTER(LaunchParams)]
@@ -163,6 +166,8 @@ def default_params(**kw) -> FitParams:
             v = DTYPE[v] if isinstance(v, str) else v
         if k == "rotation":
             v = ROT[v] if isinstance(v, str) else v
+        if k == "projection":
+            v = PROJ[v] if isinstance(v, str) else v
         if k == "calib_k_extra":
             v = (C.c_int32 * 3)(*(list(v) + [0, 0, 0])[:3])
         if not hasattr(p, k):
@@ -336,6 +341,9 @@ class Index:
             self._h, d_queries, nq, d_k or None, k_all, k_max, d_nprobe or None, nprobe_all,
             nprobe_max, alpha, CORR[mode], d_offsets or None, d_ids, d_dists, d_counters or None,
             stream or None))
+
+    def set_ads_epsilon(self, eps0: float):
+        _check(load_library().ddc_set_ads_epsilon(self._h, eps0))
 
     def set_launch(self, waves_per_query: int | None = None, lookahead: int | None = None,
                    query_order: int | None = None, xcd_swizzle: int | None = None):

@@ -441,8 +441,9 @@ static std::vector<double> get_beta(ddc_index *ix, double alpha, int mode, int t
 // dim block (beta = -inf where no test follows; entry NB = the FP8 pre-stage).
 static std::shared_ptr<DevBuf> device_tables(ddc_index *ix, double alpha, ddc_corr mode, int *ntab) {
   std::lock_guard<std::mutex> lk(ix->beta_mtx);
-  const bool lossless = mode == DDC_CORR_LOSSLESS;
-  const auto key = std::make_pair(lossless ? -1.0 : alpha, (int)mode);
+  const bool ads = mode == DDC_CORR_ADS;
+  const bool lossless = mode == DDC_CORR_LOSSLESS || ads;   // one fixed table, no pre-stage
+  const auto key = std::make_pair(ads ? ix->ads_eps0 : lossless ? -1.0 : alpha, (int)mode);
   const int nt = lossless ? 1 : (int)ix->tables.size();
   *ntab = nt;
   auto it = ix->tab_cache.find(key);
@@ -453,7 +454,14 @@ static std::shared_ptr<DevBuf> device_tables(ddc_index *ix, double alpha, ddc_co
     float *row = &h[(size_t)t * (NB + 1) * 2];
     for (int b = 0; b <= NB; ++b) { row[2 * b] = 0.f; row[2 * b + 1] = -INFINITY; }
     std::vector<double> mm(ix->Tt(), 1.0), bb(ix->Tt(), 0.0);
-    if (!lossless) {
+    if (ads) {
+      // (D / d) e > (1 + eps0 / sqrt(d))^2 tau  <=>  m e > tau
+      for (int j = 0; j < ix->St; ++j) {
+        const double d = std::min((j + 1) * ix->delta_d, ix->D);
+        const double g = 1.0 + ix->ads_eps0 / std::sqrt(d);
+        mm[P + j] = ((double)ix->D / d) / (g * g);
+      }
+    } else if (!lossless) {
       mm = ix->tables[t].m;
       bb = beta_locked(ix, alpha, DDC_CALIB_JOINT, t);
     }
@@ -500,8 +508,9 @@ void ddc::search_device(ddc_index *ix, const float *d_q, int64_t nq, const int32
   a.prune = 0;
   std::shared_ptr<DevBuf> tabs;   // keeps the device tables alive for this call
   const bool learned = mode == DDC_CORR_LEARNED && alpha > 0 && ix->Tt() > 0;
-  // LOSSLESS tests e_s > tau with the stored values only: the FP8 estimate is no lower bound
-  const bool lossless = mode == DDC_CORR_LOSSLESS && ix->St > 0;
+  // LOSSLESS tests e_s > tau with the stored values only: the FP8 estimate is no lower bound;
+  // ADS is a fixed table on the stored values too
+  const bool lossless = (mode == DDC_CORR_LOSSLESS || mode == DDC_CORR_ADS) && ix->St > 0;
   if (learned || lossless) {
     a.prune = 1;
     tabs = device_tables(ix, alpha, mode, &a.ntab);
@@ -587,7 +596,8 @@ static ddc_status check_search_args(const ddc_index *ix, int64_t nq, double alph
   if (!ix) return set_err(DDC_EINVAL, "index is NULL");
   if (nq < 0) return set_err(DDC_EINVAL, "nq must be >= 0");
   if (!(alpha >= 0.0 && alpha < 1.0)) return set_err(DDC_EINVAL, "significance must be in [0, 1)");
-  if (mode != DDC_CORR_LEARNED && mode != DDC_CORR_LOSSLESS && mode != DDC_CORR_NONE)
+  if (mode != DDC_CORR_LEARNED && mode != DDC_CORR_LOSSLESS && mode != DDC_CORR_NONE &&
+      mode != DDC_CORR_ADS)
     return set_err(DDC_EINVAL, "unknown correction mode %d", (int)mode);
   if (mode == DDC_CORR_LEARNED && alpha > 0 && ix->Tt() > 0 && ix->tables.empty())
     return set_err(DDC_EINVAL, "index has no calibrated correction table (use LOSSLESS/NONE or calibrate)");
@@ -623,6 +633,7 @@ static ddc_status check_params(const ddc_fit_params *p, int64_t n, int dim) {
   if (p->storage != DDC_F32 && p->storage != DDC_F16 && p->storage != DDC_BF16) return set_err(DDC_EINVAL, "bad storage");
   if (p->rotation != DDC_ROT_F32 && p->rotation != DDC_ROT_BF16) return set_err(DDC_EINVAL, "bad rotation");
   if (p->pca_sample < 2) return set_err(DDC_EINVAL, "pca_sample must be >= 2");
+  if (p->projection != DDC_PROJ_PCA && p->projection != DDC_PROJ_HAAR) return set_err(DDC_EINVAL, "bad projection");
   if (p->fp8_lead_dims != 0 && p->fp8_lead_dims != kFp8Lead) return set_err(DDC_EINVAL, "fp8_lead_dims must be 0 or 64");
   if (p->fp8_lead_dims && dim < kFp8Lead) return set_err(DDC_EINVAL, "the FP8 pre-stage needs dim >= 64");
   return DDC_OK;
@@ -1122,6 +1133,14 @@ ddc_status ddc_get_kernel_timing(ddc_index *ix, double *ms_total, int64_t *launc
   GUARD_END
 }
 
+ddc_status ddc_set_ads_epsilon(ddc_index *ix, double eps0) {
+  if (!ix) return set_err(DDC_EINVAL, "index is NULL");
+  if (!(eps0 > 0.0) || !std::isfinite(eps0)) return set_err(DDC_EINVAL, "eps0 must be > 0");
+  std::lock_guard<std::mutex> lk(ix->beta_mtx);
+  ix->ads_eps0 = eps0;
+  return DDC_OK;
+}
+
 ddc_status ddc_set_launch(ddc_index *ix, const ddc_launch_params *p) {
   if (!ix || !p) return set_err(DDC_EINVAL, "NULL argument");
   if (p->waves_per_query != 0 && p->waves_per_query != 1 && p->waves_per_query != 4)
@@ -1266,7 +1285,22 @@ extern "C" ddc_status ddc_fit(const float *base, int64_t n, int32_t dim, const f
   d_cpart.release();
 
   // F2: eigenvectors (rows of R, largest eigenvalue first)
-  if (!sym_eig_desc(cov, D, ix->lam, ix->R)) throw DdcError(DDC_EDEVICE, "eigen-decomposition did not converge");
+  if (p->projection == DDC_PROJ_HAAR) {
+    // a random rotation instead of PCA; lam = the variance along each rotated axis
+    haar_rotation(D, p->seed, ix->R);
+    ix->lam.assign(D, 0.0);
+    for (int i = 0; i < D; ++i) {
+      double v = 0.0;
+      for (int a = 0; a < D; ++a) {
+        double t = 0.0;
+        for (int b = 0; b < D; ++b) t += cov[(size_t)a * D + b] * ix->R[(size_t)i * D + b];
+        v += ix->R[(size_t)i * D + a] * t;
+      }
+      ix->lam[i] = v;
+    }
+  } else if (!sym_eig_desc(cov, D, ix->lam, ix->R)) {
+    throw DdcError(DDC_EDEVICE, "eigen-decomposition did not converge");
+  }
 
   // F3: rotate the base on the matrix cores, round to the storage format
   std::vector<float> R32((size_t)Dp * Dp, 0.f), mu32(Dp, 0.f);

@@ -288,4 +288,53 @@ std::vector<double> beta_for_alpha(const std::vector<double> &G, int64_t n0, int
   return beta;
 }
 
+void haar_rotation(int D, uint64_t seed, std::vector<double> &R) {
+  const int64_t cnt = (int64_t)D * D;
+  std::vector<double> Z(cnt);
+  const double two53 = 1.0 / 9007199254740992.0;   // 2^-53
+  for (int64_t p = 0; 2 * p < cnt; ++p) {
+    const double u1 = ((double)(ctr_key(seed, TAG_HAAR, 2 * p) >> 11) + 1.0) * two53;   // (0, 1]
+    const double u2 = (double)(ctr_key(seed, TAG_HAAR, 2 * p + 1) >> 11) * two53;       // [0, 1)
+    const double r = std::sqrt(-2.0 * std::log(u1));
+    const double a = 2.0 * M_PI * u2;
+    Z[2 * p] = r * std::cos(a);
+    if (2 * p + 1 < cnt) Z[2 * p + 1] = r * std::sin(a);
+  }
+  // Householder QR: Z <- H_{D-1} ... H_0 Z (upper triangular), Q = H_0 ... H_{D-1}
+  std::vector<double> Q((size_t)cnt, 0.0), v(D);
+  for (int i = 0; i < D; ++i) Q[(size_t)i * D + i] = 1.0;
+  for (int k = 0; k < D; ++k) {
+    double nx = 0.0;
+    for (int i = k; i < D; ++i) nx += Z[(size_t)i * D + k] * Z[(size_t)i * D + k];
+    nx = std::sqrt(nx);
+    if (nx == 0.0) continue;
+    const double x0 = Z[(size_t)k * D + k];
+    const double alpha = x0 >= 0 ? -nx : nx;
+    double vn = 0.0;
+    for (int i = k; i < D; ++i) {
+      v[i] = Z[(size_t)i * D + k] - (i == k ? alpha : 0.0);
+      vn += v[i] * v[i];
+    }
+    if (vn == 0.0) continue;
+    const double sc = 2.0 / vn;
+    for (int j = k; j < D; ++j) {          // Z[k:, j] -= sc v (v . Z[k:, j])
+      double d = 0.0;
+      for (int i = k; i < D; ++i) d += v[i] * Z[(size_t)i * D + j];
+      d *= sc;
+      for (int i = k; i < D; ++i) Z[(size_t)i * D + j] -= d * v[i];
+    }
+    for (int i = 0; i < D; ++i) {          // Q[i, k:] -= sc (Q[i, k:] . v) v
+      double d = 0.0;
+      for (int j = k; j < D; ++j) d += Q[(size_t)i * D + j] * v[j];
+      d *= sc;
+      for (int j = k; j < D; ++j) Q[(size_t)i * D + j] -= d * v[j];
+    }
+  }
+  R.assign((size_t)cnt, 0.0);
+  for (int j = 0; j < D; ++j) {
+    const double sg = Z[(size_t)j * D + j] < 0 ? -1.0 : 1.0;
+    for (int i = 0; i < D; ++i) R[(size_t)j * D + i] = sg * Q[(size_t)i * D + j];
+  }
+}
+
 }  // namespace ddc

@@ -15,7 +15,13 @@ uint64_t ctr_key(uint64_t seed, uint64_t tag, uint64_t i);
 // Indices (ascending) of the m smallest keys among 0..n-1, ties by index; all if m >= n.
 std::vector<int64_t> select_by_key(int64_t n, int64_t m, uint64_t seed, uint64_t tag);
 
-enum : uint64_t { TAG_PCA = 1, TAG_KMEANS_INIT = 2, TAG_KMEANS_SAMPLE = 3, TAG_NEG = 4, TAG_CALIB = 5 };
+enum : uint64_t { TAG_PCA = 1, TAG_KMEANS_INIT = 2, TAG_KMEANS_SAMPLE = 3, TAG_NEG = 4, TAG_CALIB = 5,
+                  TAG_HAAR = 6 };
+
+// A Haar-distributed random rotation (Mezzadri 2007): Householder QR of a D x D matrix of
+// standard normals (Box-Muller over pairs of counter keys, row-major), every column of Q
+// signed so that the triangular factor's diagonal is positive; rows of `R` = columns of Q.
+void haar_rotation(int D, uint64_t seed, std::vector<double> &R);
 
 // Eigen-decomposition of the symmetric n x n matrix A (row-major, FP64): Householder
 // reduction to tridiagonal form, then implicit QL iterations with Wilkinson-type shifts.

@@ -205,6 +205,9 @@ __device__ inline uint32_t wave_max_u32(uint32_t v) {
 
 __host__ __device__ inline size_t select_wave_lds(int p_stride) { return 256 * 4 + (size_t)(p_stride + kExtra) * 8; }
 
+// NR > 0: the row's keys stay in registers (key j in register j / 64 of lane j % 64), read
+// from memory once; NR = 0: every pass re-reads the row (any nlist).
+template <int NR>
 __global__ __launch_bounds__(kSelThreads) void select_kernel(const float *dist, int64_t ld,
                                                              int32_t nlist, const int32_t *nprobe,
                                                              int32_t nprobe_all, int32_t *probes,
@@ -222,12 +225,48 @@ __global__ __launch_bounds__(kSelThreads) void select_kernel(const float *dist, 
   const float *row = dist + q * ld;
   const unsigned long long lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
 
+  constexpr int R = NR > 0 ? NR : 1;
+  uint32_t ureg[R];
+  if constexpr (NR > 0) {
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const int j = lane + 64 * i;
+      ureg[i] = j < nlist ? f32_order_key(row[j]) : 0xFFFFFFFFu;
+    }
+  }
+  // f(j, key) for this lane's keys
+  auto each = [&](auto &&f) {
+    if constexpr (NR > 0) {
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        const int j = lane + 64 * i;
+        if (j < nlist) f(j, ureg[i]);
+      }
+    } else {
+      for (int j = lane; j < nlist; j += 64) f(j, f32_order_key(row[j]));
+    }
+  };
+  // f(j, key, valid) for every group of 64 consecutive keys, all lanes together
+  auto each_group = [&](auto &&f) {
+    if constexpr (NR > 0) {
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        const int j = lane + 64 * i;
+        f(j, ureg[i], j < nlist);
+      }
+    } else {
+      for (int j0 = 0; j0 < nlist; j0 += 64) {
+        const int j = j0 + lane;
+        f(j, j < nlist ? f32_order_key(row[j]) : 0xFFFFFFFFu, j < nlist);
+      }
+    }
+  };
+
   uint32_t kmin = 0xFFFFFFFFu, kmax = 0u;
-  for (int j = lane; j < nlist; j += 64) {
-    const uint32_t u = f32_order_key(row[j]);
+  each([&](int, uint32_t u) {
     kmin = min(kmin, u);
     kmax = max(kmax, u);
-  }
+  });
   kmin = wave_min_u32(kmin);
   kmax = wave_max_u32(kmax);
   // keys share the bits above `top`; digits are taken below it
@@ -245,10 +284,9 @@ __global__ __launch_bounds__(kSelThreads) void select_kernel(const float *dist, 
     const uint32_t dmask = (1u << width) - 1u;
     for (int i = lane; i < 256; i += 64) hist[i] = 0;
     __builtin_amdgcn_wave_barrier();
-    for (int j = lane; j < nlist; j += 64) {
-      const uint32_t u = f32_order_key(row[j]);
+    each([&](int, uint32_t u) {
       if ((u & mask) == prefix) atomicAdd(&hist[(u >> sh) & dmask], 1);
-    }
+    });
     __builtin_amdgcn_wave_barrier();
     const int h0 = hist[4 * lane], h1 = hist[4 * lane + 1], h2 = hist[4 * lane + 2], h3 = hist[4 * lane + 3];
     const int inc = wave_incl_scan(h0 + h1 + h2 + h3);
@@ -292,11 +330,9 @@ __global__ __launch_bounds__(kSelThreads) void select_kernel(const float *dist, 
   // small bucket; the first kk in index order when it is a single value)
   const uint32_t region_lo = prefix;
   int nsel = 0;
-  for (int j0 = 0; j0 < nlist; j0 += 64) {
-    const int j = j0 + lane;
-    const uint32_t u = j < nlist ? f32_order_key(row[j]) : 0xFFFFFFFFu;
-    const bool below = j < nlist && u < region_lo;
-    const bool inreg = j < nlist && (u & mask) == prefix;
+  each_group([&](int j, uint32_t u, bool valid) {
+    const bool below = valid && u < region_lo;
+    const bool inreg = valid && (u & mask) == prefix;
     bool take = below;
     if (!boundary_ties) take = take || inreg;
     const unsigned long long bt = __ballot(take);
@@ -306,13 +342,12 @@ __global__ __launch_bounds__(kSelThreads) void select_kernel(const float *dist, 
       sel_j[pos] = j;
     }
     nsel += __popcll(bt);
-  }
+  });
   if (boundary_ties) {
+    // the first kk keys equal to the boundary value, in index order
     int taken = 0;
-    for (int j0 = 0; j0 < nlist && taken < kk; j0 += 64) {
-      const int j = j0 + lane;
-      const uint32_t u = j < nlist ? f32_order_key(row[j]) : 0u;
-      const bool inreg = j < nlist && u == prefix;
+    each_group([&](int j, uint32_t u, bool valid) {
+      const bool inreg = valid && u == prefix;
       const unsigned long long bt = __ballot(inreg);
       const int r = __popcll(bt & lt);
       if (inreg && taken + r < kk) {
@@ -320,7 +355,7 @@ __global__ __launch_bounds__(kSelThreads) void select_kernel(const float *dist, 
         sel_j[nsel + taken + r] = j;
       }
       taken = min(kk, taken + __popcll(bt));
-    }
+    });
     nsel += taken;
   }
   __builtin_amdgcn_wave_barrier();
@@ -343,8 +378,16 @@ void launch_select(const float *dist, int64_t ld, int32_t nlist, const int32_t *
                    int64_t nq, hipStream_t s) {
   if (nq <= 0) return;
   const size_t smem = 4 * select_wave_lds(p_stride);
-  hipLaunchKernelGGL(select_kernel, dim3((unsigned)((nq + 3) / 4)), dim3(kSelThreads), smem, s, dist,
-                     ld, nlist, nprobe, nprobe_all, probes, p_stride, nq);
+  const dim3 grid((unsigned)((nq + 3) / 4));
+  if (nlist <= 1024)
+    hipLaunchKernelGGL(select_kernel<16>, grid, dim3(kSelThreads), smem, s, dist, ld, nlist, nprobe,
+                       nprobe_all, probes, p_stride, nq);
+  else if (nlist <= 4096)
+    hipLaunchKernelGGL(select_kernel<64>, grid, dim3(kSelThreads), smem, s, dist, ld, nlist, nprobe,
+                       nprobe_all, probes, p_stride, nq);
+  else
+    hipLaunchKernelGGL(select_kernel<0>, grid, dim3(kSelThreads), smem, s, dist, ld, nlist, nprobe,
+                       nprobe_all, probes, p_stride, nq);
   (void)nprobe_max;
 }
 

@@ -279,7 +279,8 @@ def _oracle_probes(q, C, nprobe):
     return np.lexsort((np.arange(C.shape[0]), d))[:nprobe], d
 
 
-@pytest.mark.parametrize("nl,nprobe", [(64, 8), (64, 64), (5000, 100), (5000, 4096), (300, 1)])
+@pytest.mark.parametrize("nl,nprobe", [(64, 8), (64, 64), (5000, 100), (5000, 4096), (300, 1),
+                                       (1024, 1024), (1025, 37), (4096, 48), (4096, 4096), (3000, 129)])
 def test_probe_selection_ties_and_sizes(nl, nprobe):
     rng = np.random.default_rng(nl + nprobe)
     C = rng.standard_normal((nl, 32)).astype(np.float32)
@@ -304,8 +305,9 @@ def test_probe_selection_ties_and_sizes(nl, nprobe):
     assert dup == sorted(dup) and dup[:min(12, nprobe)] == [3, *range(10, 20), 40][:min(12, nprobe)]
 
 
-def test_probe_selection_all_equal_distances():
-    C = np.ones((300, 32), np.float32)
+@pytest.mark.parametrize("nl", [300, 4096, 5000])
+def test_probe_selection_all_equal_distances(nl):
+    C = np.ones((nl, 32), np.float32)
     g = _probe_index(C)
     _, probes = g.debug_intermediates(np.zeros((3, 32), np.float32), 70)
     for row in probes:
