@@ -243,7 +243,15 @@ __global__ __launch_bounds__(kSelThreads) void select_kernel(const float *dist, 
         if (j < nlist) f(j, ureg[i]);
       }
     } else {
-      for (int j = lane; j < nlist; j += 64) f(j, f32_order_key(row[j]));
+      // 16 loads in flight per lane before any of them is used
+      for (int j0 = lane; j0 < nlist; j0 += 64 * 16) {
+        float v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) v[u] = j0 + 64 * u < nlist ? row[j0 + 64 * u] : 0.f;
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+          if (j0 + 64 * u < nlist) f(j0 + 64 * u, f32_order_key(v[u]));
+      }
     }
   };
   // f(j, key, valid) for every group of 64 consecutive keys, all lanes together
@@ -255,108 +263,164 @@ __global__ __launch_bounds__(kSelThreads) void select_kernel(const float *dist, 
         f(j, ureg[i], j < nlist);
       }
     } else {
-      for (int j0 = 0; j0 < nlist; j0 += 64) {
-        const int j = j0 + lane;
-        f(j, j < nlist ? f32_order_key(row[j]) : 0xFFFFFFFFu, j < nlist);
+      for (int g0 = 0; g0 < nlist; g0 += 64 * 16) {
+        float v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          const int j = g0 + 64 * u + lane;
+          v[u] = j < nlist ? row[j] : 0.f;
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          const int j = g0 + 64 * u + lane;
+          if (g0 + 64 * u < nlist) f(j, j < nlist ? f32_order_key(v[u]) : 0xFFFFFFFFu, j < nlist);
+        }
       }
     }
   };
 
-  uint32_t kmin = 0xFFFFFFFFu, kmax = 0u;
-  each([&](int, uint32_t u) {
-    kmin = min(kmin, u);
-    kmax = max(kmax, u);
-  });
-  kmin = wave_min_u32(kmin);
-  kmax = wave_max_u32(kmax);
-  // keys share the bits above `top`; digits are taken below it
-  int top = kmin == kmax ? -1 : 31 - __clz((int)(kmin ^ kmax));
-  uint32_t prefix = top >= 31 ? 0u : (kmin & ~((2u << top) - 1u));
-  uint32_t mask = top >= 31 ? 0u : ~((2u << top) - 1u);
-  if (top < 0) { prefix = kmin; mask = 0xFFFFFFFFu; }
-  int kk = np;          // rank still to place inside the current region
-  int shift = top - 7;  // low bit of the current digit (may go negative: clamp below)
-  int dig = 0;          // bucket of the remaining rank
-  bool boundary_ties = top < 0;  // the region holds a single key value
-  while (top >= 0) {
-    const int sh = max(shift, 0);
-    const int width = top - sh + 1;   // <= 8 bits
-    const uint32_t dmask = (1u << width) - 1u;
-    for (int i = lane; i < 256; i += 64) hist[i] = 0;
-    __builtin_amdgcn_wave_barrier();
+  const int cap = p_stride + kExtra;   // LDS slots for selected keys
+  int nsel = 0;
+  bool fast = false;
+  {
+    // Threshold from per-lane order statistics: with c = ceil(np / 64) and s_l = the c-th
+    // smallest key of lane l, at least k * c >= np keys are <= t = the k-th smallest s_l
+    // (k = ceil(np / c)), so the np smallest keys are all <= t.  Keys <= t are gathered in
+    // one pass; when there are more than `cap` of them the radix selection below runs.
+    const int c = (np + 63) / 64;
+    if (c <= 4) {
+      uint32_t best[4] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
+      each([&](int, uint32_t x) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          const uint32_t lo = min(best[m], x);
+          x = max(best[m], x);
+          best[m] = lo;
+        }
+      });
+      uint32_t v = c == 1 ? best[0] : c == 2 ? best[1] : c == 3 ? best[2] : best[3];
+      // bitonic sort of the 64 lane values, ascending by lane
+#pragma unroll
+      for (int size = 2; size <= 64; size <<= 1) {
+#pragma unroll
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+          const uint32_t o = (uint32_t)__shfl_xor((int)v, stride);
+          const bool up = (lane & size) == 0;
+          const bool lower = (lane & stride) == 0;
+          v = (lower == up) ? min(v, o) : max(v, o);
+        }
+      }
+      const int k = (np + c - 1) / c;
+      const uint32_t t = (uint32_t)__shfl((int)v, k - 1);
+      each_group([&](int j, uint32_t u, bool valid) {
+        const bool take = valid && u <= t;
+        const unsigned long long bt = __ballot(take);
+        const int pos = nsel + __popcll(bt & lt);
+        if (take && pos < cap) {
+          sel_k[pos] = u;
+          sel_j[pos] = j;
+        }
+        nsel += __popcll(bt);
+      });
+      fast = nsel <= cap;
+      if (!fast) nsel = 0;
+    }
+  }
+
+  if (!fast) {
+    uint32_t kmin = 0xFFFFFFFFu, kmax = 0u;
     each([&](int, uint32_t u) {
-      if ((u & mask) == prefix) atomicAdd(&hist[(u >> sh) & dmask], 1);
+      kmin = min(kmin, u);
+      kmax = max(kmax, u);
     });
-    __builtin_amdgcn_wave_barrier();
-    const int h0 = hist[4 * lane], h1 = hist[4 * lane + 1], h2 = hist[4 * lane + 2], h3 = hist[4 * lane + 3];
-    const int inc = wave_incl_scan(h0 + h1 + h2 + h3);
-    const int exc = inc - (h0 + h1 + h2 + h3);
-    int d = 0, before = 0, inb = 0;
-    if (exc < kk && kk <= inc) {
-      int c = exc, dd = 4 * lane;
-      int hv = h0;
-      if (c + h0 < kk) { c += h0; ++dd; hv = h1;
-        if (c + h1 < kk) { c += h1; ++dd; hv = h2;
-          if (c + h2 < kk) { c += h2; ++dd; hv = h3; } } }
-      d = dd; before = c; inb = hv;
-    }
-    const unsigned long long owner = __ballot(exc < kk && kk <= inc);
-    const int src = __ffsll((long long)owner) - 1;
-    d = __shfl(d, src); before = __shfl(before, src); inb = __shfl(inb, src);
-    dig = d;
-    // narrow the region to the bucket holding the remaining rank
-    const uint32_t region_lo = prefix | ((uint32_t)d << sh);
-    if (sh == 0) {
-      prefix = region_lo;
-      mask = 0xFFFFFFFFu;
-      kk -= before;
-      boundary_ties = true;
-      break;
-    }
-    if (inb <= kExtra) {
-      // finalize with the bucket's keys as extra candidates: region = [region_lo, +2^sh)
+    kmin = wave_min_u32(kmin);
+    kmax = wave_max_u32(kmax);
+    // keys share the bits above `top`; digits are taken below it
+    int top = kmin == kmax ? -1 : 31 - __clz((int)(kmin ^ kmax));
+    uint32_t prefix = top >= 31 ? 0u : (kmin & ~((2u << top) - 1u));
+    uint32_t mask = top >= 31 ? 0u : ~((2u << top) - 1u);
+    if (top < 0) { prefix = kmin; mask = 0xFFFFFFFFu; }
+    int kk = np;          // rank still to place inside the current region
+    int shift = top - 7;  // low bit of the current digit (may go negative: clamp below)
+    bool boundary_ties = top < 0;  // the region holds a single key value
+    while (top >= 0) {
+      const int sh = max(shift, 0);
+      const int width = top - sh + 1;   // <= 8 bits
+      const uint32_t dmask = (1u << width) - 1u;
+      for (int i = lane; i < 256; i += 64) hist[i] = 0;
+      __builtin_amdgcn_wave_barrier();
+      each([&](int, uint32_t u) {
+        if ((u & mask) == prefix) atomicAdd(&hist[(u >> sh) & dmask], 1);
+      });
+      __builtin_amdgcn_wave_barrier();
+      const int h0 = hist[4 * lane], h1 = hist[4 * lane + 1], h2 = hist[4 * lane + 2], h3 = hist[4 * lane + 3];
+      const int inc = wave_incl_scan(h0 + h1 + h2 + h3);
+      const int exc = inc - (h0 + h1 + h2 + h3);
+      int d = 0, before = 0, inb = 0;
+      if (exc < kk && kk <= inc) {
+        int c = exc, dd = 4 * lane;
+        int hv = h0;
+        if (c + h0 < kk) { c += h0; ++dd; hv = h1;
+          if (c + h1 < kk) { c += h1; ++dd; hv = h2;
+            if (c + h2 < kk) { c += h2; ++dd; hv = h3; } } }
+        d = dd; before = c; inb = hv;
+      }
+      const unsigned long long owner = __ballot(exc < kk && kk <= inc);
+      const int src = __ffsll((long long)owner) - 1;
+      d = __shfl(d, src); before = __shfl(before, src); inb = __shfl(inb, src);
+      // narrow the region to the bucket holding the remaining rank
+      const uint32_t region_lo = prefix | ((uint32_t)d << sh);
+      if (sh == 0) {
+        prefix = region_lo;
+        mask = 0xFFFFFFFFu;
+        kk -= before;
+        boundary_ties = true;
+        break;
+      }
+      if (inb <= kExtra) {
+        // finalize with the bucket's keys as extra candidates: region = [region_lo, +2^sh)
+        prefix = region_lo;
+        mask |= dmask << sh;
+        kk -= before;
+        break;
+      }
       prefix = region_lo;
       mask |= dmask << sh;
       kk -= before;
-      break;
+      top = sh - 1;
+      shift = top - 7;
     }
-    prefix = region_lo;
-    mask |= dmask << sh;
-    kk -= before;
-    top = sh - 1;
-    shift = top - 7;
-  }
-  // gather: every key below the region, then the region's keys (all of them when it is a
-  // small bucket; the first kk in index order when it is a single value)
-  const uint32_t region_lo = prefix;
-  int nsel = 0;
-  each_group([&](int j, uint32_t u, bool valid) {
-    const bool below = valid && u < region_lo;
-    const bool inreg = valid && (u & mask) == prefix;
-    bool take = below;
-    if (!boundary_ties) take = take || inreg;
-    const unsigned long long bt = __ballot(take);
-    if (take) {
-      const int pos = nsel + __popcll(bt & lt);
-      sel_k[pos] = u;
-      sel_j[pos] = j;
-    }
-    nsel += __popcll(bt);
-  });
-  if (boundary_ties) {
-    // the first kk keys equal to the boundary value, in index order
-    int taken = 0;
+    // gather: every key below the region, then the region's keys (all of them when it is a
+    // small bucket; the first kk in index order when it is a single value)
+    const uint32_t region_lo = prefix;
     each_group([&](int j, uint32_t u, bool valid) {
-      const bool inreg = valid && u == prefix;
-      const unsigned long long bt = __ballot(inreg);
-      const int r = __popcll(bt & lt);
-      if (inreg && taken + r < kk) {
-        sel_k[nsel + taken + r] = u;
-        sel_j[nsel + taken + r] = j;
+      const bool below = valid && u < region_lo;
+      const bool inreg = valid && (u & mask) == prefix;
+      bool take = below;
+      if (!boundary_ties) take = take || inreg;
+      const unsigned long long bt = __ballot(take);
+      if (take) {
+        const int pos = nsel + __popcll(bt & lt);
+        sel_k[pos] = u;
+        sel_j[pos] = j;
       }
-      taken = min(kk, taken + __popcll(bt));
+      nsel += __popcll(bt);
     });
-    nsel += taken;
+    if (boundary_ties) {
+      // the first kk keys equal to the boundary value, in index order
+      int taken = 0;
+      each_group([&](int j, uint32_t u, bool valid) {
+        const bool inreg = valid && u == prefix;
+        const unsigned long long bt = __ballot(inreg);
+        const int r = __popcll(bt & lt);
+        if (inreg && taken + r < kk) {
+          sel_k[nsel + taken + r] = u;
+          sel_j[nsel + taken + r] = j;
+        }
+        taken = min(kk, taken + __popcll(bt));
+      });
+      nsel += taken;
+    }
   }
   __builtin_amdgcn_wave_barrier();
   // rank sort by (key, index); the first np ranks are the probes
@@ -370,7 +434,6 @@ __global__ __launch_bounds__(kSelThreads) void select_kernel(const float *dist, 
     }
     if (r < np) probes[q * p_stride + r] = j;
   }
-  (void)dig;
 }
 
 void launch_select(const float *dist, int64_t ld, int32_t nlist, const int32_t *nprobe,
@@ -379,11 +442,8 @@ void launch_select(const float *dist, int64_t ld, int32_t nlist, const int32_t *
   if (nq <= 0) return;
   const size_t smem = 4 * select_wave_lds(p_stride);
   const dim3 grid((unsigned)((nq + 3) / 4));
-  if (nlist <= 1024)
-    hipLaunchKernelGGL(select_kernel<16>, grid, dim3(kSelThreads), smem, s, dist, ld, nlist, nprobe,
-                       nprobe_all, probes, p_stride, nq);
-  else if (nlist <= 4096)
-    hipLaunchKernelGGL(select_kernel<64>, grid, dim3(kSelThreads), smem, s, dist, ld, nlist, nprobe,
+  if (nlist <= 256)
+    hipLaunchKernelGGL(select_kernel<4>, grid, dim3(kSelThreads), smem, s, dist, ld, nlist, nprobe,
                        nprobe_all, probes, p_stride, nq);
   else
     hipLaunchKernelGGL(select_kernel<0>, grid, dim3(kSelThreads), smem, s, dist, ld, nlist, nprobe,
