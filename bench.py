@@ -41,20 +41,23 @@ CONFIGS = {
     "sift1m": dict(data="sift1m", nlist=4096, storage="f32", rotation="f32", k=10, nprobes=NPROBES,
                    serve=("frac", [0.25, 0.5])),
     # 1M x 960, stored BF16 (or FP16), query rotation on BF16 MFMA, 1,000 queries, K = 100,
-    # nprobe 64; per-result distance error against FP64 on the original data
+    # nprobe 64; per-result distance error against FP64 on the original data.  Correction
+    # tables at K_c = 10 and 100 (a K = 100 search uses the K_c = 100 table)
     "gist1m": dict(data="gist1m", nlist=4096, storage="bf16", rotation="bf16", k=100, nprobes=[64],
-                   error_vs_fp64=True, serve=None),
+                   fit=dict(calib_k_extra=(100,)), error_vs_fp64=True, serve=None),
     "gist1m-f16": dict(data="gist1m", nlist=4096, storage="f16", rotation="bf16", k=100, nprobes=[64],
-                       error_vs_fp64=True, serve=None),
+                       fit=dict(calib_k_extra=(100,)), error_vs_fp64=True, serve=None),
     # 2M x 768 unit-normalised FP16 with the FP8 E4M3 pre-stage over the leading 64 dims;
     # a step is 4 launches of 4,096 queries, each query with its own nprobe ~ U{8..256} and
     # K ~ U{10, 50, 100}
     "embed768": dict(data="embed768", nlist=4096, storage="f16", rotation="bf16", fp8=64,
                      uneven=dict(batches=4, batch=4096, nprobe=(8, 256), k=(10, 50, 100)),
-                     fit=dict(kmeans_train_per_list=64, kmeans_iters=10), serve=None),
+                     fit=dict(kmeans_train_per_list=64, kmeans_iters=10, calib_k_extra=(50, 100)),
+                     serve=None),
     # 5M x 256 unit-normalised FP16, IVF 16384: serving at absolute Poisson rates
     "embed256": dict(data="embed256", nlist=16384, storage="f16", rotation="f32", k=10,
-                     nprobes=[16, 32, 48, 64, 96, 128], fit=dict(kmeans_train_per_list=64, kmeans_iters=10),
+                     nprobes=[16, 32, 48, 64, 96, 128],
+                     fit=dict(kmeans_train_per_list=64, kmeans_iters=10, calib_k_extra=(50, 100)),
                      serve=("abs", [5e3, 1e4, 2e4, 3.5e4, 5e4]), gt_queries=2000),
 }
 
