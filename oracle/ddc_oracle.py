@@ -401,12 +401,29 @@ def partial_dists(Yc: np.ndarray, qrot: np.ndarray, bounds: np.ndarray) -> np.nd
     return cs[:, bounds - 1]
 
 
+def bsar_terms(qrot: np.ndarray, lam: np.ndarray, bounds: np.ndarray):
+    """Per test stage s (residual dims i >= d_s): ||q'_r||^2 and sigma_s = the standard
+    deviation of the omitted cross term -2 <q'_r, x_r>, sqrt(4 sum_i q'_i^2 lam_i), when x is
+    distributed with variance lam_i along rotated axis i [Eq. (2); Alg. 1 line 3]."""
+    q = np.asarray(qrot, dtype=np.float64)
+    qr = np.array([np.sum(q[d:] ** 2) for d in bounds[:-1]])
+    sig = np.array([math.sqrt(4.0 * np.sum(q[d:] ** 2 * lam[d:])) for d in bounds[:-1]])
+    return qr, sig
+
+
+def residual_norms(Yc: np.ndarray, bounds: np.ndarray) -> np.ndarray:
+    """||x_r||^2 = sum over the residual dims i >= d_s of x_i^2, per row and test stage."""
+    Yc = np.asarray(Yc, dtype=np.float64)
+    return np.column_stack([np.sum(Yc[:, d:] ** 2, axis=1) for d in bounds[:-1]]) \
+        if bounds.shape[0] > 1 else np.zeros((Yc.shape[0], 0))
+
+
 def _rel(a, b, c):
     return np.abs(a) + np.abs(b) + np.abs(c) + 1e-300
 
 
 def search_one(qrot, Y, list_off, list_ids, probes, k, m, beta, bounds, B=256, L=0,
-               prune=True, collect_neg=None, pre=None):
+               prune=True, collect_neg=None, pre=None, res=None):
     """Canonical block-synchronous pruned refinement for one rotated query.
 
     The paper's refinement updates tau after every candidate [Sec. I: result queue Q with
@@ -428,6 +445,10 @@ def search_one(qrot, Y, list_off, list_ids, probes, k, m, beta, bounds, B=256, L
     candidate's e_0 = sum over the coded lead dims of (q'_i - dec_i)^2 is tested with
     m0 e_0 + beta0 > tau_b; survivors restart at dim 0 on the stored values.  Then
     stop_counts has S + 1 entries, entry 0 counting the candidates the pre-stage pruned.
+    ``res`` = (qr, msig) replaces the stage test by the residual-estimate test of Alg. 2
+    (incremental): dis'_s = e_s + ||x_r||^2 + ||q'_r||^2 (equal to C1 - C2 of Alg. 1, the
+    exact distance without the cross term of the residual dims), pruned iff
+    dis'_s - m sigma_s > tau_b, with qr = ||q'_r||^2 and msig = m sigma_s per test stage.
     """
     S = bounds.shape[0]
     T_d = np.zeros(0)
@@ -456,14 +477,21 @@ def search_one(qrot, Y, list_off, list_ids, probes, k, m, beta, bounds, B=256, L
                 if rel0.size:
                     margin = min(margin, float(rel0.min()))
             if prune and math.isfinite(tau_b) and S > 1:
-                lhs = e[:, :S - 1] * m[None, :] + beta[None, :]   # (nb, S-1)
+                if res is None:
+                    lhs = e[:, :S - 1] * m[None, :] + beta[None, :]   # (nb, S-1)
+                    scale = _rel(e[:, :S - 1] * m[None, :], beta[None, :], tau_b)
+                else:
+                    qr, msig = res
+                    xr = residual_norms(Y[ids], bounds)
+                    lhs = e[:, :S - 1] + xr + qr[None, :] - msig[None, :]
+                    scale = np.abs(e[:, :S - 1]) + xr + qr[None, :] + msig[None, :] + abs(tau_b)
                 hit = lhs > tau_b
                 any_hit = hit.any(axis=1)
                 first = np.where(any_hit, hit.argmax(axis=1), S - 1)
                 stop = first
                 # decision margins of every evaluated test (stages <= stop)
                 evaluated = (np.arange(S - 1)[None, :] <= first[:, None]) & ~pre_hit[:, None]
-                rel = np.abs(lhs - tau_b) / _rel(e[:, :S - 1] * m[None, :], beta[None, :], tau_b)
+                rel = np.abs(lhs - tau_b) / scale
                 if evaluated.any():
                     margin = min(margin, float(rel[evaluated].min()))
             np.add.at(stop_counts, stop[~pre_hit] + P, 1)
@@ -498,7 +526,7 @@ def search_one(qrot, Y, list_off, list_ids, probes, k, m, beta, bounds, B=256, L
     return ids_out, d_out, stop_counts, margin
 
 
-def search_sequential(qrot, Y, list_off, list_ids, probes, k, m, beta, bounds, pre=None):
+def search_sequential(qrot, Y, list_off, list_ids, probes, k, m, beta, bounds, pre=None, res=None):
     """The paper's per-candidate refinement, coded separately: a binary max-heap Q of the
     K best (dis, id); tau = its root once it holds K entries; each candidate walks the
     stages and is pruned at the first stage with m_s e_s + beta_s > tau, otherwise enters
@@ -528,9 +556,17 @@ def search_sequential(qrot, Y, list_off, list_ids, probes, k, m, beta, bounds, p
                     t = q[i] - Y[x, i]
                     acc += t * t
                 lo = hi
-                if s < S - 1 and tau != math.inf and m[s] * acc + beta[s] > tau:
-                    pruned = True
-                    break
+                if s < S - 1 and tau != math.inf:
+                    if res is None:
+                        test = m[s] * acc + beta[s] > tau
+                    else:       # C1 - C2 - m sigma > tau, C1 - C2 = acc + ||x_r||^2 + ||q_r||^2
+                        xr = 0.0
+                        for i in range(hi, Y.shape[1]):
+                            xr += Y[x, i] * Y[x, i]
+                        test = acc + xr + res[0][s] - res[1][s] > tau
+                    if test:
+                        pruned = True
+                        break
             if pruned:
                 continue
             item = (-acc, -x)
@@ -762,8 +798,10 @@ def table_for_k(index, k):
 
 
 def search(index, queries, k, nprobe, alpha, mode="learned", B=None, L=None, calib_mode="joint"):
-    """Search every query; mode in {'learned', 'lossless', 'none', 'ads'} ('ads': the
-    ADSampling test of ``ads_table`` with index["ads_eps0"], default 2.1).
+    """Search every query; mode in {'learned', 'lossless', 'none', 'ads', 'bsar'} ('ads': the
+    ADSampling test of ``ads_table`` with index["ads_eps0"], default 2.1; 'bsar': the
+    residual-estimate test with multiplier index["bsar_m"], default 8, or Phi^-1(1 - alpha)
+    when that is <= 0).
     Returns ids (nq, k), dists (nq, k), stop_counts (nq, S), margin (nq,)."""
     B = index["B"] if B is None else B
     L = index["L"] if L is None else L
@@ -784,6 +822,9 @@ def search(index, queries, k, nprobe, alpha, mode="learned", B=None, L=None, cal
     elif mode == "ads":
         m, beta = ads_table(bounds, index["Y"].shape[1], index.get("ads_eps0", 2.1))
         prune = True
+    elif mode == "bsar":
+        m, beta, prune = np.ones(St), np.zeros(St), True
+        mult = bsar_multiplier(alpha, index.get("bsar_m", 8.0))
     elif mode == "none":
         m, beta, prune = np.ones(St), np.zeros(St), False
     else:
@@ -798,11 +839,25 @@ def search(index, queries, k, nprobe, alpha, mode="learned", B=None, L=None, cal
     for qi in range(nq):
         probes, _, pm = probe_order(Qr[qi], index["centroids"], nprobe)
         probes_all[qi] = probes
+        res = None
+        if mode == "bsar":
+            qr, sig = bsar_terms(Qr[qi], index["lam"], bounds)
+            res = (qr, mult * sig)
         i, d, st, mg = search_one(Qr[qi], index["Y"], index["list_off"], index["list_ids"], probes,
-                                  k, m, beta, bounds, B, L, prune, pre=pre if prune else None)
+                                  k, m, beta, bounds, B, L, prune, pre=pre if prune else None, res=res)
         ids[qi], ds[qi], stops[qi], margins[qi] = i, d, st, min(mg, pm)
     return dict(ids=ids, dists=ds, stops=stops, margin=margins, probes=probes_all, qrot=Qr, m=m,
                 beta=beta)
+
+
+def bsar_multiplier(alpha: float, m: float) -> float:
+    """The multiplier of the residual test: m itself when m > 0 (the paper fixes m per data
+    set, Sec. VII-A), else the one-sided Gaussian quantile Phi^-1(1 - alpha) of the error
+    model of Eq. (2) (Lemma 2: the quantile shrinks with the variance)."""
+    if m > 0:
+        return float(m)
+    from statistics import NormalDist
+    return NormalDist().inv_cdf(1.0 - alpha)
 
 
 def recall_at(ids: np.ndarray, gt: np.ndarray, k: int = 10) -> float:

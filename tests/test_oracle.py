@@ -614,3 +614,64 @@ def test_ads_test_is_safe_on_isotropic_data_and_exact_for_large_eps(small_worklo
     big = dict(ix, ads_eps0=1e6)
     b = O.search(big, Q, 10, 16, 0.0, mode="ads")
     assert b["ids"].tolist() == n["ids"].tolist() and b["stops"][:, :-1].sum() == 0
+
+
+# ----------------------------------------------------------------------------- residual estimate (Alg. 1/2)
+
+def test_eq2_residual_cross_term_is_gaussian_with_predicted_variance(small_workload):
+    """Eq. (2): for a fixed query, 2 <q'_r, x_r> over the data is N(0, 4 sum_{i>d} q_i^2 lam_i)
+    on the Gaussian workload (KS test against N(0, 1) after dividing by sigma)."""
+    import scipy.stats as st
+    p = O.pca_fit(small_workload["base"])
+    Y = O.rotate(small_workload["base"], p["mu"], p["R"])
+    Qr = O.rotate(small_workload["val"][:3], p["mu"], p["R"])
+    b = O.stage_bounds(128, 32)
+    for q in Qr:
+        _, sig = O.bsar_terms(q, p["lam"], b)
+        for s, d in enumerate(b[:-1]):
+            z = 2 * (Y[:, d:] @ q[d:]) / sig[s]
+            assert st.kstest(z, "norm").pvalue > 0.01
+            assert abs(z.std() - 1) < 0.02 and abs(z.mean()) < 0.05
+
+
+def test_residual_estimate_plus_cross_term_is_the_distance(small_workload):
+    """C1 - C2 - C3 = dis (Alg. 1): e_s + ||x_r||^2 + ||q_r||^2 - 2 <q_r, x_r> == ||x - q||^2."""
+    p = O.pca_fit(small_workload["base"])
+    Y = O.rotate(small_workload["base"][:500], p["mu"], p["R"])
+    q = O.rotate(small_workload["val"][:1], p["mu"], p["R"])[0]
+    b = O.stage_bounds(128, 32)
+    e = O.partial_dists(Y, q, b)
+    xr = O.residual_norms(Y, b)
+    qr, _ = O.bsar_terms(q, p["lam"], b)
+    for s, d in enumerate(b[:-1]):
+        est = e[:, s] + xr[:, s] + qr[s] - 2 * (Y[:, d:] @ q[d:])
+        np.testing.assert_allclose(est, e[:, -1], rtol=1e-11)
+
+
+def test_residual_test_block_of_one_equals_sequential(small_index, small_workload):
+    ix = small_index
+    b = ix["bounds"]
+    for qv in small_workload["queries"][:10]:
+        qr_, sig = O.bsar_terms(O.rotate(qv[None], ix["mu"], ix["R"])[0], ix["lam"], b)
+        q = O.rotate(qv[None], ix["mu"], ix["R"])[0]
+        probes, _, _ = O.probe_order(q, ix["centroids"], 8)
+        res = (qr_, 2.0 * sig)
+        one = np.ones(b.shape[0] - 1)
+        a = O.search_one(q, ix["Y"], ix["list_off"], ix["list_ids"], probes, 10, one, 0 * one, b,
+                         B=1, L=0, res=res)
+        c = O.search_sequential(q, ix["Y"], ix["list_off"], ix["list_ids"], probes, 10, one, 0 * one,
+                                b, res=res)
+        assert a[0].tolist() == c[0].tolist()
+        np.testing.assert_array_equal(a[1], c[1])
+
+
+def test_residual_test_prunes_and_huge_multiplier_is_exact(small_index, small_workload):
+    Q = small_workload["queries"]
+    n = O.search(small_index, Q, 10, 8, 0.0, mode="none")
+    r = O.search(dict(small_index, bsar_m=3.0), Q, 10, 8, 0.0, mode="bsar")
+    assert r["stops"][:, :-1].sum() > 0.3 * r["stops"].sum()
+    same = np.mean([len(set(x) & set(y)) / 10 for x, y in zip(n["ids"], r["ids"])])
+    assert same > 0.98
+    h = O.search(dict(small_index, bsar_m=1e12), Q, 10, 8, 0.0, mode="bsar")
+    assert h["ids"].tolist() == n["ids"].tolist() and h["stops"][:, :-1].sum() == 0
+    assert abs(O.bsar_multiplier(0.05, 0.0) - 1.6448536269514722) < 1e-9
