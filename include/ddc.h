@@ -65,8 +65,13 @@ typedef enum { DDC_ROT_F32 = 0, DDC_ROT_BF16 = 1 } ddc_rot;
  *  NONE    : no test; every candidate is refined (full-D scan)
  *  ADS     : the random-projection test of ADSampling (Sec. III): prune iff
  *            (D / d_s) e_s > (1 + eps0 / sqrt(d_s))^2 tau, eps0 set by ddc_set_ads_epsilon
- *            (2.1 by default); meant for a DDC_PROJ_HAAR index; significance is ignored   */
-typedef enum { DDC_CORR_LEARNED = 0, DDC_CORR_LOSSLESS = 1, DDC_CORR_NONE = 2, DDC_CORR_ADS = 3 } ddc_corr;
+ *            (2.1 by default); meant for a DDC_PROJ_HAAR index; significance is ignored
+ *  BSAR    : the residual estimate of Alg. 1/2: prune iff e_s + ||x_r||^2 + ||q'_r||^2 -
+ *            m sigma_s > tau with sigma_s = sqrt(4 sum_{i > d_s} q'_i^2 lambda_i) (Eq. (2));
+ *            m from ddc_set_bsar_multiplier (8 by default), or Phi^-1(1 - significance)
+ *            when that is set <= 0; needs the eigenvalues (fit, or lam on import)           */
+typedef enum { DDC_CORR_LEARNED = 0, DDC_CORR_LOSSLESS = 1, DDC_CORR_NONE = 2, DDC_CORR_ADS = 3,
+               DDC_CORR_BSAR = 4 } ddc_corr;
 
 /* Rotation learned by the fit: PCA (Sec. IV-B, Thm. 1) or, for the ablation of Sec. III /
  * IV-B, a Haar-distributed random rotation drawn from the fit seed. */
@@ -238,6 +243,9 @@ ddc_status ddc_get_kernel_timing(ddc_index *ix, double *ms_total, int64_t *launc
 
 /* eps0 of the DDC_CORR_ADS test (> 0; 2.1 by default, the value the paper uses for it). */
 ddc_status ddc_set_ads_epsilon(ddc_index *ix, double eps0);
+/* Multiplier m of the DDC_CORR_BSAR test (8 by default, the paper's value for SIFT, GIST and
+ * DEEP; m <= 0: m = Phi^-1(1 - significance) per search). */
+ddc_status ddc_set_bsar_multiplier(ddc_index *ix, double m);
 
 /* Launch shape of the pruned scan (A3-A5).  None of these changes any result bit (every
  * candidate's partial distances are summed in the same order in every variant); they only

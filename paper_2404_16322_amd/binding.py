@@ -13,7 +13,7 @@ _LOCK = threading.Lock()
 
 DTYPE = {"f32": 0, "f16": 1, "bf16": 2}
 ROT = {"f32": 0, "bf16": 1}
-CORR = {"learned": 0, "lossless": 1, "none": 2, "ads": 3}
+CORR = {"learned": 0, "lossless": 1, "none": 2, "ads": 3, "bsar": 4}
 PROJ = {"pca": 0, "haar": 1}
 CALIB = {"joint": 0, "bonferroni": 1}
 STATUS = {0: "DDC_OK", -1: "DDC_EINVAL", -2: "DDC_ENOMEM", -3: "DDC_EDEVICE", -4: "DDC_EIO",
@@ -24,7 +24,7 @@ SYMBOLS = ["ddc_fit_params_default", "ddc_fit", "ddc_import", "ddc_export", "ddc
            "ddc_debug_intermediates", "ddc_set_kernel_timing", "ddc_get_kernel_timing", "ddc_free",
            "ddc_last_error", "ddc_server_create", "ddc_server_submit", "ddc_server_poll",
            "ddc_server_get_stats", "ddc_server_destroy", "ddc_set_launch", "ddc_get_launch",
-           "ddc_scan_variant", "ddc_save", "ddc_load", "ddc_set_ads_epsilon"]
+           "ddc_scan_variant", "ddc_save", "ddc_load", "ddc_set_ads_epsilon", "ddc_set_bsar_multiplier"]
 
 
 class FitParams(C.Structure):
@@ -123,6 +123,7 @@ def load_library():
         lib.ddc_set_kernel_timing.argtypes = [vp, C.c_int]
         lib.ddc_get_kernel_timing.argtypes = [vp, vp, vp, C.c_int]
         lib.ddc_set_ads_epsilon.argtypes = [vp, f64]
+        lib.ddc_set_bsar_multiplier.argtypes = [vp, f64]
         lib.ddc_save.argtypes = [vp, C.c_char_p]
         lib.ddc_load.argtypes = [C.c_char_p, C.POINTER(vp)]
         lib.ddc_set_launch.argtypes = [vp, C.POINTER(LaunchParams)]
@@ -341,6 +342,9 @@ class Index:
             self._h, d_queries, nq, d_k or None, k_all, k_max, d_nprobe or None, nprobe_all,
             nprobe_max, alpha, CORR[mode], d_offsets or None, d_ids, d_dists, d_counters or None,
             stream or None))
+
+    def set_bsar_multiplier(self, m: float):
+        _check(load_library().ddc_set_bsar_multiplier(self._h, m))
 
     def set_ads_epsilon(self, eps0: float):
         _check(load_library().ddc_set_ads_epsilon(self._h, eps0))

@@ -32,10 +32,13 @@ static int ceil_log2(int64_t v) {
   return r;
 }
 
-static std::array<int, 4> tune_class(int64_t nq, int np_max, int k_max, int prune) {
+static std::array<int, 4> tune_class(int64_t nq, int np_max, int k_max, int kind) {
   return {ceil_log2(std::max<int64_t>(nq, 1)), ceil_log2(std::max(np_max, 1)),
-          ceil_log2(std::max(k_max, 1)), prune};
+          ceil_log2(std::max(k_max, 1)), kind};
 }
+
+// kernel family of a launch: pruned or not, FP8 pre-stage, residual test
+static int scan_kind(const ScanArgs &a) { return a.prune + 2 * a.pre + 4 * a.res; }
 
 // Without measurements: a workgroup per query while the batch leaves the chip's wave slots
 // mostly empty, and multi-block loads once vectors span eight or more dim blocks.
@@ -43,19 +46,20 @@ static std::pair<int, int> fixed_variant(const ddc_index *ix, int64_t nq, int pr
   return {nq < 4096 ? 4 : 1, prune && ix->NB >= 8 ? 1 : 0};
 }
 
-static std::pair<int, int> forced_or(const ddc_index *ix, std::pair<int, int> v, int prune) {
+static std::pair<int, int> forced_or(const ddc_index *ix, std::pair<int, int> v, int kind) {
   if (ix->waves_per_query) v.first = ix->waves_per_query;
   if (ix->lookahead >= 0) v.second = ix->lookahead;
-  if (!prune) v.second = 0;
+  if (!(kind & 1) || (kind & 4)) v.second = 0;   // look-ahead only for the learned/fixed-table tests
   return v;
 }
 
 // Sets a.waves_per_query / a.lookahead.  An untuned class is timed on this very launch (each
 // candidate twice, counters off; every candidate writes the same results), then cached.
 static void choose_variant(ddc_index *ix, ScanArgs &a, int np_max, hipStream_t s) {
-  const auto key = tune_class(a.nq, np_max, a.k_max, a.prune);
+  const int kind = scan_kind(a);
+  const auto key = tune_class(a.nq, np_max, a.k_max, kind);
   std::pair<int, int> v = fixed_variant(ix, a.nq, a.prune);
-  const bool need_w = ix->waves_per_query == 0, need_l = a.prune && ix->lookahead < 0;
+  const bool need_w = ix->waves_per_query == 0, need_l = a.prune && !a.res && ix->lookahead < 0;
   if (need_w || need_l) {
     std::lock_guard<std::mutex> lk(ix->tune_mtx);
     auto it = ix->tuned.find(key);
@@ -68,7 +72,7 @@ static void choose_variant(ddc_index *ix, ScanArgs &a, int np_max, hipStream_t s
         std::vector<std::pair<int, int>> cand;
         for (int w : {1, 4})
           for (int l : {0, 1}) {
-            auto c = forced_or(ix, {w, l}, a.prune);
+            auto c = forced_or(ix, {w, l}, kind);
             if (std::find(cand.begin(), cand.end(), c) == cand.end()) cand.push_back(c);
           }
         hipEvent_t e0, e1;
@@ -96,9 +100,19 @@ static void choose_variant(ddc_index *ix, ScanArgs &a, int np_max, hipStream_t s
       }
     }
   }
-  v = forced_or(ix, v, a.prune);
+  v = forced_or(ix, v, kind);
   a.waves_per_query = v.first;
   a.lookahead = v.second;
+}
+
+// Phi^-1(p) by bisection on Phi(x) = erfc(-x / sqrt 2) / 2 (monotone), to double precision.
+static double normal_quantile(double p) {
+  double lo = -40.0, hi = 40.0;
+  for (int i = 0; i < 200; ++i) {
+    const double mid = 0.5 * (lo + hi);
+    if (0.5 * std::erfc(-mid / std::sqrt(2.0)) < p) lo = mid; else hi = mid;
+  }
+  return 0.5 * (lo + hi);
 }
 
 static thread_local std::string g_err;
@@ -182,6 +196,14 @@ static void upload_index(ddc_index *ix, const float *d_Y, hipStream_t s) {
   const size_t packed = (size_t)ix->total_tiles * ix->NB * kTile * kBlockDims * ix->esize();
   ix->d_base.alloc(std::max<size_t>(packed, 16));
   launch_pack(d_Y, Dp, D, ix->NB, d_slot.as<int64_t>(), ix->total_tiles, ix->d_base.p, ix->store(), s);
+  ix->d_xnorm.alloc(std::max<size_t>((size_t)ix->total_tiles * kTile * 4, 16));
+  launch_slot_sqnorm(ix->d_base.p, ix->store(), ix->NB, ix->total_tiles, ix->d_xnorm.as<float>(), s);
+  {
+    std::vector<float> lam32(Dp, 0.f);
+    for (int i = 0; i < D && i < (int)ix->lam.size(); ++i) lam32[i] = (float)ix->lam[i];
+    ix->d_lam32.alloc(lam32.size() * 4);
+    HIPC(hipMemcpy(ix->d_lam32.p, lam32.data(), lam32.size() * 4, hipMemcpyHostToDevice));
+  }
   if (ix->fp8) {
     ix->d_base8.alloc(std::max<size_t>((size_t)ix->total_tiles * kTile * kFp8Lead, 16));
     ix->d_scale8.alloc(std::max<size_t>((size_t)ix->total_tiles * 4, 16));
@@ -511,7 +533,14 @@ void ddc::search_device(ddc_index *ix, const float *d_q, int64_t nq, const int32
   // LOSSLESS tests e_s > tau with the stored values only: the FP8 estimate is no lower bound;
   // ADS is a fixed table on the stored values too
   const bool lossless = (mode == DDC_CORR_LOSSLESS || mode == DDC_CORR_ADS) && ix->St > 0;
-  if (learned || lossless) {
+  if (mode == DDC_CORR_BSAR && ix->St > 0) {
+    a.prune = 1;
+    a.res = 1;
+    a.xnorm = ix->d_xnorm.as<float>();
+    a.lam = ix->d_lam32.as<float>();
+    a.bsar_m = (float)(ix->bsar_m > 0 ? ix->bsar_m : normal_quantile(1.0 - alpha));
+    for (int j = 0; j < ix->St; ++j) a.test_after[((j + 1) * ix->delta_d) / kBlockDims - 1] = 1;
+  } else if (learned || lossless) {
     a.prune = 1;
     tabs = device_tables(ix, alpha, mode, &a.ntab);
     a.tab = tabs->as<float>();
@@ -597,8 +626,12 @@ static ddc_status check_search_args(const ddc_index *ix, int64_t nq, double alph
   if (nq < 0) return set_err(DDC_EINVAL, "nq must be >= 0");
   if (!(alpha >= 0.0 && alpha < 1.0)) return set_err(DDC_EINVAL, "significance must be in [0, 1)");
   if (mode != DDC_CORR_LEARNED && mode != DDC_CORR_LOSSLESS && mode != DDC_CORR_NONE &&
-      mode != DDC_CORR_ADS)
+      mode != DDC_CORR_ADS && mode != DDC_CORR_BSAR)
     return set_err(DDC_EINVAL, "unknown correction mode %d", (int)mode);
+  if (mode == DDC_CORR_BSAR && (int)ix->lam.size() != ix->D)
+    return set_err(DDC_EINVAL, "the residual test needs the rotation's eigenvalues (lam)");
+  if (mode == DDC_CORR_BSAR && ix->bsar_m <= 0 && !(alpha > 0))
+    return set_err(DDC_EINVAL, "the residual test with m from the significance needs significance > 0");
   if (mode == DDC_CORR_LEARNED && alpha > 0 && ix->Tt() > 0 && ix->tables.empty())
     return set_err(DDC_EINVAL, "index has no calibrated correction table (use LOSSLESS/NONE or calibrate)");
   return DDC_OK;
@@ -1133,6 +1166,13 @@ ddc_status ddc_get_kernel_timing(ddc_index *ix, double *ms_total, int64_t *launc
   GUARD_END
 }
 
+ddc_status ddc_set_bsar_multiplier(ddc_index *ix, double m) {
+  if (!ix) return set_err(DDC_EINVAL, "index is NULL");
+  if (!std::isfinite(m)) return set_err(DDC_EINVAL, "m must be finite");
+  ix->bsar_m = m;
+  return DDC_OK;
+}
+
 ddc_status ddc_set_ads_epsilon(ddc_index *ix, double eps0) {
   if (!ix) return set_err(DDC_EINVAL, "index is NULL");
   if (!(eps0 > 0.0) || !std::isfinite(eps0)) return set_err(DDC_EINVAL, "eps0 must be > 0");
@@ -1170,15 +1210,18 @@ ddc_status ddc_scan_variant(ddc_index *ix, int64_t nq, int32_t k_max, int32_t np
                             ddc_corr mode, int32_t *waves, int32_t *lookahead) {
   if (!ix || !waves || !lookahead) return set_err(DDC_EINVAL, "NULL argument");
   if (nq < 1 || k_max < 1 || nprobe_max < 1) return set_err(DDC_EINVAL, "sizes must be >= 1");
-  const int prune = mode == DDC_CORR_LEARNED ? ix->Tt() > 0 : (mode == DDC_CORR_LOSSLESS && ix->St > 0);
+  // the kernel family a search in this mode launches (significance > 0 assumed for LEARNED)
+  const int prune = mode == DDC_CORR_LEARNED ? ix->Tt() > 0 : (mode != DDC_CORR_NONE && ix->St > 0);
+  const int kind = prune + 2 * (mode == DDC_CORR_LEARNED && ix->P() ? 1 : 0) +
+                   4 * (mode == DDC_CORR_BSAR && prune ? 1 : 0);
   const int64_t nqc = std::min<int64_t>(nq, 32768);
   std::pair<int, int> v = fixed_variant(ix, nqc, prune);
   {
     std::lock_guard<std::mutex> lk(ix->tune_mtx);
-    auto it = ix->tuned.find(tune_class(nqc, nprobe_max, k_max, prune));
+    auto it = ix->tuned.find(tune_class(nqc, nprobe_max, k_max, kind));
     if (it != ix->tuned.end()) v = it->second;
   }
-  v = forced_or(ix, v, prune);
+  v = forced_or(ix, v, kind);
   *waves = v.first;
   *lookahead = v.second;
   return DDC_OK;

@@ -46,6 +46,10 @@ struct ScanArgs {
   const uint8_t *base8;    // FP8 pre-stage codes: per tile 64 vectors x 64 B (NULL if none)
   const float *scale8;     // per tile decode scale
   int32_t pre;             // 1: run the FP8 pre-stage test first
+  int32_t res;             // 1: residual-estimate test (needs xnorm, lam, bsar_m; one stage per load)
+  const float *xnorm;      // [tiles * 64] ||y||^2 of every stored slot
+  const float *lam;        // [nblocks * 32] variance along every rotated axis (0 beyond D)
+  float bsar_m;            // multiplier m of m sigma
   int32_t waves_per_query; // 1 or 4 (result-invariant)
   int32_t lookahead;       // 0 or 1: multi-stage loads when few candidates survive (result-invariant)
   int32_t nq, nblocks, block_b, prune, nlist, k_max;
@@ -124,6 +128,9 @@ void launch_refine64(const double *qrot, int32_t D, const void *base, int store,
 // (max |y| / 448); codes: [tiles x 64 vectors x 64] bytes, scale: [tiles].
 void launch_encode_fp8(const void *base, int store, int32_t nblocks, int64_t total_tiles,
                        uint8_t *codes, float *scale, hipStream_t s);
+// ||y||^2 of every stored slot: out [tiles x 64].
+void launch_slot_sqnorm(const void *base, int store, int32_t nblocks, int64_t total_tiles, float *out,
+                        hipStream_t s);
 // FP64 pre-stage feature e_0 = sum_{i<64} (q_i - dec_i)^2 of (query, packed slot) pairs,
 // dec = fp32(value(code) * scale).
 void launch_features8(const double *qrot, int32_t D, const uint8_t *codes, const float *scale,

@@ -319,4 +319,23 @@ void launch_features8(const double *qrot, int32_t D, const uint8_t *codes, const
                      D, codes, scale, pair_q, pair_slot, npairs, out, out_stride);
 }
 
+// ||y||^2 of every stored slot of the packed base (FP64 sum, stored as float).
+__global__ void slot_sqnorm_kernel(const void *base, int store, int32_t nblocks, float *out) {
+  const int64_t t = blockIdx.x;
+  const int v = threadIdx.x;
+  double acc = 0.0;
+  for (int d = 0; d < nblocks * kBlockDims; ++d) {
+    const double x = packed_value(base, store, nblocks, t, v, d);
+    acc += x * x;
+  }
+  out[t * kTile + v] = (float)acc;
+}
+
+void launch_slot_sqnorm(const void *base, int store, int32_t nblocks, int64_t total_tiles, float *out,
+                        hipStream_t s) {
+  if (total_tiles <= 0) return;
+  hipLaunchKernelGGL(slot_sqnorm_kernel, dim3((unsigned)total_tiles), dim3(kTile), 0, s, base, store,
+                     nblocks, out);
+}
+
 }  // namespace ddc

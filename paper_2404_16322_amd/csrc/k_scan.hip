@@ -131,10 +131,11 @@ __device__ inline unsigned long long lane_mask_lt() {
 // staged scan and the per-dim-block test table (m, beta; beta = -inf where no test follows).
 struct Lds {
   size_t q, td, ti, sd, si, cnt, query_bytes;
-  size_t ac, ae, mb, wave_bytes;
+  size_t ac, ae, ap, mb, wave_bytes;
 };
 __host__ __device__ inline size_t align16(size_t b) { return (b + 15) & ~(size_t)15; }
-__host__ __device__ inline Lds lds_layout(int Dp, int kmax, int block_b, int W) {
+// res: the alive lists also carry each survivor's running sum of squared coordinates
+__host__ __device__ inline Lds lds_layout(int Dp, int kmax, int block_b, int W, bool res) {
   Lds l;
   size_t o = 0;
   l.q = o; o += align16((size_t)Dp * 4);
@@ -148,20 +149,22 @@ __host__ __device__ inline Lds lds_layout(int Dp, int kmax, int block_b, int W) 
   o = 0;
   l.ac = o; o += align16((size_t)2 * seg * 2);
   l.ae = o; o += align16((size_t)2 * seg * 4);
+  l.ap = o; o += res ? align16((size_t)2 * seg * 4) : 0;
   l.mb = o; o += align16((size_t)2 * (Dp / kBlockDims + 1) * 4);
   l.wave_bytes = o;
   return l;
 }
-__host__ __device__ inline size_t scan_lds_bytes(int Dp, int kmax, int block_b, int W) {
-  const Lds l = lds_layout(Dp, kmax, block_b, W);
+__host__ __device__ inline size_t scan_lds_bytes(int Dp, int kmax, int block_b, int W, bool res) {
+  const Lds l = lds_layout(Dp, kmax, block_b, W, res);
   return (size_t)(4 / W) * l.query_bytes + 4 * l.wave_bytes;
 }
 
 // W waves per query (W = 1: four queries per workgroup, no workgroup barrier at all; W = 4:
 // one query per workgroup, each block's tiles split over the four waves, survivors merged
 // by the workgroup between two barriers).  LOOK enables the multi-stage look-ahead; PRE the
-// FP8 pre-stage over the leading 64 dims before the first stage.
-template <int ST, bool PRUNE, bool LOOK, int W, bool PRE>
+// FP8 pre-stage over the leading 64 dims before the first stage; RES the residual-estimate
+// test of Alg. 2 instead of the learned one (one stage per load).
+template <int ST, bool PRUNE, bool LOOK, int W, bool PRE, bool RES>
 __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4, 8))) void scan_kernel(ScanArgs a) {
   using S = Store<ST>;
   constexpr int EPL = 16 / S::kBytes;          // elements per lane load
@@ -194,7 +197,7 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
   const int B = a.block_b;
   const int KM = a.k_max;
   const int SEG = W == 1 ? B : kTile;
-  const Lds L = lds_layout(Dp, KM, B, W);
+  const Lds L = lds_layout(Dp, KM, B, W, RES);
   unsigned char *ql = smem + (size_t)qs * L.query_bytes;
   unsigned char *wl = smem + (size_t)QPW * L.query_bytes + (size_t)wave * L.wave_bytes;
   float *s_q = reinterpret_cast<float *>(ql + L.q);
@@ -205,6 +208,7 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
   int32_t *s_cnt = reinterpret_cast<int32_t *>(ql + L.cnt);
   uint16_t *s_ac = reinterpret_cast<uint16_t *>(wl + L.ac);
   float *s_ae = reinterpret_cast<float *>(wl + L.ae);
+  float *s_ap = reinterpret_cast<float *>(wl + L.ap);
   float *s_mb = reinterpret_cast<float *>(wl + L.mb);
 
   const int K = __builtin_amdgcn_readfirstlane(a.k ? a.k[q] : a.k_all);
@@ -213,7 +217,7 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
   const int qt = wsub * 64 + lane;             // thread index within the query's waves
   for (int i = qt; i < Dp; i += 64 * W) s_q[i] = qg[i];
   if (qt < 2) s_cnt[qt] = 0;
-  if (PRUNE) {
+  if (PRUNE && !RES) {
     // this query's correction table (by its K) into the wave's LDS
     int tsel = 0;
     for (int t = 1; t < a.ntab; ++t)
@@ -222,6 +226,31 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
     for (int i = lane; i < 2 * (nb + 1); i += 64) s_mb[i] = tq[i];
   }
   if (W > 1) __syncthreads(); else __builtin_amdgcn_wave_barrier();
+  if (RES) {
+    // per dim block b: ||q'_r||^2 - m sigma over the residual dims >= 32 (b + 1), with
+    // sigma = sqrt(4 sum q'_i^2 lam_i) (Eq. (2)); block sums first, then suffix sums
+    for (int b = lane; b < nb; b += 64) {
+      float s2 = 0.f, sl = 0.f;
+      for (int e = 0; e < kBlockDims; ++e) {
+        const float v = s_q[b * kBlockDims + e];
+        s2 = fmaf(v, v, s2);
+        sl = fmaf(v * v, a.lam[b * kBlockDims + e], sl);
+      }
+      s_mb[2 * b] = s2;
+      s_mb[2 * b + 1] = sl;
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (lane == 0) {
+      float c2 = 0.f, cl = 0.f;
+      for (int b = nb - 1; b >= 0; --b) {
+        const float s2 = s_mb[2 * b], sl = s_mb[2 * b + 1];
+        s_mb[2 * b] = c2 - a.bsar_m * 2.f * sqrtf(fmaxf(cl, 0.f));
+        c2 += s2;
+        cl += sl;
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
 
   // statistics (wave-uniform, flushed once when counters are requested)
   int64_t st_cand = 0, st_ref = 0, st_slices = 0, st_pre = 0, st_pre_pruned = 0;
@@ -268,6 +297,7 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
       const int slen = W == 1 ? blen : min(kTile, blen - s0);
       const unsigned char *bbase = lbase + (int64_t)((bs + s0) / kTile) * nb * BLOCK_BYTES;
       const int32_t *bids = lids + bs + s0;
+      const float *xnorm_seg = RES ? a.xnorm + (int64_t)a.tile_off[lst] * kTile + bs + s0 : nullptr;
       // In a load group, chunk c, lane (sub, g) reads dims [g*EPL, g*EPL+EPL) of candidate
       // t0 + c*CPW + sub; after transpose_sum the lane owns candidate t0 + g*CPW + sub.
       if (!PRUNE || tn < K) {
@@ -477,6 +507,7 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
           const unsigned char *bp = bbase + b * BLOCK_BYTES + g * 16;
           const uint16_t *alive = s_ac + cur * SEG;
           const float *alive_e = s_ae + cur * SEG;
+          const float *alive_p = s_ap + cur * SEG;
           const bool direct = b == 0 && !listed;
           int nnext = 0;
           int pruned = 0;
@@ -491,18 +522,20 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
                                    (uint32_t)((cd % kTile) * SLICE);
               v[c] = *reinterpret_cast<const uint4 *>(bp + off);
             }
-            float part[MAXCH];
+            float part[MAXCH], partp[MAXCH];
 #pragma unroll
             for (int c = 0; c < MAXCH; ++c) {
               float f[EPL];
               S::unpack(v[c], f);
-              float acc = 0.f;
+              float acc = 0.f, accp = 0.f;
 #pragma unroll
               for (int e = 0; e < EPL; ++e) {
                 const float d = f[e] - qv[e];
                 acc = fmaf(d, d, acc);
+                if (RES) accp = fmaf(f[e], f[e], accp);
               }
               part[c] = acc;
+              partp[c] = accp;
             }
             const float tot = transpose_sum<G>(part, g);
             const int idx = t0 + g * CPW + sub;
@@ -510,8 +543,22 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
             const int ci = min(idx, SEG - 1);
             const int cand = direct ? idx : (int)alive[ci];
             const float ev = direct ? tot : alive_e[ci] + tot;
+            float pv = 0.f;   // RES: sum of the candidate's squared coordinates so far
+            if (RES) {
+              const float totp = transpose_sum<G>(partp, g);
+              pv = direct ? totp : alive_p[ci] + totp;
+            }
             bool keep = valid;
-            if (test) keep = keep && !(fmaf(mb, ev, bb) > tau);
+            if (test) {
+              if (RES) {
+                // dis' = e_s + ||x_r||^2 + ||q'_r||^2 (C1 - C2 of Alg. 1); prune iff
+                // dis' - m sigma > tau (Alg. 2)
+                const float xn = valid ? xnorm_seg[cand] : 0.f;
+                keep = keep && !(ev + (xn - pv) + mb > tau);
+              } else {
+                keep = keep && !(fmaf(mb, ev, bb) > tau);
+              }
+            }
             if (last) {
               int32_t id = 0;
               bool take = false;
@@ -526,6 +573,7 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
                 const int pos = nnext + __popcll(bal & lt);
                 s_ac[(cur ^ 1) * SEG + pos] = (uint16_t)cand;
                 s_ae[(cur ^ 1) * SEG + pos] = ev;
+                if (RES) s_ap[(cur ^ 1) * SEG + pos] = pv;
               }
               nnext += __popcll(bal);
             }
@@ -661,12 +709,12 @@ void launch_query_order(const int32_t *probes, int32_t p_stride, int64_t nq, int
                      order);
 }
 
-template <int ST, bool P, bool LK, int W, bool PRE = false>
+template <int ST, bool P, bool LK, int W, bool PRE = false, bool RES = false>
 static void launch_variant(const ScanArgs &a, hipStream_t s) {
-  const size_t smem = scan_lds_bytes(a.nblocks * kBlockDims, a.k_max, a.block_b, W);
+  const size_t smem = scan_lds_bytes(a.nblocks * kBlockDims, a.k_max, a.block_b, W, RES);
   if (smem > kMaxLds) throw std::runtime_error("scan: LDS request exceeds 160 KiB");
   const int qpw = 4 / W;
-  hipLaunchKernelGGL((scan_kernel<ST, P, LK, W, PRE>), dim3((unsigned)((a.nq + qpw - 1) / qpw)),
+  hipLaunchKernelGGL((scan_kernel<ST, P, LK, W, PRE, RES>), dim3((unsigned)((a.nq + qpw - 1) / qpw)),
                      dim3(kScanThreads), smem, s, a);
 }
 
@@ -674,6 +722,8 @@ template <int ST> static void launch_store(const ScanArgs &a, hipStream_t s) {
   const bool w4 = a.waves_per_query == 4;
   if (!a.prune) {
     if (w4) launch_variant<ST, false, false, 4>(a, s); else launch_variant<ST, false, false, 1>(a, s);
+  } else if (a.res) {
+    if (w4) launch_variant<ST, true, false, 4, false, true>(a, s); else launch_variant<ST, true, false, 1, false, true>(a, s);
   } else if (a.pre) {
     if (a.lookahead) {
       if (w4) launch_variant<ST, true, true, 4, true>(a, s); else launch_variant<ST, true, true, 1, true>(a, s);

@@ -157,6 +157,8 @@ struct ddc_index {
   ddc::DevBuf d_R32, d_mu32, d_cent, d_cnorm, d_tile_off, d_list_len, d_ids, d_base, d_R64, d_mu64;
   int fp8 = 0;                      // FP8 pre-stage lead dims (0 or 64)
   double ads_eps0 = 2.1;            // eps0 of the ADSampling test
+  double bsar_m = 8.0;              // multiplier of the residual test (<= 0: from the significance)
+  ddc::DevBuf d_xnorm, d_lam32;     // ||y||^2 per stored slot; eigenvalues (Dp, zero padded)
   ddc::DevBuf d_base8, d_scale8;    // its codes (tiles x 64 x 64 B) and per-tile scales
   int P() const { return fp8 ? 1 : 0; }
   int Tt() const { return St + P(); }   // columns of the correction table

@@ -232,7 +232,7 @@ ddc_status ddc_server_create(const ddc_index *ixc, const ddc_server_params *p, d
   if (p->max_batch < 1 || p->max_batch > 65536) return set_err(DDC_EINVAL, "max_batch must be in [1, 65536]");
   if (!(p->significance >= 0.0 && p->significance < 1.0)) return set_err(DDC_EINVAL, "significance must be in [0, 1)");
   if (p->mode != DDC_CORR_LEARNED && p->mode != DDC_CORR_LOSSLESS && p->mode != DDC_CORR_NONE &&
-      p->mode != DDC_CORR_ADS)
+      p->mode != DDC_CORR_ADS && p->mode != DDC_CORR_BSAR)
     return set_err(DDC_EINVAL, "unknown correction mode");
   if (p->mode == DDC_CORR_LEARNED && p->significance > 0 && ixc->Tt() > 0 && ixc->tables.empty())
     return set_err(DDC_EINVAL, "index has no calibrated correction table");

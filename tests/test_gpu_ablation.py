@@ -71,3 +71,44 @@ def test_ads_with_huge_eps_is_the_full_scan(haar_oracle):
     n = g.search(w["queries"], 10, 8, 0.0, mode="none")
     np.testing.assert_array_equal(a[0], n[0])
     assert a[2]["refined"] == a[2]["candidates"]
+
+
+# ------------------------------------------------------------------ residual estimate (Alg. 1/2)
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+@pytest.mark.parametrize("m,alpha", [(8.0, 0.0), (3.0, 0.0), (0.0, 0.05), (0.0, 0.2)])
+def test_residual_test_matches_oracle(storage, m, alpha):
+    from paper_2404_16322_amd import Index
+    from parity_util import oracle_index
+    ix = oracle_index(storage=storage, n_calib=300)
+    w = workload("gauss128")
+    g = Index.from_artifacts(artifacts(ix))
+    g.set_bsar_multiplier(m)
+    Q = np.vstack([w["queries"], w["val"][:200]])
+    ids, d, st = g.search(Q, 10, 8, alpha, mode="bsar")
+    ora = O.search(dict(ix, bsar_m=m), Q, 10, 8, alpha, mode="bsar")
+    _ok(check_search(ids, d, ora, ix))
+    assert st["candidates"] == int(ora["stops"].sum())
+    assert abs(st["refined"] - int(ora["stops"][:, -1].sum())) <= 0.01 * st["candidates"] + 5
+    assert st["refined"] < st["candidates"]
+
+
+def test_residual_test_variants_identical_and_huge_m_is_exact():
+    from paper_2404_16322_amd import Index
+    from parity_util import oracle_index
+    ix = oracle_index()
+    w = workload("gauss128")
+    g = Index.from_artifacts(artifacts(ix))
+    g.set_bsar_multiplier(4.0)
+    res = []
+    for wv in (1, 4):
+        g.set_launch(waves_per_query=wv, lookahead=1)   # look-ahead does not apply to this test
+        res.append(g.search(w["queries"], 10, 8, 0.0, mode="bsar"))
+    np.testing.assert_array_equal(res[0][0], res[1][0])
+    np.testing.assert_array_equal(res[0][1], res[1][1])
+    g.set_launch(waves_per_query=0, lookahead=-1)
+    g.set_bsar_multiplier(1e12)
+    a = g.search(w["queries"], 10, 8, 0.0, mode="bsar")
+    n = g.search(w["queries"], 10, 8, 0.0, mode="none")
+    np.testing.assert_array_equal(a[0], n[0])
+    assert a[2]["refined"] == a[2]["candidates"]
