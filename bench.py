@@ -168,6 +168,9 @@ def main():
                     help="offered loads of the serving phase (override; fractions of the peak QPS "
                          "or absolute queries/s, as the workload defines)")
     ap.add_argument("--serve-seconds", type=float, default=3.0)
+    ap.add_argument("--ablation", action="store_true",
+                    help="also sweep the residual test, lossless pruning, and a random rotation with "
+                         "the learned and the ADSampling tests at the operating nprobe")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -446,6 +449,43 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
 
+    # ---- ablation at the operating nprobe: each test's knob swept, best QPS at recall >= 0.95
+    ablation = None
+    if args.ablation and not uneven:
+        ix_main = ix
+
+        def sweep_mode(label, mode, knobs, setter, alpha_of):
+            pts = []
+            for kb in knobs:
+                setter(kb)
+                a_ = alpha_of(kb)
+                r = recall(nprobe, a_, mode)
+                ms = timed(nprobe, a_, mode, 3)
+                ctr.zero_()
+                run(nprobe, a_, mode, counters=True)
+                stream.synchronize()
+                cc = ctr.cpu().numpy()
+                pts.append(dict(knob=kb, recall=round(r, 4), qps=round(nq / ms * 1e3, 1),
+                                scanned_dim_ratio=round(int(cc[2]) / max(1, int(cc[0]) * NB), 4)))
+            ok = [x for x in pts if x["recall"] >= 0.95]
+            best = max(ok, key=lambda x: x["qps"]) if ok else max(pts, key=lambda x: x["recall"])
+            log(f"[bench] ablation {label}: best {best}")
+            return dict(best=best, points=pts)
+
+        ablation = {"nprobe": nprobe}
+        ablation["pca_learned"] = sweep_mode("PCA + learned", "learned", ALPHAS, lambda _: None, lambda a_: a_)
+        ablation["pca_residual"] = sweep_mode("PCA + residual (Alg. 2)", "bsar", [1, 2, 3, 4, 6, 8, 12, 16],
+                                              ix.set_bsar_multiplier, lambda _: 0.0)
+        ablation["pca_lossless"] = sweep_mode("PCA + lossless", "lossless", [0], lambda _: None, lambda _: 0.0)
+        ix = Index.fit(w["base"], w["calib"], nlist=nlist, seed=spec["cfg"], storage=cfg["storage"],
+                       rotation=cfg["rotation"], projection="haar", **cfg.get("fit", {}))
+        ablation["haar_learned"] = sweep_mode("random rotation + learned", "learned", ALPHAS,
+                                              lambda _: None, lambda a_: a_)
+        ablation["haar_ads"] = sweep_mode("random rotation + ADSampling test", "ads",
+                                          [0.5, 1.0, 1.5, 2.1, 3.0, 4.0], ix.set_ads_epsilon, lambda _: 0.0)
+        ix.close()
+        ix = ix_main
+
     # ---- serving: open-loop Poisson arrivals, continuous batching --------------------------
     serve = []
     rates = []
@@ -511,6 +551,7 @@ def main():
                         "scan_achieved_GBs": round(full_scan_bytes / (full_scan_ms * 1e-3) / 1e9, 1)},
         "speedup_vs_full_d": round(qps / full_qps, 3),
         "without_fp8_prestage": no_pre,
+        "ablation": ablation,
         "scan_variant_ms": variants,
         "scan_variant_tuned": {"waves_per_query": chosen[0], "lookahead": chosen[1]},
         "kernel_ms": {"rotation": round(kms[0] / max(1, kn[0]), 4),
