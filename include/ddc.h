@@ -257,7 +257,8 @@ ddc_status ddc_set_bsar_multiplier(ddc_index *ix, double m);
  * xcd_swizzle: give each XCD a contiguous query range (0 or 1 each).  Tuned values are picked
  * per (queries, N_probe, K, pruned or not) size class on the first search of that class by
  * timing each candidate on the actual launch (that search synchronises its stream once); a
- * stream that is capturing a graph gets a fixed rule instead.  Defaults: 0, -1, 1, 1. */
+ * stream that is capturing a graph, and the server (which must not stall), get a fixed rule
+ * for classes not tuned yet.  Defaults: 0, -1, 1, 1. */
 typedef struct {
   int32_t waves_per_query, lookahead, query_order, xcd_swizzle;
 } ddc_launch_params;

@@ -54,8 +54,9 @@ static std::pair<int, int> forced_or(const ddc_index *ix, std::pair<int, int> v,
 }
 
 // Sets a.waves_per_query / a.lookahead.  An untuned class is timed on this very launch (each
-// candidate twice, counters off; every candidate writes the same results), then cached.
-static void choose_variant(ddc_index *ix, ScanArgs &a, int np_max, hipStream_t s) {
+// candidate twice, counters off; every candidate writes the same results), then cached;
+// callers that must not stall (the server) pass may_tune = false and get the fixed rule.
+static void choose_variant(ddc_index *ix, ScanArgs &a, int np_max, hipStream_t s, bool may_tune) {
   const int kind = scan_kind(a);
   const auto key = tune_class(a.nq, np_max, a.k_max, kind);
   std::pair<int, int> v = fixed_variant(ix, a.nq, a.prune);
@@ -68,7 +69,7 @@ static void choose_variant(ddc_index *ix, ScanArgs &a, int np_max, hipStream_t s
     } else {
       hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
       HIPC(hipStreamIsCapturing(s, &cs));
-      if (cs == hipStreamCaptureStatusNone) {
+      if (may_tune && cs == hipStreamCaptureStatusNone) {
         std::vector<std::pair<int, int>> cand;
         for (int w : {1, 4})
           for (int l : {0, 1}) {
@@ -524,7 +525,8 @@ size_t ddc::search_scratch_bytes(const ddc_index *ix, int64_t nq, int np_max) {
 void ddc::search_device(ddc_index *ix, const float *d_q, int64_t nq, const int32_t *d_k, int k_all,
                         int k_max, const int32_t *d_np, int np_all, int np_max, double alpha,
                         ddc_corr mode, const int64_t *d_off, int64_t *d_ids, float *d_d,
-                        int64_t *d_ctr, hipStream_t s, float *qrot_out, int32_t *probes_out) {
+                        int64_t *d_ctr, hipStream_t s, float *qrot_out, int32_t *probes_out,
+                        bool may_tune) {
   const int Dp = ix->Dp, D = ix->D;
   ScanArgs a{};
   a.prune = 0;
@@ -601,7 +603,7 @@ void ddc::search_device(ddc_index *ix, const float *d_q, int64_t nq, const int32
     a.xcd_swizzle = ix->xcd_swizzle;
     a.nq = (int32_t)nqc; a.nblocks = ix->NB; a.block_b = ix->B; a.nlist = ix->nlist;
     a.k_max = k_max;
-    choose_variant(ix, a, np_max, s);
+    choose_variant(ix, a, np_max, s, may_tune);
     timed(ix, 3, s, [&] { launch_scan(a, ix->store(), s); });
   }
   HIPC(hipGetLastError());

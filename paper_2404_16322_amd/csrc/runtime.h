@@ -189,7 +189,7 @@ void search_device(ddc_index *ix, const float *d_q, int64_t nq, const int32_t *d
                    int k_max, const int32_t *d_np, int np_all, int np_max, double alpha,
                    ddc_corr mode, const int64_t *d_off, int64_t *d_ids, float *d_d,
                    int64_t *d_ctr, hipStream_t s, float *qrot_out = nullptr,
-                   int32_t *probes_out = nullptr);
+                   int32_t *probes_out = nullptr, bool may_tune = true);
 // Device bytes one search of nq queries allocates from the stream-ordered pool.
 size_t search_scratch_bytes(const ddc_index *ix, int64_t nq, int np_max);
 

@@ -183,7 +183,8 @@ static bool admit(ddc_server *s, Slot &sl) {
   HIPC(hipMemcpyAsync(sl.d_off.p, sl.h_off, (size_t)(nq + 1) * 8, hipMemcpyHostToDevice, st));
   search_device(s->ix, sl.d_q.as<float>(), nq, sl.d_k.as<int32_t>(), 0, k_max, sl.d_np.as<int32_t>(),
                 0, np_max, s->p.significance, s->p.mode, sl.d_off.as<int64_t>(),
-                sl.d_ids.as<int64_t>(), sl.d_d.as<float>(), nullptr, st);
+                sl.d_ids.as<int64_t>(), sl.d_d.as<float>(), nullptr, st, nullptr, nullptr,
+                /*may_tune=*/false);
   HIPC(hipMemcpyAsync(sl.h_ids, sl.d_ids.p, (size_t)nres * 8, hipMemcpyDeviceToHost, st));
   HIPC(hipMemcpyAsync(sl.h_d, sl.d_d.p, (size_t)nres * 4, hipMemcpyDeviceToHost, st));
   HIPC(hipEventRecord(sl.done, st));
