@@ -81,10 +81,10 @@ static void choose_variant(ddc_index *ix, ScanArgs &a, int np_max, hipStream_t s
         HIPC(hipEventCreate(&e1));
         ScanArgs t = a;
         t.counters = nullptr;
-        float best = INFINITY;
-        for (auto c : cand) {
-          t.waves_per_query = c.first;
-          t.lookahead = c.second;
+        std::vector<float> tbest(cand.size(), INFINITY);
+        for (size_t ci = 0; ci < cand.size(); ++ci) {
+          t.waves_per_query = cand[ci].first;
+          t.lookahead = cand[ci].second;
           for (int rep = 0; rep < 2; ++rep) {
             HIPC(hipEventRecord(e0, s));
             launch_scan(t, ix->store(), s);
@@ -92,9 +92,14 @@ static void choose_variant(ddc_index *ix, ScanArgs &a, int np_max, hipStream_t s
             HIPC(hipEventSynchronize(e1));
             float ms = 0.f;
             HIPC(hipEventElapsedTime(&ms, e0, e1));
-            if (ms < best) { best = ms; v = c; }
+            tbest[ci] = std::min(tbest[ci], ms);
           }
         }
+        // the first candidate (simplest shape first) within 3% of the fastest: timing noise
+        // does not flip the choice between near-equal shapes
+        const float fastest = *std::min_element(tbest.begin(), tbest.end());
+        for (size_t ci = 0; ci < cand.size(); ++ci)
+          if (tbest[ci] <= fastest * 1.03f) { v = cand[ci]; break; }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         ix->tuned[key] = v;

@@ -255,6 +255,11 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
   // statistics (wave-uniform, flushed once when counters are requested)
   int64_t st_cand = 0, st_ref = 0, st_slices = 0, st_pre = 0, st_pre_pruned = 0;
   unsigned long long *ctr = reinterpret_cast<unsigned long long *>(a.counters);
+  // stop-stage histogram, lane i counting stage i (one atomic per lane at the end)
+  uint32_t st_stop = 0;
+  auto stop_add = [&](int stage, uint32_t cnt) {
+    if (lane == min(stage, 63)) st_stop += cnt;
+  };
 
   int tin = 0, tn = 0, par = 0;
   float tau = INFINITY;
@@ -339,7 +344,7 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
           append(keep, dis, id);
         }
         st_cand += slen; st_ref += slen; st_slices += (int64_t)slen * nb;
-        if (ctr && lane == 0) atomicAdd(&ctr[4 + min(nb - 1, 63)], (unsigned long long)slen);
+        if (ctr) stop_add(nb - 1, (uint32_t)slen);
       } else if (PRUNE) {
         // ---- staged scan: test after every stage, compact the survivors ----
         // Lanes past the live count read the group's first live candidate (same cache
@@ -470,11 +475,14 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
             st_slices += __popcll(__ballot(valid && my_ss < Le && my_ss <= firstp));
             const bool writer = valid && my_ss == Le - 1;
             const bool survive = writer && bits == 0;
-            if (ctr && writer && bits) atomicAdd(&ctr[4 + min(b + firstp, 63)], 1ull);
+            if (ctr)
+              for (int s2 = 0; s2 < Le; ++s2)
+                stop_add(b + s2, (uint32_t)__popcll(__ballot(writer && bits && firstp == s2)));
             if (b + Le == nb) {
               // the window reached the last stage: survivors carry their exact distance
-              if (ctr && survive) atomicAdd(&ctr[4 + min(nb - 1, 63)], 1ull);
-              st_ref += __popcll(__ballot(survive));
+              const int nsurv = __popcll(__ballot(survive));
+              if (ctr) stop_add(nb - 1, (uint32_t)nsurv);
+              st_ref += nsurv;
               int32_t id = 0;
               bool take = false;
               if (survive) {
@@ -581,10 +589,7 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
           }
           st_slices += nalive;
           if (last) st_ref += nalive - pruned;
-          if (ctr && lane == 0) {
-            const int fin = last ? nalive : pruned;   // last block: every remaining one stops here
-            if (fin) atomicAdd(&ctr[4 + min(b, 63)], (unsigned long long)fin);
-          }
+          if (ctr) stop_add(b, (uint32_t)(last ? nalive : pruned));   // last block: all stop here
           __builtin_amdgcn_wave_barrier();
           if (!last) { nalive = nnext; cur ^= 1; }
           b += 1;
@@ -650,6 +655,7 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
     a.out_ids[off + i] = have ? (int64_t)s_ti[tin * KM + i] : (int64_t)-1;
     a.out_d[off + i] = have ? s_td[tin * KM + i] : INFINITY;
   }
+  if (ctr && st_stop) atomicAdd(&ctr[4 + lane], (unsigned long long)st_stop);
   if (ctr && lane == 0) {
     atomicAdd(&ctr[0], (unsigned long long)st_cand);
     atomicAdd(&ctr[1], (unsigned long long)st_ref);

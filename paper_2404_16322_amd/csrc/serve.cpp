@@ -263,6 +263,15 @@ ddc_status ddc_server_create(const ddc_index *ixc, const ddc_server_params *p, d
       HIPC(hipHostMalloc((void **)&sl.h_ids, mb * kMaxK * 8, 0));
       HIPC(hipHostMalloc((void **)&sl.h_d, mb * kMaxK * 4, 0));
     }
+    {
+      // grow the stream-ordered pool once for n_streams batches of max_batch queries (it keeps
+      // what it reserved), so the first requests do not pay for mapping new memory
+      std::vector<AsyncBuf> warm;
+      for (auto &sl : s->slots)
+        warm.emplace_back(search_scratch_bytes(ix, mb, std::min(ix->nlist, 4096)), sl.stream);
+      for (auto &sl : s->slots) HIPC(hipStreamSynchronize(sl.stream));
+    }
+    for (auto &sl : s->slots) HIPC(hipStreamSynchronize(sl.stream));
   } catch (const DdcError &e) {
     for (auto &sl : s->slots) release_slot(sl);
     return set_err(e.st, "%s", e.what());
