@@ -175,3 +175,34 @@ def uneven_requests(nq: int, seed: int, nprobe_lo: int, nprobe_hi: int, k_choice
     nprobe = rng.integers(nprobe_lo, nprobe_hi + 1, size=nq).astype(np.int32)
     k = np.asarray(k_choices, dtype=np.int32)[rng.integers(0, len(k_choices), size=nq)]
     return k, nprobe
+
+
+STREAM_OOD = 11   # streams 11, 12, 13: out-of-distribution queries, calibration, validation
+
+
+def ood_queries(name: str, n: int, stream: int = STREAM_OOD, within_scale: float = 2.0) -> np.ndarray:
+    """Queries from a shifted distribution (out-of-distribution for an index fitted on the
+    workload): for the mixtures, the same component means with every within-component scale
+    multiplied by ``within_scale`` (noisier queries, same post-processing); for the Gaussian
+    case, another Haar rotation and the flatter spectrum lambda_i = i^-0.5 at the same total
+    variance."""
+    spec = dict(WORKLOADS[name])
+    cfg, D, kind = spec["cfg"], spec["D"], spec["kind"]
+    sd = 1000 * cfg + stream
+    lam = _power_spectrum(D, spec["expo"])
+    if kind == "gauss":
+        rot2 = haar_rotation(D, np.random.default_rng(1000 * cfg + STREAM_ROT + 10))
+        lam2 = _power_spectrum(D, 0.5)
+        lam2 *= lam.sum() / lam2.sum()
+        return np.ascontiguousarray(gauss_points(n, D, sd, rot2, lam2))
+    centre, ms, ws = {"sift": (127.5, 21.0, 24.0), "gist": (0.0, 0.6, 0.4), "embed": (0.0, 0.6, 0.4)}[kind]
+    mix = Mixture(D, spec["comps"], lam, centre=centre, mean_std=ms, within_std=ws,
+                  seed_rot=1000 * cfg + STREAM_ROT, seed_mix=1000 * cfg + STREAM_MIX)
+    mix.scales = mix.scales * within_scale
+    if kind == "sift":
+        post = lambda x: np.rint(np.clip(x, 0.0, 255.0))
+    elif kind == "embed":
+        post = lambda x: x / np.linalg.norm(x, axis=1, keepdims=True)
+    else:
+        post = None
+    return np.ascontiguousarray(mix.sample(n, sd, post=post, dtype=np.float32))

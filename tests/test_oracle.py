@@ -675,3 +675,26 @@ def test_residual_test_prunes_and_huge_multiplier_is_exact(small_index, small_wo
     h = O.search(dict(small_index, bsar_m=1e12), Q, 10, 8, 0.0, mode="bsar")
     assert h["ids"].tolist() == n["ids"].tolist() and h["stops"][:, :-1].sum() == 0
     assert abs(O.bsar_multiplier(0.05, 0.0) - 1.6448536269514722) < 1e-9
+
+
+# ----------------------------------------------------------------------------- out-of-distribution queries
+
+def test_recalibration_on_100_ood_queries_restores_significance(small_index):
+    """Sec. V-C: queries from a shifted distribution move the held-out false-prune rate away
+    from alpha; recalibrating on about 100 such queries brings it back (99% bootstrap interval
+    of the validation rate, widened by sqrt(1 + 1000/100) for the ten times smaller
+    calibration sample)."""
+    ix = small_index
+    val = synthdata.ood_queries("gauss128", 1000, stream=13)
+    cal = synthdata.ood_queries("gauss128", 100, stream=12)
+    before, _ = O.false_prune_rate(ix, val, 10, 0.1)
+    assert abs(before - 0.1) > 0.03                       # the in-distribution table misses alpha
+    c2 = O.calibrate(ix["Y"], ix["list_off"], ix["list_ids"], ix["centroids"], ix["mu"], ix["R"], cal,
+                     ix["bounds"], 10, 8, 256, 0, 7, 50)
+    ix2 = dict(ix, m=c2["m"], G=c2["G"])
+    rng = np.random.default_rng(5)
+    for a in [0.05, 0.1]:
+        rate, per_q = O.false_prune_rate(ix2, val, 10, a)
+        boots = np.array([per_q[rng.integers(0, 1000, 1000)].mean() / 10 for _ in range(2000)])
+        lo, hi = np.quantile(boots, [0.005, 0.995])
+        assert abs(rate - a) <= (hi - lo) / 2 * math.sqrt(11), (a, rate)
