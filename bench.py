@@ -28,6 +28,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# MI355X dense matrix-core peaks (TFLOP/s) by input type
+MFMA_PEAK_TFLOPS = {"f32": 157.3, "bf16": 2500.0}
 NPROBES = [16, 24, 32, 48, 64, 96, 128]
 ALPHAS = [0.001, 0.005, 0.01, 0.02, 0.05, 0.1, 0.2, 0.3]
 
@@ -92,12 +94,13 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
-def serve_phase(ix, w, offered_qps, seconds, alpha, nlist, seed=0, n_streams=4, max_batch=2048,
+def serve_phase(ix, w, gt, offered_qps, seconds, alpha, nlist, seed=0, n_streams=4, max_batch=2048,
                 budget=4 << 30):
     """Open-loop load: requests of U{1..256} queries (drawn from the query set) arrive as a
     Poisson process at `offered_qps` queries/s; every query has its own K ~ U{10..100} and
     nprobe ~ U{16..128}.  Latency = completion seen on the host - scheduled arrival, so a
-    producer running late never hides queueing delay."""
+    producer running late never hides queueing delay.  recall@10 of every served query is
+    taken against FP64 exact KNN (`gt`, rows of the query set)."""
     import threading
     from paper_2404_16322_amd import Server
     rng = np.random.default_rng(1000 + seed)
@@ -107,8 +110,10 @@ def serve_phase(ix, w, offered_qps, seconds, alpha, nlist, seed=0, n_streams=4, 
     gaps = rng.exponential(mean_req / offered_qps, size=n_req)
     Q = w["queries"]
     reqs = []
+    req_rows = []
     for nqr in sizes:
         rows = rng.integers(0, Q.shape[0], size=nqr)
+        req_rows.append(rows)
         reqs.append((np.ascontiguousarray(Q[rows]), rng.integers(10, 101, size=nqr).astype(np.int32),
                      rng.integers(16, min(128, nlist) + 1, size=nqr).astype(np.int32)))
     srv = Server(ix, n_streams=n_streams, max_batch=max_batch, hbm_budget_bytes=budget, alpha=alpha)
@@ -128,6 +133,7 @@ def serve_phase(ix, w, offered_qps, seconds, alpha, nlist, seed=0, n_streams=4, 
     th = threading.Thread(target=producer)
     th.start()
     lat = []
+    results = []
     i = 0
     while i < n_req:
         if tickets[i] is None:
@@ -138,9 +144,16 @@ def serve_phase(ix, w, offered_qps, seconds, alpha, nlist, seed=0, n_streams=4, 
             time.sleep(0.0001)
             continue
         lat.append((r[3] - t_sched[i]) * 1e-6)
+        results.append((r[0], r[2]))
         i += 1
     th.join()
     end = time.monotonic_ns()
+    hits = 0
+    served_rows = set()
+    for (ids_r, off_r), rows in zip(results, req_rows):
+        got = ids_r[off_r[:-1, None] + np.arange(10)[None, :]]          # every K >= 10
+        hits += int((got[:, :, None] == gt[rows, :10][:, None, :]).any(-1).sum())
+        served_rows.update(rows.tolist())
     st = srv.stats()
     srv.close()
     lat = np.sort(np.asarray(lat))
@@ -148,6 +161,7 @@ def serve_phase(ix, w, offered_qps, seconds, alpha, nlist, seed=0, n_streams=4, 
     return dict(offered_qps=round(offered_qps, 1), achieved_qps=round(total_q / ((end - start) * 1e-9), 1),
                 requests=n_req, queries=total_q, p50_ms=round(float(np.percentile(lat, 50)), 3),
                 p99_ms=round(float(np.percentile(lat, 99)), 3), max_ms=round(float(lat[-1]), 3),
+                recall_at_10=round(hits / (10 * total_q), 4), distinct_queries=len(served_rows),
                 server_p50_ms=round(st["p50_ms"], 3), server_p99_ms=round(st["p99_ms"], 3),
                 max_concurrent_batches=st["max_concurrent"], budget_peak_bytes=st["budget_peak_bytes"],
                 n_streams=n_streams, max_batch=max_batch, hbm_budget_bytes=budget)
@@ -385,8 +399,8 @@ def main():
     # every launch shape of the scan at the operating point (results are bit-identical)
     chosen = ix.scan_variant(bsz, k, int(nps.max())) if uneven else ix.scan_variant(nq, k, nprobe)
     variants = {}
-    for wv, la in ((1, 0), (1, 1), (4, 0), (4, 1)):
-        ix.set_launch(waves_per_query=wv, lookahead=la)
+    for wv, la, pe in [(w_, l_, p_) for p_ in (0, 1) for w_ in (1, 4) for l_ in (0, 1)]:
+        ix.set_launch(waves_per_query=wv, lookahead=la, persistent=pe)
         run(nprobe, alpha, "learned")
         stream.synchronize()
         ix.set_kernel_timing(True)
@@ -395,8 +409,9 @@ def main():
         stream.synchronize()
         ix.set_kernel_timing(False)
         vms, vn = ix.kernel_timing(reset=True)
-        variants[f"waves{wv}{'_lookahead' if la else ''}"] = round(vms[3] / max(1, vn[3]), 4)
-    ix.set_launch(waves_per_query=0, lookahead=-1)
+        variants[f"waves{wv}{'_lookahead' if la else ''}{'_persistent' if pe else ''}"] = \
+            round(vms[3] / max(1, vn[3]), 4)
+    ix.set_launch(waves_per_query=0, lookahead=-1, persistent=-1)
     log(f"[bench] scan variants (ms): {variants}; tuned choice {chosen}")
 
     # full-D scan at its own operating point, same protocol
@@ -447,14 +462,28 @@ def main():
             tuned_name = (f"void ddc::scan_kernel<{info['storage']}, true, {'true' if chosen[1] else 'false'}, "
                           f"{chosen[0]}, {'true' if cfg.get('fp8') else 'false'}, false>(ddc::ScanArgs)")
             if pm.get("kernel_hash") == kernel_hash() and pm.get("nprobe") == nprobe and \
-                    abs(pm.get("alpha", -1) - alpha) < 1e-12 and pm.get("kernel") == tuned_name:
+                    abs(pm.get("alpha", -1) - alpha) < 1e-12 and pm.get("kernel") == tuned_name and \
+                    pm.get("persistent", 0) == chosen[2]:
                 traffic = pm.get("hbm_bytes_per_launch")
         except Exception:
             traffic = None
+    # matrix-core use of the two GEMMs (algorithmic flops / HIP-event kernel time / dense peak)
+    rot_prec = "bf16" if cfg["rotation"] == "bf16" else "f32"
+    bq = bsz if uneven else nq
+
+    def mfma_entry(flops, ms, prec):
+        peak = MFMA_PEAK_TFLOPS[prec]
+        ach = flops / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
+        return dict(dtype=prec, flops_per_launch=int(flops), kernel_ms=round(ms, 4),
+                    achieved_tflops=round(ach, 2), peak_tflops=peak, frac=round(ach / peak, 4))
+    mfma = {"rotation": mfma_entry(2.0 * bq * info["dim_padded"] * D, kms[0] / max(1, kn[0]), rot_prec),
+            "coarse": mfma_entry(2.0 * bq * nlist * info["dim_padded"], kms[1] / max(1, kn[1]), "f32")}
+    log(f"[bench] matrix cores: {mfma}")
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
                     kernel=f"scan_kernel<{cfg['storage']}, pruned, lookahead={chosen[1]}, "
-                           f"waves={chosen[0]}>", bytes_per_launch=int(scan_bytes),
+                           f"waves={chosen[0]}>{' persistent' if chosen[2] else ''}",
+                    bytes_per_launch=int(scan_bytes),
                     kernel_ms=round(scan_ms, 4))
 
     if args.copy_probe:
@@ -510,7 +539,7 @@ def main():
             vals = [float(x) for x in args.serve_rates.split(",") if x.strip()]
         rates = [qps * v for v in vals] if kind == "frac" else list(vals)
     for rate in rates:
-        serve.append(serve_phase(ix, w, rate, args.serve_seconds, alpha, nlist, seed=len(serve)))
+        serve.append(serve_phase(ix, w, gt, rate, args.serve_seconds, alpha, nlist, seed=len(serve)))
         log(f"[bench] serve {serve[-1]}")
 
     # ---- CPU oracle baseline (bounded sample) --------------------------------------------
@@ -592,7 +621,8 @@ def main():
         "ablation": ablation,
         "out_of_distribution": ood,
         "scan_variant_ms": variants,
-        "scan_variant_tuned": {"waves_per_query": chosen[0], "lookahead": chosen[1]},
+        "scan_variant_tuned": {"waves_per_query": chosen[0], "lookahead": chosen[1],
+                               "persistent": chosen[2]},
         "kernel_ms": {"rotation": round(kms[0] / max(1, kn[0]), 4),
                       "coarse": round(kms[1] / max(1, kn[1]), 4),
                       "select": round(kms[2] / max(1, kn[2]), 4), "scan": round(scan_ms, 4)},
@@ -602,6 +632,7 @@ def main():
                        "bytes_vs_full_d": round((slices * slice_bytes + pre_reads * 64) / launches
                                                 / max(1, full_bytes_per_launch), 4)},
         "roofline": roofline,
+        "mfma": mfma,
         "distance_error_vs_fp64": dist_err,
         "serve": serve,
         "serve_p50_ms": serve[-1]["p50_ms"] if serve else None,

@@ -258,16 +258,21 @@ ddc_status ddc_set_bsar_multiplier(ddc_index *ix, double m);
  * per (queries, N_probe, K, pruned or not) size class on the first search of that class by
  * timing each candidate on the actual launch (that search synchronises its stream once); a
  * stream that is capturing a graph, and the server (which must not stall), get a fixed rule
- * for classes not tuned yet.  Defaults: 0, -1, 1, 1. */
+ * for classes not tuned yet.  persistent: 0 (one workgroup per query group, the grid covers
+ * the batch), 1 (the grid holds only the workgroups the device keeps resident at once; each
+ * takes the next query from a device counter until none is left, queries ordered by
+ * decreasing candidate count so long scans start first; query_order does not apply), -1 =
+ * tuned.  Defaults: 0, -1, 1, 1, -1. */
 typedef struct {
-  int32_t waves_per_query, lookahead, query_order, xcd_swizzle;
+  int32_t waves_per_query, lookahead, query_order, xcd_swizzle, persistent;
 } ddc_launch_params;
 ddc_status ddc_set_launch(ddc_index *ix, const ddc_launch_params *p);
 ddc_status ddc_get_launch(const ddc_index *ix, ddc_launch_params *p);
-/* The scan variant a search of nq queries with this K, N_probe and mode runs: waves (1 or 4)
- * and lookahead (0 or 1).  A size class not tuned yet reports the fixed rule's choice. */
+/* The scan variant a search of nq queries with this K, N_probe and mode runs: waves (1 or 4),
+ * lookahead (0 or 1) and persistent (0 or 1; nullable).  A size class not tuned yet reports
+ * the fixed rule's choice. */
 ddc_status ddc_scan_variant(ddc_index *ix, int64_t nq, int32_t k_max, int32_t nprobe_max,
-                            ddc_corr mode, int32_t *waves, int32_t *lookahead);
+                            ddc_corr mode, int32_t *waves, int32_t *lookahead, int32_t *persistent);
 
 /* ---- continuous-batching server --------------------------------------------------------
  * A scheduler thread admits queued requests into micro-batches on n_streams HIP streams while

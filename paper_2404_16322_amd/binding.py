@@ -81,7 +81,7 @@ class ServerStats(C.Structure):
 
 class LaunchParams(C.Structure):
     _fields_ = [("waves_per_query", C.c_int32), ("lookahead", C.c_int32),
-                ("query_order", C.c_int32), ("xcd_swizzle", C.c_int32)]
+                ("query_order", C.c_int32), ("xcd_swizzle", C.c_int32), ("persistent", C.c_int32)]
 
 
 class DdcError(RuntimeError):
@@ -129,7 +129,7 @@ def load_library():
         lib.ddc_set_launch.argtypes = [vp, C.POINTER(LaunchParams)]
         lib.ddc_get_launch.argtypes = [vp, C.POINTER(LaunchParams)]
         lib.ddc_scan_variant.argtypes = [vp, i64, i32, i32, C.c_int, C.POINTER(C.c_int32),
-                                         C.POINTER(C.c_int32)]
+                                         C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
         lib.ddc_server_create.argtypes = [vp, C.POINTER(ServerParams), C.POINTER(vp)]
         lib.ddc_server_submit.argtypes = [vp, vp, i32, vp, vp, C.POINTER(C.c_uint64)]
         lib.ddc_server_poll.argtypes = [vp, C.c_uint64, vp, vp, C.POINTER(C.c_int), C.POINTER(C.c_uint64)]
@@ -350,13 +350,15 @@ class Index:
         _check(load_library().ddc_set_ads_epsilon(self._h, eps0))
 
     def set_launch(self, waves_per_query: int | None = None, lookahead: int | None = None,
-                   query_order: int | None = None, xcd_swizzle: int | None = None):
+                   query_order: int | None = None, xcd_swizzle: int | None = None,
+                   persistent: int | None = None):
         """Result-invariant launch shape of the scan; None keeps the current value
-        (waves_per_query 0 and lookahead -1 mean tuned per size class)."""
+        (waves_per_query 0, lookahead -1 and persistent -1 mean tuned per size class)."""
         cur = self.launch()
         lp = LaunchParams(*(cur[k] if v is None else int(v) for k, v in
                             (("waves_per_query", waves_per_query), ("lookahead", lookahead),
-                             ("query_order", query_order), ("xcd_swizzle", xcd_swizzle))))
+                             ("query_order", query_order), ("xcd_swizzle", xcd_swizzle),
+                             ("persistent", persistent))))
         _check(load_library().ddc_set_launch(self._h, C.byref(lp)))
 
     def launch(self) -> dict:
@@ -365,11 +367,12 @@ class Index:
         return {k: getattr(lp, k) for k, _ in LaunchParams._fields_}
 
     def scan_variant(self, nq: int, k: int, nprobe: int, mode: str = "learned") -> tuple:
-        """(waves per query, lookahead) a search of this shape runs (tuned or fixed rule)."""
-        w, la = C.c_int32(), C.c_int32()
+        """(waves per query, lookahead, persistent) a search of this shape runs (tuned or
+        fixed rule)."""
+        w, la, pe = C.c_int32(), C.c_int32(), C.c_int32()
         _check(load_library().ddc_scan_variant(self._h, nq, k, nprobe, CORR[mode], C.byref(w),
-                                               C.byref(la)))
-        return w.value, la.value
+                                               C.byref(la), C.byref(pe)))
+        return w.value, la.value, pe.value
 
     def set_kernel_timing(self, enable: bool):
         _check(load_library().ddc_set_kernel_timing(self._h, int(enable)))
@@ -433,15 +436,6 @@ class Server:
         st = ServerStats()
         _check(load_library().ddc_server_get_stats(self._h, C.byref(st)))
         return {f: getattr(st, f) for f, _ in ServerStats._fields_}
-
-    @classmethod
-    def load(cls, path: str) -> "Index":
-        h = C.c_void_p()
-        _check(load_library().ddc_load(os.fsencode(path), C.byref(h)))
-        return cls(h.value)
-
-    def save(self, path: str):
-        _check(load_library().ddc_save(self._h, os.fsencode(path)))
 
     def close(self):
         if self._h is not None and self._h.value:

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <limits>
 #include <map>
 #include <memory>
@@ -40,28 +41,54 @@ static std::array<int, 4> tune_class(int64_t nq, int np_max, int k_max, int kind
 // kernel family of a launch: pruned or not, FP8 pre-stage, residual test
 static int scan_kind(const ScanArgs &a) { return a.prune + 2 * a.pre + 4 * a.res; }
 
+// Launch shape of the scan: waves per query (1 or 4), look-ahead (0 or 1), persistent (0 or 1).
+using Variant = std::array<int, 3>;
+
 // Without measurements: a workgroup per query while the batch leaves the chip's wave slots
-// mostly empty, and multi-block loads once vectors span eight or more dim blocks.
-static std::pair<int, int> fixed_variant(const ddc_index *ix, int64_t nq, int prune) {
-  return {nq < 4096 ? 4 : 1, prune && ix->NB >= 8 ? 1 : 0};
+// mostly empty, multi-block loads once vectors span eight or more dim blocks, one pass.
+static Variant fixed_variant(const ddc_index *ix, int64_t nq, int prune) {
+  return {nq < 4096 ? 4 : 1, prune && ix->NB >= 8 ? 1 : 0, 0};
 }
 
-static std::pair<int, int> forced_or(const ddc_index *ix, std::pair<int, int> v, int kind) {
-  if (ix->waves_per_query) v.first = ix->waves_per_query;
-  if (ix->lookahead >= 0) v.second = ix->lookahead;
-  if (!(kind & 1) || (kind & 4)) v.second = 0;   // look-ahead only for the learned/fixed-table tests
+static Variant forced_or(const ddc_index *ix, Variant v, int kind) {
+  if (ix->waves_per_query) v[0] = ix->waves_per_query;
+  if (ix->lookahead >= 0) v[1] = ix->lookahead;
+  if (ix->persistent >= 0) v[2] = ix->persistent;
+  if (!(kind & 1) || (kind & 4)) v[1] = 0;   // look-ahead only for the learned/fixed-table tests
   return v;
 }
 
-// Sets a.waves_per_query / a.lookahead.  An untuned class is timed on this very launch (each
-// candidate twice, counters off; every candidate writes the same results), then cached;
-// callers that must not stall (the server) pass may_tune = false and get the fixed rule.
-static void choose_variant(ddc_index *ix, ScanArgs &a, int np_max, hipStream_t s, bool may_tune) {
+// Query orders a launch may use: grouped by first probed list (one pass per workgroup), and
+// longest first with a slot counter (persistent), the latter made on first use.
+struct LaunchOrders {
+  const int32_t *group = nullptr;
+  std::function<std::pair<const int32_t *, int32_t *>()> longest_first;
+};
+
+static void apply_variant(ScanArgs &a, const Variant &v, LaunchOrders &o) {
+  a.waves_per_query = v[0];
+  a.lookahead = v[1];
+  if (v[2]) {
+    const auto pq = o.longest_first();
+    a.order = pq.first;
+    a.queue = pq.second;
+  } else {
+    a.order = o.group;
+    a.queue = nullptr;
+  }
+}
+
+// Sets the launch shape of a.  An untuned class is timed on this very launch (each candidate
+// twice, counters off; every candidate writes the same results), then cached; callers that
+// must not stall (the server) pass may_tune = false and get the fixed rule.
+static void choose_variant(ddc_index *ix, ScanArgs &a, int np_max, hipStream_t s, bool may_tune,
+                           LaunchOrders &orders) {
   const int kind = scan_kind(a);
   const auto key = tune_class(a.nq, np_max, a.k_max, kind);
-  std::pair<int, int> v = fixed_variant(ix, a.nq, a.prune);
+  Variant v = fixed_variant(ix, a.nq, a.prune);
   const bool need_w = ix->waves_per_query == 0, need_l = a.prune && !a.res && ix->lookahead < 0;
-  if (need_w || need_l) {
+  const bool need_p = ix->persistent < 0;
+  if (need_w || need_l || need_p) {
     std::lock_guard<std::mutex> lk(ix->tune_mtx);
     auto it = ix->tuned.find(key);
     if (it != ix->tuned.end()) {
@@ -70,12 +97,13 @@ static void choose_variant(ddc_index *ix, ScanArgs &a, int np_max, hipStream_t s
       hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
       HIPC(hipStreamIsCapturing(s, &cs));
       if (may_tune && cs == hipStreamCaptureStatusNone) {
-        std::vector<std::pair<int, int>> cand;
-        for (int w : {1, 4})
-          for (int l : {0, 1}) {
-            auto c = forced_or(ix, {w, l}, kind);
-            if (std::find(cand.begin(), cand.end(), c) == cand.end()) cand.push_back(c);
-          }
+        std::vector<Variant> cand;   // simplest shapes first
+        for (int p : {0, 1})
+          for (int w : {1, 4})
+            for (int l : {0, 1}) {
+              auto c = forced_or(ix, {w, l, p}, kind);
+              if (std::find(cand.begin(), cand.end(), c) == cand.end()) cand.push_back(c);
+            }
         hipEvent_t e0, e1;
         HIPC(hipEventCreate(&e0));
         HIPC(hipEventCreate(&e1));
@@ -83,8 +111,7 @@ static void choose_variant(ddc_index *ix, ScanArgs &a, int np_max, hipStream_t s
         t.counters = nullptr;
         std::vector<float> tbest(cand.size(), INFINITY);
         for (size_t ci = 0; ci < cand.size(); ++ci) {
-          t.waves_per_query = cand[ci].first;
-          t.lookahead = cand[ci].second;
+          apply_variant(t, cand[ci], orders);
           for (int rep = 0; rep < 2; ++rep) {
             HIPC(hipEventRecord(e0, s));
             launch_scan(t, ix->store(), s);
@@ -107,8 +134,7 @@ static void choose_variant(ddc_index *ix, ScanArgs &a, int np_max, hipStream_t s
     }
   }
   v = forced_or(ix, v, kind);
-  a.waves_per_query = v.first;
-  a.lookahead = v.second;
+  apply_variant(a, v, orders);
 }
 
 // Phi^-1(p) by bisection on Phi(x) = erfc(-x / sqrt 2) / 2 (monotone), to double precision.
@@ -267,7 +293,7 @@ static ddc_index::Table run_calibration(ddc_index *ix, const float *calib, int64
     a.out_ids = d_cid.as<int64_t>(); a.out_d = d_cd.as<float>();
     a.nq = (int32_t)nc; a.nblocks = ix->NB; a.block_b = ix->B; a.prune = 0; a.nlist = ix->nlist;
     a.k_max = kp;
-    a.waves_per_query = fixed_variant(ix, nc, 0).first;
+    a.waves_per_query = fixed_variant(ix, nc, 0)[0];
     launch_scan(a, ix->store(), s);
   }
   std::vector<int64_t> cid((size_t)nc * kp);
@@ -524,7 +550,7 @@ template <class F> static void timed(ddc_index *ix, int kernel, hipStream_t s, F
 size_t ddc::search_scratch_bytes(const ddc_index *ix, int64_t nq, int np_max) {
   const int64_t c = std::min<int64_t>(nq, 32768);
   return (size_t)c * ix->Dp * 4 + (size_t)c * ix->nlist * 4 + (size_t)c * np_max * 4 +
-         (size_t)(ix->nlist + 1) * 4 + (size_t)c * 8 + 4096;
+         (size_t)(ix->nlist + 1) * 4 + (size_t)c * 8 + (size_t)c * 12 + 2048 + 4096;
 }
 
 void ddc::search_device(ddc_index *ix, const float *d_q, int64_t nq, const int32_t *d_k, int k_all,
@@ -596,19 +622,34 @@ void ddc::search_device(ddc_index *ix, const float *d_q, int64_t nq, const int32
     a.out_ids = d_off ? d_ids : d_ids + q0 * k_all;
     a.out_d = d_off ? d_d : d_d + q0 * k_all;
     a.counters = d_ctr;
-    AsyncBuf ord_hist(0, s), ord_rank(0, s), ord(0, s);
+    AsyncBuf ord_hist(0, s), ord_rank(0, s), ord(0, s), lpt_key(0, s), lpt_hist(0, s), lpt_rank(0, s),
+        lpt(0, s), queue(0, s);
+    LaunchOrders orders;
     if (ix->query_order) {
       ord_hist = AsyncBuf((size_t)(ix->nlist + 1) * 4, s);
       ord_rank = AsyncBuf((size_t)nqc * 4, s);
       ord = AsyncBuf((size_t)nqc * 4, s);
       launch_query_order(probes.as<int32_t>(), np_max, nqc, ix->nlist, ord_hist.as<int32_t>(),
                          ord_rank.as<int32_t>(), ord.as<int32_t>(), s);
-      a.order = ord.as<int32_t>();
+      orders.group = ord.as<int32_t>();
     }
+    orders.longest_first = [&]() -> std::pair<const int32_t *, int32_t *> {
+      if (!lpt.p) {
+        lpt_key = AsyncBuf((size_t)nqc * 4, s);
+        lpt_hist = AsyncBuf((size_t)257 * 4, s);
+        lpt_rank = AsyncBuf((size_t)nqc * 4, s);
+        lpt = AsyncBuf((size_t)nqc * 4, s);
+        queue = AsyncBuf(256, s);
+        launch_work_order(probes.as<int32_t>(), np_max, d_np ? d_np + q0 : nullptr, np_all,
+                          ix->d_list_len.as<int32_t>(), ix->nlist, nqc, lpt_key.as<int32_t>(),
+                          lpt_hist.as<int32_t>(), lpt_rank.as<int32_t>(), lpt.as<int32_t>(), s);
+      }
+      return {lpt.as<int32_t>(), queue.as<int32_t>()};
+    };
     a.xcd_swizzle = ix->xcd_swizzle;
     a.nq = (int32_t)nqc; a.nblocks = ix->NB; a.block_b = ix->B; a.nlist = ix->nlist;
     a.k_max = k_max;
-    choose_variant(ix, a, np_max, s, may_tune);
+    choose_variant(ix, a, np_max, s, may_tune, orders);
     timed(ix, 3, s, [&] { launch_scan(a, ix->store(), s); });
   }
   HIPC(hipGetLastError());
@@ -1195,12 +1236,14 @@ ddc_status ddc_set_launch(ddc_index *ix, const ddc_launch_params *p) {
   if (p->lookahead < -1 || p->lookahead > 1) return set_err(DDC_EINVAL, "lookahead must be -1, 0 or 1");
   if ((p->query_order != 0 && p->query_order != 1) || (p->xcd_swizzle != 0 && p->xcd_swizzle != 1))
     return set_err(DDC_EINVAL, "query_order and xcd_swizzle must be 0 or 1");
+  if (p->persistent < -1 || p->persistent > 1) return set_err(DDC_EINVAL, "persistent must be -1, 0 or 1");
   std::lock_guard<std::mutex> lk(ix->tune_mtx);
   ix->tuned.clear();   // a choice tuned under other forced knobs may not be the best now
   ix->waves_per_query = p->waves_per_query;
   ix->lookahead = p->lookahead;
   ix->query_order = p->query_order;
   ix->xcd_swizzle = p->xcd_swizzle;
+  ix->persistent = p->persistent;
   return DDC_OK;
 }
 
@@ -1210,11 +1253,12 @@ ddc_status ddc_get_launch(const ddc_index *ix, ddc_launch_params *p) {
   p->lookahead = ix->lookahead;
   p->query_order = ix->query_order;
   p->xcd_swizzle = ix->xcd_swizzle;
+  p->persistent = ix->persistent;
   return DDC_OK;
 }
 
 ddc_status ddc_scan_variant(ddc_index *ix, int64_t nq, int32_t k_max, int32_t nprobe_max,
-                            ddc_corr mode, int32_t *waves, int32_t *lookahead) {
+                            ddc_corr mode, int32_t *waves, int32_t *lookahead, int32_t *persistent) {
   if (!ix || !waves || !lookahead) return set_err(DDC_EINVAL, "NULL argument");
   if (nq < 1 || k_max < 1 || nprobe_max < 1) return set_err(DDC_EINVAL, "sizes must be >= 1");
   // the kernel family a search in this mode launches (significance > 0 assumed for LEARNED)
@@ -1222,15 +1266,16 @@ ddc_status ddc_scan_variant(ddc_index *ix, int64_t nq, int32_t k_max, int32_t np
   const int kind = prune + 2 * (mode == DDC_CORR_LEARNED && ix->P() ? 1 : 0) +
                    4 * (mode == DDC_CORR_BSAR && prune ? 1 : 0);
   const int64_t nqc = std::min<int64_t>(nq, 32768);
-  std::pair<int, int> v = fixed_variant(ix, nqc, prune);
+  Variant v = fixed_variant(ix, nqc, prune);
   {
     std::lock_guard<std::mutex> lk(ix->tune_mtx);
     auto it = ix->tuned.find(tune_class(nqc, nprobe_max, k_max, kind));
     if (it != ix->tuned.end()) v = it->second;
   }
   v = forced_or(ix, v, kind);
-  *waves = v.first;
-  *lookahead = v.second;
+  *waves = v[0];
+  *lookahead = v[1];
+  if (persistent) *persistent = v[2];
   return DDC_OK;
 }
 

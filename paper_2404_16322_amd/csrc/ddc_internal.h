@@ -42,6 +42,9 @@ struct ScanArgs {
   float *out_d;
   int64_t *counters;       // NULL or [kMaxCounters] (added to)
   const int32_t *order;    // NULL or [nq]: wave slot -> query (results do not depend on it)
+  int32_t *queue;          // NULL: one workgroup per slot group; else a device counter: the
+                           // grid is sized to the resident capacity and workgroups take slots
+                           // from it until none is left (launch_scan zeroes it first)
   int32_t xcd_swizzle;     // 1: workgroup w runs slot range of XCD (w mod 8), contiguous per XCD
   const uint8_t *base8;    // FP8 pre-stage codes: per tile 64 vectors x 64 B (NULL if none)
   const float *scale8;     // per tile decode scale
@@ -68,6 +71,12 @@ void launch_scan(const ScanArgs &a, int store, hipStream_t s);
 // order within a group arbitrary).  hist: [nlist + 1] scratch, rank: [nq] scratch.
 void launch_query_order(const int32_t *probes, int32_t p_stride, int64_t nq, int32_t nlist,
                         int32_t *hist, int32_t *rank, int32_t *order, hipStream_t s);
+// Longest-first query order for the persistent launch: key[q] = 255 - bucket of the query's
+// candidate count (sum of its probed list lengths; 8 buckets per octave), then the counting
+// sort above over the 256 keys.  key, rank: [nq] scratch; hist: [257] scratch.
+void launch_work_order(const int32_t *probes, int32_t p_stride, const int32_t *nprobe,
+                       int32_t nprobe_all, const int32_t *list_len, int32_t nlist, int64_t nq,
+                       int32_t *key, int32_t *hist, int32_t *rank, int32_t *order, hipStream_t s);
 
 // C[M x N] = (A - mu)[M x K] * B[N x K]^T on MFMA, FP32 accumulation.
 //   mode 0: out[m][n] = acc                      (query / base rotation)

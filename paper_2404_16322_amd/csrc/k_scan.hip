@@ -23,7 +23,11 @@
 #include <hip/hip_fp16.h>
 #include <math.h>
 
+#include <algorithm>
+#include <map>
+#include <mutex>
 #include <stdexcept>
+#include <tuple>
 
 namespace ddc {
 
@@ -187,9 +191,6 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
     const int per = n / 8, rem = n % 8;
     wg = x * per + min(x, rem) + r;
   }
-  const int slot = wg * QPW + qs;
-  if (slot >= a.nq) return;   // W = 4: the whole workgroup leaves together
-  const int q = a.order ? a.order[slot] : slot;
   const int g = lane % G;
   const int sub = lane / G;
   const int nb = a.nblocks;
@@ -210,6 +211,40 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
   float *s_ae = reinterpret_cast<float *>(wl + L.ae);
   float *s_ap = reinterpret_cast<float *>(wl + L.ap);
   float *s_mb = reinterpret_cast<float *>(wl + L.mb);
+
+  // statistics (wave-uniform, flushed once when counters are requested)
+  int64_t st_cand = 0, st_ref = 0, st_slices = 0, st_pre = 0, st_pre_pruned = 0;
+  unsigned long long *ctr = reinterpret_cast<unsigned long long *>(a.counters);
+  // stop-stage histogram, lane i counting stage i (one atomic per lane at the end)
+  uint32_t st_stop = 0;
+  auto stop_add = [&](int stage, uint32_t cnt) {
+    if (lane == min(stage, 63)) st_stop += cnt;
+  };
+
+  // One query per pass.  Persistent launch (a.queue set): the workgroup stays resident and
+  // takes the next slot from a device counter until none is left (the counter only grows, so
+  // every wave reaches the exit); otherwise the slot is fixed by the workgroup index and there
+  // is one pass.
+  for (int pass = 0;; ++pass) {
+  int slot;
+  if (a.queue) {
+    if (W == 1) {
+      int v = 0;
+      if (lane == 0) v = atomicAdd(a.queue, 1);
+      slot = __builtin_amdgcn_readfirstlane(__shfl(v, 0));
+    } else {
+      if (threadIdx.x == 0) s_cnt[2] = atomicAdd(a.queue, 1);
+      __syncthreads();
+      slot = __builtin_amdgcn_readfirstlane(s_cnt[2]);
+      __syncthreads();
+    }
+  } else {
+    if (pass) break;
+    slot = wg * QPW + qs;
+  }
+  if (slot >= a.nq) break;    // W = 4: the whole workgroup leaves together
+  __builtin_amdgcn_wave_barrier();
+  const int q = a.order ? a.order[slot] : slot;
 
   const int K = __builtin_amdgcn_readfirstlane(a.k ? a.k[q] : a.k_all);
   const int np = a.nprobe ? a.nprobe[q] : a.nprobe_all;
@@ -251,15 +286,6 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
     }
     __builtin_amdgcn_wave_barrier();
   }
-
-  // statistics (wave-uniform, flushed once when counters are requested)
-  int64_t st_cand = 0, st_ref = 0, st_slices = 0, st_pre = 0, st_pre_pruned = 0;
-  unsigned long long *ctr = reinterpret_cast<unsigned long long *>(a.counters);
-  // stop-stage histogram, lane i counting stage i (one atomic per lane at the end)
-  uint32_t st_stop = 0;
-  auto stop_add = [&](int stage, uint32_t cnt) {
-    if (lane == min(stage, 63)) st_stop += cnt;
-  };
 
   int tin = 0, tn = 0, par = 0;
   float tau = INFINITY;
@@ -655,8 +681,9 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
     a.out_ids[off + i] = have ? (int64_t)s_ti[tin * KM + i] : (int64_t)-1;
     a.out_d[off + i] = have ? s_td[tin * KM + i] : INFINITY;
   }
+  }  // passes
   if (ctr && st_stop) atomicAdd(&ctr[4 + lane], (unsigned long long)st_stop);
-  if (ctr && lane == 0) {
+  if (ctr && lane == 0 && st_cand) {
     atomicAdd(&ctr[0], (unsigned long long)st_cand);
     atomicAdd(&ctr[1], (unsigned long long)st_ref);
     atomicAdd(&ctr[2], (unsigned long long)st_slices);
@@ -715,13 +742,63 @@ void launch_query_order(const int32_t *probes, int32_t p_stride, int64_t nq, int
                      order);
 }
 
+__global__ void work_key_kernel(const int32_t *probes, int32_t p_stride, const int32_t *nprobe,
+                                int32_t nprobe_all, const int32_t *list_len, int32_t nlist, int64_t nq,
+                                int32_t *key) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nq) return;
+  const int np = nprobe ? nprobe[q] : nprobe_all;
+  int64_t work = 0;
+  for (int p = 0; p < np; ++p) {
+    const int l = probes[q * p_stride + p];
+    if (l >= 0 && l < nlist) work += list_len[l];
+  }
+  const int bucket = work > 0 ? min(255, (int)(log2f((float)work) * 8.f)) : 0;
+  key[q] = 255 - bucket;
+}
+
+void launch_work_order(const int32_t *probes, int32_t p_stride, const int32_t *nprobe,
+                       int32_t nprobe_all, const int32_t *list_len, int32_t nlist, int64_t nq,
+                       int32_t *key, int32_t *hist, int32_t *rank, int32_t *order, hipStream_t s) {
+  if (nq <= 0) return;
+  hipLaunchKernelGGL(work_key_kernel, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, s, probes,
+                     p_stride, nprobe, nprobe_all, list_len, nlist, nq, key);
+  launch_query_order(key, 1, nq, 256, hist, rank, order, s);
+}
+
+// Workgroups of this kernel that fit on the device at once (occupancy x compute units).
+static int resident_workgroups(const void *kern, size_t smem) {
+  static std::mutex mtx;
+  static std::map<std::tuple<const void *, size_t, int>, int> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) throw std::runtime_error("scan: hipGetDevice failed");
+  std::lock_guard<std::mutex> lk(mtx);
+  const auto key = std::make_tuple(kern, smem, dev);
+  auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
+  int per_cu = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kScanThreads, smem) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    throw std::runtime_error("scan: occupancy query failed");
+  const int r = std::max(1, per_cu) * std::max(1, cus);
+  cache[key] = r;
+  return r;
+}
+
 template <int ST, bool P, bool LK, int W, bool PRE = false, bool RES = false>
 static void launch_variant(const ScanArgs &a, hipStream_t s) {
   const size_t smem = scan_lds_bytes(a.nblocks * kBlockDims, a.k_max, a.block_b, W, RES);
   if (smem > kMaxLds) throw std::runtime_error("scan: LDS request exceeds 160 KiB");
   const int qpw = 4 / W;
-  hipLaunchKernelGGL((scan_kernel<ST, P, LK, W, PRE, RES>), dim3((unsigned)((a.nq + qpw - 1) / qpw)),
-                     dim3(kScanThreads), smem, s, a);
+  const void *kern = reinterpret_cast<const void *>(&scan_kernel<ST, P, LK, W, PRE, RES>);
+  int64_t grid = (a.nq + qpw - 1) / qpw;
+  if (a.queue) {
+    // W = 1: each wave takes its own slots, so the grid covers ceil(nq / 4) workgroups at most
+    grid = std::min<int64_t>(grid, resident_workgroups(kern, smem));
+    hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(64), 0, s, a.queue, (int64_t)1, 0);
+  }
+  hipLaunchKernelGGL((scan_kernel<ST, P, LK, W, PRE, RES>), dim3((unsigned)grid), dim3(kScanThreads),
+                     smem, s, a);
 }
 
 template <int ST> static void launch_store(const ScanArgs &a, hipStream_t s) {

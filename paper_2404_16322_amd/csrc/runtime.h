@@ -172,9 +172,10 @@ struct ddc_index {
   }
 
   // result-invariant launch knobs of the scan (0 / -1 = tuned per size class)
-  int waves_per_query = 0, lookahead = -1, query_order = 1, xcd_swizzle = 1;
+  int waves_per_query = 0, lookahead = -1, query_order = 1, xcd_swizzle = 1, persistent = -1;
   std::mutex tune_mtx;
-  std::map<std::array<int, 4>, std::pair<int, int>> tuned;  // class -> (waves, lookahead)
+  // class -> (waves per query, look-ahead, persistent)
+  std::map<std::array<int, 4>, std::array<int, 3>> tuned;
   int store() const {
     return storage == DDC_F32 ? ddc::ST_F32 : storage == DDC_F16 ? ddc::ST_F16 : ddc::ST_BF16;
   }

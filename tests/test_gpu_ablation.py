@@ -102,11 +102,14 @@ def test_residual_test_variants_identical_and_huge_m_is_exact():
     g.set_bsar_multiplier(4.0)
     res = []
     for wv in (1, 4):
-        g.set_launch(waves_per_query=wv, lookahead=1)   # look-ahead does not apply to this test
-        res.append(g.search(w["queries"], 10, 8, 0.0, mode="bsar"))
-    np.testing.assert_array_equal(res[0][0], res[1][0])
-    np.testing.assert_array_equal(res[0][1], res[1][1])
-    g.set_launch(waves_per_query=0, lookahead=-1)
+        for p in (0, 1):
+            # look-ahead does not apply to this test
+            g.set_launch(waves_per_query=wv, lookahead=1, persistent=p)
+            res.append(g.search(w["queries"], 10, 8, 0.0, mode="bsar"))
+    for r in res[1:]:
+        np.testing.assert_array_equal(res[0][0], r[0])
+        np.testing.assert_array_equal(res[0][1], r[1])
+    g.set_launch(waves_per_query=0, lookahead=-1, persistent=-1)
     g.set_bsar_multiplier(1e12)
     a = g.search(w["queries"], 10, 8, 0.0, mode="bsar")
     n = g.search(w["queries"], 10, 8, 0.0, mode="none")

@@ -71,8 +71,8 @@ def test_prestage_variants_bitwise_identical():
     w = workload("gauss128")
     g = _index(ix)
     res = []
-    for wv, la in [(1, 0), (1, 1), (4, 0), (4, 1)]:
-        g.set_launch(waves_per_query=wv, lookahead=la)
+    for wv, la, p in [(w_, l_, p_) for p_ in (0, 1) for w_ in (1, 4) for l_ in (0, 1)]:
+        g.set_launch(waves_per_query=wv, lookahead=la, persistent=p)
         res.append(g.search(w["queries"], 10, 8, 0.1))
     for r in res[1:]:
         np.testing.assert_array_equal(r[0], res[0][0])

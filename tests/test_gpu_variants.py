@@ -1,6 +1,7 @@
 """Launch-shape variants of the scan (one wavefront or a workgroup of four per query, with and
-without multi-block look-ahead loads) return bit-identical results, which match the oracle;
-the tuner picks one of them per size class."""
+without multi-block look-ahead loads, one pass per workgroup or a persistent grid taking queries
+longest first from a counter) return bit-identical results, which match the oracle; the tuner
+picks one of them per size class."""
 import numpy as np
 import pytest
 
@@ -9,7 +10,7 @@ from parity_util import artifacts, check_search, oracle_index, workload
 
 pytestmark = pytest.mark.gpu
 
-VARIANTS = [(1, 0), (1, 1), (4, 0), (4, 1)]
+VARIANTS = [(w, la, p) for p in (0, 1) for w in (1, 4) for la in (0, 1)]
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -25,10 +26,10 @@ def _index(ix):
 
 def _all_variants(g, run):
     out = []
-    for w, la in VARIANTS:
-        g.set_launch(waves_per_query=w, lookahead=la)
+    for w, la, p in VARIANTS:
+        g.set_launch(waves_per_query=w, lookahead=la, persistent=p)
         out.append(run())
-    g.set_launch(waves_per_query=0, lookahead=-1)
+    g.set_launch(waves_per_query=0, lookahead=-1, persistent=-1)
     return out
 
 
@@ -98,16 +99,44 @@ def test_tuner_picks_a_variant_and_caches_it():
     ix = oracle_index()
     w = workload("gauss128")
     g = _index(ix)
-    assert g.launch() == dict(waves_per_query=0, lookahead=-1, query_order=1, xcd_swizzle=1)
+    assert g.launch() == dict(waves_per_query=0, lookahead=-1, query_order=1, xcd_swizzle=1,
+                              persistent=-1)
     ids0, d0, _ = g.search(w["queries"], 10, 8, 0.1)
     v = g.scan_variant(w["queries"].shape[0], 10, 8)
     assert v in VARIANTS
     ids1, d1, _ = g.search(w["queries"], 10, 8, 0.1)
     np.testing.assert_array_equal(ids0, ids1)
     np.testing.assert_array_equal(d0, d1)
-    g.set_launch(waves_per_query=4, lookahead=0, query_order=0, xcd_swizzle=0)
-    assert g.scan_variant(1000, 10, 8) == (4, 0)
-    assert g.scan_variant(1000, 10, 8, mode="none") == (4, 0)
+    g.set_launch(waves_per_query=4, lookahead=0, query_order=0, xcd_swizzle=0, persistent=1)
+    assert g.scan_variant(1000, 10, 8) == (4, 0, 1)
+    assert g.scan_variant(1000, 10, 8, mode="none") == (4, 0, 1)
     ids2, d2, _ = g.search(w["queries"], 10, 8, 0.1)
     np.testing.assert_array_equal(ids0, ids2)
     np.testing.assert_array_equal(d0, d2)
+
+
+def test_persistent_grid_smaller_than_batch():
+    """A batch far larger than the resident grid: every workgroup of the persistent launch
+    runs many queries in turn; results equal the one-pass launch bit for bit."""
+    ix = oracle_index()
+    w = workload("gauss128")
+    g = _index(ix)
+    Q = np.tile(w["queries"], (120, 1))            # 12,000 queries
+    rng = np.random.default_rng(5)
+    ks = np.tile(rng.integers(1, 64, 100), 120).astype(np.int32)
+    nps = np.tile(rng.integers(1, 33, 100), 120).astype(np.int32)
+    res = []
+    for wv in (1, 4):
+        for p in (0, 1):
+            g.set_launch(waves_per_query=wv, lookahead=0, persistent=p)
+            res.append(g.search_var(Q, ks, nps, 0.1))
+    _assert_identical([r[:3] for r in res])
+    for r in res[1:]:
+        for key in ("candidates", "refined", "stage_slices"):
+            assert r[3][key] == res[0][3][key], key
+    # every copy of a query returns that query's result, wherever the launch placed it
+    ids, d, off = res[-1][:3]
+    for i in range(100, Q.shape[0]):
+        j = i % 100
+        np.testing.assert_array_equal(ids[off[i]:off[i + 1]], ids[off[j]:off[j + 1]])
+        np.testing.assert_array_equal(d[off[i]:off[i + 1]], d[off[j]:off[j + 1]])
