@@ -188,6 +188,9 @@ def main():
     ap.add_argument("--ood", action="store_true",
                     help="also search shifted queries with the fitted table, the residual test and a "
                          "table recalibrated on 100 of them")
+    ap.add_argument("--exp7", action="store_true",
+                    help="also rank the whole base by each estimate over the leading 32 dims alone "
+                         "(PCA, residual, random projection) and report recall@100")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -530,6 +533,33 @@ def main():
         ix.close()
         ix = ix_main
 
+    # ---- approximation accuracy of the estimates alone (Exp-7 / Table III analogue): every
+    # point ranked by its estimate over the leading 32 rotated dims, recall@100 against FP64
+    exp7 = None
+    if args.exp7 and nlist > 4096:
+        log("[bench] estimates alone: skipped (probe selection covers at most 4,096 lists, so the "
+            "whole base cannot be ranked on this index)")
+    elif args.exp7 and not uneven:
+        n7 = min(nq, 1000)
+        Q7 = w["queries"][:n7]
+        gt100 = exact_knn_fp64(torch.from_numpy(w["base"]).to(dev, torch.float64),
+                               torch.from_numpy(Q7).to(dev, torch.float64), 100)
+        torch.cuda.empty_cache()
+
+        def rec100(ids_):
+            return round(float(np.mean([len(set(a.tolist()) & set(b.tolist())) / 100
+                                        for a, b in zip(ids_, gt100)])), 4)
+        cols = {}
+        for est, name in (("partial", "pca"), ("residual", "residual_alg1")):
+            cols[name] = rec100(ix.search_estimate(Q7, 100, nlist, 32, est)[0])
+        ixh = Index.fit(w["base"], w["calib"], nlist=nlist, seed=spec["cfg"], storage=cfg["storage"],
+                        rotation=cfg["rotation"], projection="haar", **cfg.get("fit", {}))
+        cols["rand"] = rec100(ixh.search_estimate(Q7, 100, nlist, 32, "partial")[0])
+        ixh.close()
+        exp7 = dict(dims=32, k=100, queries=n7, candidates="every base vector (nprobe = nlist)",
+                    recall_at_100=cols)
+        log(f"[bench] estimates alone at 32 dims: {exp7}")
+
     # ---- serving: open-loop Poisson arrivals, continuous batching --------------------------
     serve = []
     rates = []
@@ -620,6 +650,7 @@ def main():
         "without_fp8_prestage": no_pre,
         "ablation": ablation,
         "out_of_distribution": ood,
+        "estimate_accuracy": exp7,
         "scan_variant_ms": variants,
         "scan_variant_tuned": {"waves_per_query": chosen[0], "lookahead": chosen[1],
                                "persistent": chosen[2]},

@@ -226,6 +226,25 @@ ddc_status ddc_search_device(const ddc_index *ix, const float *d_queries, int64_
                              int64_t *d_ids, float *d_dists, int64_t *d_counters,
                              void *hip_stream);
 
+/* Approximation accuracy of a distance estimate alone (the direct scan of the paper's
+ * approximation-accuracy experiment, Sec. VII Exp-7 and its Table III): for every query, the
+ * k candidates of the nprobe nearest lists (nprobe = nlist: the whole base) with the smallest
+ * estimated squared distance over the leading `dims` rotated dimensions, with no correction and
+ * no refinement.  Estimators:
+ *   DDC_EST_PARTIAL  (dim / min(dims, dim)) * sum_{i < dims} (q'_i - y_i)^2: the projection
+ *                    estimate (on a PCA index the paper's "PCA" column, on a Haar index its
+ *                    random-projection "Rand" column, unbiased there);
+ *   DDC_EST_RESIDUAL sum_{i < dims} (q'_i - y_i)^2 + ||y_r||^2 + ||q'_r||^2 = C1 - C2 of
+ *                    Alg. 1 (the residual decomposition behind the paper's third column).
+ * dims: a multiple of 32 in [32, dim rounded up to 32]; dims >= dim gives exact distances.
+ * ids/dists: host [nq x k], ascending by (estimate, id), dists = the estimates, padding
+ * (-1, +inf).  Errors: EINVAL for bad sizes, k, nprobe, dims or estimator (before any GPU
+ * work). */
+typedef enum { DDC_EST_PARTIAL = 0, DDC_EST_RESIDUAL = 1 } ddc_estimator;
+ddc_status ddc_search_estimate(const ddc_index *ix, const float *queries, int64_t nq, int32_t k,
+                               int32_t nprobe, int32_t dims, ddc_estimator estimator, int64_t *ids,
+                               float *dists);
+
 /* Intermediates of the first two hot-path steps for parity checks (host buffers):
  * q_rot [nq x dim] = R (q - mu) as the search computes it; probes [nq x nprobe] in probe
  * order (ascending centroid distance, then list id). */

@@ -850,6 +850,63 @@ def search(index, queries, k, nprobe, alpha, mode="learned", B=None, L=None, cal
                 beta=beta)
 
 
+# --------------------------------------------------------------------------------------
+# Approximation accuracy of an estimate alone  [Sec. VII Exp-7, Table III: the estimate
+# ranks the points directly, with no AKNN index logic, correction or refinement]
+# --------------------------------------------------------------------------------------
+
+def estimate_values(Y, qrot, ids, dims, estimator="partial"):
+    """The estimate of ``estimate_scan`` for the stored rows ``ids`` and one rotated query."""
+    D = Y.shape[1]
+    d = min(int(dims), D)
+    Yc = np.asarray(Y[ids], dtype=np.float64)
+    q = np.asarray(qrot, dtype=np.float64)
+    e = np.sum((Yc[:, :d] - q[None, :d]) ** 2, axis=1)
+    if estimator == "partial":
+        return (D / d) * e
+    if estimator == "residual":
+        return e + np.sum(Yc[:, d:] ** 2, axis=1) + float(np.sum(q[d:] ** 2))
+    raise ValueError(estimator)
+
+
+def estimate_scan(index, queries, k, nprobe, dims, estimator="partial"):
+    """Top-k of the candidates of the nprobe nearest lists (nprobe = nlist: every point) by
+    an estimated squared distance over the leading d = min(dims, D) rotated dimensions:
+
+      'partial':  (D / d) * sum_{i<d} (q'_i - y_i)^2  -- the projection estimate; under a
+                  random rotation its expectation is the distance (Sec. III, Lemma 1's
+                  scaling); on the PCA rotation it ranks like the plain projected distance;
+      'residual': sum_{i<d} (q'_i - y_i)^2 + ||y_r||^2 + ||q'_r||^2 = C1 - C2 of Alg. 1,
+                  i.e. Eq. (1) with the cross term of the residual dims i >= d dropped.
+
+    Ranked by (estimate, id), padded with (-1, inf).  Returns ids (nq, k), estimates (nq, k)
+    and margin (nq,): the smallest relative gap at the k-th / (k+1)-th estimate and in the
+    probe order, where other rounding may swap candidates."""
+    Qr = rotate(queries, index["mu"], index["R"])
+    nq = Qr.shape[0]
+    ids = np.full((nq, k), -1, dtype=np.int64)
+    est = np.full((nq, k), np.inf)
+    margin = np.full(nq, math.inf)
+    off, lids = index["list_off"], index["list_ids"]
+    for qi in range(nq):
+        probes, _, pm = probe_order(Qr[qi], index["centroids"], nprobe)
+        cand = np.concatenate([lids[off[l]:off[l + 1]] for l in probes]) if len(probes) else \
+            np.zeros(0, np.int64)
+        if cand.size == 0:
+            continue
+        v = estimate_values(index["Y"], Qr[qi], cand, dims, estimator)
+        order = np.lexsort((cand, v))
+        top = order[:k]
+        ids[qi, :top.size] = cand[top]
+        est[qi, :top.size] = v[top]
+        mg = pm
+        if order.size > k:
+            a_, b_ = v[order[k - 1]], v[order[k]]
+            mg = min(mg, abs(b_ - a_) / max(abs(b_), 1e-300))
+        margin[qi] = mg
+    return dict(ids=ids, est=est, margin=margin, qrot=Qr)
+
+
 def bsar_multiplier(alpha: float, m: float) -> float:
     """The multiplier of the residual test: m itself when m > 0 (the paper fixes m per data
     set, Sec. VII-A), else the one-sided Gaussian quantile Phi^-1(1 - alpha) of the error

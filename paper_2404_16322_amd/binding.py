@@ -15,6 +15,7 @@ DTYPE = {"f32": 0, "f16": 1, "bf16": 2}
 ROT = {"f32": 0, "bf16": 1}
 CORR = {"learned": 0, "lossless": 1, "none": 2, "ads": 3, "bsar": 4}
 PROJ = {"pca": 0, "haar": 1}
+EST = {"partial": 0, "residual": 1}
 CALIB = {"joint": 0, "bonferroni": 1}
 STATUS = {0: "DDC_OK", -1: "DDC_EINVAL", -2: "DDC_ENOMEM", -3: "DDC_EDEVICE", -4: "DDC_EIO",
           -5: "DDC_EBUSY", -6: "DDC_EUNSUP"}
@@ -24,7 +25,8 @@ SYMBOLS = ["ddc_fit_params_default", "ddc_fit", "ddc_import", "ddc_export", "ddc
            "ddc_debug_intermediates", "ddc_set_kernel_timing", "ddc_get_kernel_timing", "ddc_free",
            "ddc_last_error", "ddc_server_create", "ddc_server_submit", "ddc_server_poll",
            "ddc_server_get_stats", "ddc_server_destroy", "ddc_set_launch", "ddc_get_launch",
-           "ddc_scan_variant", "ddc_save", "ddc_load", "ddc_set_ads_epsilon", "ddc_set_bsar_multiplier"]
+           "ddc_scan_variant", "ddc_save", "ddc_load", "ddc_set_ads_epsilon", "ddc_set_bsar_multiplier",
+           "ddc_search_estimate"]
 
 
 class FitParams(C.Structure):
@@ -120,6 +122,7 @@ def load_library():
         lib.ddc_search_device.argtypes = [vp, vp, i64, vp, i32, i32, vp, i32, i32, f64, C.c_int, vp,
                                           vp, vp, vp, vp]
         lib.ddc_debug_intermediates.argtypes = [vp, vp, i64, i32, vp, vp]
+        lib.ddc_search_estimate.argtypes = [vp, vp, i64, i32, i32, i32, C.c_int, vp, vp]
         lib.ddc_set_kernel_timing.argtypes = [vp, C.c_int]
         lib.ddc_get_kernel_timing.argtypes = [vp, vp, vp, C.c_int]
         lib.ddc_set_ads_epsilon.argtypes = [vp, f64]
@@ -319,6 +322,16 @@ class Index:
         _check(load_library().ddc_search(self._h, _ptr(q), nq, k, nprobe, alpha, CORR[mode],
                                          _ptr(ids), _ptr(d), C.byref(st)))
         return ids, d, st.as_dict()
+
+    def search_estimate(self, queries, k: int, nprobe: int, dims: int, estimator: str = "partial"):
+        """Top-k by an estimate over the leading `dims` rotated dims (no correction, no
+        refinement): (ids [nq, k], estimates [nq, k])."""
+        q = _f32(queries)
+        ids = np.empty((q.shape[0], k), np.int64)
+        d = np.empty((q.shape[0], k), np.float32)
+        _check(load_library().ddc_search_estimate(self._h, _ptr(q), q.shape[0], k, nprobe, dims,
+                                                  EST[estimator], _ptr(ids), _ptr(d)))
+        return ids, d
 
     def search_var(self, queries, k, nprobe, alpha: float, mode: str = "learned"):
         q = _f32(queries)

@@ -38,8 +38,10 @@ static std::array<int, 4> tune_class(int64_t nq, int np_max, int k_max, int kind
           ceil_log2(std::max(k_max, 1)), kind};
 }
 
-// kernel family of a launch: pruned or not, FP8 pre-stage, residual test
-static int scan_kind(const ScanArgs &a) { return a.prune + 2 * a.pre + 4 * a.res; }
+// kernel family of a launch: pruned or not, FP8 pre-stage, residual test, estimate only
+static int scan_kind(const ScanArgs &a) {
+  return a.prune + 2 * a.pre + 4 * a.res + 8 * (a.est_nb > 0 ? 1 : 0);
+}
 
 // Launch shape of the scan: waves per query (1 or 4), look-ahead (0 or 1), persistent (0 or 1).
 using Variant = std::array<int, 3>;
@@ -557,11 +559,18 @@ void ddc::search_device(ddc_index *ix, const float *d_q, int64_t nq, const int32
                         int k_max, const int32_t *d_np, int np_all, int np_max, double alpha,
                         ddc_corr mode, const int64_t *d_off, int64_t *d_ids, float *d_d,
                         int64_t *d_ctr, hipStream_t s, float *qrot_out, int32_t *probes_out,
-                        bool may_tune) {
+                        bool may_tune, const EstimateSpec *est) {
   const int Dp = ix->Dp, D = ix->D;
   ScanArgs a{};
   a.prune = 0;
   std::shared_ptr<DevBuf> tabs;   // keeps the device tables alive for this call
+  if (est) {
+    mode = DDC_CORR_NONE;
+    a.est_nb = est->nb;
+    a.est_res = est->residual;
+    a.est_scale = est->scale;
+    a.xnorm = ix->d_xnorm.as<float>();
+  }
   const bool learned = mode == DDC_CORR_LEARNED && alpha > 0 && ix->Tt() > 0;
   // LOSSLESS tests e_s > tau with the stored values only: the FP8 estimate is no lower bound;
   // ADS is a fixed table on the stored values too
@@ -1151,6 +1160,37 @@ ddc_status ddc_search(const ddc_index *ix, const float *queries, int64_t nq, int
   if (nq > 0 && (!queries || !ids || !dists)) return set_err(DDC_EINVAL, "NULL buffer");
   return search_host(ix, queries, nq, nullptr, k, nullptr, nprobe, significance, mode, nullptr, ids,
                      dists, stats);
+}
+
+ddc_status ddc_search_estimate(const ddc_index *ixc, const float *queries, int64_t nq, int32_t k,
+                               int32_t nprobe, int32_t dims, ddc_estimator estimator, int64_t *ids,
+                               float *dists) {
+  if (!ixc) return set_err(DDC_EINVAL, "index is NULL");
+  ddc_status st = check_k_np(ixc, k, nprobe);
+  if (st != DDC_OK) return st;
+  if (dims < kBlockDims || dims % kBlockDims || dims > ixc->Dp)
+    return set_err(DDC_EINVAL, "dims must be a multiple of 32 in [32, %d], got %d", ixc->Dp, dims);
+  if (estimator != DDC_EST_PARTIAL && estimator != DDC_EST_RESIDUAL)
+    return set_err(DDC_EINVAL, "unknown estimator %d", (int)estimator);
+  if (nq < 0 || (nq > 0 && (!queries || !ids || !dists))) return set_err(DDC_EINVAL, "bad buffers");
+  if (!all_finite(queries, nq * ixc->D)) return set_err(DDC_EINVAL, "non-finite query values");
+  if (nq == 0) return DDC_OK;
+  GUARD_BEGIN
+  ddc_index *ix = const_cast<ddc_index *>(ixc);
+  DeviceGuard dg(ix->device);
+  StreamHolder sh;
+  EstimateSpec es{dims / kBlockDims, estimator == DDC_EST_RESIDUAL ? 1 : 0,
+                  (float)((double)ix->D / std::min(dims, ix->D))};
+  DevBuf d_q((size_t)nq * ix->D * 4), d_ids((size_t)nq * k * 8), d_d((size_t)nq * k * 4);
+  HIPC(hipMemcpyAsync(d_q.p, queries, (size_t)nq * ix->D * 4, hipMemcpyHostToDevice, sh.s));
+  search_device(ix, d_q.as<float>(), nq, nullptr, k, k, nullptr, nprobe, nprobe, 0.0, DDC_CORR_NONE,
+                nullptr, d_ids.as<int64_t>(), d_d.as<float>(), nullptr, sh.s, nullptr, nullptr, true,
+                &es);
+  HIPC(hipMemcpyAsync(ids, d_ids.p, (size_t)nq * k * 8, hipMemcpyDeviceToHost, sh.s));
+  HIPC(hipMemcpyAsync(dists, d_d.p, (size_t)nq * k * 4, hipMemcpyDeviceToHost, sh.s));
+  HIPC(hipStreamSynchronize(sh.s));
+  return DDC_OK;
+  GUARD_END
 }
 
 ddc_status ddc_search_var(const ddc_index *ix, const float *queries, int64_t nq, const int32_t *k,

@@ -53,6 +53,10 @@ struct ScanArgs {
   const float *xnorm;      // [tiles * 64] ||y||^2 of every stored slot
   const float *lam;        // [nblocks * 32] variance along every rotated axis (0 beyond D)
   float bsar_m;            // multiplier m of m sigma
+  int32_t est_nb;          // > 0 (with prune = 0): rank by an estimate over the leading est_nb
+                           // dim blocks, no refinement (needs xnorm when est_res)
+  int32_t est_res;         // estimate: 0 = est_scale * partial distance, 1 = residual (Alg. 1)
+  float est_scale;
   int32_t waves_per_query; // 1 or 4 (result-invariant)
   int32_t lookahead;       // 0 or 1: multi-stage loads when few candidates survive (result-invariant)
   int32_t nq, nblocks, block_b, prune, nlist, k_max;

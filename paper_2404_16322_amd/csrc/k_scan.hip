@@ -167,8 +167,11 @@ __host__ __device__ inline size_t scan_lds_bytes(int Dp, int kmax, int block_b, 
 // one query per workgroup, each block's tiles split over the four waves, survivors merged
 // by the workgroup between two barriers).  LOOK enables the multi-stage look-ahead; PRE the
 // FP8 pre-stage over the leading 64 dims before the first stage; RES the residual-estimate
-// test of Alg. 2 instead of the learned one (one stage per load).
-template <int ST, bool PRUNE, bool LOOK, int W, bool PRE, bool RES>
+// test of Alg. 2 instead of the learned one (one stage per load).  EST (with PRUNE off): rank
+// every candidate by an estimate over the leading est_nb dim blocks instead of its distance
+// (no refinement): est_scale * e_d, or with est_res the residual estimate of Alg. 1
+// e_d + ||x_r||^2 + ||q'_r||^2 (C1 - C2).
+template <int ST, bool PRUNE, bool LOOK, int W, bool PRE, bool RES, bool EST = false>
 __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4, 8))) void scan_kernel(ScanArgs a) {
   using S = Store<ST>;
   constexpr int EPL = 16 / S::kBytes;          // elements per lane load
@@ -261,6 +264,13 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
     for (int i = lane; i < 2 * (nb + 1); i += 64) s_mb[i] = tq[i];
   }
   if (W > 1) __syncthreads(); else __builtin_amdgcn_wave_barrier();
+  const int nbe = EST ? a.est_nb : nb;           // dim blocks the no-test path reads
+  float qres = 0.f;                              // EST: ||q'_r||^2 beyond the leading blocks
+  if (EST) {
+    for (int i = nbe * kBlockDims + lane; i < Dp; i += 64) qres = fmaf(s_q[i], s_q[i], qres);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) qres += __shfl_xor(qres, o);
+  }
   if (RES) {
     // per dim block b: ||q'_r||^2 - m sigma over the residual dims >= 32 (b + 1), with
     // sigma = sqrt(4 sum q'_i^2 lam_i) (Eq. (2)); block sums first, then suffix sums
@@ -328,18 +338,18 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
       const int slen = W == 1 ? blen : min(kTile, blen - s0);
       const unsigned char *bbase = lbase + (int64_t)((bs + s0) / kTile) * nb * BLOCK_BYTES;
       const int32_t *bids = lids + bs + s0;
-      const float *xnorm_seg = RES ? a.xnorm + (int64_t)a.tile_off[lst] * kTile + bs + s0 : nullptr;
+      const float *xnorm_seg = (RES || EST) ? a.xnorm + (int64_t)a.tile_off[lst] * kTile + bs + s0 : nullptr;
       // In a load group, chunk c, lane (sub, g) reads dims [g*EPL, g*EPL+EPL) of candidate
       // t0 + c*CPW + sub; after transpose_sum the lane owns candidate t0 + g*CPW + sub.
       if (!PRUNE || tn < K) {
         // ---- no test can prune: every candidate, every dim block ----
         // Slots past slen inside the last tile are zero padding: loads stay in bounds.
         for (int t0 = 0; t0 < slen; t0 += GROUP) {
-          float acc[MAXCH];
+          float acc[MAXCH], accp[MAXCH];
 #pragma unroll
-          for (int c = 0; c < MAXCH; ++c) acc[c] = 0.f;
+          for (int c = 0; c < MAXCH; ++c) acc[c] = accp[c] = 0.f;
           const uint32_t tile_off = (uint32_t)(t0 / kTile) * nb * (uint32_t)BLOCK_BYTES;
-          for (int b = 0; b < nb; ++b) {
+          for (int b = 0; b < nbe; ++b) {
             float qv[EPL];
 #pragma unroll
             for (int e = 0; e < EPL; ++e) qv[e] = s_q[b * kBlockDims + g * EPL + e];
@@ -356,11 +366,16 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
               for (int e = 0; e < EPL; ++e) {
                 const float d = f[e] - qv[e];
                 acc[c] = fmaf(d, d, acc[c]);
+                if (EST) accp[c] = fmaf(f[e], f[e], accp[c]);
               }
             }
           }
-          const float dis = transpose_sum<G>(acc, g);
+          float dis = transpose_sum<G>(acc, g);
           const int sl = t0 + g * CPW + sub;
+          if (EST) {
+            const float xr = transpose_sum<G>(accp, g);   // ||x_d||^2 of the leading blocks
+            dis = a.est_res ? dis + ((sl < slen ? xnorm_seg[sl] : 0.f) - xr) + qres : a.est_scale * dis;
+          }
           bool keep = false;
           int32_t id = 0;
           if (sl < slen) {
@@ -369,8 +384,8 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
           }
           append(keep, dis, id);
         }
-        st_cand += slen; st_ref += slen; st_slices += (int64_t)slen * nb;
-        if (ctr) stop_add(nb - 1, (uint32_t)slen);
+        st_cand += slen; st_ref += slen; st_slices += (int64_t)slen * nbe;
+        if (ctr) stop_add(nbe - 1, (uint32_t)slen);
       } else if (PRUNE) {
         // ---- staged scan: test after every stage, compact the survivors ----
         // Lanes past the live count read the group's first live candidate (same cache
@@ -388,45 +403,56 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
 #pragma unroll
           for (int e = 0; e < 16; ++e) q8[e] = s_q[g8 * 16 + e];
           const int tile0 = a.tile_off[lst] + (bs + s0) / kTile;   // wave-uniform
+          const int last_tile = tile0 + (slen - 1) / kTile;
           int nn = 0;
-          for (int t0 = 0; t0 < slen; t0 += kTile) {
-            const int tile = tile0 + t0 / kTile;
-            const float sc = a.scale8[tile];
-            const unsigned char *p8 = a.base8 + (int64_t)tile * (kTile * kFp8Lead) + g8 * 16;
-            uint4 v[CH8];
+          // two tiles per round trip: their loads are issued together; a second tile past the
+          // segment re-reads the last one (in bounds) and every lane of it is masked out
+          constexpr int NT8 = 2;
+          for (int t0 = 0; t0 < slen; t0 += NT8 * kTile) {
+            uint4 v[NT8][CH8];
+            float sc[NT8];
 #pragma unroll
-            for (int c = 0; c < CH8; ++c)
-              v[c] = *reinterpret_cast<const uint4 *>(p8 + (c * CPW8 + sub8) * 64);
-            float part[CH8];
+            for (int u = 0; u < NT8; ++u) {
+              const int tile = min(tile0 + t0 / kTile + u, last_tile);
+              sc[u] = a.scale8[tile];
+              const unsigned char *p8 = a.base8 + (int64_t)tile * (kTile * kFp8Lead) + g8 * 16;
 #pragma unroll
-            for (int c = 0; c < CH8; ++c) {
-              const uint32_t w[4] = {v[c].x, v[c].y, v[c].z, v[c].w};
-              float acc = 0.f;
+              for (int c = 0; c < CH8; ++c)
+                v[u][c] = *reinterpret_cast<const uint4 *>(p8 + (c * CPW8 + sub8) * 64);
+            }
 #pragma unroll
-              for (int i = 0; i < 4; ++i) {
-                float f[4];
-                e4m3x4_to_f32(w[i], f);
+            for (int u = 0; u < NT8; ++u) {
+              float part[CH8];
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                  const float d = f[e] * sc - q8[4 * i + e];
-                  acc = fmaf(d, d, acc);
+              for (int c = 0; c < CH8; ++c) {
+                const uint32_t w[4] = {v[u][c].x, v[u][c].y, v[u][c].z, v[u][c].w};
+                float acc = 0.f;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                  float f[4];
+                  e4m3x4_to_f32(w[i], f);
+#pragma unroll
+                  for (int e = 0; e < 4; ++e) {
+                    const float d = f[e] * sc[u] - q8[4 * i + e];
+                    acc = fmaf(d, d, acc);
+                  }
                 }
+                part[c] = acc;
               }
-              part[c] = acc;
+              const float e0 = transpose_sum<G8>(part, g8);
+              const int idx = t0 + u * kTile + g8 * CPW8 + sub8;
+              const bool valid = idx < slen;
+              const bool prune = valid && fmaf(s_mb[2 * nb], e0, s_mb[2 * nb + 1]) > tau;
+              const bool keep = valid && !prune;
+              const unsigned long long bal = __ballot(keep);
+              if (keep) {
+                const int pos = nn + __popcll(bal & lt);
+                s_ac[pos] = (uint16_t)idx;
+                s_ae[pos] = 0.f;
+              }
+              nn += __popcll(bal);
+              st_pre_pruned += __popcll(__ballot(prune));
             }
-            const float e0 = transpose_sum<G8>(part, g8);
-            const int idx = t0 + g8 * CPW8 + sub8;
-            const bool valid = idx < slen;
-            const bool prune = valid && fmaf(s_mb[2 * nb], e0, s_mb[2 * nb + 1]) > tau;
-            const bool keep = valid && !prune;
-            const unsigned long long bal = __ballot(keep);
-            if (keep) {
-              const int pos = nn + __popcll(bal & lt);
-              s_ac[pos] = (uint16_t)idx;
-              s_ae[pos] = 0.f;
-            }
-            nn += __popcll(bal);
-            st_pre_pruned += __popcll(__ballot(prune));
           }
           st_pre += slen;
           __builtin_amdgcn_wave_barrier();
@@ -785,25 +811,28 @@ static int resident_workgroups(const void *kern, size_t smem) {
   return r;
 }
 
-template <int ST, bool P, bool LK, int W, bool PRE = false, bool RES = false>
+template <int ST, bool P, bool LK, int W, bool PRE = false, bool RES = false, bool EST = false>
 static void launch_variant(const ScanArgs &a, hipStream_t s) {
   const size_t smem = scan_lds_bytes(a.nblocks * kBlockDims, a.k_max, a.block_b, W, RES);
   if (smem > kMaxLds) throw std::runtime_error("scan: LDS request exceeds 160 KiB");
   const int qpw = 4 / W;
-  const void *kern = reinterpret_cast<const void *>(&scan_kernel<ST, P, LK, W, PRE, RES>);
+  const void *kern = reinterpret_cast<const void *>(&scan_kernel<ST, P, LK, W, PRE, RES, EST>);
   int64_t grid = (a.nq + qpw - 1) / qpw;
   if (a.queue) {
     // W = 1: each wave takes its own slots, so the grid covers ceil(nq / 4) workgroups at most
     grid = std::min<int64_t>(grid, resident_workgroups(kern, smem));
     hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(64), 0, s, a.queue, (int64_t)1, 0);
   }
-  hipLaunchKernelGGL((scan_kernel<ST, P, LK, W, PRE, RES>), dim3((unsigned)grid), dim3(kScanThreads),
-                     smem, s, a);
+  hipLaunchKernelGGL((scan_kernel<ST, P, LK, W, PRE, RES, EST>), dim3((unsigned)grid),
+                     dim3(kScanThreads), smem, s, a);
 }
 
 template <int ST> static void launch_store(const ScanArgs &a, hipStream_t s) {
   const bool w4 = a.waves_per_query == 4;
-  if (!a.prune) {
+  if (a.est_nb > 0) {
+    if (w4) launch_variant<ST, false, false, 4, false, false, true>(a, s);
+    else launch_variant<ST, false, false, 1, false, false, true>(a, s);
+  } else if (!a.prune) {
     if (w4) launch_variant<ST, false, false, 4>(a, s); else launch_variant<ST, false, false, 1>(a, s);
   } else if (a.res) {
     if (w4) launch_variant<ST, true, false, 4, false, true>(a, s); else launch_variant<ST, true, false, 1, false, true>(a, s);

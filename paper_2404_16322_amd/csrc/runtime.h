@@ -185,12 +185,21 @@ struct ddc_index {
 
 namespace ddc {
 
+// Estimate-only scan: rank candidates by an estimate over the leading nb dim blocks.
+struct EstimateSpec {
+  int nb;        // dim blocks read
+  int residual;  // 0: scale * partial distance; 1: residual estimate (Alg. 1, C1 - C2)
+  float scale;
+};
+
 // The search pipeline on device buffers (rotation -> coarse -> select -> scan), queued on s.
+// est (nullable): rank by that estimate instead (mode and alpha are then ignored).
 void search_device(ddc_index *ix, const float *d_q, int64_t nq, const int32_t *d_k, int k_all,
                    int k_max, const int32_t *d_np, int np_all, int np_max, double alpha,
                    ddc_corr mode, const int64_t *d_off, int64_t *d_ids, float *d_d,
                    int64_t *d_ctr, hipStream_t s, float *qrot_out = nullptr,
-                   int32_t *probes_out = nullptr, bool may_tune = true);
+                   int32_t *probes_out = nullptr, bool may_tune = true,
+                   const EstimateSpec *est = nullptr);
 // Device bytes one search of nq queries allocates from the stream-ordered pool.
 size_t search_scratch_bytes(const ddc_index *ix, int64_t nq, int np_max);
 

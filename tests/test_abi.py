@@ -43,7 +43,8 @@ def test_struct_layouts_match_the_c_compiler(tmp_path):
     """sizeof / offsetof of every ABI struct, as gcc lays out include/ddc.h, equal ctypes'."""
     structs = {"ddc_fit_params": B.FitParams, "ddc_artifacts": B.Artifacts,
                "ddc_index_info": B.IndexInfo, "ddc_search_stats": B.SearchStats,
-               "ddc_server_params": B.ServerParams, "ddc_server_stats": B.ServerStats}
+               "ddc_server_params": B.ServerParams, "ddc_server_stats": B.ServerStats,
+               "ddc_launch_params": B.LaunchParams}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "ddc.h"', "int main(void){"]
     for cname, cls in structs.items():
         lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
@@ -83,6 +84,12 @@ def test_search_rejects_bad_arguments_without_device(lib):
     rc = lib.ddc_search_device(None, None, 1, None, 10, 10, None, 1, 1, 0.1, 0, None, None, None,
                                None, None)
     assert rc == -1
+    rc = lib.ddc_search_estimate(None, q.ctypes.data, 1, 10, 1, 32, 0, ids.ctypes.data, d.ctypes.data)
+    assert rc == -1 and b"NULL" in lib.ddc_last_error()
+    lp = B.LaunchParams(0, -1, 1, 1, -1)
+    assert lib.ddc_set_launch(None, C.byref(lp)) == -1
+    w = C.c_int32()
+    assert lib.ddc_scan_variant(None, 1, 1, 1, 0, C.byref(w), C.byref(w), None) == -1
 
 
 def test_fit_rejects_bad_parameters_without_device(lib):

@@ -698,3 +698,79 @@ def test_recalibration_on_100_ood_queries_restores_significance(small_index):
         boots = np.array([per_q[rng.integers(0, 1000, 1000)].mean() / 10 for _ in range(2000)])
         lo, hi = np.quantile(boots, [0.005, 0.995])
         assert abs(rate - a) <= (hi - lo) / 2 * math.sqrt(11), (a, rate)
+
+
+# ----------------------------------------------------------------------------- estimate-only scan (Exp-7)
+
+def _flat_index(Y, R=None, mu=None):
+    """An index dict with one list holding every row (nprobe = 1 scans everything)."""
+    n, D = Y.shape
+    return dict(Y=np.asarray(Y, np.float64), R=np.eye(D) if R is None else R,
+                mu=np.zeros(D) if mu is None else mu, centroids=np.zeros((1, D)),
+                list_off=np.array([0, n]), list_ids=np.arange(n))
+
+
+def test_estimate_scan_worked_example():
+    """By hand, D = 2, d = 1, R = I, q' = (1, 2):
+    x0 = (0, 0): partial 2 * 1^2 = 2; residual 1 + 0 + 4 = 5; exact 5
+    x1 = (3, 1): partial 2 * 2^2 = 8; residual 4 + 1 + 4 = 9; exact 5
+    x2 = (1,-1): partial 0;           residual 0 + 1 + 4 = 5; exact 9
+    so partial ranks x2, x0, x1; residual ranks x0, x2 (tie 5, lower id first), x1."""
+    ix = _flat_index(np.array([[0.0, 0.0], [3.0, 1.0], [1.0, -1.0]]))
+    q = np.array([[1.0, 2.0]])
+    p = O.estimate_scan(ix, q, 3, 1, 1, "partial")
+    assert p["ids"][0].tolist() == [2, 0, 1] and p["est"][0].tolist() == [0.0, 2.0, 8.0]
+    r = O.estimate_scan(ix, q, 3, 1, 1, "residual")
+    assert r["ids"][0].tolist() == [0, 2, 1] and r["est"][0].tolist() == [5.0, 5.0, 9.0]
+    assert r["margin"][0] == math.inf                  # k = n: no (k+1)-th candidate
+    full = O.estimate_scan(ix, q, 2, 1, 2, "residual")  # d = D: exact distances
+    assert full["ids"][0].tolist() == [0, 1] and full["est"][0].tolist() == [5.0, 5.0]
+    pad = O.estimate_scan(ix, q, 5, 1, 1, "partial")
+    assert pad["ids"][0, 3:].tolist() == [-1, -1] and np.all(np.isinf(pad["est"][0, 3:]))
+
+
+def test_estimate_scan_full_dims_is_brute_force(small_index, small_workload):
+    """d >= D: both estimates are the exact distance, so all lists give the exact KNN."""
+    Q = small_workload["queries"][:20]
+    Qr = O.rotate(Q, small_index["mu"], small_index["R"])
+    gi, gd = O.bruteforce_knn(small_index["Y"], Qr, 10)
+    for est in ("partial", "residual"):
+        r = O.estimate_scan(small_index, Q, 10, 64, 128, est)
+        assert r["ids"].tolist() == gi.tolist()
+        np.testing.assert_allclose(r["est"], gd, rtol=1e-12)
+
+
+def test_estimates_match_the_projector_form_in_original_coordinates(small_index, small_workload):
+    """Written with the projector P_d = R_d^T R_d onto the leading d axes, in the original
+    coordinates:  partial = (D/d) ||P_d (q - x)||^2  and  residual = ||q - x||^2 +
+    2 (q - mu)^T (I - P_d) (x - mu)  (the dropped cross term of the residual dims, sign
+    included)."""
+    X = small_workload["base"][:300].astype(np.float64)
+    q = small_workload["queries"][3].astype(np.float64)
+    mu, R, Y = small_index["mu"], small_index["R"], small_index["Y"]
+    qr = O.rotate(q[None, :], mu, R)[0]
+    for d in (32, 64, 96):
+        Pd = R[:d].T @ R[:d]
+        diff = q[None, :] - X
+        part = (128 / d) * np.einsum("ij,jk,ik->i", diff, Pd, diff)
+        res = np.sum(diff ** 2, axis=1) + 2 * ((q - mu) @ (np.eye(128) - Pd) @ (X - mu).T)
+        # the oracle works on the stored (rotated, FP32-rounded) rows of the same points
+        ids = np.arange(300)
+        np.testing.assert_allclose(O.estimate_values(Y, qr, ids, d, "partial"), part, rtol=1e-5)
+        np.testing.assert_allclose(O.estimate_values(Y, qr, ids, d, "residual"), res, rtol=1e-5)
+
+
+def test_partial_estimate_unbiased_over_random_rotations():
+    """Averaged over Haar rotations, the partial estimate of a fixed pair is its distance
+    (the (D/d) scale of the random-projection column); a wrong scale is off by >= 25%."""
+    rng = np.random.default_rng(4)
+    X = rng.standard_normal((4, 16))
+    q = rng.standard_normal((1, 16))
+    exact = np.sum((X - q) ** 2, axis=1)
+    acc = np.zeros(4)
+    reps = 600
+    for s in range(reps):
+        R = O.haar_rotation(16, 100 + s)
+        r = O.estimate_scan(_flat_index(X @ R.T, R=R), q, 4, 1, 4, "partial")
+        acc[r["ids"][0]] += r["est"][0]
+    np.testing.assert_allclose(acc / reps, exact, rtol=0.12)
