@@ -45,6 +45,7 @@ import numpy as np
 # --------------------------------------------------------------------------------------
 _M64 = (1 << 64) - 1
 TAG_PCA, TAG_KMEANS_INIT, TAG_KMEANS_SAMPLE, TAG_NEG, TAG_CALIB, TAG_HAAR = 1, 2, 3, 4, 5, 6
+TAG_PQ_SAMPLE = 7
 
 
 def splitmix64(x):
@@ -381,6 +382,98 @@ def probe_order(qrot: np.ndarray, C: np.ndarray, nprobe: int):
 
 
 # --------------------------------------------------------------------------------------
+# Quantization estimate (BSA-O)  [Sec. V-B "Approximate Distances": the asymmetric distance
+# from the query to the point's OPQ codewords is dis', the point's distance to its own
+# reconstruction is one more classifier feature; Sec. VI-B (M subspaces of 2^nbits
+# codewords, O(D 2^nbits) lookup-table build); Sec. VII-A (M = D/4, D/8 for GIST; nbits = 8;
+# OPQ trained on 65,536 sampled points)]
+# --------------------------------------------------------------------------------------
+
+def opq_allocation(lam: np.ndarray, M: int) -> np.ndarray:
+    """OPQ's parametric solution (eigenvalue allocation, Ge et al.): the PCA axes, largest
+    eigenvalue first, are dealt to M subspaces of D/M axes each, every axis to the subspace
+    whose product of eigenvalues so far is smallest among those not full (lowest index on
+    ties), which balances the subspaces' variance products.  The OPQ rotation is then the PCA
+    rotation with its rows permuted.  Reading: the eigenvalues are first divided by their
+    geometric mean (eigenvalues below 1e-12 of the largest count as 1e-12 of it), so an empty
+    subspace's product 1 sits in the middle of the spectrum and the rule does not depend on
+    the data's scale (with raw eigenvalues all below 1 it would fill one subspace at a time).
+    Returns perm (M, D/M): the axes of subspace j, ascending."""
+    lam = np.asarray(lam, dtype=np.float64)
+    D = lam.shape[0]
+    if M < 1 or D % M:
+        raise ValueError("M must divide D")
+    dsub = D // M
+    ll = np.log(np.maximum(lam, lam.max() * 1e-12 if lam.max() > 0 else 1e-300))
+    ll = ll - ll.mean()
+    logp = np.zeros(M)
+    members = [[] for _ in range(M)]
+    for i in np.argsort(-lam, kind="stable"):
+        best = -1
+        for j in range(M):
+            if len(members[j]) < dsub and (best < 0 or logp[j] < logp[best]):
+                best = j
+        members[best].append(int(i))
+        logp[best] += ll[i]
+    return np.array([sorted(m) for m in members], dtype=np.int64)
+
+
+def pq_train(Y: np.ndarray, perm: np.ndarray, ksub: int = 256, iters: int = 25, seed: int = 0,
+             train: int = 65536) -> np.ndarray:
+    """Codebooks: ``kmeans`` with ksub centroids in every subspace over the same <= ``train``
+    stored rows (the smallest SplitMix64 keys); centroids rounded to FP32, as stored.
+    Returns books (M, ksub, dsub), FP64 holding FP32 values."""
+    n = Y.shape[0]
+    rows = select_by_key(n, min(n, train), seed, TAG_PQ_SAMPLE)
+    T = np.asarray(Y, dtype=np.float64)[rows]
+    if T.shape[0] < ksub:
+        raise ValueError("fewer training rows than codewords")
+    books = []
+    for j in range(perm.shape[0]):
+        C, _ = kmeans(T[:, perm[j]], ksub, iters, seed, train_per_list=max(1, -(-T.shape[0] // ksub)))
+        books.append(C.astype(np.float32).astype(np.float64))
+    return np.stack(books)
+
+
+def pq_encode(Y: np.ndarray, perm: np.ndarray, books: np.ndarray) -> np.ndarray:
+    """codes[x, j] = argmin_c ||y_j - C_j[c]||^2 (lowest c on ties).  The argmin decides an
+    integer, so it is taken in FP32 as the GPU takes it: differences rounded to FP32,
+    squared and rounded, added in subspace-axis order, each operation rounded separately."""
+    Y32 = np.asarray(Y, dtype=np.float32)
+    M, ksub, dsub = books.shape
+    B32 = books.astype(np.float32)
+    codes = np.empty((Y32.shape[0], M), dtype=np.uint8)
+    for j in range(M):
+        acc = np.zeros((Y32.shape[0], ksub), dtype=np.float32)
+        for t in range(dsub):
+            dlt = Y32[:, perm[j, t]][:, None] - B32[j, :, t][None, :]
+            acc = acc + dlt * dlt
+        codes[:, j] = np.argmin(acc, axis=1)
+    return codes
+
+
+def pq_error(Y: np.ndarray, perm: np.ndarray, books: np.ndarray, codes: np.ndarray) -> np.ndarray:
+    """||u - c(u)||^2: squared distance of every stored row to its own codewords (FP64)."""
+    Y = np.asarray(Y, dtype=np.float64)
+    out = np.zeros(Y.shape[0])
+    for j in range(perm.shape[0]):
+        out += np.sum((Y[:, perm[j]] - books[j][codes[:, j]]) ** 2, axis=1)
+    return out
+
+
+def pq_lut(qrot: np.ndarray, perm: np.ndarray, books: np.ndarray) -> np.ndarray:
+    """lut[j, c] = ||q'_j - C_j[c]||^2 for one rotated query (FP64)."""
+    q = np.asarray(qrot, dtype=np.float64)
+    return np.stack([np.sum((q[perm[j]][None, :] - books[j]) ** 2, axis=1)
+                     for j in range(perm.shape[0])])
+
+
+def pq_adc(lut: np.ndarray, codes: np.ndarray) -> np.ndarray:
+    """Asymmetric distance dis' = sum_j lut[j, codes[x, j]] for the given code rows."""
+    return lut[np.arange(lut.shape[0])[None, :], codes.astype(np.int64)].sum(axis=1)
+
+
+# --------------------------------------------------------------------------------------
 # Stages  [Sec. IV-D Alg. 2: dimensions are added Delta_d at a time; Sec. V-B
 # "Incremental Correction": one classifier per stage until d = D]
 # --------------------------------------------------------------------------------------
@@ -423,7 +516,7 @@ def _rel(a, b, c):
 
 
 def search_one(qrot, Y, list_off, list_ids, probes, k, m, beta, bounds, B=256, L=0,
-               prune=True, collect_neg=None, pre=None, res=None):
+               prune=True, collect_neg=None, pre=None, res=None, pq=None):
     """Canonical block-synchronous pruned refinement for one rotated query.
 
     The paper's refinement updates tau after every candidate [Sec. I: result queue Q with
@@ -449,12 +542,17 @@ def search_one(qrot, Y, list_off, list_ids, probes, k, m, beta, bounds, B=256, L
     (incremental): dis'_s = e_s + ||x_r||^2 + ||q'_r||^2 (equal to C1 - C2 of Alg. 1, the
     exact distance without the cross term of the residual dims), pruned iff
     dis'_s - m sigma_s > tau_b, with qr = ||q'_r||^2 and msig = m sigma_s per test stage.
+    ``pq`` = (lut, codes, err, m1, m3, beta) adds the quantization test of BSA-O before the
+    stages: every tested candidate with m1 dis' + m3 err + beta > tau_b is pruned (dis' =
+    ``pq_adc``, err = its ``pq_error``), entry 0 of stop_counts counting them; survivors are
+    refined over all dims (with m = 1, beta = -inf no stage test fires: the paper's BSA-O is
+    one classifier, not incremental).
     """
     S = bounds.shape[0]
     T_d = np.zeros(0)
     T_i = np.zeros(0, dtype=np.int64)
     tau_hist = []
-    P = 1 if pre is not None else 0
+    P = 1 if (pre is not None or pq is not None) else 0
     stop_counts = np.zeros(S + P, dtype=np.int64)
     margin = math.inf
     b = 0
@@ -476,7 +574,16 @@ def search_one(qrot, Y, list_off, list_ids, probes, k, m, beta, bounds, B=256, L
                 rel0 = np.abs(lhs0 - tau_b) / _rel(m0 * e0, np.full_like(e0, beta0), tau_b)
                 if rel0.size:
                     margin = min(margin, float(rel0.min()))
-            if prune and math.isfinite(tau_b) and S > 1:
+            if prune and pq is not None and math.isfinite(tau_b):
+                lut, codes, err, m1, m3, beta0 = pq
+                adc = pq_adc(lut, codes[ids])
+                lhs0 = m1 * adc + m3 * err[ids] + beta0
+                pre_hit = lhs0 > tau_b
+                rel0 = np.abs(lhs0 - tau_b) / (np.abs(m1 * adc) + np.abs(m3 * err[ids]) + abs(beta0)
+                                               + abs(tau_b) + 1e-300)
+                if rel0.size:
+                    margin = min(margin, float(rel0.min()))
+            if prune and math.isfinite(tau_b) and S > 1 and (res is not None or np.isfinite(beta).any()):
                 if res is None:
                     lhs = e[:, :S - 1] * m[None, :] + beta[None, :]   # (nb, S-1)
                     scale = _rel(e[:, :S - 1] * m[None, :], beta[None, :], tau_b)
@@ -526,12 +633,14 @@ def search_one(qrot, Y, list_off, list_ids, probes, k, m, beta, bounds, B=256, L
     return ids_out, d_out, stop_counts, margin
 
 
-def search_sequential(qrot, Y, list_off, list_ids, probes, k, m, beta, bounds, pre=None, res=None):
+def search_sequential(qrot, Y, list_off, list_ids, probes, k, m, beta, bounds, pre=None, res=None,
+                      pq=None):
     """The paper's per-candidate refinement, coded separately: a binary max-heap Q of the
     K best (dis, id); tau = its root once it holds K entries; each candidate walks the
     stages and is pruned at the first stage with m_s e_s + beta_s > tau, otherwise enters
     Q when (dis, id) is smaller than the root [Sec. I refinement; Alg. 2 stage loop;
-    Sec. V-A classifier].  Equals ``search_one`` with B = 1, L = 0 (``pre`` as there)."""
+    Sec. V-A classifier].  Equals ``search_one`` with B = 1, L = 0 (``pre``, ``pq`` as
+    there; the quantization estimate is summed codeword by codeword here)."""
     heap = []   # entries (-dis, -id): the root is the largest (dis, id)
     q = np.asarray(qrot, dtype=np.float64)
     S = bounds.shape[0]
@@ -546,6 +655,13 @@ def search_sequential(qrot, Y, list_off, list_ids, probes, k, m, beta, bounds, p
                     t = q[i] - dec[x, i]
                     e0 += t * t
                 if m0 * e0 + beta0 > tau:
+                    continue
+            if pq is not None and tau != math.inf:
+                lut, codes, err, m1, m3, beta0 = pq
+                adc = 0.0
+                for j in range(lut.shape[0]):
+                    adc += lut[j, int(codes[x, j])]
+                if m1 * adc + m3 * err[x] + beta0 > tau:
                     continue
             acc = 0.0
             lo = 0
@@ -629,6 +745,18 @@ def classifier_to_correction(b: float, w1: float, w2: float):
     return 1.0, 0.0
 
 
+def classifier3_to_correction(b: float, w1: float, w3: float, w2: float):
+    """The BSA-O classifier sign(w1 dis' + w3 err + w2 tau + b) > 0 as the test
+    m1 dis' + m3 err + beta > tau: m1 = -w1/w2, m3 = -w3/w2, beta = -b/w2 when w2 < 0
+    [Sec. V-A linear model with the extra feature of Sec. V-B].  Same fallback as
+    ``classifier_to_correction``: m1 = 1, m3 = 0 without a usable orientation."""
+    if w2 < 0:
+        m1 = -w1 / w2
+        if m1 > 0:
+            return m1, -w3 / w2, -b / w2
+    return 1.0, 0.0, 0.0
+
+
 # --------------------------------------------------------------------------------------
 # Target-recall adjustment  [Sec. V-A "Adaptive Adjustment": move beta to beta' so that the
 # recall of label 0 reaches r].  Reading: alpha = 1 - r is the probability that a true
@@ -685,7 +813,7 @@ def calibrate(Y, list_off, list_ids, centroids, mu, R, calib, bounds, calib_k=10
     St = S - 1
     Qr = rotate(calib, mu, R)
     knn_ids, knn_d = bruteforce_knn(Y, Qr, calib_k)
-    pos_e, pos_tau, neg_e, neg_tau = [], [], [], []
+    pos_e, pos_tau, neg_e, neg_tau, neg_q, neg_id = [], [], [], [], [], []
     zeros_m = np.zeros(St)
     for qi in range(Qr.shape[0]):
         tau_q = knn_d[qi, calib_k - 1]
@@ -712,6 +840,8 @@ def calibrate(Y, list_off, list_ids, centroids, mu, R, calib, bounds, calib_k=10
                     en = np.concatenate([e0, en])
                 neg_e.append(en)
                 neg_tau.append(pool[t][1])
+                neg_q.append(qi)
+                neg_id.append(pool[t][0])
     pos_e = np.vstack(pos_e)
     pos_tau = np.concatenate(pos_tau)
     neg_e = np.vstack(neg_e) if neg_e else np.zeros((0, St + P))
@@ -729,7 +859,38 @@ def calibrate(Y, list_off, list_ids, centroids, mu, R, calib, bounds, calib_k=10
         lr.append((b, w[0], w[1]))
     G = pos_tau[:, None] - pos_e * m[None, :]
     return dict(m=m, G=G, pos_e=pos_e, pos_tau=pos_tau, neg_e=neg_e, neg_tau=neg_tau, lr=lr,
-                knn_ids=knn_ids, knn_d=knn_d)
+                knn_ids=knn_ids, knn_d=knn_d, neg_q=np.asarray(neg_q, dtype=np.int64),
+                neg_id=np.asarray(neg_id, dtype=np.int64), qrot=Qr)
+
+
+def calibrate_pq(cal: dict, pq: dict) -> dict:
+    """The BSA-O classifier on the calibration pairs ``calibrate`` collected (label 0 = the
+    K_c nearest stored vectors with tau = the K_c-th distance, label 1 = the sampled pairs of
+    the unpruned query process with their tau_b): features (dis' = ADC, err = the point's
+    quantization error, tau) [Sec. V-B], logistic regression by ``irls_logistic``, then the
+    residuals g(j) = tau_j - m1 dis'_j - m3 err_j of label 0 for the target-recall shift
+    (``beta_for_alpha`` on the one test).  Returns dict(m1, m3, G (n0, 1), lr)."""
+    Qr, perm, books, codes, err = cal["qrot"], pq["perm"], pq["books"], pq["codes"], pq["err"]
+    luts = [pq_lut(q, perm, books) for q in Qr]
+    kc = cal["knn_ids"].shape[1]
+    pos_adc = np.concatenate([pq_adc(luts[qi], codes[cal["knn_ids"][qi]]) for qi in range(Qr.shape[0])])
+    pos_err = err[cal["knn_ids"].reshape(-1)]
+    pos_tau = cal["pos_tau"]
+    assert pos_adc.shape[0] == pos_tau.shape[0] == Qr.shape[0] * kc
+    neg_adc = np.array([pq_adc(luts[q], codes[[x]])[0] for q, x in zip(cal["neg_q"], cal["neg_id"])])
+    neg_err = err[cal["neg_id"]] if cal["neg_id"].size else np.zeros(0)
+    if neg_adc.size == 0:
+        m1, m3, lr = 1.0, 0.0, (0.0, np.zeros(3))
+    else:
+        F = np.vstack([np.column_stack([pos_adc, pos_err, pos_tau]),
+                       np.column_stack([neg_adc, neg_err, cal["neg_tau"]])])
+        lab = np.concatenate([np.zeros(pos_adc.shape[0]), np.ones(neg_adc.shape[0])])
+        b, w = irls_logistic(F, lab)
+        m1, m3, _ = classifier3_to_correction(b, w[0], w[1], w[2])
+        lr = (b, w)
+    G = (pos_tau - m1 * pos_adc - m3 * pos_err)[:, None]
+    return dict(m1=m1, m3=m3, G=G, lr=lr, pos_adc=pos_adc, pos_err=pos_err, neg_adc=neg_adc,
+                neg_err=neg_err)
 
 
 # --------------------------------------------------------------------------------------
@@ -749,11 +910,14 @@ def ads_table(bounds: np.ndarray, D: int, eps0: float = 2.1):
 
 def fit(base, calib, nlist, delta_d=32, storage="f32", kmeans_iters=25, calib_k=10,
         calib_nprobe=None, B=256, L=0, seed=0, pca_sample=1_000_000, max_neg=50, fp8_lead=0,
-        calib_k_extra=(), projection="pca"):
+        calib_k_extra=(), projection="pca", pq_m=0, pq_iters=25, pq_train_rows=65536):
     """Projection + IVF lists + calibrated correction table for ``base``; ``fp8_lead`` = 64
     adds the FP8 pre-stage over the leading 64 rotated dims.  ``calib_k_extra`` adds one
     table per further K_c (see ``table_for_k``).  ``projection`` = "haar" replaces the PCA
-    rotation by ``haar_rotation(D, seed)`` (centring and everything after it unchanged)."""
+    rotation by ``haar_rotation(D, seed)`` (centring and everything after it unchanged).
+    ``pq_m`` > 0 adds the BSA-O quantization estimate: OPQ (``opq_allocation`` of the PCA
+    axes into pq_m subspaces, 256 codewords each, ``pq_train`` on pq_train_rows rows) and one
+    BSA-O classifier per table (``calibrate_pq``)."""
     base = np.asarray(base)
     D = base.shape[1]
     pca = pca_fit(base, pca_sample, seed)
@@ -770,16 +934,39 @@ def fit(base, calib, nlist, delta_d=32, storage="f32", kmeans_iters=25, calib_k=
     if calib_nprobe is None:
         calib_nprobe = int(min(max(1, nlist // 8), 64))
     pre = fp8_encode_lead(Y, off, ids, fp8_lead) if fp8_lead else None
+    pq = None
+    if pq_m:
+        if projection != "pca":
+            raise ValueError("the OPQ allocation needs the PCA rotation")
+        perm = opq_allocation(pca["lam"], pq_m)
+        books = pq_train(Y, perm, 256, pq_iters, seed, pq_train_rows)
+        codes = pq_encode(Y, perm, books)
+        pq = dict(m=pq_m, perm=perm, books=books, codes=codes, err=pq_error(Y, perm, books, codes))
     tables = []
     for kc in [calib_k, *calib_k_extra]:
         cal = calibrate(Y, off, ids, C, pca["mu"], pca["R"], calib, bounds, kc, calib_nprobe,
                         B, L, seed, max_neg, pre_dec=pre["dec"] if pre else None)
-        tables.append(dict(kc=kc, m=cal["m"], G=cal["G"], calib=cal))
+        tables.append(dict(kc=kc, m=cal["m"], G=cal["G"], calib=cal,
+                           pq=calibrate_pq(cal, pq) if pq else None))
     cal = tables[0]["calib"]
     return dict(mu=pca["mu"], R=pca["R"], lam=pca["lam"], cov=pca["cov"], Y=Y, centroids=C,
                 assign=assign, list_off=off, list_ids=ids, bounds=bounds, m=cal["m"], G=cal["G"],
                 calib=cal, storage=storage, delta_d=delta_d, B=B, L=L, pre=pre,
-                tables=tables if len(tables) > 1 else None)
+                tables=tables if len(tables) > 1 else None, pq=pq, pq_tab=tables[0]["pq"])
+
+
+def pq_table_for_k(index, k):
+    """The BSA-O classifier (m1, m3, G) a search with K uses (same K_c rule as ``table_for_k``)."""
+    tabs = index.get("tables")
+    if not tabs:
+        t = index["pq_tab"]
+    else:
+        best = tabs[0]
+        for c in tabs:
+            if c["kc"] <= k and c["kc"] >= best["kc"]:
+                best = c
+        t = best["pq"]
+    return t["m1"], t["m3"], t["G"]
 
 
 def table_for_k(index, k):
@@ -798,10 +985,11 @@ def table_for_k(index, k):
 
 
 def search(index, queries, k, nprobe, alpha, mode="learned", B=None, L=None, calib_mode="joint"):
-    """Search every query; mode in {'learned', 'lossless', 'none', 'ads', 'bsar'} ('ads': the
-    ADSampling test of ``ads_table`` with index["ads_eps0"], default 2.1; 'bsar': the
-    residual-estimate test with multiplier index["bsar_m"], default 8, or Phi^-1(1 - alpha)
-    when that is <= 0).
+    """Search every query; mode in {'learned', 'lossless', 'none', 'ads', 'bsar', 'bsao'}
+    ('ads': the ADSampling test of ``ads_table`` with index["ads_eps0"], default 2.1; 'bsar':
+    the residual-estimate test with multiplier index["bsar_m"], default 8, or Phi^-1(1 - alpha)
+    when that is <= 0; 'bsao': the OPQ estimate with its learned classifier, index fitted
+    with pq_m > 0).
     Returns ids (nq, k), dists (nq, k), stop_counts (nq, S), margin (nq,)."""
     B = index["B"] if B is None else B
     L = index["L"] if L is None else L
@@ -827,13 +1015,19 @@ def search(index, queries, k, nprobe, alpha, mode="learned", B=None, L=None, cal
         mult = bsar_multiplier(alpha, index.get("bsar_m", 8.0))
     elif mode == "none":
         m, beta, prune = np.ones(St), np.zeros(St), False
+    elif mode == "bsao":
+        # one quantization test, then survivors refined over all dims (no stage test)
+        m1, m3, Gq = pq_table_for_k(index, k)
+        beta_q = float(beta_for_alpha(Gq, alpha, calib_mode)[0])
+        m, beta, prune = np.ones(St), np.full(St, -np.inf), alpha > 0
     else:
         raise ValueError(mode)
     Qr = rotate(queries, index["mu"], index["R"])
     nq = Qr.shape[0]
     ids = np.full((nq, k), -1, dtype=np.int64)
     ds = np.full((nq, k), np.inf)
-    stops = np.zeros((nq, bounds.shape[0] + (1 if pre is not None and prune else 0)), dtype=np.int64)
+    stops = np.zeros((nq, bounds.shape[0] + (1 if (pre is not None or mode == "bsao") and prune else 0)),
+                     dtype=np.int64)
     margins = np.full(nq, math.inf)
     probes_all = np.zeros((nq, nprobe), dtype=np.int64)
     for qi in range(nq):
@@ -843,8 +1037,14 @@ def search(index, queries, k, nprobe, alpha, mode="learned", B=None, L=None, cal
         if mode == "bsar":
             qr, sig = bsar_terms(Qr[qi], index["lam"], bounds)
             res = (qr, mult * sig)
+        pqa = None
+        if mode == "bsao" and prune:
+            pqix = index["pq"]
+            pqa = (pq_lut(Qr[qi], pqix["perm"], pqix["books"]), pqix["codes"], pqix["err"], m1, m3,
+                   beta_q)
         i, d, st, mg = search_one(Qr[qi], index["Y"], index["list_off"], index["list_ids"], probes,
-                                  k, m, beta, bounds, B, L, prune, pre=pre if prune else None, res=res)
+                                  k, m, beta, bounds, B, L, prune, pre=pre if prune else None, res=res,
+                                  pq=pqa)
         ids[qi], ds[qi], stops[qi], margins[qi] = i, d, st, min(mg, pm)
     return dict(ids=ids, dists=ds, stops=stops, margin=margins, probes=probes_all, qrot=Qr, m=m,
                 beta=beta)
@@ -925,11 +1125,22 @@ def recall_at(ids: np.ndarray, gt: np.ndarray, k: int = 10) -> float:
     return hits / (k * ids.shape[0])
 
 
-def false_prune_rate(index, queries, k, alpha, calib_mode="joint"):
+def false_prune_rate(index, queries, k, alpha, calib_mode="joint", mode="learned"):
     """Held-out check of the calibration: the fraction of (query, true K-NN) pairs that the
-    stage tests would prune at the query's final tau (its K-th true distance), i.e. the
-    label-0 miss rate the target recall r = 1 - alpha bounds [Sec. V-A].  Also returns the
-    per-query miss counts for a query-level bootstrap."""
+    stage tests (mode 'bsao': the quantization test) would prune at the query's final tau
+    (its K-th true distance), i.e. the label-0 miss rate the target recall r = 1 - alpha
+    bounds [Sec. V-A].  Also returns the per-query miss counts for a query-level bootstrap."""
+    if mode == "bsao":
+        m1, m3, Gq = pq_table_for_k(index, k)
+        bq = float(beta_for_alpha(Gq, alpha, calib_mode)[0])
+        pq = index["pq"]
+        Qr = rotate(queries, index["mu"], index["R"])
+        knn_ids, knn_d = bruteforce_knn(index["Y"], Qr, k)
+        per_q = np.zeros(Qr.shape[0])
+        for qi in range(Qr.shape[0]):
+            adc = pq_adc(pq_lut(Qr[qi], pq["perm"], pq["books"]), pq["codes"][knn_ids[qi]])
+            per_q[qi] = np.count_nonzero(m1 * adc + m3 * pq["err"][knn_ids[qi]] + bq > knn_d[qi, k - 1])
+        return float(per_q.sum() / (k * Qr.shape[0])), per_q
     bounds = index["bounds"]
     St = bounds.shape[0] - 1
     m, G = table_for_k(index, k)

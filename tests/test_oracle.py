@@ -774,3 +774,139 @@ def test_partial_estimate_unbiased_over_random_rotations():
         r = O.estimate_scan(_flat_index(X @ R.T, R=R), q, 4, 1, 4, "partial")
         acc[r["ids"][0]] += r["est"][0]
     np.testing.assert_allclose(acc / reps, exact, rtol=0.12)
+
+
+# ----------------------------------------------------------------------------- quantization estimate (BSA-O)
+
+@pytest.fixture(scope="module")
+def pq_index(small_workload):
+    w = small_workload
+    return O.fit(w["base"], w["calib"], nlist=64, kmeans_iters=10, calib_k=10, calib_nprobe=8, seed=7,
+                 pq_m=32, pq_iters=8)
+
+
+def test_opq_allocation_worked_examples():
+    """By hand, eigenvalues over their geometric mean g: [8, 4, 2, 1] (g = 2 sqrt 2) into 2
+    subspaces: 8 -> s0 (ties: lowest), 4 -> s1 (empty product 1 < 8/g), 2 -> s1 (4/g < 8/g),
+    1 -> s0 (s1 full); products 8 and 8.  [16, 8, 4, 2, 1, 1] (g = 1024^(1/6)) into 3:
+    16 -> s0, 8 -> s1, 4 -> s2 (empty subspaces first: 1 < 8/g), 2 -> s2 (4/g smallest),
+    1 -> s1 (8/g < 16/g), 1 -> s0; products 16, 8, 8.  Scaling the eigenvalues changes
+    nothing."""
+    assert O.opq_allocation(np.array([8.0, 4, 2, 1]), 2).tolist() == [[0, 3], [1, 2]]
+    assert O.opq_allocation(np.array([16.0, 8, 4, 2, 1, 1]), 3).tolist() == [[0, 5], [1, 4], [2, 3]]
+    # unsorted input: axes are dealt by eigenvalue, not by index
+    assert O.opq_allocation(np.array([1.0, 8, 2, 4]), 2).tolist() == [[0, 1], [2, 3]]
+    for c in (1e-6, 1e6):
+        assert O.opq_allocation(c * np.array([16.0, 8, 4, 2, 1, 1]), 3).tolist() == \
+            [[0, 5], [1, 4], [2, 3]]
+
+
+def test_opq_allocation_is_a_balanced_partition():
+    lam = 1.0 / np.arange(1, 129)
+    perm = O.opq_allocation(lam, 32)
+    assert sorted(perm.reshape(-1).tolist()) == list(range(128)) and perm.shape == (32, 4)
+    logp = np.log(lam)[perm].sum(axis=1)
+    contiguous = np.log(lam).reshape(32, 4).sum(axis=1)
+    assert np.ptp(logp) < 0.2 * np.ptp(contiguous)
+
+
+def test_pq_encode_is_the_nearest_codeword(pq_index):
+    """FP32 argmin == FP64 brute-force nearest codeword, except at FP64 near ties."""
+    pq = pq_index["pq"]
+    Y = pq_index["Y"][:2000]
+    codes = pq["codes"][:2000]
+    for j in range(0, 32, 5):
+        d = ((Y[:, pq["perm"][j]][:, None, :] - pq["books"][j][None, :, :]) ** 2).sum(-1)   # FP64
+        best = d.argmin(axis=1)
+        got = codes[:, j].astype(np.int64)
+        diff = got != best
+        if diff.any():
+            r = np.nonzero(diff)[0]
+            gap = np.abs(d[r, got[r]] - d[r, best[r]]) / np.maximum(d[r, best[r]], 1e-300)
+            assert np.all(gap < 1e-5), gap.max()
+        assert diff.mean() < 1e-3
+
+
+def test_pq_error_and_adc_equal_distances_to_the_reconstruction(pq_index, small_workload):
+    """err(x) = ||y - recon(y)||^2 and dis' = ||q' - recon(y)||^2, with recon(y) assembled by
+    writing every codeword back to its subspace's axes."""
+    pq = pq_index["pq"]
+    ids = np.arange(0, 10000, 37)
+    rec = np.zeros((ids.size, 128))
+    for j in range(32):
+        rec[:, pq["perm"][j]] = pq["books"][j][pq["codes"][ids, j]]
+    Y = pq_index["Y"][ids]
+    np.testing.assert_allclose(pq["err"][ids], ((Y - rec) ** 2).sum(1), rtol=1e-12)
+    q = O.rotate(small_workload["queries"][:1], pq_index["mu"], pq_index["R"])[0]
+    adc = O.pq_adc(O.pq_lut(q, pq["perm"], pq["books"]), pq["codes"][ids])
+    np.testing.assert_allclose(adc, ((q[None, :] - rec) ** 2).sum(1), rtol=1e-12)
+
+
+def test_classifier3_to_correction_is_the_same_decision():
+    rng = np.random.default_rng(2)
+    for _ in range(50):
+        b, w1, w3 = rng.normal(size=3)
+        w2 = -abs(rng.normal())
+        w1 = abs(w1)
+        m1, m3, beta = O.classifier3_to_correction(b, w1, w3, w2)
+        F = rng.normal(size=(200, 3)) * 3
+        lhs = (w1 * F[:, 0] + w3 * F[:, 1] + w2 * F[:, 2] + b) > 0
+        rhs = m1 * F[:, 0] + m3 * F[:, 1] + beta > F[:, 2]
+        close = np.abs(w1 * F[:, 0] + w3 * F[:, 1] + w2 * F[:, 2] + b) < 1e-9
+        assert np.array_equal(lhs[~close], rhs[~close])
+    assert O.classifier3_to_correction(0.3, 1.0, 0.5, 0.2) == (1.0, 0.0, 0.0)
+
+
+def test_pq_classifier_is_the_logistic_optimum(pq_index):
+    """The BSA-O weights are a stationary point of the penalised cross-entropy (3 features)."""
+    t = pq_index["pq_tab"]
+    cal = pq_index["calib"]
+    F = np.vstack([np.column_stack([t["pos_adc"], t["pos_err"], cal["pos_tau"]]),
+                   np.column_stack([t["neg_adc"], t["neg_err"], cal["neg_tau"]])])
+    y = np.concatenate([np.zeros(t["pos_adc"].size), np.ones(t["neg_adc"].size)])
+    b, w = t["lr"]
+    mean, std = F.mean(0), F.std(0)
+    Z = (F - mean) / std
+    ws = w * std
+    b0 = b + float(np.dot(w, mean))
+    p = 1.0 / (1.0 + np.exp(-(Z @ ws + b0)))
+    g = np.concatenate([[np.mean(p - y)], Z.T @ (p - y) / y.size + 1e-8 * ws])
+    assert np.abs(g).max() < 1e-9
+    m1, m3, _ = O.classifier3_to_correction(b, w[0], w[1], w[2])
+    assert (t["m1"], t["m3"]) == (m1, m3) and t["m1"] > 0
+
+
+def test_bsao_zero_significance_is_the_unpruned_search(pq_index, small_workload):
+    Q = small_workload["queries"][:30]
+    a = O.search(pq_index, Q, 10, 8, 0.0, mode="bsao")
+    n = O.search(pq_index, Q, 10, 8, 0.0, mode="none")
+    assert a["ids"].tolist() == n["ids"].tolist()
+
+
+def test_bsao_block_of_one_equals_sequential(pq_index, small_workload):
+    Q = small_workload["queries"][:12]
+    r = O.search(pq_index, Q, 10, 8, 0.2, mode="bsao", B=1)
+    m1, m3, Gq = O.pq_table_for_k(pq_index, 10)
+    bq = float(O.beta_for_alpha(Gq, 0.2)[0])
+    pq = pq_index["pq"]
+    St = pq_index["bounds"].shape[0] - 1
+    pruned = r["stops"][:, 0].sum()
+    assert pruned > 0
+    for qi in range(Q.shape[0]):
+        qr = r["qrot"][qi]
+        arg = (O.pq_lut(qr, pq["perm"], pq["books"]), pq["codes"], pq["err"], m1, m3, bq)
+        ids, ds = O.search_sequential(qr, pq_index["Y"], pq_index["list_off"], pq_index["list_ids"],
+                                      r["probes"][qi], 10, np.ones(St), np.full(St, -np.inf),
+                                      pq_index["bounds"], pq=arg)
+        assert ids.tolist() == r["ids"][qi].tolist()
+        np.testing.assert_allclose(ds, r["dists"][qi], rtol=1e-12)
+
+
+def test_bsao_heldout_false_prune_rate_matches_significance(pq_index, small_workload):
+    rng = np.random.default_rng(11)
+    for a in (0.05, 0.2):
+        rate, per_q = O.false_prune_rate(pq_index, small_workload["val"], 10, a, mode="bsao")
+        boots = np.array([per_q[rng.integers(0, per_q.shape[0], per_q.shape[0])].mean() / 10
+                          for _ in range(2000)])
+        lo, hi = np.quantile(boots, [0.005, 0.995])
+        assert abs(rate - a) <= (hi - lo) / 2 * math.sqrt(2), (a, rate)
