@@ -71,7 +71,14 @@ typedef enum { DDC_ROT_F32 = 0, DDC_ROT_BF16 = 1 } ddc_rot;
  *            m from ddc_set_bsar_multiplier (8 by default), or Phi^-1(1 - significance)
  *            when that is set <= 0; needs the eigenvalues (fit, or lam on import)           */
 typedef enum { DDC_CORR_LEARNED = 0, DDC_CORR_LOSSLESS = 1, DDC_CORR_NONE = 2, DDC_CORR_ADS = 3,
-               DDC_CORR_BSAR = 4 } ddc_corr;
+               DDC_CORR_BSAR = 4, DDC_CORR_BSAO = 5 } ddc_corr;
+/*  BSAO    : the quantization estimate of Sec. V-B ("BSA-O"): before any dimension is read, a
+ *            candidate is pruned iff m1 dis' + m3 err + beta(alpha) > tau, with dis' the
+ *            asymmetric distance from the query to the candidate's OPQ codewords, err the
+ *            candidate's distance to its own codewords and (m1, m3, beta) the calibrated
+ *            classifier of the table the search's K selects; survivors are refined to their
+ *            exact distance (stage tests there are lossless, so they prune without changing
+ *            the result).  Needs an index fitted or imported with pq_m > 0 and its tables.   */
 
 /* Rotation learned by the fit: PCA (Sec. IV-B, Thm. 1) or, for the ablation of Sec. III /
  * IV-B, a Haar-distributed random rotation drawn from the fit seed. */
@@ -104,6 +111,12 @@ typedef struct {
                              before the stored-precision stages (needs dim >= 64); 0 */
   int64_t pca_sample;     /* PCA rows: all if n <= this, else a SplitMix64 sample; 1,000,000 */
   uint64_t seed;          /* SplitMix64 seed of every random choice in fit; 0 */
+  int32_t pq_m;           /* 0, or M subspaces of the quantization estimate (DDC_CORR_BSAO): OPQ
+                             eigenvalue allocation of the PCA axes into M subspaces of dim/M axes
+                             with 256 codewords each (Sec. VII-A: M = dim/4, dim/8 for GIST);
+                             M divides dim, M % 8 == 0, dim/M <= 32, M <= 128; needs PCA; 0 */
+  int32_t pq_iters;       /* k-means iterations of every subspace codebook; 25 */
+  int64_t pq_train;       /* codebook training rows (SplitMix64 sample); 65,536 (Sec. VII-A) */
 } ddc_fit_params;
 
 /* Artifacts of a fitted index, host memory, for ddc_import / ddc_export.
@@ -134,6 +147,14 @@ typedef struct {
                              pairs, table after table */
   uint8_t *codes8;        /* [n x 64]   export only, may be NULL: FP8 codes of vector i (by id) */
   float *scale8;          /* [n]        export only, may be NULL: decode scale of vector i's tile */
+  int32_t pq_m;           /* 0, or M: the quantization estimate's subspaces (as in ddc_fit_params) */
+  int32_t *pq_perm;       /* [D]        rotated axes of subspace j at [j D/M, (j+1) D/M) */
+  float *pq_books;        /* [M x 256 x D/M] codewords */
+  uint8_t *pq_codes;      /* [n x M]    export only, may be NULL: codes of vector i (by id); import
+                                         encodes them from y and pq_books */
+  double *pq_m1, *pq_m3;  /* [n_tables] the BSA-O classifier of each table (NULL on import: none) */
+  double *pq_resid;       /* [sum n0]   its label-0 residuals tau_j - m1 dis'_j - m3 err_j, table
+                                         after table (NULL on import: none) */
 } ddc_artifacts;
 
 typedef struct {
@@ -147,6 +168,8 @@ typedef struct {
   int32_t fp8_lead_dims;  /* 0 or 64; n_test_stages counts the FP8 pre-stage when 64 */
   int32_t n_tables;       /* correction tables and their calibration K_c */
   int32_t table_k[4];
+  int32_t pq_m;           /* subspaces of the quantization estimate, 0 = none */
+  int32_t pq_tables;      /* 1 if the tables hold the BSA-O classifier */
 } ddc_index_info;
 
 /* Per-call counters of the scan (sums over all queries of the call). */
@@ -198,6 +221,12 @@ ddc_status ddc_calibrate(ddc_index *ix, const float *calib, int64_t n_calib, int
  * in ddc_index_info.n_test_stages (the FP8 pre-stage first when present). */
 ddc_status ddc_correction(const ddc_index *ix, int32_t k, double significance, ddc_calib_mode mode,
                           double *m_out, double *beta_out);
+
+/* The BSA-O classifier a search with K uses at significance alpha: *m1, *m3 and *beta of
+ * m1 dis' + m3 err + beta > tau (beta = -INFINITY when alpha = 0).  EINVAL without BSA-O
+ * tables. */
+ddc_status ddc_correction_pq(const ddc_index *ix, int32_t k, double significance, double *m1,
+                             double *m3, double *beta);
 
 /* Search, host buffers.  queries: [nq x dim]; ids/dists: [nq x k].
  * 1 <= k <= 256, 1 <= nprobe <= nlist, 0 <= significance < 1 (0: no learned pruning). */

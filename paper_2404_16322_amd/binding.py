@@ -13,7 +13,7 @@ _LOCK = threading.Lock()
 
 DTYPE = {"f32": 0, "f16": 1, "bf16": 2}
 ROT = {"f32": 0, "bf16": 1}
-CORR = {"learned": 0, "lossless": 1, "none": 2, "ads": 3, "bsar": 4}
+CORR = {"learned": 0, "lossless": 1, "none": 2, "ads": 3, "bsar": 4, "bsao": 5}
 PROJ = {"pca": 0, "haar": 1}
 EST = {"partial": 0, "residual": 1}
 CALIB = {"joint": 0, "bonferroni": 1}
@@ -26,7 +26,7 @@ SYMBOLS = ["ddc_fit_params_default", "ddc_fit", "ddc_import", "ddc_export", "ddc
            "ddc_last_error", "ddc_server_create", "ddc_server_submit", "ddc_server_poll",
            "ddc_server_get_stats", "ddc_server_destroy", "ddc_set_launch", "ddc_get_launch",
            "ddc_scan_variant", "ddc_save", "ddc_load", "ddc_set_ads_epsilon", "ddc_set_bsar_multiplier",
-           "ddc_search_estimate"]
+           "ddc_search_estimate", "ddc_correction_pq"]
 
 
 class FitParams(C.Structure):
@@ -37,7 +37,8 @@ class FitParams(C.Structure):
                 ("calib_k_extra", C.c_int32 * 3), ("storage", C.c_int),
                 ("rotation", C.c_int), ("projection", C.c_int), ("fp8_lead_dims", C.c_int32),
                 ("pca_sample", C.c_int64),
-                ("seed", C.c_uint64)]
+                ("seed", C.c_uint64), ("pq_m", C.c_int32), ("pq_iters", C.c_int32),
+                ("pq_train", C.c_int64)]
 
 
 class Artifacts(C.Structure):
@@ -47,7 +48,10 @@ class Artifacts(C.Structure):
                 ("rot", C.c_void_p), ("lam", C.c_void_p), ("centroids", C.c_void_p),
                 ("assign", C.c_void_p), ("y", C.c_void_p), ("n_tables", C.c_int32),
                 ("table_k", C.c_int32 * 4), ("table_n0", C.c_int64 * 4), ("m", C.c_void_p),
-                ("resid", C.c_void_p), ("codes8", C.c_void_p), ("scale8", C.c_void_p)]
+                ("resid", C.c_void_p), ("codes8", C.c_void_p), ("scale8", C.c_void_p),
+                ("pq_m", C.c_int32), ("pq_perm", C.c_void_p), ("pq_books", C.c_void_p),
+                ("pq_codes", C.c_void_p), ("pq_m1", C.c_void_p), ("pq_m3", C.c_void_p),
+                ("pq_resid", C.c_void_p)]
 
 
 class IndexInfo(C.Structure):
@@ -56,7 +60,8 @@ class IndexInfo(C.Structure):
                 ("n_test_stages", C.c_int32), ("block_b", C.c_int32), ("lag_l", C.c_int32),
                 ("storage", C.c_int), ("rotation", C.c_int), ("n0", C.c_int64),
                 ("packed_bytes", C.c_int64), ("total_tiles", C.c_int64), ("fp8_lead_dims", C.c_int32),
-                ("n_tables", C.c_int32), ("table_k", C.c_int32 * 4)]
+                ("n_tables", C.c_int32), ("table_k", C.c_int32 * 4), ("pq_m", C.c_int32),
+                ("pq_tables", C.c_int32)]
 
 
 class SearchStats(C.Structure):
@@ -123,6 +128,7 @@ def load_library():
                                           vp, vp, vp, vp]
         lib.ddc_debug_intermediates.argtypes = [vp, vp, i64, i32, vp, vp]
         lib.ddc_search_estimate.argtypes = [vp, vp, i64, i32, i32, i32, C.c_int, vp, vp]
+        lib.ddc_correction_pq.argtypes = [vp, i32, f64, vp, vp, vp]
         lib.ddc_set_kernel_timing.argtypes = [vp, C.c_int]
         lib.ddc_get_kernel_timing.argtypes = [vp, vp, vp, C.c_int]
         lib.ddc_set_ads_epsilon.argtypes = [vp, f64]
@@ -200,7 +206,9 @@ class Index:
     def from_artifacts(cls, art: dict) -> "Index":
         """art: mu, R (rows = eigenvectors), centroids, assign, y (stored rotated base), and
         optionally m, resid (label-0 residual matrix), lam, storage, rotation, delta_d, block_b,
-        fp8_lead_dims (0 or 64; the codes are encoded from y on import)."""
+        fp8_lead_dims (0 or 64; the codes are encoded from y on import), pq_perm (M, D/M) and
+        pq_books (M, 256, D/M) of the quantization estimate (codes encoded on import), and per
+        table pq_m1, pq_m3, pq_resid (the BSA-O classifier)."""
         mu = np.ascontiguousarray(art["mu"], np.float64)
         R = np.ascontiguousarray(art["R"], np.float64)
         cent = _f32(art["centroids"])
@@ -226,7 +234,21 @@ class Index:
             a.lam = _ptr(lam)
         tabs = art.get("tables")
         if tabs is None and art.get("resid") is not None:
-            tabs = [dict(kc=int(art.get("calib_k", 1)), m=art["m"], resid=art["resid"])]
+            tabs = [dict(kc=int(art.get("calib_k", 1)), m=art["m"], resid=art["resid"],
+                         pq_m1=art.get("pq_m1"), pq_m3=art.get("pq_m3"), pq_resid=art.get("pq_resid"))]
+        if art.get("pq_perm") is not None:
+            perm = np.ascontiguousarray(np.asarray(art["pq_perm"]).reshape(-1), np.int32)
+            books = _f32(art["pq_books"])
+            keep += [perm, books]
+            a.pq_m = int(np.asarray(art["pq_books"]).shape[0])
+            a.pq_perm, a.pq_books = _ptr(perm), _ptr(books)
+            if tabs and all(t.get("pq_resid") is not None for t in tabs):
+                m1 = np.array([t["pq_m1"] for t in tabs], np.float64)
+                m3 = np.array([t["pq_m3"] for t in tabs], np.float64)
+                pr = np.ascontiguousarray(np.concatenate([np.reshape(t["pq_resid"], -1) for t in tabs]),
+                                          np.float64)
+                keep += [m1, m3, pr]
+                a.pq_m1, a.pq_m3, a.pq_resid = _ptr(m1), _ptr(m3), _ptr(pr)
         if tabs:
             m = np.ascontiguousarray(np.vstack([np.atleast_2d(t["m"]) for t in tabs]), np.float64)
             G = np.ascontiguousarray(np.vstack([t["resid"] for t in tabs]), np.float64)
@@ -288,11 +310,23 @@ class Index:
             out["codes8"] = np.zeros((n, inf["fp8_lead_dims"]), np.uint8)
             out["scale8"] = np.zeros(n, np.float32)
             a.codes8, a.scale8 = _ptr(out["codes8"]), _ptr(out["scale8"])
+        M = inf["pq_m"]
+        if M:
+            out["pq_perm"] = np.zeros((M, D // M), np.int32)
+            out["pq_books"] = np.zeros((M, 256, D // M), np.float32)
+            out["pq_codes"] = np.zeros((n, M), np.uint8)
+            a.pq_perm, a.pq_books, a.pq_codes = _ptr(out["pq_perm"]), _ptr(out["pq_books"]), \
+                _ptr(out["pq_codes"])
+            pm1, pm3, pres = np.zeros(max(nt, 1)), np.zeros(max(nt, 1)), np.zeros(max(n0, 1))
+            if inf["pq_tables"]:
+                a.pq_m1, a.pq_m3, a.pq_resid = _ptr(pm1), _ptr(pm3), _ptr(pres)
         _check(load_library().ddc_export(self._h, C.byref(a)))
         tabs, r0 = [], 0
         for t in range(nt):
             n0t = a.table_n0[t]
             tabs.append(dict(kc=a.table_k[t], m=m_all[t].copy(), resid=r_all[r0:r0 + n0t].copy()))
+            if M and inf["pq_tables"]:
+                tabs[-1].update(pq_m1=float(pm1[t]), pq_m3=float(pm3[t]), pq_resid=pres[r0:r0 + n0t].copy())
             r0 += n0t
         if tabs:
             out["m"], out["resid"], out["calib_k"] = tabs[0]["m"], tabs[0]["resid"], tabs[0]["kc"]
@@ -306,6 +340,12 @@ class Index:
         m, b = np.zeros(St), np.zeros(St)
         _check(load_library().ddc_correction(self._h, k, alpha, CALIB[mode], _ptr(m), _ptr(b)))
         return m, b
+
+    def correction_pq(self, alpha: float, k: int = 1):
+        """(m1, m3, beta) of the BSA-O classifier a search with this K uses."""
+        m1, m3, b = C.c_double(), C.c_double(), C.c_double()
+        _check(load_library().ddc_correction_pq(self._h, k, alpha, C.byref(m1), C.byref(m3), C.byref(b)))
+        return m1.value, m3.value, b.value
 
     def calibrate(self, calib, calib_k=10, calib_nprobe=0, max_neg=50, seed=0):
         calib = _f32(calib)

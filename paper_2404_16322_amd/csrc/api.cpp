@@ -40,7 +40,7 @@ static std::array<int, 4> tune_class(int64_t nq, int np_max, int k_max, int kind
 
 // kernel family of a launch: pruned or not, FP8 pre-stage, residual test, estimate only
 static int scan_kind(const ScanArgs &a) {
-  return a.prune + 2 * a.pre + 4 * a.res + 8 * (a.est_nb > 0 ? 1 : 0);
+  return a.prune + 2 * a.pre + 4 * a.res + 8 * (a.est_nb > 0 ? 1 : 0) + 16 * (a.pq_m > 0 ? 1 : 0);
 }
 
 // Launch shape of the scan: waves per query (1 or 4), look-ahead (0 or 1), persistent (0 or 1).
@@ -88,6 +88,7 @@ static void choose_variant(ddc_index *ix, ScanArgs &a, int np_max, hipStream_t s
   const int kind = scan_kind(a);
   const auto key = tune_class(a.nq, np_max, a.k_max, kind);
   Variant v = fixed_variant(ix, a.nq, a.prune);
+  if (scan_lds_request(a, v[0]) > kMaxLds) v[0] = 4;   // e.g. four lookup tables of BSA-O
   const bool need_w = ix->waves_per_query == 0, need_l = a.prune && !a.res && ix->lookahead < 0;
   const bool need_p = ix->persistent < 0;
   if (need_w || need_l || need_p) {
@@ -99,13 +100,15 @@ static void choose_variant(ddc_index *ix, ScanArgs &a, int np_max, hipStream_t s
       hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
       HIPC(hipStreamIsCapturing(s, &cs));
       if (may_tune && cs == hipStreamCaptureStatusNone) {
-        std::vector<Variant> cand;   // simplest shapes first
+        std::vector<Variant> cand;   // simplest shapes first; shapes whose LDS does not fit skipped
         for (int p : {0, 1})
           for (int w : {1, 4})
             for (int l : {0, 1}) {
               auto c = forced_or(ix, {w, l, p}, kind);
+              if (scan_lds_request(a, c[0]) > kMaxLds) continue;
               if (std::find(cand.begin(), cand.end(), c) == cand.end()) cand.push_back(c);
             }
+        if (cand.empty()) cand.push_back(v);
         hipEvent_t e0, e1;
         HIPC(hipEventCreate(&e0));
         HIPC(hipEventCreate(&e1));
@@ -247,6 +250,8 @@ static void upload_index(ddc_index *ix, const float *d_Y, hipStream_t s) {
   HIPC(hipGetLastError());
   HIPC(hipStreamSynchronize(s));
 }
+
+static void pq_upload_encode(ddc_index *ix, hipStream_t s);
 
 static bool all_finite(const float *x, int64_t cnt) {
   for (int64_t i = 0; i < cnt; ++i)
@@ -459,6 +464,41 @@ static ddc_index::Table run_calibration(ddc_index *ix, const float *calib, int64
   tab.m = m;
   tab.resid = G;
   tab.n0 = n0;
+
+  // -- BSA-O: features (asymmetric distance, quantization error, tau) of the same pairs, FP64;
+  // one logistic regression, then the label-0 residuals of its test
+  if (ix->pq_m > 0) {
+    DevBuf d_pq_q(npairs * 4), d_pq_s(npairs * 8), d_adc(npairs * 8), d_err(npairs * 8);
+    HIPC(hipMemcpyAsync(d_pq_q.p, pair_q.data(), npairs * 4, hipMemcpyHostToDevice, s));
+    HIPC(hipMemcpyAsync(d_pq_s.p, pair_slot.data(), npairs * 8, hipMemcpyHostToDevice, s));
+    launch_pq_features64(d_q64.as<double>(), D, ix->d_base.p, ix->store(), ix->NB,
+                         ix->d_pq_perm.as<int32_t>(), ix->d_pq_books.as<float>(), ix->pq_m, ix->pq_dsub,
+                         ix->d_pq_codes.as<uint8_t>(), d_pq_q.as<int32_t>(), d_pq_s.as<int64_t>(), npairs,
+                         d_adc.as<double>(), d_err.as<double>(), s);
+    std::vector<double> adc(npairs), err(npairs);
+    HIPC(hipMemcpyAsync(adc.data(), d_adc.p, npairs * 8, hipMemcpyDeviceToHost, s));
+    HIPC(hipMemcpyAsync(err.data(), d_err.p, npairs * 8, hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    HIPC(hipGetLastError());
+    if (n1 > 0) {
+      std::vector<double> F((size_t)npairs * 3), y(npairs), w;
+      for (int64_t p = 0; p < npairs; ++p) {
+        F[3 * p] = adc[p];
+        F[3 * p + 1] = err[p];
+        F[3 * p + 2] = pair_tau[p];
+        y[p] = p < n0 ? 0.0 : 1.0;
+      }
+      double b;
+      logistic_fit_p(F, 3, y, b, w);
+      // sign(w1 dis' + w3 err + w2 tau + b) > 0  <=>  m1 dis' + m3 err + beta > tau (w2 < 0)
+      if (w[2] < 0 && -w[0] / w[2] > 0) {
+        tab.pq_m1 = -w[0] / w[2];
+        tab.pq_m3 = -w[1] / w[2];
+      }
+    }
+    tab.pq_resid.resize(n0);
+    for (int64_t j = 0; j < n0; ++j) tab.pq_resid[j] = pair_tau[j] - tab.pq_m1 * adc[j] - tab.pq_m3 * err[j];
+  }
   return tab;
 }
 
@@ -534,6 +574,40 @@ static std::shared_ptr<DevBuf> device_tables(ddc_index *ix, double alpha, ddc_co
   return buf;
 }
 
+// Device tables of a BSA-O search: [ntab][NB + 1][2] lossless stage rows (m = 1, beta = 0 where
+// a test follows: refinement only prunes candidates whose partial distance already exceeds
+// tau), then [ntab][4] = (m1, m3, beta(alpha), 0) of each table's quantization test.
+static std::shared_ptr<DevBuf> device_pq_tables(ddc_index *ix, double alpha, int *ntab) {
+  std::lock_guard<std::mutex> lk(ix->beta_mtx);
+  const auto key = std::make_pair(alpha, (int)DDC_CORR_BSAO);
+  const int nt = (int)ix->tables.size();
+  *ntab = nt;
+  auto it = ix->tab_cache.find(key);
+  if (it != ix->tab_cache.end()) return it->second;
+  const int NB = ix->NB;
+  std::vector<float> h((size_t)nt * (NB + 1) * 2 + (size_t)nt * 4);
+  for (int t = 0; t < nt; ++t) {
+    float *row = &h[(size_t)t * (NB + 1) * 2];
+    for (int b = 0; b <= NB; ++b) { row[2 * b] = 0.f; row[2 * b + 1] = -INFINITY; }
+    for (int j = 0; j < ix->St; ++j) {
+      const int b = ((j + 1) * ix->delta_d) / kBlockDims - 1;
+      row[2 * b] = 1.f;
+      row[2 * b + 1] = 0.f;
+    }
+    const auto &tb = ix->tables[t];
+    const double beta = beta_for_alpha(tb.pq_resid, tb.n0, 1, alpha, 0)[0];
+    float *pq = &h[(size_t)nt * (NB + 1) * 2 + (size_t)t * 4];
+    pq[0] = (float)tb.pq_m1;
+    pq[1] = (float)tb.pq_m3;
+    pq[2] = (float)beta;
+    pq[3] = 0.f;
+  }
+  auto buf = std::make_shared<DevBuf>(h.size() * 4);
+  HIPC(hipMemcpy(buf->p, h.data(), h.size() * 4, hipMemcpyHostToDevice));
+  ix->tab_cache[key] = buf;
+  return buf;
+}
+
 // ---------------------------------------------------------------------------------------
 // search pipeline
 // ---------------------------------------------------------------------------------------
@@ -575,7 +649,20 @@ void ddc::search_device(ddc_index *ix, const float *d_q, int64_t nq, const int32
   // LOSSLESS tests e_s > tau with the stored values only: the FP8 estimate is no lower bound;
   // ADS is a fixed table on the stored values too
   const bool lossless = (mode == DDC_CORR_LOSSLESS || mode == DDC_CORR_ADS) && ix->St > 0;
-  if (mode == DDC_CORR_BSAR && ix->St > 0) {
+  if (mode == DDC_CORR_BSAO) {
+    a.prune = 1;
+    tabs = device_pq_tables(ix, alpha, &a.ntab);
+    a.tab = tabs->as<float>();
+    a.pq_tab = a.tab + (size_t)a.ntab * (ix->NB + 1) * 2;
+    for (int t = 0; t < a.ntab; ++t) a.tab_k[t] = ix->tables[t].kc;
+    for (int j = 0; j < ix->St; ++j) a.test_after[((j + 1) * ix->delta_d) / kBlockDims - 1] = 1;
+    a.pq_m = ix->pq_m;
+    a.pq_dsub = ix->pq_dsub;
+    a.pq_codes = ix->d_pq_codes.as<uint8_t>();
+    a.pq_err = ix->d_pq_err.as<float>();
+    a.pq_books = ix->d_pq_books.as<float>();
+    a.pq_perm = ix->d_pq_perm.as<int32_t>();
+  } else if (mode == DDC_CORR_BSAR && ix->St > 0) {
     a.prune = 1;
     a.res = 1;
     a.xnorm = ix->d_xnorm.as<float>();
@@ -683,8 +770,10 @@ static ddc_status check_search_args(const ddc_index *ix, int64_t nq, double alph
   if (nq < 0) return set_err(DDC_EINVAL, "nq must be >= 0");
   if (!(alpha >= 0.0 && alpha < 1.0)) return set_err(DDC_EINVAL, "significance must be in [0, 1)");
   if (mode != DDC_CORR_LEARNED && mode != DDC_CORR_LOSSLESS && mode != DDC_CORR_NONE &&
-      mode != DDC_CORR_ADS && mode != DDC_CORR_BSAR)
+      mode != DDC_CORR_ADS && mode != DDC_CORR_BSAR && mode != DDC_CORR_BSAO)
     return set_err(DDC_EINVAL, "unknown correction mode %d", (int)mode);
+  if (mode == DDC_CORR_BSAO && !ix->pq_tables())
+    return set_err(DDC_EINVAL, "the BSA-O test needs an index with pq_m > 0 and its calibrated tables");
   if (mode == DDC_CORR_BSAR && (int)ix->lam.size() != ix->D)
     return set_err(DDC_EINVAL, "the residual test needs the rotation's eigenvalues (lam)");
   if (mode == DDC_CORR_BSAR && ix->bsar_m <= 0 && !(alpha > 0))
@@ -698,6 +787,12 @@ static ddc_status check_k_np(const ddc_index *ix, int k, int np) {
   if (k < 1 || k > kMaxK) return set_err(DDC_EINVAL, "k must be in [1, %d], got %d", kMaxK, k);
   if (np < 1 || np > ix->nlist) return set_err(DDC_EINVAL, "nprobe must be in [1, nlist=%d], got %d", ix->nlist, np);
   if (np > 4096) return set_err(DDC_EUNSUP, "nprobe > 4096 is not supported");
+  return DDC_OK;
+}
+
+static ddc_status check_pq_shape(int M, int dim) {
+  if (M < 8 || M > 128 || M % 8 || dim % M || dim / M > 32)
+    return set_err(DDC_EINVAL, "pq_m must be a multiple of 8 in [8, 128] dividing dim with dim/pq_m <= 32");
   return DDC_OK;
 }
 
@@ -726,6 +821,13 @@ static ddc_status check_params(const ddc_fit_params *p, int64_t n, int dim) {
   if (p->projection != DDC_PROJ_PCA && p->projection != DDC_PROJ_HAAR) return set_err(DDC_EINVAL, "bad projection");
   if (p->fp8_lead_dims != 0 && p->fp8_lead_dims != kFp8Lead) return set_err(DDC_EINVAL, "fp8_lead_dims must be 0 or 64");
   if (p->fp8_lead_dims && dim < kFp8Lead) return set_err(DDC_EINVAL, "the FP8 pre-stage needs dim >= 64");
+  if (p->pq_m != 0) {
+    ddc_status st = check_pq_shape(p->pq_m, dim);
+    if (st != DDC_OK) return st;
+    if (p->projection != DDC_PROJ_PCA) return set_err(DDC_EINVAL, "the OPQ allocation needs the PCA rotation");
+    if (p->pq_iters < 0 || p->pq_train < 256) return set_err(DDC_EINVAL, "pq_iters >= 0 and pq_train >= 256");
+    if (n < 256) return set_err(DDC_EINVAL, "the quantization estimate needs n >= 256");
+  }
   return DDC_OK;
 }
 
@@ -748,7 +850,7 @@ static void init_sizes(ddc_index *ix, int64_t n, int D, int nlist, int dd, int B
 // in memory), then a 64-bit FNV-1a checksum of everything before it --------------------------
 namespace {
 constexpr char kMagic[8] = {'D', 'D', 'C', 'I', 'N', 'D', 'E', 'X'};
-constexpr uint32_t kFileVersion = 1;
+constexpr uint32_t kFileVersion = 2;   // 2: the quantization estimate's section (1 still loads)
 
 struct Fnv {
   uint64_t h = 1469598103934665603ull;
@@ -793,6 +895,7 @@ ddc_status ddc_fit_params_default(ddc_fit_params *p) {
   p->calib_k = 10; p->calib_nprobe = 0; p->calib_max_neg = 50;
   p->storage = DDC_F32; p->rotation = DDC_ROT_F32;
   p->pca_sample = 1000000; p->seed = 0;
+  p->pq_m = 0; p->pq_iters = 25; p->pq_train = 65536;
   return DDC_OK;
 }
 
@@ -815,6 +918,8 @@ ddc_status ddc_index_get_info(const ddc_index *ix, ddc_index_info *info) {
   info->n0 = ix->n0_total(); info->packed_bytes = (int64_t)ix->d_base.bytes; info->total_tiles = ix->total_tiles;
   info->n_tables = (int32_t)ix->tables.size();
   for (size_t t = 0; t < ix->tables.size(); ++t) info->table_k[t] = ix->tables[t].kc;
+  info->pq_m = ix->pq_m;
+  info->pq_tables = ix->pq_tables() ? 1 : 0;
   return DDC_OK;
 }
 
@@ -840,6 +945,20 @@ ddc_status ddc_import(const ddc_artifacts *a, ddc_index **out) {
       return set_err(DDC_EINVAL, "bad correction table %d (n0 >= 1, K_c ascending)", t);
   }
   if (a->n_tables > 0 && (!a->m || !a->resid)) return set_err(DDC_EINVAL, "missing m/resid");
+  if (a->pq_m != 0) {
+    ddc_status st = check_pq_shape(a->pq_m, a->dim);
+    if (st != DDC_OK) return st;
+    if (!a->pq_perm || !a->pq_books) return set_err(DDC_EINVAL, "missing pq_perm/pq_books");
+    std::vector<int> seen(a->dim, 0);
+    for (int i = 0; i < a->dim; ++i) {
+      const int v = a->pq_perm[i];
+      if (v < 0 || v >= a->dim || seen[v]++) return set_err(DDC_EINVAL, "pq_perm is not a permutation of the axes");
+    }
+    if (!all_finite(a->pq_books, (int64_t)a->pq_m * 256 * (a->dim / a->pq_m)))
+      return set_err(DDC_EINVAL, "non-finite codewords");
+    if (a->n_tables > 0 && (!a->pq_m1) != (!a->pq_resid)) return set_err(DDC_EINVAL, "pq_m1/pq_m3/pq_resid: all or none");
+    if (a->pq_m1 && !a->pq_m3) return set_err(DDC_EINVAL, "pq_m1/pq_m3/pq_resid: all or none");
+  }
   for (int64_t i = 0; i < a->n; ++i)
     if (a->assign[i] < 0 || a->assign[i] >= a->nlist) return set_err(DDC_EINVAL, "assign out of range at %lld", (long long)i);
   if (!all_finite(a->y, a->n * D) || !all_finite(a->centroids, (int64_t)a->nlist * D))
@@ -861,9 +980,20 @@ ddc_status ddc_import(const ddc_artifacts *a, ddc_index **out) {
       tabs[t].n0 = a->table_n0[t];
       tabs[t].m.assign(a->m + (size_t)t * Tt, a->m + (size_t)(t + 1) * Tt);
       tabs[t].resid.assign(a->resid + roff * Tt, a->resid + (roff + a->table_n0[t]) * Tt);
+      if (a->pq_m && a->pq_m1) {
+        tabs[t].pq_m1 = a->pq_m1[t];
+        tabs[t].pq_m3 = a->pq_m3[t];
+        tabs[t].pq_resid.assign(a->pq_resid + roff, a->pq_resid + roff + a->table_n0[t]);
+      }
       roff += a->table_n0[t];
     }
     set_tables(ix.get(), std::move(tabs));
+  }
+  if (a->pq_m) {
+    ix->pq_m = a->pq_m;
+    ix->pq_dsub = D / a->pq_m;
+    ix->pq_perm.assign(a->pq_perm, a->pq_perm + D);
+    ix->pq_books.assign(a->pq_books, a->pq_books + (size_t)a->pq_m * 256 * ix->pq_dsub);
   }
   StreamHolder sh;
   DevBuf d_Y((size_t)a->n * ix->Dp * 4);
@@ -871,6 +1001,7 @@ ddc_status ddc_import(const ddc_artifacts *a, ddc_index **out) {
   HIPC(hipMemcpy2DAsync(d_Y.p, ix->Dp * 4, a->y, D * 4, D * 4, a->n, hipMemcpyHostToDevice, sh.s));
   launch_round_storage(d_Y.as<float>(), a->n * ix->Dp, ix->store(), sh.s);
   upload_index(ix.get(), d_Y.as<float>(), sh.s);
+  if (ix->pq_m) pq_upload_encode(ix.get(), sh.s);
   *out = ix.release();
   return DDC_OK;
   GUARD_END
@@ -897,6 +1028,28 @@ ddc_status ddc_export(const ddc_index *ixc, ddc_artifacts *a) {
       const int64_t slot = ix->id_to_slot[i];
       if (a->codes8) std::memcpy(a->codes8 + (size_t)i * kFp8Lead, &c8[(size_t)slot * kFp8Lead], kFp8Lead);
       if (a->scale8) a->scale8[i] = s8[slot / kTile];
+    }
+  }
+  a->pq_m = ix->pq_m;
+  if (ix->pq_m) {
+    if (a->pq_perm) std::copy(ix->pq_perm.begin(), ix->pq_perm.end(), a->pq_perm);
+    if (a->pq_books) std::copy(ix->pq_books.begin(), ix->pq_books.end(), a->pq_books);
+    if (a->pq_codes) {
+      const int M = ix->pq_m;
+      std::vector<uint8_t> c((size_t)ix->total_tiles * kTile * M);
+      HIPC(hipMemcpy(c.data(), ix->d_pq_codes.p, c.size(), hipMemcpyDeviceToHost));
+      for (int64_t i = 0; i < ix->n; ++i)
+        std::memcpy(a->pq_codes + (size_t)i * M, &c[(size_t)ix->id_to_slot[i] * M], M);
+    }
+    if (ix->pq_tables() && a->pq_m1 && a->pq_m3 && a->pq_resid) {
+      size_t roff = 0;
+      for (size_t t = 0; t < ix->tables.size(); ++t) {
+        const auto &tb = ix->tables[t];
+        a->pq_m1[t] = tb.pq_m1;
+        a->pq_m3[t] = tb.pq_m3;
+        std::copy(tb.pq_resid.begin(), tb.pq_resid.end(), a->pq_resid + roff);
+        roff += (size_t)tb.n0;
+      }
     }
   }
   std::copy(ix->mu.begin(), ix->mu.end(), a->mu);
@@ -995,6 +1148,20 @@ ddc_status ddc_save(const ddc_index *ixc, const char *path) {
   w.put(y.data(), y.size() * 4);
   w.put(m.data(), (size_t)nt * T * 8);
   w.put(resid.data(), resid.size() * 8);
+  // quantization estimate: M, then axes, codewords and (when calibrated) each table's classifier
+  w.val<int32_t>(ix->pq_m);
+  if (ix->pq_m) {
+    const uint8_t has_pq_tab = ix->pq_tables() ? 1 : 0;
+    w.val<uint8_t>(has_pq_tab);
+    w.put(ix->pq_perm.data(), ix->pq_perm.size() * 4);
+    w.put(ix->pq_books.data(), ix->pq_books.size() * 4);
+    if (has_pq_tab)
+      for (const auto &tb : ix->tables) {
+        w.val<double>(tb.pq_m1);
+        w.val<double>(tb.pq_m3);
+        w.put(tb.pq_resid.data(), tb.pq_resid.size() * 8);
+      }
+  }
   const uint64_t h = w.sum.h;
   if (fwrite(&h, 1, 8, fc.f) != 8) throw DdcError(DDC_EIO, "write failed");
   if (fflush(fc.f) != 0) throw DdcError(DDC_EIO, "write failed");
@@ -1013,7 +1180,8 @@ ddc_status ddc_load(const char *path, ddc_index **out) {
   char magic[8];
   r.get(magic, 8);
   if (std::memcmp(magic, kMagic, 8) != 0) return set_err(DDC_EIO, "%s is not an index file", path);
-  if (r.val<uint32_t>() != kFileVersion) return set_err(DDC_EIO, "unsupported index file version");
+  const uint32_t version = r.val<uint32_t>();
+  if (version != 1 && version != kFileVersion) return set_err(DDC_EIO, "unsupported index file version");
   ddc_artifacts a{};
   a.n = r.val<int64_t>();
   a.dim = r.val<int32_t>(); a.nlist = r.val<int32_t>(); a.delta_d = r.val<int32_t>();
@@ -1043,12 +1211,55 @@ ddc_status ddc_load(const char *path, ddc_index **out) {
   r.get(y.data(), y.size() * 4);
   r.get(m.data(), m.size() * 8);
   r.get(resid.data(), resid.size() * 8);
+  std::vector<int32_t> pq_perm;
+  std::vector<float> pq_books;
+  std::vector<double> pq_m1, pq_m3, pq_resid;
+  if (version >= 2) {
+    a.pq_m = r.val<int32_t>();
+    if (a.pq_m) {
+      if (a.pq_m < 1 || a.pq_m > 128 || D % a.pq_m) return set_err(DDC_EIO, "corrupt index file (pq section)");
+      const uint8_t has_pq_tab = r.val<uint8_t>();
+      pq_perm.resize(D);
+      pq_books.resize((size_t)a.pq_m * 256 * (D / a.pq_m));
+      r.get(pq_perm.data(), pq_perm.size() * 4);
+      r.get(pq_books.data(), pq_books.size() * 4);
+      if (has_pq_tab) {
+        pq_m1.resize(a.n_tables);
+        pq_m3.resize(a.n_tables);
+        pq_resid.resize(n0);
+        size_t roff = 0;
+        for (int t = 0; t < a.n_tables; ++t) {
+          pq_m1[t] = r.val<double>();
+          pq_m3[t] = r.val<double>();
+          r.get(pq_resid.data() + roff, (size_t)a.table_n0[t] * 8);
+          roff += (size_t)a.table_n0[t];
+        }
+        a.pq_m1 = pq_m1.data(); a.pq_m3 = pq_m3.data(); a.pq_resid = pq_resid.data();
+      }
+      a.pq_perm = pq_perm.data(); a.pq_books = pq_books.data();
+    }
+  }
   const uint64_t want = r.sum.h;
   uint64_t got = 0;
   if (fread(&got, 1, 8, fc.f) != 8 || got != want) return set_err(DDC_EIO, "index file checksum mismatch");
   a.mu = mu.data(); a.rot = R.data(); a.lam = has_lam ? lam.data() : nullptr; a.centroids = cent.data();
   a.assign = assign.data(); a.y = y.data(); a.m = m.data(); a.resid = resid.data();
   return ddc_import(&a, out);
+  GUARD_END
+}
+
+ddc_status ddc_correction_pq(const ddc_index *ixc, int32_t k, double alpha, double *m1, double *m3,
+                             double *beta) {
+  if (!ixc || !m1 || !m3 || !beta) return set_err(DDC_EINVAL, "NULL argument");
+  if (!(alpha >= 0.0 && alpha < 1.0)) return set_err(DDC_EINVAL, "significance must be in [0, 1)");
+  if (k < 1 || k > kMaxK) return set_err(DDC_EINVAL, "k must be in [1, %d]", kMaxK);
+  if (!ixc->pq_tables()) return set_err(DDC_EINVAL, "index has no BSA-O table");
+  GUARD_BEGIN
+  const auto &tb = ixc->tables[table_for_k(ixc, k)];
+  *m1 = tb.pq_m1;
+  *m3 = tb.pq_m3;
+  *beta = beta_for_alpha(tb.pq_resid, tb.n0, 1, alpha, 0)[0];
+  return DDC_OK;
   GUARD_END
 }
 
@@ -1302,11 +1513,18 @@ ddc_status ddc_scan_variant(ddc_index *ix, int64_t nq, int32_t k_max, int32_t np
   if (!ix || !waves || !lookahead) return set_err(DDC_EINVAL, "NULL argument");
   if (nq < 1 || k_max < 1 || nprobe_max < 1) return set_err(DDC_EINVAL, "sizes must be >= 1");
   // the kernel family a search in this mode launches (significance > 0 assumed for LEARNED)
-  const int prune = mode == DDC_CORR_LEARNED ? ix->Tt() > 0 : (mode != DDC_CORR_NONE && ix->St > 0);
+  const int prune = mode == DDC_CORR_BSAO ? 1 :
+                    mode == DDC_CORR_LEARNED ? ix->Tt() > 0 : (mode != DDC_CORR_NONE && ix->St > 0);
   const int kind = prune + 2 * (mode == DDC_CORR_LEARNED && ix->P() ? 1 : 0) +
-                   4 * (mode == DDC_CORR_BSAR && prune ? 1 : 0);
+                   4 * (mode == DDC_CORR_BSAR && prune ? 1 : 0) + 16 * (mode == DDC_CORR_BSAO ? 1 : 0);
   const int64_t nqc = std::min<int64_t>(nq, 32768);
   Variant v = fixed_variant(ix, nqc, prune);
+  {
+    ScanArgs la{};
+    la.nblocks = ix->NB; la.k_max = k_max; la.block_b = ix->B; la.res = mode == DDC_CORR_BSAR;
+    la.pq_m = mode == DDC_CORR_BSAO ? ix->pq_m : 0;
+    if (scan_lds_request(la, v[0]) > kMaxLds) v[0] = 4;
+  }
   {
     std::lock_guard<std::mutex> lk(ix->tune_mtx);
     auto it = ix->tuned.find(tune_class(nqc, nprobe_max, k_max, kind));
@@ -1365,6 +1583,65 @@ static void kmeans_assign(const float *d_Y, int64_t n, int Dp, const float *d_C,
   g.M = n; g.N = nlist; g.K = Dp; g.mode = 2; g.prec = 0;
   launch_gemm(g, s);
   launch_decode_argmin(d_key, n, d_assign, s);
+}
+
+// Upload the quantizer (axes, codebooks) and encode every packed slot on the GPU.
+static void pq_upload_encode(ddc_index *ix, hipStream_t s) {
+  const int M = ix->pq_m;
+  ix->d_pq_perm.alloc(ix->pq_perm.size() * 4);
+  ix->d_pq_books.alloc(ix->pq_books.size() * 4);
+  HIPC(hipMemcpyAsync(ix->d_pq_perm.p, ix->pq_perm.data(), ix->pq_perm.size() * 4, hipMemcpyHostToDevice, s));
+  HIPC(hipMemcpyAsync(ix->d_pq_books.p, ix->pq_books.data(), ix->pq_books.size() * 4, hipMemcpyHostToDevice, s));
+  ix->d_pq_codes.alloc(std::max<size_t>((size_t)ix->total_tiles * kTile * M, 16));
+  ix->d_pq_err.alloc(std::max<size_t>((size_t)ix->total_tiles * kTile * 4, 16));
+  launch_pq_encode(ix->d_base.p, ix->store(), ix->NB, ix->total_tiles, ix->d_pq_perm.as<int32_t>(),
+                   ix->d_pq_books.as<float>(), M, ix->pq_dsub, ix->d_pq_codes.as<uint8_t>(),
+                   ix->d_pq_err.as<float>(), s);
+  HIPC(hipGetLastError());
+  HIPC(hipStreamSynchronize(s));
+}
+
+// Codebooks of the quantization estimate: OPQ eigenvalue allocation of the PCA axes, then
+// Lloyd k-means with 256 codewords in every subspace over the same key-sampled stored rows
+// (initial codewords: the training rows with the smallest keys).
+static void pq_train(ddc_index *ix, const float *d_Y, int M, int iters, int64_t ntrain, uint64_t seed,
+                     hipStream_t s) {
+  const int ds = ix->D / M;
+  constexpr int K = 256;
+  ix->pq_m = M;
+  ix->pq_dsub = ds;
+  ix->pq_perm = opq_allocation(ix->lam, M);
+  const std::vector<int64_t> rows = select_by_key(ix->n, std::min<int64_t>(ix->n, ntrain), seed, TAG_PQ_SAMPLE);
+  const int64_t ntr = (int64_t)rows.size();
+  const std::vector<int64_t> init = select_by_key(ntr, K, seed, TAG_KMEANS_INIT);
+  DevBuf d_rows(ntr * 8), d_cols((size_t)ds * 4), d_T((size_t)ntr * ds * 4), d_C((size_t)K * ds * 4),
+      d_cn(K * 4), d_key(ntr * 8), d_as(ntr * 4), d_off((K + 1) * 4), d_mem(ntr * 4);
+  HIPC(hipMemcpyAsync(d_rows.p, rows.data(), ntr * 8, hipMemcpyHostToDevice, s));
+  std::vector<int32_t> asg(ntr), off(K + 1), mem(ntr), fill(K);
+  ix->pq_books.assign((size_t)M * K * ds, 0.f);
+  for (int j = 0; j < M; ++j) {
+    HIPC(hipMemcpyAsync(d_cols.p, &ix->pq_perm[(size_t)j * ds], (size_t)ds * 4, hipMemcpyHostToDevice, s));
+    launch_gather_cols(d_Y, ix->Dp, d_rows.as<int64_t>(), ntr, d_cols.as<int32_t>(), ds, d_T.as<float>(), s);
+    gather_rows(d_T.as<float>(), ds, init, ds, d_C.as<float>(), ds, s);
+    for (int it = 0; it < iters; ++it) {
+      kmeans_assign(d_T.as<float>(), ntr, ds, d_C.as<float>(), K, d_cn.as<float>(),
+                    d_key.as<unsigned long long>(), d_as.as<int32_t>(), s);
+      HIPC(hipMemcpyAsync(asg.data(), d_as.p, ntr * 4, hipMemcpyDeviceToHost, s));
+      HIPC(hipStreamSynchronize(s));
+      std::fill(off.begin(), off.end(), 0);
+      for (int64_t i = 0; i < ntr; ++i) off[asg[i] + 1]++;
+      for (int c = 0; c < K; ++c) off[c + 1] += off[c];
+      for (int c = 0; c < K; ++c) fill[c] = off[c];
+      for (int64_t i = 0; i < ntr; ++i) mem[fill[asg[i]]++] = (int32_t)i;
+      HIPC(hipMemcpyAsync(d_off.p, off.data(), off.size() * 4, hipMemcpyHostToDevice, s));
+      HIPC(hipMemcpyAsync(d_mem.p, mem.data(), ntr * 4, hipMemcpyHostToDevice, s));
+      launch_centroid_update(d_T.as<float>(), ds, ds, d_off.as<int32_t>(), d_mem.as<int32_t>(), K,
+                             d_C.as<float>(), ds, s);
+    }
+    HIPC(hipMemcpyAsync(&ix->pq_books[(size_t)j * K * ds], d_C.p, (size_t)K * ds * 4, hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+  }
+  HIPC(hipGetLastError());
 }
 
 extern "C" ddc_status ddc_fit(const float *base, int64_t n, int32_t dim, const float *calib,
@@ -1504,6 +1781,10 @@ extern "C" ddc_status ddc_fit(const float *base, int64_t n, int32_t dim, const f
   d_key.release();
 
   upload_index(ix.get(), d_Y.as<float>(), s);
+  if (p->pq_m) {
+    pq_train(ix.get(), d_Y.as<float>(), p->pq_m, p->pq_iters, p->pq_train, p->seed, s);
+    pq_upload_encode(ix.get(), s);
+  }
   d_Y.release();
 
   // F5: calibration of the correction table

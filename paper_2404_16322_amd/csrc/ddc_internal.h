@@ -53,6 +53,15 @@ struct ScanArgs {
   const float *xnorm;      // [tiles * 64] ||y||^2 of every stored slot
   const float *lam;        // [nblocks * 32] variance along every rotated axis (0 beyond D)
   float bsar_m;            // multiplier m of m sigma
+  // quantization test of BSA-O before the stages (pq_m > 0): codes [tiles * 64][pq_m] bytes,
+  // per-slot quantization error, codebooks [pq_m][256][pq_dsub], subspace axes [pq_m * pq_dsub],
+  // per-table (m1, m3, beta, unused) at pq_tab[4 t]
+  const uint8_t *pq_codes;
+  const float *pq_err;
+  const float *pq_books;
+  const int32_t *pq_perm;
+  const float *pq_tab;
+  int32_t pq_m, pq_dsub;
   int32_t est_nb;          // > 0 (with prune = 0): rank by an estimate over the leading est_nb
                            // dim blocks, no refinement (needs xnorm when est_res)
   int32_t est_res;         // estimate: 0 = est_scale * partial distance, 1 = residual (Alg. 1)
@@ -70,6 +79,8 @@ struct ScanArgs {
 };
 
 void launch_scan(const ScanArgs &a, int store, hipStream_t s);
+// LDS bytes one workgroup of the scan needs with W waves per query (> kMaxLds: not launchable).
+size_t scan_lds_request(const ScanArgs &a, int W);
 
 // Query order for cache locality: queries grouped by their first probed list (counting sort,
 // order within a group arbitrary).  hist: [nlist + 1] scratch, rank: [nq] scratch.
@@ -152,6 +163,23 @@ void launch_features8(const double *qrot, int32_t D, const uint8_t *codes, const
 void launch_features64(const double *qrot, int32_t D, const void *base, int store, int32_t nblocks,
                        const int32_t *pair_q, const int64_t *pair_slot, int64_t npairs,
                        const int32_t *stage_end_block, int32_t n_test, double *out, hipStream_t s);
+// ---- OPQ / PQ kernels of the quantization estimate (k_pq.hip) ----
+// out[r][t] = Y[rows[r]][cols[t]]  (t < ncols)
+void launch_gather_cols(const float *Y, int64_t ldy, const int64_t *rows, int64_t nrows,
+                        const int32_t *cols, int32_t ncols, float *out, hipStream_t s);
+// Codes of every packed slot: codes[slot][j] = argmin_c ||y_j - books[j][c]||^2 in FP32 with
+// every operation rounded separately (differences, squares, sums in axis order; lowest c on
+// ties); err[slot] = FP32 sum over j of the minima.
+void launch_pq_encode(const void *base, int store, int32_t nblocks, int64_t total_tiles,
+                      const int32_t *perm, const float *books, int32_t M, int32_t dsub,
+                      uint8_t *codes, float *err, hipStream_t s);
+// FP64 features of (query, slot) pairs: adc = sum_j ||q'_j - books[j][code_j]||^2 and
+// err = sum_j ||y_j - books[j][code_j]||^2 (y from the packed base).
+void launch_pq_features64(const double *qrot, int32_t D, const void *base, int store,
+                          int32_t nblocks, const int32_t *perm, const float *books, int32_t M,
+                          int32_t dsub, const uint8_t *codes, const int32_t *pair_q,
+                          const int64_t *pair_slot, int64_t npairs, double *adc, double *err,
+                          hipStream_t s);
 // FP64 centroid distances for probe ordering of calibration queries.
 void launch_cdist64(const double *qrot, int64_t nq, int32_t D, const float *cent, int64_t ldc,
                     int32_t nlist, double *out, hipStream_t s);

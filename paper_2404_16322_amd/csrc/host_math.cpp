@@ -5,6 +5,7 @@
 #include <cmath>
 #include <limits>
 #include <numeric>
+#include <stdexcept>
 
 namespace ddc {
 
@@ -184,73 +185,87 @@ bool sym_eig_desc(const std::vector<double> &Ain, int n, std::vector<double> &la
 }
 
 // ---------------------------------------------------------------------------------------
-void logistic_fit(const std::vector<double> &F, const std::vector<double> &y, double &b, double &w1,
-                  double &w2) {
+void logistic_fit_p(const std::vector<double> &F, int p, const std::vector<double> &y, double &b,
+                    std::vector<double> &wout) {
+  if (p < 1 || p > 3) throw std::invalid_argument("logistic_fit_p: 1..3 features");
   const size_t n = y.size();
-  double mean[2] = {0, 0}, sd[2] = {0, 0};
-  for (size_t i = 0; i < n; ++i) { mean[0] += F[2 * i]; mean[1] += F[2 * i + 1]; }
-  mean[0] /= n; mean[1] /= n;
-  for (size_t i = 0; i < n; ++i) {
-    sd[0] += (F[2 * i] - mean[0]) * (F[2 * i] - mean[0]);
-    sd[1] += (F[2 * i + 1] - mean[1]) * (F[2 * i + 1] - mean[1]);
-  }
-  for (int j = 0; j < 2; ++j) {
+  const int q = p + 1;   // intercept + features
+  double mean[3] = {0, 0, 0}, sd[3] = {0, 0, 0};
+  for (size_t i = 0; i < n; ++i)
+    for (int j = 0; j < p; ++j) mean[j] += F[p * i + j];
+  for (int j = 0; j < p; ++j) mean[j] /= n;
+  for (size_t i = 0; i < n; ++i)
+    for (int j = 0; j < p; ++j) sd[j] += (F[p * i + j] - mean[j]) * (F[p * i + j] - mean[j]);
+  for (int j = 0; j < p; ++j) {
     sd[j] = std::sqrt(sd[j] / n);
     if (sd[j] == 0) sd[j] = 1.0;
   }
   const double ridge = 1e-8;
-  double w[3] = {0, 0, 0};
+  double w[4] = {0, 0, 0, 0};
   for (int it = 0; it < 100; ++it) {
-    double g[3] = {0, 0, 0}, H[3][3] = {{0}};
+    double g[4] = {0, 0, 0, 0}, H[4][4] = {{0}};
     for (size_t i = 0; i < n; ++i) {
-      const double z[3] = {1.0, (F[2 * i] - mean[0]) / sd[0], (F[2 * i + 1] - mean[1]) / sd[1]};
-      const double t = w[0] + w[1] * z[1] + w[2] * z[2];
+      double z[4] = {1.0, 0, 0, 0};
+      for (int j = 0; j < p; ++j) z[j + 1] = (F[p * i + j] - mean[j]) / sd[j];
+      double t = w[0];
+      for (int j = 1; j < q; ++j) t += w[j] * z[j];
       const double pr = 0.5 * (1.0 + std::tanh(0.5 * t));
       const double r = pr - y[i], wt = pr * (1.0 - pr);
-      for (int a = 0; a < 3; ++a) {
+      for (int a = 0; a < q; ++a) {
         g[a] += z[a] * r;
-        for (int c = 0; c < 3; ++c) H[a][c] += wt * z[a] * z[c];
+        for (int c = 0; c < q; ++c) H[a][c] += wt * z[a] * z[c];
       }
     }
-    for (int a = 0; a < 3; ++a) {
+    for (int a = 0; a < q; ++a) {
       g[a] /= n;
-      for (int c = 0; c < 3; ++c) H[a][c] /= n;
+      for (int c = 0; c < q; ++c) H[a][c] /= n;
     }
-    for (int a = 1; a < 3; ++a) { g[a] += ridge * w[a]; H[a][a] += ridge; }
+    for (int a = 1; a < q; ++a) { g[a] += ridge * w[a]; H[a][a] += ridge; }
     // solve H x = g (Gaussian elimination with partial pivoting)
-    double M[3][4];
-    for (int a = 0; a < 3; ++a) {
-      for (int c = 0; c < 3; ++c) M[a][c] = H[a][c];
-      M[a][3] = g[a];
+    double M[4][5];
+    for (int a = 0; a < q; ++a) {
+      for (int c = 0; c < q; ++c) M[a][c] = H[a][c];
+      M[a][q] = g[a];
     }
-    for (int col = 0; col < 3; ++col) {
+    for (int col = 0; col < q; ++col) {
       int piv = col;
-      for (int r = col + 1; r < 3; ++r)
+      for (int r = col + 1; r < q; ++r)
         if (std::fabs(M[r][col]) > std::fabs(M[piv][col])) piv = r;
       if (piv != col)
-        for (int c = 0; c < 4; ++c) std::swap(M[col][c], M[piv][c]);
+        for (int c = 0; c <= q; ++c) std::swap(M[col][c], M[piv][c]);
       const double dv = M[col][col] != 0 ? M[col][col] : 1e-300;
-      for (int r = col + 1; r < 3; ++r) {
+      for (int r = col + 1; r < q; ++r) {
         const double f = M[r][col] / dv;
-        for (int c = col; c < 4; ++c) M[r][c] -= f * M[col][c];
+        for (int c = col; c <= q; ++c) M[r][c] -= f * M[col][c];
       }
     }
-    double x[3];
-    for (int r = 2; r >= 0; --r) {
-      double s = M[r][3];
-      for (int c = r + 1; c < 3; ++c) s -= M[r][c] * x[c];
-      x[r] = s / (M[r][r] != 0 ? M[r][r] : 1e-300);
+    double x[4];
+    for (int r = q - 1; r >= 0; --r) {
+      double s2 = M[r][q];
+      for (int c = r + 1; c < q; ++c) s2 -= M[r][c] * x[c];
+      x[r] = s2 / (M[r][r] != 0 ? M[r][r] : 1e-300);
     }
     double mx = 0;
-    for (int a = 0; a < 3; ++a) {
+    for (int a = 0; a < q; ++a) {
       w[a] -= x[a];
       mx = std::max(mx, std::fabs(x[a]));
     }
     if (mx < 1e-12) break;
   }
-  w1 = w[1] / sd[0];
-  w2 = w[2] / sd[1];
-  b = w[0] - w[1] * mean[0] / sd[0] - w[2] * mean[1] / sd[1];
+  wout.assign(p, 0.0);
+  b = w[0];
+  for (int j = 0; j < p; ++j) {
+    wout[j] = w[j + 1] / sd[j];
+    b -= w[j + 1] * mean[j] / sd[j];
+  }
+}
+
+void logistic_fit(const std::vector<double> &F, const std::vector<double> &y, double &b, double &w1,
+                  double &w2) {
+  std::vector<double> w;
+  logistic_fit_p(F, 2, y, b, w);
+  w1 = w[0];
+  w2 = w[1];
 }
 
 std::vector<double> beta_for_alpha(const std::vector<double> &G, int64_t n0, int st, double alpha,
@@ -335,6 +350,38 @@ void haar_rotation(int D, uint64_t seed, std::vector<double> &R) {
     const double sg = Z[(size_t)j * D + j] < 0 ? -1.0 : 1.0;
     for (int i = 0; i < D; ++i) R[(size_t)j * D + i] = sg * Q[(size_t)i * D + j];
   }
+}
+
+std::vector<int32_t> opq_allocation(const std::vector<double> &lam, int M) {
+  const int D = (int)lam.size();
+  if (M < 1 || D % M) throw std::invalid_argument("opq_allocation: M must divide D");
+  const int dsub = D / M;
+  double mx = 0;
+  for (double v : lam) mx = std::max(mx, v);
+  const double floor_v = mx > 0 ? mx * 1e-12 : 1e-300;
+  std::vector<double> ll(D);
+  double mean = 0;
+  for (int i = 0; i < D; ++i) { ll[i] = std::log(std::max(lam[i], floor_v)); mean += ll[i]; }
+  mean /= D;
+  for (int i = 0; i < D; ++i) ll[i] -= mean;
+  std::vector<int> order(D);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return lam[a] > lam[b]; });
+  std::vector<double> logp(M, 0.0);
+  std::vector<std::vector<int32_t>> mem(M);
+  for (int i : order) {
+    int best = -1;
+    for (int j = 0; j < M; ++j)
+      if ((int)mem[j].size() < dsub && (best < 0 || logp[j] < logp[best])) best = j;
+    mem[best].push_back(i);
+    logp[best] += ll[i];
+  }
+  std::vector<int32_t> perm((size_t)D);
+  for (int j = 0; j < M; ++j) {
+    std::sort(mem[j].begin(), mem[j].end());
+    for (int t = 0; t < dsub; ++t) perm[(size_t)j * dsub + t] = mem[j][t];
+  }
+  return perm;
 }
 
 }  // namespace ddc

@@ -16,7 +16,13 @@ uint64_t ctr_key(uint64_t seed, uint64_t tag, uint64_t i);
 std::vector<int64_t> select_by_key(int64_t n, int64_t m, uint64_t seed, uint64_t tag);
 
 enum : uint64_t { TAG_PCA = 1, TAG_KMEANS_INIT = 2, TAG_KMEANS_SAMPLE = 3, TAG_NEG = 4, TAG_CALIB = 5,
-                  TAG_HAAR = 6 };
+                  TAG_HAAR = 6, TAG_PQ_SAMPLE = 7 };
+
+// OPQ eigenvalue allocation: the axes (eigenvalues lam, largest first) dealt to M subspaces of
+// D/M axes, each to the non-full subspace with the smallest product of its eigenvalues over
+// their geometric mean (lowest index on ties); perm[j * D/M + t] = axis t of subspace j,
+// ascending within a subspace.
+std::vector<int32_t> opq_allocation(const std::vector<double> &lam, int M);
 
 // A Haar-distributed random rotation (Mezzadri 2007): Householder QR of a D x D matrix of
 // standard normals (Box-Muller over pairs of counter keys, row-major), every column of Q
@@ -36,6 +42,9 @@ bool sym_eig_desc(const std::vector<double> &A, int n, std::vector<double> &lam,
 // Returns b, w1, w2 in the original units.
 void logistic_fit(const std::vector<double> &F, const std::vector<double> &y, double &b,
                   double &w1, double &w2);
+// The same for p = 1..3 features (F: n x p, row-major): w[p] in the original units.
+void logistic_fit_p(const std::vector<double> &F, int p, const std::vector<double> &y, double &b,
+                    std::vector<double> &w);
 
 // beta_s(alpha) from the label-0 residual matrix G (n0 x st, row-major); mode 0 = joint,
 // 1 = per-stage alpha / st.  alpha <= 0 -> -inf.

@@ -134,15 +134,18 @@ __device__ inline unsigned long long lane_mask_lt() {
 // buffer), the block's survivors and two survivor counters; per wave two alive lists of the
 // staged scan and the per-dim-block test table (m, beta; beta = -inf where no test follows).
 struct Lds {
-  size_t q, td, ti, sd, si, cnt, query_bytes;
+  size_t q, td, ti, sd, si, cnt, lut, query_bytes;
   size_t ac, ae, ap, mb, wave_bytes;
 };
 __host__ __device__ inline size_t align16(size_t b) { return (b + 15) & ~(size_t)15; }
-// res: the alive lists also carry each survivor's running sum of squared coordinates
-__host__ __device__ inline Lds lds_layout(int Dp, int kmax, int block_b, int W, bool res) {
+// res: the alive lists also carry each survivor's running sum of squared coordinates;
+// lut_floats: the query's quantization lookup table (BSA-O), 0 when unused
+__host__ __device__ inline Lds lds_layout(int Dp, int kmax, int block_b, int W, bool res,
+                                          int lut_floats) {
   Lds l;
   size_t o = 0;
   l.q = o; o += align16((size_t)Dp * 4);
+  l.lut = o; o += align16((size_t)lut_floats * 4);
   l.td = o; o += align16((size_t)2 * kmax * 4);
   l.ti = o; o += align16((size_t)2 * kmax * 4);
   l.sd = o; o += align16((size_t)block_b * 4);
@@ -158,8 +161,9 @@ __host__ __device__ inline Lds lds_layout(int Dp, int kmax, int block_b, int W, 
   l.wave_bytes = o;
   return l;
 }
-__host__ __device__ inline size_t scan_lds_bytes(int Dp, int kmax, int block_b, int W, bool res) {
-  const Lds l = lds_layout(Dp, kmax, block_b, W, res);
+__host__ __device__ inline size_t scan_lds_bytes(int Dp, int kmax, int block_b, int W, bool res,
+                                                  int lut_floats) {
+  const Lds l = lds_layout(Dp, kmax, block_b, W, res, lut_floats);
   return (size_t)(4 / W) * l.query_bytes + 4 * l.wave_bytes;
 }
 
@@ -170,8 +174,10 @@ __host__ __device__ inline size_t scan_lds_bytes(int Dp, int kmax, int block_b, 
 // test of Alg. 2 instead of the learned one (one stage per load).  EST (with PRUNE off): rank
 // every candidate by an estimate over the leading est_nb dim blocks instead of its distance
 // (no refinement): est_scale * e_d, or with est_res the residual estimate of Alg. 1
-// e_d + ||x_r||^2 + ||q'_r||^2 (C1 - C2).
-template <int ST, bool PRUNE, bool LOOK, int W, bool PRE, bool RES, bool EST = false>
+// e_d + ||x_r||^2 + ||q'_r||^2 (C1 - C2).  PQ: the quantization test of BSA-O (asymmetric
+// distance from the query's lookup table in LDS and the candidate's codes, with its
+// quantization error as second feature) before the stages, whose tests are then lossless.
+template <int ST, bool PRUNE, bool LOOK, int W, bool PRE, bool RES, bool EST = false, bool PQ = false>
 __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4, 8))) void scan_kernel(ScanArgs a) {
   using S = Store<ST>;
   constexpr int EPL = 16 / S::kBytes;          // elements per lane load
@@ -201,7 +207,7 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
   const int B = a.block_b;
   const int KM = a.k_max;
   const int SEG = W == 1 ? B : kTile;
-  const Lds L = lds_layout(Dp, KM, B, W, RES);
+  const Lds L = lds_layout(Dp, KM, B, W, RES, PQ ? a.pq_m * 256 : 0);
   unsigned char *ql = smem + (size_t)qs * L.query_bytes;
   unsigned char *wl = smem + (size_t)QPW * L.query_bytes + (size_t)wave * L.wave_bytes;
   float *s_q = reinterpret_cast<float *>(ql + L.q);
@@ -214,6 +220,7 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
   float *s_ae = reinterpret_cast<float *>(wl + L.ae);
   float *s_ap = reinterpret_cast<float *>(wl + L.ap);
   float *s_mb = reinterpret_cast<float *>(wl + L.mb);
+  float *s_lut = reinterpret_cast<float *>(ql + L.lut);
 
   // statistics (wave-uniform, flushed once when counters are requested)
   int64_t st_cand = 0, st_ref = 0, st_slices = 0, st_pre = 0, st_pre_pruned = 0;
@@ -255,6 +262,7 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
   const int qt = wsub * 64 + lane;             // thread index within the query's waves
   for (int i = qt; i < Dp; i += 64 * W) s_q[i] = qg[i];
   if (qt < 2) s_cnt[qt] = 0;
+  float pq_m1 = 0.f, pq_m3 = 0.f, pq_beta = -INFINITY;
   if (PRUNE && !RES) {
     // this query's correction table (by its K) into the wave's LDS
     int tsel = 0;
@@ -262,8 +270,28 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
       if (K >= a.tab_k[t]) tsel = t;
     const float *tq = a.tab + (size_t)tsel * (nb + 1) * 2;
     for (int i = lane; i < 2 * (nb + 1); i += 64) s_mb[i] = tq[i];
+    if (PQ) {
+      pq_m1 = a.pq_tab[4 * tsel];
+      pq_m3 = a.pq_tab[4 * tsel + 1];
+      pq_beta = a.pq_tab[4 * tsel + 2];
+    }
   }
   if (W > 1) __syncthreads(); else __builtin_amdgcn_wave_barrier();
+  if (PQ) {
+    // lookup table lut[j][c] = ||q'_j - C_j[c]||^2 over the axes of subspace j
+    const int ds = a.pq_dsub;
+    for (int e = qt; e < a.pq_m * 256; e += 64 * W) {
+      const float *cw = a.pq_books + (int64_t)e * ds;
+      const int32_t *ax = a.pq_perm + (e >> 8) * ds;
+      float acc = 0.f;
+      for (int t = 0; t < ds; ++t) {
+        const float d = s_q[ax[t]] - cw[t];
+        acc = fmaf(d, d, acc);
+      }
+      s_lut[e] = acc;
+    }
+    if (W > 1) __syncthreads(); else __builtin_amdgcn_wave_barrier();
+  }
   const int nbe = EST ? a.est_nb : nb;           // dim blocks the no-test path reads
   float qres = 0.f;                              // EST: ||q'_r||^2 beyond the leading blocks
   if (EST) {
@@ -394,6 +422,44 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
         int nalive = slen;
         st_cand += slen;
         bool listed = false;   // the alive list holds pre-stage survivors (partial sums restart at 0)
+        if (PQ) {
+          // ---- quantization test (BSA-O): lane = candidate; its code bytes (8 per load) index
+          // the lookup table, the sum over subspaces is the asymmetric distance; prune iff
+          // m1 dis' + m3 err + beta > tau; survivors go to the alive list ----
+          const int tile0 = a.tile_off[lst] + (bs + s0) / kTile;   // wave-uniform
+          const int M = a.pq_m;
+          int nn = 0;
+          for (int t0 = 0; t0 < slen; t0 += kTile) {
+            const int idx = t0 + lane;
+            const int64_t slot = (int64_t)(tile0 + t0 / kTile) * kTile + lane;   // in the tile: in bounds
+            const uint2 *cp = reinterpret_cast<const uint2 *>(a.pq_codes + slot * M);
+            float adc = 0.f;
+            for (int c8 = 0; c8 < M / 8; ++c8) {
+              const uint2 w = cp[c8];
+              const int j0 = c8 * 8 * 256;
+#pragma unroll
+              for (int e = 0; e < 4; ++e) adc += s_lut[j0 + e * 256 + ((w.x >> (8 * e)) & 255u)];
+#pragma unroll
+              for (int e = 0; e < 4; ++e) adc += s_lut[j0 + (4 + e) * 256 + ((w.y >> (8 * e)) & 255u)];
+            }
+            const float er = a.pq_err[slot];
+            const bool valid = idx < slen;
+            const bool prune = valid && fmaf(pq_m1, adc, fmaf(pq_m3, er, pq_beta)) > tau;
+            const bool keep = valid && !prune;
+            const unsigned long long bal = __ballot(keep);
+            if (keep) {
+              const int pos = nn + __popcll(bal & lt);
+              s_ac[pos] = (uint16_t)idx;
+              s_ae[pos] = 0.f;
+            }
+            nn += __popcll(bal);
+            st_pre_pruned += __popcll(__ballot(prune));
+          }
+          st_pre += slen;
+          __builtin_amdgcn_wave_barrier();
+          nalive = nn;
+          listed = true;
+        }
         if (PRE) {
           // ---- FP8 pre-stage: one 64-byte code slice per candidate, decoded with the tile's
           // scale; survivors go to the alive list and the stages start over at dim 0 ----
@@ -713,7 +779,7 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
     atomicAdd(&ctr[0], (unsigned long long)st_cand);
     atomicAdd(&ctr[1], (unsigned long long)st_ref);
     atomicAdd(&ctr[2], (unsigned long long)st_slices);
-    if (PRE) {
+    if (PRE || PQ) {
       atomicAdd(&ctr[kCtrPreReads], (unsigned long long)st_pre);
       atomicAdd(&ctr[kCtrPrePruned], (unsigned long long)st_pre_pruned);
     }
@@ -811,19 +877,26 @@ static int resident_workgroups(const void *kern, size_t smem) {
   return r;
 }
 
-template <int ST, bool P, bool LK, int W, bool PRE = false, bool RES = false, bool EST = false>
+size_t scan_lds_request(const ScanArgs &a, int W) {
+  return scan_lds_bytes(a.nblocks * kBlockDims, a.k_max, a.block_b, W, a.res != 0,
+                        a.pq_m > 0 ? a.pq_m * 256 : 0);
+}
+
+template <int ST, bool P, bool LK, int W, bool PRE = false, bool RES = false, bool EST = false,
+          bool PQ = false>
 static void launch_variant(const ScanArgs &a, hipStream_t s) {
-  const size_t smem = scan_lds_bytes(a.nblocks * kBlockDims, a.k_max, a.block_b, W, RES);
+  const size_t smem = scan_lds_bytes(a.nblocks * kBlockDims, a.k_max, a.block_b, W, RES,
+                                     PQ ? a.pq_m * 256 : 0);
   if (smem > kMaxLds) throw std::runtime_error("scan: LDS request exceeds 160 KiB");
   const int qpw = 4 / W;
-  const void *kern = reinterpret_cast<const void *>(&scan_kernel<ST, P, LK, W, PRE, RES, EST>);
+  const void *kern = reinterpret_cast<const void *>(&scan_kernel<ST, P, LK, W, PRE, RES, EST, PQ>);
   int64_t grid = (a.nq + qpw - 1) / qpw;
   if (a.queue) {
     // W = 1: each wave takes its own slots, so the grid covers ceil(nq / 4) workgroups at most
     grid = std::min<int64_t>(grid, resident_workgroups(kern, smem));
     hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(64), 0, s, a.queue, (int64_t)1, 0);
   }
-  hipLaunchKernelGGL((scan_kernel<ST, P, LK, W, PRE, RES, EST>), dim3((unsigned)grid),
+  hipLaunchKernelGGL((scan_kernel<ST, P, LK, W, PRE, RES, EST, PQ>), dim3((unsigned)grid),
                      dim3(kScanThreads), smem, s, a);
 }
 
@@ -834,6 +907,14 @@ template <int ST> static void launch_store(const ScanArgs &a, hipStream_t s) {
     else launch_variant<ST, false, false, 1, false, false, true>(a, s);
   } else if (!a.prune) {
     if (w4) launch_variant<ST, false, false, 4>(a, s); else launch_variant<ST, false, false, 1>(a, s);
+  } else if (a.pq_m > 0) {
+    if (a.lookahead) {
+      if (w4) launch_variant<ST, true, true, 4, false, false, false, true>(a, s);
+      else launch_variant<ST, true, true, 1, false, false, false, true>(a, s);
+    } else {
+      if (w4) launch_variant<ST, true, false, 4, false, false, false, true>(a, s);
+      else launch_variant<ST, true, false, 1, false, false, false, true>(a, s);
+    }
   } else if (a.res) {
     if (w4) launch_variant<ST, true, false, 4, false, true>(a, s); else launch_variant<ST, true, false, 1, false, true>(a, s);
   } else if (a.pre) {

@@ -144,7 +144,15 @@ struct ddc_index {
   int64_t total_tiles = 0;
   // correction tables, ascending calibration K_c; a search with K uses the last with
   // kc <= K (the first when none): m [Tt], resid [n0 x Tt] (label-0 residuals)
-  struct Table { int kc = 1; std::vector<double> m, resid; int64_t n0 = 0; };
+  // pq: the BSA-O classifier m1 dis' + m3 err + beta > tau of the same label-0/1 pairs, with
+  // the label-0 residuals tau - m1 dis' - m3 err (empty: no BSA-O table)
+  struct Table {
+    int kc = 1;
+    std::vector<double> m, resid;
+    int64_t n0 = 0;
+    double pq_m1 = 1.0, pq_m3 = 0.0;
+    std::vector<double> pq_resid;
+  };
   std::vector<Table> tables;
   int64_t n0_total() const {
     int64_t t = 0;
@@ -160,6 +168,12 @@ struct ddc_index {
   double bsar_m = 8.0;              // multiplier of the residual test (<= 0: from the significance)
   ddc::DevBuf d_xnorm, d_lam32;     // ||y||^2 per stored slot; eigenvalues (Dp, zero padded)
   ddc::DevBuf d_base8, d_scale8;    // its codes (tiles x 64 x 64 B) and per-tile scales
+  // quantization estimate (BSA-O): OPQ subspaces of the rotated axes, 256 codewords each
+  int pq_m = 0, pq_dsub = 0;
+  std::vector<int32_t> pq_perm;     // [D] axes of subspace j at [j * dsub, (j + 1) * dsub)
+  std::vector<float> pq_books;      // [M x 256 x dsub]
+  ddc::DevBuf d_pq_perm, d_pq_books, d_pq_codes, d_pq_err;   // codes [tiles x 64 x M], err [tiles x 64]
+  bool pq_tables() const { return pq_m > 0 && !tables.empty() && !tables[0].pq_resid.empty(); }
   int P() const { return fp8 ? 1 : 0; }
   int Tt() const { return St + P(); }   // columns of the correction table
   // optional per-kernel event timing

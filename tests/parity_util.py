@@ -26,11 +26,12 @@ def workload(name, n=None, nq=None, n_calib=None, n_val=None, D=None):
 
 @functools.lru_cache(maxsize=None)
 def oracle_index(name="gauss128", nlist=64, storage="f32", delta_d=32, B=256, n=None, n_calib=None,
-                 calib_k=10, calib_nprobe=8, D=None, kmeans_iters=25, seed=7, fp8_lead=0):
+                 calib_k=10, calib_nprobe=8, D=None, kmeans_iters=25, seed=7, fp8_lead=0, pq_m=0,
+                 calib_k_extra=()):
     w = workload(name, n=n, n_calib=n_calib, D=D)
     ix = O.fit(w["base"], w["calib"], nlist=nlist, delta_d=delta_d, storage=storage,
                kmeans_iters=kmeans_iters, calib_k=calib_k, calib_nprobe=calib_nprobe, B=B, seed=seed,
-               fp8_lead=fp8_lead)
+               fp8_lead=fp8_lead, pq_m=pq_m, pq_iters=8, calib_k_extra=calib_k_extra)
     # centroids handed to the GPU in float32: the oracle uses the same float32 values
     ix["centroids"] = ix["centroids"].astype(np.float32).astype(np.float64)
     return ix
@@ -42,10 +43,18 @@ def artifacts(ix, with_table=True):
                storage=ix["storage"], delta_d=ix["delta_d"], block_b=ix["B"])
     if ix.get("pre") is not None:
         art["fp8_lead_dims"] = ix["pre"]["lead"]
+    if ix.get("pq") is not None:
+        art.update(pq_perm=ix["pq"]["perm"], pq_books=ix["pq"]["books"].astype(np.float32))
     if with_table:
         art.update(m=ix["m"], resid=ix["G"])
+        if ix.get("pq") is not None:
+            t0 = ix["pq_tab"]
+            art.update(pq_m1=t0["m1"], pq_m3=t0["m3"], pq_resid=t0["G"][:, 0])
         if ix.get("tables"):
             art["tables"] = [dict(kc=t["kc"], m=t["m"], resid=t["G"]) for t in ix["tables"]]
+            if ix.get("pq") is not None:
+                for d, t in zip(art["tables"], ix["tables"]):
+                    d.update(pq_m1=t["pq"]["m1"], pq_m3=t["pq"]["m3"], pq_resid=t["pq"]["G"][:, 0])
     return art
 
 

@@ -28,6 +28,13 @@ void hm_logit(const double *F, const double *y, long n, double *out) {
   std::vector<double> f(F, F + 2 * n), yy(y, y + n);
   ddc::logistic_fit(f, yy, out[0], out[1], out[2]);
 }
+void hm_logit3(const double *F, const double *y, long n, double *out) {
+  std::vector<double> f(F, F + 3 * n), yy(y, y + n), w;
+  ddc::logistic_fit_p(f, 3, yy, out[0], w); std::memcpy(out + 1, w.data(), 24);
+}
+void hm_opq(const double *lam, int D, int M, int *out) {
+  auto p = ddc::opq_allocation(std::vector<double>(lam, lam + D), M); std::memcpy(out, p.data(), D * 4);
+}
 void hm_beta(const double *G, long n0, int st, double alpha, int mode, double *out) {
   std::vector<double> g(G, G + n0 * st);
   auto b = ddc::beta_for_alpha(g, n0, st, alpha, mode); std::memcpy(out, b.data(), st * 8);
@@ -52,6 +59,8 @@ def hm(tmp_path_factory):
     lib.hm_eig.argtypes = [vp, C.c_int, vp, vp]
     lib.hm_logit.argtypes = [vp, vp, C.c_long, vp]
     lib.hm_beta.argtypes = [vp, C.c_long, C.c_int, C.c_double, C.c_int, vp]
+    lib.hm_logit3.argtypes = [vp, vp, C.c_long, vp]
+    lib.hm_opq.argtypes = [vp, C.c_int, C.c_int, vp]
     lib.hm_select.argtypes = [C.c_long, C.c_long, C.c_ulonglong, C.c_ulonglong, vp]
     lib.hm_select.restype = C.c_long
     return lib
@@ -99,3 +108,23 @@ def test_beta_and_key_selection_equal_oracle(hm):
     out = np.zeros(100, np.int64)
     k = hm.hm_select(5000, 100, 11, O.TAG_CALIB, out.ctypes.data)
     assert k == 100 and out.tolist() == O.select_by_key(5000, 100, 11, O.TAG_CALIB).tolist()
+
+
+def test_three_feature_logistic_fit_equals_oracle_irls(hm):
+    rng = np.random.default_rng(4)
+    n = 3000
+    F = np.column_stack([rng.gamma(2.0, 50.0, n), rng.gamma(1.5, 5.0, n), rng.gamma(3.0, 40.0, n)])
+    t = 0.05 * F[:, 0] + 0.1 * F[:, 1] - 0.04 * F[:, 2] + 0.3
+    y = (rng.random(n) < 1 / (1 + np.exp(-t))).astype(np.float64)
+    out = np.zeros(4)
+    hm.hm_logit3(np.ascontiguousarray(F).ctypes.data, y.ctypes.data, n, out.ctypes.data)
+    b, w = O.irls_logistic(F, y)
+    np.testing.assert_allclose(out, [b, *w], rtol=1e-7, atol=1e-10)
+
+
+def test_opq_allocation_equals_oracle(hm):
+    for lam, M in [(1.0 / np.arange(1, 129), 32), (np.arange(1, 961) ** -1.2, 120),
+                   (np.array([16.0, 8, 4, 2, 1, 1]), 3), (np.r_[np.ones(8), np.zeros(8)], 4)]:
+        out = np.zeros(lam.size, np.int32)
+        hm.hm_opq(np.ascontiguousarray(lam).ctypes.data, lam.size, M, out.ctypes.data)
+        assert out.reshape(M, -1).tolist() == O.opq_allocation(lam, M).tolist()
