@@ -183,8 +183,9 @@ def main():
                          "or absolute queries/s, as the workload defines)")
     ap.add_argument("--serve-seconds", type=float, default=3.0)
     ap.add_argument("--ablation", action="store_true",
-                    help="also sweep the residual test, lossless pruning, and a random rotation with "
-                         "the learned and the ADSampling tests at the operating nprobe")
+                    help="also sweep the residual test, lossless pruning, a random rotation with the "
+                         "learned and the ADSampling tests, and the OPQ estimate with its learned "
+                         "classifier (BSA-O) at the operating nprobe")
     ap.add_argument("--ood", action="store_true",
                     help="also search shifted queries with the fitted table, the residual test and a "
                          "table recalibrated on 100 of them")
@@ -514,6 +515,8 @@ def main():
                 cc = ctr.cpu().numpy()
                 pts.append(dict(knob=kb, recall=round(r, 4), qps=round(nq / ms * 1e3, 1),
                                 scanned_dim_ratio=round(int(cc[2]) / max(1, int(cc[0]) * NB), 4)))
+                if mode == "bsao":   # the paper's measure for the quantization estimate
+                    pts[-1]["pruned_rate"] = round(int(cc[69]) / max(1, int(cc[0])), 4)
             ok = [x for x in pts if x["recall"] >= 0.95]
             best = max(ok, key=lambda x: x["qps"]) if ok else max(pts, key=lambda x: x["recall"])
             log(f"[bench] ablation {label}: best {best}")
@@ -530,6 +533,15 @@ def main():
                                               lambda _: None, lambda a_: a_)
         ablation["haar_ads"] = sweep_mode("random rotation + ADSampling test", "ads",
                                           [0.5, 1.0, 1.5, 2.1, 3.0, 4.0], ix.set_ads_epsilon, lambda _: 0.0)
+        ix.close()
+        # OPQ estimate + learned classifier (BSA-O): M = D/4 subspaces (D/8 from 512 dims on, as
+        # the paper sets for GIST), 256 codewords each
+        pq_m = D // 8 if D >= 512 else D // 4
+        ix = Index.fit(w["base"], w["calib"], nlist=nlist, seed=spec["cfg"], storage=cfg["storage"],
+                       rotation=cfg["rotation"], pq_m=pq_m, **cfg.get("fit", {}))
+        ablation["opq_learned"] = sweep_mode(f"OPQ (M={pq_m}) + learned (BSA-O)", "bsao", ALPHAS,
+                                             lambda _: None, lambda a_: a_)
+        ablation["opq_learned"]["pq_m"] = pq_m
         ix.close()
         ix = ix_main
 
