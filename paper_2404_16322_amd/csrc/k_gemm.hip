@@ -37,8 +37,10 @@ __device__ inline unsigned short bf16_rne(float f) {
 }  // namespace
 
 __global__ __launch_bounds__(256) void gemm_nt_kernel(GemmArgs g) {
-  __shared__ __align__(16) float As[BM * LDA];
-  __shared__ __align__(16) float Bs[BN * LDA];
+  // two LDS stages: tile t is stored to stage t & 1 while the global loads of tile t + 1 are in
+  // flight, so one barrier per K step suffices (stage t & 1 was last read in step t - 2)
+  __shared__ __align__(16) float As[2][BM * LDA];
+  __shared__ __align__(16) float Bs[2][BN * LDA];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -52,8 +54,9 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(GemmArgs g) {
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-  for (int k0 = 0; k0 < g.K; k0 += BK) {
-    // stage A (minus mu) and B tiles: 64 rows x 32 k, 8 elements per thread each
+  // A (minus mu) and B tiles: 64 rows x 32 k each, 8 elements per thread each
+  float4 ra[2], rb[2];
+  auto load_tile = [&](int k0) {
     const bool vec = (g.lda % 4 == 0) && (g.ldb % 4 == 0) && (k0 + BK <= g.K);
 #pragma unroll
     for (int it = 0; it < 2; ++it) {
@@ -87,20 +90,36 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(GemmArgs g) {
         av = make_float4(ta[0], ta[1], ta[2], ta[3]);
         bv = make_float4(tb[0], tb[1], tb[2], tb[3]);
       }
-      *reinterpret_cast<float4 *>(&As[r * LDA + kc]) = av;
-      *reinterpret_cast<float4 *>(&Bs[r * LDA + kc]) = bv;
+      ra[it] = av;
+      rb[it] = bv;
+    }
+  };
+
+  load_tile(0);
+  int stage = 0;
+  for (int k0 = 0; k0 < g.K; k0 += BK, stage ^= 1) {
+    float *as = As[stage];
+    float *bs = Bs[stage];
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+      const int e = tid + it * 256;
+      const int r = e >> 3;
+      const int kc = (e & 7) * 4;
+      *reinterpret_cast<float4 *>(&as[r * LDA + kc]) = ra[it];
+      *reinterpret_cast<float4 *>(&bs[r * LDA + kc]) = rb[it];
     }
     __syncthreads();
+    if (k0 + BK < g.K) load_tile(k0 + BK);   // next tile's loads overlap this step's products
     if (g.prec == 0) {
 #pragma unroll
       for (int kk = 0; kk < BK; kk += 4) {
         float af[2], bf[2];
 #pragma unroll
         for (int i = 0; i < 2; ++i)
-          af[i] = As[(wr * 32 + i * 16 + (lane & 15)) * LDA + kk + (lane >> 4)];
+          af[i] = as[(wr * 32 + i * 16 + (lane & 15)) * LDA + kk + (lane >> 4)];
 #pragma unroll
         for (int j = 0; j < 2; ++j)
-          bf[j] = Bs[(wc * 32 + j * 16 + (lane & 15)) * LDA + kk + (lane >> 4)];
+          bf[j] = bs[(wc * 32 + j * 16 + (lane & 15)) * LDA + kk + (lane >> 4)];
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -111,7 +130,7 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(GemmArgs g) {
       bf16x8 af[2], bf[2];
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
-        const float *src = &As[(wr * 32 + i * 16 + (lane & 15)) * LDA + 8 * (lane >> 4)];
+        const float *src = &as[(wr * 32 + i * 16 + (lane & 15)) * LDA + 8 * (lane >> 4)];
         unsigned short h[8];
 #pragma unroll
         for (int t = 0; t < 8; ++t) h[t] = bf16_rne(src[t]);
@@ -119,7 +138,7 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(GemmArgs g) {
       }
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
-        const float *src = &Bs[(wc * 32 + j * 16 + (lane & 15)) * LDA + 8 * (lane >> 4)];
+        const float *src = &bs[(wc * 32 + j * 16 + (lane & 15)) * LDA + 8 * (lane >> 4)];
         unsigned short h[8];
 #pragma unroll
         for (int t = 0; t < 8; ++t) h[t] = bf16_rne(src[t]);
@@ -131,7 +150,6 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(GemmArgs g) {
         for (int j = 0; j < 2; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bf[j], acc[i][j], 0, 0, 0);
     }
-    __syncthreads();
   }
 
   // epilogue
