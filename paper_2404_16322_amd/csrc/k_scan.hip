@@ -133,19 +133,23 @@ __device__ inline unsigned long long lane_mask_lt() {
 // LDS: per query (shared by its W waves) the rotated query, two result queues (double
 // buffer), the block's survivors and two survivor counters; per wave two alive lists of the
 // staged scan and the per-dim-block test table (m, beta; beta = -inf where no test follows).
+// probe lists of a query staged in LDS (list id, length, first tile) when nprobe_max <= this
+constexpr int kMetaCap = 256;
+
 struct Lds {
-  size_t q, td, ti, sd, si, cnt, lut, query_bytes;
-  size_t ac, ae, ap, mb, wave_bytes;
+  size_t q, td, ti, sd, si, cnt, lut, meta, query_bytes;
+  size_t ac, ae, ap, mb, pr, wave_bytes;
 };
 __host__ __device__ inline size_t align16(size_t b) { return (b + 15) & ~(size_t)15; }
 // res: the alive lists also carry each survivor's running sum of squared coordinates;
 // lut_floats: the query's quantization lookup table (BSA-O), 0 when unused
 __host__ __device__ inline Lds lds_layout(int Dp, int kmax, int block_b, int W, bool res,
-                                          int lut_floats) {
+                                          int lut_floats, int p_stride) {
   Lds l;
   size_t o = 0;
   l.q = o; o += align16((size_t)Dp * 4);
   l.lut = o; o += align16((size_t)lut_floats * 4);
+  l.meta = o; o += p_stride <= kMetaCap ? align16((size_t)3 * p_stride * 4) : 0;
   l.td = o; o += align16((size_t)2 * kmax * 4);
   l.ti = o; o += align16((size_t)2 * kmax * 4);
   l.sd = o; o += align16((size_t)block_b * 4);
@@ -158,12 +162,13 @@ __host__ __device__ inline Lds lds_layout(int Dp, int kmax, int block_b, int W, 
   l.ae = o; o += align16((size_t)2 * seg * 4);
   l.ap = o; o += res ? align16((size_t)2 * seg * 4) : 0;
   l.mb = o; o += align16((size_t)2 * (Dp / kBlockDims + 1) * 4);
+  l.pr = o; o += 64 * 4;   // per-pair stage sums of a deep look-ahead round
   l.wave_bytes = o;
   return l;
 }
 __host__ __device__ inline size_t scan_lds_bytes(int Dp, int kmax, int block_b, int W, bool res,
-                                                  int lut_floats) {
-  const Lds l = lds_layout(Dp, kmax, block_b, W, res, lut_floats);
+                                                  int lut_floats, int p_stride) {
+  const Lds l = lds_layout(Dp, kmax, block_b, W, res, lut_floats, p_stride);
   return (size_t)(4 / W) * l.query_bytes + 4 * l.wave_bytes;
 }
 
@@ -207,7 +212,7 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
   const int B = a.block_b;
   const int KM = a.k_max;
   const int SEG = W == 1 ? B : kTile;
-  const Lds L = lds_layout(Dp, KM, B, W, RES, PQ ? a.pq_m * 256 : 0);
+  const Lds L = lds_layout(Dp, KM, B, W, RES, PQ ? a.pq_m * 256 : 0, a.p_stride);
   unsigned char *ql = smem + (size_t)qs * L.query_bytes;
   unsigned char *wl = smem + (size_t)QPW * L.query_bytes + (size_t)wave * L.wave_bytes;
   float *s_q = reinterpret_cast<float *>(ql + L.q);
@@ -220,7 +225,10 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
   float *s_ae = reinterpret_cast<float *>(wl + L.ae);
   float *s_ap = reinterpret_cast<float *>(wl + L.ap);
   float *s_mb = reinterpret_cast<float *>(wl + L.mb);
+  float *s_pr = reinterpret_cast<float *>(wl + L.pr);
   float *s_lut = reinterpret_cast<float *>(ql + L.lut);
+  const bool meta_lds = a.p_stride <= kMetaCap;
+  int32_t *s_ml = reinterpret_cast<int32_t *>(ql + L.meta);   // list ids, lengths, first tiles
 
   // statistics (wave-uniform, flushed once when counters are requested)
   int64_t st_cand = 0, st_ref = 0, st_slices = 0, st_pre = 0, st_pre_pruned = 0;
@@ -261,6 +269,17 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
   const float *qg = a.qrot + (int64_t)q * a.q_stride;
   const int qt = wsub * 64 + lane;             // thread index within the query's waves
   for (int i = qt; i < Dp; i += 64 * W) s_q[i] = qg[i];
+  if (meta_lds) {
+    // the query's probed lists and their lengths / first tiles, gathered once, so the list
+    // loop below reads them from LDS instead of two dependent trips to memory per list
+    for (int i = qt; i < np; i += 64 * W) {
+      const int l = a.probes[(int64_t)q * a.p_stride + i];
+      const bool ok = l >= 0 && l < a.nlist;
+      s_ml[i] = ok ? l : -1;
+      s_ml[a.p_stride + i] = ok ? a.list_len[l] : 0;
+      s_ml[2 * a.p_stride + i] = ok ? a.tile_off[l] : 0;
+    }
+  }
   if (qt < 2) s_cnt[qt] = 0;
   float pq_m1 = 0.f, pq_m3 = 0.f, pq_beta = -INFINITY;
   if (PRUNE && !RES) {
@@ -353,12 +372,20 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
   };
 
   for (int p = 0; p < np; ++p) {
-    const int lst = a.probes[(int64_t)q * a.p_stride + p];
+    int lst, len, toff;
+    if (meta_lds) {
+      lst = __builtin_amdgcn_readfirstlane(s_ml[p]);
+      len = __builtin_amdgcn_readfirstlane(s_ml[a.p_stride + p]);
+      toff = __builtin_amdgcn_readfirstlane(s_ml[2 * a.p_stride + p]);
+    } else {
+      lst = a.probes[(int64_t)q * a.p_stride + p];
+      len = (lst >= 0 && lst < a.nlist) ? a.list_len[lst] : 0;
+      toff = (lst >= 0 && lst < a.nlist) ? a.tile_off[lst] : 0;
+    }
     if (lst < 0 || lst >= a.nlist) continue;  // never follow an invalid list id
-    const int len = a.list_len[lst];
     const unsigned char *lbase = reinterpret_cast<const unsigned char *>(a.base) +
-                                 (int64_t)a.tile_off[lst] * nb * BLOCK_BYTES;  // wave-uniform
-    const int32_t *lids = a.ids + (int64_t)a.tile_off[lst] * kTile;
+                                 (int64_t)toff * nb * BLOCK_BYTES;  // wave-uniform
+    const int32_t *lids = a.ids + (int64_t)toff * kTile;
     for (int bs = 0; bs < len; bs += B) {
       const int blen = min(B, len - bs);
       ns = 0;
@@ -366,7 +393,7 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
       const int slen = W == 1 ? blen : min(kTile, blen - s0);
       const unsigned char *bbase = lbase + (int64_t)((bs + s0) / kTile) * nb * BLOCK_BYTES;
       const int32_t *bids = lids + bs + s0;
-      const float *xnorm_seg = (RES || EST) ? a.xnorm + (int64_t)a.tile_off[lst] * kTile + bs + s0 : nullptr;
+      const float *xnorm_seg = (RES || EST) ? a.xnorm + (int64_t)toff * kTile + bs + s0 : nullptr;
       // In a load group, chunk c, lane (sub, g) reads dims [g*EPL, g*EPL+EPL) of candidate
       // t0 + c*CPW + sub; after transpose_sum the lane owns candidate t0 + g*CPW + sub.
       if (!PRUNE || tn < K) {
@@ -426,7 +453,7 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
           // ---- quantization test (BSA-O): lane = candidate; its code bytes (8 per load) index
           // the lookup table, the sum over subspaces is the asymmetric distance; prune iff
           // m1 dis' + m3 err + beta > tau; survivors go to the alive list ----
-          const int tile0 = a.tile_off[lst] + (bs + s0) / kTile;   // wave-uniform
+          const int tile0 = toff + (bs + s0) / kTile;   // wave-uniform
           const int M = a.pq_m;
           int nn = 0;
           for (int t0 = 0; t0 < slen; t0 += kTile) {
@@ -468,7 +495,7 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
           float q8[16];
 #pragma unroll
           for (int e = 0; e < 16; ++e) q8[e] = s_q[g8 * 16 + e];
-          const int tile0 = a.tile_off[lst] + (bs + s0) / kTile;   // wave-uniform
+          const int tile0 = toff + (bs + s0) / kTile;   // wave-uniform
           const int last_tile = tile0 + (slen - 1) / kTile;
           int nn = 0;
           // two tiles per round trip: their loads are issued together; a second tile past the
@@ -527,6 +554,101 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
         }
         int b = 0;
         while (b < nb && nalive > 0) {
+          if (LOOK && nalive <= 8 && 64 / (nalive <= 1 ? 1 : nalive <= 2 ? 2 : nalive <= 4 ? 4 : 8) > G &&
+              nb - b > G) {
+            // ---- deep look-ahead: at most 8 live candidates; the 64 load slots of one round
+            // hold Lr = 64 / 2^ceil(log2 nalive) consecutive stages of every one of them, so a
+            // candidate walks up to 64 stages per memory round trip.  Slot p = c * CPW + sub
+            // loads (candidate p / Lr, stage b + p % Lr); after the transposed reduction lane
+            // (g, sub) holds slot g * CPW + sub, whose sum goes to LDS; lane i < nalive then
+            // adds its candidate's stage sums in stage order and takes every test as the
+            // one-stage path does, so results and counters are bit-identical to it.
+            const int P2 = nalive <= 1 ? 1 : nalive <= 2 ? 2 : nalive <= 4 ? 4 : 8;
+            const int Lr = 64 / P2;
+            const int lgLr = Lr == 64 ? 6 : Lr == 32 ? 5 : Lr == 16 ? 4 : 3;
+            const int Le = min(Lr, nb - b);
+            const uint16_t *alive = s_ac + cur * SEG;
+            const float *alive_e = s_ae + cur * SEG;
+            const bool direct = b == 0 && !listed;
+            const int first = direct ? 0 : (int)alive[0];
+            uint4 v[MAXCH];
+#pragma unroll
+            for (int c = 0; c < MAXCH; ++c) {
+              const int pp = c * CPW + sub;
+              const int ci = pp >> lgLr;
+              const int cd = ci < nalive ? (direct ? ci : (int)alive[ci]) : first;
+              const int bb = min(b + (pp & (Lr - 1)), nb - 1);
+              const uint32_t off = (uint32_t)((cd / kTile) * nb + bb) * (uint32_t)BLOCK_BYTES +
+                                   (uint32_t)((cd % kTile) * SLICE + g * 16);
+              v[c] = *reinterpret_cast<const uint4 *>(bbase + off);
+            }
+            float part[MAXCH];
+#pragma unroll
+            for (int c = 0; c < MAXCH; ++c) {
+              const int bb = min(b + ((c * CPW + sub) & (Lr - 1)), nb - 1);
+              float f[EPL];
+              S::unpack(v[c], f);
+              float acc = 0.f;
+#pragma unroll
+              for (int e = 0; e < EPL; ++e) {
+                const float d = f[e] - s_q[bb * kBlockDims + g * EPL + e];
+                acc = fmaf(d, d, acc);
+              }
+              part[c] = acc;
+            }
+            const float tot = transpose_sum<G>(part, g);
+            s_pr[g * CPW + sub] = tot;
+            __builtin_amdgcn_wave_barrier();
+            const bool mine = lane < nalive;
+            const int cand = mine ? (direct ? lane : (int)alive[lane]) : 0;
+            float ev = mine ? (direct ? 0.f : alive_e[lane]) : 0.f;
+            int stop = Le;          // first pruning stage in the window (Le: none)
+            if (mine) {
+              for (int st = 0; st < Le; ++st) {
+                ev += s_pr[lane * Lr + st];
+                const int bb = b + st;
+                if (fmaf(s_mb[2 * bb], ev, s_mb[2 * bb + 1]) > tau) { stop = st; break; }
+              }
+            }
+            const bool survive = mine && stop == Le;
+            // slices read up to each candidate's stopping stage
+            {
+              int cnt = mine ? (stop < Le ? stop + 1 : Le) : 0;
+#pragma unroll
+              for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o);
+              st_slices += cnt;
+            }
+            if (ctr)
+              for (int st = 0; st < Le; ++st)
+                stop_add(b + st, (uint32_t)__popcll(__ballot(mine && stop == st)));
+            __builtin_amdgcn_wave_barrier();
+            if (b + Le == nb) {
+              const int nsurv = __popcll(__ballot(survive));
+              if (ctr) stop_add(nb - 1, (uint32_t)nsurv);
+              st_ref += nsurv;
+              int32_t id = 0;
+              bool take = false;
+              if (survive) {
+                id = bids[cand];
+                take = lex_less(ev, id, tau, tau_id);
+              }
+              append(take, ev, id);
+              __builtin_amdgcn_wave_barrier();
+              nalive = 0;
+            } else {
+              const unsigned long long bal = __ballot(survive);
+              if (survive) {
+                const int pos = __popcll(bal & lt);
+                s_ac[(cur ^ 1) * SEG + pos] = (uint16_t)cand;
+                s_ae[(cur ^ 1) * SEG + pos] = ev;
+              }
+              __builtin_amdgcn_wave_barrier();
+              nalive = __popcll(bal);
+              cur ^= 1;
+            }
+            b += Le;
+            continue;
+          }
           int L = 1;
           if (LOOK && nb - b > 1) {
             // Look-ahead: when the live candidates fit in MAXCH / L load slots, every slot
@@ -879,14 +1001,14 @@ static int resident_workgroups(const void *kern, size_t smem) {
 
 size_t scan_lds_request(const ScanArgs &a, int W) {
   return scan_lds_bytes(a.nblocks * kBlockDims, a.k_max, a.block_b, W, a.res != 0,
-                        a.pq_m > 0 ? a.pq_m * 256 : 0);
+                        a.pq_m > 0 ? a.pq_m * 256 : 0, a.p_stride);
 }
 
 template <int ST, bool P, bool LK, int W, bool PRE = false, bool RES = false, bool EST = false,
           bool PQ = false>
 static void launch_variant(const ScanArgs &a, hipStream_t s) {
   const size_t smem = scan_lds_bytes(a.nblocks * kBlockDims, a.k_max, a.block_b, W, RES,
-                                     PQ ? a.pq_m * 256 : 0);
+                                     PQ ? a.pq_m * 256 : 0, a.p_stride);
   if (smem > kMaxLds) throw std::runtime_error("scan: LDS request exceeds 160 KiB");
   const int qpw = 4 / W;
   const void *kern = reinterpret_cast<const void *>(&scan_kernel<ST, P, LK, W, PRE, RES, EST, PQ>);
