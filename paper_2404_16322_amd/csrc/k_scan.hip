@@ -212,7 +212,7 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
   const int B = a.block_b;
   const int KM = a.k_max;
   const int SEG = W == 1 ? B : kTile;
-  const Lds L = lds_layout(Dp, KM, B, W, RES, PQ ? a.pq_m * 256 : 0, a.p_stride);
+  const Lds L = lds_layout(Dp, KM, B, W, RES, PQ ? a.pq_m * 256 + Dp : 0, a.p_stride);
   unsigned char *ql = smem + (size_t)qs * L.query_bytes;
   unsigned char *wl = smem + (size_t)QPW * L.query_bytes + (size_t)wave * L.wave_bytes;
   float *s_q = reinterpret_cast<float *>(ql + L.q);
@@ -297,17 +297,33 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
   }
   if (W > 1) __syncthreads(); else __builtin_amdgcn_wave_barrier();
   if (PQ) {
-    // lookup table lut[j][c] = ||q'_j - C_j[c]||^2 over the axes of subspace j
-    const int ds = a.pq_dsub;
-    for (int e = qt; e < a.pq_m * 256; e += 64 * W) {
-      const float *cw = a.pq_books + (int64_t)e * ds;
-      const int32_t *ax = a.pq_perm + (e >> 8) * ds;
-      float acc = 0.f;
+    // lookup table lut[j][c] = ||q'_j - C_j[c]||^2 over the axes of subspace j: first the
+    // query's coordinates in subspace order (after the table in LDS), then every entry from
+    // its codeword (contiguous, coalesced across threads; four entries' loads in flight)
+    const int ds = a.pq_dsub, M = a.pq_m;
+    float *s_qp = s_lut + M * 256;
+    for (int i = qt; i < M * ds; i += 64 * W) s_qp[i] = s_q[a.pq_perm[i]];
+    if (W > 1) __syncthreads(); else __builtin_amdgcn_wave_barrier();
+    const int nent = M * 256, step = 64 * W;
+    for (int e0 = qt; e0 < nent; e0 += 4 * step) {
+      float acc[4] = {0.f, 0.f, 0.f, 0.f};
       for (int t = 0; t < ds; ++t) {
-        const float d = s_q[ax[t]] - cw[t];
-        acc = fmaf(d, d, acc);
+        float cv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int e = min(e0 + u * step, nent - 1);
+          cv[u] = a.pq_books[(int64_t)e * ds + t];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int e = min(e0 + u * step, nent - 1);
+          const float d = s_qp[(e >> 8) * ds + t] - cv[u];
+          acc[u] = fmaf(d, d, acc[u]);
+        }
       }
-      s_lut[e] = acc;
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (e0 + u * step < nent) s_lut[e0 + u * step] = acc[u];
     }
     if (W > 1) __syncthreads(); else __builtin_amdgcn_wave_barrier();
   }
@@ -1001,14 +1017,14 @@ static int resident_workgroups(const void *kern, size_t smem) {
 
 size_t scan_lds_request(const ScanArgs &a, int W) {
   return scan_lds_bytes(a.nblocks * kBlockDims, a.k_max, a.block_b, W, a.res != 0,
-                        a.pq_m > 0 ? a.pq_m * 256 : 0, a.p_stride);
+                        a.pq_m > 0 ? a.pq_m * 256 + a.nblocks * kBlockDims : 0, a.p_stride);
 }
 
 template <int ST, bool P, bool LK, int W, bool PRE = false, bool RES = false, bool EST = false,
           bool PQ = false>
 static void launch_variant(const ScanArgs &a, hipStream_t s) {
   const size_t smem = scan_lds_bytes(a.nblocks * kBlockDims, a.k_max, a.block_b, W, RES,
-                                     PQ ? a.pq_m * 256 : 0, a.p_stride);
+                                     PQ ? a.pq_m * 256 + a.nblocks * kBlockDims : 0, a.p_stride);
   if (smem > kMaxLds) throw std::runtime_error("scan: LDS request exceeds 160 KiB");
   const int qpw = 4 / W;
   const void *kern = reinterpret_cast<const void *>(&scan_kernel<ST, P, LK, W, PRE, RES, EST, PQ>);
