@@ -81,7 +81,7 @@ static void apply_variant(ScanArgs &a, const Variant &v, LaunchOrders &o) {
 }
 
 // Sets the launch shape of a.  An untuned class is timed on this very launch (each candidate
-// twice, counters off; every candidate writes the same results), then cached; callers that
+// three times, counters off; every candidate writes the same results), then cached; callers that
 // must not stall (the server) pass may_tune = false and get the fixed rule.
 static void choose_variant(ddc_index *ix, ScanArgs &a, int np_max, hipStream_t s, bool may_tune,
                            LaunchOrders &orders) {
@@ -117,7 +117,7 @@ static void choose_variant(ddc_index *ix, ScanArgs &a, int np_max, hipStream_t s
         std::vector<float> tbest(cand.size(), INFINITY);
         for (size_t ci = 0; ci < cand.size(); ++ci) {
           apply_variant(t, cand[ci], orders);
-          for (int rep = 0; rep < 2; ++rep) {
+          for (int rep = 0; rep < 3; ++rep) {
             HIPC(hipEventRecord(e0, s));
             launch_scan(t, ix->store(), s);
             HIPC(hipEventRecord(e1, s));
