@@ -420,15 +420,32 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
 #pragma unroll
           for (int c = 0; c < MAXCH; ++c) acc[c] = accp[c] = 0.f;
           const uint32_t tile_off = (uint32_t)(t0 / kTile) * nb * (uint32_t)BLOCK_BYTES;
+          const int sl = t0 + g * CPW + sub;      // the candidate this lane owns after the reduction
+          const int32_t id_pre = bids[min(sl, slen - 1)];
+          // full-D kernels: dim block b + 1 is loaded while block b is summed (a second register
+          // set; the pruned kernels, whose full path is only a query's first block, keep their
+          // registers for the staged scan, and the FP32 estimate kernels have none to spare)
+          constexpr bool PIPE = !PRUNE && (S::kBytes == 2 || !EST);
+          const unsigned char *tp = bbase + tile_off + g * 16;
+          auto load_blk = [&](uint4 (&dst)[MAXCH], int b) {
+#pragma unroll
+            for (int c = 0; c < MAXCH; ++c)
+              dst[c] = *reinterpret_cast<const uint4 *>(tp + b * BLOCK_BYTES + (uint32_t)((c * CPW + sub) * SLICE));
+          };
+          uint4 vn[MAXCH];
+          if (PIPE) load_blk(vn, 0);
           for (int b = 0; b < nbe; ++b) {
             float qv[EPL];
 #pragma unroll
             for (int e = 0; e < EPL; ++e) qv[e] = s_q[b * kBlockDims + g * EPL + e];
-            const unsigned char *bp = bbase + tile_off + b * BLOCK_BYTES + g * 16;
             uint4 v[MAXCH];
+            if (PIPE) {
 #pragma unroll
-            for (int c = 0; c < MAXCH; ++c)
-              v[c] = *reinterpret_cast<const uint4 *>(bp + (uint32_t)((c * CPW + sub) * SLICE));
+              for (int c = 0; c < MAXCH; ++c) v[c] = vn[c];
+              if (b + 1 < nbe) load_blk(vn, b + 1);
+            } else {
+              load_blk(v, b);
+            }
 #pragma unroll
             for (int c = 0; c < MAXCH; ++c) {
               float f[EPL];
@@ -442,7 +459,6 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
             }
           }
           float dis = transpose_sum<G>(acc, g);
-          const int sl = t0 + g * CPW + sub;
           if (EST) {
             const float xr = transpose_sum<G>(accp, g);   // ||x_d||^2 of the leading blocks
             dis = a.est_res ? dis + ((sl < slen ? xnorm_seg[sl] : 0.f) - xr) + qres : a.est_scale * dis;
@@ -450,7 +466,7 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
           bool keep = false;
           int32_t id = 0;
           if (sl < slen) {
-            id = bids[sl];
+            id = id_pre;
             keep = tn < K || lex_less(dis, id, tau, tau_id);
           }
           append(keep, dis, id);
@@ -598,6 +614,11 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
                                    (uint32_t)((cd % kTile) * SLICE + g * 16);
               v[c] = *reinterpret_cast<const uint4 *>(bbase + off);
             }
+            const bool mine = lane < nalive;
+            const int cand = mine ? (direct ? lane : (int)alive[lane]) : 0;
+            // a window that ends the scan fetches its candidates' ids with the data
+            int32_t id_pre = 0;
+            if (b + Le == nb) id_pre = bids[cand];
             float part[MAXCH];
 #pragma unroll
             for (int c = 0; c < MAXCH; ++c) {
@@ -615,8 +636,6 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
             const float tot = transpose_sum<G>(part, g);
             s_pr[g * CPW + sub] = tot;
             __builtin_amdgcn_wave_barrier();
-            const bool mine = lane < nalive;
-            const int cand = mine ? (direct ? lane : (int)alive[lane]) : 0;
             float ev = mine ? (direct ? 0.f : alive_e[lane]) : 0.f;
             int stop = Le;          // first pruning stage in the window (Le: none)
             if (mine) {
@@ -645,7 +664,7 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
               int32_t id = 0;
               bool take = false;
               if (survive) {
-                id = bids[cand];
+                id = id_pre;
                 take = lex_less(ev, id, tau, tau_id);
               }
               append(take, ev, id);
@@ -693,6 +712,14 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
                                    (uint32_t)((cd % kTile) * SLICE + g * 16);
               v[c] = *reinterpret_cast<const uint4 *>(bbase + off);
             }
+            // lane (g, sub) owns slot g = (candidate g >> lgL, stage g & (L-1)) after the reduction
+            const int my_cc = g >> lgL, my_ss = g & (L - 1);
+            const int idx = my_cc * CPW + sub;
+            const bool valid = idx < nalive;
+            const int ci = min(idx, SEG - 1);
+            const int cand = direct ? idx : (int)alive[ci];
+            int32_t id_pre = 0;
+            if (b + Le == nb) id_pre = bids[valid ? cand : first];
             float part[MAXCH];
 #pragma unroll
             for (int c = 0; c < MAXCH; ++c) {
@@ -707,12 +734,7 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
               }
               part[c] = acc;
             }
-            const float tot = transpose_sum<G>(part, g);  // lane g: slot g = (candidate g >> lgL, stage g & (L-1))
-            const int my_cc = g >> lgL, my_ss = g & (L - 1);
-            const int idx = my_cc * CPW + sub;
-            const bool valid = idx < nalive;
-            const int ci = min(idx, SEG - 1);
-            const int cand = direct ? idx : (int)alive[ci];
+            const float tot = transpose_sum<G>(part, g);
             // running partial distance, added one stage at a time in stage order: the same
             // rounding as the one-stage path, so the variant changes no result bit
             float ev = my_ss == 0 ? (direct ? tot : alive_e[ci] + tot) : tot;
@@ -742,7 +764,7 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
               int32_t id = 0;
               bool take = false;
               if (survive) {
-                id = bids[cand];
+                id = id_pre;
                 take = lex_less(ev, id, tau, tau_id);
               }
               append(take, ev, id);
@@ -786,6 +808,12 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
                                    (uint32_t)((cd % kTile) * SLICE);
               v[c] = *reinterpret_cast<const uint4 *>(bp + off);
             }
+            const int idx = t0 + g * CPW + sub;   // the candidate this lane owns after the reduction
+            const bool valid = idx < nalive;
+            const int ci = min(idx, SEG - 1);
+            const int cand = direct ? idx : (int)alive[ci];
+            int32_t id_pre = 0;
+            if (last) id_pre = bids[valid ? cand : first];
             float part[MAXCH], partp[MAXCH];
 #pragma unroll
             for (int c = 0; c < MAXCH; ++c) {
@@ -802,10 +830,6 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
               partp[c] = accp;
             }
             const float tot = transpose_sum<G>(part, g);
-            const int idx = t0 + g * CPW + sub;
-            const bool valid = idx < nalive;
-            const int ci = min(idx, SEG - 1);
-            const int cand = direct ? idx : (int)alive[ci];
             const float ev = direct ? tot : alive_e[ci] + tot;
             float pv = 0.f;   // RES: sum of the candidate's squared coordinates so far
             if (RES) {
@@ -827,7 +851,7 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
               int32_t id = 0;
               bool take = false;
               if (keep) {
-                id = bids[cand];
+                id = id_pre;
                 take = lex_less(ev, id, tau, tau_id);
               }
               append(take, ev, id);
