@@ -13,6 +13,11 @@
 //   result: lane l, register r holds C[4 (l / 16) + r][l % 16].
 #include "ddc_internal.h"
 
+#include <cstdint>
+#include <map>
+#include <mutex>
+#include <stdexcept>
+
 namespace ddc {
 
 namespace {
@@ -36,9 +41,16 @@ __device__ inline unsigned short bf16_rne(float f) {
 
 }  // namespace
 
+// PD: K steps whose global loads are in flight at once (PD register sets).  Tile t is stored to
+// LDS stage t & 1 while the loads of tiles t + 1 .. t + PD are in flight, so one barrier per K
+// step suffices (stage t & 1 was last read in step t - 2).  PD = 1 for grids that fill the chip;
+// a grid of at most one workgroup per compute unit walks its K steps one after another, and PD =
+// 3 keeps three steps' loads in flight.  The products and their order do not depend on PD.
+// VEC: every K step is a full 32-wide tile of 16-byte aligned rows (the host checks lda, ldb, K
+// and the base pointers), so each thread's loads are four float4 loads with only a row mask;
+// otherwise every element is loaded on its own with a K mask.
+template <int PD, bool VEC>
 __global__ __launch_bounds__(256) void gemm_nt_kernel(GemmArgs g) {
-  // two LDS stages: tile t is stored to stage t & 1 while the global loads of tile t + 1 are in
-  // flight, so one barrier per K step suffices (stage t & 1 was last read in step t - 2)
   __shared__ __align__(16) float As[2][BM * LDA];
   __shared__ __align__(16) float Bs[2][BN * LDA];
   const int tid = threadIdx.x;
@@ -54,10 +66,11 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(GemmArgs g) {
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-  // A (minus mu) and B tiles: 64 rows x 32 k each, 8 elements per thread each
-  float4 ra[2], rb[2];
-  auto load_tile = [&](int k0) {
-    const bool vec = (g.lda % 4 == 0) && (g.ldb % 4 == 0) && (k0 + BK <= g.K);
+  // A, mu and B tiles: 64 rows x 32 k each, 8 elements per thread each.  The loads only fill
+  // registers; A - mu is formed when the tile is stored to LDS, so no load is waited for before
+  // its tile's turn
+  float4 ra[PD][2], rm[PD][2], rb[PD][2];
+  auto load_tile = [&](float4 (&ra_)[2], float4 (&rm_)[2], float4 (&rb_)[2], int k0) {
 #pragma unroll
     for (int it = 0; it < 2; ++it) {
       const int e = tid + it * 256;       // 0..511 -> (row, k4)
@@ -65,39 +78,49 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(GemmArgs g) {
       const int kc = (e & 7) * 4;
       const int64_t gm = m0 + r;
       const int gn = n0 + r;
-      float4 av = make_float4(0.f, 0.f, 0.f, 0.f), bv = av;
-      if (vec) {
+      float4 av = make_float4(0.f, 0.f, 0.f, 0.f), mv = av, bv = av;
+      if (VEC) {
         if (gm < g.M) {
           av = *reinterpret_cast<const float4 *>(g.A + gm * g.lda + k0 + kc);
-          if (g.mu) {
-            const float4 mv = *reinterpret_cast<const float4 *>(g.mu + k0 + kc);
-            av.x -= mv.x; av.y -= mv.y; av.z -= mv.z; av.w -= mv.w;
-          }
+          if (g.mu) mv = *reinterpret_cast<const float4 *>(g.mu + k0 + kc);
         }
         if (gn < g.N) bv = *reinterpret_cast<const float4 *>(g.B + (int64_t)gn * g.ldb + k0 + kc);
       } else {
-        float ta[4], tb[4];
+        float ta[4], tm[4], tb[4];
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
           const int k = k0 + kc + t;
-          float x = 0.f, y = 0.f;
+          float x = 0.f, m = 0.f, y = 0.f;
           if (k < g.K) {
-            if (gm < g.M) x = g.A[gm * g.lda + k] - (g.mu ? g.mu[k] : 0.f);
+            if (gm < g.M) {
+              x = g.A[gm * g.lda + k];
+              if (g.mu) m = g.mu[k];
+            }
             if (gn < g.N) y = g.B[(int64_t)gn * g.ldb + k];
           }
-          ta[t] = x; tb[t] = y;
+          ta[t] = x; tm[t] = m; tb[t] = y;
         }
         av = make_float4(ta[0], ta[1], ta[2], ta[3]);
+        mv = make_float4(tm[0], tm[1], tm[2], tm[3]);
         bv = make_float4(tb[0], tb[1], tb[2], tb[3]);
       }
-      ra[it] = av;
-      rb[it] = bv;
+      ra_[it] = av;
+      rm_[it] = mv;
+      rb_[it] = bv;
     }
   };
 
-  load_tile(0);
-  int stage = 0;
-  for (int k0 = 0; k0 < g.K; k0 += BK, stage ^= 1) {
+#pragma unroll
+  for (int u = 0; u < PD; ++u)
+    if (u * BK < g.K) load_tile(ra[u], rm[u], rb[u], u * BK);
+  // register set u holds tile t with t % PD == u: the inner loop is unrolled, so every set is
+  // addressed statically and stays in registers
+  for (int kb = 0; kb < g.K; kb += PD * BK) {
+#pragma unroll
+  for (int u = 0; u < PD; ++u) {
+    const int k0 = kb + u * BK;
+    if (k0 >= g.K) break;
+    const int stage = (k0 / BK) & 1;
     float *as = As[stage];
     float *bs = Bs[stage];
 #pragma unroll
@@ -105,11 +128,17 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(GemmArgs g) {
       const int e = tid + it * 256;
       const int r = e >> 3;
       const int kc = (e & 7) * 4;
-      *reinterpret_cast<float4 *>(&as[r * LDA + kc]) = ra[it];
-      *reinterpret_cast<float4 *>(&bs[r * LDA + kc]) = rb[it];
+      float4 av = ra[u][it];
+      if (g.mu) {
+        const float4 mv = rm[u][it];
+        av.x -= mv.x; av.y -= mv.y; av.z -= mv.z; av.w -= mv.w;
+      }
+      *reinterpret_cast<float4 *>(&as[r * LDA + kc]) = av;
+      *reinterpret_cast<float4 *>(&bs[r * LDA + kc]) = rb[u][it];
     }
     __syncthreads();
-    if (k0 + BK < g.K) load_tile(k0 + BK);   // next tile's loads overlap this step's products
+    // tile t + PD's loads overlap the products of tiles t .. t + PD - 1
+    if (k0 + PD * BK < g.K) load_tile(ra[u], rm[u], rb[u], k0 + PD * BK);
     if (g.prec == 0) {
 #pragma unroll
       for (int kk = 0; kk < BK; kk += 4) {
@@ -151,6 +180,7 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(GemmArgs g) {
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bf[j], acc[i][j], 0, 0, 0);
     }
   }
+  }
 
   // epilogue
 #pragma unroll
@@ -182,10 +212,34 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(GemmArgs g) {
   }
 }
 
+// compute units of the current device (cached per device)
+static int device_cus() {
+  static std::mutex mtx;
+  static std::map<int, int> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) throw std::runtime_error("gemm: hipGetDevice failed");
+  std::lock_guard<std::mutex> lk(mtx);
+  auto it = cache.find(dev);
+  if (it != cache.end()) return it->second;
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+    throw std::runtime_error("gemm: device query failed");
+  cache[dev] = cus;
+  return cus;
+}
+
 void launch_gemm(const GemmArgs &g, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0) return;
   dim3 grid((g.N + BN - 1) / BN, (unsigned)((g.M + BM - 1) / BM));
-  hipLaunchKernelGGL(gemm_nt_kernel, grid, dim3(256), 0, s, g);
+  auto al16 = [](const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
+  const bool vec = g.lda % 4 == 0 && g.ldb % 4 == 0 && g.K % BK == 0 && al16(g.A) && al16(g.B) &&
+                   (g.mu == nullptr || al16(g.mu));
+  if (!vec)
+    hipLaunchKernelGGL((gemm_nt_kernel<1, false>), grid, dim3(256), 0, s, g);
+  else if ((int64_t)grid.x * grid.y <= device_cus())
+    hipLaunchKernelGGL((gemm_nt_kernel<3, true>), grid, dim3(256), 0, s, g);
+  else
+    hipLaunchKernelGGL((gemm_nt_kernel<1, true>), grid, dim3(256), 0, s, g);
 }
 
 // ------------------------------------------------------------------------------------
