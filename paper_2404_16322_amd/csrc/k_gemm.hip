@@ -244,8 +244,9 @@ void launch_gemm(const GemmArgs &g, hipStream_t s) {
 
 // ------------------------------------------------------------------------------------
 // Probe selection: the nprobe smallest (distance, list) pairs of a query, ascending.
-// One wavefront per query (four per workgroup).  Radix select on the order-preserving
-// 32-bit key of the distance, whose first 8-bit digit starts at the highest bit where the
+// One wavefront per query (four per workgroup).  A threshold from the lanes' smallest keys
+// gathers the candidates in one pass when few enough pass it; otherwise a radix select on
+// the order-preserving 32-bit key of the distance, whose first 8-bit digit starts at the highest bit where the
 // row's smallest and largest keys differ (so the first histogram is spread over the whole
 // range); passes stop once the bucket holding the remaining rank has at most kExtra keys,
 // or on the last digit (then every key in it is equal and index order decides).  The
@@ -277,6 +278,56 @@ __device__ inline uint32_t wave_max_u32(uint32_t v) {
 
 __host__ __device__ inline size_t select_wave_lds(int p_stride) { return 256 * 4 + (size_t)(p_stride + kExtra) * 8; }
 
+// The np-th smallest (np <= 64 RR) of the union of every lane's RR smallest keys: the lanes'
+// keys are passed through `each`, the RR smallest kept sorted in v, then the 64 RR kept keys
+// (key r * 64 + lane in register r of that lane) are bitonic-sorted across the wavefront.
+template <int RR, typename Each>
+__device__ inline uint32_t lane_union_threshold(Each &&each, int np) {
+  uint32_t v[RR];
+#pragma unroll
+  for (int r = 0; r < RR; ++r) v[r] = 0xFFFFFFFFu;
+  each([&](int, uint32_t x) {
+#pragma unroll
+    for (int m = 0; m < RR; ++m) {
+      const uint32_t lo = min(v[m], x);
+      x = max(v[m], x);
+      v[m] = lo;
+    }
+  });
+  const int lane = __lane_id();
+#pragma unroll
+  for (int size = 2; size <= 64 * RR; size <<= 1) {
+#pragma unroll
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      if (stride >= 64) {
+        const int rs = stride >> 6;
+#pragma unroll
+        for (int r = 0; r < RR; ++r) {
+          if (r & rs) continue;
+          const bool up = ((r * 64) & size) == 0;
+          const uint32_t lo = min(v[r], v[r | rs]), hi = max(v[r], v[r | rs]);
+          v[r] = up ? lo : hi;
+          v[r | rs] = up ? hi : lo;
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < RR; ++r) {
+          const uint32_t o = (uint32_t)__shfl_xor((int)v[r], stride);
+          const bool up = ((r * 64 + lane) & size) == 0;
+          const bool lower = (lane & stride) == 0;
+          v[r] = (lower == up) ? min(v[r], o) : max(v[r], o);
+        }
+      }
+    }
+  }
+  const int e = np - 1, er = e >> 6;
+  uint32_t pick = v[0];
+#pragma unroll
+  for (int r = 1; r < RR; ++r)
+    if (er == r) pick = v[r];
+  return (uint32_t)__shfl((int)pick, e & 63);
+}
+
 // NR > 0: the row's keys stay in registers (key j in register j / 64 of lane j % 64), read
 // from memory once; NR = 0: every pass re-reads the row (any nlist).
 template <int NR>
@@ -291,8 +342,8 @@ __global__ __launch_bounds__(kSelThreads) void select_kernel(const float *dist, 
   if (q >= nq) return;
   unsigned char *wl = smem + (size_t)wave * select_wave_lds(p_stride);
   int32_t *hist = reinterpret_cast<int32_t *>(wl);
-  uint32_t *sel_k = reinterpret_cast<uint32_t *>(wl + 256 * 4);
-  int32_t *sel_j = reinterpret_cast<int32_t *>(sel_k + p_stride + kExtra);
+  // selected (key, index) pairs packed as key << 32 | index: one 64-bit compare orders them
+  unsigned long long *sel = reinterpret_cast<unsigned long long *>(wl + 256 * 4);
   const int np = nprobe ? nprobe[q] : nprobe_all;
   const float *row = dist + q * ld;
   const unsigned long long lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
@@ -355,43 +406,21 @@ __global__ __launch_bounds__(kSelThreads) void select_kernel(const float *dist, 
   int nsel = 0;
   bool fast = false;
   {
-    // Threshold from per-lane order statistics: with c = ceil(np / 64) and s_l = the c-th
-    // smallest key of lane l, at least k * c >= np keys are <= t = the k-th smallest s_l
-    // (k = ceil(np / c)), so the np smallest keys are all <= t.  Keys <= t are gathered in
-    // one pass; when there are more than `cap` of them the radix selection below runs.
-    const int c = (np + 63) / 64;
-    if (c <= 4) {
-      uint32_t best[4] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
-      each([&](int, uint32_t x) {
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-          const uint32_t lo = min(best[m], x);
-          x = max(best[m], x);
-          best[m] = lo;
-        }
-      });
-      uint32_t v = c == 1 ? best[0] : c == 2 ? best[1] : c == 3 ? best[2] : best[3];
-      // bitonic sort of the 64 lane values, ascending by lane
-#pragma unroll
-      for (int size = 2; size <= 64; size <<= 1) {
-#pragma unroll
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-          const uint32_t o = (uint32_t)__shfl_xor((int)v, stride);
-          const bool up = (lane & size) == 0;
-          const bool lower = (lane & stride) == 0;
-          v = (lower == up) ? min(v, o) : max(v, o);
-        }
-      }
-      const int k = (np + c - 1) / c;
-      const uint32_t t = (uint32_t)__shfl((int)v, k - 1);
+    // Threshold from the lanes' RR smallest keys (RR = 1 for np <= 16, 2 for np <= 64, else 4):
+    // t = the np-th smallest of these 64 RR keys.  At least np keys
+    // are <= t (those np of them), so the np smallest keys are all <= t; keys <= t are gathered
+    // in one pass.  A lane rarely holds more than RR of the np smallest keys, so few more than np
+    // are gathered; when more than `cap` are, the radix selection below runs.
+    if (np <= 256) {
+      uint32_t t;
+      if (np <= 16) t = lane_union_threshold<1>(each, np);
+      else if (np <= 64) t = lane_union_threshold<2>(each, np);
+      else t = lane_union_threshold<4>(each, np);
       each_group([&](int j, uint32_t u, bool valid) {
         const bool take = valid && u <= t;
         const unsigned long long bt = __ballot(take);
         const int pos = nsel + __popcll(bt & lt);
-        if (take && pos < cap) {
-          sel_k[pos] = u;
-          sel_j[pos] = j;
-        }
+        if (take && pos < cap) sel[pos] = ((unsigned long long)u << 32) | (uint32_t)j;
         nsel += __popcll(bt);
       });
       fast = nsel <= cap;
@@ -473,8 +502,7 @@ __global__ __launch_bounds__(kSelThreads) void select_kernel(const float *dist, 
       const unsigned long long bt = __ballot(take);
       if (take) {
         const int pos = nsel + __popcll(bt & lt);
-        sel_k[pos] = u;
-        sel_j[pos] = j;
+        sel[pos] = ((unsigned long long)u << 32) | (uint32_t)j;
       }
       nsel += __popcll(bt);
     });
@@ -486,8 +514,7 @@ __global__ __launch_bounds__(kSelThreads) void select_kernel(const float *dist, 
         const unsigned long long bt = __ballot(inreg);
         const int r = __popcll(bt & lt);
         if (inreg && taken + r < kk) {
-          sel_k[nsel + taken + r] = u;
-          sel_j[nsel + taken + r] = j;
+          sel[nsel + taken + r] = ((unsigned long long)u << 32) | (uint32_t)j;
         }
         taken = min(kk, taken + __popcll(bt));
       });
@@ -497,14 +524,11 @@ __global__ __launch_bounds__(kSelThreads) void select_kernel(const float *dist, 
   __builtin_amdgcn_wave_barrier();
   // rank sort by (key, index); the first np ranks are the probes
   for (int i = lane; i < nsel; i += 64) {
-    const uint32_t u = sel_k[i];
-    const int j = sel_j[i];
+    const unsigned long long u = sel[i];
     int r = 0;
-    for (int t = 0; t < nsel; ++t) {
-      const uint32_t v = sel_k[t];
-      r += (v < u) || (v == u && sel_j[t] < j);
-    }
-    if (r < np) probes[q * p_stride + r] = j;
+#pragma unroll 8
+    for (int t = 0; t < nsel; ++t) r += sel[t] < u ? 1 : 0;
+    if (r < np) probes[q * p_stride + r] = (int32_t)(uint32_t)u;
   }
 }
 
@@ -514,8 +538,17 @@ void launch_select(const float *dist, int64_t ld, int32_t nlist, const int32_t *
   if (nq <= 0) return;
   const size_t smem = 4 * select_wave_lds(p_stride);
   const dim3 grid((unsigned)((nq + 3) / 4));
+  // the row's keys in registers when they fit (64 per lane at most) and the batch is small
+  // (64 keys per lane allow 3 waves per SIMD; a 10,000-query batch measured faster re-reading
+  // its rows with 8 waves per SIMD), else re-read per pass
   if (nlist <= 256)
     hipLaunchKernelGGL(select_kernel<4>, grid, dim3(kSelThreads), smem, s, dist, ld, nlist, nprobe,
+                       nprobe_all, probes, p_stride, nq);
+  else if (nlist <= 1024)
+    hipLaunchKernelGGL(select_kernel<16>, grid, dim3(kSelThreads), smem, s, dist, ld, nlist, nprobe,
+                       nprobe_all, probes, p_stride, nq);
+  else if (nlist <= 4096 && nq <= 4096)
+    hipLaunchKernelGGL(select_kernel<64>, grid, dim3(kSelThreads), smem, s, dist, ld, nlist, nprobe,
                        nprobe_all, probes, p_stride, nq);
   else
     hipLaunchKernelGGL(select_kernel<0>, grid, dim3(kSelThreads), smem, s, dist, ld, nlist, nprobe,
