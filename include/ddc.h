@@ -247,7 +247,12 @@ ddc_status ddc_search_var(const ddc_index *ix, const float *queries, int64_t nq,
  * to use k_all / nprobe_all; k_max / nprobe_max bound them; d_out_offsets: CSR as in
  * ddc_search_var or NULL for dense [nq x k_all]; d_ids int64 / d_dists float32 outputs;
  * d_counters: NULL or device int64[4 + 64 + 2] (added to): candidates, refined, stage
- * slices, unused, stage_stop[64], prestage_reads, prestage_pruned. */
+ * slices, unused, stage_stop[64], prestage_reads, prestage_pruned.
+ * Scratch: the index keeps one grow-only device workspace per stream (rotated queries, coarse
+ * distances, probes; about nq x (dim + nlist + nprobe_max) x 4 bytes for nq <= 32,768), made on
+ * the stream's first call and reused by the next ones, freed with the index; calls on one
+ * stream from several host threads must therefore not overlap.  Under graph capture the
+ * scratch comes from the stream-ordered pool instead. */
 ddc_status ddc_search_device(const ddc_index *ix, const float *d_queries, int64_t nq,
                              const int32_t *d_k, int32_t k_all, int32_t k_max,
                              const int32_t *d_nprobe, int32_t nprobe_all, int32_t nprobe_max,

@@ -61,17 +61,18 @@ static Variant forced_or(const ddc_index *ix, Variant v, int kind) {
 }
 
 // Query orders a launch may use: grouped by first probed list (one pass per workgroup), and
-// longest first with a slot counter (persistent), the latter made on first use.
+// longest first with a slot counter (persistent), the latter made on first use (rebuild = true
+// makes it again: the tuner charges a persistent candidate for its order kernels).
 struct LaunchOrders {
   const int32_t *group = nullptr;
-  std::function<std::pair<const int32_t *, int32_t *>()> longest_first;
+  std::function<std::pair<const int32_t *, int32_t *>(bool rebuild)> longest_first;
 };
 
 static void apply_variant(ScanArgs &a, const Variant &v, LaunchOrders &o) {
   a.waves_per_query = v[0];
   a.lookahead = v[1];
   if (v[2]) {
-    const auto pq = o.longest_first();
+    const auto pq = o.longest_first(false);
     a.order = pq.first;
     a.queue = pq.second;
   } else {
@@ -119,6 +120,7 @@ static void choose_variant(ddc_index *ix, ScanArgs &a, int np_max, hipStream_t s
           apply_variant(t, cand[ci], orders);
           for (int rep = 0; rep < 3; ++rep) {
             HIPC(hipEventRecord(e0, s));
+            if (cand[ci][2]) orders.longest_first(true);   // the persistent launch's own order kernels
             launch_scan(t, ix->store(), s);
             HIPC(hipEventRecord(e1, s));
             HIPC(hipEventSynchronize(e1));
@@ -623,6 +625,25 @@ template <class F> static void timed(ddc_index *ix, int kernel, hipStream_t s, F
   ix->marks.push_back(m);
 }
 
+// A piece of a search's scratch buffer.
+struct ScratchPart {
+  void *p;
+  template <class T> T *as() const { return reinterpret_cast<T *>(p); }
+};
+
+// The stream's search workspace, grown to at least `bytes` (a grown one replaces the old after
+// the stream's queued work is done with it).
+static void *stream_workspace(ddc_index *ix, hipStream_t s, size_t bytes) {
+  std::lock_guard<std::mutex> lk(ix->scratch_mtx);
+  auto &w = ix->scratch[s];
+  if (!w) w = std::make_unique<DevBuf>();
+  if (w->bytes < bytes) {
+    if (w->p) HIPC(hipStreamSynchronize(s));
+    w->alloc(bytes);
+  }
+  return w->p;
+}
+
 size_t ddc::search_scratch_bytes(const ddc_index *ix, int64_t nq, int np_max) {
   const int64_t c = std::min<int64_t>(nq, 32768);
   return (size_t)c * ix->Dp * 4 + (size_t)c * ix->nlist * 4 + (size_t)c * np_max * 4 +
@@ -633,7 +654,7 @@ void ddc::search_device(ddc_index *ix, const float *d_q, int64_t nq, const int32
                         int k_max, const int32_t *d_np, int np_all, int np_max, double alpha,
                         ddc_corr mode, const int64_t *d_off, int64_t *d_ids, float *d_d,
                         int64_t *d_ctr, hipStream_t s, float *qrot_out, int32_t *probes_out,
-                        bool may_tune, const EstimateSpec *est) {
+                        bool may_tune, const EstimateSpec *est, bool stream_scratch) {
   const int Dp = ix->Dp, D = ix->D;
   ScanArgs a{};
   a.prune = 0;
@@ -682,10 +703,34 @@ void ddc::search_device(ddc_index *ix, const float *d_q, int64_t nq, const int32
     }
   }
   const int64_t chunk = 32768;
+  // Scratch of a chunk (rotated queries, coarse distances, probes, query orders), carved from
+  // one buffer: with stream_scratch and outside graph capture the stream's grow-only workspace,
+  // reused call after call (stream order keeps a call's kernels from overlapping the next
+  // call's use of it; per-call stream-ordered allocations left the GPU idle about 30 us at
+  // every call); else one stream-ordered allocation (which a captured graph records).
+  const int64_t cmax = std::min(chunk, nq);
+  const size_t sizes[] = {(size_t)cmax * Dp * 4, (size_t)cmax * ix->nlist * 4, (size_t)cmax * np_max * 4,
+                          (size_t)(ix->nlist + 1) * 4, (size_t)cmax * 4, (size_t)cmax * 4,
+                          (size_t)cmax * 4, (size_t)257 * 4, (size_t)cmax * 4, (size_t)cmax * 4, 256};
+  size_t total = 0;
+  for (size_t b : sizes) total += (b + 255) & ~(size_t)255;
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  HIPC(hipStreamIsCapturing(s, &cap));
+  const bool reuse = stream_scratch && cap == hipStreamCaptureStatusNone;
+  AsyncBuf pooled(reuse ? 0 : total, s);
+  char *const ws = reuse ? reinterpret_cast<char *>(stream_workspace(ix, s, total)) : pooled.as<char>();
+  void *part[11];
+  {
+    size_t off = 0;
+    for (int i = 0; i < 11; ++i) {
+      part[i] = ws + off;
+      off += (sizes[i] + 255) & ~(size_t)255;
+    }
+  }
+  const ScratchPart qrot{part[0]}, cdist{part[1]}, probes{part[2]}, ord_hist{part[3]}, ord_rank{part[4]},
+      ord{part[5]}, lpt_key{part[6]}, lpt_hist{part[7]}, lpt_rank{part[8]}, lpt{part[9]}, queue{part[10]};
   for (int64_t q0 = 0; q0 < nq; q0 += chunk) {
     const int64_t nqc = std::min(chunk, nq - q0);
-    AsyncBuf qrot((size_t)nqc * Dp * 4, s), cdist((size_t)nqc * ix->nlist * 4, s),
-        probes((size_t)nqc * np_max * 4, s);
     GemmArgs g{};
     g.A = d_q + q0 * D; g.lda = D; g.mu = ix->d_mu32.as<float>();
     g.B = ix->d_R32.as<float>(); g.ldb = Dp; g.C = qrot.as<float>(); g.ldc = Dp;
@@ -718,24 +763,17 @@ void ddc::search_device(ddc_index *ix, const float *d_q, int64_t nq, const int32
     a.out_ids = d_off ? d_ids : d_ids + q0 * k_all;
     a.out_d = d_off ? d_d : d_d + q0 * k_all;
     a.counters = d_ctr;
-    AsyncBuf ord_hist(0, s), ord_rank(0, s), ord(0, s), lpt_key(0, s), lpt_hist(0, s), lpt_rank(0, s),
-        lpt(0, s), queue(0, s);
     LaunchOrders orders;
     if (ix->query_order) {
-      ord_hist = AsyncBuf((size_t)(ix->nlist + 1) * 4, s);
-      ord_rank = AsyncBuf((size_t)nqc * 4, s);
-      ord = AsyncBuf((size_t)nqc * 4, s);
       launch_query_order(probes.as<int32_t>(), np_max, nqc, ix->nlist, ord_hist.as<int32_t>(),
                          ord_rank.as<int32_t>(), ord.as<int32_t>(), s);
       orders.group = ord.as<int32_t>();
     }
-    orders.longest_first = [&]() -> std::pair<const int32_t *, int32_t *> {
-      if (!lpt.p) {
-        lpt_key = AsyncBuf((size_t)nqc * 4, s);
-        lpt_hist = AsyncBuf((size_t)257 * 4, s);
-        lpt_rank = AsyncBuf((size_t)nqc * 4, s);
-        lpt = AsyncBuf((size_t)nqc * 4, s);
-        queue = AsyncBuf(256, s);
+    bool lpt_made = false;
+    orders.longest_first = [&](bool rebuild) -> std::pair<const int32_t *, int32_t *> {
+      const bool first = !lpt_made;
+      lpt_made = true;
+      if (first || rebuild) {
         launch_work_order(probes.as<int32_t>(), np_max, d_np ? d_np + q0 : nullptr, np_all,
                           ix->d_list_len.as<int32_t>(), ix->nlist, nqc, lpt_key.as<int32_t>(),
                           lpt_hist.as<int32_t>(), lpt_rank.as<int32_t>(), lpt.as<int32_t>(), s);
@@ -1298,7 +1336,8 @@ ddc_status ddc_search_device(const ddc_index *ixc, const float *d_queries, int64
   DeviceGuard dg(ix->device);
   search_device(ix, d_queries, nq, d_k, k_all, d_k ? k_max : k_all, d_nprobe, nprobe_all, npm,
                 significance, mode, d_out_offsets, d_ids, d_dists, d_counters,
-                reinterpret_cast<hipStream_t>(hip_stream));
+                reinterpret_cast<hipStream_t>(hip_stream), nullptr, nullptr, true, nullptr,
+                /*stream_scratch=*/true);
   return DDC_OK;
   GUARD_END
 }

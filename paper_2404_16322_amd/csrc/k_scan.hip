@@ -984,9 +984,63 @@ __global__ void order_scatter_kernel(const int32_t *probes, int32_t p_stride, in
   if (q < nq) order[hist[probes[q * p_stride] + 1] + rank[q]] = (int32_t)q;
 }
 
+// Counting sort of the queries by key (keys[q * stride] in [0, nbins); anything else counts as
+// one more key below all of them) in one workgroup: histogram in LDS, exclusive prefix, scatter.
+// rank[q] (global scratch) is the query's place among equal keys, in the order the atomics
+// took them; the scan gives the same results for any order of the queries.
+constexpr int kOrderThreads = 1024;
+__global__ __launch_bounds__(kOrderThreads) void order_fused_kernel(const int32_t *keys, int32_t stride,
+                                                                   int64_t nq, int32_t nbins,
+                                                                   int32_t *rank, int32_t *order) {
+  extern __shared__ int32_t hist_lds[];      // nbins + 1 counters
+  __shared__ int32_t wsum[kOrderThreads / 64];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int nb1 = nbins + 1;
+  for (int i = t; i < nb1; i += kOrderThreads) hist_lds[i] = 0;
+  __syncthreads();
+  for (int64_t q = t; q < nq; q += kOrderThreads) {
+    const int k = keys[q * stride];
+    rank[q] = atomicAdd(&hist_lds[(k >= 0 && k < nbins) ? k + 1 : 0], 1);
+  }
+  __syncthreads();
+  // exclusive prefix: every thread a contiguous chunk of counters, then a scan of the chunk sums
+  const int chunk = (nb1 + kOrderThreads - 1) / kOrderThreads;
+  const int b0 = min(nb1, t * chunk), b1 = min(nb1, b0 + chunk);
+  int sum = 0;
+  for (int i = b0; i < b1; ++i) sum += hist_lds[i];
+  int inc = sum;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int v = __shfl_up(inc, o);
+    if (lane >= o) inc += v;
+  }
+  if (lane == 63) wsum[w] = inc;
+  __syncthreads();
+  if (t == 0) {
+    int c = 0;
+    for (int i = 0; i < kOrderThreads / 64; ++i) { const int v = wsum[i]; wsum[i] = c; c += v; }
+  }
+  __syncthreads();
+  int c = wsum[w] + inc - sum;
+  for (int i = b0; i < b1; ++i) { const int v = hist_lds[i]; hist_lds[i] = c; c += v; }
+  __syncthreads();
+  for (int64_t q = t; q < nq; q += kOrderThreads) {
+    const int k = keys[q * stride];
+    order[hist_lds[(k >= 0 && k < nbins) ? k + 1 : 0] + rank[q]] = (int32_t)q;
+  }
+}
+
+// up to this many keys the one-workgroup sort (its counters in LDS) is used
+constexpr int kOrderMaxBins = 32767;
+
 void launch_query_order(const int32_t *probes, int32_t p_stride, int64_t nq, int32_t nlist,
                         int32_t *hist, int32_t *rank, int32_t *order, hipStream_t s) {
   if (nq <= 0) return;
+  if (nlist <= kOrderMaxBins) {
+    hipLaunchKernelGGL(order_fused_kernel, dim3(1), dim3(kOrderThreads), (size_t)(nlist + 1) * 4, s,
+                       probes, p_stride, nq, nlist, rank, order);
+    return;
+  }
   hipLaunchKernelGGL(fill_i32_kernel, dim3((nlist + 256) / 256), dim3(256), 0, s, hist,
                      (int64_t)nlist + 1, 0);
   const unsigned g = (unsigned)((nq + 255) / 256);
@@ -996,26 +1050,34 @@ void launch_query_order(const int32_t *probes, int32_t p_stride, int64_t nq, int
                      order);
 }
 
-__global__ void work_key_kernel(const int32_t *probes, int32_t p_stride, const int32_t *nprobe,
-                                int32_t nprobe_all, const int32_t *list_len, int32_t nlist, int64_t nq,
-                                int32_t *key) {
-  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// One wavefront per query: the lanes add the lengths of its probed lists, and the key is 255
+// minus the log2 of that candidate count in eighths (longest first).
+__global__ __launch_bounds__(256) void work_key_kernel(const int32_t *probes, int32_t p_stride,
+                                                       const int32_t *nprobe, int32_t nprobe_all,
+                                                       const int32_t *list_len, int32_t nlist, int64_t nq,
+                                                       int32_t *key) {
+  const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   if (q >= nq) return;
   const int np = nprobe ? nprobe[q] : nprobe_all;
-  int64_t work = 0;
-  for (int p = 0; p < np; ++p) {
+  long long work = 0;
+  for (int p = lane; p < np; p += 64) {
     const int l = probes[q * p_stride + p];
     if (l >= 0 && l < nlist) work += list_len[l];
   }
-  const int bucket = work > 0 ? min(255, (int)(log2f((float)work) * 8.f)) : 0;
-  key[q] = 255 - bucket;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) work += __shfl_xor(work, o);
+  if (lane == 0) {
+    const int bucket = work > 0 ? min(255, (int)(log2f((float)work) * 8.f)) : 0;
+    key[q] = 255 - bucket;
+  }
 }
 
 void launch_work_order(const int32_t *probes, int32_t p_stride, const int32_t *nprobe,
                        int32_t nprobe_all, const int32_t *list_len, int32_t nlist, int64_t nq,
                        int32_t *key, int32_t *hist, int32_t *rank, int32_t *order, hipStream_t s) {
   if (nq <= 0) return;
-  hipLaunchKernelGGL(work_key_kernel, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, s, probes,
+  hipLaunchKernelGGL(work_key_kernel, dim3((unsigned)((nq + 3) / 4)), dim3(256), 0, s, probes,
                      p_stride, nprobe, nprobe_all, list_len, nlist, nq, key);
   launch_query_order(key, 1, nq, 256, hist, rank, order, s);
 }

@@ -185,6 +185,10 @@ struct ddc_index {
     for (auto &m : marks) { (void)hipEventDestroy(m.a); (void)hipEventDestroy(m.b); }
   }
 
+  // search scratch per stream: grow-only, reused by the next call on the same stream
+  std::mutex scratch_mtx;
+  std::map<hipStream_t, std::unique_ptr<ddc::DevBuf>> scratch;
+
   // result-invariant launch knobs of the scan (0 / -1 = tuned per size class)
   int waves_per_query = 0, lookahead = -1, query_order = 1, xcd_swizzle = 1, persistent = -1;
   std::mutex tune_mtx;
@@ -208,13 +212,16 @@ struct EstimateSpec {
 
 // The search pipeline on device buffers (rotation -> coarse -> select -> scan), queued on s.
 // est (nullable): rank by that estimate instead (mode and alpha are then ignored).
+// stream_scratch: take the scratch from s's grow-only workspace in the index (callers whose
+// streams live on; calls on one stream must not overlap), else from the stream-ordered pool.
 void search_device(ddc_index *ix, const float *d_q, int64_t nq, const int32_t *d_k, int k_all,
                    int k_max, const int32_t *d_np, int np_all, int np_max, double alpha,
                    ddc_corr mode, const int64_t *d_off, int64_t *d_ids, float *d_d,
                    int64_t *d_ctr, hipStream_t s, float *qrot_out = nullptr,
                    int32_t *probes_out = nullptr, bool may_tune = true,
-                   const EstimateSpec *est = nullptr);
-// Device bytes one search of nq queries allocates from the stream-ordered pool.
+                   const EstimateSpec *est = nullptr, bool stream_scratch = false);
+// Device bytes of one search's scratch for nq queries (from the stream-ordered pool, or the
+// stream's workspace).
 size_t search_scratch_bytes(const ddc_index *ix, int64_t nq, int np_max);
 
 }  // namespace ddc
