@@ -25,7 +25,7 @@ namespace {
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-constexpr int BM = 64, BN = 64, BK = 32;
+constexpr int BK = 32;
 constexpr int LDA = BK + 4;  // padded LDS row (floats)
 
 __device__ inline uint32_t f32_order_key(float f) {
@@ -49,30 +49,38 @@ __device__ inline unsigned short bf16_rne(float f) {
 // VEC: every K step is a full 32-wide tile of 16-byte aligned rows (the host checks lda, ldb, K
 // and the base pointers), so each thread's loads are four float4 loads with only a row mask;
 // otherwise every element is loaded on its own with a K mask.
-template <int PD, bool VEC>
+// WT: MFMA 16x16 blocks per wave in each dimension; the workgroup's four waves (2 x 2) cover a
+// TB x TB output tile, TB = 32 WT (64 for WT = 2; 128 for WT = 4, half the global and LDS
+// traffic per product, taken for FP32 products with K >= 512 and at least two workgroups per
+// compute unit: measured 11% faster at K = 768, equal at K = 256, 13% slower at K = 128).
+// GEN: any operands (A - mu when g.mu is set, BF16 products when g.prec = 1); false: the host
+// guarantees g.mu == NULL and g.prec == 0, and neither costs registers.
+template <int PD, bool VEC, int WT, bool GEN>
 __global__ __launch_bounds__(256) void gemm_nt_kernel(GemmArgs g) {
-  __shared__ __align__(16) float As[2][BM * LDA];
-  __shared__ __align__(16) float Bs[2][BN * LDA];
+  constexpr int TB = 32 * WT;        // output tile rows = columns
+  constexpr int NIT = TB / 32;       // float4 loads per thread per operand and K step
+  extern __shared__ __align__(16) float gemm_lds[];   // As[2][TB * LDA], Bs[2][TB * LDA]
+  float *const As0 = gemm_lds, *const Bs0 = gemm_lds + 2 * TB * LDA;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1;
-  const int64_t m0 = (int64_t)blockIdx.y * BM;
-  const int n0 = blockIdx.x * BN;
+  const int64_t m0 = (int64_t)blockIdx.y * TB;
+  const int n0 = blockIdx.x * TB;
 
-  floatx4 acc[2][2];
+  floatx4 acc[WT][WT];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < WT; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < WT; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-  // A, mu and B tiles: 64 rows x 32 k each, 8 elements per thread each.  The loads only fill
-  // registers; A - mu is formed when the tile is stored to LDS, so no load is waited for before
-  // its tile's turn
-  float4 ra[PD][2], rm[PD][2], rb[PD][2];
-  auto load_tile = [&](float4 (&ra_)[2], float4 (&rm_)[2], float4 (&rb_)[2], int k0) {
+  // A, mu and B tiles: TB rows x 32 k each, TB / 8 elements per thread each.  The loads only
+  // fill registers; A - mu is formed when the tile is stored to LDS, so no load is waited for
+  // before its tile's turn
+  float4 ra[PD][NIT], rm[PD][NIT], rb[PD][NIT];
+  auto load_tile = [&](float4 (&ra_)[NIT], float4 (&rm_)[NIT], float4 (&rb_)[NIT], int k0) {
 #pragma unroll
-    for (int it = 0; it < 2; ++it) {
+    for (int it = 0; it < NIT; ++it) {
       const int e = tid + it * 256;       // 0..511 -> (row, k4)
       const int r = e >> 3;
       const int kc = (e & 7) * 4;
@@ -82,7 +90,7 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(GemmArgs g) {
       if (VEC) {
         if (gm < g.M) {
           av = *reinterpret_cast<const float4 *>(g.A + gm * g.lda + k0 + kc);
-          if (g.mu) mv = *reinterpret_cast<const float4 *>(g.mu + k0 + kc);
+          if (GEN && g.mu) mv = *reinterpret_cast<const float4 *>(g.mu + k0 + kc);
         }
         if (gn < g.N) bv = *reinterpret_cast<const float4 *>(g.B + (int64_t)gn * g.ldb + k0 + kc);
       } else {
@@ -94,7 +102,7 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(GemmArgs g) {
           if (k < g.K) {
             if (gm < g.M) {
               x = g.A[gm * g.lda + k];
-              if (g.mu) m = g.mu[k];
+              if (GEN && g.mu) m = g.mu[k];
             }
             if (gn < g.N) y = g.B[(int64_t)gn * g.ldb + k];
           }
@@ -121,15 +129,15 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(GemmArgs g) {
     const int k0 = kb + u * BK;
     if (k0 >= g.K) break;
     const int stage = (k0 / BK) & 1;
-    float *as = As[stage];
-    float *bs = Bs[stage];
+    float *as = As0 + stage * TB * LDA;
+    float *bs = Bs0 + stage * TB * LDA;
 #pragma unroll
-    for (int it = 0; it < 2; ++it) {
+    for (int it = 0; it < NIT; ++it) {
       const int e = tid + it * 256;
       const int r = e >> 3;
       const int kc = (e & 7) * 4;
       float4 av = ra[u][it];
-      if (g.mu) {
+      if (GEN && g.mu) {
         const float4 mv = rm[u][it];
         av.x -= mv.x; av.y -= mv.y; av.z -= mv.z; av.w -= mv.w;
       }
@@ -139,44 +147,44 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(GemmArgs g) {
     __syncthreads();
     // tile t + PD's loads overlap the products of tiles t .. t + PD - 1
     if (k0 + PD * BK < g.K) load_tile(ra[u], rm[u], rb[u], k0 + PD * BK);
-    if (g.prec == 0) {
+    if (!GEN || g.prec == 0) {
 #pragma unroll
       for (int kk = 0; kk < BK; kk += 4) {
-        float af[2], bf[2];
+        float af[WT], bf[WT];
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
-          af[i] = as[(wr * 32 + i * 16 + (lane & 15)) * LDA + kk + (lane >> 4)];
+        for (int i = 0; i < WT; ++i)
+          af[i] = as[(wr * 16 * WT + i * 16 + (lane & 15)) * LDA + kk + (lane >> 4)];
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
-          bf[j] = bs[(wc * 32 + j * 16 + (lane & 15)) * LDA + kk + (lane >> 4)];
+        for (int j = 0; j < WT; ++j)
+          bf[j] = bs[(wc * 16 * WT + j * 16 + (lane & 15)) * LDA + kk + (lane >> 4)];
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < WT; ++i)
 #pragma unroll
-          for (int j = 0; j < 2; ++j)
+          for (int j = 0; j < WT; ++j)
             acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i], bf[j], acc[i][j], 0, 0, 0);
       }
-    } else {
-      bf16x8 af[2], bf[2];
+    } else if constexpr (GEN) {
+      bf16x8 af[WT], bf[WT];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        const float *src = &as[(wr * 32 + i * 16 + (lane & 15)) * LDA + 8 * (lane >> 4)];
+      for (int i = 0; i < WT; ++i) {
+        const float *src = &as[(wr * 16 * WT + i * 16 + (lane & 15)) * LDA + 8 * (lane >> 4)];
         unsigned short h[8];
 #pragma unroll
         for (int t = 0; t < 8; ++t) h[t] = bf16_rne(src[t]);
         af[i] = *reinterpret_cast<const bf16x8 *>(h);
       }
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const float *src = &bs[(wc * 32 + j * 16 + (lane & 15)) * LDA + 8 * (lane >> 4)];
+      for (int j = 0; j < WT; ++j) {
+        const float *src = &bs[(wc * 16 * WT + j * 16 + (lane & 15)) * LDA + 8 * (lane >> 4)];
         unsigned short h[8];
 #pragma unroll
         for (int t = 0; t < 8; ++t) h[t] = bf16_rne(src[t]);
         bf[j] = *reinterpret_cast<const bf16x8 *>(h);
       }
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < WT; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < WT; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bf[j], acc[i][j], 0, 0, 0);
     }
   }
@@ -184,13 +192,13 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(GemmArgs g) {
 
   // epilogue
 #pragma unroll
-  for (int i = 0; i < 2; ++i) {
+  for (int i = 0; i < WT; ++i) {
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int col = n0 + wc * 32 + j * 16 + (lane & 15);
+    for (int j = 0; j < WT; ++j) {
+      const int col = n0 + wc * 16 * WT + j * 16 + (lane & 15);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t row = m0 + wr * 32 + i * 16 + 4 * (lane >> 4) + r;
+        const int64_t row = m0 + wr * 16 * WT + i * 16 + 4 * (lane >> 4) + r;
         const float v = acc[i][j][r];
         if (g.mode == 2) {
           // row-wise argmin of bias[n] - 2 v, ties to the lower column
@@ -230,16 +238,21 @@ static int device_cus() {
 
 void launch_gemm(const GemmArgs &g, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0) return;
-  dim3 grid((g.N + BN - 1) / BN, (unsigned)((g.M + BM - 1) / BM));
+  auto grid_for = [&](int tb) { return dim3((g.N + tb - 1) / tb, (unsigned)((g.M + tb - 1) / tb)); };
+  auto lds = [](int tb) { return (size_t)4 * 2 * 2 * tb * LDA; };
   auto al16 = [](const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
   const bool vec = g.lda % 4 == 0 && g.ldb % 4 == 0 && g.K % BK == 0 && al16(g.A) && al16(g.B) &&
                    (g.mu == nullptr || al16(g.mu));
+  const dim3 g64 = grid_for(64), g128 = grid_for(128);
+  const int cus = device_cus();
   if (!vec)
-    hipLaunchKernelGGL((gemm_nt_kernel<1, false>), grid, dim3(256), 0, s, g);
-  else if ((int64_t)grid.x * grid.y <= device_cus())
-    hipLaunchKernelGGL((gemm_nt_kernel<3, true>), grid, dim3(256), 0, s, g);
+    hipLaunchKernelGGL((gemm_nt_kernel<1, false, 2, true>), g64, dim3(256), lds(64), s, g);
+  else if ((int64_t)g64.x * g64.y <= cus)
+    hipLaunchKernelGGL((gemm_nt_kernel<3, true, 2, true>), g64, dim3(256), lds(64), s, g);
+  else if (g.mu == nullptr && g.prec == 0 && g.K >= 512 && (int64_t)g128.x * g128.y >= 2 * cus)
+    hipLaunchKernelGGL((gemm_nt_kernel<1, true, 4, false>), g128, dim3(256), lds(128), s, g);
   else
-    hipLaunchKernelGGL((gemm_nt_kernel<1, true>), grid, dim3(256), 0, s, g);
+    hipLaunchKernelGGL((gemm_nt_kernel<1, true, 2, true>), g64, dim3(256), lds(64), s, g);
 }
 
 // ------------------------------------------------------------------------------------

@@ -312,3 +312,25 @@ def test_probe_selection_all_equal_distances(nl):
     _, probes = g.debug_intermediates(np.zeros((3, 32), np.float32), 70)
     for row in probes:
         assert row.tolist() == list(range(70))
+
+
+@pytest.mark.parametrize("D,nl,nq", [(512, 4096, 2048), (768, 4096, 1100)])
+def test_probe_selection_wide_gemm_tiles(D, nl, nq):
+    """Coarse distances of large batches with long vectors (the 128 x 128 GEMM tile when the grid
+    has at least two such tiles per compute unit, the 64 x 64 tile otherwise): the rotated
+    queries and the probes match FP64."""
+    rng = np.random.default_rng(D + nl)
+    C = rng.standard_normal((nl, D)).astype(np.float32)
+    g = _probe_index(C, D=D)
+    Q = rng.standard_normal((nq, D)).astype(np.float32)
+    qrot, probes = g.debug_intermediates(Q, 20)
+    np.testing.assert_allclose(qrot, Q, rtol=0, atol=0)   # identity rotation, zero mean
+    C64 = C.astype(np.float64)
+    for qi in range(0, nq, 7):
+        ref, d = _oracle_probes(Q[qi].astype(np.float64), C64, 20)
+        if probes[qi].tolist() == ref.tolist():
+            continue
+        ds = np.sort(d)[:21]
+        gaps = np.abs(np.diff(ds)) / np.maximum(ds[1:], 1e-30)
+        gaps = gaps[gaps > 0]
+        assert gaps.size and gaps.min() < TOL, (qi, probes[qi][:12], ref[:12])
