@@ -49,7 +49,7 @@ typedef enum {
   DDC_EDEVICE = -3, /* a HIP call failed */
   DDC_EIO = -4,     /* file error in save/load */
   DDC_EBUSY = -5,
-  DDC_EUNSUP = -6   /* valid request this build does not implement */
+  DDC_EUNSUP = -6   /* valid request the library does not implement */
 } ddc_status;
 
 /* Storage format of the rotated base vectors (the paper stores FP32, Sec. VII-A). */
