@@ -42,6 +42,10 @@ CONFIGS = {
     # 1M x 128 integer descriptors, FP32, IVF 4096, 10,000 queries, K = 10 (the headline)
     "sift1m": dict(data="sift1m", nlist=4096, storage="f32", rotation="f32", k=10, nprobes=NPROBES,
                    serve=("frac", [0.25, 0.5])),
+    # the same data and index with the FP8 E4M3 pre-stage over the leading 64 rotated dims
+    # (64 B per candidate instead of the 128 B FP32 first stage; FP32 stages after it)
+    "sift1m-fp8": dict(data="sift1m", nlist=4096, storage="f32", rotation="f32", fp8=64, k=10,
+                       nprobes=NPROBES, serve=None),
     # 1M x 960, stored BF16 (or FP16), query rotation on BF16 MFMA, 1,000 queries, K = 100,
     # nprobe 64; per-result distance error against FP64 on the original data.  Correction
     # tables at K_c = 10 and 100 (a K = 100 search uses the K_c = 100 table)
