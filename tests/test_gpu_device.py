@@ -85,3 +85,41 @@ def test_device_per_query_k_and_nprobe(setup):
         torch.cuda.synchronize()
         np.testing.assert_array_equal(ids.cpu().numpy(), hi)
         np.testing.assert_array_equal(d.cpu().numpy(), hd)
+
+
+def test_device_calls_from_two_threads_on_their_own_streams(setup):
+    """Two host threads, each with its own stream (and so its own workspace), search at the
+    same time; every result equals the host entry point's."""
+    import threading
+    import torch
+    ix, g, Q = setup
+    sizes = (64, 300, 17)
+    ref = {n: g.search(Q[:n], 10, 8, 0.1)[:2] for n in sizes}
+    errors = []
+
+    def worker(seed):
+        try:
+            stream = torch.cuda.Stream()
+            q = torch.from_numpy(np.ascontiguousarray(Q[:max(sizes)], dtype=np.float32)).cuda()
+            ids = torch.empty((max(sizes), 10), dtype=torch.int64, device="cuda")
+            d = torch.empty((max(sizes), 10), dtype=torch.float32, device="cuda")
+            torch.cuda.synchronize()   # the upload above ran on the default stream
+            rng = np.random.default_rng(seed)
+            for _ in range(12):
+                n = int(rng.choice(sizes))
+                stream.synchronize()
+                g.search_device(q.data_ptr(), n, 10, 8, 0.1, "learned", ids.data_ptr(), d.data_ptr(),
+                                stream=stream.cuda_stream)
+                stream.synchronize()
+                hi, hd = ref[n]
+                if not (np.array_equal(ids[:n].cpu().numpy(), hi) and np.array_equal(d[:n].cpu().numpy(), hd)):
+                    errors.append((seed, n))
+        except Exception as e:   # reported below
+            errors.append((seed, repr(e)))
+
+    ths = [threading.Thread(target=worker, args=(s,)) for s in (1, 2)]
+    for t in ths:
+        t.start()
+    for t in ths:
+        t.join()
+    assert not errors, errors[:4]
