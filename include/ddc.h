@@ -94,7 +94,9 @@ typedef struct {
   int32_t nlist;          /* IVF lists (k-means centroids); paper: 4096 (Sec. VII-A) */
   int32_t delta_d;        /* dims per stage, Delta_d (Alg. 2); 32; must be a multiple of 32 */
   int32_t block_b;        /* tau refresh block B, candidates; multiple of 64, 64..1024; 256 */
-  int32_t lag_l;          /* tau lag L in blocks; 0 (only 0 is implemented on the GPU) */
+  int32_t lag_l;          /* tau lag L in blocks, 0..64: the candidates of block b are tested
+                             against the tau in force after block b - 1 - L (+inf before it);
+                             the calibration replays the same schedule; 0 */
   int32_t kmeans_iters;   /* Lloyd iterations; 25 */
   int32_t kmeans_train_per_list; /* k-means trains on <= this * nlist rows; 256 */
   int32_t calib_k;        /* K_c of the label-0 pairs (KNN of each calibration query), 1..256; 10 */

@@ -330,7 +330,7 @@ class Index:
             r0 += n0t
         if tabs:
             out["m"], out["resid"], out["calib_k"] = tabs[0]["m"], tabs[0]["resid"], tabs[0]["kc"]
-        out.update(delta_d=a.delta_d, block_b=a.block_b, storage=a.storage, rotation=a.rotation,
+        out.update(delta_d=a.delta_d, block_b=a.block_b, lag_l=a.lag_l, storage=a.storage, rotation=a.rotation,
                    fp8_lead_dims=a.fp8_lead_dims, tables=tabs)
         return out
 

@@ -392,7 +392,7 @@ static ddc_index::Table run_calibration(ddc_index *ix, const float *calib, int64
     a.qrot = d_q64.as<double>(); a.D = D; a.probes = d_pr.as<int32_t>(); a.nprobe = nprobe_c;
     a.tile_off = ix->d_tile_off.as<int32_t>(); a.list_len = ix->d_list_len.as<int32_t>();
     a.base = ix->d_base.p; a.store = ix->store(); a.nblocks = ix->NB; a.ids = ix->d_ids.as<int32_t>();
-    a.k = kc; a.block_b = ix->B; a.max_neg = max_neg;
+    a.k = kc; a.block_b = ix->B; a.max_neg = max_neg; a.lag = ix->L;
     a.key_base = splitmix64(seed + TAG_NEG); a.nq = nc;
     a.neg_slot = d_ns.as<int64_t>(); a.neg_tau = d_nt.as<double>();
     launch_negatives64(a, s);
@@ -782,7 +782,7 @@ void ddc::search_device(ddc_index *ix, const float *d_q, int64_t nq, const int32
     };
     a.xcd_swizzle = ix->xcd_swizzle;
     a.nq = (int32_t)nqc; a.nblocks = ix->NB; a.block_b = ix->B; a.nlist = ix->nlist;
-    a.k_max = k_max;
+    a.k_max = k_max; a.lag = ix->L;
     choose_variant(ix, a, np_max, s, may_tune, orders);
     timed(ix, 3, s, [&] { launch_scan(a, ix->store(), s); });
   }
@@ -841,7 +841,7 @@ static ddc_status check_params(const ddc_fit_params *p, int64_t n, int dim) {
   if (n < p->nlist) return set_err(DDC_EINVAL, "need n >= nlist");
   if (p->delta_d < kBlockDims || p->delta_d % kBlockDims) return set_err(DDC_EINVAL, "delta_d must be a positive multiple of 32");
   if (p->block_b < 64 || p->block_b > 1024 || p->block_b % 64) return set_err(DDC_EINVAL, "block_b must be a multiple of 64 in [64, 1024]");
-  if (p->lag_l != 0) return set_err(DDC_EUNSUP, "only lag_l = 0 is implemented");
+  if (p->lag_l < 0 || p->lag_l > kMaxLag) return set_err(DDC_EINVAL, "lag_l must be in [0, 64]");
   if (p->kmeans_iters < 0 || p->kmeans_train_per_list < 1) return set_err(DDC_EINVAL, "bad k-means parameters");
   if (p->calib_k < 1 || p->calib_k > kMaxK) return set_err(DDC_EINVAL, "calib_k must be in [1, 256]");
   for (int i = 0, prev = p->calib_k; i < kMaxTables - 1; ++i) {
@@ -969,7 +969,7 @@ ddc_status ddc_import(const ddc_artifacts *a, ddc_index **out) {
   if (a->nlist < 1 || a->nlist > 65536) return set_err(DDC_EINVAL, "nlist must be in [1, 65536]");
   if (a->delta_d < kBlockDims || a->delta_d % kBlockDims) return set_err(DDC_EINVAL, "delta_d must be a positive multiple of 32");
   if (a->block_b < 64 || a->block_b > 1024 || a->block_b % 64) return set_err(DDC_EINVAL, "block_b must be a multiple of 64 in [64, 1024]");
-  if (a->lag_l != 0) return set_err(DDC_EUNSUP, "only lag_l = 0 is implemented");
+  if (a->lag_l < 0 || a->lag_l > kMaxLag) return set_err(DDC_EINVAL, "lag_l must be in [0, 64]");
   if (a->storage != DDC_F32 && a->storage != DDC_F16 && a->storage != DDC_BF16) return set_err(DDC_EINVAL, "bad storage");
   if (a->rotation != DDC_ROT_F32 && a->rotation != DDC_ROT_BF16) return set_err(DDC_EINVAL, "bad rotation");
   if (!a->mu || !a->rot || !a->centroids || !a->assign || !a->y) return set_err(DDC_EINVAL, "missing artifact array");

@@ -12,6 +12,7 @@ namespace ddc {
 constexpr int kBlockDims = 32;
 constexpr int kTile = 64;
 constexpr int kMaxBlocks = 128;      // D <= 4096
+constexpr int kMaxLag = 64;          // tau lag L in blocks
 constexpr int kMaxK = 256;
 constexpr int kScanThreads = 256;    // 4 wavefronts per query
 // counters: candidates, refined, stage_slices, unused, stop[64], pre-stage reads, pre-stage prunes
@@ -69,6 +70,7 @@ struct ScanArgs {
   int32_t waves_per_query; // 1 or 4 (result-invariant)
   int32_t lookahead;       // 0 or 1: multi-stage loads when few candidates survive (result-invariant)
   int32_t nq, nblocks, block_b, prune, nlist, k_max;
+  int32_t lag;           // tau lag L in blocks: block b is tested against the tau after block b - 1 - L
   // Correction tables [ntab][nblocks + 1][2] = (m, beta) of the test after dim block b
   // (beta = -inf, m = 0 where none follows); entry nblocks is the FP8 pre-stage.  A query
   // with K uses the last table t with tab_k[t] <= K (table 0 when none).
@@ -191,7 +193,7 @@ struct NegArgs {
   const int32_t *tile_off; const int32_t *list_len;
   const void *base; int store; int32_t nblocks;
   const int32_t *ids;
-  int32_t k, block_b, max_neg;
+  int32_t k, block_b, max_neg, lag;
   unsigned long long key_base;   // splitmix64(seed + tag)
   int64_t nq;
   int64_t *neg_slot;   // [nq x max_neg] stored slot or -1

@@ -131,7 +131,7 @@ void launch_cdist64(const double *qrot, int64_t nq, int32_t D, const float *cent
 }
 
 // One workgroup per calibration query: the unpruned canonical block-synchronous IVF
-// search (tau_b = K-th distance after the previous block) in FP64.  Every candidate met
+// search (tau_b = K-th distance after block b - 1 - lag) in FP64.  Every candidate met
 // with a finite tau_b and dis > tau_b is label-1 eligible; the max_neg with the smallest
 // (SplitMix64 key, id) are kept.
 constexpr int kNegThreads = 256;
@@ -159,12 +159,13 @@ __global__ __launch_bounds__(kNegThreads) void negatives64_kernel(NegArgs a) {
   int64_t *s_es = reinterpret_cast<int64_t *>(carve((size_t)B * 8));
   int32_t *s_ei = reinterpret_cast<int32_t *>(carve((size_t)B * 4));
   int32_t *s_ctr = reinterpret_cast<int32_t *>(carve(8));                            // [2]
+  double *s_th = reinterpret_cast<double *>(carve((size_t)(a.lag + 1) * 8));         // taus of the last lag + 1 blocks
 
   for (int i = tid; i < D; i += kNegThreads) s_q[i] = a.qrot[q * D + i];
   if (tid < 2) s_ctr[tid] = 0;
   __syncthreads();
 
-  int tin = 0, tn = 0, pin = 0, pn = 0;
+  int tin = 0, tn = 0, pin = 0, pn = 0, bidx = 0;
   double tau = INFINITY;
   for (int p = 0; p < a.nprobe; ++p) {
     const int lst = a.probes[q * a.nprobe + p];
@@ -175,6 +176,13 @@ __global__ __launch_bounds__(kNegThreads) void negatives64_kernel(NegArgs a) {
       const bool finite = tn == K;
       const double tkd = finite ? s_td[tin * K + K - 1] : INFINITY;
       const int32_t tki = finite ? s_ti[tin * K + K - 1] : 0x7FFFFFFF;
+      // tau_b: the tau after block bidx - 1 - lag (+inf before it or while that queue held < K)
+      double tau_b = tau;
+      if (a.lag > 0) {
+        const int j = bidx - 1 - a.lag;
+        tau_b = j >= 0 ? s_th[j % (a.lag + 1)] : INFINITY;
+      }
+      const bool fin_b = tau_b < INFINITY;
       const bool pfull = pn == MN;
       const unsigned long long pkk = pfull ? s_pk[pin * MN + MN - 1] : ~0ull;
       const int32_t pki = pfull ? s_pi[pin * MN + MN - 1] : 0x7FFFFFFF;
@@ -190,7 +198,7 @@ __global__ __launch_bounds__(kNegThreads) void negatives64_kernel(NegArgs a) {
           const int pos = atomicAdd(&s_ctr[0], 1);
           s_bd[pos] = s; s_bi[pos] = id;
         }
-        if (finite && s > tau) {
+        if (fin_b && s > tau_b) {
           const unsigned long long key =
               splitmix64(a.key_base + (((unsigned long long)q << 32) + (unsigned long long)(uint32_t)id));
           if (!pfull || key < pkk || (key == pkk && id < pki)) {
@@ -219,7 +227,7 @@ __global__ __launch_bounds__(kNegThreads) void negatives64_kernel(NegArgs a) {
           k = s_pk[pin * MN + i]; sl = s_ps[pin * MN + i]; id = s_pi[pin * MN + i];
           tb = s_pt[pin * MN + i]; r = i;
         } else {
-          k = s_ek[i - pn]; sl = s_es[i - pn]; id = s_ei[i - pn]; tb = tau; r = 0;
+          k = s_ek[i - pn]; sl = s_es[i - pn]; id = s_ei[i - pn]; tb = tau_b; r = 0;
           for (int t = 0; t < pn; ++t) {
             const unsigned long long o = s_pk[pin * MN + t];
             r += o < k || (o == k && s_pi[pin * MN + t] < id);
@@ -235,7 +243,11 @@ __global__ __launch_bounds__(kNegThreads) void negatives64_kernel(NegArgs a) {
       if (nb > 0) { tin ^= 1; tn = min(K, tn + nb); }
       if (ne > 0) { pin ^= 1; pn = min(MN, pn + ne); }
       if (tn == K) tau = s_td[tin * K + K - 1];
-      if (tid == 0) { s_ctr[0] = 0; s_ctr[1] = 0; }
+      if (tid == 0) {
+        s_ctr[0] = 0; s_ctr[1] = 0;
+        if (a.lag > 0) s_th[bidx % (a.lag + 1)] = tn == K ? tau : INFINITY;
+      }
+      ++bidx;
       __syncthreads();
     }
   }
@@ -245,16 +257,16 @@ __global__ __launch_bounds__(kNegThreads) void negatives64_kernel(NegArgs a) {
   }
 }
 
-size_t negatives_smem(int D, int K, int B, int MN) {
+size_t negatives_smem(int D, int K, int B, int MN, int lag) {
   auto r8 = [](size_t b) { return (b + 7) & ~(size_t)7; };
   return r8((size_t)D * 8) + r8((size_t)2 * K * 8) + r8((size_t)2 * K * 4) + r8((size_t)B * 8) +
          r8((size_t)B * 4) + 3 * r8((size_t)2 * MN * 8) + r8((size_t)2 * MN * 4) +
-         2 * r8((size_t)B * 8) + r8((size_t)B * 4) + 8;
+         2 * r8((size_t)B * 8) + r8((size_t)B * 4) + 8 + r8((size_t)(lag + 1) * 8);
 }
 
 void launch_negatives64(const NegArgs &a, hipStream_t s) {
   if (a.nq <= 0) return;
-  const size_t smem = negatives_smem(a.D, a.k, a.block_b, a.max_neg);
+  const size_t smem = negatives_smem(a.D, a.k, a.block_b, a.max_neg, a.lag);
   hipLaunchKernelGGL(negatives64_kernel, dim3((unsigned)a.nq), dim3(kNegThreads), smem, s, a);
 }
 

@@ -138,13 +138,14 @@ constexpr int kMetaCap = 256;
 
 struct Lds {
   size_t q, td, ti, sd, si, cnt, lut, meta, query_bytes;
-  size_t ac, ae, ap, mb, pr, wave_bytes;
+  size_t ac, ae, ap, mb, pr, th, wave_bytes;
 };
 __host__ __device__ inline size_t align16(size_t b) { return (b + 15) & ~(size_t)15; }
 // res: the alive lists also carry each survivor's running sum of squared coordinates;
 // lut_floats: the query's quantization lookup table (BSA-O), 0 when unused
+// lag: the wave keeps the taus after its query's last lag + 1 blocks (lag > 0)
 __host__ __device__ inline Lds lds_layout(int Dp, int kmax, int block_b, int W, bool res,
-                                          int lut_floats, int p_stride) {
+                                          int lut_floats, int p_stride, int lag) {
   Lds l;
   size_t o = 0;
   l.q = o; o += align16((size_t)Dp * 4);
@@ -163,12 +164,13 @@ __host__ __device__ inline Lds lds_layout(int Dp, int kmax, int block_b, int W, 
   l.ap = o; o += res ? align16((size_t)2 * seg * 4) : 0;
   l.mb = o; o += align16((size_t)2 * (Dp / kBlockDims + 1) * 4);
   l.pr = o; o += 64 * 4;   // per-pair stage sums of a deep look-ahead round
+  l.th = o; o += lag > 0 ? align16((size_t)(lag + 1) * 4) : 0;
   l.wave_bytes = o;
   return l;
 }
 __host__ __device__ inline size_t scan_lds_bytes(int Dp, int kmax, int block_b, int W, bool res,
-                                                  int lut_floats, int p_stride) {
-  const Lds l = lds_layout(Dp, kmax, block_b, W, res, lut_floats, p_stride);
+                                                  int lut_floats, int p_stride, int lag) {
+  const Lds l = lds_layout(Dp, kmax, block_b, W, res, lut_floats, p_stride, lag);
   return (size_t)(4 / W) * l.query_bytes + 4 * l.wave_bytes;
 }
 
@@ -182,7 +184,8 @@ __host__ __device__ inline size_t scan_lds_bytes(int Dp, int kmax, int block_b, 
 // e_d + ||x_r||^2 + ||q'_r||^2 (C1 - C2).  PQ: the quantization test of BSA-O (asymmetric
 // distance from the query's lookup table in LDS and the candidate's codes, with its
 // quantization error as second feature) before the stages, whose tests are then lossless.
-template <int ST, bool PRUNE, bool LOOK, int W, bool PRE, bool RES, bool EST = false, bool PQ = false>
+template <int ST, bool PRUNE, bool LOOK, int W, bool PRE, bool RES, bool EST = false, bool PQ = false,
+          bool LAG = false>
 __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4, 8))) void scan_kernel(ScanArgs a) {
   using S = Store<ST>;
   constexpr int EPL = 16 / S::kBytes;          // elements per lane load
@@ -212,7 +215,7 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
   const int B = a.block_b;
   const int KM = a.k_max;
   const int SEG = W == 1 ? B : kTile;
-  const Lds L = lds_layout(Dp, KM, B, W, RES, PQ ? a.pq_m * 256 + Dp : 0, a.p_stride);
+  const Lds L = lds_layout(Dp, KM, B, W, RES, PQ ? a.pq_m * 256 + Dp : 0, a.p_stride, LAG ? a.lag : 0);
   unsigned char *ql = smem + (size_t)qs * L.query_bytes;
   unsigned char *wl = smem + (size_t)QPW * L.query_bytes + (size_t)wave * L.wave_bytes;
   float *s_q = reinterpret_cast<float *>(ql + L.q);
@@ -226,6 +229,7 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
   float *s_ap = reinterpret_cast<float *>(wl + L.ap);
   float *s_mb = reinterpret_cast<float *>(wl + L.mb);
   float *s_pr = reinterpret_cast<float *>(wl + L.pr);
+  float *s_th = reinterpret_cast<float *>(wl + L.th);   // taus after the last lag + 1 blocks
   float *s_lut = reinterpret_cast<float *>(ql + L.lut);
   const bool meta_lds = a.p_stride <= kMetaCap;
   int32_t *s_ml = reinterpret_cast<int32_t *>(ql + L.meta);   // list ids, lengths, first tiles
@@ -363,6 +367,7 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
   int tin = 0, tn = 0, par = 0;
   float tau = INFINITY;
   int32_t tau_id = 0x7FFFFFFF;
+  int bidx = 0;   // blocks of this query done (the lagged tau's index)
   const unsigned long long lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   int ns = 0;   // W = 1: survivors of the current block (wave-uniform)
 
@@ -405,6 +410,15 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
     for (int bs = 0; bs < len; bs += B) {
       const int blen = min(B, len - bs);
       ns = 0;
+      // the stage tests' threshold: the tau after block bidx - 1 - lag (+inf before it exists
+      // or while that queue held fewer than K); the merge below is exact against the queue
+      // (LAG: lag > 0; otherwise the current tau, +inf while the queue holds fewer than K)
+      float tau_t = tau;
+      if constexpr (LAG) {
+        const int j = bidx - 1 - a.lag;
+        tau_t = j >= 0 ? s_th[j % (a.lag + 1)] : INFINITY;
+        tau_t = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, tau_t)));
+      }
       for (int s0 = (W == 1 ? 0 : wsub * kTile); s0 < blen; s0 += (W == 1 ? blen : W * kTile)) {
       const int slen = W == 1 ? blen : min(kTile, blen - s0);
       const unsigned char *bbase = lbase + (int64_t)((bs + s0) / kTile) * nb * BLOCK_BYTES;
@@ -412,7 +426,7 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
       const float *xnorm_seg = (RES || EST) ? a.xnorm + (int64_t)toff * kTile + bs + s0 : nullptr;
       // In a load group, chunk c, lane (sub, g) reads dims [g*EPL, g*EPL+EPL) of candidate
       // t0 + c*CPW + sub; after transpose_sum the lane owns candidate t0 + g*CPW + sub.
-      if (!PRUNE || tn < K) {
+      if (!PRUNE || (LAG ? !(tau_t < INFINITY) : tn < K)) {
         // ---- no test can prune: every candidate, every dim block ----
         // Slots past slen inside the last tile are zero padding: loads stay in bounds.
         for (int t0 = 0; t0 < slen; t0 += GROUP) {
@@ -503,7 +517,7 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
             }
             const float er = a.pq_err[slot];
             const bool valid = idx < slen;
-            const bool prune = valid && fmaf(pq_m1, adc, fmaf(pq_m3, er, pq_beta)) > tau;
+            const bool prune = valid && fmaf(pq_m1, adc, fmaf(pq_m3, er, pq_beta)) > tau_t;
             const bool keep = valid && !prune;
             const unsigned long long bal = __ballot(keep);
             if (keep) {
@@ -567,7 +581,7 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
               const float e0 = transpose_sum<G8>(part, g8);
               const int idx = t0 + u * kTile + g8 * CPW8 + sub8;
               const bool valid = idx < slen;
-              const bool prune = valid && fmaf(s_mb[2 * nb], e0, s_mb[2 * nb + 1]) > tau;
+              const bool prune = valid && fmaf(s_mb[2 * nb], e0, s_mb[2 * nb + 1]) > tau_t;
               const bool keep = valid && !prune;
               const unsigned long long bal = __ballot(keep);
               if (keep) {
@@ -642,7 +656,7 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
               for (int st = 0; st < Le; ++st) {
                 ev += s_pr[lane * Lr + st];
                 const int bb = b + st;
-                if (fmaf(s_mb[2 * bb], ev, s_mb[2 * bb + 1]) > tau) { stop = st; break; }
+                if (fmaf(s_mb[2 * bb], ev, s_mb[2 * bb + 1]) > tau_t) { stop = st; break; }
               }
             }
             const bool survive = mine && stop == Le;
@@ -745,7 +759,7 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
             bool prune = false;
             if (valid && my_ss < Le) {
               const int bb = b + my_ss;
-              prune = fmaf(s_mb[2 * bb], ev, s_mb[2 * bb + 1]) > tau;
+              prune = fmaf(s_mb[2 * bb], ev, s_mb[2 * bb + 1]) > tau_t;
             }
             const unsigned long long pm = __ballot(prune);
             const uint32_t bits = (uint32_t)(pm >> (sub * G + my_cc * L)) & ((1u << L) - 1u);
@@ -842,9 +856,9 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
                 // dis' = e_s + ||x_r||^2 + ||q'_r||^2 (C1 - C2 of Alg. 1); prune iff
                 // dis' - m sigma > tau (Alg. 2)
                 const float xn = valid ? xnorm_seg[cand] : 0.f;
-                keep = keep && !(ev + (xn - pv) + mb > tau);
+                keep = keep && !(ev + (xn - pv) + mb > tau_t);
               } else {
-                keep = keep && !(fmaf(mb, ev, bb) > tau);
+                keep = keep && !(fmaf(mb, ev, bb) > tau_t);
               }
             }
             if (last) {
@@ -924,6 +938,12 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
           tau = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(s_td[tin * KM + K - 1])));
           tau_id = __builtin_amdgcn_readfirstlane(s_ti[tin * KM + K - 1]);
         }
+      }
+      if constexpr (LAG) {
+        // this block's tau into the wave's ring (every wave of the query keeps the same ring)
+        if (lane == 0) s_th[bidx % (a.lag + 1)] = tn == K ? tau : INFINITY;
+        __builtin_amdgcn_wave_barrier();
+        ++bidx;
       }
     }
   }
@@ -1103,25 +1123,58 @@ static int resident_workgroups(const void *kern, size_t smem) {
 
 size_t scan_lds_request(const ScanArgs &a, int W) {
   return scan_lds_bytes(a.nblocks * kBlockDims, a.k_max, a.block_b, W, a.res != 0,
-                        a.pq_m > 0 ? a.pq_m * 256 + a.nblocks * kBlockDims : 0, a.p_stride);
+                        a.pq_m > 0 ? a.pq_m * 256 + a.nblocks * kBlockDims : 0, a.p_stride, a.lag);
 }
 
 template <int ST, bool P, bool LK, int W, bool PRE = false, bool RES = false, bool EST = false,
-          bool PQ = false>
+          bool PQ = false, bool LG = false>
 static void launch_variant(const ScanArgs &a, hipStream_t s) {
   const size_t smem = scan_lds_bytes(a.nblocks * kBlockDims, a.k_max, a.block_b, W, RES,
-                                     PQ ? a.pq_m * 256 + a.nblocks * kBlockDims : 0, a.p_stride);
+                                     PQ ? a.pq_m * 256 + a.nblocks * kBlockDims : 0, a.p_stride,
+                                     LG ? a.lag : 0);
   if (smem > kMaxLds) throw std::runtime_error("scan: LDS request exceeds 160 KiB");
   const int qpw = 4 / W;
-  const void *kern = reinterpret_cast<const void *>(&scan_kernel<ST, P, LK, W, PRE, RES, EST, PQ>);
+  const void *kern = reinterpret_cast<const void *>(&scan_kernel<ST, P, LK, W, PRE, RES, EST, PQ, LG>);
   int64_t grid = (a.nq + qpw - 1) / qpw;
   if (a.queue) {
     // W = 1: each wave takes its own slots, so the grid covers ceil(nq / 4) workgroups at most
     grid = std::min<int64_t>(grid, resident_workgroups(kern, smem));
     hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(64), 0, s, a.queue, (int64_t)1, 0);
   }
-  hipLaunchKernelGGL((scan_kernel<ST, P, LK, W, PRE, RES, EST, PQ>), dim3((unsigned)grid),
+  hipLaunchKernelGGL((scan_kernel<ST, P, LK, W, PRE, RES, EST, PQ, LG>), dim3((unsigned)grid),
                      dim3(kScanThreads), smem, s, a);
+}
+
+// LG: the pruned kernels with a lagged threshold (lag > 0), a separate instantiation so that
+// the lag-free kernels carry none of its bookkeeping
+template <int ST, bool LG> static void launch_pruned(const ScanArgs &a, hipStream_t s) {
+  const bool w4 = a.waves_per_query == 4;
+  if (a.pq_m > 0) {
+    if (a.lookahead) {
+      if (w4) launch_variant<ST, true, true, 4, false, false, false, true, LG>(a, s);
+      else launch_variant<ST, true, true, 1, false, false, false, true, LG>(a, s);
+    } else {
+      if (w4) launch_variant<ST, true, false, 4, false, false, false, true, LG>(a, s);
+      else launch_variant<ST, true, false, 1, false, false, false, true, LG>(a, s);
+    }
+  } else if (a.res) {
+    if (w4) launch_variant<ST, true, false, 4, false, true, false, false, LG>(a, s);
+    else launch_variant<ST, true, false, 1, false, true, false, false, LG>(a, s);
+  } else if (a.pre) {
+    if (a.lookahead) {
+      if (w4) launch_variant<ST, true, true, 4, true, false, false, false, LG>(a, s);
+      else launch_variant<ST, true, true, 1, true, false, false, false, LG>(a, s);
+    } else {
+      if (w4) launch_variant<ST, true, false, 4, true, false, false, false, LG>(a, s);
+      else launch_variant<ST, true, false, 1, true, false, false, false, LG>(a, s);
+    }
+  } else if (a.lookahead) {
+    if (w4) launch_variant<ST, true, true, 4, false, false, false, false, LG>(a, s);
+    else launch_variant<ST, true, true, 1, false, false, false, false, LG>(a, s);
+  } else {
+    if (w4) launch_variant<ST, true, false, 4, false, false, false, false, LG>(a, s);
+    else launch_variant<ST, true, false, 1, false, false, false, false, LG>(a, s);
+  }
 }
 
 template <int ST> static void launch_store(const ScanArgs &a, hipStream_t s) {
@@ -1131,26 +1184,10 @@ template <int ST> static void launch_store(const ScanArgs &a, hipStream_t s) {
     else launch_variant<ST, false, false, 1, false, false, true>(a, s);
   } else if (!a.prune) {
     if (w4) launch_variant<ST, false, false, 4>(a, s); else launch_variant<ST, false, false, 1>(a, s);
-  } else if (a.pq_m > 0) {
-    if (a.lookahead) {
-      if (w4) launch_variant<ST, true, true, 4, false, false, false, true>(a, s);
-      else launch_variant<ST, true, true, 1, false, false, false, true>(a, s);
-    } else {
-      if (w4) launch_variant<ST, true, false, 4, false, false, false, true>(a, s);
-      else launch_variant<ST, true, false, 1, false, false, false, true>(a, s);
-    }
-  } else if (a.res) {
-    if (w4) launch_variant<ST, true, false, 4, false, true>(a, s); else launch_variant<ST, true, false, 1, false, true>(a, s);
-  } else if (a.pre) {
-    if (a.lookahead) {
-      if (w4) launch_variant<ST, true, true, 4, true>(a, s); else launch_variant<ST, true, true, 1, true>(a, s);
-    } else {
-      if (w4) launch_variant<ST, true, false, 4, true>(a, s); else launch_variant<ST, true, false, 1, true>(a, s);
-    }
-  } else if (a.lookahead) {
-    if (w4) launch_variant<ST, true, true, 4>(a, s); else launch_variant<ST, true, true, 1>(a, s);
+  } else if (a.lag > 0) {
+    launch_pruned<ST, true>(a, s);
   } else {
-    if (w4) launch_variant<ST, true, false, 4>(a, s); else launch_variant<ST, true, false, 1>(a, s);
+    launch_pruned<ST, false>(a, s);
   }
 }
 

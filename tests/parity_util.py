@@ -27,10 +27,10 @@ def workload(name, n=None, nq=None, n_calib=None, n_val=None, D=None):
 @functools.lru_cache(maxsize=None)
 def oracle_index(name="gauss128", nlist=64, storage="f32", delta_d=32, B=256, n=None, n_calib=None,
                  calib_k=10, calib_nprobe=8, D=None, kmeans_iters=25, seed=7, fp8_lead=0, pq_m=0,
-                 calib_k_extra=()):
+                 calib_k_extra=(), L=0):
     w = workload(name, n=n, n_calib=n_calib, D=D)
     ix = O.fit(w["base"], w["calib"], nlist=nlist, delta_d=delta_d, storage=storage,
-               kmeans_iters=kmeans_iters, calib_k=calib_k, calib_nprobe=calib_nprobe, B=B, seed=seed,
+               kmeans_iters=kmeans_iters, calib_k=calib_k, calib_nprobe=calib_nprobe, B=B, L=L, seed=seed,
                fp8_lead=fp8_lead, pq_m=pq_m, pq_iters=8, calib_k_extra=calib_k_extra)
     # centroids handed to the GPU in float32: the oracle uses the same float32 values
     ix["centroids"] = ix["centroids"].astype(np.float32).astype(np.float64)
@@ -40,7 +40,7 @@ def oracle_index(name="gauss128", nlist=64, storage="f32", delta_d=32, B=256, n=
 def artifacts(ix, with_table=True):
     art = dict(mu=ix["mu"], R=ix["R"], lam=ix["lam"], centroids=ix["centroids"].astype(np.float32),
                assign=ix["assign"].astype(np.int32), y=ix["Y"].astype(np.float32),
-               storage=ix["storage"], delta_d=ix["delta_d"], block_b=ix["B"])
+               storage=ix["storage"], delta_d=ix["delta_d"], block_b=ix["B"], lag_l=ix.get("L", 0))
     if ix.get("pre") is not None:
         art["fp8_lead_dims"] = ix["pre"]["lead"]
     if ix.get("pq") is not None:

@@ -96,7 +96,7 @@ def test_fit_rejects_bad_parameters_without_device(lib):
     base = np.zeros((100, 16), np.float32)
     cal = np.zeros((10, 16), np.float32)
     out = C.c_void_p()
-    cases = [dict(nlist=0), dict(nlist=200), dict(delta_d=16), dict(block_b=100), dict(lag_l=1),
+    cases = [dict(nlist=0), dict(nlist=200), dict(delta_d=16), dict(block_b=100), dict(lag_l=-1), dict(lag_l=65),
              dict(calib_k=0), dict(calib_max_neg=0), dict(storage=7)]
     for kw in cases:
         p = B.default_params(nlist=4)
@@ -130,8 +130,9 @@ def test_import_rejects_bad_artifacts_without_device(lib):
         assign.ctypes.data, y.ctypes.data
     assert lib.ddc_import(C.byref(a), C.byref(out)) == -1
     assert b"assign" in lib.ddc_last_error()
-    a.lag_l = 2
-    assert lib.ddc_import(C.byref(a), C.byref(out)) == -6
+    a.lag_l = 65
+    assert lib.ddc_import(C.byref(a), C.byref(out)) == -1
+    assert b"lag_l" in lib.ddc_last_error()
 
 
 def test_correction_rejects_bad_significance(lib):

@@ -4,6 +4,7 @@ Each test checks an oracle function against something other than itself: a close
 form, a published value, an invariant, a library routine or brute force on a tiny
 input.  Paper references are to sections, equations, theorems and algorithms.
 """
+import heapq
 import math
 import os
 
@@ -258,6 +259,66 @@ def test_lag_beyond_block_count_disables_pruning(small_index, small_workload):
     r0 = O.search(ix, small_workload["queries"][:8], 10, 8, 0.0, mode="none")
     np.testing.assert_array_equal(r1["ids"], r0["ids"])
     assert r1["stops"][:, :-1].sum() == 0
+
+
+def _lagged_heap_search(q, Y, off, ids, probes, k, m, beta, bounds, lag):
+    """Per-candidate refinement with a lagged threshold, coded with heapq in this test: the
+    c-th candidate of the scan is tested against the tau in force after candidate c-1-lag
+    (+inf before it exists or while the queue held fewer than k)."""
+    heap, taus = [], []   # heap of (-dis, -id); taus[c] = tau after candidate c
+    stops = [0] * len(bounds)
+    q = np.asarray(q, np.float64)
+    c = 0
+    for lst in probes:
+        for pos in range(int(off[lst]), int(off[lst + 1])):
+            x = int(ids[pos])
+            j = c - 1 - lag
+            tau = taus[j] if j >= 0 else math.inf
+            diff = q - Y[x]
+            pruned = False
+            if tau != math.inf:
+                for s in range(len(bounds) - 1):
+                    e = float(np.sum(diff[:bounds[s]] ** 2))
+                    if m[s] * e + beta[s] > tau:
+                        pruned = True
+                        stops[s] += 1
+                        break
+            if not pruned:
+                stops[-1] += 1
+                d = float(np.sum(diff ** 2))
+                if len(heap) < k:
+                    heapq.heappush(heap, (-d, -x))
+                elif (d, x) < (-heap[0][0], -heap[0][1]):
+                    heapq.heapreplace(heap, (-d, -x))
+            taus.append(-heap[0][0] if len(heap) == k else math.inf)
+            c += 1
+    best = sorted((-a, -b) for a, b in heap)
+    return [b for _, b in best], [a for a, _ in best], stops
+
+
+@pytest.mark.parametrize("lag", [1, 3])
+def test_block_of_one_with_lag_equals_lagged_heap_loop(small_index, small_workload, lag):
+    """B = 1, L > 0: candidate c is tested against the tau after candidate c-1-L; the oracle's
+    block-synchronous search equals a separately coded heap loop keeping every tau, and the
+    lag changes what is pruned."""
+    ix = small_index
+    beta = O.beta_for_alpha(ix["G"], 0.1)
+    qr = O.rotate(small_workload["queries"][:6], ix["mu"], ix["R"])
+    pruned_lag = pruned0 = 0
+    for q in qr:
+        probes, _, _ = O.probe_order(q, ix["centroids"], 3)
+        a_ids, a_d, stops, _ = O.search_one(q, ix["Y"], ix["list_off"], ix["list_ids"], probes, 10,
+                                            ix["m"], beta, ix["bounds"], B=1, L=lag)
+        b_ids, b_d, b_st = _lagged_heap_search(q, ix["Y"], ix["list_off"], ix["list_ids"], probes, 10,
+                                         ix["m"], beta, ix["bounds"], lag)
+        assert a_ids.tolist() == b_ids
+        np.testing.assert_allclose(a_d, b_d, rtol=1e-12)
+        assert stops.tolist() == b_st   # the same candidate pruned at the same stage
+        _, _, st0, _ = O.search_one(q, ix["Y"], ix["list_off"], ix["list_ids"], probes, 10,
+                                    ix["m"], beta, ix["bounds"], B=1, L=0)
+        pruned_lag += int(stops[:-1].sum())
+        pruned0 += int(st0[:-1].sum())
+    assert 0 < pruned_lag != pruned0
 
 
 def test_returned_distances_are_exact_for_stored_vectors(small_index, small_workload):
