@@ -480,7 +480,8 @@ def main():
         try:
             pm = json.load(open(pmc_file))
             tuned_name = (f"void ddc::scan_kernel<{info['storage']}, true, {'true' if chosen[1] else 'false'}, "
-                          f"{chosen[0]}, {'true' if cfg.get('fp8') else 'false'}, false, false, false>(ddc::ScanArgs)")
+                          f"{chosen[0]}, {'true' if cfg.get('fp8') else 'false'}, false, false, false, "
+                          f"{'true' if info['lag_l'] > 0 else 'false'}>(ddc::ScanArgs)")
             if pm.get("kernel_hash") == kernel_hash() and pm.get("nprobe") == nprobe and \
                     abs(pm.get("alpha", -1) - alpha) < 1e-12 and pm.get("kernel") == tuned_name and \
                     pm.get("persistent", 0) == chosen[2]:
