@@ -103,3 +103,50 @@ def test_gpu_calibration_with_lag_equals_oracle(L):
         np.testing.assert_allclose(m, ix["m"], rtol=1e-6)
         ref = O.beta_for_alpha(ix["G"], a)
         np.testing.assert_allclose(b, ref, rtol=1e-6, atol=1e-9 * np.abs(ref).max())
+
+
+def test_lagged_residual_test_matches_oracle():
+    """The residual-estimate test (Alg. 2, incremental) under a lagged threshold, in every
+    launch shape that runs it."""
+    ix = oracle_index(B=64, L=2, n_calib=300)
+    w = workload("gauss128")
+    g = _index(ix)
+    g.set_bsar_multiplier(3.0)
+    Q = w["queries"]
+    res = []
+    for wv in (1, 4):
+        for p in (0, 1):
+            g.set_launch(waves_per_query=wv, lookahead=0, persistent=p)
+            res.append(g.search(Q, 10, 8, 0.0, mode="bsar"))
+    g.set_launch(waves_per_query=0, lookahead=-1, persistent=-1)
+    for r in res[1:]:
+        np.testing.assert_array_equal(res[0][0], r[0])
+        np.testing.assert_array_equal(res[0][1], r[1])
+    ids, d, st = res[0]
+    ora = O.search(dict(ix, bsar_m=3.0), Q, 10, 8, 0.0, mode="bsar")
+    r = check_search(ids, d, ora, ix)
+    assert not r["bad"], r["bad"][:5]
+    assert r["excused"] <= 0.05 * r["nq"] + 1
+    assert st["candidates"] == int(ora["stops"].sum())
+    assert abs(st["refined"] - int(ora["stops"][:, -1].sum())) <= 0.01 * st["candidates"] + 5
+
+
+def test_lagged_quantization_test_matches_oracle():
+    """BSA-O's quantization test before the refinement, under a lagged threshold, in every
+    launch shape."""
+    ix = oracle_index(B=64, L=2, pq_m=32, n_calib=400)
+    w = workload("gauss128")
+    g = _index(ix)
+    Q = w["queries"]
+    res = _all_variants(g, lambda: g.search(Q, 10, 8, 0.1, mode="bsao"))
+    for r in res[1:]:
+        np.testing.assert_array_equal(res[0][0], r[0])
+        np.testing.assert_array_equal(res[0][1], r[1])
+        assert r[2]["prestage_pruned"] == res[0][2]["prestage_pruned"]
+    ids, d, st = res[0]
+    ora = O.search(ix, Q, 10, 8, 0.1, mode="bsao")
+    r = check_search(ids, d, ora, ix)
+    assert not r["bad"], r["bad"][:5]
+    assert r["excused"] <= 0.05 * r["nq"] + 1
+    assert 0 < st["prestage_pruned"]
+    assert abs(st["prestage_pruned"] - int(ora["stops"][:, 0].sum())) <= 0.01 * st["candidates"] + 5
