@@ -129,8 +129,8 @@ typedef struct {
   int32_t dim;            /* D */
   int32_t nlist;
   int32_t delta_d;
-  int32_t block_b;
-  int32_t lag_l;
+  int32_t block_b;        /* as ddc_params.block_b */
+  int32_t lag_l;          /* as ddc_params.lag_l, 0..64 */
   ddc_dtype storage;
   ddc_rot rotation;
   int32_t fp8_lead_dims;  /* 0 or 64 (import encodes the codes from y) */
