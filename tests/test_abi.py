@@ -177,3 +177,27 @@ def test_fit_rejects_bad_table_and_fp8_parameters_without_device(lib):
         rc = lib.ddc_fit(base.ctypes.data, 100, 16, cal.ctypes.data, 10, C.byref(p), C.byref(out))
         assert rc == -1, kw
         assert out.value is None
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """No fallback: with the library absent the first call raises instead of computing."""
+    from paper_2404_16322_amd import binding
+    monkeypatch.setattr(binding, "_LIB", None)
+    monkeypatch.setattr(binding, "lib_path", lambda: str(tmp_path / "libddc.so"))
+    with pytest.raises(RuntimeError, match="not built"):
+        binding.load_library()
+    with pytest.raises(RuntimeError, match="not built"):
+        binding.default_params(nlist=4)
+
+
+def test_product_package_never_loads_the_oracle():
+    """The package and its library load without the oracle (test infrastructure only)."""
+    import sys
+    code = ("import sys; import paper_2404_16322_amd as P; P.load_library(); "
+            "P.binding.default_params(nlist=4); "
+            "bad = [m for m in sys.modules if m == 'oracle' or m.startswith('oracle.')]; "
+            "assert not bad, bad")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 0, r.stderr[-2000:]
