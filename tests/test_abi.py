@@ -201,3 +201,24 @@ def test_product_package_never_loads_the_oracle():
     r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True,
                        timeout=120)
     assert r.returncode == 0, r.stderr[-2000:]
+
+
+def test_oracle_and_product_share_no_code():
+    """Neither side imports, includes or links the other: the package's sources never name
+    the oracle, and the oracle's sources never name the package, its C++ sources or header."""
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    pkg = os.path.join(root, "paper_2404_16322_amd")
+    use_oracle = re.compile(r"^\s*(import\s+oracle\b|from\s+oracle\b|#\s*include\s*[<\"].*oracle)", re.M)
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".cpp", ".hip", ".h")):
+                txt = open(os.path.join(dirpath, f), encoding="utf-8").read()
+                assert not use_oracle.search(txt), os.path.join(dirpath, f)
+    use_pkg = re.compile(r"^\s*(import\s+paper_2404_16322_amd|from\s+paper_2404_16322_amd|"
+                         r".*\bcsrc\b|.*ddc\.h|.*libddc)", re.M)
+    for f in os.listdir(os.path.join(root, "oracle")):
+        if f.endswith(".py"):
+            txt = open(os.path.join(root, "oracle", f), encoding="utf-8").read()
+            code = "\n".join(l for l in txt.splitlines() if not l.lstrip().startswith("#"))
+            code = re.sub(r'"""(?:.|\n)*?"""', "", code)
+            assert not use_pkg.search(code), f
