@@ -1562,6 +1562,7 @@ ddc_status ddc_scan_variant(ddc_index *ix, int64_t nq, int32_t k_max, int32_t np
     ScanArgs la{};
     la.nblocks = ix->NB; la.k_max = k_max; la.block_b = ix->B; la.res = mode == DDC_CORR_BSAR;
     la.pq_m = mode == DDC_CORR_BSAO ? ix->pq_m : 0;
+    la.p_stride = nprobe_max; la.lag = ix->L;   // as the search sets them
     if (scan_lds_request(la, v[0]) > kMaxLds) v[0] = 4;
   }
   {
