@@ -261,46 +261,51 @@ def test_lag_beyond_block_count_disables_pruning(small_index, small_workload):
     assert r1["stops"][:, :-1].sum() == 0
 
 
-def _lagged_heap_search(q, Y, off, ids, probes, k, m, beta, bounds, lag):
-    """Per-candidate refinement with a lagged threshold, coded with heapq in this test: the
-    c-th candidate of the scan is tested against the tau in force after candidate c-1-lag
-    (+inf before it exists or while the queue held fewer than k)."""
-    heap, taus = [], []   # heap of (-dis, -id); taus[c] = tau after candidate c
+def _lagged_heap_search(q, Y, off, ids, probes, k, m, beta, bounds, lag, B=1):
+    """Block-synchronous refinement with a lagged threshold, coded with heapq in this test:
+    each list is cut into blocks of B consecutive positions; every candidate of block b is
+    tested against the tau in force after block b-1-lag (+inf before it exists or while the
+    queue held fewer than k); the block's survivors then enter the queue one by one."""
+    heap, taus = [], []   # heap of (-dis, -id); taus[b] = tau after block b
     stops = [0] * len(bounds)
     q = np.asarray(q, np.float64)
-    c = 0
+    b = 0
     for lst in probes:
-        for pos in range(int(off[lst]), int(off[lst + 1])):
-            x = int(ids[pos])
-            j = c - 1 - lag
+        lo_l, hi_l = int(off[lst]), int(off[lst + 1])
+        for start in range(lo_l, hi_l, B):
+            j = b - 1 - lag
             tau = taus[j] if j >= 0 else math.inf
-            diff = q - Y[x]
-            pruned = False
-            if tau != math.inf:
-                for s in range(len(bounds) - 1):
-                    e = float(np.sum(diff[:bounds[s]] ** 2))
-                    if m[s] * e + beta[s] > tau:
-                        pruned = True
-                        stops[s] += 1
-                        break
-            if not pruned:
-                stops[-1] += 1
-                d = float(np.sum(diff ** 2))
+            survivors = []
+            for pos in range(start, min(start + B, hi_l)):
+                x = int(ids[pos])
+                diff = q - Y[x]
+                pruned = False
+                if tau != math.inf:
+                    for s in range(len(bounds) - 1):
+                        e = float(np.sum(diff[:bounds[s]] ** 2))
+                        if m[s] * e + beta[s] > tau:
+                            pruned = True
+                            stops[s] += 1
+                            break
+                if not pruned:
+                    stops[-1] += 1
+                    survivors.append((float(np.sum(diff ** 2)), x))
+            for d, x in survivors:
                 if len(heap) < k:
                     heapq.heappush(heap, (-d, -x))
                 elif (d, x) < (-heap[0][0], -heap[0][1]):
                     heapq.heapreplace(heap, (-d, -x))
             taus.append(-heap[0][0] if len(heap) == k else math.inf)
-            c += 1
-    best = sorted((-a, -b) for a, b in heap)
-    return [b for _, b in best], [a for a, _ in best], stops
+            b += 1
+    best = sorted((-a, -c) for a, c in heap)
+    return [c for _, c in best], [a for a, _ in best], stops
 
 
-@pytest.mark.parametrize("lag", [1, 3])
-def test_block_of_one_with_lag_equals_lagged_heap_loop(small_index, small_workload, lag):
-    """B = 1, L > 0: candidate c is tested against the tau after candidate c-1-L; the oracle's
-    block-synchronous search equals a separately coded heap loop keeping every tau, and the
-    lag changes what is pruned."""
+@pytest.mark.parametrize("B,lag", [(1, 1), (1, 3), (16, 1), (64, 1), (64, 3)])
+def test_lagged_blocks_equal_heap_loop(small_index, small_workload, B, lag):
+    """Block b is tested against the tau after block b-1-L; the oracle's block-synchronous
+    search equals a separately coded heap loop keeping every block's tau (ids, distances and
+    the stage each candidate stopped at), and the lag changes what is pruned."""
     ix = small_index
     beta = O.beta_for_alpha(ix["G"], 0.1)
     qr = O.rotate(small_workload["queries"][:6], ix["mu"], ix["R"])
@@ -308,14 +313,14 @@ def test_block_of_one_with_lag_equals_lagged_heap_loop(small_index, small_worklo
     for q in qr:
         probes, _, _ = O.probe_order(q, ix["centroids"], 3)
         a_ids, a_d, stops, _ = O.search_one(q, ix["Y"], ix["list_off"], ix["list_ids"], probes, 10,
-                                            ix["m"], beta, ix["bounds"], B=1, L=lag)
+                                            ix["m"], beta, ix["bounds"], B=B, L=lag)
         b_ids, b_d, b_st = _lagged_heap_search(q, ix["Y"], ix["list_off"], ix["list_ids"], probes, 10,
-                                         ix["m"], beta, ix["bounds"], lag)
+                                               ix["m"], beta, ix["bounds"], lag, B)
         assert a_ids.tolist() == b_ids
         np.testing.assert_allclose(a_d, b_d, rtol=1e-12)
-        assert stops.tolist() == b_st   # the same candidate pruned at the same stage
+        assert stops.tolist() == b_st   # the same candidates pruned at the same stages
         _, _, st0, _ = O.search_one(q, ix["Y"], ix["list_off"], ix["list_ids"], probes, 10,
-                                    ix["m"], beta, ix["bounds"], B=1, L=0)
+                                    ix["m"], beta, ix["bounds"], B=B, L=0)
         pruned_lag += int(stops[:-1].sum())
         pruned0 += int(st0[:-1].sum())
     assert 0 < pruned_lag != pruned0
