@@ -976,3 +976,17 @@ def test_bsao_heldout_false_prune_rate_matches_significance(pq_index, small_work
                           for _ in range(2000)])
         lo, hi = np.quantile(boots, [0.005, 0.995])
         assert abs(rate - a) <= (hi - lo) / 2 * math.sqrt(2), (a, rate)
+
+
+def test_lag_beyond_every_training_scan_leaves_label_one_empty():
+    """With a lag longer than any training query's block count no candidate meets a finite
+    tau_b: the label-1 pool is empty, no classifier is fitted (m_s = 1), and the label-0
+    residuals are tau - e_s, non-negative since e_s <= dis <= tau (Eq. (1))."""
+    w = synthdata.make_workload("gauss128", n_calib=60)
+    ix = O.fit(w["base"], w["calib"], nlist=64, kmeans_iters=5, calib_k=10, calib_nprobe=8,
+               seed=7, B=1024, L=64)
+    cal = ix["calib"]
+    assert cal["neg_e"].shape[0] == 0
+    np.testing.assert_array_equal(ix["m"], np.ones_like(ix["m"]))
+    np.testing.assert_allclose(ix["G"], cal["pos_tau"][:, None] - cal["pos_e"], rtol=0, atol=0)
+    assert np.all(ix["G"] >= 0)
