@@ -204,7 +204,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
-              f"(the search shards by query with no exchange; see the design notes)", flush=True)
+              f"(the search would shard by query, each GPU holding the index, with no exchange)", flush=True)
         sys.exit(2)
 
     import torch
