@@ -497,7 +497,7 @@ def partial_dists(Yc: np.ndarray, qrot: np.ndarray, bounds: np.ndarray) -> np.nd
 def bsar_terms(qrot: np.ndarray, lam: np.ndarray, bounds: np.ndarray):
     """Per test stage s (residual dims i >= d_s): ||q'_r||^2 and sigma_s = the standard
     deviation of the omitted cross term -2 <q'_r, x_r>, sqrt(4 sum_i q'_i^2 lam_i), when x is
-    distributed with variance lam_i along rotated axis i [Eq. (2); Alg. 1 line 3]."""
+    distributed with variance lam_i along rotated axis i [Eq. (2); the sigma of Alg. 1]."""
     q = np.asarray(qrot, dtype=np.float64)
     qr = np.array([np.sum(q[d:] ** 2) for d in bounds[:-1]])
     sig = np.array([math.sqrt(4.0 * np.sum(q[d:] ** 2 * lam[d:])) for d in bounds[:-1]])
