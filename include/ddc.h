@@ -214,7 +214,8 @@ ddc_status ddc_load(const char *path, ddc_index **out);
 
 /* Re-run the calibration of Sec. V-A on new training queries (e.g. ~100 out-of-distribution
  * queries, Sec. V-C) and replace the index's correction tables: one table at K_c = calib_k,
- * or, with calib_k = 0, one at every K_c the index has now.  calib: host [n_calib x dim]. */
+ * or, with calib_k = 0, one at every K_c the index has now.  calib: host [n_calib x dim].
+ * The label-1 candidates come from an unpruned search with the index's block_b and lag_l. */
 ddc_status ddc_calibrate(ddc_index *ix, const float *calib, int64_t n_calib, int32_t calib_k,
                          int32_t calib_nprobe, int32_t calib_max_neg, uint64_t seed);
 
