@@ -225,6 +225,33 @@ def round_storage(y: np.ndarray, dtype: str) -> np.ndarray:
     return out.astype(np.float64)
 
 
+def rotate_bf16(X: np.ndarray, mu: np.ndarray, R: np.ndarray) -> np.ndarray:
+    """x_D = R (x - mu) [Eq. (1)] with both operands of the product rounded to bfloat16.
+
+    Reading for a query rotation on BF16 matrix units (the paper rotates in FP32): the
+    query and the mean are FP32 values, the centred query is their FP32 difference
+    (correctly rounded), then rounded to bfloat16 (nearest, ties to even); every entry of R
+    is rounded to FP32 and then to bfloat16 the same way (the storage rule of
+    ``round_storage``).  The product of the two rounded operands is then taken exactly up
+    to FP64 rounding, so this reading fixes the operands and leaves only the summation
+    order of an FP32 accumulation open."""
+    x32 = np.asarray(X, dtype=np.float32)
+    mu32 = np.asarray(mu, dtype=np.float64).astype(np.float32)
+    c = _bf16_round_f32((x32 - mu32[None, :]).astype(np.float32)).astype(np.float64)
+    Rb = _bf16_round_f32(np.asarray(R, dtype=np.float64).astype(np.float32)).astype(np.float64)
+    return c @ Rb.T
+
+
+def rotate_as(X: np.ndarray, mu: np.ndarray, R: np.ndarray, rotation: str = "f32") -> np.ndarray:
+    """The query rotation a search takes: ``rotate`` (FP64, the paper's FP32 reading within
+    rounding) for rotation 'f32', ``rotate_bf16`` for 'bf16'."""
+    if rotation == "f32":
+        return rotate(X, mu, R)
+    if rotation == "bf16":
+        return rotate_bf16(X, mu, R)
+    raise ValueError(rotation)
+
+
 # --------------------------------------------------------------------------------------
 # FP8 pre-stage codes.  Not in the paper (it stores FP32 only, Sec. VII-A); the paper's
 # argument that the learned correction absorbs whatever error the estimate carries
@@ -516,7 +543,8 @@ def _rel(a, b, c):
 
 
 def search_one(qrot, Y, list_off, list_ids, probes, k, m, beta, bounds, B=256, L=0,
-               prune=True, collect_neg=None, pre=None, res=None, pq=None):
+               prune=True, collect_neg=None, pre=None, res=None, pq=None, log=None, flip=(),
+               near_tol=1e-4):
     """Canonical block-synchronous pruned refinement for one rotated query.
 
     The paper's refinement updates tau after every candidate [Sec. I: result queue Q with
@@ -547,6 +575,16 @@ def search_one(qrot, Y, list_off, list_ids, probes, k, m, beta, bounds, B=256, L
     ``pq_adc``, err = its ``pq_error``), entry 0 of stop_counts counting them; survivors are
     refined over all dims (with m = 1, beta = -inf no stage test fires: the paper's BSA-O is
     one classifier, not incremental).
+
+    Near-threshold log (parity with other rounding): if ``log`` is a dict it receives
+      'stage': ids with an evaluated test whose decision quantity lies within ``near_tol``
+               (relative) of tau_b,
+      'near':  those ids plus every id whose distance lies within ``near_tol`` of the K-th
+               distance of a merge that cut the queue, or of a neighbour in the final order.
+    ``flip`` (ids): for each listed candidate the outcome of its first evaluated test within
+    ``near_tol`` of its threshold is inverted (a pass becomes a prune and the other way
+    round); its walk through the later tests continues as usual.  This replays the search
+    as hardware whose rounding took that one decision the other way.
     """
     S = bounds.shape[0]
     T_d = np.zeros(0)
@@ -555,6 +593,8 @@ def search_one(qrot, Y, list_off, list_ids, probes, k, m, beta, bounds, B=256, L
     P = 1 if (pre is not None or pq is not None) else 0
     stop_counts = np.zeros(S + P, dtype=np.int64)
     margin = math.inf
+    flip = set(int(x) for x in flip)
+    near_stage, near_all = set(), set()
     b = 0
     for lst in probes:
         lo, hi = int(list_off[lst]), int(list_off[lst + 1])
@@ -563,26 +603,23 @@ def search_one(qrot, Y, list_off, list_ids, probes, k, m, beta, bounds, B=256, L
             j = b - 1 - L
             tau_b = tau_hist[j] if j >= 0 else math.inf
             e = partial_dists(Y[ids], qrot, bounds)          # (nb, S)
-            stop = np.full(ids.shape[0], S - 1, dtype=np.int64)
-            pre_hit = np.zeros(ids.shape[0], dtype=bool)
+            # every test this block can take, in test order: (prune outcome, relative margin)
+            hits, rels = [], []
             if prune and pre is not None and math.isfinite(tau_b):
                 dec, m0, beta0 = pre
                 lead = dec.shape[1]
                 e0 = partial_dists(dec[ids], qrot[:lead], np.array([lead]))[:, 0]
                 lhs0 = m0 * e0 + beta0
-                pre_hit = lhs0 > tau_b
-                rel0 = np.abs(lhs0 - tau_b) / _rel(m0 * e0, np.full_like(e0, beta0), tau_b)
-                if rel0.size:
-                    margin = min(margin, float(rel0.min()))
+                hits.append(lhs0 > tau_b)
+                rels.append(np.abs(lhs0 - tau_b) / _rel(m0 * e0, np.full_like(e0, beta0), tau_b))
             if prune and pq is not None and math.isfinite(tau_b):
                 lut, codes, err, m1, m3, beta0 = pq
                 adc = pq_adc(lut, codes[ids])
                 lhs0 = m1 * adc + m3 * err[ids] + beta0
-                pre_hit = lhs0 > tau_b
-                rel0 = np.abs(lhs0 - tau_b) / (np.abs(m1 * adc) + np.abs(m3 * err[ids]) + abs(beta0)
-                                               + abs(tau_b) + 1e-300)
-                if rel0.size:
-                    margin = min(margin, float(rel0.min()))
+                hits.append(lhs0 > tau_b)
+                rels.append(np.abs(lhs0 - tau_b) / (np.abs(m1 * adc) + np.abs(m3 * err[ids]) + abs(beta0)
+                                                    + abs(tau_b) + 1e-300))
+            P_b = len(hits)                                  # 1 if the pre-test ran on this block
             if prune and math.isfinite(tau_b) and S > 1 and (res is not None or np.isfinite(beta).any()):
                 if res is None:
                     lhs = e[:, :S - 1] * m[None, :] + beta[None, :]   # (nb, S-1)
@@ -592,15 +629,36 @@ def search_one(qrot, Y, list_off, list_ids, probes, k, m, beta, bounds, B=256, L
                     xr = residual_norms(Y[ids], bounds)
                     lhs = e[:, :S - 1] + xr + qr[None, :] - msig[None, :]
                     scale = np.abs(e[:, :S - 1]) + xr + qr[None, :] + msig[None, :] + abs(tau_b)
-                hit = lhs > tau_b
-                any_hit = hit.any(axis=1)
-                first = np.where(any_hit, hit.argmax(axis=1), S - 1)
-                stop = first
-                # decision margins of every evaluated test (stages <= stop)
-                evaluated = (np.arange(S - 1)[None, :] <= first[:, None]) & ~pre_hit[:, None]
-                rel = np.abs(lhs - tau_b) / scale
+                for st in range(S - 1):
+                    hits.append(lhs[:, st] > tau_b)
+                    with np.errstate(invalid="ignore"):
+                        rels.append(np.abs(lhs[:, st] - tau_b) / scale[:, st])
+            nt = len(hits)
+            if nt:
+                H = np.column_stack(hits)
+                Rl = np.nan_to_num(np.column_stack(rels), nan=math.inf)
+                first = np.where(H.any(axis=1), H.argmax(axis=1), nt)   # nt: no test prunes
+                for r in range(ids.shape[0]):
+                    if int(ids[r]) in flip:
+                        first[r] = nt
+                        flipped = False
+                        for t in range(nt):
+                            h = bool(H[r, t])
+                            if not flipped and Rl[r, t] < near_tol:
+                                h, flipped = not h, True
+                            if h:
+                                first[r] = t
+                                break
+                evaluated = np.arange(nt)[None, :] <= first[:, None]
                 if evaluated.any():
-                    margin = min(margin, float(rel[evaluated].min()))
+                    margin = min(margin, float(Rl[evaluated].min()))
+                close = (evaluated & (Rl < near_tol)).any(axis=1)
+                for x in ids[close]:
+                    near_stage.add(int(x))
+            else:
+                first = np.zeros(ids.shape[0], dtype=np.int64)
+            pre_hit = (first == 0) if P_b else np.zeros(ids.shape[0], dtype=bool)
+            stop = np.where(first >= nt, S - 1, first - P_b) if nt else np.full(ids.shape[0], S - 1)
             np.add.at(stop_counts, stop[~pre_hit] + P, 1)
             if P:
                 stop_counts[0] += int(pre_hit.sum())
@@ -619,6 +677,9 @@ def search_one(qrot, Y, list_off, list_ids, probes, k, m, beta, bounds, B=256, L
             if order.shape[0] > k:
                 dk, dk1 = all_d[order[k - 1]], all_d[order[k]]
                 margin = min(margin, float(abs(dk1 - dk) / max(abs(dk1), 1e-300)))
+                close = np.abs(all_d - dk) <= near_tol * max(abs(dk), 1e-300)
+                if close.sum() > 1:
+                    near_all.update(int(x) for x in all_i[close])
             order = order[:k]
             T_d, T_i = all_d[order], all_i[order]
             tau_hist.append(float(T_d[k - 1]) if T_d.shape[0] == k else math.inf)
@@ -626,6 +687,11 @@ def search_one(qrot, Y, list_off, list_ids, probes, k, m, beta, bounds, B=256, L
     if T_d.shape[0] > 1:
         gaps = np.abs(np.diff(T_d)) / np.maximum(np.abs(T_d[1:]), 1e-300)
         margin = min(margin, float(gaps.min()))
+        for i in np.nonzero(gaps < near_tol)[0]:
+            near_all.update((int(T_i[i]), int(T_i[i + 1])))
+    if log is not None:
+        log["stage"] = sorted(near_stage)
+        log["near"] = near_all | near_stage
     ids_out = np.full(k, -1, dtype=np.int64)
     d_out = np.full(k, np.inf)
     ids_out[:T_i.shape[0]] = T_i
@@ -984,13 +1050,21 @@ def table_for_k(index, k):
     return best["m"], best["G"]
 
 
-def search(index, queries, k, nprobe, alpha, mode="learned", B=None, L=None, calib_mode="joint"):
+def search(index, queries, k, nprobe, alpha, mode="learned", B=None, L=None, calib_mode="joint",
+           flip=None, probe_swap=None, near_tol=1e-4):
     """Search every query; mode in {'learned', 'lossless', 'none', 'ads', 'bsar', 'bsao'}
     ('ads': the ADSampling test of ``ads_table`` with index["ads_eps0"], default 2.1; 'bsar':
     the residual-estimate test with multiplier index["bsar_m"], default 8, or Phi^-1(1 - alpha)
     when that is <= 0; 'bsao': the OPQ estimate with its learned classifier, index fitted
-    with pq_m > 0).
-    Returns ids (nq, k), dists (nq, k), stop_counts (nq, S), margin (nq,)."""
+    with pq_m > 0).  The queries are rotated as index["rotation"] says ('f32' default,
+    'bf16': ``rotate_bf16``).
+    Returns ids (nq, k), dists (nq, k), stop_counts (nq, S), margin (nq,), and per query the
+    near-threshold log of ``search_one`` ('near', 'stage_near') plus 'probe_near': the
+    positions i < nprobe whose ranked centroid distances i and i + 1 lie within ``near_tol``
+    (relative) of each other.
+    Replays under other rounding: ``flip`` = {query: ids} passes those ids to ``search_one``;
+    ``probe_swap`` = {query: i} exchanges the lists ranked i and i + 1 (i + 1 = nprobe brings
+    in the next list in place of the last probed one)."""
     B = index["B"] if B is None else B
     L = index["L"] if L is None else L
     bounds = index["bounds"]
@@ -1022,7 +1096,7 @@ def search(index, queries, k, nprobe, alpha, mode="learned", B=None, L=None, cal
         m, beta, prune = np.ones(St), np.full(St, -np.inf), alpha > 0
     else:
         raise ValueError(mode)
-    Qr = rotate(queries, index["mu"], index["R"])
+    Qr = rotate_as(queries, index["mu"], index["R"], index.get("rotation", "f32"))
     nq = Qr.shape[0]
     ids = np.full((nq, k), -1, dtype=np.int64)
     ds = np.full((nq, k), np.inf)
@@ -1030,8 +1104,20 @@ def search(index, queries, k, nprobe, alpha, mode="learned", B=None, L=None, cal
                      dtype=np.int64)
     margins = np.full(nq, math.inf)
     probes_all = np.zeros((nq, nprobe), dtype=np.int64)
+    near, stage_near, probe_near = [], [], []
+    nl = index["centroids"].shape[0]
     for qi in range(nq):
-        probes, _, pm = probe_order(Qr[qi], index["centroids"], nprobe)
+        ranked, rd, pm = probe_order(Qr[qi], index["centroids"], min(nprobe + 1, nl))
+        gaps = np.abs(np.diff(rd)) / np.maximum(np.abs(rd[1:]), 1e-300)
+        probe_near.append([int(i) for i in np.nonzero(gaps < near_tol)[0] if i < nprobe])
+        probes = ranked[:nprobe].copy()
+        pm = float(gaps.min()) if gaps.size else math.inf
+        if probe_swap and qi in probe_swap:
+            i = probe_swap[qi]
+            if i + 1 < nprobe:
+                probes[i], probes[i + 1] = probes[i + 1], probes[i]
+            elif i + 1 == nprobe and ranked.shape[0] > nprobe:
+                probes[i] = ranked[nprobe]
         probes_all[qi] = probes
         res = None
         if mode == "bsar":
@@ -1042,12 +1128,18 @@ def search(index, queries, k, nprobe, alpha, mode="learned", B=None, L=None, cal
             pqix = index["pq"]
             pqa = (pq_lut(Qr[qi], pqix["perm"], pqix["books"]), pqix["codes"], pqix["err"], m1, m3,
                    beta_q)
+        lg = {}
         i, d, st, mg = search_one(Qr[qi], index["Y"], index["list_off"], index["list_ids"], probes,
                                   k, m, beta, bounds, B, L, prune, pre=pre if prune else None, res=res,
-                                  pq=pqa)
+                                  pq=pqa, log=lg, flip=(flip or {}).get(qi, ()), near_tol=near_tol)
         ids[qi], ds[qi], stops[qi], margins[qi] = i, d, st, min(mg, pm)
+        near.append(lg["near"])
+        stage_near.append(lg["stage"])
     return dict(ids=ids, dists=ds, stops=stops, margin=margins, probes=probes_all, qrot=Qr, m=m,
-                beta=beta)
+                beta=beta, near=near, stage_near=stage_near, probe_near=probe_near,
+                queries=np.asarray(queries),
+                args=dict(k=k, nprobe=nprobe, alpha=alpha, mode=mode, B=B, L=L, calib_mode=calib_mode,
+                          near_tol=near_tol))
 
 
 # --------------------------------------------------------------------------------------
@@ -1082,7 +1174,7 @@ def estimate_scan(index, queries, k, nprobe, dims, estimator="partial"):
     Ranked by (estimate, id), padded with (-1, inf).  Returns ids (nq, k), estimates (nq, k)
     and margin (nq,): the smallest relative gap at the k-th / (k+1)-th estimate and in the
     probe order, where other rounding may swap candidates."""
-    Qr = rotate(queries, index["mu"], index["R"])
+    Qr = rotate_as(queries, index["mu"], index["R"], index.get("rotation", "f32"))
     nq = Qr.shape[0]
     ids = np.full((nq, k), -1, dtype=np.int64)
     est = np.full((nq, k), np.inf)

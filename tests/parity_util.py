@@ -58,42 +58,83 @@ def artifacts(ix, with_table=True):
     return art
 
 
+def _near_only(gi, oi, near):
+    """Same number of results and every id in exactly one of the two lists is a logged
+    near-threshold id."""
+    gs, os_ = set(gi[gi >= 0].tolist()), set(oi[oi >= 0].tolist())
+    return len(gs) == len(os_) and (gs ^ os_) <= set(near)
+
+
+def _replays(ix, ora, qi, max_flips=16):
+    """The oracle's own replays of query qi under other rounding: each logged near-threshold
+    stage decision taken the other way, and each near tie of the probe order swapped.  Every
+    replay is computed from the oracle's inputs alone."""
+    args = dict(ora["args"])
+    q = ora["queries"][qi:qi + 1]
+    for x in ora["stage_near"][qi][:max_flips]:
+        yield "flip", O.search(ix, q, flip={0: [x]}, **args)
+    for i in ora["probe_near"][qi]:
+        yield "probe swap", O.search(ix, q, probe_swap={0: i}, **args)
+
+
 def check_search(gpu_ids, gpu_d, ora, ix, tol=TOL, k=None):
-    """Per query: ids identical to the oracle's unless the oracle logged a decision within
-    `tol` (relative) of its threshold; every GPU distance within `tol` of the FP64 distance of
-    the returned stored vector; results sorted and padded.  Returns a summary dict."""
+    """Per query, with the bar of the method's contract:
+      * every GPU distance within `tol` (relative, per result) of the FP64 distance of the
+        returned stored vector to the oracle's rotated query; results ascending, no
+        duplicate ids, padding (-1, +inf) after the results;
+      * ids identical to the oracle's, or every id in the symmetric difference is one the
+        oracle logged within `tol` of a decision threshold (a stage test against tau_b, the
+        K-th distance of a merge, a neighbour in the final order), or the same holds against
+        one of the oracle's replays with a single logged decision taken the other way (a
+        stage test, or a near tie of the probe order): a flipped decision changes tau for
+        later blocks, and the replay follows that cascade;
+      * ids shared with the oracle carry the oracle's distance within `tol`.
+    Returns dict(nq, same, excused, replayed, bad)."""
     nq = gpu_ids.shape[0]
-    same = excused = 0
+    same = excused = replayed = 0
     bad = []
     Y = ix["Y"]
     for qi in range(nq):
         gi, gd = gpu_ids[qi], gpu_d[qi].astype(np.float64)
         oi, od = ora["ids"][qi], ora["dists"][qi]
         valid = gi >= 0
-        # padding layout identical to the oracle's (same candidate counts)
-        if not np.array_equal(valid, oi >= 0):
+        nv = int(valid.sum())
+        if not np.all(valid[:nv]) or np.any(np.isfinite(gd[~valid])) or np.any(gi[~valid] != -1):
             bad.append((qi, "padding"))
             continue
-        if np.any(np.isfinite(gd[~valid])) or np.any(gi[~valid] != -1):
-            bad.append((qi, "pad values"))
-            continue
-        if valid.any():
+        if nv:
             exact = O.sq_dist_direct(Y[gi[valid]], ora["qrot"][qi])
-            if not np.allclose(gd[valid], exact, rtol=tol, atol=tol * max(1e-30, float(exact.max()))):
+            floor = np.where(exact == 0.0, 1e-30, 0.0)
+            if np.any(np.abs(gd[valid] - exact) > tol * np.abs(exact) + floor):
                 bad.append((qi, "distance"))
                 continue
             if np.any(np.diff(gd[valid]) < 0):
                 bad.append((qi, "order"))
                 continue
-            if len(set(gi[valid].tolist())) != int(valid.sum()):
+            if len(set(gi[valid].tolist())) != nv:
                 bad.append((qi, "duplicate id"))
                 continue
+        omap = {int(a): float(b) for a, b in zip(oi, od) if a >= 0}
+        common = [(float(d_), omap[int(a)]) for a, d_ in zip(gi[valid], gd[valid]) if int(a) in omap]
+        if common and not np.allclose([c[0] for c in common], [c[1] for c in common], rtol=tol, atol=0):
+            bad.append((qi, "distance vs oracle"))
+            continue
         if np.array_equal(gi, oi):
             same += 1
-            if not np.allclose(gd[valid], od[valid], rtol=tol):
-                bad.append((qi, "distance vs oracle"))
-        elif ora["margin"][qi] < tol:
+        elif _near_only(gi, oi, ora["near"][qi]):
             excused += 1
         else:
-            bad.append((qi, f"ids differ, oracle margin {ora['margin'][qi]:.3g}"))
-    return dict(nq=nq, same=same, excused=excused, bad=bad)
+            ok = False
+            for kind, alt in _replays(ix, ora, qi):
+                if np.array_equal(gi, alt["ids"][0]) or _near_only(gi, alt["ids"][0], alt["near"][0]):
+                    ok = True
+                    break
+            if ok:
+                excused += 1
+                replayed += 1
+            else:
+                diff = sorted(set(gi[valid].tolist()) ^ set(oi[oi >= 0].tolist()))
+                bad.append((qi, f"ids differ: {diff[:6]} not logged near a threshold "
+                                f"({len(ora['stage_near'][qi])} near stage decisions, "
+                                f"probe ties {ora['probe_near'][qi]})"))
+    return dict(nq=nq, same=same, excused=excused, replayed=replayed, bad=bad)

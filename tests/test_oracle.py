@@ -163,6 +163,53 @@ def test_storage_rounding_matches_library_and_definition():
     assert O.round_storage(np.array([1 + 3 * 2 ** -8]), "bf16")[0] == 1 + 2 ** -6
 
 
+def test_rotate_bf16_is_the_exact_product_of_the_rounded_operands():
+    """BF16 query rotation reading: the centred query is the FP32 difference of the FP32
+    query and the FP32 mean, rounded to bfloat16; R is rounded to FP32 and then bfloat16;
+    the product is exact up to FP64 rounding.  Checked entry by entry against a product of
+    the operands rounded by torch's bfloat16 conversion and summed in exact rational
+    arithmetic, with inputs that sit on bfloat16 rounding ties."""
+    import fractions
+
+    import torch
+    rng = np.random.default_rng(11)
+    D = 6
+    R = np.linalg.qr(rng.standard_normal((D, D)))[0]
+    mu = rng.integers(-4, 5, D).astype(np.float64)     # integers: the tie rows centre exactly
+    X = (rng.standard_normal((5, D)) * 3).astype(np.float32)
+    mu32 = mu.astype(np.float32)
+    X[0] = mu32 + np.float32(1 + 2 ** -8)          # tie: rounds to 1 (even)
+    X[1] = mu32 + np.float32(1 + 3 * 2 ** -8)      # tie: rounds up to 1 + 2^-6 (even)
+    got = O.rotate_bf16(X, mu, R)
+    c = torch.from_numpy(X - mu32[None, :]).to(torch.bfloat16).double().numpy()
+    assert np.all(c[0] == 1.0) and np.all(c[1] == 1 + 2 ** -6)
+    Rb = torch.from_numpy(R.astype(np.float32)).to(torch.bfloat16).double().numpy()
+    for qi in range(X.shape[0]):
+        for i in range(D):
+            exact = sum(fractions.Fraction(float(Rb[i, j])) * fractions.Fraction(float(c[qi, j]))
+                        for j in range(D))
+            bound = 1e-15 * sum(abs(Rb[i, j] * c[qi, j]) for j in range(D))
+            assert abs(got[qi, i] - float(exact)) <= bound, (qi, i)
+    # rows 0 and 1 are the tie values times the row sums of the rounded R
+    np.testing.assert_allclose(got[0], Rb.sum(axis=1), rtol=1e-15)
+    np.testing.assert_allclose(got[1], (1 + 2 ** -6) * Rb.sum(axis=1), rtol=1e-15)
+
+
+def test_rotate_bf16_within_the_rounding_bound_of_the_fp64_rotation(small_workload, small_index):
+    """Both operands are rounded with relative error <= 2^-9 (plus one FP32 rounding of the
+    centred query), so |q'_bf16 - q'_64| <= (2^-8 + 2^-16) sum_j |R_ij| |q_j - mu_j| + tiny,
+    and the reading really differs from the FP64 rotation."""
+    ix = small_index
+    Q = small_workload["queries"]
+    a = O.rotate_bf16(Q, ix["mu"], ix["R"])
+    b = O.rotate(Q, ix["mu"], ix["R"])
+    bound = (2.0 ** -8 + 2.0 ** -16) * (np.abs(Q.astype(np.float64) - ix["mu"]) @ np.abs(ix["R"]).T)
+    assert np.all(np.abs(a - b) <= bound * (1 + 1e-6) + 1e-12)
+    assert np.abs(a - b).max() > 1e-4 * np.abs(b).max()
+    np.testing.assert_array_equal(O.rotate_as(Q, ix["mu"], ix["R"], "bf16"), a)
+    np.testing.assert_array_equal(O.rotate_as(Q, ix["mu"], ix["R"], "f32"), b)
+
+
 # ----------------------------------------------------------------------------- IVF
 
 def test_kmeans_two_clumps_closed_form():
@@ -261,11 +308,15 @@ def test_lag_beyond_block_count_disables_pruning(small_index, small_workload):
     assert r1["stops"][:, :-1].sum() == 0
 
 
-def _lagged_heap_search(q, Y, off, ids, probes, k, m, beta, bounds, lag, B=1):
+def _lagged_heap_search(q, Y, off, ids, probes, k, m, beta, bounds, lag, B=1, invert_first=(),
+                        pool=None):
     """Block-synchronous refinement with a lagged threshold, coded with heapq in this test:
     each list is cut into blocks of B consecutive positions; every candidate of block b is
     tested against the tau in force after block b-1-lag (+inf before it exists or while the
-    queue held fewer than k); the block's survivors then enter the queue one by one."""
+    queue held fewer than k); the block's survivors then enter the queue one by one.
+    Candidates in ``invert_first`` take their first stage test the other way round.  With
+    ``pool`` a list, (id, tau_b, dis) of every survivor with a finite tau_b below its
+    distance is appended to it."""
     heap, taus = [], []   # heap of (-dis, -id); taus[b] = tau after block b
     stops = [0] * len(bounds)
     q = np.asarray(q, np.float64)
@@ -283,13 +334,19 @@ def _lagged_heap_search(q, Y, off, ids, probes, k, m, beta, bounds, lag, B=1):
                 if tau != math.inf:
                     for s in range(len(bounds) - 1):
                         e = float(np.sum(diff[:bounds[s]] ** 2))
-                        if m[s] * e + beta[s] > tau:
+                        test = m[s] * e + beta[s] > tau
+                        if s == 0 and x in invert_first:
+                            test = not test
+                        if test:
                             pruned = True
                             stops[s] += 1
                             break
                 if not pruned:
                     stops[-1] += 1
-                    survivors.append((float(np.sum(diff ** 2)), x))
+                    dis = float(np.sum(diff ** 2))
+                    survivors.append((dis, x))
+                    if pool is not None and tau != math.inf and dis > tau:
+                        pool.append((x, tau, dis))
             for d, x in survivors:
                 if len(heap) < k:
                     heapq.heappush(heap, (-d, -x))
@@ -435,6 +492,123 @@ def test_calibration_labels(small_index):
     assert np.all(np.isfinite(cal["neg_tau"]))
     m = small_index["m"]
     assert np.all(m > 0)
+
+
+_M64 = (1 << 64) - 1
+
+
+def _splitmix64_int(x):
+    """SplitMix64 on Python integers (Steele, Lea & Flood 2014), written here on its own."""
+    z = (x + 0x9E3779B97F4A7C15) & _M64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _M64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _M64
+    return z ^ (z >> 31)
+
+
+def test_splitmix64_int_matches_published_outputs():
+    want = [int(line.split()[1], 16) for line in open(os.path.join(GOLDEN, "splitmix64.txt"))
+            if line.strip() and not line.startswith("#")]
+    state, got = 0, []
+    for _ in range(len(want)):
+        got.append(_splitmix64_int(state))
+        state = (state + 0x9E3779B97F4A7C15) & _M64
+    assert got == want
+
+
+@pytest.mark.parametrize("B,lag", [(64, 0), (64, 1), (64, 3)])
+def test_label_one_pool_is_smallest_keys_of_eligible_pairs(small_index, small_workload, B, lag):
+    """Label 1 of the calibration [Sec. V-A "Parameter Learning"; Sec. VII-A: pairs met in a
+    query process]: per training query, the unpruned canonical search (calib_nprobe lists,
+    blocks of B, threshold lag L, K = K_c) is replayed with a heap loop written in this test;
+    the eligible pairs are the candidates whose exact distance exceeds the finite tau_b of
+    their block (the tau after block b-1-L, not the query's final tau); the kept pairs are
+    the <= 50 with the smallest SplitMix64 keys of (query index << 32) + id.  The oracle's
+    pairs, their tau_b and their stage features must be exactly these."""
+    ix = small_index
+    calib = small_workload["calib"][:40]
+    seed, kc, nprobe_c, max_neg = 7, 10, 8, 50
+    cal = O.calibrate(ix["Y"], ix["list_off"], ix["list_ids"], ix["centroids"], ix["mu"], ix["R"], calib,
+                      ix["bounds"], calib_k=kc, calib_nprobe=nprobe_c, B=B, L=lag, seed=seed,
+                      max_neg=max_neg)
+    S = ix["bounds"].shape[0]
+    base_key = _splitmix64_int((seed + O.TAG_NEG) & _M64)
+    qr = (calib.astype(np.float64) - ix["mu"][None, :]) @ ix["R"].T
+    total_pool = capped = 0
+    for qi in range(calib.shape[0]):
+        dc = ssd.cdist(qr[qi][None], ix["centroids"], "sqeuclidean")[0]
+        probes = sorted(range(dc.shape[0]), key=lambda j: (dc[j], j))[:nprobe_c]
+        pool = []
+        _lagged_heap_search(qr[qi], ix["Y"], ix["list_off"], ix["list_ids"], probes, kc,
+                            np.zeros(S - 1), np.full(S - 1, -np.inf), ix["bounds"], lag, B, pool=pool)
+        total_pool += len(pool)
+        capped += len(pool) > max_neg
+        for x, tau_b, dis in pool:
+            assert math.isfinite(tau_b) and dis > tau_b
+        keyed = sorted(pool, key=lambda p: (_splitmix64_int((base_key + (qi << 32) + p[0]) & _M64), p[0]))
+        want = sorted((x, t) for x, t, _ in keyed[:max_neg])
+        sel = np.nonzero(cal["neg_q"] == qi)[0]
+        got = sorted((int(cal["neg_id"][i]), float(cal["neg_tau"][i])) for i in sel)
+        assert [g[0] for g in got] == [w_[0] for w_ in want], qi
+        np.testing.assert_allclose([g[1] for g in got], [w_[1] for w_ in want], rtol=1e-12)
+        for i in sel:   # stage features: the partial distances over the leading d_s dims
+            y = ix["Y"][cal["neg_id"][i]]
+            e = [float(np.sum((qr[qi][:d] - y[:d]) ** 2)) for d in ix["bounds"][:-1]]
+            np.testing.assert_allclose(cal["neg_e"][i], e, rtol=1e-12)
+    assert total_pool > 0 and capped > 0    # the key selection really chose among more pairs
+
+
+def test_near_log_and_flip_replay(small_index, small_workload):
+    """The near-threshold log holds exactly the candidates with an evaluated test within the
+    tolerance of tau_b (recomputed here from the stage features), and a replay that inverts
+    one candidate's first test equals the separately coded heap loop with that test
+    inverted (ids, distances and stopping stages)."""
+    ix = small_index
+    beta = O.beta_for_alpha(ix["G"], 0.1)
+    q = O.rotate(small_workload["queries"][:1], ix["mu"], ix["R"])[0]
+    probes, _, _ = O.probe_order(q, ix["centroids"], 4)
+    tol = 0.02
+    lg = {}
+    ids0, d0, st0, _ = O.search_one(q, ix["Y"], ix["list_off"], ix["list_ids"], probes, 10, ix["m"], beta,
+                                    ix["bounds"], B=1, L=0, log=lg, near_tol=tol)
+    # recompute: walk the sequential search keeping tau, note every test within tol
+    heap, want = [], set()
+    for lst in probes:
+        for pos in range(int(ix["list_off"][lst]), int(ix["list_off"][lst + 1])):
+            x = int(ix["list_ids"][pos])
+            tau = -heap[0][0] if len(heap) == 10 else math.inf
+            diff = q - ix["Y"][x]
+            pruned = False
+            if tau != math.inf:
+                for s_, d in enumerate(ix["bounds"][:-1]):
+                    lhs = ix["m"][s_] * float(np.sum(diff[:d] ** 2)) + beta[s_]
+                    if abs(lhs - tau) / (abs(lhs - beta[s_]) + abs(beta[s_]) + abs(tau)) < tol:
+                        want.add(x)
+                    if lhs > tau:
+                        pruned = True
+                        break
+            if not pruned:
+                dis = float(np.sum(diff ** 2))
+                if len(heap) < 10:
+                    heapq.heappush(heap, (-dis, -x))
+                elif (dis, x) < (-heap[0][0], -heap[0][1]):
+                    heapq.heapreplace(heap, (-dis, -x))
+    assert set(lg["stage"]) == want and len(want) > 0
+    assert set(lg["stage"]) <= lg["near"]
+    # invert the first test of candidates whose first test decided (huge tolerance: every
+    # evaluated test counts as near, so "first near" is the first test)
+    pruned_at_0 = [x for x in want][:3]
+    for x in pruned_at_0:
+        a_ids, a_d, a_st, _ = O.search_one(q, ix["Y"], ix["list_off"], ix["list_ids"], probes, 10, ix["m"],
+                                           beta, ix["bounds"], B=1, L=0, flip=[x], near_tol=1e300)
+        b_ids, b_d, b_st = _lagged_heap_search(q, ix["Y"], ix["list_off"], ix["list_ids"], probes, 10,
+                                               ix["m"], beta, ix["bounds"], 0, 1, invert_first={x})
+        assert a_ids.tolist() == b_ids and a_st.tolist() == b_st
+        np.testing.assert_allclose(a_d, b_d, rtol=1e-12)
+    # flipping a candidate with no test near its threshold changes nothing
+    far = [int(x) for x in ids0 if int(x) not in lg["near"]][:1]
+    r_ids, r_d, r_st, _ = O.search_one(q, ix["Y"], ix["list_off"], ix["list_ids"], probes, 10, ix["m"], beta,
+                                       ix["bounds"], B=1, L=0, flip=far, near_tol=tol)
+    assert r_ids.tolist() == ids0.tolist() and r_st.tolist() == st0.tolist()
 
 
 def test_heldout_false_prune_rate_matches_significance(small_index, small_workload):
