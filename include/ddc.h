@@ -231,23 +231,35 @@ ddc_status ddc_correction(const ddc_index *ix, int32_t k, double significance, d
 ddc_status ddc_correction_pq(const ddc_index *ix, int32_t k, double significance, double *m1,
                              double *m3, double *beta);
 
-/* Search, host buffers.  queries: [nq x dim]; ids/dists: [nq x k].
- * 1 <= k <= 256, 1 <= nprobe <= nlist, 0 <= significance < 1 (0: no learned pruning). */
+/* Search, host buffers: for every query the k stored vectors nearest in squared Euclidean
+ * distance among the nprobe lists whose centroids are nearest (the AKNN problem and the IVF
+ * probe step of Sec. II-A), each candidate tested stage by stage with the data-driven
+ * correction (Sec. V-A, V-B) at significance = 1 - the target recall r of Sec. V-A "Adaptive
+ * Adjustment", survivors refined to their exact distance.  queries: [nq x dim] FP32 row-major;
+ * ids (int64, original row ids) / dists (FP32 squared distances in the original coordinates,
+ * Eq. (1)): [nq x k], ascending by (dist, id), padded with (-1, +inf).
+ * 1 <= k <= 256, 1 <= nprobe <= nlist, 0 <= significance < 1 (0: no learned pruning);
+ * otherwise EINVAL before any GPU work.  Inputs are copied; outputs are the caller's. */
 ddc_status ddc_search(const ddc_index *ix, const float *queries, int64_t nq, int32_t k,
                       int32_t nprobe, double significance, ddc_corr mode, int64_t *ids,
                       float *dists, ddc_search_stats *stats);
 
-/* Search with a K and an N_probe per query (host buffers).  k[nq], nprobe[nq];
- * results of query i at out_offsets[i] .. out_offsets[i] + k[i] (caller-built CSR with
+/* Search with a K and an N_probe per query (host buffers): the search of ddc_search (Sec.
+ * II-A, V-A, V-B) where every query carries its own K and N_probe.  k[nq], nprobe[nq], each
+ * within the bounds of ddc_search (EINVAL otherwise, before any GPU work); results of query i
+ * at out_offsets[i] .. out_offsets[i] + k[i] (caller-built CSR with
  * out_offsets[i+1] - out_offsets[i] >= k[i]); ids/dists sized out_offsets[nq]. */
 ddc_status ddc_search_var(const ddc_index *ix, const float *queries, int64_t nq, const int32_t *k,
                           const int32_t *nprobe, double significance, ddc_corr mode,
                           const int64_t *out_offsets, int64_t *ids, float *dists,
                           ddc_search_stats *stats);
 
-/* Search on device buffers, queued on `hip_stream` (a hipStream_t; NULL = default stream),
- * no host synchronisation.  d_queries [nq x dim]; d_k / d_nprobe: per-query arrays or NULL
- * to use k_all / nprobe_all; k_max / nprobe_max bound them; d_out_offsets: CSR as in
+/* Search on device buffers (the search of ddc_search / ddc_search_var: Sec. II-A, V-A,
+ * V-B), queued on `hip_stream` (a hipStream_t; NULL = default stream), no host
+ * synchronisation.  d_queries [nq x dim]; d_k / d_nprobe: per-query arrays or NULL
+ * to use k_all / nprobe_all; k_max / nprobe_max bound them (the host checks the bounds
+ * themselves; the device clamps a per-query entry outside [1, k_max] or [1, nprobe_max]
+ * into that range rather than trusting it); d_out_offsets: CSR as in
  * ddc_search_var or NULL for dense [nq x k_all]; d_ids int64 / d_dists float32 outputs;
  * d_counters: NULL or device int64[4 + 64 + 2] (added to): candidates, refined, stage
  * slices, unused, stage_stop[64], prestage_reads, prestage_pruned.

@@ -357,7 +357,9 @@ __global__ __launch_bounds__(kSelThreads) void select_kernel(const float *dist, 
   int32_t *hist = reinterpret_cast<int32_t *>(wl);
   // selected (key, index) pairs packed as key << 32 | index: one 64-bit compare orders them
   unsigned long long *sel = reinterpret_cast<unsigned long long *>(wl + 256 * 4);
-  const int np = nprobe ? nprobe[q] : nprobe_all;
+  // a per-query count outside [1, min(p_stride, nlist)] is clamped to it (device arrays are
+  // the caller's: an entry past the probe row would write past it)
+  const int np = min(max(nprobe ? nprobe[q] : nprobe_all, 1), min(p_stride, nlist));
   const float *row = dist + q * ld;
   const unsigned long long lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
 

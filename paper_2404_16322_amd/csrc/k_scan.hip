@@ -268,8 +268,10 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
   __builtin_amdgcn_wave_barrier();
   const int q = a.order ? a.order[slot] : slot;
 
-  const int K = __builtin_amdgcn_readfirstlane(a.k ? a.k[q] : a.k_all);
-  const int np = a.nprobe ? a.nprobe[q] : a.nprobe_all;
+  // per-query K and nprobe clamped to [1, k_max] and [1, p_stride]: the result queues and the
+  // probe row are sized by those bounds
+  const int K = __builtin_amdgcn_readfirstlane(min(max(a.k ? a.k[q] : a.k_all, 1), KM));
+  const int np = min(max(a.nprobe ? a.nprobe[q] : a.nprobe_all, 1), a.p_stride);
   const float *qg = a.qrot + (int64_t)q * a.q_stride;
   const int qt = wsub * 64 + lane;             // thread index within the query's waves
   for (int i = qt; i < Dp; i += 64 * W) s_q[i] = qg[i];
@@ -1079,7 +1081,7 @@ __global__ __launch_bounds__(256) void work_key_kernel(const int32_t *probes, in
   const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (q >= nq) return;
-  const int np = nprobe ? nprobe[q] : nprobe_all;
+  const int np = min(max(nprobe ? nprobe[q] : nprobe_all, 1), p_stride);
   long long work = 0;
   for (int p = lane; p < np; p += 64) {
     const int l = probes[q * p_stride + p];
