@@ -275,6 +275,31 @@ ddc_status ddc_search_device(const ddc_index *ix, const float *d_queries, int64_
                              int64_t *d_ids, float *d_dists, int64_t *d_counters,
                              void *hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): the search of ddc_search_device, same arguments,
+ * same kernels, same results, but its correction rows and scratch (rotated queries, coarse
+ * distances, probes, query orders) come from one fixed device array of
+ * ddc_search_device_noalloc_bytes() bytes (64 MiB) inside the library, which each device it
+ * runs on holds until the process ends.  The call allocates and frees no device memory, never
+ * times or tunes a launch shape (an untuned size class takes the fixed rule), and queues a
+ * copy of the correction rows (host memory held by the index) and the kernels on `hip_stream`.
+ * Size limit: the scratch of one chunk of min(nq, 32768) queries, about
+ * (dim rounded up to 32 + nlist + nprobe_max + 5) x 4 bytes per query, plus 16 KiB of tables
+ * and (nlist + 1) x 4 bytes, must fit, else
+ * EINVAL before any device work, with the largest query count that fits in the message
+ * (e.g. nlist 4096, dim 128, nprobe_max 48: about 3,900 queries).
+ * Every call on one device shares that device's array and leaves its contents behind (the
+ * kernels clear what must start at zero): calls that overlap on one device, from any stream or
+ * thread, race and give wrong results; serialise them (one stream, or events).  Other errors as
+ * ddc_search_device. */
+ddc_status ddc_search_device_noalloc(const ddc_index *ix, const float *d_queries, int64_t nq,
+                                     const int32_t *d_k, int32_t k_all, int32_t k_max,
+                                     const int32_t *d_nprobe, int32_t nprobe_all, int32_t nprobe_max,
+                                     double significance, ddc_corr mode,
+                                     const int64_t *d_out_offsets, int64_t *d_ids, float *d_dists,
+                                     int64_t *d_counters, void *hip_stream);
+size_t ddc_search_device_noalloc_bytes(void);
+
 /* Approximation accuracy of a distance estimate alone (the direct scan of the paper's
  * approximation-accuracy experiment, Sec. VII Exp-7 and its Table III): for every query, the
  * k candidates of the nprobe nearest lists (nprobe = nlist: the whole base) with the smallest

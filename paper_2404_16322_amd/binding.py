@@ -26,7 +26,8 @@ SYMBOLS = ["ddc_fit_params_default", "ddc_fit", "ddc_import", "ddc_export", "ddc
            "ddc_last_error", "ddc_server_create", "ddc_server_submit", "ddc_server_poll",
            "ddc_server_get_stats", "ddc_server_destroy", "ddc_set_launch", "ddc_get_launch",
            "ddc_scan_variant", "ddc_save", "ddc_load", "ddc_set_ads_epsilon", "ddc_set_bsar_multiplier",
-           "ddc_search_estimate", "ddc_correction_pq"]
+           "ddc_search_estimate", "ddc_correction_pq", "ddc_search_device_noalloc",
+           "ddc_search_device_noalloc_bytes"]
 
 
 class FitParams(C.Structure):
@@ -126,6 +127,8 @@ def load_library():
                                        C.POINTER(SearchStats)]
         lib.ddc_search_device.argtypes = [vp, vp, i64, vp, i32, i32, vp, i32, i32, f64, C.c_int, vp,
                                           vp, vp, vp, vp]
+        lib.ddc_search_device_noalloc.argtypes = lib.ddc_search_device.argtypes
+        lib.ddc_search_device_noalloc_bytes.argtypes = []
         lib.ddc_debug_intermediates.argtypes = [vp, vp, i64, i32, vp, vp]
         lib.ddc_search_estimate.argtypes = [vp, vp, i64, i32, i32, i32, C.c_int, vp, vp]
         lib.ddc_correction_pq.argtypes = [vp, i32, f64, vp, vp, vp]
@@ -148,8 +151,10 @@ def load_library():
         lib.ddc_free.argtypes = [vp]
         lib.ddc_free.restype = None
         for name in SYMBOLS:
-            if name not in ("ddc_free", "ddc_last_error", "ddc_server_destroy"):
+            if name not in ("ddc_free", "ddc_last_error", "ddc_server_destroy",
+                            "ddc_search_device_noalloc_bytes"):
                 getattr(lib, name).restype = st
+        lib.ddc_search_device_noalloc_bytes.restype = C.c_size_t
         _LIB = lib
         return lib
 
@@ -392,6 +397,15 @@ class Index:
                       d_offsets=0):
         """Device pointers (ints, e.g. torch tensors' data_ptr()) and a hipStream_t handle."""
         _check(load_library().ddc_search_device(
+            self._h, d_queries, nq, d_k or None, k_all, k_max, d_nprobe or None, nprobe_all,
+            nprobe_max, alpha, CORR[mode], d_offsets or None, d_ids, d_dists, d_counters or None,
+            stream or None))
+
+    def search_device_noalloc(self, d_queries, nq, k_all, nprobe_all, alpha, mode, d_ids, d_dists,
+                              d_counters=0, stream=0, d_k=0, k_max=0, d_nprobe=0, nprobe_max=0,
+                              d_offsets=0):
+        """search_device with the library's fixed device scratch: allocates no device memory."""
+        _check(load_library().ddc_search_device_noalloc(
             self._h, d_queries, nq, d_k or None, k_all, k_max, d_nprobe or None, nprobe_all,
             nprobe_max, alpha, CORR[mode], d_offsets or None, d_ids, d_dists, d_counters or None,
             stream or None))

@@ -23,7 +23,7 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     f"-I{INCLUDE}", f"-I{CSRC}",
 ]
-SOURCES = ["k_scan.hip", "k_gemm.hip", "k_fit.hip", "k_calib.hip", "k_pq.hip", "api.cpp", "serve.cpp",
+SOURCES = ["k_scan.hip", "k_gemm.hip", "k_fit.hip", "k_calib.hip", "k_pq.hip", "api.cpp", "serve.cpp", "search_noalloc.cpp",
            "host_math.cpp"]
 
 

@@ -510,6 +510,7 @@ static void set_tables(ddc_index *ix, std::vector<ddc_index::Table> t) {
   ix->tables = std::move(t);
   ix->beta_cache.clear();
   ix->tab_cache.clear();
+  ix->tab_host.clear();
 }
 
 // The table a search with K uses: the last (largest K_c) with K_c <= K, else the first.
@@ -535,19 +536,21 @@ static std::vector<double> get_beta(ddc_index *ix, double alpha, int mode, int t
   return beta_locked(ix, alpha, mode, t);
 }
 
-// Device copy of every table for one (alpha, correction mode): [ntab][NB + 1][2] (m, beta) per
-// dim block (beta = -inf where no test follows; entry NB = the FP8 pre-stage).
-static std::shared_ptr<DevBuf> device_tables(ddc_index *ix, double alpha, ddc_corr mode, int *ntab) {
-  std::lock_guard<std::mutex> lk(ix->beta_mtx);
+// Every table for one (alpha, correction mode) as the scan reads it: [ntab][NB + 1][2] (m, beta)
+// per dim block (beta = -inf where no test follows; entry NB = the FP8 pre-stage).  Host rows,
+// cached per key (beta_mtx held).
+static std::shared_ptr<const std::vector<float>> host_tables_locked(ddc_index *ix, double alpha,
+                                                                    ddc_corr mode, int *ntab) {
   const bool ads = mode == DDC_CORR_ADS;
   const bool lossless = mode == DDC_CORR_LOSSLESS || ads;   // one fixed table, no pre-stage
   const auto key = std::make_pair(ads ? ix->ads_eps0 : lossless ? -1.0 : alpha, (int)mode);
   const int nt = lossless ? 1 : (int)ix->tables.size();
   *ntab = nt;
-  auto it = ix->tab_cache.find(key);
-  if (it != ix->tab_cache.end()) return it->second;
+  auto it = ix->tab_host.find(key);
+  if (it != ix->tab_host.end()) return it->second;
   const int NB = ix->NB, P = ix->P();
-  std::vector<float> h((size_t)nt * (NB + 1) * 2);
+  auto hp = std::make_shared<std::vector<float>>((size_t)nt * (NB + 1) * 2);
+  std::vector<float> &h = *hp;
   for (int t = 0; t < nt; ++t) {
     float *row = &h[(size_t)t * (NB + 1) * 2];
     for (int b = 0; b <= NB; ++b) { row[2 * b] = 0.f; row[2 * b + 1] = -INFINITY; }
@@ -570,8 +573,21 @@ static std::shared_ptr<DevBuf> device_tables(ddc_index *ix, double alpha, ddc_co
     }
     if (P && !lossless) { row[2 * NB] = (float)mm[0]; row[2 * NB + 1] = (float)bb[0]; }
   }
-  auto buf = std::make_shared<DevBuf>(h.size() * 4);
-  HIPC(hipMemcpy(buf->p, h.data(), h.size() * 4, hipMemcpyHostToDevice));
+  ix->tab_host[key] = hp;
+  return hp;
+}
+
+// Device copy of host_tables_locked's rows, cached per key.
+static std::shared_ptr<DevBuf> device_tables(ddc_index *ix, double alpha, ddc_corr mode, int *ntab) {
+  std::lock_guard<std::mutex> lk(ix->beta_mtx);
+  const bool ads = mode == DDC_CORR_ADS;
+  const bool lossless = mode == DDC_CORR_LOSSLESS || ads;
+  const auto key = std::make_pair(ads ? ix->ads_eps0 : lossless ? -1.0 : alpha, (int)mode);
+  const auto h = host_tables_locked(ix, alpha, mode, ntab);
+  auto it = ix->tab_cache.find(key);
+  if (it != ix->tab_cache.end()) return it->second;
+  auto buf = std::make_shared<DevBuf>(h->size() * 4);
+  HIPC(hipMemcpy(buf->p, h->data(), h->size() * 4, hipMemcpyHostToDevice));
   ix->tab_cache[key] = buf;
   return buf;
 }
@@ -579,15 +595,16 @@ static std::shared_ptr<DevBuf> device_tables(ddc_index *ix, double alpha, ddc_co
 // Device tables of a BSA-O search: [ntab][NB + 1][2] lossless stage rows (m = 1, beta = 0 where
 // a test follows: refinement only prunes candidates whose partial distance already exceeds
 // tau), then [ntab][4] = (m1, m3, beta(alpha), 0) of each table's quantization test.
-static std::shared_ptr<DevBuf> device_pq_tables(ddc_index *ix, double alpha, int *ntab) {
-  std::lock_guard<std::mutex> lk(ix->beta_mtx);
+static std::shared_ptr<const std::vector<float>> host_pq_tables_locked(ddc_index *ix, double alpha,
+                                                                       int *ntab) {
   const auto key = std::make_pair(alpha, (int)DDC_CORR_BSAO);
   const int nt = (int)ix->tables.size();
   *ntab = nt;
-  auto it = ix->tab_cache.find(key);
-  if (it != ix->tab_cache.end()) return it->second;
+  auto it = ix->tab_host.find(key);
+  if (it != ix->tab_host.end()) return it->second;
   const int NB = ix->NB;
-  std::vector<float> h((size_t)nt * (NB + 1) * 2 + (size_t)nt * 4);
+  auto hp = std::make_shared<std::vector<float>>((size_t)nt * (NB + 1) * 2 + (size_t)nt * 4);
+  std::vector<float> &h = *hp;
   for (int t = 0; t < nt; ++t) {
     float *row = &h[(size_t)t * (NB + 1) * 2];
     for (int b = 0; b <= NB; ++b) { row[2 * b] = 0.f; row[2 * b + 1] = -INFINITY; }
@@ -604,8 +621,18 @@ static std::shared_ptr<DevBuf> device_pq_tables(ddc_index *ix, double alpha, int
     pq[2] = (float)beta;
     pq[3] = 0.f;
   }
-  auto buf = std::make_shared<DevBuf>(h.size() * 4);
-  HIPC(hipMemcpy(buf->p, h.data(), h.size() * 4, hipMemcpyHostToDevice));
+  ix->tab_host[key] = hp;
+  return hp;
+}
+
+static std::shared_ptr<DevBuf> device_pq_tables(ddc_index *ix, double alpha, int *ntab) {
+  std::lock_guard<std::mutex> lk(ix->beta_mtx);
+  const auto key = std::make_pair(alpha, (int)DDC_CORR_BSAO);
+  const auto h = host_pq_tables_locked(ix, alpha, ntab);
+  auto it = ix->tab_cache.find(key);
+  if (it != ix->tab_cache.end()) return it->second;
+  auto buf = std::make_shared<DevBuf>(h->size() * 4);
+  HIPC(hipMemcpy(buf->p, h->data(), h->size() * 4, hipMemcpyHostToDevice));
   ix->tab_cache[key] = buf;
   return buf;
 }
@@ -613,8 +640,9 @@ static std::shared_ptr<DevBuf> device_pq_tables(ddc_index *ix, double alpha, int
 // ---------------------------------------------------------------------------------------
 // search pipeline
 // ---------------------------------------------------------------------------------------
-template <class F> static void timed(ddc_index *ix, int kernel, hipStream_t s, F &&launch) {
-  if (!ix->timing) { launch(); return; }
+template <class F> static void timed(ddc_index *ix, int kernel, hipStream_t s, F &&launch,
+                                     bool off = false) {
+  if (!ix->timing || off) { launch(); return; }
   ddc_index::Mark m{kernel, nullptr, nullptr};
   HIPC(hipEventCreate(&m.a));
   HIPC(hipEventCreate(&m.b));
@@ -644,18 +672,42 @@ static void *stream_workspace(ddc_index *ix, hipStream_t s, size_t bytes) {
   return w->p;
 }
 
+// Queries per scratch chunk, and the scratch pieces of one chunk of cmax queries: rotated
+// queries, coarse distances, probes, then the query orders' keys, histograms and ranks and the
+// persistent launch's slot counter; each piece 256-byte aligned.
+constexpr int64_t kChunk = 32768;
+constexpr int kParts = 11;
+static void scratch_sizes(const ddc_index *ix, int64_t cmax, int np_max, size_t (&sizes)[kParts]) {
+  const size_t v[kParts] = {(size_t)cmax * ix->Dp * 4, (size_t)cmax * ix->nlist * 4,
+                            (size_t)cmax * np_max * 4, (size_t)(ix->nlist + 1) * 4, (size_t)cmax * 4,
+                            (size_t)cmax * 4, (size_t)cmax * 4, (size_t)257 * 4, (size_t)cmax * 4,
+                            (size_t)cmax * 4, 256};
+  for (int i = 0; i < kParts; ++i) sizes[i] = v[i];
+}
+
 size_t ddc::search_scratch_bytes(const ddc_index *ix, int64_t nq, int np_max) {
-  const int64_t c = std::min<int64_t>(nq, 32768);
-  return (size_t)c * ix->Dp * 4 + (size_t)c * ix->nlist * 4 + (size_t)c * np_max * 4 +
-         (size_t)(ix->nlist + 1) * 4 + (size_t)c * 8 + (size_t)c * 12 + 2048 + 4096;
+  size_t sizes[kParts], total = 0;
+  scratch_sizes(ix, std::min(kChunk, nq), np_max, sizes);
+  for (size_t b : sizes) total += (b + 255) & ~(size_t)255;
+  return total;
 }
 
 void ddc::search_device(ddc_index *ix, const float *d_q, int64_t nq, const int32_t *d_k, int k_all,
                         int k_max, const int32_t *d_np, int np_all, int np_max, double alpha,
                         ddc_corr mode, const int64_t *d_off, int64_t *d_ids, float *d_d,
                         int64_t *d_ctr, hipStream_t s, float *qrot_out, int32_t *probes_out,
-                        bool may_tune, const EstimateSpec *est, bool stream_scratch) {
+                        bool may_tune, const EstimateSpec *est, bool stream_scratch,
+                        const Workspace *ws_ext) {
   const int Dp = ix->Dp, D = ix->D;
+  const bool fixed_ws = ws_ext != nullptr;
+  if (fixed_ws) may_tune = false;
+  // correction rows: from the device cache, or (fixed workspace) copied from their host rows into
+  // the workspace's start on s (the host rows live in the index, so the copy's source outlives it)
+  auto take_tables = [&](std::shared_ptr<const std::vector<float>> h) -> float * {
+    if (h->size() * 4 > Workspace::kTableBytes) throw DdcError(DDC_EINVAL, "correction tables exceed the workspace");
+    HIPC(hipMemcpyAsync(ws_ext->p, h->data(), h->size() * 4, hipMemcpyHostToDevice, s));
+    return reinterpret_cast<float *>(ws_ext->p);
+  };
   ScanArgs a{};
   a.prune = 0;
   std::shared_ptr<DevBuf> tabs;   // keeps the device tables alive for this call
@@ -672,8 +724,17 @@ void ddc::search_device(ddc_index *ix, const float *d_q, int64_t nq, const int32
   const bool lossless = (mode == DDC_CORR_LOSSLESS || mode == DDC_CORR_ADS) && ix->St > 0;
   if (mode == DDC_CORR_BSAO) {
     a.prune = 1;
-    tabs = device_pq_tables(ix, alpha, &a.ntab);
-    a.tab = tabs->as<float>();
+    if (fixed_ws) {
+      std::shared_ptr<const std::vector<float>> h;
+      {
+        std::lock_guard<std::mutex> lk(ix->beta_mtx);
+        h = host_pq_tables_locked(ix, alpha, &a.ntab);
+      }
+      a.tab = take_tables(h);
+    } else {
+      tabs = device_pq_tables(ix, alpha, &a.ntab);
+      a.tab = tabs->as<float>();
+    }
     a.pq_tab = a.tab + (size_t)a.ntab * (ix->NB + 1) * 2;
     for (int t = 0; t < a.ntab; ++t) a.tab_k[t] = ix->tables[t].kc;
     for (int j = 0; j < ix->St; ++j) a.test_after[((j + 1) * ix->delta_d) / kBlockDims - 1] = 1;
@@ -692,8 +753,17 @@ void ddc::search_device(ddc_index *ix, const float *d_q, int64_t nq, const int32
     for (int j = 0; j < ix->St; ++j) a.test_after[((j + 1) * ix->delta_d) / kBlockDims - 1] = 1;
   } else if (learned || lossless) {
     a.prune = 1;
-    tabs = device_tables(ix, alpha, mode, &a.ntab);
-    a.tab = tabs->as<float>();
+    if (fixed_ws) {
+      std::shared_ptr<const std::vector<float>> h;
+      {
+        std::lock_guard<std::mutex> lk(ix->beta_mtx);
+        h = host_tables_locked(ix, alpha, mode, &a.ntab);
+      }
+      a.tab = take_tables(h);
+    } else {
+      tabs = device_tables(ix, alpha, mode, &a.ntab);
+      a.tab = tabs->as<float>();
+    }
     for (int t = 0; t < a.ntab; ++t) a.tab_k[t] = lossless ? 1 : ix->tables[t].kc;
     for (int j = 0; j < ix->St; ++j) a.test_after[((j + 1) * ix->delta_d) / kBlockDims - 1] = 1;
     if (learned && ix->P()) {
@@ -702,27 +772,31 @@ void ddc::search_device(ddc_index *ix, const float *d_q, int64_t nq, const int32
       a.scale8 = ix->d_scale8.as<float>();
     }
   }
-  const int64_t chunk = 32768;
+  const int64_t chunk = kChunk;
   // Scratch of a chunk (rotated queries, coarse distances, probes, query orders), carved from
-  // one buffer: with stream_scratch and outside graph capture the stream's grow-only workspace,
-  // reused call after call (stream order keeps a call's kernels from overlapping the next
-  // call's use of it; per-call stream-ordered allocations left the GPU idle about 30 us at
-  // every call); else one stream-ordered allocation (which a captured graph records).
+  // one buffer: a caller's fixed workspace after its table bytes; with stream_scratch and
+  // outside graph capture the stream's grow-only workspace, reused call after call (stream
+  // order keeps a call's kernels from overlapping the next call's use of it; per-call
+  // stream-ordered allocations left the GPU idle about 30 us at every call); else one
+  // stream-ordered allocation (which a captured graph records).
   const int64_t cmax = std::min(chunk, nq);
-  const size_t sizes[] = {(size_t)cmax * Dp * 4, (size_t)cmax * ix->nlist * 4, (size_t)cmax * np_max * 4,
-                          (size_t)(ix->nlist + 1) * 4, (size_t)cmax * 4, (size_t)cmax * 4,
-                          (size_t)cmax * 4, (size_t)257 * 4, (size_t)cmax * 4, (size_t)cmax * 4, 256};
+  size_t sizes[kParts];
+  scratch_sizes(ix, cmax, np_max, sizes);
   size_t total = 0;
   for (size_t b : sizes) total += (b + 255) & ~(size_t)255;
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
   HIPC(hipStreamIsCapturing(s, &cap));
-  const bool reuse = stream_scratch && cap == hipStreamCaptureStatusNone;
-  AsyncBuf pooled(reuse ? 0 : total, s);
-  char *const ws = reuse ? reinterpret_cast<char *>(stream_workspace(ix, s, total)) : pooled.as<char>();
-  void *part[11];
+  if (fixed_ws && Workspace::kTableBytes + total > ws_ext->bytes)
+    throw DdcError(DDC_EINVAL, "search scratch exceeds the workspace");
+  const bool reuse = !fixed_ws && stream_scratch && cap == hipStreamCaptureStatusNone;
+  AsyncBuf pooled(reuse || fixed_ws ? 0 : total, s);
+  char *const ws = fixed_ws ? reinterpret_cast<char *>(ws_ext->p) + Workspace::kTableBytes
+                   : reuse  ? reinterpret_cast<char *>(stream_workspace(ix, s, total))
+                            : pooled.as<char>();
+  void *part[kParts];
   {
     size_t off = 0;
-    for (int i = 0; i < 11; ++i) {
+    for (int i = 0; i < kParts; ++i) {
       part[i] = ws + off;
       off += (sizes[i] + 255) & ~(size_t)255;
     }
@@ -735,16 +809,16 @@ void ddc::search_device(ddc_index *ix, const float *d_q, int64_t nq, const int32
     g.A = d_q + q0 * D; g.lda = D; g.mu = ix->d_mu32.as<float>();
     g.B = ix->d_R32.as<float>(); g.ldb = Dp; g.C = qrot.as<float>(); g.ldc = Dp;
     g.M = nqc; g.N = Dp; g.K = D; g.mode = 0; g.prec = ix->rot == DDC_ROT_BF16 ? 1 : 0;
-    timed(ix, 0, s, [&] { launch_gemm(g, s); });
+    timed(ix, 0, s, [&] { launch_gemm(g, s); }, fixed_ws);
     GemmArgs c{};
     c.A = qrot.as<float>(); c.lda = Dp; c.mu = nullptr; c.B = ix->d_cent.as<float>(); c.ldb = Dp;
     c.bias = ix->d_cnorm.as<float>(); c.C = cdist.as<float>(); c.ldc = ix->nlist;
     c.M = nqc; c.N = ix->nlist; c.K = Dp; c.mode = 1; c.prec = 0;
-    timed(ix, 1, s, [&] { launch_gemm(c, s); });
+    timed(ix, 1, s, [&] { launch_gemm(c, s); }, fixed_ws);
     timed(ix, 2, s, [&] {
       launch_select(cdist.as<float>(), ix->nlist, ix->nlist, d_np ? d_np + q0 : nullptr, np_all,
                     np_max, probes.as<int32_t>(), np_max, nqc, s);
-    });
+    }, fixed_ws);
     if (qrot_out) {
       HIPC(hipMemcpy2DAsync(qrot_out + q0 * D, D * 4, qrot.p, Dp * 4, D * 4, nqc,
                             hipMemcpyDeviceToHost, s));
@@ -784,7 +858,7 @@ void ddc::search_device(ddc_index *ix, const float *d_q, int64_t nq, const int32
     a.nq = (int32_t)nqc; a.nblocks = ix->NB; a.block_b = ix->B; a.nlist = ix->nlist;
     a.k_max = k_max; a.lag = ix->L;
     choose_variant(ix, a, np_max, s, may_tune, orders);
-    timed(ix, 3, s, [&] { launch_scan(a, ix->store(), s); });
+    timed(ix, 3, s, [&] { launch_scan(a, ix->store(), s); }, fixed_ws);
   }
   HIPC(hipGetLastError());
 }
@@ -1322,22 +1396,17 @@ ddc_status ddc_search_device(const ddc_index *ixc, const float *d_queries, int64
                              const int32_t *d_nprobe, int32_t nprobe_all, int32_t nprobe_max,
                              double significance, ddc_corr mode, const int64_t *d_out_offsets,
                              int64_t *d_ids, float *d_dists, int64_t *d_counters, void *hip_stream) {
-  ddc_status st = check_search_args(ixc, nq, significance, mode);
+  ddc_status st = check_device_search(ixc, d_queries, nq, d_k, k_all, k_max, d_nprobe, nprobe_all,
+                                      nprobe_max, significance, mode, d_out_offsets, d_ids, d_dists);
   if (st != DDC_OK) return st;
-  if (nq > 0 && (!d_queries || !d_ids || !d_dists)) return set_err(DDC_EINVAL, "NULL buffer");
-  if (!d_k && (st = check_k_np(ixc, k_all, 1)) != DDC_OK) return st;
-  if (d_k && (k_max < 1 || k_max > kMaxK)) return set_err(DDC_EINVAL, "k_max must be in [1, %d]", kMaxK);
-  if (d_k && !d_out_offsets) return set_err(DDC_EINVAL, "per-query k needs out_offsets");
-  const int npm = d_nprobe ? nprobe_max : nprobe_all;
-  if ((st = check_k_np(ixc, 1, npm)) != DDC_OK) return st;
   if (nq == 0) return DDC_OK;
   GUARD_BEGIN
   ddc_index *ix = const_cast<ddc_index *>(ixc);
   DeviceGuard dg(ix->device);
-  search_device(ix, d_queries, nq, d_k, k_all, d_k ? k_max : k_all, d_nprobe, nprobe_all, npm,
-                significance, mode, d_out_offsets, d_ids, d_dists, d_counters,
-                reinterpret_cast<hipStream_t>(hip_stream), nullptr, nullptr, true, nullptr,
-                /*stream_scratch=*/true);
+  search_device(ix, d_queries, nq, d_k, k_all, d_k ? k_max : k_all, d_nprobe, nprobe_all,
+                d_nprobe ? nprobe_max : nprobe_all, significance, mode, d_out_offsets, d_ids,
+                d_dists, d_counters, reinterpret_cast<hipStream_t>(hip_stream), nullptr, nullptr,
+                true, nullptr, /*stream_scratch=*/true);
   return DDC_OK;
   GUARD_END
 }
@@ -1601,6 +1670,21 @@ ddc_status ddc_calibrate(ddc_index *ix, const float *calib, int64_t n_calib, int
 }
 
 }  // extern "C"
+
+ddc_status ddc::check_device_search(const ddc_index *ixc, const float *d_queries, int64_t nq,
+                                     const int32_t *d_k, int32_t k_all, int32_t k_max,
+                                     const int32_t *d_nprobe, int32_t nprobe_all, int32_t nprobe_max,
+                                     double significance, ddc_corr mode, const int64_t *d_out_offsets,
+                                     int64_t *d_ids, float *d_dists) {
+  ddc_status st = check_search_args(ixc, nq, significance, mode);
+  if (st != DDC_OK) return st;
+  if (nq > 0 && (!d_queries || !d_ids || !d_dists)) return set_err(DDC_EINVAL, "NULL buffer");
+  if (!d_k && (st = check_k_np(ixc, k_all, 1)) != DDC_OK) return st;
+  if (d_k && (k_max < 1 || k_max > kMaxK)) return set_err(DDC_EINVAL, "k_max must be in [1, %d]", kMaxK);
+  if (d_k && !d_out_offsets) return set_err(DDC_EINVAL, "per-query k needs out_offsets");
+  return check_k_np(ixc, 1, d_nprobe ? nprobe_max : nprobe_all);
+}
+
 
 // ---------------------------------------------------------------------------------------
 // fit

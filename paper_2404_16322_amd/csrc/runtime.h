@@ -162,6 +162,7 @@ struct ddc_index {
   std::mutex beta_mtx;
   std::map<std::tuple<double, int, int>, std::vector<double>> beta_cache;   // (alpha, mode, table)
   std::map<std::pair<double, int>, std::shared_ptr<ddc::DevBuf>> tab_cache; // device tables
+  std::map<std::pair<double, int>, std::shared_ptr<const std::vector<float>>> tab_host;  // their rows
   ddc::DevBuf d_R32, d_mu32, d_cent, d_cnorm, d_tile_off, d_list_len, d_ids, d_base, d_R64, d_mu64;
   int fp8 = 0;                      // FP8 pre-stage lead dims (0 or 64)
   double ads_eps0 = 2.1;            // eps0 of the ADSampling test
@@ -210,18 +211,35 @@ struct EstimateSpec {
   float scale;
 };
 
+// A caller-provided device workspace for one search: the correction tables at its start
+// (kTableBytes), then the scratch of search_scratch_bytes.
+struct Workspace {
+  void *p;
+  size_t bytes;
+  static constexpr size_t kTableBytes = 16384;
+};
+
 // The search pipeline on device buffers (rotation -> coarse -> select -> scan), queued on s.
 // est (nullable): rank by that estimate instead (mode and alpha are then ignored).
 // stream_scratch: take the scratch from s's grow-only workspace in the index (callers whose
 // streams live on; calls on one stream must not overlap), else from the stream-ordered pool.
+// ws (nullable): take tables and scratch from this workspace instead, allocate nothing, time
+// nothing and never tune (the caller has checked that it is large enough).
 void search_device(ddc_index *ix, const float *d_q, int64_t nq, const int32_t *d_k, int k_all,
                    int k_max, const int32_t *d_np, int np_all, int np_max, double alpha,
                    ddc_corr mode, const int64_t *d_off, int64_t *d_ids, float *d_d,
                    int64_t *d_ctr, hipStream_t s, float *qrot_out = nullptr,
                    int32_t *probes_out = nullptr, bool may_tune = true,
-                   const EstimateSpec *est = nullptr, bool stream_scratch = false);
-// Device bytes of one search's scratch for nq queries (from the stream-ordered pool, or the
-// stream's workspace).
+                   const EstimateSpec *est = nullptr, bool stream_scratch = false,
+                   const Workspace *ws = nullptr);
+// Argument checks of a search on device buffers (no device call).
+ddc_status check_device_search(const ddc_index *ix, const float *d_queries, int64_t nq,
+                               const int32_t *d_k, int32_t k_all, int32_t k_max,
+                               const int32_t *d_nprobe, int32_t nprobe_all, int32_t nprobe_max,
+                               double significance, ddc_corr mode, const int64_t *d_out_offsets,
+                               int64_t *d_ids, float *d_dists);
+// Device bytes of one search's scratch for nq queries (from the stream-ordered pool, the
+// stream's workspace, or a Workspace after its table bytes).
 size_t search_scratch_bytes(const ddc_index *ix, int64_t nq, int np_max);
 
 }  // namespace ddc

@@ -84,6 +84,10 @@ def test_search_rejects_bad_arguments_without_device(lib):
     rc = lib.ddc_search_device(None, None, 1, None, 10, 10, None, 1, 1, 0.1, 0, None, None, None,
                                None, None)
     assert rc == -1
+    rc = lib.ddc_search_device_noalloc(None, None, 1, None, 10, 10, None, 1, 1, 0.1, 0, None, None,
+                                       None, None, None)
+    assert rc == -1 and b"NULL" in lib.ddc_last_error()
+    assert lib.ddc_search_device_noalloc_bytes() == 64 << 20
     rc = lib.ddc_search_estimate(None, q.ctypes.data, 1, 10, 1, 32, 0, ids.ctypes.data, d.ctypes.data)
     assert rc == -1 and b"NULL" in lib.ddc_last_error()
     lp = B.LaunchParams(0, -1, 1, 1, -1)
