@@ -328,8 +328,9 @@ ddc_status ddc_debug_intermediates(const ddc_index *ix, const float *queries, in
 /* Per-kernel timing of the search pipeline with HIP events recorded on the launch stream
  * around every kernel of every later search on this index (enable = 1) or none (0).
  * Kernels: 0 query rotation (A1), 1 coarse centroid distances (A2), 2 probe selection (A2),
- * 3 pruned scan + top-K merge + finalize (A3-A5).  ddc_get_kernel_timing waits for the
- * recorded events, adds their elapsed times to ms_total[4] and counts to launches[4]
+ * 3 pruned scan + top-K merge + finalize (A3-A5), 4 the two-phase scan's first phase (its
+ * list grouping and stage-1 sums).  ddc_get_kernel_timing waits for the
+ * recorded events, adds their elapsed times to ms_total[5] and counts to launches[5]
  * (both caller arrays, overwritten), and clears the record when reset != 0. */
 ddc_status ddc_set_kernel_timing(ddc_index *ix, int enable);
 ddc_status ddc_get_kernel_timing(ddc_index *ix, double *ms_total, int64_t *launches, int reset);
@@ -355,17 +356,24 @@ ddc_status ddc_set_bsar_multiplier(ddc_index *ix, double m);
  * the batch), 1 (the grid holds only the workgroups the device keeps resident at once; each
  * takes the next query from a device counter until none is left, queries ordered by
  * decreasing candidate count so long scans start first; query_order does not apply), -1 =
- * tuned.  Defaults: 0, -1, 1, 1, -1. */
+ * tuned.  two_phase: 0 (every candidate's first dim block is read by its query's scan), 1 (for
+ * the learned and fixed-table tests with Delta_d = 32 and no FP8 pre-stage: first the partial
+ * distance over dim block 0 of every candidate of every probed list is computed list by list,
+ * each stored tile read once for all the queries that probe its list, in the scan's own
+ * arithmetic; the scan then tests those sums and reads dim blocks 1.. of the survivors only; its
+ * scratch holds one float per candidate of the batch), -1 = tuned (fixed rule: on once a list is
+ * probed by four or more queries on average).  Defaults: 0, -1, 1, 1, -1, -1. */
 typedef struct {
-  int32_t waves_per_query, lookahead, query_order, xcd_swizzle, persistent;
+  int32_t waves_per_query, lookahead, query_order, xcd_swizzle, persistent, two_phase;
 } ddc_launch_params;
 ddc_status ddc_set_launch(ddc_index *ix, const ddc_launch_params *p);
 ddc_status ddc_get_launch(const ddc_index *ix, ddc_launch_params *p);
 /* The scan variant a search of nq queries with this K, N_probe and mode runs: waves (1 or 4),
- * lookahead (0 or 1) and persistent (0 or 1; nullable).  A size class not tuned yet reports
- * the fixed rule's choice. */
+ * lookahead (0 or 1), persistent (0 or 1; nullable) and two_phase (0 or 1; nullable).  A size
+ * class not tuned yet reports the fixed rule's choice. */
 ddc_status ddc_scan_variant(ddc_index *ix, int64_t nq, int32_t k_max, int32_t nprobe_max,
-                            ddc_corr mode, int32_t *waves, int32_t *lookahead, int32_t *persistent);
+                            ddc_corr mode, int32_t *waves, int32_t *lookahead, int32_t *persistent,
+                            int32_t *two_phase);
 
 /* ---- continuous-batching server --------------------------------------------------------
  * A scheduler thread admits queued requests into micro-batches on n_streams HIP streams while

@@ -89,7 +89,8 @@ class ServerStats(C.Structure):
 
 class LaunchParams(C.Structure):
     _fields_ = [("waves_per_query", C.c_int32), ("lookahead", C.c_int32),
-                ("query_order", C.c_int32), ("xcd_swizzle", C.c_int32), ("persistent", C.c_int32)]
+                ("query_order", C.c_int32), ("xcd_swizzle", C.c_int32), ("persistent", C.c_int32),
+                ("two_phase", C.c_int32)]
 
 
 class DdcError(RuntimeError):
@@ -141,7 +142,8 @@ def load_library():
         lib.ddc_set_launch.argtypes = [vp, C.POINTER(LaunchParams)]
         lib.ddc_get_launch.argtypes = [vp, C.POINTER(LaunchParams)]
         lib.ddc_scan_variant.argtypes = [vp, i64, i32, i32, C.c_int, C.POINTER(C.c_int32),
-                                         C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+                                         C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                         C.POINTER(C.c_int32)]
         lib.ddc_server_create.argtypes = [vp, C.POINTER(ServerParams), C.POINTER(vp)]
         lib.ddc_server_submit.argtypes = [vp, vp, i32, vp, vp, C.POINTER(C.c_uint64)]
         lib.ddc_server_poll.argtypes = [vp, C.c_uint64, vp, vp, C.POINTER(C.c_int), C.POINTER(C.c_uint64)]
@@ -418,14 +420,15 @@ class Index:
 
     def set_launch(self, waves_per_query: int | None = None, lookahead: int | None = None,
                    query_order: int | None = None, xcd_swizzle: int | None = None,
-                   persistent: int | None = None):
+                   persistent: int | None = None, two_phase: int | None = None):
         """Result-invariant launch shape of the scan; None keeps the current value
-        (waves_per_query 0, lookahead -1 and persistent -1 mean tuned per size class)."""
+        (waves_per_query 0, lookahead -1, persistent -1 and two_phase -1 mean tuned per size
+        class)."""
         cur = self.launch()
         lp = LaunchParams(*(cur[k] if v is None else int(v) for k, v in
                             (("waves_per_query", waves_per_query), ("lookahead", lookahead),
                              ("query_order", query_order), ("xcd_swizzle", xcd_swizzle),
-                             ("persistent", persistent))))
+                             ("persistent", persistent), ("two_phase", two_phase))))
         _check(load_library().ddc_set_launch(self._h, C.byref(lp)))
 
     def launch(self) -> dict:
@@ -434,20 +437,21 @@ class Index:
         return {k: getattr(lp, k) for k, _ in LaunchParams._fields_}
 
     def scan_variant(self, nq: int, k: int, nprobe: int, mode: str = "learned") -> tuple:
-        """(waves per query, lookahead, persistent) a search of this shape runs (tuned or
-        fixed rule)."""
-        w, la, pe = C.c_int32(), C.c_int32(), C.c_int32()
+        """(waves per query, lookahead, persistent, two-phase) a search of this shape runs
+        (tuned or fixed rule)."""
+        w, la, pe, tp = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
         _check(load_library().ddc_scan_variant(self._h, nq, k, nprobe, CORR[mode], C.byref(w),
-                                               C.byref(la), C.byref(pe)))
-        return w.value, la.value, pe.value
+                                               C.byref(la), C.byref(pe), C.byref(tp)))
+        return w.value, la.value, pe.value, tp.value
 
     def set_kernel_timing(self, enable: bool):
         _check(load_library().ddc_set_kernel_timing(self._h, int(enable)))
 
     def kernel_timing(self, reset: bool = True):
-        """(ms_total[4], launches[4]) for rotation, coarse, select, scan since the last reset."""
-        ms = np.zeros(4)
-        n = np.zeros(4, np.int64)
+        """(ms_total[5], launches[5]) for rotation, coarse, select, scan and the two-phase
+        scan's first phase since the last reset."""
+        ms = np.zeros(5)
+        n = np.zeros(5, np.int64)
         _check(load_library().ddc_get_kernel_timing(self._h, _ptr(ms), _ptr(n), int(reset)))
         return ms, n
 

@@ -39,33 +39,50 @@ static std::array<int, 4> tune_class(int64_t nq, int np_max, int k_max, int kind
 }
 
 // kernel family of a launch: pruned or not, FP8 pre-stage, residual test, estimate only
+// Whether a launch can run two-phase: the learned or fixed-table stage tests on the stored
+// values with the first test right after dim block 0 and more blocks after it (no FP8
+// pre-stage, residual or quantization test, no estimate-only scan).
+static bool two_phase_eligible(const ddc_index *ix, const ScanArgs &a) {
+  return a.prune && !a.res && !a.pre && a.pq_m == 0 && a.est_nb == 0 && ix->NB > 1 && ix->St > 0 &&
+         ix->delta_d == kBlockDims && ix->d_tile_list.p != nullptr;
+}
+
 static int scan_kind(const ScanArgs &a) {
   return a.prune + 2 * a.pre + 4 * a.res + 8 * (a.est_nb > 0 ? 1 : 0) + 16 * (a.pq_m > 0 ? 1 : 0);
 }
 
-// Launch shape of the scan: waves per query (1 or 4), look-ahead (0 or 1), persistent (0 or 1).
-using Variant = std::array<int, 3>;
+// Launch shape of the scan: waves per query (1 or 4), look-ahead (0 or 1), persistent (0 or 1),
+// two-phase (0 or 1: stage-1 sums computed list by list first).
+using Variant = std::array<int, 4>;
 
 // Without measurements: a workgroup per query while the batch leaves the chip's wave slots
-// mostly empty, multi-block loads once vectors span eight or more dim blocks, one pass.
-static Variant fixed_variant(const ddc_index *ix, int64_t nq, int prune) {
-  return {nq < 4096 ? 4 : 1, prune && ix->NB >= 8 ? 1 : 0, 0};
+// mostly empty, multi-block loads once vectors span eight or more dim blocks, one pass, and the
+// two-phase scan once a list is probed by four or more queries on average.
+static Variant fixed_variant(const ddc_index *ix, int64_t nq, int prune, int np_max, bool two_ok) {
+  const bool reuse = two_ok && (double)nq * np_max >= 4.0 * ix->nlist;
+  return {nq < 4096 ? 4 : 1, prune && ix->NB >= 8 ? 1 : 0, 0, reuse ? 1 : 0};
 }
 
-static Variant forced_or(const ddc_index *ix, Variant v, int kind) {
+static Variant forced_or(const ddc_index *ix, Variant v, int kind, bool two_ok) {
   if (ix->waves_per_query) v[0] = ix->waves_per_query;
   if (ix->lookahead >= 0) v[1] = ix->lookahead;
   if (ix->persistent >= 0) v[2] = ix->persistent;
+  if (ix->two_phase >= 0) v[3] = ix->two_phase;
   if (!(kind & 1) || (kind & 4)) v[1] = 0;   // look-ahead only for the learned/fixed-table tests
+  if (!two_ok) v[3] = 0;
   return v;
 }
 
 // Query orders a launch may use: grouped by first probed list (one pass per workgroup), and
 // longest first with a slot counter (persistent), the latter made on first use (rebuild = true
 // makes it again: the tuner charges a persistent candidate for its order kernels).
+// stage1 (set when the launch may run two-phase) queues the first phase, made on first use
+// like longest_first, and returns the stage-1 sums and the per-query offsets into them.
 struct LaunchOrders {
   const int32_t *group = nullptr;
   std::function<std::pair<const int32_t *, int32_t *>(bool rebuild)> longest_first;
+  std::function<std::pair<const float *, const int64_t *>(bool rebuild)> stage1;
+  int64_t e1_cap = 0;
 };
 
 static void apply_variant(ScanArgs &a, const Variant &v, LaunchOrders &o) {
@@ -79,6 +96,16 @@ static void apply_variant(ScanArgs &a, const Variant &v, LaunchOrders &o) {
     a.order = o.group;
     a.queue = nullptr;
   }
+  if (v[3] && o.stage1) {
+    const auto e = o.stage1(false);
+    a.e1 = e.first;
+    a.e1_qoff = e.second;
+    a.e1_cap = o.e1_cap;
+  } else {
+    a.e1 = nullptr;
+    a.e1_qoff = nullptr;
+    a.e1_cap = 0;
+  }
 }
 
 // Sets the launch shape of a.  An untuned class is timed on this very launch (each candidate
@@ -87,12 +114,13 @@ static void apply_variant(ScanArgs &a, const Variant &v, LaunchOrders &o) {
 static void choose_variant(ddc_index *ix, ScanArgs &a, int np_max, hipStream_t s, bool may_tune,
                            LaunchOrders &orders) {
   const int kind = scan_kind(a);
-  const auto key = tune_class(a.nq, np_max, a.k_max, kind);
-  Variant v = fixed_variant(ix, a.nq, a.prune);
+  const bool two_ok = static_cast<bool>(orders.stage1);
+  const auto key = tune_class(a.nq, np_max, a.k_max, kind + (two_ok ? 32 : 0));
+  Variant v = fixed_variant(ix, a.nq, a.prune, np_max, two_ok);
   if (scan_lds_request(a, v[0]) > kMaxLds) v[0] = 4;   // e.g. four lookup tables of BSA-O
   const bool need_w = ix->waves_per_query == 0, need_l = a.prune && !a.res && ix->lookahead < 0;
-  const bool need_p = ix->persistent < 0;
-  if (need_w || need_l || need_p) {
+  const bool need_p = ix->persistent < 0, need_t = two_ok && ix->two_phase < 0;
+  if (need_w || need_l || need_p || need_t) {
     std::lock_guard<std::mutex> lk(ix->tune_mtx);
     auto it = ix->tuned.find(key);
     if (it != ix->tuned.end()) {
@@ -102,13 +130,14 @@ static void choose_variant(ddc_index *ix, ScanArgs &a, int np_max, hipStream_t s
       HIPC(hipStreamIsCapturing(s, &cs));
       if (may_tune && cs == hipStreamCaptureStatusNone) {
         std::vector<Variant> cand;   // simplest shapes first; shapes whose LDS does not fit skipped
-        for (int p : {0, 1})
-          for (int w : {1, 4})
-            for (int l : {0, 1}) {
-              auto c = forced_or(ix, {w, l, p}, kind);
-              if (scan_lds_request(a, c[0]) > kMaxLds) continue;
-              if (std::find(cand.begin(), cand.end(), c) == cand.end()) cand.push_back(c);
-            }
+        for (int t2 : {0, 1})
+          for (int p : {0, 1})
+            for (int w : {1, 4})
+              for (int l : {0, 1}) {
+                auto c = forced_or(ix, {w, l, p, t2}, kind, two_ok);
+                if (scan_lds_request(a, c[0]) > kMaxLds) continue;
+                if (std::find(cand.begin(), cand.end(), c) == cand.end()) cand.push_back(c);
+              }
         if (cand.empty()) cand.push_back(v);
         hipEvent_t e0, e1;
         HIPC(hipEventCreate(&e0));
@@ -121,6 +150,7 @@ static void choose_variant(ddc_index *ix, ScanArgs &a, int np_max, hipStream_t s
           for (int rep = 0; rep < 3; ++rep) {
             HIPC(hipEventRecord(e0, s));
             if (cand[ci][2]) orders.longest_first(true);   // the persistent launch's own order kernels
+            if (cand[ci][3]) orders.stage1(true);          // the two-phase launch's first phase
             launch_scan(t, ix->store(), s);
             HIPC(hipEventRecord(e1, s));
             HIPC(hipEventSynchronize(e1));
@@ -140,7 +170,7 @@ static void choose_variant(ddc_index *ix, ScanArgs &a, int np_max, hipStream_t s
       }
     }
   }
-  v = forced_or(ix, v, kind);
+  v = forced_or(ix, v, kind, two_ok);
   apply_variant(a, v, orders);
 }
 
@@ -229,6 +259,19 @@ static void upload_index(ddc_index *ix, const float *d_Y, hipStream_t s) {
   HIPC(hipMemcpy(ix->d_tile_off.p, ix->tile_off.data(), ix->tile_off.size() * 4, hipMemcpyHostToDevice));
   HIPC(hipMemcpy(ix->d_list_len.p, ix->list_len.data(), ix->list_len.size() * 4, hipMemcpyHostToDevice));
   if (!ids.empty()) HIPC(hipMemcpy(ix->d_ids.p, ids.data(), ids.size() * 4, hipMemcpyHostToDevice));
+  {
+    // list of every tile (the two-phase scan's first phase runs a workgroup per tile), and the
+    // list lengths in descending order, summed (a bound on any query's candidate count)
+    std::vector<int32_t> tl(std::max<int64_t>(ix->total_tiles, 1), -1);
+    for (int j = 0; j < ix->nlist; ++j)
+      for (int t = ix->tile_off[j]; t < ix->tile_off[j + 1]; ++t) tl[t] = j;
+    ix->d_tile_list.alloc(tl.size() * 4);
+    HIPC(hipMemcpy(ix->d_tile_list.p, tl.data(), tl.size() * 4, hipMemcpyHostToDevice));
+    std::vector<int64_t> ls(ix->list_len.begin(), ix->list_len.end());
+    std::sort(ls.begin(), ls.end(), std::greater<int64_t>());
+    ix->len_desc_prefix.assign(ls.size() + 1, 0);
+    for (size_t i = 0; i < ls.size(); ++i) ix->len_desc_prefix[i + 1] = ix->len_desc_prefix[i] + ls[i];
+  }
   DevBuf d_slot(std::max<size_t>(slot_row.size(), 1) * 8);
   if (!slot_row.empty())
     HIPC(hipMemcpy(d_slot.p, slot_row.data(), slot_row.size() * 8, hipMemcpyHostToDevice));
@@ -302,7 +345,7 @@ static ddc_index::Table run_calibration(ddc_index *ix, const float *calib, int64
     a.out_ids = d_cid.as<int64_t>(); a.out_d = d_cd.as<float>();
     a.nq = (int32_t)nc; a.nblocks = ix->NB; a.block_b = ix->B; a.prune = 0; a.nlist = ix->nlist;
     a.k_max = kp;
-    a.waves_per_query = fixed_variant(ix, nc, 0)[0];
+    a.waves_per_query = fixed_variant(ix, nc, 0, ix->nlist, false)[0];
     launch_scan(a, ix->store(), s);
   }
   std::vector<int64_t> cid((size_t)nc * kp);
@@ -674,20 +717,39 @@ static void *stream_workspace(ddc_index *ix, hipStream_t s, size_t bytes) {
 
 // Queries per scratch chunk, and the scratch pieces of one chunk of cmax queries: rotated
 // queries, coarse distances, probes, then the query orders' keys, histograms and ranks and the
-// persistent launch's slot counter; each piece 256-byte aligned.
+// persistent launch's slot counter; with two_phase the first phase's list counts and starts,
+// pair ranks, pairs by list, pair offsets, query counts and offsets, and its stage-1 sums (a
+// bound on the batch's candidates: cmax times the summed lengths of the np_max longest lists);
+// each piece 256-byte aligned.
 constexpr int64_t kChunk = 32768;
-constexpr int kParts = 11;
-static void scratch_sizes(const ddc_index *ix, int64_t cmax, int np_max, size_t (&sizes)[kParts]) {
+constexpr int kParts = 19;
+static int64_t e1_bound(const ddc_index *ix, int64_t cmax, int np_max) {
+  const int np = std::min<int>(std::max(np_max, 0), (int)ix->len_desc_prefix.size() - 1);
+  return np > 0 ? cmax * ix->len_desc_prefix[np] : 0;
+}
+static void scratch_sizes(const ddc_index *ix, int64_t cmax, int np_max, bool two_phase,
+                          size_t (&sizes)[kParts]) {
+  const size_t pairs = (size_t)cmax * np_max, t = two_phase ? 1 : 0;
   const size_t v[kParts] = {(size_t)cmax * ix->Dp * 4, (size_t)cmax * ix->nlist * 4,
                             (size_t)cmax * np_max * 4, (size_t)(ix->nlist + 1) * 4, (size_t)cmax * 4,
                             (size_t)cmax * 4, (size_t)cmax * 4, (size_t)257 * 4, (size_t)cmax * 4,
-                            (size_t)cmax * 4, 256};
+                            (size_t)cmax * 4, 256,
+                            t * (ix->nlist + 1) * 4, t * (ix->nlist + 1) * 4, t * pairs * 4, t * pairs * 4,
+                            t * pairs * 8, t * cmax * 8, t * (cmax + 1) * 8,
+                            t * (size_t)e1_bound(ix, cmax, np_max) * 4};
   for (int i = 0; i < kParts; ++i) sizes[i] = v[i];
 }
 
-size_t ddc::search_scratch_bytes(const ddc_index *ix, int64_t nq, int np_max) {
+// Queries per chunk: kChunk, fewer when the two-phase sums of a chunk would pass 4 GiB.
+static int64_t chunk_queries(const ddc_index *ix, int np_max, bool two_phase) {
+  if (!two_phase) return kChunk;
+  const int64_t per = std::max<int64_t>(1, e1_bound(ix, 1, np_max));
+  return std::max<int64_t>(1, std::min<int64_t>(kChunk, ((int64_t)1 << 30) / per));
+}
+
+size_t ddc::search_scratch_bytes(const ddc_index *ix, int64_t nq, int np_max, bool two_phase) {
   size_t sizes[kParts], total = 0;
-  scratch_sizes(ix, std::min(kChunk, nq), np_max, sizes);
+  scratch_sizes(ix, std::min(chunk_queries(ix, np_max, two_phase), nq), np_max, two_phase, sizes);
   for (size_t b : sizes) total += (b + 255) & ~(size_t)255;
   return total;
 }
@@ -772,16 +834,23 @@ void ddc::search_device(ddc_index *ix, const float *d_q, int64_t nq, const int32
       a.scale8 = ix->d_scale8.as<float>();
     }
   }
-  const int64_t chunk = kChunk;
   // Scratch of a chunk (rotated queries, coarse distances, probes, query orders), carved from
   // one buffer: a caller's fixed workspace after its table bytes; with stream_scratch and
   // outside graph capture the stream's grow-only workspace, reused call after call (stream
   // order keeps a call's kernels from overlapping the next call's use of it; per-call
   // stream-ordered allocations left the GPU idle about 30 us at every call); else one
   // stream-ordered allocation (which a captured graph records).
+  // the two-phase scan may run (its scratch is then part of the buffer)
+  ScanArgs elig{};
+  elig.prune = a.prune; elig.res = a.res; elig.pre = a.pre; elig.pq_m = a.pq_m; elig.est_nb = a.est_nb;
+  // (not for the fixed workspace, which has no room for the stage-1 sums, nor for callers that
+  // neither tune nor keep a stream workspace: the server sizes its admission budget without them)
+  const bool two_ok = !fixed_ws && !qrot_out && (may_tune || stream_scratch) && ix->two_phase != 0 &&
+                      two_phase_eligible(ix, elig);
+  const int64_t chunk = chunk_queries(ix, np_max, two_ok);
   const int64_t cmax = std::min(chunk, nq);
   size_t sizes[kParts];
-  scratch_sizes(ix, cmax, np_max, sizes);
+  scratch_sizes(ix, cmax, np_max, two_ok, sizes);
   size_t total = 0;
   for (size_t b : sizes) total += (b + 255) & ~(size_t)255;
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
@@ -802,7 +871,10 @@ void ddc::search_device(ddc_index *ix, const float *d_q, int64_t nq, const int32
     }
   }
   const ScratchPart qrot{part[0]}, cdist{part[1]}, probes{part[2]}, ord_hist{part[3]}, ord_rank{part[4]},
-      ord{part[5]}, lpt_key{part[6]}, lpt_hist{part[7]}, lpt_rank{part[8]}, lpt{part[9]}, queue{part[10]};
+      ord{part[5]}, lpt_key{part[6]}, lpt_hist{part[7]}, lpt_rank{part[8]}, lpt{part[9]}, queue{part[10]},
+      s1_lcnt{part[11]}, s1_lstart{part[12]}, s1_rank{part[13]}, s1_lpair{part[14]}, s1_poff{part[15]},
+      s1_qcnt{part[16]}, s1_qoff{part[17]}, s1_e1{part[18]};
+  const int64_t e1_cap = two_ok ? e1_bound(ix, cmax, np_max) : 0;
   for (int64_t q0 = 0; q0 < nq; q0 += chunk) {
     const int64_t nqc = std::min(chunk, nq - q0);
     GemmArgs g{};
@@ -854,6 +926,29 @@ void ddc::search_device(ddc_index *ix, const float *d_q, int64_t nq, const int32
       }
       return {lpt.as<int32_t>(), queue.as<int32_t>()};
     };
+    bool s1_made = false;
+    if (two_ok) {
+      orders.e1_cap = e1_cap;
+      orders.stage1 = [&](bool rebuild) -> std::pair<const float *, const int64_t *> {
+        const bool first = !s1_made;
+        s1_made = true;
+        if (first || rebuild) {
+          Stage1Args s1{};
+          s1.probes = probes.as<int32_t>(); s1.p_stride = np_max;
+          s1.nprobe = d_np ? d_np + q0 : nullptr; s1.nprobe_all = np_all;
+          s1.list_len = ix->d_list_len.as<int32_t>(); s1.tile_off = ix->d_tile_off.as<int32_t>();
+          s1.tile_list = ix->d_tile_list.as<int32_t>(); s1.nlist = ix->nlist;
+          s1.total_tiles = ix->total_tiles; s1.nq = nqc;
+          s1.qrot = qrot.as<float>(); s1.q_stride = Dp; s1.base = ix->d_base.p; s1.nblocks = ix->NB;
+          s1.lcnt = s1_lcnt.as<int32_t>(); s1.lstart = s1_lstart.as<int32_t>();
+          s1.rank = s1_rank.as<int32_t>(); s1.lpair = s1_lpair.as<int32_t>();
+          s1.poff = s1_poff.as<int64_t>(); s1.qcnt = s1_qcnt.as<int64_t>(); s1.qoff = s1_qoff.as<int64_t>();
+          s1.e1 = s1_e1.as<float>(); s1.e1_cap = e1_cap;
+          timed(ix, 4, s, [&] { launch_stage1_lists(s1, ix->store(), s); }, fixed_ws);
+        }
+        return {s1_e1.as<float>(), s1_qoff.as<int64_t>()};
+      };
+    }
     a.xcd_swizzle = ix->xcd_swizzle;
     a.nq = (int32_t)nqc; a.nblocks = ix->NB; a.block_b = ix->B; a.nlist = ix->nlist;
     a.k_max = k_max; a.lag = ix->L;
@@ -1557,7 +1652,7 @@ ddc_status ddc_get_kernel_timing(ddc_index *ix, double *ms_total, int64_t *launc
   GUARD_BEGIN
   DeviceGuard dg(ix->device);
   std::lock_guard<std::mutex> lk(ix->timing_mtx);
-  for (int i = 0; i < 4; ++i) { ms_total[i] = 0.0; launches[i] = 0; }
+  for (int i = 0; i < 5; ++i) { ms_total[i] = 0.0; launches[i] = 0; }
   for (auto &m : ix->marks) {
     HIPC(hipEventSynchronize(m.b));
     float ms = 0.f;
@@ -1596,6 +1691,7 @@ ddc_status ddc_set_launch(ddc_index *ix, const ddc_launch_params *p) {
   if ((p->query_order != 0 && p->query_order != 1) || (p->xcd_swizzle != 0 && p->xcd_swizzle != 1))
     return set_err(DDC_EINVAL, "query_order and xcd_swizzle must be 0 or 1");
   if (p->persistent < -1 || p->persistent > 1) return set_err(DDC_EINVAL, "persistent must be -1, 0 or 1");
+  if (p->two_phase < -1 || p->two_phase > 1) return set_err(DDC_EINVAL, "two_phase must be -1, 0 or 1");
   std::lock_guard<std::mutex> lk(ix->tune_mtx);
   ix->tuned.clear();   // a choice tuned under other forced knobs may not be the best now
   ix->waves_per_query = p->waves_per_query;
@@ -1603,6 +1699,7 @@ ddc_status ddc_set_launch(ddc_index *ix, const ddc_launch_params *p) {
   ix->query_order = p->query_order;
   ix->xcd_swizzle = p->xcd_swizzle;
   ix->persistent = p->persistent;
+  ix->two_phase = p->two_phase;
   return DDC_OK;
 }
 
@@ -1613,11 +1710,13 @@ ddc_status ddc_get_launch(const ddc_index *ix, ddc_launch_params *p) {
   p->query_order = ix->query_order;
   p->xcd_swizzle = ix->xcd_swizzle;
   p->persistent = ix->persistent;
+  p->two_phase = ix->two_phase;
   return DDC_OK;
 }
 
 ddc_status ddc_scan_variant(ddc_index *ix, int64_t nq, int32_t k_max, int32_t nprobe_max,
-                            ddc_corr mode, int32_t *waves, int32_t *lookahead, int32_t *persistent) {
+                            ddc_corr mode, int32_t *waves, int32_t *lookahead, int32_t *persistent,
+                            int32_t *two_phase) {
   if (!ix || !waves || !lookahead) return set_err(DDC_EINVAL, "NULL argument");
   if (nq < 1 || k_max < 1 || nprobe_max < 1) return set_err(DDC_EINVAL, "sizes must be >= 1");
   // the kernel family a search in this mode launches (significance > 0 assumed for LEARNED)
@@ -1626,23 +1725,24 @@ ddc_status ddc_scan_variant(ddc_index *ix, int64_t nq, int32_t k_max, int32_t np
   const int kind = prune + 2 * (mode == DDC_CORR_LEARNED && ix->P() ? 1 : 0) +
                    4 * (mode == DDC_CORR_BSAR && prune ? 1 : 0) + 16 * (mode == DDC_CORR_BSAO ? 1 : 0);
   const int64_t nqc = std::min<int64_t>(nq, 32768);
-  Variant v = fixed_variant(ix, nqc, prune);
-  {
-    ScanArgs la{};
-    la.nblocks = ix->NB; la.k_max = k_max; la.block_b = ix->B; la.res = mode == DDC_CORR_BSAR;
-    la.pq_m = mode == DDC_CORR_BSAO ? ix->pq_m : 0;
-    la.p_stride = nprobe_max; la.lag = ix->L;   // as the search sets them
-    if (scan_lds_request(la, v[0]) > kMaxLds) v[0] = 4;
-  }
+  ScanArgs la{};
+  la.nblocks = ix->NB; la.k_max = k_max; la.block_b = ix->B; la.res = mode == DDC_CORR_BSAR;
+  la.pq_m = mode == DDC_CORR_BSAO ? ix->pq_m : 0;
+  la.pre = (kind & 2) ? 1 : 0; la.prune = prune;
+  la.p_stride = nprobe_max; la.lag = ix->L;   // as the search sets them
+  const bool two_ok = two_phase_eligible(ix, la);
+  Variant v = fixed_variant(ix, nqc, prune, nprobe_max, two_ok);
+  if (scan_lds_request(la, v[0]) > kMaxLds) v[0] = 4;
   {
     std::lock_guard<std::mutex> lk(ix->tune_mtx);
-    auto it = ix->tuned.find(tune_class(nqc, nprobe_max, k_max, kind));
+    auto it = ix->tuned.find(tune_class(nqc, nprobe_max, k_max, kind + (two_ok ? 32 : 0)));
     if (it != ix->tuned.end()) v = it->second;
   }
-  v = forced_or(ix, v, kind);
+  v = forced_or(ix, v, kind, two_ok);
   *waves = v[0];
   *lookahead = v[1];
   if (persistent) *persistent = v[2];
+  if (two_phase) *two_phase = v[3];
   return DDC_OK;
 }
 

@@ -78,9 +78,35 @@ struct ScanArgs {
   int32_t ntab;
   int32_t tab_k[kMaxTables];
   int8_t test_after[kMaxBlocks]; // 1 if a stage test follows block b
+  // Two-phase scan: when e1 is set, the partial distance after dim block 0 of every candidate
+  // of every probed list was computed beforehand list by list (launch_stage1_lists): query q's
+  // candidates start at e1[e1_qoff[q]], its lists' in probe order, each list's in stored order.
+  // The first stage test then reads these instead of the base (bit-identical sums).
+  const float *e1;
+  const int64_t *e1_qoff;
+  int64_t e1_cap;          // entries of e1 (no read at or past it)
 };
 
 void launch_scan(const ScanArgs &a, int store, hipStream_t s);
+
+// First phase of the two-phase scan: the partial distance over dim block 0 of every candidate
+// of every probed list, computed list by list so each stored tile is read once for all the
+// queries that probe its list, with the arithmetic (and rounding) of the scan's own first
+// stage.  Probes of query q: probes[q * p_stride + p], p < clamp(nprobe[q], 1, p_stride), every
+// list at most once per query.  Scratch (caller's): lcnt, lstart [nlist + 1]; rank, lpair
+// [nq * p_stride] int32; poff [nq * p_stride], qcnt [nq], qoff [nq + 1] int64; e1 [e1_cap].
+struct Stage1Args {
+  const int32_t *probes; int32_t p_stride;
+  const int32_t *nprobe; int32_t nprobe_all;
+  const int32_t *list_len, *tile_off, *tile_list;   // tile_list: [total_tiles] list of each tile
+  int32_t nlist; int64_t total_tiles; int64_t nq;
+  const float *qrot; int64_t q_stride;
+  const void *base; int32_t nblocks;
+  int32_t *lcnt, *lstart, *rank, *lpair;
+  int64_t *poff, *qcnt, *qoff;
+  float *e1; int64_t e1_cap;
+};
+void launch_stage1_lists(const Stage1Args &a, int store, hipStream_t s);
 // LDS bytes one workgroup of the scan needs with W waves per query (> kMaxLds: not launchable).
 size_t scan_lds_request(const ScanArgs &a, int W);
 

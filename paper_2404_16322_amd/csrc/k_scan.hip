@@ -394,6 +394,8 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
     }
   };
 
+  // two-phase scan: the first e1 entry of the current list (its candidates follow in order)
+  int64_t e1_at = a.e1 ? a.e1_qoff[q] : 0;
   for (int p = 0; p < np; ++p) {
     int lst, len, toff;
     if (meta_lds) {
@@ -405,6 +407,8 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
       len = (lst >= 0 && lst < a.nlist) ? a.list_len[lst] : 0;
       toff = (lst >= 0 && lst < a.nlist) ? a.tile_off[lst] : 0;
     }
+    const int64_t e1_list = e1_at;
+    e1_at += (lst >= 0 && lst < a.nlist) ? len : 0;
     if (lst < 0 || lst >= a.nlist) continue;  // never follow an invalid list id
     const unsigned char *lbase = reinterpret_cast<const unsigned char *>(a.base) +
                                  (int64_t)toff * nb * BLOCK_BYTES;  // wave-uniform
@@ -601,6 +605,35 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
           listed = true;
         }
         int b = 0;
+        if (!PQ && !PRE && !RES && a.e1) {
+          // ---- two-phase scan: the stage-1 sums of the segment come from e1 (one 4-byte load
+          // per candidate instead of its dim block 0); the test after block 0 as the one-stage
+          // path takes it; survivors go to the alive list and the stages continue at block 1 ----
+          const float mb = s_mb[0], bb = s_mb[1];
+          const int64_t e0 = e1_list + bs + s0;
+          int nn = 0, pruned = 0;
+          for (int t0 = 0; t0 < slen; t0 += 64) {
+            const int idx = t0 + lane;
+            const bool valid = idx < slen && e0 + idx < a.e1_cap;
+            const float ev = valid ? a.e1[e0 + idx] : 0.f;
+            const bool prune = valid && fmaf(mb, ev, bb) > tau_t;
+            const bool keep = valid && !prune;
+            const unsigned long long bal = __ballot(keep);
+            if (keep) {
+              const int pos = nn + __popcll(bal & lt);
+              s_ac[pos] = (uint16_t)idx;
+              s_ae[pos] = ev;
+            }
+            nn += __popcll(bal);
+            pruned += __popcll(__ballot(prune));
+          }
+          st_slices += slen;
+          if (ctr) stop_add(0, (uint32_t)pruned);
+          __builtin_amdgcn_wave_barrier();
+          nalive = nn;
+          listed = true;
+          b = 1;
+        }
         while (b < nb && nalive > 0) {
           if (LOOK && nalive <= 8 && 64 / (nalive <= 1 ? 1 : nalive <= 2 ? 2 : nalive <= 4 ? 4 : 8) > G &&
               nb - b > G) {
@@ -1102,6 +1135,188 @@ void launch_work_order(const int32_t *probes, int32_t p_stride, const int32_t *n
   hipLaunchKernelGGL(work_key_kernel, dim3((unsigned)((nq + 3) / 4)), dim3(256), 0, s, probes,
                      p_stride, nprobe, nprobe_all, list_len, nlist, nq, key);
   launch_query_order(key, 1, nq, 256, hist, rank, order, s);
+}
+
+// ---- two-phase scan, first phase: stage-1 partial distances list by list ----------------
+
+// Exclusive prefix sum in one workgroup: start[i] = cnt[0] + ... + cnt[i-1], start[n] = total.
+constexpr int kScanPrefixThreads = 1024;
+template <class T>
+__global__ __launch_bounds__(kScanPrefixThreads) void excl_prefix_kernel(const T *cnt, int64_t n, T *start) {
+  __shared__ T wsum[kScanPrefixThreads / 64];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int64_t chunk = (n + kScanPrefixThreads - 1) / kScanPrefixThreads;
+  const int64_t b0 = min(n, t * chunk), b1 = min(n, b0 + chunk);
+  T sum = 0;
+  for (int64_t i = b0; i < b1; ++i) sum += cnt[i];
+  T inc = sum;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const T v = __shfl_up(inc, o);
+    if (lane >= o) inc += v;
+  }
+  if (lane == 63) wsum[w] = inc;
+  __syncthreads();
+  if (t == 0) {
+    T c = 0;
+    for (int i = 0; i < kScanPrefixThreads / 64; ++i) { const T v = wsum[i]; wsum[i] = c; c += v; }
+    start[n] = c;
+  }
+  __syncthreads();
+  T c = wsum[w] + inc - sum;
+  for (int64_t i = b0; i < b1; ++i) { const T v = cnt[i]; start[i] = c; c += v; }
+}
+
+// One wavefront per query: offset of each probed list's first candidate among the query's
+// candidates (lengths of the lists before it, in probe order) and the query's total.
+__global__ __launch_bounds__(256) void pair_offsets_kernel(const int32_t *probes, int32_t p_stride,
+                                                           const int32_t *nprobe, int32_t nprobe_all,
+                                                           const int32_t *list_len, int32_t nlist,
+                                                           int64_t nq, int64_t *poff, int64_t *qcnt) {
+  const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (q >= nq) return;
+  const int np = min(max(nprobe ? nprobe[q] : nprobe_all, 1), p_stride);
+  int64_t carry = 0;
+  for (int p0 = 0; p0 < np; p0 += 64) {
+    const int p = p0 + lane;
+    int64_t len = 0;
+    if (p < np) {
+      const int l = probes[q * p_stride + p];
+      len = (l >= 0 && l < nlist) ? list_len[l] : 0;
+    }
+    int64_t inc = len;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int64_t v = __shfl_up(inc, o);
+      if (lane >= o) inc += v;
+    }
+    if (p < np) poff[q * p_stride + p] = carry + inc - len;
+    carry += __shfl(inc, 63);
+  }
+  if (lane == 0) qcnt[q] = carry;
+}
+
+// Probed (query, list) pairs grouped by list: count, then scatter after the prefix sum.
+__global__ __launch_bounds__(256) void pair_count_kernel(const int32_t *probes, int32_t p_stride,
+                                                         const int32_t *nprobe, int32_t nprobe_all,
+                                                         int32_t nlist, int64_t nq, int32_t *lcnt,
+                                                         int32_t *rank) {
+  const int64_t pidx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (pidx >= nq * p_stride) return;
+  const int64_t q = pidx / p_stride;
+  const int p = (int)(pidx - q * p_stride);
+  if (p >= min(max(nprobe ? nprobe[q] : nprobe_all, 1), p_stride)) return;
+  const int l = probes[pidx];
+  if (l >= 0 && l < nlist) rank[pidx] = atomicAdd(&lcnt[l], 1);
+}
+
+__global__ __launch_bounds__(256) void pair_scatter_kernel(const int32_t *probes, int32_t p_stride,
+                                                           const int32_t *nprobe, int32_t nprobe_all,
+                                                           int32_t nlist, int64_t nq, const int32_t *lstart,
+                                                           const int32_t *rank, int32_t *lpair) {
+  const int64_t pidx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (pidx >= nq * p_stride) return;
+  const int64_t q = pidx / p_stride;
+  const int p = (int)(pidx - q * p_stride);
+  if (p >= min(max(nprobe ? nprobe[q] : nprobe_all, 1), p_stride)) return;
+  const int l = probes[pidx];
+  if (l >= 0 && l < nlist) lpair[lstart[l] + rank[pidx]] = (int32_t)pidx;
+}
+
+// One workgroup per stored tile: its 64 vectors' dim block 0 stay in registers while the four
+// waves take the queries that probe its list in turn.  Lane (sub, g) holds dims
+// [g EPL, g EPL + EPL) of vectors c CPW + sub (c < MAXCH); each query's partial sums are formed
+// exactly as the scan's one-stage path forms them (per-lane FMA chain, then the transposed
+// group reduction), so lane (g, sub) ends with vector g CPW + sub's sum.
+template <int ST>
+__global__ __launch_bounds__(256) void stage1_lists_kernel(Stage1Args a) {
+  using S = Store<ST>;
+  constexpr int EPL = 16 / S::kBytes;
+  constexpr int G = kBlockDims / EPL;
+  constexpr int CPW = 64 / G;
+  constexpr int MAXCH = 64 / CPW;
+  constexpr int SLICE = kBlockDims * S::kBytes;
+  constexpr int64_t BLOCK_BYTES = (int64_t)kTile * SLICE;
+  const int64_t t = blockIdx.x;
+  if (t >= a.total_tiles) return;
+  const int l = a.tile_list[t];
+  if (l < 0 || l >= a.nlist) return;
+  const int pb = a.lstart[l], pe = a.lstart[l + 1];
+  if (pb >= pe) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane % G, sub = lane / G;
+  const int tl = (int)(t - a.tile_off[l]);                 // tile within its list
+  const int cnt = min(kTile, a.list_len[l] - tl * kTile);  // stored vectors in this tile
+  const unsigned char *tp = reinterpret_cast<const unsigned char *>(a.base) + t * a.nblocks * BLOCK_BYTES + g * 16;
+  float f[MAXCH][EPL];
+#pragma unroll
+  for (int c = 0; c < MAXCH; ++c) {
+    const uint4 v = *reinterpret_cast<const uint4 *>(tp + (c * CPW + sub) * SLICE);
+    S::unpack(v, f[c]);
+  }
+  const int mine = g * CPW + sub;   // the vector this lane's sum belongs to
+  // two queries per round: their query slices are loaded together
+  for (int i = pb + wave; i < pe; i += 8) {
+    int64_t dst[2];
+    float qv[2][EPL];
+    bool have[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int j = i + 4 * u;
+      have[u] = j < pe;
+      const int pidx = a.lpair[have[u] ? j : i];
+      const int64_t q = pidx / a.p_stride;
+      dst[u] = a.qoff[q] + a.poff[pidx] + (int64_t)tl * kTile;
+      const float4 *qp = reinterpret_cast<const float4 *>(a.qrot + q * a.q_stride + g * EPL);
+#pragma unroll
+      for (int e4 = 0; e4 < EPL / 4; ++e4) {
+        const float4 x = qp[e4];
+        qv[u][4 * e4] = x.x; qv[u][4 * e4 + 1] = x.y; qv[u][4 * e4 + 2] = x.z; qv[u][4 * e4 + 3] = x.w;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      float part[MAXCH];
+#pragma unroll
+      for (int c = 0; c < MAXCH; ++c) {
+        float acc = 0.f;
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) {
+          const float d = f[c][e] - qv[u][e];
+          acc = fmaf(d, d, acc);
+        }
+        part[c] = acc;
+      }
+      const float tot = transpose_sum<G>(part, g);
+      const int64_t o = dst[u] + mine;
+      if (have[u] && mine < cnt && o < a.e1_cap) a.e1[o] = tot;
+    }
+  }
+}
+
+void launch_stage1_lists(const Stage1Args &a, int store, hipStream_t s) {
+  if (a.nq <= 0 || a.total_tiles <= 0) return;
+  const int64_t npair = a.nq * a.p_stride;
+  const unsigned gp = (unsigned)((npair + 255) / 256);
+  hipLaunchKernelGGL(fill_i32_kernel, dim3((a.nlist + 256) / 256), dim3(256), 0, s, a.lcnt,
+                     (int64_t)a.nlist + 1, 0);
+  hipLaunchKernelGGL(pair_offsets_kernel, dim3((unsigned)((a.nq + 3) / 4)), dim3(256), 0, s, a.probes,
+                     a.p_stride, a.nprobe, a.nprobe_all, a.list_len, a.nlist, a.nq, a.poff, a.qcnt);
+  hipLaunchKernelGGL(excl_prefix_kernel<int64_t>, dim3(1), dim3(kScanPrefixThreads), 0, s, a.qcnt, a.nq,
+                     a.qoff);
+  hipLaunchKernelGGL(pair_count_kernel, dim3(gp), dim3(256), 0, s, a.probes, a.p_stride, a.nprobe,
+                     a.nprobe_all, a.nlist, a.nq, a.lcnt, a.rank);
+  hipLaunchKernelGGL(excl_prefix_kernel<int32_t>, dim3(1), dim3(kScanPrefixThreads), 0, s, a.lcnt,
+                     (int64_t)a.nlist, a.lstart);
+  hipLaunchKernelGGL(pair_scatter_kernel, dim3(gp), dim3(256), 0, s, a.probes, a.p_stride, a.nprobe,
+                     a.nprobe_all, a.nlist, a.nq, a.lstart, a.rank, a.lpair);
+  const dim3 grid((unsigned)a.total_tiles);
+  switch (store) {
+    case ST_F32: hipLaunchKernelGGL(stage1_lists_kernel<ST_F32>, grid, dim3(256), 0, s, a); break;
+    case ST_F16: hipLaunchKernelGGL(stage1_lists_kernel<ST_F16>, grid, dim3(256), 0, s, a); break;
+    default: hipLaunchKernelGGL(stage1_lists_kernel<ST_BF16>, grid, dim3(256), 0, s, a); break;
+  }
 }
 
 // Workgroups of this kernel that fit on the device at once (occupancy x compute units).

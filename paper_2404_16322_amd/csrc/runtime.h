@@ -142,6 +142,7 @@ struct ddc_index {
   std::vector<int32_t> list_len, tile_off;
   std::vector<int64_t> id_to_slot;  // n
   int64_t total_tiles = 0;
+  std::vector<int64_t> len_desc_prefix;   // [nlist + 1] sums of the longest lists' lengths
   // correction tables, ascending calibration K_c; a search with K uses the last with
   // kc <= K (the first when none): m [Tt], resid [n0 x Tt] (label-0 residuals)
   // pq: the BSA-O classifier m1 dis' + m3 err + beta > tau of the same label-0/1 pairs, with
@@ -164,6 +165,7 @@ struct ddc_index {
   std::map<std::pair<double, int>, std::shared_ptr<ddc::DevBuf>> tab_cache; // device tables
   std::map<std::pair<double, int>, std::shared_ptr<const std::vector<float>>> tab_host;  // their rows
   ddc::DevBuf d_R32, d_mu32, d_cent, d_cnorm, d_tile_off, d_list_len, d_ids, d_base, d_R64, d_mu64;
+  ddc::DevBuf d_tile_list;          // [total_tiles] list of each tile
   int fp8 = 0;                      // FP8 pre-stage lead dims (0 or 64)
   double ads_eps0 = 2.1;            // eps0 of the ADSampling test
   double bsar_m = 8.0;              // multiplier of the residual test (<= 0: from the significance)
@@ -192,9 +194,10 @@ struct ddc_index {
 
   // result-invariant launch knobs of the scan (0 / -1 = tuned per size class)
   int waves_per_query = 0, lookahead = -1, query_order = 1, xcd_swizzle = 1, persistent = -1;
+  int two_phase = -1;
   std::mutex tune_mtx;
-  // class -> (waves per query, look-ahead, persistent)
-  std::map<std::array<int, 4>, std::array<int, 3>> tuned;
+  // class -> (waves per query, look-ahead, persistent, two-phase)
+  std::map<std::array<int, 4>, std::array<int, 4>> tuned;
   int store() const {
     return storage == DDC_F32 ? ddc::ST_F32 : storage == DDC_F16 ? ddc::ST_F16 : ddc::ST_BF16;
   }
@@ -240,6 +243,6 @@ ddc_status check_device_search(const ddc_index *ix, const float *d_queries, int6
                                int64_t *d_ids, float *d_dists);
 // Device bytes of one search's scratch for nq queries (from the stream-ordered pool, the
 // stream's workspace, or a Workspace after its table bytes).
-size_t search_scratch_bytes(const ddc_index *ix, int64_t nq, int np_max);
+size_t search_scratch_bytes(const ddc_index *ix, int64_t nq, int np_max, bool two_phase = false);
 
 }  // namespace ddc

@@ -12,7 +12,7 @@ from parity_util import artifacts, check_search, oracle_index, workload
 
 pytestmark = pytest.mark.gpu
 
-VARIANTS = [(w, la, p) for p in (0, 1) for w in (1, 4) for la in (0, 1)]
+VARIANTS = [(w, la, p, t) for t in (0, 1) for p in (0, 1) for w in (1, 4) for la in (0, 1)]
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -28,10 +28,10 @@ def _index(ix, with_table=True):
 
 def _all_variants(g, run):
     out = []
-    for w, la, p in VARIANTS:
-        g.set_launch(waves_per_query=w, lookahead=la, persistent=p)
+    for w, la, p, t in VARIANTS:
+        g.set_launch(waves_per_query=w, lookahead=la, persistent=p, two_phase=t)
         out.append(run())
-    g.set_launch(waves_per_query=0, lookahead=-1, persistent=-1)
+    g.set_launch(waves_per_query=0, lookahead=-1, persistent=-1, two_phase=-1)
     return out
 
 

@@ -8,7 +8,8 @@
   256, in every launch shape; at 768 dims with 16-bit storage the deep look-ahead is entered
   from the pre-stage's alive list;
 * more probed lists than the scan keeps in LDS (nprobe_max > 256), so list ids, lengths and
-  first tiles come from memory, in both wave shapes, one pass and persistent, also lagged.
+  first tiles come from memory, in both wave shapes, one pass and persistent, one phase and
+  two-phase, also lagged.
 """
 import numpy as np
 import pytest
@@ -18,7 +19,7 @@ from parity_util import artifacts, check_search, workload
 
 pytestmark = pytest.mark.gpu
 
-VARIANTS = [(w, la, p) for p in (0, 1) for w in (1, 4) for la in (0, 1)]
+VARIANTS = [(w, la, p, t) for t in (0, 1) for p in (0, 1) for w in (1, 4) for la in (0, 1)]
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -62,10 +63,10 @@ def _per_query(nq, seed, np_hi=256):
 
 def _check_var(g, ix, Q, ks, nps, alpha, label):
     res = []
-    for w, la, p in VARIANTS:
-        g.set_launch(waves_per_query=w, lookahead=la, persistent=p)
+    for w, la, p, t in VARIANTS:
+        g.set_launch(waves_per_query=w, lookahead=la, persistent=p, two_phase=t)
         res.append(g.search_var(Q, ks, nps, alpha))
-    g.set_launch(waves_per_query=0, lookahead=-1, persistent=-1)
+    g.set_launch(waves_per_query=0, lookahead=-1, persistent=-1, two_phase=-1)
     ids, d, off, st = res[0]
     for r in res[1:]:     # every launch shape: bit-identical results and work counters
         np.testing.assert_array_equal(r[0], ids)
@@ -146,10 +147,10 @@ def test_probe_table_beyond_lds(many_lists, lag):
     ix = ixs[lag]
     g = _index(ix)
     Q = w["queries"][:40]
-    shapes = [(1, 0), (1, 1), (4, 0), (4, 1)]      # (waves per query, persistent)
+    shapes = [(wv, p, t) for t in (0, 1) for wv in (1, 4) for p in (0, 1)]   # (waves, persistent, two-phase)
     fixed = []
-    for wv, p in shapes:
-        g.set_launch(waves_per_query=wv, lookahead=0, persistent=p)
+    for wv, p, t in shapes:
+        g.set_launch(waves_per_query=wv, lookahead=0, persistent=p, two_phase=t)
         fixed.append(g.search(Q, 10, 300, 0.1)[:2])
     for r in fixed[1:]:
         np.testing.assert_array_equal(r[0], fixed[0][0])
@@ -160,8 +161,8 @@ def test_probe_table_beyond_lds(many_lists, lag):
     ks = rng.choice([1, 10, 50, 100], size=Q.shape[0]).astype(np.int32)
     nps = rng.integers(200, 401, size=Q.shape[0]).astype(np.int32)
     var = []
-    for wv, p in shapes:
-        g.set_launch(waves_per_query=wv, lookahead=0, persistent=p)
+    for wv, p, t in shapes:
+        g.set_launch(waves_per_query=wv, lookahead=0, persistent=p, two_phase=t)
         var.append(g.search_var(Q, ks, nps, 0.1))
     g.set_launch(waves_per_query=0, lookahead=-1, persistent=-1)
     for r in var[1:]:

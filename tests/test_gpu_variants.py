@@ -1,7 +1,8 @@
 """Launch-shape variants of the scan (one wavefront or a workgroup of four per query, with and
 without multi-block look-ahead loads, one pass per workgroup or a persistent grid taking queries
-longest first from a counter) return bit-identical results, which match the oracle; the tuner
-picks one of them per size class."""
+longest first from a counter, with or without the stage-1 sums computed list by list first)
+return bit-identical results, which match the oracle; the tuner picks one of them per size
+class."""
 import numpy as np
 import pytest
 
@@ -10,7 +11,7 @@ from parity_util import artifacts, check_search, oracle_index, workload
 
 pytestmark = pytest.mark.gpu
 
-VARIANTS = [(w, la, p) for p in (0, 1) for w in (1, 4) for la in (0, 1)]
+VARIANTS = [(w, la, p, t) for t in (0, 1) for p in (0, 1) for w in (1, 4) for la in (0, 1)]
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -26,10 +27,10 @@ def _index(ix):
 
 def _all_variants(g, run):
     out = []
-    for w, la, p in VARIANTS:
-        g.set_launch(waves_per_query=w, lookahead=la, persistent=p)
+    for w, la, p, t in VARIANTS:
+        g.set_launch(waves_per_query=w, lookahead=la, persistent=p, two_phase=t)
         out.append(run())
-    g.set_launch(waves_per_query=0, lookahead=-1, persistent=-1)
+    g.set_launch(waves_per_query=0, lookahead=-1, persistent=-1, two_phase=-1)
     return out
 
 
@@ -100,16 +101,17 @@ def test_tuner_picks_a_variant_and_caches_it():
     w = workload("gauss128")
     g = _index(ix)
     assert g.launch() == dict(waves_per_query=0, lookahead=-1, query_order=1, xcd_swizzle=1,
-                              persistent=-1)
+                              persistent=-1, two_phase=-1)
     ids0, d0, _ = g.search(w["queries"], 10, 8, 0.1)
     v = g.scan_variant(w["queries"].shape[0], 10, 8)
     assert v in VARIANTS
     ids1, d1, _ = g.search(w["queries"], 10, 8, 0.1)
     np.testing.assert_array_equal(ids0, ids1)
     np.testing.assert_array_equal(d0, d1)
-    g.set_launch(waves_per_query=4, lookahead=0, query_order=0, xcd_swizzle=0, persistent=1)
-    assert g.scan_variant(1000, 10, 8) == (4, 0, 1)
-    assert g.scan_variant(1000, 10, 8, mode="none") == (4, 0, 1)
+    g.set_launch(waves_per_query=4, lookahead=0, query_order=0, xcd_swizzle=0, persistent=1,
+                 two_phase=1)
+    assert g.scan_variant(1000, 10, 8) == (4, 0, 1, 1)
+    assert g.scan_variant(1000, 10, 8, mode="none") == (4, 0, 1, 0)   # no test: one phase
     ids2, d2, _ = g.search(w["queries"], 10, 8, 0.1)
     np.testing.assert_array_equal(ids0, ids2)
     np.testing.assert_array_equal(d0, d2)
@@ -126,10 +128,12 @@ def test_persistent_grid_smaller_than_batch():
     ks = np.tile(rng.integers(1, 64, 100), 120).astype(np.int32)
     nps = np.tile(rng.integers(1, 33, 100), 120).astype(np.int32)
     res = []
-    for wv in (1, 4):
-        for p in (0, 1):
-            g.set_launch(waves_per_query=wv, lookahead=0, persistent=p)
-            res.append(g.search_var(Q, ks, nps, 0.1))
+    for t in (0, 1):
+        for wv in (1, 4):
+            for p in (0, 1):
+                g.set_launch(waves_per_query=wv, lookahead=0, persistent=p, two_phase=t)
+                res.append(g.search_var(Q, ks, nps, 0.1))
+    g.set_launch(waves_per_query=0, lookahead=-1, persistent=-1, two_phase=-1)
     _assert_identical([r[:3] for r in res])
     for r in res[1:]:
         for key in ("candidates", "refined", "stage_slices"):
