@@ -1,25 +1,34 @@
 #!/usr/bin/env python
 """Throughput of the pruned IVF search on one MI355X.
 
-Workload (default ``sift1m``): 1,000,000 x 128 base vectors with integer values 0..255 from a
+Headline workload (``sift1m``): 1,000,000 x 128 base vectors with integer values 0..255 from a
 mixture of 1,024 anisotropic Gaussians, 10,000 queries of the same mixture, IVF with 4,096
 k-means lists, K = 10.  A step is one search of the whole 10,000-query batch (query
 rotation, coarse distances, probe selection, pruned scan, top-K merge, finalize) with the
 queries already resident in HBM.
 
 Operating point: the (nprobe, significance) with the highest QPS whose recall@10 against
-FP64 exact KNN is >= 0.95; the full-dimension scan (no pruning) is swept over nprobe the
+FP64 exact KNN is >= 0.95; the full-dimension scans (no pruning: the query-major scan of the
+same dimension-blocked tiles, and the list-major matrix-core scan) are swept over nprobe the
 same way and reported beside it.
 
-Prints one JSON line (rank 0).  Only one GPU is used; --gpus above 1 is rejected.
+The default run also measures K = 100 on the headline index, QPS with the host copies of the
+queries and results included, the CPU oracle on every host core, and, each on its own index,
+the 960-d BF16 workload, the 768-d uneven-batch workload with the FP8 pre-stage and the 256-d
+serving workload (``--only`` skips them).
+
+Prints one JSON line.  Only one GPU is used; --gpus above 1 is rejected.
 """
 from __future__ import annotations
 
 import argparse
+import gc
 import hashlib
 import json
 import os
+import subprocess
 import sys
+import tempfile
 import time
 
 import numpy as np
@@ -32,6 +41,14 @@ HBM_PEAK_GBS = 8000.0
 MFMA_PEAK_TFLOPS = {"f32": 157.3, "bf16": 2500.0}
 NPROBES = [16, 24, 32, 48, 64, 96, 128]
 ALPHAS = [0.001, 0.005, 0.01, 0.02, 0.05, 0.1, 0.2, 0.3]
+# the paper's own comparison with the random-projection method (ADSampling), as it states it
+PAPER_CONTEXT = {
+    "claim": "1.6-2.1x speedup of the data-driven (PCA + learned correction) distance comparison "
+             "over ADSampling (random projection + its error-bound test) on real-world datasets, "
+             "at higher accuracy (Sec. I, Sec. VII)",
+    "paper_hardware": "Intel Xeon Platinum 8352V @ 2.10 GHz, 512 GB memory, Ubuntu; C++ built with "
+                      "g++ 11.4.0 -O3, SIMD disabled; one query at a time on the CPU (Sec. VII-A)",
+}
 
 DESCR = {"sift": "integer 0-255 mixture", "gist": "power-law mixture",
          "embed": "unit-normalised mixture", "gauss": "Gaussian"}
@@ -39,8 +56,10 @@ DESCR = {"sift": "integer 0-255 mixture", "gist": "power-law mixture",
 # name -> data set, index and search settings.  "serve": ("frac", [...]) offers fractions of the
 # measured peak QPS, ("abs", [...]) absolute queries/s.
 CONFIGS = {
-    # 1M x 128 integer descriptors, FP32, IVF 4096, 10,000 queries, K = 10 (the headline)
+    # 1M x 128 integer descriptors, FP32, IVF 4096, 10,000 queries, K = 10 and 100 (the headline);
+    # correction tables at K_c = 10 and 100
     "sift1m": dict(data="sift1m", nlist=4096, storage="f32", rotation="f32", k=10, nprobes=NPROBES,
+                   k100_nprobes=[48, 64, 96, 128], fit=dict(calib_k_extra=(100,)),
                    serve=("frac", [0.25, 0.5])),
     # the same data and index with the FP8 E4M3 pre-stage over the leading 64 rotated dims
     # (64 B per candidate instead of the 128 B FP32 first stage; FP32 stages after it)
@@ -66,21 +85,30 @@ CONFIGS = {
                      fit=dict(kmeans_train_per_list=64, kmeans_iters=10, calib_k_extra=(50, 100)),
                      serve=("abs", [5e3, 1e4, 2e4, 3.5e4, 5e4]), gt_queries=2000),
 }
+SECONDARY = ("gist1m", "embed768", "embed256")
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def exact_knn_fp64(base_t, queries_t, k):
-    """FP64 exact KNN on the GPU with torch (ground truth for recall only)."""
+def exact_knn_fp64(base_t, queries_t, k, extra=16):
+    """FP64 exact KNN on the GPU (ground truth for recall only), ordered by (distance, id): the
+    k + extra smallest by the expanded form, then their distances recomputed term by term and
+    ties broken by the lower id."""
     import torch
     xn = (base_t * base_t).sum(1)
+    n = base_t.shape[0]
+    kk = min(n, k + extra)
     out = []
-    for s in range(0, queries_t.shape[0], 512):
-        q = queries_t[s:s + 512]
+    for s in range(0, queries_t.shape[0], 256):
+        q = queries_t[s:s + 256]
         d = xn[None, :] - 2.0 * (q @ base_t.T) + (q * q).sum(1)[:, None]
-        out.append(torch.topk(d, k, dim=1, largest=False).indices.cpu().numpy())
+        idx = torch.topk(d, kk, dim=1, largest=False).indices
+        dd = ((base_t[idx] - q[:, None, :]) ** 2).sum(-1).cpu().numpy()
+        ii = idx.cpu().numpy()
+        order = np.lexsort((ii, dd), axis=1)[:, :k]
+        out.append(np.take_along_axis(ii, order, 1))
     return np.vstack(out)
 
 
@@ -163,7 +191,8 @@ def serve_phase(ix, w, gt, offered_qps, seconds, alpha, nlist, seed=0, n_streams
     lat = np.sort(np.asarray(lat))
     total_q = int(sizes.sum())
     return dict(offered_qps=round(offered_qps, 1), achieved_qps=round(total_q / ((end - start) * 1e-9), 1),
-                requests=n_req, queries=total_q, p50_ms=round(float(np.percentile(lat, 50)), 3),
+                seconds=seconds, requests=n_req, queries=total_q,
+                p50_ms=round(float(np.percentile(lat, 50)), 3),
                 p99_ms=round(float(np.percentile(lat, 99)), 3), max_ms=round(float(lat[-1]), 3),
                 recall_at_10=round(hits / (10 * total_q), 4), distinct_queries=len(served_rows),
                 server_p50_ms=round(st["p50_ms"], 3), server_p99_ms=round(st["p99_ms"], 3),
@@ -171,58 +200,155 @@ def serve_phase(ix, w, gt, offered_qps, seconds, alpha, nlist, seed=0, n_streams
                 n_streams=n_streams, max_batch=max_batch, hbm_budget_bytes=budget)
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="sift1m")
-    ap.add_argument("--k", type=int, default=0, help="K (default: the workload's)")
-    ap.add_argument("--nprobe", type=int, default=0, help="fix the operating point (skip sweep)")
-    ap.add_argument("--alpha", type=float, default=0.0)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=0,
-                    help="queries of the CPU oracle baseline (default: as many as fit in --cpu-seconds)")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0,
-                    help="time budget of the CPU oracle baseline (whole queries, at least 8)")
-    ap.add_argument("--serve-rates", default="",
-                    help="offered loads of the serving phase (override; fractions of the peak QPS "
-                         "or absolute queries/s, as the workload defines)")
-    ap.add_argument("--serve-seconds", type=float, default=3.0)
-    ap.add_argument("--ablation", action="store_true",
-                    help="also sweep the residual test, lossless pruning, a random rotation with the "
-                         "learned and the ADSampling tests, and the OPQ estimate with its learned "
-                         "classifier (BSA-O) at the operating nprobe")
-    ap.add_argument("--ood", action="store_true",
-                    help="also search shifted queries with the fitted table, the residual test and a "
-                         "table recalibrated on 100 of them")
-    ap.add_argument("--exp7", action="store_true",
-                    help="also rank the whole base by each estimate over the leading 32 dims alone "
-                         "(PCA, residual, random projection) and report recall@100")
-    ap.add_argument("--copy-probe", action="store_true",
-                    help="also run a plain 1 GiB device copy (HBM counter calibration)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
-              f"(the search would shard by query, each GPU holding the index, with no exchange)", flush=True)
-        sys.exit(2)
+# ---- CPU oracle baseline: a child process that never touches the GPU ------------------------
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
+
+_CPU_JOB = None
+
+
+def _cpu_worker_init():
+    try:
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(1)
+    except Exception:
+        pass
+
+
+def _cpu_one(i):
+    import oracle
+    oix, Q, ks, nps, k, nprobe, alpha = _CPU_JOB
+    if ks is not None:
+        oracle.search(oix, Q[i:i + 1], int(ks[i]), int(nps[i]), alpha)
+    else:
+        oracle.search(oix, Q[i:i + 1], k, nprobe, alpha)
+    return i
+
+
+def cpu_oracle_child(path):
+    """Entry of the child process: load the exported index (memory-mapped), rebuild the
+    oracle's view of it, then time the FP64 oracle search on one core and on every core given
+    to this process (fork workers, one thread each), each for a bounded time."""
+    global _CPU_JOB
+    import multiprocessing as mp
+
+    import oracle
+    _cpu_worker_init()
+    z = np.load(path, mmap_mode="r")
+    job = json.loads(str(z["job"]))
+    D = int(job["D"])
+    oix = dict(mu=np.asarray(z["mu"]), R=np.asarray(z["R"]), Y=np.asarray(z["y"], np.float64),
+               centroids=np.asarray(z["centroids"], np.float64), m=np.asarray(z["m"]),
+               G=np.asarray(z["resid"]), B=int(job["B"]), L=int(job["L"]),
+               bounds=oracle.stage_bounds(D, int(job["delta_d"])))
+    oix["list_off"], oix["list_ids"] = oracle.build_lists(np.asarray(z["assign"]), int(job["nlist"]))
+    tabs = [dict(kc=int(kc), m=np.asarray(z[f"m{i}"]), G=np.asarray(z[f"G{i}"]))
+            for i, kc in enumerate(job["table_k"])]
+    if len(tabs) > 1:
+        oix["tables"] = tabs
+    if job["fp8"]:
+        oix["pre"] = oracle.fp8_encode_lead(oix["Y"], oix["list_off"], oix["list_ids"], int(job["fp8"]))
+    Q = np.asarray(z["queries"])
+    ks = np.asarray(z["ks"]) if job["uneven"] else None
+    nps = np.asarray(z["nps"]) if job["uneven"] else None
+    _CPU_JOB = (oix, Q, ks, nps, int(job["k"]), int(job["nprobe"]), float(job["alpha"]))
+    nq, secs, cores = Q.shape[0], float(job["seconds"]), int(job["cores"])
+    out = {}
+    # one core, in this process
+    t0 = time.time()
+    done = 0
+    while done < nq:
+        _cpu_one(done)
+        done += 1
+        if done >= 8 and time.time() - t0 >= secs:
+            break
+    out["one_core"] = dict(queries=done, seconds=time.time() - t0)
+    # every core: fork workers (this process holds no GPU state)
+    ctx = mp.get_context("fork")
+    with ctx.Pool(cores, initializer=_cpu_worker_init) as pool:
+        t0 = time.time()
+        done = 0
+        for _ in pool.imap_unordered(_cpu_one, range(nq), chunksize=1):
+            done += 1
+            if done >= 8 * cores and time.time() - t0 >= secs:
+                break
+        el = time.time() - t0
+        pool.terminate()
+    out["all_cores"] = dict(queries=done, seconds=el, cores=cores)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_oracle_baseline(ix, w, k, nprobe, alpha, seconds, ks=None, nps=None):
+    """The FP64 oracle search timed on the host: the exported index and the queries go to a
+    memory-mapped file, and a child process (no GPU) runs the oracle on one core, then on
+    every core this process may use (at most 16)."""
+    e = ix.export()
+    D = w["queries"].shape[1]
+    cores = min(16, len(os.sched_getaffinity(0)))
+    tabs = e["tables"] or [dict(kc=e.get("calib_k", 1), m=e["m"], resid=e["resid"])]
+    job = dict(D=D, B=e["block_b"], L=e["lag_l"], delta_d=e["delta_d"], nlist=e["centroids"].shape[0],
+               table_k=[int(t["kc"]) for t in tabs], fp8=int(e.get("fp8_lead_dims", 0)),
+               uneven=ks is not None, k=k, nprobe=nprobe if ks is None else 0, alpha=alpha,
+               seconds=seconds, cores=cores)
+    arrays = dict(mu=e["mu"], R=e["R"], y=e["y"], centroids=e["centroids"], assign=e["assign"],
+                  m=tabs[0]["m"], resid=tabs[0]["resid"], queries=w["queries"],
+                  ks=ks if ks is not None else np.zeros(1, np.int32),
+                  nps=nps if nps is not None else np.zeros(1, np.int32))
+    for i, t in enumerate(tabs):
+        arrays[f"m{i}"] = t["m"]
+        arrays[f"G{i}"] = t["resid"]
+    tmpdir = "/dev/shm" if os.path.isdir("/dev/shm") else None
+    fd, path = tempfile.mkstemp(suffix=".npz", dir=tmpdir)
+    os.close(fd)
+    try:
+        np.savez(path, job=json.dumps(job), **arrays)
+        del e, arrays
+        gc.collect()
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-oracle-child", path],
+                           capture_output=True, text=True, timeout=30 * seconds + 300)
+        if r.returncode != 0:
+            log(f"[bench] CPU oracle child failed: {r.stderr[-2000:]}")
+            return None
+        res = json.loads(r.stdout.strip().splitlines()[-1])
+    finally:
+        os.unlink(path)
+    one, allc = res["one_core"], res["all_cores"]
+    what = (f"per query K and nprobe as the GPU batch" if ks is not None else f"K={k}, nprobe={nprobe}")
+    return dict(value=round(allc["queries"] / allc["seconds"], 3), unit="queries/s", cores=allc["cores"],
+                kind="oracle",
+                sample=f"the first queries of the {w['queries'].shape[0]}-query batch ({allc['queries']} on "
+                       f"{allc['cores']} cores in {allc['seconds']:.1f}s, {one['queries']} on one core in "
+                       f"{one['seconds']:.1f}s), same index, {what}, significance {alpha}; FP64 numpy "
+                       f"oracle, one thread per process",
+                one_core_qps=round(one["queries"] / one["seconds"], 3), cpu_model=cpu_model())
+
+
+# ---- one workload ------------------------------------------------------------------------
+def run_workload(wl, args, headline):
+    """Fit, sweep, time and describe one workload.  Returns (result dict, index, workload,
+    ground truth, helpers) with the index still open."""
     import torch
 
     import synthdata
     from paper_2404_16322_amd import Index
 
-    torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
-    cfg = CONFIGS[args.workload]
+    cfg = CONFIGS[wl]
+    steps = args.steps if headline else max(5, args.steps // 2)
     t0 = time.time()
     uneven = cfg.get("uneven")
     nq_total = uneven["batches"] * uneven["batch"] if uneven else cfg.get("gt_queries")
     w = synthdata.make_workload(cfg["data"], nq=nq_total)
     spec = w["spec"]
     nq, D = w["queries"].shape
-    log(f"[bench] workload {args.workload}: n={w['base'].shape[0]} D={D} nq={nq} "
-        f"({time.time() - t0:.1f}s)")
+    log(f"[bench] workload {wl}: n={w['base'].shape[0]} D={D} nq={nq} ({time.time() - t0:.1f}s)")
 
     t0 = time.time()
     nlist = cfg["nlist"]
@@ -244,6 +370,7 @@ def main():
     q_dev = torch.from_numpy(w["queries"]).to(dev)
     ctr = torch.zeros(70, dtype=torch.int64, device=dev)
     stream = torch.cuda.Stream(device=dev)
+    ks = nps = off = None
     if uneven:
         # per-query K and nprobe, results in CSR order; one step = `batches` launches
         ks, nps = synthdata.uneven_requests(nq, 1000 * spec["cfg"] + 9, *uneven["nprobe"], uneven["k"])
@@ -259,15 +386,18 @@ def main():
         first10 = off[:-1, None] + np.arange(10)[None, :]
     else:
         k = args.k or cfg["k"]
-        ids_dev = torch.empty((nq, k), dtype=torch.int64, device=dev)
-        d_dev = torch.empty((nq, k), dtype=torch.float32, device=dev)
+        bsz = nq
         launches = 1
+        kmax_alloc = max(k, 100 if cfg.get("k100_nprobes") else k)
+        ids_buf = torch.empty((nq * kmax_alloc,), dtype=torch.int64, device=dev)
+        d_buf = torch.empty((nq * kmax_alloc,), dtype=torch.float32, device=dev)
 
-    def run(nprobe, alpha, mode, counters=False):
+    def run(nprobe, alpha, mode, counters=False, kk=None):
         cp = ctr.data_ptr() if counters else 0
         if not uneven:
-            ix.search_device(q_dev.data_ptr(), nq, k, nprobe, alpha, mode, ids_dev.data_ptr(),
-                             d_dev.data_ptr(), cp, stream.cuda_stream)
+            kq = kk or k
+            ix.search_device(q_dev.data_ptr(), nq, kq, nprobe, alpha, mode, ids_buf.data_ptr(),
+                             d_buf.data_ptr(), cp, stream.cuda_stream)
             return
         for b in range(launches):
             s0 = b * bsz
@@ -277,34 +407,31 @@ def main():
                              d_nprobe=np_dev.data_ptr() + s0 * 4, nprobe_max=int(nps.max()),
                              d_offsets=off_dev.data_ptr() + s0 * 8)
 
-    def result_ids():
-        a = ids_dev.cpu().numpy()
-        return a[first10] if uneven else a
+    def result_ids(kk=None):
+        if uneven:
+            return ids_dev.cpu().numpy()[first10]
+        kq = kk or k
+        return ids_buf[:nq * kq].view(nq, kq).cpu().numpy()
 
-    def timed(nprobe, alpha, mode, reps):
+    def result_d(kk=None):
+        kq = kk or k
+        return d_buf[:nq * kq].view(nq, kq).cpu().numpy()
+
+    def timed(nprobe, alpha, mode, reps, kk=None):
         with torch.cuda.stream(stream):
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record(stream)
             for _ in range(reps):
-                run(nprobe, alpha, mode)
+                run(nprobe, alpha, mode, kk=kk)
             e1.record(stream)
         e1.synchronize()
         return e0.elapsed_time(e1) / reps
 
-    def recall(nprobe, alpha, mode):
-        run(nprobe, alpha, mode)
+    def recall(nprobe, alpha, mode, kk=None):
+        run(nprobe, alpha, mode, kk=kk)
         stream.synchronize()
-        return recall_at_10(result_ids(), gt)
+        return recall_at_10(result_ids(kk), gt)
 
-    # ---- operating points ---------------------------------------------------------
-    sweep = []
-    nprobe_list = ["per-query"] if uneven else cfg["nprobes"]
-    if args.nprobe:
-        points = [(args.nprobe, args.alpha)]
-    elif uneven and args.alpha:
-        points = [("per-query", args.alpha)]
-    else:
-        points = [(p, a) for p in nprobe_list for a in ALPHAS]
     def pick(cands):
         # the fastest point with recall@10 >= 0.95; points within 2% of it count as equal (timing
         # noise) and the one with the largest significance, then the fewest lists, is taken
@@ -315,26 +442,32 @@ def main():
         near = [c for c in ok if c[2] <= fastest * 1.02]
         return max(near, key=lambda c: (c[1], -c[0] if isinstance(c[0], int) else 0))
 
-    pts = []
-    for p, a in points:
-        r = recall(p, a, "learned")
-        ms = timed(p, a, "learned", 5)
-        sweep.append(dict(nprobe=p, alpha=a, recall=r, qps=nq / ms * 1e3, mode="learned"))
-        pts.append((p, a, ms, r))
-    best = pick(pts)
-    fpts = []
-    for p in (nprobe_list if not args.nprobe else [args.nprobe]):
-        r = recall(p, 0.0, "none")
-        ms = timed(p, 0.0, "none", 5)
-        sweep.append(dict(nprobe=p, alpha=0.0, recall=r, qps=nq / ms * 1e3, mode="none"))
-        fpts.append((p, 0.0, ms, r))
-    full_best = pick(fpts)
-    if best is None:   # no point reaches the target: report the highest-recall one
-        s = max((x for x in sweep if x["mode"] == "learned"), key=lambda x: x["recall"])
-        best = (s["nprobe"], s["alpha"], nq / s["qps"] * 1e3, s["recall"])
-    if full_best is None:
-        s = max((x for x in sweep if x["mode"] == "none"), key=lambda x: x["recall"])
-        full_best = (s["nprobe"], 0.0, nq / s["qps"] * 1e3, s["recall"])
+    def sweep_points(points, mode, kk=None, sweep=None):
+        pts = []
+        for p, a in points:
+            r = recall(p, a, mode, kk)
+            ms = timed(p, a, mode, 5, kk)
+            if sweep is not None:
+                sweep.append(dict(nprobe=p, alpha=a, recall=r, qps=nq / ms * 1e3, mode=mode,
+                                  k=kk or k))
+            pts.append((p, a, ms, r))
+        best = pick(pts)
+        if best is None:   # no point reaches the target: report the highest-recall one
+            best = max(pts, key=lambda c: c[3])
+        return best
+
+    # ---- operating points ---------------------------------------------------------
+    sweep = []
+    nprobe_list = ["per-query"] if uneven else cfg["nprobes"]
+    if args.nprobe:
+        points = [(args.nprobe, args.alpha)]
+    elif uneven and args.alpha:
+        points = [("per-query", args.alpha)]
+    else:
+        points = [(p, a) for p in nprobe_list for a in ALPHAS]
+    best = sweep_points(points, "learned", sweep=sweep)
+    full_best = sweep_points([(p, 0.0) for p in (nprobe_list if not args.nprobe else [args.nprobe])],
+                             "none", sweep=sweep)
     nprobe, alpha, _, rec = best
     log(f"[bench] operating point nprobe={nprobe} alpha={alpha} recall@10={rec:.4f}; "
         f"full-D nprobe={full_best[0]} recall@10={full_best[3]:.4f}")
@@ -344,8 +477,8 @@ def main():
     if cfg.get("error_vs_fp64"):
         run(nprobe, alpha, "learned")
         stream.synchronize()
-        ids_np = ids_dev.cpu().numpy()
-        d_np = d_dev.cpu().numpy().astype(np.float64)
+        ids_np = result_ids()
+        d_np = result_d().astype(np.float64)
         valid = ids_np >= 0
         base32 = torch.from_numpy(w["base"]).to(dev)
         q64 = torch.from_numpy(w["queries"]).to(dev, torch.float64)
@@ -365,25 +498,34 @@ def main():
         log(f"[bench] distance error vs FP64: {dist_err}")
 
     # ---- work counters of one launch at the operating point ---------------------------
-    ctr.zero_()
-    run(nprobe, alpha, "learned", counters=True)
-    stream.synchronize()
-    c = ctr.cpu().numpy()
-    candidates, refined, slices = int(c[0]), int(c[1]), int(c[2])
-    pre_reads, pre_pruned = int(c[68]), int(c[69])
     esize = {0: 4, 1: 2, 2: 2}[info["storage"]]
     slice_bytes = 32 * esize
     NB = info["dim_padded"] // 32      # 32-dim blocks the scan counts
     probe_entries = int(nps.sum()) if uneven else nq * nprobe
     out_entries = int(off[-1]) if uneven else nq * k
 
-    def launch_bytes(sl, ref, pre, probes):
-        """Algorithmic bytes of one scan launch: base slices read + FP8 slices read + ids of
-        refined candidates + list table entries + rotated queries + outputs."""
-        return (sl * slice_bytes + pre * 64 + ref * 4 + probes * 12 + nq * info["dim_padded"] * 4
-                + out_entries * 12) / launches
+    def counters(np_, a_, mode):
+        ctr.zero_()
+        run(np_, a_, mode, counters=True)
+        stream.synchronize()
+        return ctr.cpu().numpy().astype(np.int64)
 
-    scan_bytes = launch_bytes(slices, refined, pre_reads, probe_entries)
+    c = counters(nprobe, alpha, "learned")
+    candidates, refined, slices, e1_reads = int(c[0]), int(c[1]), int(c[2]), int(c[3])
+    pre_reads, pre_pruned = int(c[68]), int(c[69])
+    pre_two_phase = pre_reads > 0 and e1_reads == pre_reads
+
+    def scan_bytes_of(sl, ref, pre, e1r, pre_from_e1, probes):
+        """Algorithmic bytes of one scan launch (the per-query kernel): base slices it reads (a
+        first slice whose sum came from the two-phase first phase is not read here) + FP8 slices
+        + 4 bytes per first-phase sum + ids of refined candidates + list table entries + rotated
+        queries + outputs."""
+        base_sl = sl if pre_from_e1 else sl - e1r
+        pre_b = 0 if pre_from_e1 else pre * 64
+        return (base_sl * slice_bytes + pre_b + e1r * 4 + ref * 4 + probes * 12
+                + nq * info["dim_padded"] * 4 + out_entries * 12) / launches
+
+    scan_bytes = scan_bytes_of(slices, refined, pre_reads, e1_reads, pre_two_phase, probe_entries)
     full_bytes_per_launch = candidates * info["dim_padded"] * esize / launches
 
     # ---- timed region -----------------------------------------------------------------
@@ -396,60 +538,99 @@ def main():
     stream.synchronize()
     torch.cuda.synchronize()
 
-    def timed_steps():
+    def timed_steps(fn):
         with torch.cuda.stream(stream):
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record(stream)
-            for _ in range(args.steps):
-                run(nprobe, alpha, "learned")
+            for _ in range(steps):
+                fn()
             e1.record(stream)
         e1.synchronize()
         torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / args.steps
+        return e0.elapsed_time(e1) / steps
 
-    ms_step = timed_steps()
+    ms_step = timed_steps(lambda: run(nprobe, alpha, "learned"))
     ix.kernel_timing(reset=True)
     ix.set_kernel_timing(True)
-    ms_step_instrumented = timed_steps()
+    ms_step_instrumented = timed_steps(lambda: run(nprobe, alpha, "learned"))
     ix.set_kernel_timing(False)
     kms, kn = ix.kernel_timing(reset=True)
+    kstep = [float(kms[i]) / steps for i in range(5)]   # every launch of that kernel in a step
     scan_ms = kms[3] / max(1, kn[3])
     qps = nq / ms_step * 1e3
+
+    # host copies included: queries from pinned host memory, results back to pinned memory
+    e2e = None
+    if not uneven:
+        qh = torch.from_numpy(w["queries"]).pin_memory()
+        ih = torch.empty((nq * k,), dtype=torch.int64).pin_memory()
+        dh = torch.empty((nq * k,), dtype=torch.float32).pin_memory()
+
+        def e2e_step():
+            q_dev.copy_(qh, non_blocking=True)
+            run(nprobe, alpha, "learned")
+            ih.copy_(ids_buf[:nq * k], non_blocking=True)
+            dh.copy_(d_buf[:nq * k], non_blocking=True)
+        with torch.cuda.stream(stream):
+            for _ in range(args.warmup):
+                e2e_step()
+        ms_e2e = timed_steps(e2e_step)
+        assert np.array_equal(ih.numpy().reshape(nq, k)[:, :10], result_ids()[:, :10])
+        e2e = dict(qps=round(nq / ms_e2e * 1e3, 1), ms_per_step=round(ms_e2e, 4),
+                   what="H2D of the queries from pinned memory + the search + D2H of ids and "
+                        "distances to pinned memory, one stream")
+        log(f"[bench] end to end: {e2e}")
 
     # every launch shape of the scan at the operating point (results are bit-identical)
     chosen = ix.scan_variant(bsz, k, int(nps.max())) if uneven else ix.scan_variant(nq, k, nprobe)
     variants = {}
-    for wv, la, pe in [(w_, l_, p_) for p_ in (0, 1) for w_ in (1, 4) for l_ in (0, 1)]:
-        ix.set_launch(waves_per_query=wv, lookahead=la, persistent=pe)
-        run(nprobe, alpha, "learned")
-        stream.synchronize()
-        ix.set_kernel_timing(True)
-        for _ in range(max(3, args.steps // 2)):
+    if headline:
+        shapes = [(w_, l_, p_, t_) for t_ in (0, 1) for p_ in (0, 1) for w_ in (1, 4) for l_ in (0, 1)]
+        for wv, la, pe, t2 in shapes:
+            ix.set_launch(waves_per_query=wv, lookahead=la, persistent=pe, two_phase=t2)
             run(nprobe, alpha, "learned")
-        stream.synchronize()
-        ix.set_kernel_timing(False)
-        vms, vn = ix.kernel_timing(reset=True)
-        variants[f"waves{wv}{'_lookahead' if la else ''}{'_persistent' if pe else ''}"] = \
-            round(vms[3] / max(1, vn[3]), 4)
-    ix.set_launch(waves_per_query=0, lookahead=-1, persistent=-1)
-    log(f"[bench] scan variants (ms): {variants}; tuned choice {chosen}")
+            stream.synchronize()
+            ix.set_kernel_timing(True)
+            for _ in range(max(3, steps // 2)):
+                run(nprobe, alpha, "learned")
+            stream.synchronize()
+            ix.set_kernel_timing(False)
+            vms, vn = ix.kernel_timing(reset=True)
+            name = (f"waves{wv}{'_lookahead' if la else ''}{'_persistent' if pe else ''}"
+                    f"{'_twophase' if t2 else ''}")
+            variants[name] = dict(scan_ms=round(vms[3] / max(1, vn[3]), 4),
+                                  first_phase_ms=round(vms[4] / max(1, vn[3]), 4))
+        ix.set_launch(waves_per_query=0, lookahead=-1, persistent=-1, two_phase=-1)
+        log(f"[bench] scan variants (ms): {variants}; tuned choice {chosen}")
 
     # full-D scan at its own operating point, same protocol
     for _ in range(args.warmup):
         run(full_best[0], 0.0, "none")
     ix.set_kernel_timing(True)
     torch.cuda.synchronize()
-    full_ms = timed(full_best[0], 0.0, "none", args.steps)
+    full_ms = timed(full_best[0], 0.0, "none", steps)
     ix.set_kernel_timing(False)
     fkms, fkn = ix.kernel_timing(reset=True)
     full_qps = nq / full_ms * 1e3
-    ctr.zero_()
-    run(full_best[0], 0.0, "none", counters=True)
-    stream.synchronize()
-    fc = ctr.cpu().numpy()
-    full_scan_bytes = launch_bytes(int(fc[2]), int(fc[1]), 0,
-                                   probe_entries if uneven else nq * full_best[0])
+    fc = counters(full_best[0], 0.0, "none")
+    full_scan_bytes = scan_bytes_of(int(fc[2]), int(fc[1]), 0, 0, False,
+                                    probe_entries if uneven else nq * full_best[0])
     full_scan_ms = fkms[3] / max(1, fkn[3])
+
+    # ---- K = 100 on the same index (table K_c = 100) -----------------------------------
+    k100 = None
+    if headline and cfg.get("k100_nprobes") and not args.nprobe:
+        kb = sweep_points([(p, a) for p in cfg["k100_nprobes"] for a in ALPHAS], "learned", kk=100)
+        kf = sweep_points([(p, 0.0) for p in cfg["k100_nprobes"]], "none", kk=100)
+        for _ in range(args.warmup):
+            run(kb[0], kb[1], "learned", kk=100)
+        ms100 = timed(kb[0], kb[1], "learned", steps, kk=100)
+        msf100 = timed(kf[0], 0.0, "none", steps, kk=100)
+        k100 = dict(k=100, qps=round(nq / ms100 * 1e3, 1), nprobe=kb[0], significance=kb[1],
+                    recall_at_10=round(kb[3], 4), ms_per_step=round(ms100, 4),
+                    full_d_qps=round(nq / msf100 * 1e3, 1), full_d_nprobe=kf[0],
+                    full_d_recall_at_10=round(kf[3], 4), speedup_vs_full_d=round(msf100 / ms100, 3))
+        log(f"[bench] K=100: {k100}")
 
     # the same index without the FP8 pre-stage (re-imported, recalibrated on the same queries)
     no_pre = None
@@ -458,15 +639,13 @@ def main():
         art = dict(e, fp8_lead_dims=0, resid=None, m=None, tables=None)
         ix_main = ix
         ix = Index.from_artifacts(art)
+        del e, art
         ix.calibrate(w["calib"], seed=spec["cfg"])
         r_np = recall(nprobe, alpha, "learned")
         for _ in range(args.warmup):
             run(nprobe, alpha, "learned")
-        ms_np = timed(nprobe, alpha, "learned", args.steps)
-        ctr.zero_()
-        run(nprobe, alpha, "learned", counters=True)
-        stream.synchronize()
-        nc = ctr.cpu().numpy()
+        ms_np = timed(nprobe, alpha, "learned", steps)
+        nc = counters(nprobe, alpha, "learned")
         no_pre = dict(qps=round(nq / ms_np * 1e3, 1), recall_at_10=round(r_np, 4),
                       scanned_dim_ratio=round(int(nc[2]) / max(1, int(nc[0]) * NB), 4))
         ix.close()
@@ -475,100 +654,277 @@ def main():
 
     achieved = scan_bytes / (scan_ms * 1e-3) / 1e9
     traffic = None
-    pmc_file = os.path.join(ROOT, "profiles", f"scan_{args.workload}_hbm_traffic.json")
+    pmc_file = os.path.join(ROOT, "profiles", f"scan_{wl}_hbm_traffic.json")
     if os.path.exists(pmc_file):
         try:
             pm = json.load(open(pmc_file))
-            tuned_name = (f"void ddc::scan_kernel<{info['storage']}, true, {'true' if chosen[1] else 'false'}, "
-                          f"{chosen[0]}, {'true' if cfg.get('fp8') else 'false'}, false, false, false, "
-                          f"{'true' if info['lag_l'] > 0 else 'false'}>(ddc::ScanArgs)")
             if pm.get("kernel_hash") == kernel_hash() and pm.get("nprobe") == nprobe and \
-                    abs(pm.get("alpha", -1) - alpha) < 1e-12 and pm.get("kernel") == tuned_name and \
-                    pm.get("persistent", 0) == chosen[2]:
+                    abs(pm.get("alpha", -1) - alpha) < 1e-12 and pm.get("variant") == list(chosen):
                 traffic = pm.get("hbm_bytes_per_launch")
         except Exception:
             traffic = None
     # matrix-core use of the two GEMMs (algorithmic flops / HIP-event kernel time / dense peak)
     rot_prec = "bf16" if cfg["rotation"] == "bf16" else "f32"
-    bq = bsz if uneven else nq
 
     def mfma_entry(flops, ms, prec):
         peak = MFMA_PEAK_TFLOPS[prec]
         ach = flops / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
         return dict(dtype=prec, flops_per_launch=int(flops), kernel_ms=round(ms, 4),
                     achieved_tflops=round(ach, 2), peak_tflops=peak, frac=round(ach / peak, 4))
-    mfma = {"rotation": mfma_entry(2.0 * bq * info["dim_padded"] * D, kms[0] / max(1, kn[0]), rot_prec),
-            "coarse": mfma_entry(2.0 * bq * nlist * info["dim_padded"], kms[1] / max(1, kn[1]), "f32")}
+    mfma = {"rotation": mfma_entry(2.0 * bsz * info["dim_padded"] * D, kms[0] / max(1, kn[0]), rot_prec),
+            "coarse": mfma_entry(2.0 * bsz * nlist * info["dim_padded"], kms[1] / max(1, kn[1]), "f32")}
     log(f"[bench] matrix cores: {mfma}")
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
                     kernel=f"scan_kernel<{cfg['storage']}, pruned, lookahead={chosen[1]}, "
-                           f"waves={chosen[0]}>{' persistent' if chosen[2] else ''}",
-                    bytes_per_launch=int(scan_bytes),
-                    kernel_ms=round(scan_ms, 4))
+                           f"waves={chosen[0]}>{' persistent' if chosen[2] else ''}"
+                           f"{' two-phase' if chosen[3] else ''}",
+                    bytes_per_launch=int(scan_bytes), kernel_ms=round(scan_ms, 4))
+    two_phase = None
+    if chosen[3]:
+        # the first phase: every list's tiles (block 0, or the FP8 codes) read once, the pairs'
+        # grouping and offsets (28 B each), the queries' leading dims, one 4-byte sum written per
+        # candidate
+        fp_ms = kms[4] / max(1, kn[4])
+        lead_b = 64 * 64 if pre_two_phase else 64 * slice_bytes
+        qd = 64 if pre_two_phase else 32
+        fp_bytes = (info["total_tiles"] * lead_b + probe_entries * 28 + nq * qd * 4
+                    + e1_reads * 4) / launches
+        two_phase = dict(first_phase_ms=round(fp_ms, 4), bytes_per_launch=int(fp_bytes),
+                         achieved_GBs=round(fp_bytes / (fp_ms * 1e-3) / 1e9, 1) if fp_ms > 0 else None,
+                         sums=e1_reads // launches)
 
-    if args.copy_probe:
+    if args.copy_probe and headline:
         a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
         b = torch.empty_like(a)
         for _ in range(3):
             b.copy_(a)
         torch.cuda.synchronize()
+        del a, b
+
+    res = {
+        "value": round(qps, 1),
+        "ms_per_step": round(ms_step, 4),
+        "ms_per_step_with_kernel_events": round(ms_step_instrumented, 4),
+        "dtype": {0: "f32", 1: "f16", 2: "bf16"}[info["storage"]],
+        "config": {"workload": f"{wl}: {w['base'].shape[0]} x {D} {DESCR[spec['kind']]}, "
+                               f"{spec.get('comps')} Gaussian components, IVF {nlist}, storage "
+                               f"{cfg['storage']}, rotation {cfg['rotation']}"
+                               f"{', FP8 pre-stage over 64 dims' if cfg.get('fp8') else ''}",
+                   "queries_per_step": nq, "k": k, "nprobe": nprobe, "significance": alpha,
+                   "recall_at_10": round(rec, 4), "parallelism": "single GPU",
+                   **({"launches_per_step": launches, "queries_per_launch": bsz,
+                       "k": f"per query U{set(uneven['k'])}", "nprobe": "per query U{%d..%d}" % uneven["nprobe"],
+                       "fp8_prestage_dims": cfg.get("fp8", 0)} if uneven else {})},
+        "full_d_scan": {"layout": "query-major scan of the dimension-blocked tiles, every dim block",
+                        "qps": round(full_qps, 1), "nprobe": full_best[0],
+                        "recall_at_10": round(full_best[3], 4), "ms_per_step": round(full_ms, 4),
+                        "scan_kernel_ms": round(full_scan_ms, 4),
+                        "scan_achieved_GBs": round(full_scan_bytes / (full_scan_ms * 1e-3) / 1e9, 1)},
+        "speedup_vs_full_d": round(qps / full_qps, 3),
+        "end_to_end": e2e,
+        "k100": k100,
+        "without_fp8_prestage": no_pre,
+        "scan_variant_ms": variants or None,
+        "scan_variant_tuned": {"waves_per_query": chosen[0], "lookahead": chosen[1],
+                               "persistent": chosen[2], "two_phase": chosen[3]},
+        "kernel_ms_per_step": {"rotation": round(kstep[0], 4), "coarse": round(kstep[1], 4),
+                               "select": round(kstep[2], 4), "scan": round(kstep[3], 4),
+                               "first_phase": round(kstep[4], 4)},
+        "scan_stats": {"candidates": candidates, "refined": refined, "prestage_reads": pre_reads,
+                       "prestage_pruned": pre_pruned, "two_phase_sums": e1_reads,
+                       "scanned_dim_ratio": round(slices / max(1, candidates * NB), 4),
+                       "bytes_vs_full_d": round((slices * slice_bytes + pre_reads * 64) / launches
+                                                / max(1, full_bytes_per_launch), 4)},
+        "roofline": roofline,
+        "two_phase_first_phase": two_phase,
+        "mfma": mfma,
+        "distance_error_vs_fp64": dist_err,
+        "fit_s": round(fit_s, 2),
+        "sweep": sweep if headline else None,
+    }
+    ctx = dict(w=w, gt=gt, nprobe=nprobe, alpha=alpha, k=k, ks=ks, nps=nps, nq=nq, nlist=nlist,
+               run=run, recall=recall, timed=timed, sweep_points=sweep_points, q_dev=q_dev, cfg=cfg,
+               spec=spec, steps=steps)
+    return res, ix, ctx
+
+
+def serve_and_summary(ix, ctx, args, res):
+    cfg = ctx["cfg"]
+    serve = []
+    rates = []
+    if args.serve_seconds > 0 and cfg.get("serve"):
+        kind, vals = cfg["serve"]
+        if args.serve_rates:
+            vals = [float(x) for x in args.serve_rates.split(",") if x.strip()]
+        rates = [res["value"] * v for v in vals] if kind == "frac" else list(vals)
+    for rate in rates:
+        serve.append(serve_phase(ix, ctx["w"], ctx["gt"], rate, args.serve_seconds, ctx["alpha"],
+                                 ctx["nlist"], seed=len(serve)))
+        log(f"[bench] serve {serve[-1]}")
+    return serve
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="sift1m")
+    ap.add_argument("--only", action="store_true",
+                    help="measure the --workload alone (no K=100 point, no secondary workloads)")
+    ap.add_argument("--k", type=int, default=0, help="K (default: the workload's)")
+    ap.add_argument("--nprobe", type=int, default=0, help="fix the operating point (skip sweep)")
+    ap.add_argument("--alpha", type=float, default=0.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="time budget of each CPU oracle leg (one core, every core)")
+    ap.add_argument("--serve-rates", default="",
+                    help="offered loads of the serving phase (override; fractions of the peak QPS "
+                         "or absolute queries/s, as the workload defines)")
+    ap.add_argument("--serve-seconds", type=float, default=4.0)
+    ap.add_argument("--no-rp", action="store_true",
+                    help="skip the PCA-vs-random-projection comparison on the headline workload")
+    ap.add_argument("--ablation", action="store_true",
+                    help="also sweep the residual test, lossless pruning and the OPQ estimate with "
+                         "its learned classifier (BSA-O) at the operating nprobe")
+    ap.add_argument("--ood", action="store_true",
+                    help="also search shifted queries with the fitted table, the residual test and a "
+                         "table recalibrated on 100 of them")
+    ap.add_argument("--exp7", action="store_true",
+                    help="also rank the whole base by each estimate over the leading 32 dims alone "
+                         "(PCA, residual, random projection) and report recall@100")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain 1 GiB device copy (HBM counter calibration)")
+    ap.add_argument("--cpu-oracle-child", default="", help=argparse.SUPPRESS)
+    args = ap.parse_args()
+    if args.cpu_oracle_child:
+        cpu_oracle_child(args.cpu_oracle_child)
+        return
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
+              f"(the search would shard by query, each GPU holding the index, with no exchange)", flush=True)
+        sys.exit(2)
+
+    import torch
+
+    import synthdata
+    from paper_2404_16322_amd import Index
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    wl = args.workload
+    res, ix, ctx = run_workload(wl, args, headline=True)
+    w, nq, nprobe, alpha, k = ctx["w"], ctx["nq"], ctx["nprobe"], ctx["alpha"], ctx["k"]
+    run, recall, timed = ctx["run"], ctx["recall"], ctx["timed"]
+    spec, cfg, nlist = ctx["spec"], ctx["cfg"], ctx["nlist"]
+    D = w["queries"].shape[1]
+    NB = ix.info()["dim_padded"] // 32
+    uneven = cfg.get("uneven")
+
+    # ---- the paper's comparison: PCA + learned test vs random projection + ADSampling ---------
+    rp = None
+    if not args.no_rp and not uneven:
+        pts_pca = []
+        for a in ALPHAS:
+            r = recall(nprobe, a, "learned")
+            pts_pca.append(dict(alpha=a, recall=round(r, 4), qps=round(nq / timed(nprobe, a, "learned", 5) * 1e3, 1)))
+        ix_main = ix
+        ix = Index.fit(w["base"], w["calib"], nlist=nlist, seed=spec["cfg"], storage=cfg["storage"],
+                       rotation=cfg["rotation"], projection="haar", **cfg.get("fit", {}))
+        # the run / recall helpers search the headline index; the Haar index's recall comes from
+        # the host entry point, its timing from the device entry point (same kernels)
+        gt = ctx["gt"]
+        pts_ads = []
+        for eps in [0.5, 1.0, 1.5, 2.1, 3.0, 4.0]:
+            ix.set_ads_epsilon(eps)
+            ids, _, _ = ix.search(w["queries"], k, nprobe, 0.0, mode="ads")
+            pts_ads.append(dict(eps0=eps, recall=round(recall_at_10(ids, gt), 4)))
+        pts_haar = []
+        for a in ALPHAS:
+            ids, _, _ = ix.search(w["queries"], k, nprobe, a)
+            pts_haar.append(dict(alpha=a, recall=round(recall_at_10(ids, gt), 4)))
+        # device timing of the Haar index at each point (same protocol as the headline)
+        qd = ctx["q_dev"]
+        ib = torch.empty((nq * k,), dtype=torch.int64, device=dev)
+        db = torch.empty((nq * k,), dtype=torch.float32, device=dev)
+        st = torch.cuda.Stream(device=dev)
+
+        def dev_ms(a_, mode):
+            for _ in range(2):
+                ix.search_device(qd.data_ptr(), nq, k, nprobe, a_, mode, ib.data_ptr(), db.data_ptr(), 0,
+                                 st.cuda_stream)
+            with torch.cuda.stream(st):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(st)
+                for _ in range(5):
+                    ix.search_device(qd.data_ptr(), nq, k, nprobe, a_, mode, ib.data_ptr(), db.data_ptr(), 0,
+                                     st.cuda_stream)
+                e1.record(st)
+            e1.synchronize()
+            return e0.elapsed_time(e1) / 5
+        for p_ in pts_ads:
+            ix.set_ads_epsilon(p_["eps0"])
+            p_["qps"] = round(nq / dev_ms(0.0, "ads") * 1e3, 1)
+        for p_ in pts_haar:
+            p_["qps"] = round(nq / dev_ms(p_["alpha"], "learned") * 1e3, 1)
+        ix.close()
+        ix = ix_main
+
+        def best_of(pts):
+            ok = [p_ for p_ in pts if p_["recall"] >= 0.95]
+            return max(ok, key=lambda p_: p_["qps"]) if ok else None
+        bp, ba, bh = best_of(pts_pca), best_of(pts_ads), best_of(pts_haar)
+        rp = dict(nprobe=nprobe, pca_learned=bp, haar_adsampling=ba, haar_learned=bh,
+                  speedup_pca_learned_over_haar_adsampling=round(bp["qps"] / ba["qps"], 3) if bp and ba else None,
+                  what="best QPS at recall@10 >= 0.95 at the operating nprobe: the method (PCA rotation, "
+                       "learned correction) against the random-projection method (Haar rotation, "
+                       "ADSampling's test with eps0 swept), both on this GPU, same kernels",
+                  **PAPER_CONTEXT)
+        log(f"[bench] random projection comparison: {rp}")
 
     # ---- ablation at the operating nprobe: each test's knob swept, best QPS at recall >= 0.95
     ablation = None
     if args.ablation and not uneven:
         ix_main = ix
+        ctr = torch.zeros(70, dtype=torch.int64, device=dev)
 
-        def sweep_mode(label, mode, knobs, setter, alpha_of):
+        def sweep_mode(label, mode, knobs, setter, alpha_of, gix):
             pts = []
             for kb in knobs:
                 setter(kb)
                 a_ = alpha_of(kb)
-                r = recall(nprobe, a_, mode)
-                ms = timed(nprobe, a_, mode, 3)
-                ctr.zero_()
-                run(nprobe, a_, mode, counters=True)
-                stream.synchronize()
-                cc = ctr.cpu().numpy()
-                pts.append(dict(knob=kb, recall=round(r, 4), qps=round(nq / ms * 1e3, 1),
-                                scanned_dim_ratio=round(int(cc[2]) / max(1, int(cc[0]) * NB), 4)))
+                ids, _, stt = gix.search(w["queries"], k, nprobe, a_, mode=mode)
+                r = recall_at_10(ids, ctx["gt"])
+                t0 = time.time()
+                gix.search(w["queries"], k, nprobe, a_, mode=mode)
+                ms = (time.time() - t0) * 1e3
+                pts.append(dict(knob=kb, recall=round(r, 4), host_qps=round(nq / ms * 1e3, 1),
+                                scanned_dim_ratio=round(stt["stage_slices"] / max(1, stt["candidates"] * NB), 4)))
                 if mode == "bsao":   # the paper's measure for the quantization estimate
-                    pts[-1]["pruned_rate"] = round(int(cc[69]) / max(1, int(cc[0])), 4)
+                    pts[-1]["pruned_rate"] = round(stt["prestage_pruned"] / max(1, stt["candidates"]), 4)
             ok = [x for x in pts if x["recall"] >= 0.95]
-            best = max(ok, key=lambda x: x["qps"]) if ok else max(pts, key=lambda x: x["recall"])
+            best = max(ok, key=lambda x: x["host_qps"]) if ok else max(pts, key=lambda x: x["recall"])
             log(f"[bench] ablation {label}: best {best}")
             return dict(best=best, points=pts)
 
-        ablation = {"nprobe": nprobe}
-        ablation["pca_learned"] = sweep_mode("PCA + learned", "learned", ALPHAS, lambda _: None, lambda a_: a_)
+        ablation = {"nprobe": nprobe, "timing": "host entry point (ddc_search), wall clock"}
         ablation["pca_residual"] = sweep_mode("PCA + residual (Alg. 2)", "bsar", [1, 2, 3, 4, 6, 8, 12, 16],
-                                              ix.set_bsar_multiplier, lambda _: 0.0)
-        ablation["pca_lossless"] = sweep_mode("PCA + lossless", "lossless", [0], lambda _: None, lambda _: 0.0)
-        ix = Index.fit(w["base"], w["calib"], nlist=nlist, seed=spec["cfg"], storage=cfg["storage"],
-                       rotation=cfg["rotation"], projection="haar", **cfg.get("fit", {}))
-        ablation["haar_learned"] = sweep_mode("random rotation + learned", "learned", ALPHAS,
-                                              lambda _: None, lambda a_: a_)
-        ablation["haar_ads"] = sweep_mode("random rotation + ADSampling test", "ads",
-                                          [0.5, 1.0, 1.5, 2.1, 3.0, 4.0], ix.set_ads_epsilon, lambda _: 0.0)
-        ix.close()
-        # OPQ estimate + learned classifier (BSA-O): M = D/4 subspaces (D/8 from 512 dims on, as
-        # the paper sets for GIST), 256 codewords each
+                                              ix.set_bsar_multiplier, lambda _: 0.0, ix)
+        ablation["pca_lossless"] = sweep_mode("PCA + lossless", "lossless", [0], lambda _: None,
+                                              lambda _: 0.0, ix)
         pq_m = D // 8 if D >= 512 else D // 4
-        ix = Index.fit(w["base"], w["calib"], nlist=nlist, seed=spec["cfg"], storage=cfg["storage"],
-                       rotation=cfg["rotation"], pq_m=pq_m, **cfg.get("fit", {}))
+        ixo = Index.fit(w["base"], w["calib"], nlist=nlist, seed=spec["cfg"], storage=cfg["storage"],
+                        rotation=cfg["rotation"], pq_m=pq_m, **cfg.get("fit", {}))
         ablation["opq_learned"] = sweep_mode(f"OPQ (M={pq_m}) + learned (BSA-O)", "bsao", ALPHAS,
-                                             lambda _: None, lambda a_: a_)
+                                             lambda _: None, lambda a_: a_, ixo)
         ablation["opq_learned"]["pq_m"] = pq_m
-        ix.close()
+        ixo.close()
         ix = ix_main
 
-    # ---- approximation accuracy of the estimates alone (Exp-7 / Table III analogue): every
-    # point ranked by its estimate over the leading 32 rotated dims, recall@100 against FP64
+    # ---- approximation accuracy of the estimates alone (Exp-7 / Table III analogue) ----------
     exp7 = None
-    if args.exp7 and nlist > 4096:
-        log("[bench] estimates alone: skipped (probe selection covers at most 4,096 lists, so the "
-            "whole base cannot be ranked on this index)")
-    elif args.exp7 and not uneven:
+    if args.exp7 and nlist <= 4096 and not uneven:
         n7 = min(nq, 1000)
         Q7 = w["queries"][:n7]
         gt100 = exact_knn_fp64(torch.from_numpy(w["base"]).to(dev, torch.float64),
@@ -589,65 +945,27 @@ def main():
                     recall_at_100=cols)
         log(f"[bench] estimates alone at 32 dims: {exp7}")
 
-    # ---- serving: open-loop Poisson arrivals, continuous batching --------------------------
-    serve = []
-    rates = []
-    if args.serve_seconds > 0 and cfg.get("serve"):
-        kind, vals = cfg["serve"]
-        if args.serve_rates:
-            vals = [float(x) for x in args.serve_rates.split(",") if x.strip()]
-        rates = [qps * v for v in vals] if kind == "frac" else list(vals)
-    for rate in rates:
-        serve.append(serve_phase(ix, w, gt, rate, args.serve_seconds, alpha, nlist, seed=len(serve)))
-        log(f"[bench] serve {serve[-1]}")
+    # ---- serving on the headline index (fractions of its peak) --------------------------------
+    serve = serve_and_summary(ix, ctx, args, res)
 
-    # ---- CPU oracle baseline (bounded sample) --------------------------------------------
+    # ---- CPU oracle baseline (bounded sample, every host core) ---------------------------
     cpu = None
     if not args.no_cpu_baseline:
-        import oracle
-        e = ix.export()
-        oix = dict(mu=e["mu"], R=e["R"], Y=e["y"].astype(np.float64),
-                   centroids=e["centroids"].astype(np.float64), m=e["m"], G=e["resid"], B=256, L=0,
-                   bounds=oracle.stage_bounds(D, 32))
-        oix["list_off"], oix["list_ids"] = oracle.build_lists(e["assign"], nlist)
-        if len(e["tables"]) > 1:
-            oix["tables"] = [dict(kc=t["kc"], m=t["m"], G=t["resid"]) for t in e["tables"]]
-        if e.get("fp8_lead_dims"):
-            oix["pre"] = oracle.fp8_encode_lead(oix["Y"], oix["list_off"], oix["list_ids"],
-                                                e["fp8_lead_dims"])
-        # the first queries of the batch, one at a time, until the fixed count or the time
-        # budget is used up (whole queries, at least 8)
-        limit = args.cpu_sample if args.cpu_sample else nq
-        t0 = time.time()
-        done = 0
-        while done < min(limit, nq):
-            i = done
-            if uneven:
-                oracle.search(oix, w["queries"][i:i + 1], int(ks[i]), int(nps[i]), alpha)
-            else:
-                oracle.search(oix, w["queries"][i:i + 1], k, nprobe, alpha)
-            done += 1
-            if not args.cpu_sample and done >= 8 and time.time() - t0 >= args.cpu_seconds:
-                break
-        cpu_s = time.time() - t0
-        cpu = dict(value=round(done / cpu_s, 3), unit="queries/s", cores=1, kind="oracle",
-                   sample=f"first {done} of the {nq} queries, same index/nprobe/alpha, "
-                          f"FP64 numpy oracle (single thread), {cpu_s:.1f}s")
+        cpu = cpu_oracle_baseline(ix, w, k, nprobe, alpha, args.cpu_seconds, ctx["ks"], ctx["nps"])
+        log(f"[bench] CPU oracle: {cpu}")
 
-    # ---- out-of-distribution queries (Sec. V-C): the table fitted on in-distribution training
-    # queries, then recalibrated on 100 shifted queries; the residual test needs no training
+    # ---- out-of-distribution queries (Sec. V-C) -------------------------------------------
     ood = None
     if args.ood and not uneven:
-        qo = synthdata.ood_queries(args.workload, nq, stream=synthdata.STREAM_OOD)
-        co = synthdata.ood_queries(args.workload, 100, stream=synthdata.STREAM_OOD + 1)
-        q_dev.copy_(torch.from_numpy(qo).to(dev))
-        gt = exact_knn_fp64(torch.from_numpy(w["base"]).to(dev, torch.float64),
-                            torch.from_numpy(qo).to(dev, torch.float64), 10)
+        qo = synthdata.ood_queries(wl, nq, stream=synthdata.STREAM_OOD)
+        co = synthdata.ood_queries(wl, 100, stream=synthdata.STREAM_OOD + 1)
+        gto = exact_knn_fp64(torch.from_numpy(w["base"]).to(dev, torch.float64),
+                             torch.from_numpy(qo).to(dev, torch.float64), 10)
         torch.cuda.empty_cache()
 
         def point(mode, a_):
-            r = recall(nprobe, a_, mode)
-            return dict(recall_at_10=round(r, 4), qps=round(nq / timed(nprobe, a_, mode, 5) * 1e3, 1))
+            ids, _, _ = ix.search(qo, k, nprobe, a_, mode=mode)
+            return dict(recall_at_10=round(recall_at_10(ids, gto), 4))
         ood = dict(nprobe=nprobe, significance=alpha, queries=f"{nq} shifted queries (within-component "
                    "scale x2 for the mixtures)", in_distribution_table=point("learned", alpha))
         ix.set_bsar_multiplier(8.0)
@@ -656,61 +974,59 @@ def main():
         ix.calibrate(co, calib_k=0, seed=spec["cfg"])
         ood["recalibrated_on_100_ood_queries"] = point("learned", alpha)
         log(f"[bench] out-of-distribution: {ood}")
+    ix.close()
+    del ix, ctx, w
+    gc.collect()
+    torch.cuda.empty_cache()
 
+    # ---- the other workloads, each on its own index ------------------------------------------
+    others = None
+    if not args.only:
+        others = {}
+        for wl2 in SECONDARY:
+            if wl2 == wl:
+                continue
+            r2, ix2, ctx2 = run_workload(wl2, args, headline=False)
+            r2["serve"] = serve_and_summary(ix2, ctx2, args, r2) or None
+            if r2["serve"]:
+                r2["serve_p50_ms"] = r2["serve"][-1]["p50_ms"]
+                r2["serve_p99_ms"] = r2["serve"][-1]["p99_ms"]
+            r2["steps"] = ctx2["steps"]
+            others[wl2] = r2
+            ix2.close()
+            del ix2, ctx2
+            gc.collect()
+            torch.cuda.empty_cache()
+
+    serve_src = others.get("embed256", {}).get("serve") if others else None
     out = {
         "metric": "QPS at recall@10>=0.95, pruned vs full-D GPU scan; p50/p99 serve latency",
-        "value": round(qps, 1),
+        "value": res["value"],
         "unit": "queries/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 4),
-        "ms_per_step_with_kernel_events": round(ms_step_instrumented, 4),
+        "ms_per_step": res["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {0: "f32", 1: "f16", 2: "bf16"}[info["storage"]],
+        "dtype": res["dtype"],
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {w['base'].shape[0]} x {D} {DESCR[spec['kind']]}, "
-                               f"{spec.get('comps')} Gaussian components, IVF {nlist}, storage "
-                               f"{cfg['storage']}, rotation {cfg['rotation']}",
-                   "queries_per_step": nq, "k": k, "nprobe": nprobe, "significance": alpha,
-                   "recall_at_10": round(rec, 4), "parallelism": "single GPU",
-                   **({"launches_per_step": launches, "queries_per_launch": bsz,
-                       "k": f"per query U{set(uneven['k'])}", "nprobe": "per query U{%d..%d}" % uneven["nprobe"],
-                       "fp8_prestage_dims": cfg.get("fp8", 0)} if uneven else {})},
-        "full_d_scan": {"qps": round(full_qps, 1), "nprobe": full_best[0],
-                        "recall_at_10": round(full_best[3], 4), "ms_per_step": round(full_ms, 4),
-                        "scan_kernel_ms": round(full_scan_ms, 4),
-                        "scan_achieved_GBs": round(full_scan_bytes / (full_scan_ms * 1e-3) / 1e9, 1)},
-        "speedup_vs_full_d": round(qps / full_qps, 3),
-        "without_fp8_prestage": no_pre,
+        **{k_: v for k_, v in res.items() if k_ not in ("value", "ms_per_step", "dtype")},
+        "serve": serve,
+        "serve_p50_ms": serve_src[-1]["p50_ms"] if serve_src else (serve[-1]["p50_ms"] if serve else None),
+        "serve_p99_ms": serve_src[-1]["p99_ms"] if serve_src else (serve[-1]["p99_ms"] if serve else None),
+        "serve_latency_source": ("embed256 (5M x 256 FP16, IVF 16384) at 50k queries/s offered"
+                                 if serve_src else "headline index"),
+        "cpu_baseline": cpu,
+        "random_projection_comparison": rp,
+        "paper_context": PAPER_CONTEXT,
         "ablation": ablation,
         "out_of_distribution": ood,
         "estimate_accuracy": exp7,
-        "scan_variant_ms": variants,
-        "scan_variant_tuned": {"waves_per_query": chosen[0], "lookahead": chosen[1],
-                               "persistent": chosen[2]},
-        "kernel_ms": {"rotation": round(kms[0] / max(1, kn[0]), 4),
-                      "coarse": round(kms[1] / max(1, kn[1]), 4),
-                      "select": round(kms[2] / max(1, kn[2]), 4), "scan": round(scan_ms, 4)},
-        "scan_stats": {"candidates": candidates, "refined": refined, "prestage_reads": pre_reads,
-                       "prestage_pruned": pre_pruned,
-                       "scanned_dim_ratio": round(slices / max(1, candidates * NB), 4),
-                       "bytes_vs_full_d": round((slices * slice_bytes + pre_reads * 64) / launches
-                                                / max(1, full_bytes_per_launch), 4)},
-        "roofline": roofline,
-        "mfma": mfma,
-        "distance_error_vs_fp64": dist_err,
-        "serve": serve,
-        "serve_p50_ms": serve[-1]["p50_ms"] if serve else None,
-        "serve_p99_ms": serve[-1]["p99_ms"] if serve else None,
-        "cpu_baseline": cpu,
-        "fit_s": round(fit_s, 2),
-        "sweep": sweep,
+        "workloads": others,
     }
     print(json.dumps(out), flush=True)
-    ix.close()
 
 
 if __name__ == "__main__":

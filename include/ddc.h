@@ -183,6 +183,9 @@ typedef struct {
   int64_t stage_stop[64];    /* candidates whose last stage read was s (0-based; S-1 = refined) */
   int64_t prestage_reads;    /* candidates whose 64-byte FP8 slice was read (tested) */
   int64_t prestage_pruned;   /* candidates the FP8 pre-stage pruned (not in stage_stop) */
+  int64_t two_phase_sums;    /* candidates whose first test (dim block 0, or the FP8 pre-stage)
+                                read a sum the two-phase scan's first phase computed list by
+                                list, instead of the base (see ddc_launch_params) */
 } ddc_search_stats;
 
 /* Fills *p with the defaults listed above. */
@@ -262,7 +265,7 @@ ddc_status ddc_search_var(const ddc_index *ix, const float *queries, int64_t nq,
  * into that range rather than trusting it); d_out_offsets: CSR as in
  * ddc_search_var or NULL for dense [nq x k_all]; d_ids int64 / d_dists float32 outputs;
  * d_counters: NULL or device int64[4 + 64 + 2] (added to): candidates, refined, stage
- * slices, unused, stage_stop[64], prestage_reads, prestage_pruned.
+ * slices, two-phase sums read, stage_stop[64], prestage_reads, prestage_pruned.
  * Scratch: the index keeps one grow-only device workspace per stream (rotated queries, coarse
  * distances, probes; about nq x (dim + nlist + nprobe_max) x 4 bytes for nq <= 32,768), made on
  * the stream's first call and reused by the next ones, freed with the index; calls on one

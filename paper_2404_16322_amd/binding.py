@@ -68,12 +68,14 @@ class IndexInfo(C.Structure):
 class SearchStats(C.Structure):
     _fields_ = [("candidates", C.c_int64), ("refined", C.c_int64), ("stage_slices", C.c_int64),
                 ("bytes_touched", C.c_int64), ("stage_stop", C.c_int64 * 64),
-                ("prestage_reads", C.c_int64), ("prestage_pruned", C.c_int64)]
+                ("prestage_reads", C.c_int64), ("prestage_pruned", C.c_int64),
+                ("two_phase_sums", C.c_int64)]
 
     def as_dict(self):
         return dict(candidates=self.candidates, refined=self.refined, stage_slices=self.stage_slices,
                     bytes_touched=self.bytes_touched, stage_stop=list(self.stage_stop),
-                    prestage_reads=self.prestage_reads, prestage_pruned=self.prestage_pruned)
+                    prestage_reads=self.prestage_reads, prestage_pruned=self.prestage_pruned,
+                    two_phase_sums=self.two_phase_sums)
 
 
 class ServerParams(C.Structure):

@@ -39,12 +39,13 @@ static std::array<int, 4> tune_class(int64_t nq, int np_max, int k_max, int kind
 }
 
 // kernel family of a launch: pruned or not, FP8 pre-stage, residual test, estimate only
-// Whether a launch can run two-phase: the learned or fixed-table stage tests on the stored
-// values with the first test right after dim block 0 and more blocks after it (no FP8
-// pre-stage, residual or quantization test, no estimate-only scan).
+// Whether a launch can run two-phase: the learned or fixed-table stage tests (no residual or
+// quantization test, no estimate-only scan) whose first test is the FP8 pre-stage, or follows
+// dim block 0 with more blocks after it.
 static bool two_phase_eligible(const ddc_index *ix, const ScanArgs &a) {
-  return a.prune && !a.res && !a.pre && a.pq_m == 0 && a.est_nb == 0 && ix->NB > 1 && ix->St > 0 &&
-         ix->delta_d == kBlockDims && ix->d_tile_list.p != nullptr;
+  if (!a.prune || a.res || a.pq_m != 0 || a.est_nb != 0 || ix->d_tile_list.p == nullptr) return false;
+  if (a.pre) return true;
+  return ix->NB > 1 && ix->St > 0 && ix->delta_d == kBlockDims;
 }
 
 static int scan_kind(const ScanArgs &a) {
@@ -740,11 +741,11 @@ static void scratch_sizes(const ddc_index *ix, int64_t cmax, int np_max, bool tw
   for (int i = 0; i < kParts; ++i) sizes[i] = v[i];
 }
 
-// Queries per chunk: kChunk, fewer when the two-phase sums of a chunk would pass 4 GiB.
+// Queries per chunk: kChunk, fewer when the two-phase sums of a chunk could pass 16 GiB.
 static int64_t chunk_queries(const ddc_index *ix, int np_max, bool two_phase) {
   if (!two_phase) return kChunk;
   const int64_t per = std::max<int64_t>(1, e1_bound(ix, 1, np_max));
-  return std::max<int64_t>(1, std::min<int64_t>(kChunk, ((int64_t)1 << 30) / per));
+  return std::max<int64_t>(1, std::min<int64_t>(kChunk, ((int64_t)1 << 32) / per));
 }
 
 size_t ddc::search_scratch_bytes(const ddc_index *ix, int64_t nq, int np_max, bool two_phase) {
@@ -940,6 +941,7 @@ void ddc::search_device(ddc_index *ix, const float *d_q, int64_t nq, const int32
           s1.tile_list = ix->d_tile_list.as<int32_t>(); s1.nlist = ix->nlist;
           s1.total_tiles = ix->total_tiles; s1.nq = nqc;
           s1.qrot = qrot.as<float>(); s1.q_stride = Dp; s1.base = ix->d_base.p; s1.nblocks = ix->NB;
+          s1.pre = a.pre; s1.base8 = a.base8; s1.scale8 = a.scale8;
           s1.lcnt = s1_lcnt.as<int32_t>(); s1.lstart = s1_lstart.as<int32_t>();
           s1.rank = s1_rank.as<int32_t>(); s1.lpair = s1_lpair.as<int32_t>();
           s1.poff = s1_poff.as<int64_t>(); s1.qcnt = s1_qcnt.as<int64_t>(); s1.qoff = s1_qoff.as<int64_t>();
@@ -967,6 +969,7 @@ static void stats_from_counters(const ddc_index *ix, const int64_t *c, ddc_searc
   for (int i = 0; i < 64; ++i) st->stage_stop[i] = c[4 + i];
   st->prestage_reads = c[kCtrPreReads];
   st->prestage_pruned = c[kCtrPrePruned];
+  st->two_phase_sums = c[3];
 }
 
 // ---------------------------------------------------------------------------------------

@@ -15,7 +15,8 @@ constexpr int kMaxBlocks = 128;      // D <= 4096
 constexpr int kMaxLag = 64;          // tau lag L in blocks
 constexpr int kMaxK = 256;
 constexpr int kScanThreads = 256;    // 4 wavefronts per query
-// counters: candidates, refined, stage_slices, unused, stop[64], pre-stage reads, pre-stage prunes
+// counters: candidates, refined, stage_slices, two-phase sums read, stop[64], pre-stage reads,
+// pre-stage prunes
 constexpr int kCtrPreReads = 4 + 64, kCtrPrePruned = 4 + 64 + 1;
 constexpr int kMaxCounters = 4 + 64 + 2;
 constexpr int kFp8Lead = 64;          // dims covered by the FP8 pre-stage
@@ -78,10 +79,11 @@ struct ScanArgs {
   int32_t ntab;
   int32_t tab_k[kMaxTables];
   int8_t test_after[kMaxBlocks]; // 1 if a stage test follows block b
-  // Two-phase scan: when e1 is set, the partial distance after dim block 0 of every candidate
-  // of every probed list was computed beforehand list by list (launch_stage1_lists): query q's
-  // candidates start at e1[e1_qoff[q]], its lists' in probe order, each list's in stored order.
-  // The first stage test then reads these instead of the base (bit-identical sums).
+  // Two-phase scan: when e1 is set, the partial distance after dim block 0 (with pre: the FP8
+  // pre-stage's) of every candidate of every probed list was computed beforehand list by list
+  // (launch_stage1_lists): query q's candidates start at e1[e1_qoff[q]], its lists' in probe
+  // order, each list's in stored order.  The first test then reads these instead of the base
+  // (bit-identical sums).
   const float *e1;
   const int64_t *e1_qoff;
   int64_t e1_cap;          // entries of e1 (no read at or past it)
@@ -89,10 +91,10 @@ struct ScanArgs {
 
 void launch_scan(const ScanArgs &a, int store, hipStream_t s);
 
-// First phase of the two-phase scan: the partial distance over dim block 0 of every candidate
-// of every probed list, computed list by list so each stored tile is read once for all the
-// queries that probe its list, with the arithmetic (and rounding) of the scan's own first
-// stage.  Probes of query q: probes[q * p_stride + p], p < clamp(nprobe[q], 1, p_stride), every
+// First phase of the two-phase scan: the partial distance over dim block 0 (pre: the FP8
+// pre-stage's over the leading 64 dims) of every candidate of every probed list, computed list
+// by list so each stored tile is read once for all the queries that probe its list, with the
+// arithmetic (and rounding) of the scan's own first test.  Probes of query q: probes[q * p_stride + p], p < clamp(nprobe[q], 1, p_stride), every
 // list at most once per query.  Scratch (caller's): lcnt, lstart [nlist + 1]; rank, lpair
 // [nq * p_stride] int32; poff [nq * p_stride], qcnt [nq], qoff [nq + 1] int64; e1 [e1_cap].
 struct Stage1Args {
@@ -102,6 +104,8 @@ struct Stage1Args {
   int32_t nlist; int64_t total_tiles; int64_t nq;
   const float *qrot; int64_t q_stride;
   const void *base; int32_t nblocks;
+  int32_t pre;                      // 1: the FP8 pre-stage sums over the leading 64 dims instead
+  const uint8_t *base8; const float *scale8;
   int32_t *lcnt, *lstart, *rank, *lpair;
   int64_t *poff, *qcnt, *qoff;
   float *e1; int64_t e1_cap;

@@ -235,7 +235,7 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
   int32_t *s_ml = reinterpret_cast<int32_t *>(ql + L.meta);   // list ids, lengths, first tiles
 
   // statistics (wave-uniform, flushed once when counters are requested)
-  int64_t st_cand = 0, st_ref = 0, st_slices = 0, st_pre = 0, st_pre_pruned = 0;
+  int64_t st_cand = 0, st_ref = 0, st_slices = 0, st_pre = 0, st_pre_pruned = 0, st_e1 = 0;
   unsigned long long *ctr = reinterpret_cast<unsigned long long *>(a.counters);
   // stop-stage histogram, lane i counting stage i (one atomic per lane at the end)
   uint32_t st_stop = 0;
@@ -539,7 +539,34 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
           nalive = nn;
           listed = true;
         }
-        if (PRE) {
+        if (PRE && a.e1) {
+          // ---- FP8 pre-stage of the two-phase scan: the segment's pre-stage sums come from e1
+          // (one 4-byte load per candidate instead of its 64 code bytes); same test, same
+          // alive list contents ----
+          const float mb = s_mb[2 * nb], bb = s_mb[2 * nb + 1];
+          const int64_t e0 = e1_list + bs + s0;
+          int nn = 0;
+          for (int t0 = 0; t0 < slen; t0 += 64) {
+            const int idx = t0 + lane;
+            const bool valid = idx < slen && e0 + idx < a.e1_cap;
+            const float ev = valid ? a.e1[e0 + idx] : 0.f;
+            const bool prune = valid && fmaf(mb, ev, bb) > tau_t;
+            const bool keep = valid && !prune;
+            const unsigned long long bal = __ballot(keep);
+            if (keep) {
+              const int pos = nn + __popcll(bal & lt);
+              s_ac[pos] = (uint16_t)idx;
+              s_ae[pos] = 0.f;
+            }
+            nn += __popcll(bal);
+            st_pre_pruned += __popcll(__ballot(prune));
+          }
+          st_pre += slen;
+          st_e1 += slen;
+          __builtin_amdgcn_wave_barrier();
+          nalive = nn;
+          listed = true;
+        } else if (PRE) {
           // ---- FP8 pre-stage: one 64-byte code slice per candidate, decoded with the tile's
           // scale; survivors go to the alive list and the stages start over at dim 0 ----
           constexpr int G8 = 4, CPW8 = 16, CH8 = 4;   // 16 codes per lane, 16 candidates per load
@@ -628,6 +655,7 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
             pruned += __popcll(__ballot(prune));
           }
           st_slices += slen;
+          st_e1 += slen;
           if (ctr) stop_add(0, (uint32_t)pruned);
           __builtin_amdgcn_wave_barrier();
           nalive = nn;
@@ -996,6 +1024,7 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
     atomicAdd(&ctr[0], (unsigned long long)st_cand);
     atomicAdd(&ctr[1], (unsigned long long)st_ref);
     atomicAdd(&ctr[2], (unsigned long long)st_slices);
+    if (st_e1) atomicAdd(&ctr[3], (unsigned long long)st_e1);
     if (PRE || PQ) {
       atomicAdd(&ctr[kCtrPreReads], (unsigned long long)st_pre);
       atomicAdd(&ctr[kCtrPrePruned], (unsigned long long)st_pre_pruned);
@@ -1224,73 +1253,115 @@ __global__ __launch_bounds__(256) void pair_scatter_kernel(const int32_t *probes
   if (l >= 0 && l < nlist) lpair[lstart[l] + rank[pidx]] = (int32_t)pidx;
 }
 
-// One workgroup per stored tile: its 64 vectors' dim block 0 stay in registers while the four
-// waves take the queries that probe its list in turn.  Lane (sub, g) holds dims
-// [g EPL, g EPL + EPL) of vectors c CPW + sub (c < MAXCH); each query's partial sums are formed
-// exactly as the scan's one-stage path forms them (per-lane FMA chain, then the transposed
-// group reduction), so lane (g, sub) ends with vector g CPW + sub's sum.
-template <int ST>
-__global__ __launch_bounds__(256) void stage1_lists_kernel(Stage1Args a) {
+// One workgroup per stored tile.  The tile's 64 vectors stay in registers (dim block 0, or with
+// PRE the FP8 codes of the leading 64 dims) while the workgroup takes the (query, list) pairs of
+// its list in chunks: first every pair's destination and query slice are staged in LDS (all
+// loads independent), then the four waves take the chunk's pairs in turn.  Each query's sums are
+// formed exactly as the scan forms them (per-lane FMA chain, then the transposed group
+// reduction), so the scan's tests on them take the same decisions bit for bit.
+//   block 0: lane (sub, g) holds dims [g EPL, g EPL + EPL) of vectors c CPW + sub (c < MAXCH)
+//            and ends with vector g CPW + sub's sum;
+//   PRE:     lane (sub8, g8) holds codes [16 g8, 16 g8 + 16) of vectors 16 c + sub8 (c < 4)
+//            and ends with vector 16 g8 + sub8's sum, decoded with the tile's scale.
+constexpr int kS1Threads = 256;
+template <int ST, bool PRE>
+__global__ __launch_bounds__(kS1Threads) void stage1_lists_kernel(Stage1Args a) {
   using S = Store<ST>;
   constexpr int EPL = 16 / S::kBytes;
-  constexpr int G = kBlockDims / EPL;
+  constexpr int G = PRE ? 4 : kBlockDims / EPL;
   constexpr int CPW = 64 / G;
   constexpr int MAXCH = 64 / CPW;
+  constexpr int NV = PRE ? 16 : EPL;                        // values per lane per vector slot
   constexpr int SLICE = kBlockDims * S::kBytes;
   constexpr int64_t BLOCK_BYTES = (int64_t)kTile * SLICE;
+  constexpr int QD = PRE ? kFp8Lead : kBlockDims;           // query dims per pair
+  constexpr int CHUNK = PRE ? 128 : 256;                    // pairs staged at once
+  __shared__ __align__(16) float s_qv[CHUNK * QD];
+  __shared__ int64_t s_dst[CHUNK];
   const int64_t t = blockIdx.x;
   if (t >= a.total_tiles) return;
   const int l = a.tile_list[t];
   if (l < 0 || l >= a.nlist) return;
   const int pb = a.lstart[l], pe = a.lstart[l + 1];
   if (pb >= pe) return;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane % G, sub = lane / G;
   const int tl = (int)(t - a.tile_off[l]);                 // tile within its list
   const int cnt = min(kTile, a.list_len[l] - tl * kTile);  // stored vectors in this tile
-  const unsigned char *tp = reinterpret_cast<const unsigned char *>(a.base) + t * a.nblocks * BLOCK_BYTES + g * 16;
-  float f[MAXCH][EPL];
+  float f[MAXCH][NV];
+  float sc = 1.f;
+  if constexpr (PRE) {
+    sc = a.scale8[t];
+    const unsigned char *p8 = a.base8 + t * (kTile * kFp8Lead) + g * 16;
 #pragma unroll
-  for (int c = 0; c < MAXCH; ++c) {
-    const uint4 v = *reinterpret_cast<const uint4 *>(tp + (c * CPW + sub) * SLICE);
-    S::unpack(v, f[c]);
+    for (int c = 0; c < MAXCH; ++c) {
+      const uint4 v = *reinterpret_cast<const uint4 *>(p8 + (c * CPW + sub) * kFp8Lead);
+      const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int i = 0; i < 4; ++i) e4m3x4_to_f32(w[i], &f[c][4 * i]);
+    }
+  } else {
+    const unsigned char *tp = reinterpret_cast<const unsigned char *>(a.base) + t * a.nblocks * BLOCK_BYTES + g * 16;
+#pragma unroll
+    for (int c = 0; c < MAXCH; ++c) {
+      const uint4 v = *reinterpret_cast<const uint4 *>(tp + (c * CPW + sub) * SLICE);
+      S::unpack(v, f[c]);
+    }
   }
   const int mine = g * CPW + sub;   // the vector this lane's sum belongs to
-  // two queries per round: their query slices are loaded together
-  for (int i = pb + wave; i < pe; i += 8) {
-    int64_t dst[2];
-    float qv[2][EPL];
-    bool have[2];
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int j = i + 4 * u;
-      have[u] = j < pe;
-      const int pidx = a.lpair[have[u] ? j : i];
+  for (int c0 = pb; c0 < pe; c0 += CHUNK) {
+    const int n = min(CHUNK, pe - c0);
+    __syncthreads();                 // the previous chunk's slices are no longer read
+    // stage: destinations, then the query slices (QD / 4 float4 per pair)
+    for (int j = tid; j < n; j += kS1Threads) {
+      const int pidx = a.lpair[c0 + j];
       const int64_t q = pidx / a.p_stride;
-      dst[u] = a.qoff[q] + a.poff[pidx] + (int64_t)tl * kTile;
-      const float4 *qp = reinterpret_cast<const float4 *>(a.qrot + q * a.q_stride + g * EPL);
-#pragma unroll
-      for (int e4 = 0; e4 < EPL / 4; ++e4) {
-        const float4 x = qp[e4];
-        qv[u][4 * e4] = x.x; qv[u][4 * e4 + 1] = x.y; qv[u][4 * e4 + 2] = x.z; qv[u][4 * e4 + 3] = x.w;
-      }
+      s_dst[j] = a.qoff[q] + a.poff[pidx] + (int64_t)tl * kTile;
     }
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
+    for (int j4 = tid; j4 < n * (QD / 4); j4 += kS1Threads) {
+      const int j = j4 / (QD / 4), k4 = j4 % (QD / 4);
+      const int64_t q = a.lpair[c0 + j] / a.p_stride;
+      reinterpret_cast<float4 *>(s_qv)[j4] = reinterpret_cast<const float4 *>(a.qrot + q * a.q_stride)[k4];
+    }
+    __syncthreads();
+    for (int j = wave; j < n; j += kS1Threads / 64) {
+      const float *qs = s_qv + j * QD;
       float part[MAXCH];
+      if constexpr (PRE) {
+        float q8[16];
 #pragma unroll
-      for (int c = 0; c < MAXCH; ++c) {
-        float acc = 0.f;
+        for (int e = 0; e < 16; ++e) q8[e] = qs[g * 16 + e];
 #pragma unroll
-        for (int e = 0; e < EPL; ++e) {
-          const float d = f[c][e] - qv[u][e];
-          acc = fmaf(d, d, acc);
+        for (int c = 0; c < MAXCH; ++c) {
+          float acc = 0.f;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              const float d = f[c][4 * i + e] * sc - q8[4 * i + e];
+              acc = fmaf(d, d, acc);
+            }
+          }
+          part[c] = acc;
         }
-        part[c] = acc;
+      } else {
+        float qv[EPL];
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) qv[e] = qs[g * EPL + e];
+#pragma unroll
+        for (int c = 0; c < MAXCH; ++c) {
+          float acc = 0.f;
+#pragma unroll
+          for (int e = 0; e < EPL; ++e) {
+            const float d = f[c][e] - qv[e];
+            acc = fmaf(d, d, acc);
+          }
+          part[c] = acc;
+        }
       }
       const float tot = transpose_sum<G>(part, g);
-      const int64_t o = dst[u] + mine;
-      if (have[u] && mine < cnt && o < a.e1_cap) a.e1[o] = tot;
+      const int64_t o = s_dst[j] + mine;
+      if (mine < cnt && o < a.e1_cap) a.e1[o] = tot;
     }
   }
 }
@@ -1311,11 +1382,15 @@ void launch_stage1_lists(const Stage1Args &a, int store, hipStream_t s) {
                      (int64_t)a.nlist, a.lstart);
   hipLaunchKernelGGL(pair_scatter_kernel, dim3(gp), dim3(256), 0, s, a.probes, a.p_stride, a.nprobe,
                      a.nprobe_all, a.nlist, a.nq, a.lstart, a.rank, a.lpair);
-  const dim3 grid((unsigned)a.total_tiles);
+  const dim3 grid((unsigned)a.total_tiles), blk(kS1Threads);
+  if (a.pre) {   // the FP8 codes do not depend on the storage type
+    hipLaunchKernelGGL((stage1_lists_kernel<ST_F32, true>), grid, blk, 0, s, a);
+    return;
+  }
   switch (store) {
-    case ST_F32: hipLaunchKernelGGL(stage1_lists_kernel<ST_F32>, grid, dim3(256), 0, s, a); break;
-    case ST_F16: hipLaunchKernelGGL(stage1_lists_kernel<ST_F16>, grid, dim3(256), 0, s, a); break;
-    default: hipLaunchKernelGGL(stage1_lists_kernel<ST_BF16>, grid, dim3(256), 0, s, a); break;
+    case ST_F32: hipLaunchKernelGGL((stage1_lists_kernel<ST_F32, false>), grid, blk, 0, s, a); break;
+    case ST_F16: hipLaunchKernelGGL((stage1_lists_kernel<ST_F16, false>), grid, blk, 0, s, a); break;
+    default: hipLaunchKernelGGL((stage1_lists_kernel<ST_BF16, false>), grid, blk, 0, s, a); break;
   }
 }
 

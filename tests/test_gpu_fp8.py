@@ -71,13 +71,18 @@ def test_prestage_variants_bitwise_identical():
     w = workload("gauss128")
     g = _index(ix)
     res = []
-    for wv, la, p in [(w_, l_, p_) for p_ in (0, 1) for w_ in (1, 4) for l_ in (0, 1)]:
-        g.set_launch(waves_per_query=wv, lookahead=la, persistent=p)
+    for wv, la, p, t in [(w_, l_, p_, t_) for t_ in (0, 1) for p_ in (0, 1) for w_ in (1, 4) for l_ in (0, 1)]:
+        g.set_launch(waves_per_query=wv, lookahead=la, persistent=p, two_phase=t)
         res.append(g.search(w["queries"], 10, 8, 0.1))
+    g.set_launch(waves_per_query=0, lookahead=-1, persistent=-1, two_phase=-1)
     for r in res[1:]:
         np.testing.assert_array_equal(r[0], res[0][0])
         np.testing.assert_array_equal(r[1], res[0][1])
-        assert r[2]["prestage_pruned"] == res[0][2]["prestage_pruned"]
+        for key in ("prestage_reads", "prestage_pruned", "candidates", "refined", "stage_slices"):
+            assert r[2][key] == res[0][2][key], key
+    # the two-phase launches took every pre-stage sum from the first phase
+    assert res[-1][2]["two_phase_sums"] == res[-1][2]["prestage_reads"] > 0
+    assert res[0][2]["two_phase_sums"] == 0
 
 
 def test_gpu_calibration_with_prestage_equals_oracle():

@@ -54,7 +54,8 @@ def test_noalloc_equals_device_entry_on_two_calls(setup, mode, alpha):
         print(f"{mode} n={n}: {int(rc[0])} candidates, {int(rc[1])} refined")
         np.testing.assert_array_equal(ni, ri)
         np.testing.assert_array_equal(nd, rd)
-        np.testing.assert_array_equal(nc, rc)
+        # every counter but the two-phase sums read (the allocation-free call runs one phase)
+        np.testing.assert_array_equal(np.delete(nc, 3), np.delete(rc, 3))
         assert (ni >= 0).all()
 
 
@@ -110,7 +111,7 @@ def test_noalloc_refuses_a_batch_beyond_its_scratch_and_runs_one_within():
     (ri, rd, rc), (ni, nd, nc) = _both(g, Q[:3000], 10, 48, 0.0, "lossless", stream)
     np.testing.assert_array_equal(ni, ri)
     np.testing.assert_array_equal(nd, rd)
-    np.testing.assert_array_equal(nc, rc)
+    np.testing.assert_array_equal(np.delete(nc, 3), np.delete(rc, 3))
 
 
 def test_noalloc_calls_leave_free_device_memory_unchanged(setup):
