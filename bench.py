@@ -368,7 +368,7 @@ def run_workload(wl, args, headline):
     log(f"[bench] FP64 ground truth {time.time() - t0:.1f}s")
 
     q_dev = torch.from_numpy(w["queries"]).to(dev)
-    ctr = torch.zeros(70, dtype=torch.int64, device=dev)
+    ctr = torch.zeros(71, dtype=torch.int64, device=dev)
     stream = torch.cuda.Stream(device=dev)
     ks = nps = off = None
     if uneven:
@@ -512,20 +512,20 @@ def run_workload(wl, args, headline):
 
     c = counters(nprobe, alpha, "learned")
     candidates, refined, slices, e1_reads = int(c[0]), int(c[1]), int(c[2]), int(c[3])
-    pre_reads, pre_pruned = int(c[68]), int(c[69])
-    pre_two_phase = pre_reads > 0 and e1_reads == pre_reads
+    pre_reads, pre_pruned, e1_slices = int(c[68]), int(c[69]), int(c[70])
+    pre_two_phase = pre_reads > 0 and e1_reads > 0 and e1_slices == 0
 
-    def scan_bytes_of(sl, ref, pre, e1r, pre_from_e1, probes):
-        """Algorithmic bytes of one scan launch (the per-query kernel): base slices it reads (a
-        first slice whose sum came from the two-phase first phase is not read here) + FP8 slices
-        + 4 bytes per first-phase sum + ids of refined candidates + list table entries + rotated
-        queries + outputs."""
-        base_sl = sl if pre_from_e1 else sl - e1r
-        pre_b = 0 if pre_from_e1 else pre * 64
-        return (base_sl * slice_bytes + pre_b + e1r * 4 + ref * 4 + probes * 12
+    def scan_bytes_of(cc):
+        """Algorithmic bytes of one scan launch (the per-query kernel): base slices it reads
+        (slices whose sums came from the first phase are not read here) + FP8 slices (not read
+        when the first phase summed them) + 4 bytes per first-phase sum + ids of refined
+        candidates + list table entries + rotated queries + outputs."""
+        sl, ref, e1r, e1s, pre = int(cc[2]), int(cc[1]), int(cc[3]), int(cc[70]), int(cc[68])
+        pre_b = 0 if (pre > 0 and e1r > 0 and e1s == 0) else pre * 64
+        return ((sl - e1s) * slice_bytes + pre_b + e1r * 4 + ref * 4 + probe_entries * 12
                 + nq * info["dim_padded"] * 4 + out_entries * 12) / launches
 
-    scan_bytes = scan_bytes_of(slices, refined, pre_reads, e1_reads, pre_two_phase, probe_entries)
+    scan_bytes = scan_bytes_of(c)
     full_bytes_per_launch = candidates * info["dim_padded"] * esize / launches
 
     # ---- timed region -----------------------------------------------------------------
@@ -613,9 +613,38 @@ def run_workload(wl, args, headline):
     fkms, fkn = ix.kernel_timing(reset=True)
     full_qps = nq / full_ms * 1e3
     fc = counters(full_best[0], 0.0, "none")
-    full_scan_bytes = scan_bytes_of(int(fc[2]), int(fc[1]), 0, 0, False,
-                                    probe_entries if uneven else nq * full_best[0])
+    full_scan_bytes = scan_bytes_of(fc)
     full_scan_ms = fkms[3] / max(1, fkn[3])
+    # the list-major full-D scan: every tile's distances to the queries probing its list on the
+    # matrix cores, then the per-query merge (its own operating point, same protocol)
+    ix.set_launch(full_d_matrix=1)
+    lm_best = sweep_points([(p, 0.0) for p in (nprobe_list if not args.nprobe else [args.nprobe])], "none")
+    for _ in range(args.warmup):
+        run(lm_best[0], 0.0, "none")
+    ix.set_kernel_timing(True)
+    torch.cuda.synchronize()
+    lm_ms = timed(lm_best[0], 0.0, "none", steps)
+    ix.set_kernel_timing(False)
+    lkms, lkn = ix.kernel_timing(reset=True)
+    ix.set_launch(full_d_matrix=0)
+    lm_flops = 2.0 * int(fc[0]) * info["dim_padded"] / launches   # candidates x dims per launch
+    lm_dist_ms = lkms[4] / max(1, lkn[4])
+    full_layouts = {
+        "query_major": {"layout": "query-major scan of the dimension-blocked tiles, every dim block",
+                        "qps": round(full_qps, 1), "nprobe": full_best[0],
+                        "recall_at_10": round(full_best[3], 4), "ms_per_step": round(full_ms, 4),
+                        "scan_kernel_ms": round(full_scan_ms, 4),
+                        "scan_achieved_GBs": round(full_scan_bytes / (full_scan_ms * 1e-3) / 1e9, 1)},
+        "list_major": {"layout": "list-major: each tile's distances to every query probing its list on "
+                                 "the FP32 matrix cores, then the per-query merge",
+                       "qps": round(nq / lm_ms * 1e3, 1), "nprobe": lm_best[0],
+                       "recall_at_10": round(lm_best[3], 4), "ms_per_step": round(lm_ms, 4),
+                       "distance_kernel_ms": round(lm_dist_ms, 4),
+                       "distance_kernel_tflops": round(lm_flops / (lm_dist_ms * 1e-3) / 1e12, 2)
+                       if lm_dist_ms > 0 else None,
+                       "merge_scan_ms": round(lkms[3] / max(1, lkn[3]), 4)},
+    }
+    log(f"[bench] full-D layouts: {full_layouts}")
 
     # ---- K = 100 on the same index (table K_c = 100) -----------------------------------
     k100 = None
@@ -716,12 +745,9 @@ def run_workload(wl, args, headline):
                    **({"launches_per_step": launches, "queries_per_launch": bsz,
                        "k": f"per query U{set(uneven['k'])}", "nprobe": "per query U{%d..%d}" % uneven["nprobe"],
                        "fp8_prestage_dims": cfg.get("fp8", 0)} if uneven else {})},
-        "full_d_scan": {"layout": "query-major scan of the dimension-blocked tiles, every dim block",
-                        "qps": round(full_qps, 1), "nprobe": full_best[0],
-                        "recall_at_10": round(full_best[3], 4), "ms_per_step": round(full_ms, 4),
-                        "scan_kernel_ms": round(full_scan_ms, 4),
-                        "scan_achieved_GBs": round(full_scan_bytes / (full_scan_ms * 1e-3) / 1e9, 1)},
-        "speedup_vs_full_d": round(qps / full_qps, 3),
+        "full_d_scan": dict(max(full_layouts.values(), key=lambda x: x["qps"]),
+                            layouts=full_layouts),
+        "speedup_vs_full_d": round(qps / max(x["qps"] for x in full_layouts.values()), 3),
         "end_to_end": e2e,
         "k100": k100,
         "without_fp8_prestage": no_pre,
@@ -733,6 +759,7 @@ def run_workload(wl, args, headline):
                                "first_phase": round(kstep[4], 4)},
         "scan_stats": {"candidates": candidates, "refined": refined, "prestage_reads": pre_reads,
                        "prestage_pruned": pre_pruned, "two_phase_sums": e1_reads,
+                       "two_phase_slices": e1_slices,
                        "scanned_dim_ratio": round(slices / max(1, candidates * NB), 4),
                        "bytes_vs_full_d": round((slices * slice_bytes + pre_reads * 64) / launches
                                                 / max(1, full_bytes_per_launch), 4)},
@@ -887,7 +914,7 @@ def main():
     ablation = None
     if args.ablation and not uneven:
         ix_main = ix
-        ctr = torch.zeros(70, dtype=torch.int64, device=dev)
+        ctr = torch.zeros(71, dtype=torch.int64, device=dev)
 
         def sweep_mode(label, mode, knobs, setter, alpha_of, gix):
             pts = []

@@ -185,7 +185,9 @@ typedef struct {
   int64_t prestage_pruned;   /* candidates the FP8 pre-stage pruned (not in stage_stop) */
   int64_t two_phase_sums;    /* candidates whose first test (dim block 0, or the FP8 pre-stage)
                                 read a sum the two-phase scan's first phase computed list by
-                                list, instead of the base (see ddc_launch_params) */
+                                list, or whose full distance the list-major full-D scan
+                                computed, instead of the base (see ddc_launch_params) */
+  int64_t two_phase_slices;  /* dim-block slices those sums stood in for */
 } ddc_search_stats;
 
 /* Fills *p with the defaults listed above. */
@@ -264,8 +266,9 @@ ddc_status ddc_search_var(const ddc_index *ix, const float *queries, int64_t nq,
  * themselves; the device clamps a per-query entry outside [1, k_max] or [1, nprobe_max]
  * into that range rather than trusting it); d_out_offsets: CSR as in
  * ddc_search_var or NULL for dense [nq x k_all]; d_ids int64 / d_dists float32 outputs;
- * d_counters: NULL or device int64[4 + 64 + 2] (added to): candidates, refined, stage
- * slices, two-phase sums read, stage_stop[64], prestage_reads, prestage_pruned.
+ * d_counters: NULL or device int64[4 + 64 + 3] (added to): candidates, refined, stage
+ * slices, two-phase sums read, stage_stop[64], prestage_reads, prestage_pruned, dim-block slices
+ * the two-phase sums stood in for (read by the first phase instead of the query's scan).
  * Scratch: the index keeps one grow-only device workspace per stream (rotated queries, coarse
  * distances, probes; about nq x (dim + nlist + nprobe_max) x 4 bytes for nq <= 32,768), made on
  * the stream's first call and reused by the next ones, freed with the index; calls on one
@@ -359,15 +362,23 @@ ddc_status ddc_set_bsar_multiplier(ddc_index *ix, double m);
  * the batch), 1 (the grid holds only the workgroups the device keeps resident at once; each
  * takes the next query from a device counter until none is left, queries ordered by
  * decreasing candidate count so long scans start first; query_order does not apply), -1 =
- * tuned.  two_phase: 0 (every candidate's first dim block is read by its query's scan), 1 (for
- * the learned and fixed-table tests with Delta_d = 32 and no FP8 pre-stage: first the partial
- * distance over dim block 0 of every candidate of every probed list is computed list by list,
- * each stored tile read once for all the queries that probe its list, in the scan's own
- * arithmetic; the scan then tests those sums and reads dim blocks 1.. of the survivors only; its
- * scratch holds one float per candidate of the batch), -1 = tuned (fixed rule: on once a list is
- * probed by four or more queries on average).  Defaults: 0, -1, 1, 1, -1, -1. */
+ * tuned.  two_phase: 0 (every candidate's first test reads its data in its query's scan), 1
+ * (for the learned and fixed-table tests whose first test follows dim block 0 with Delta_d = 32,
+ * or is the FP8 pre-stage: first that test's partial distance of every candidate of every
+ * probed list is computed list by list, each stored tile read once for all the queries that
+ * probe its list, in the scan's own arithmetic; the scan then tests those sums and reads the
+ * survivors' remaining dims only; its scratch holds one float per candidate of the batch), -1 =
+ * tuned (fixed rule: on once a list is probed by four or more queries on average).
+ * full_d_matrix (not result-invariant, never tuned; 0 or 1): with 1, scans without a test
+ * (DDC_CORR_NONE, or significance 0 in the learned mode) run list by list: for every stored
+ * tile and every query probing its list the distance ||q'||^2 + ||y||^2 - 2 <q', y> is formed
+ * on the matrix cores (FP32 products; each tile read once for all those queries), clamped at 0,
+ * and the per-query scan merges these distances.  The result is the exact full-D search up to
+ * FP32 rounding of that expanded form (its ids and distances can differ from the default scan's
+ * in the last bits and at near ties).  Defaults: 0, -1, 1, 1, -1, -1, 0. */
 typedef struct {
   int32_t waves_per_query, lookahead, query_order, xcd_swizzle, persistent, two_phase;
+  int32_t full_d_matrix;
 } ddc_launch_params;
 ddc_status ddc_set_launch(ddc_index *ix, const ddc_launch_params *p);
 ddc_status ddc_get_launch(const ddc_index *ix, ddc_launch_params *p);

@@ -69,13 +69,13 @@ class SearchStats(C.Structure):
     _fields_ = [("candidates", C.c_int64), ("refined", C.c_int64), ("stage_slices", C.c_int64),
                 ("bytes_touched", C.c_int64), ("stage_stop", C.c_int64 * 64),
                 ("prestage_reads", C.c_int64), ("prestage_pruned", C.c_int64),
-                ("two_phase_sums", C.c_int64)]
+                ("two_phase_sums", C.c_int64), ("two_phase_slices", C.c_int64)]
 
     def as_dict(self):
         return dict(candidates=self.candidates, refined=self.refined, stage_slices=self.stage_slices,
                     bytes_touched=self.bytes_touched, stage_stop=list(self.stage_stop),
                     prestage_reads=self.prestage_reads, prestage_pruned=self.prestage_pruned,
-                    two_phase_sums=self.two_phase_sums)
+                    two_phase_sums=self.two_phase_sums, two_phase_slices=self.two_phase_slices)
 
 
 class ServerParams(C.Structure):
@@ -92,7 +92,7 @@ class ServerStats(C.Structure):
 class LaunchParams(C.Structure):
     _fields_ = [("waves_per_query", C.c_int32), ("lookahead", C.c_int32),
                 ("query_order", C.c_int32), ("xcd_swizzle", C.c_int32), ("persistent", C.c_int32),
-                ("two_phase", C.c_int32)]
+                ("two_phase", C.c_int32), ("full_d_matrix", C.c_int32)]
 
 
 class DdcError(RuntimeError):
@@ -422,7 +422,8 @@ class Index:
 
     def set_launch(self, waves_per_query: int | None = None, lookahead: int | None = None,
                    query_order: int | None = None, xcd_swizzle: int | None = None,
-                   persistent: int | None = None, two_phase: int | None = None):
+                   persistent: int | None = None, two_phase: int | None = None,
+                   full_d_matrix: int | None = None):
         """Result-invariant launch shape of the scan; None keeps the current value
         (waves_per_query 0, lookahead -1, persistent -1 and two_phase -1 mean tuned per size
         class)."""
@@ -430,7 +431,8 @@ class Index:
         lp = LaunchParams(*(cur[k] if v is None else int(v) for k, v in
                             (("waves_per_query", waves_per_query), ("lookahead", lookahead),
                              ("query_order", query_order), ("xcd_swizzle", xcd_swizzle),
-                             ("persistent", persistent), ("two_phase", two_phase))))
+                             ("persistent", persistent), ("two_phase", two_phase),
+                             ("full_d_matrix", full_d_matrix))))
         _check(load_library().ddc_set_launch(self._h, C.byref(lp)))
 
     def launch(self) -> dict:

@@ -718,12 +718,12 @@ static void *stream_workspace(ddc_index *ix, hipStream_t s, size_t bytes) {
 
 // Queries per scratch chunk, and the scratch pieces of one chunk of cmax queries: rotated
 // queries, coarse distances, probes, then the query orders' keys, histograms and ranks and the
-// persistent launch's slot counter; with two_phase the first phase's list counts and starts,
-// pair ranks, pairs by list, pair offsets, query counts and offsets, and its stage-1 sums (a
-// bound on the batch's candidates: cmax times the summed lengths of the np_max longest lists);
-// each piece 256-byte aligned.
+// persistent launch's slot counter; with two_phase (or the list-major full-D scan) the first
+// phase's list counts and starts, pair ranks, pairs by list, pair offsets, query counts and
+// offsets, its sums (a bound on the batch's candidates: cmax times the summed lengths of the
+// np_max longest lists) and the queries' squared norms; each piece 256-byte aligned.
 constexpr int64_t kChunk = 32768;
-constexpr int kParts = 19;
+constexpr int kParts = 20;
 static int64_t e1_bound(const ddc_index *ix, int64_t cmax, int np_max) {
   const int np = std::min<int>(std::max(np_max, 0), (int)ix->len_desc_prefix.size() - 1);
   return np > 0 ? cmax * ix->len_desc_prefix[np] : 0;
@@ -737,7 +737,7 @@ static void scratch_sizes(const ddc_index *ix, int64_t cmax, int np_max, bool tw
                             (size_t)cmax * 4, 256,
                             t * (ix->nlist + 1) * 4, t * (ix->nlist + 1) * 4, t * pairs * 4, t * pairs * 4,
                             t * pairs * 8, t * cmax * 8, t * (cmax + 1) * 8,
-                            t * (size_t)e1_bound(ix, cmax, np_max) * 4};
+                            t * (size_t)e1_bound(ix, cmax, np_max) * 4, t * cmax * 4};
   for (int i = 0; i < kParts; ++i) sizes[i] = v[i];
 }
 
@@ -848,10 +848,13 @@ void ddc::search_device(ddc_index *ix, const float *d_q, int64_t nq, const int32
   // neither tune nor keep a stream workspace: the server sizes its admission budget without them)
   const bool two_ok = !fixed_ws && !qrot_out && (may_tune || stream_scratch) && ix->two_phase != 0 &&
                       two_phase_eligible(ix, elig);
-  const int64_t chunk = chunk_queries(ix, np_max, two_ok);
+  // the list-major full-D scan (no test; opted into with full_d_matrix)
+  const bool lm_full = !fixed_ws && !qrot_out && !a.prune && !est && ix->full_d_matrix == 1 &&
+                       ix->d_tile_list.p != nullptr;
+  const int64_t chunk = chunk_queries(ix, np_max, two_ok || lm_full);
   const int64_t cmax = std::min(chunk, nq);
   size_t sizes[kParts];
-  scratch_sizes(ix, cmax, np_max, two_ok, sizes);
+  scratch_sizes(ix, cmax, np_max, two_ok || lm_full, sizes);
   size_t total = 0;
   for (size_t b : sizes) total += (b + 255) & ~(size_t)255;
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
@@ -874,8 +877,8 @@ void ddc::search_device(ddc_index *ix, const float *d_q, int64_t nq, const int32
   const ScratchPart qrot{part[0]}, cdist{part[1]}, probes{part[2]}, ord_hist{part[3]}, ord_rank{part[4]},
       ord{part[5]}, lpt_key{part[6]}, lpt_hist{part[7]}, lpt_rank{part[8]}, lpt{part[9]}, queue{part[10]},
       s1_lcnt{part[11]}, s1_lstart{part[12]}, s1_rank{part[13]}, s1_lpair{part[14]}, s1_poff{part[15]},
-      s1_qcnt{part[16]}, s1_qoff{part[17]}, s1_e1{part[18]};
-  const int64_t e1_cap = two_ok ? e1_bound(ix, cmax, np_max) : 0;
+      s1_qcnt{part[16]}, s1_qoff{part[17]}, s1_e1{part[18]}, s1_qnorm{part[19]};
+  const int64_t e1_cap = two_ok || lm_full ? e1_bound(ix, cmax, np_max) : 0;
   for (int64_t q0 = 0; q0 < nq; q0 += chunk) {
     const int64_t nqc = std::min(chunk, nq - q0);
     GemmArgs g{};
@@ -928,24 +931,28 @@ void ddc::search_device(ddc_index *ix, const float *d_q, int64_t nq, const int32
       return {lpt.as<int32_t>(), queue.as<int32_t>()};
     };
     bool s1_made = false;
+    auto stage1_args = [&]() {
+      Stage1Args s1{};
+      s1.probes = probes.as<int32_t>(); s1.p_stride = np_max;
+      s1.nprobe = d_np ? d_np + q0 : nullptr; s1.nprobe_all = np_all;
+      s1.list_len = ix->d_list_len.as<int32_t>(); s1.tile_off = ix->d_tile_off.as<int32_t>();
+      s1.tile_list = ix->d_tile_list.as<int32_t>(); s1.nlist = ix->nlist;
+      s1.total_tiles = ix->total_tiles; s1.nq = nqc;
+      s1.qrot = qrot.as<float>(); s1.q_stride = Dp; s1.base = ix->d_base.p; s1.nblocks = ix->NB;
+      s1.pre = a.pre; s1.base8 = a.base8; s1.scale8 = a.scale8;
+      s1.lcnt = s1_lcnt.as<int32_t>(); s1.lstart = s1_lstart.as<int32_t>();
+      s1.rank = s1_rank.as<int32_t>(); s1.lpair = s1_lpair.as<int32_t>();
+      s1.poff = s1_poff.as<int64_t>(); s1.qcnt = s1_qcnt.as<int64_t>(); s1.qoff = s1_qoff.as<int64_t>();
+      s1.e1 = s1_e1.as<float>(); s1.e1_cap = e1_cap;
+      return s1;
+    };
     if (two_ok) {
       orders.e1_cap = e1_cap;
       orders.stage1 = [&](bool rebuild) -> std::pair<const float *, const int64_t *> {
         const bool first = !s1_made;
         s1_made = true;
         if (first || rebuild) {
-          Stage1Args s1{};
-          s1.probes = probes.as<int32_t>(); s1.p_stride = np_max;
-          s1.nprobe = d_np ? d_np + q0 : nullptr; s1.nprobe_all = np_all;
-          s1.list_len = ix->d_list_len.as<int32_t>(); s1.tile_off = ix->d_tile_off.as<int32_t>();
-          s1.tile_list = ix->d_tile_list.as<int32_t>(); s1.nlist = ix->nlist;
-          s1.total_tiles = ix->total_tiles; s1.nq = nqc;
-          s1.qrot = qrot.as<float>(); s1.q_stride = Dp; s1.base = ix->d_base.p; s1.nblocks = ix->NB;
-          s1.pre = a.pre; s1.base8 = a.base8; s1.scale8 = a.scale8;
-          s1.lcnt = s1_lcnt.as<int32_t>(); s1.lstart = s1_lstart.as<int32_t>();
-          s1.rank = s1_rank.as<int32_t>(); s1.lpair = s1_lpair.as<int32_t>();
-          s1.poff = s1_poff.as<int64_t>(); s1.qcnt = s1_qcnt.as<int64_t>(); s1.qoff = s1_qoff.as<int64_t>();
-          s1.e1 = s1_e1.as<float>(); s1.e1_cap = e1_cap;
+          const Stage1Args s1 = stage1_args();
           timed(ix, 4, s, [&] { launch_stage1_lists(s1, ix->store(), s); }, fixed_ws);
         }
         return {s1_e1.as<float>(), s1_qoff.as<int64_t>()};
@@ -955,6 +962,15 @@ void ddc::search_device(ddc_index *ix, const float *d_q, int64_t nq, const int32
     a.nq = (int32_t)nqc; a.nblocks = ix->NB; a.block_b = ix->B; a.nlist = ix->nlist;
     a.k_max = k_max; a.lag = ix->L;
     choose_variant(ix, a, np_max, s, may_tune, orders);
+    if (lm_full) {
+      const Stage1Args s1 = stage1_args();
+      timed(ix, 4, s, [&] {
+        launch_full_lists(s1, ix->d_xnorm.as<float>(), s1_qnorm.as<float>(), ix->store(), s);
+      }, fixed_ws);
+      a.e1 = s1_e1.as<float>();
+      a.e1_qoff = s1_qoff.as<int64_t>();
+      a.e1_cap = e1_cap;
+    }
     timed(ix, 3, s, [&] { launch_scan(a, ix->store(), s); }, fixed_ws);
   }
   HIPC(hipGetLastError());
@@ -970,6 +986,7 @@ static void stats_from_counters(const ddc_index *ix, const int64_t *c, ddc_searc
   st->prestage_reads = c[kCtrPreReads];
   st->prestage_pruned = c[kCtrPrePruned];
   st->two_phase_sums = c[3];
+  st->two_phase_slices = c[kCtrSlicesSummed];
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1695,6 +1712,7 @@ ddc_status ddc_set_launch(ddc_index *ix, const ddc_launch_params *p) {
     return set_err(DDC_EINVAL, "query_order and xcd_swizzle must be 0 or 1");
   if (p->persistent < -1 || p->persistent > 1) return set_err(DDC_EINVAL, "persistent must be -1, 0 or 1");
   if (p->two_phase < -1 || p->two_phase > 1) return set_err(DDC_EINVAL, "two_phase must be -1, 0 or 1");
+  if (p->full_d_matrix != 0 && p->full_d_matrix != 1) return set_err(DDC_EINVAL, "full_d_matrix must be 0 or 1");
   std::lock_guard<std::mutex> lk(ix->tune_mtx);
   ix->tuned.clear();   // a choice tuned under other forced knobs may not be the best now
   ix->waves_per_query = p->waves_per_query;
@@ -1703,6 +1721,7 @@ ddc_status ddc_set_launch(ddc_index *ix, const ddc_launch_params *p) {
   ix->xcd_swizzle = p->xcd_swizzle;
   ix->persistent = p->persistent;
   ix->two_phase = p->two_phase;
+  ix->full_d_matrix = p->full_d_matrix;
   return DDC_OK;
 }
 
@@ -1714,6 +1733,7 @@ ddc_status ddc_get_launch(const ddc_index *ix, ddc_launch_params *p) {
   p->xcd_swizzle = ix->xcd_swizzle;
   p->persistent = ix->persistent;
   p->two_phase = ix->two_phase;
+  p->full_d_matrix = ix->full_d_matrix;
   return DDC_OK;
 }
 

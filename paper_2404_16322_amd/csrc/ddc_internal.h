@@ -16,9 +16,9 @@ constexpr int kMaxLag = 64;          // tau lag L in blocks
 constexpr int kMaxK = 256;
 constexpr int kScanThreads = 256;    // 4 wavefronts per query
 // counters: candidates, refined, stage_slices, two-phase sums read, stop[64], pre-stage reads,
-// pre-stage prunes
-constexpr int kCtrPreReads = 4 + 64, kCtrPrePruned = 4 + 64 + 1;
-constexpr int kMaxCounters = 4 + 64 + 2;
+// pre-stage prunes, dim-block slices the two-phase sums stood in for
+constexpr int kCtrPreReads = 4 + 64, kCtrPrePruned = 4 + 64 + 1, kCtrSlicesSummed = 4 + 64 + 2;
+constexpr int kMaxCounters = 4 + 64 + 3;
 constexpr int kFp8Lead = 64;          // dims covered by the FP8 pre-stage
 constexpr int kMaxTables = 4;         // correction tables (calibration K_c values) per index
 constexpr size_t kMaxLds = 160 * 1024;  // LDS per workgroup on gfx950
@@ -87,6 +87,7 @@ struct ScanArgs {
   const float *e1;
   const int64_t *e1_qoff;
   int64_t e1_cap;          // entries of e1 (no read at or past it)
+  // (prune = 0 with e1 set: e1 holds every candidate's full distance, from launch_full_lists)
 };
 
 void launch_scan(const ScanArgs &a, int store, hipStream_t s);
@@ -111,6 +112,13 @@ struct Stage1Args {
   float *e1; int64_t e1_cap;
 };
 void launch_stage1_lists(const Stage1Args &a, int store, hipStream_t s);
+
+// Full-dimension distances list by list on the matrix cores (the list-major full-D scan):
+// the pair grouping of launch_stage1_lists, then for every stored tile and every query that
+// probes its list  ||q'||^2 + ||y||^2 - 2 <q', y>  (FP32 products, v_mfma_f32_16x16x4_f32; the
+// norms ||y||^2 of the stored values from xnorm, ||q'||^2 in FP32), clamped at 0, written to
+// e1 in the layout of launch_stage1_lists.  qnorm: [nq] scratch.
+void launch_full_lists(const Stage1Args &a, const float *xnorm, float *qnorm, int store, hipStream_t s);
 // LDS bytes one workgroup of the scan needs with W waves per query (> kMaxLds: not launchable).
 size_t scan_lds_request(const ScanArgs &a, int W);
 

@@ -185,7 +185,7 @@ __host__ __device__ inline size_t scan_lds_bytes(int Dp, int kmax, int block_b, 
 // distance from the query's lookup table in LDS and the candidate's codes, with its
 // quantization error as second feature) before the stages, whose tests are then lossless.
 template <int ST, bool PRUNE, bool LOOK, int W, bool PRE, bool RES, bool EST = false, bool PQ = false,
-          bool LAG = false>
+          bool LAG = false, bool LM = false>
 __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4, 8))) void scan_kernel(ScanArgs a) {
   using S = Store<ST>;
   constexpr int EPL = 16 / S::kBytes;          // elements per lane load
@@ -235,7 +235,7 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
   int32_t *s_ml = reinterpret_cast<int32_t *>(ql + L.meta);   // list ids, lengths, first tiles
 
   // statistics (wave-uniform, flushed once when counters are requested)
-  int64_t st_cand = 0, st_ref = 0, st_slices = 0, st_pre = 0, st_pre_pruned = 0, st_e1 = 0;
+  int64_t st_cand = 0, st_ref = 0, st_slices = 0, st_pre = 0, st_pre_pruned = 0, st_e1 = 0, st_e1_sl = 0;
   unsigned long long *ctr = reinterpret_cast<unsigned long long *>(a.counters);
   // stop-stage histogram, lane i counting stage i (one atomic per lane at the end)
   uint32_t st_stop = 0;
@@ -432,7 +432,30 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
       const float *xnorm_seg = (RES || EST) ? a.xnorm + (int64_t)toff * kTile + bs + s0 : nullptr;
       // In a load group, chunk c, lane (sub, g) reads dims [g*EPL, g*EPL+EPL) of candidate
       // t0 + c*CPW + sub; after transpose_sum the lane owns candidate t0 + g*CPW + sub.
-      if (!PRUNE || (LAG ? !(tau_t < INFINITY) : tn < K)) {
+      if (LM) {
+        // ---- list-major full-D scan: every candidate's distance was computed beforehand on
+        // the matrix cores (launch_full_lists); one 4-byte load per candidate, four in flight ----
+        const int64_t e0 = e1_list + bs + s0;
+        for (int c0 = 0; c0 < slen; c0 += 256) {
+          float ds[4];
+          int32_t is[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int idx = c0 + u * 64 + lane;
+            ds[u] = (idx < slen && e0 + idx < a.e1_cap) ? a.e1[e0 + idx] : 0.f;
+            is[u] = bids[min(idx, slen - 1)];
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int idx = c0 + u * 64 + lane;
+            const bool valid = idx < slen && e0 + idx < a.e1_cap;
+            append(valid && (tn < K || lex_less(ds[u], is[u], tau, tau_id)), ds[u], is[u]);
+          }
+        }
+        st_cand += slen; st_ref += slen; st_slices += (int64_t)slen * nb;
+        st_e1 += slen; st_e1_sl += (int64_t)slen * nb;
+        if (ctr) stop_add(nb - 1, (uint32_t)slen);
+      } else if (!PRUNE || (LAG ? !(tau_t < INFINITY) : tn < K)) {
         // ---- no test can prune: every candidate, every dim block ----
         // Slots past slen inside the last tile are zero padding: loads stay in bounds.
         for (int t0 = 0; t0 < slen; t0 += GROUP) {
@@ -546,20 +569,28 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
           const float mb = s_mb[2 * nb], bb = s_mb[2 * nb + 1];
           const int64_t e0 = e1_list + bs + s0;
           int nn = 0;
-          for (int t0 = 0; t0 < slen; t0 += 64) {
-            const int idx = t0 + lane;
-            const bool valid = idx < slen && e0 + idx < a.e1_cap;
-            const float ev = valid ? a.e1[e0 + idx] : 0.f;
-            const bool prune = valid && fmaf(mb, ev, bb) > tau_t;
-            const bool keep = valid && !prune;
-            const unsigned long long bal = __ballot(keep);
-            if (keep) {
-              const int pos = nn + __popcll(bal & lt);
-              s_ac[pos] = (uint16_t)idx;
-              s_ae[pos] = 0.f;
+          for (int c0 = 0; c0 < slen; c0 += 256) {
+            float evs[4];   // four loads in flight, then the tests
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const int idx = c0 + u * 64 + lane;
+              evs[u] = (idx < slen && e0 + idx < a.e1_cap) ? a.e1[e0 + idx] : 0.f;
             }
-            nn += __popcll(bal);
-            st_pre_pruned += __popcll(__ballot(prune));
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const int idx = c0 + u * 64 + lane;
+              const bool valid = idx < slen && e0 + idx < a.e1_cap;
+              const bool prune = valid && fmaf(mb, evs[u], bb) > tau_t;
+              const bool keep = valid && !prune;
+              const unsigned long long bal = __ballot(keep);
+              if (keep) {
+                const int pos = nn + __popcll(bal & lt);
+                s_ac[pos] = (uint16_t)idx;
+                s_ae[pos] = 0.f;
+              }
+              nn += __popcll(bal);
+              st_pre_pruned += __popcll(__ballot(prune));
+            }
           }
           st_pre += slen;
           st_e1 += slen;
@@ -639,23 +670,33 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
           const float mb = s_mb[0], bb = s_mb[1];
           const int64_t e0 = e1_list + bs + s0;
           int nn = 0, pruned = 0;
-          for (int t0 = 0; t0 < slen; t0 += 64) {
-            const int idx = t0 + lane;
-            const bool valid = idx < slen && e0 + idx < a.e1_cap;
-            const float ev = valid ? a.e1[e0 + idx] : 0.f;
-            const bool prune = valid && fmaf(mb, ev, bb) > tau_t;
-            const bool keep = valid && !prune;
-            const unsigned long long bal = __ballot(keep);
-            if (keep) {
-              const int pos = nn + __popcll(bal & lt);
-              s_ac[pos] = (uint16_t)idx;
-              s_ae[pos] = ev;
+          for (int c0 = 0; c0 < slen; c0 += 256) {
+            float evs[4];   // four loads in flight, then the tests
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const int idx = c0 + u * 64 + lane;
+              evs[u] = (idx < slen && e0 + idx < a.e1_cap) ? a.e1[e0 + idx] : 0.f;
             }
-            nn += __popcll(bal);
-            pruned += __popcll(__ballot(prune));
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const int idx = c0 + u * 64 + lane;
+              const bool valid = idx < slen && e0 + idx < a.e1_cap;
+              const float ev = evs[u];
+              const bool prune = valid && fmaf(mb, ev, bb) > tau_t;
+              const bool keep = valid && !prune;
+              const unsigned long long bal = __ballot(keep);
+              if (keep) {
+                const int pos = nn + __popcll(bal & lt);
+                s_ac[pos] = (uint16_t)idx;
+                s_ae[pos] = ev;
+              }
+              nn += __popcll(bal);
+              pruned += __popcll(__ballot(prune));
+            }
           }
           st_slices += slen;
           st_e1 += slen;
+          st_e1_sl += slen;
           if (ctr) stop_add(0, (uint32_t)pruned);
           __builtin_amdgcn_wave_barrier();
           nalive = nn;
@@ -1025,6 +1066,7 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
     atomicAdd(&ctr[1], (unsigned long long)st_ref);
     atomicAdd(&ctr[2], (unsigned long long)st_slices);
     if (st_e1) atomicAdd(&ctr[3], (unsigned long long)st_e1);
+    if (st_e1_sl) atomicAdd(&ctr[kCtrSlicesSummed], (unsigned long long)st_e1_sl);
     if (PRE || PQ) {
       atomicAdd(&ctr[kCtrPreReads], (unsigned long long)st_pre);
       atomicAdd(&ctr[kCtrPrePruned], (unsigned long long)st_pre_pruned);
@@ -1366,8 +1408,8 @@ __global__ __launch_bounds__(kS1Threads) void stage1_lists_kernel(Stage1Args a) 
   }
 }
 
-void launch_stage1_lists(const Stage1Args &a, int store, hipStream_t s) {
-  if (a.nq <= 0 || a.total_tiles <= 0) return;
+// Pair grouping of both list-major first phases: per-query offsets, then pairs by list.
+static void launch_pair_groups(const Stage1Args &a, hipStream_t s) {
   const int64_t npair = a.nq * a.p_stride;
   const unsigned gp = (unsigned)((npair + 255) / 256);
   hipLaunchKernelGGL(fill_i32_kernel, dim3((a.nlist + 256) / 256), dim3(256), 0, s, a.lcnt,
@@ -1382,6 +1424,148 @@ void launch_stage1_lists(const Stage1Args &a, int store, hipStream_t s) {
                      (int64_t)a.nlist, a.lstart);
   hipLaunchKernelGGL(pair_scatter_kernel, dim3(gp), dim3(256), 0, s, a.probes, a.p_stride, a.nprobe,
                      a.nprobe_all, a.nlist, a.nq, a.lstart, a.rank, a.lpair);
+}
+
+// ---- list-major full-D scan: distances on the matrix cores ----------------------------------
+
+typedef float lm_floatx4 __attribute__((ext_vector_type(4)));
+
+// ||q'||^2 of every rotated query (FP32, dims in order; zero padding beyond D adds nothing)
+__global__ __launch_bounds__(256) void qnorm_kernel(const float *qrot, int64_t q_stride, int32_t Dp,
+                                                    int64_t nq, float *qnorm) {
+  const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (q >= nq) return;
+  float s = 0.f;
+  for (int i = lane; i < Dp; i += 64) s = fmaf(qrot[q * q_stride + i], qrot[q * q_stride + i], s);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  if (lane == 0) qnorm[q] = s;
+}
+
+// One workgroup per stored tile: a 64-query x 64-vector block of inner products per chunk of the
+// list's pairs, K stepping one 32-dim block at a time through LDS (the tile's block b is a
+// row-major 64 x 32 matrix in the packed layout).  Four waves own 32 x 32 quarters, 2 x 2 MFMA
+// 16x16 blocks each (A[i][k] at lane i + 16 k, B[k][j] at lane j + 16 k; result lane l, register
+// r holds C[4 (l / 16) + r][l % 16]).
+constexpr int kLmLd = 36;   // padded LDS row (floats)
+template <int ST>
+__global__ __launch_bounds__(256) void full_lists_kernel(Stage1Args a, const float *xnorm, const float *qnorm) {
+  using S = Store<ST>;
+  constexpr int EPL = 16 / S::kBytes;                        // elements per 16-byte load
+  constexpr int SLICE = kBlockDims * S::kBytes;
+  constexpr int64_t BLOCK_BYTES = (int64_t)kTile * SLICE;
+  constexpr int YLOADS = (kTile * kBlockDims / EPL) / 256;  // 16-byte loads per thread per block
+  __shared__ __align__(16) float Ys[kTile * kLmLd];
+  __shared__ __align__(16) float Qs[kTile * kLmLd];
+  __shared__ int64_t s_dst[kTile];
+  __shared__ int64_t s_q[kTile];
+  __shared__ float s_qn[kTile], s_yn[kTile];
+  const int64_t t = blockIdx.x;
+  if (t >= a.total_tiles) return;
+  const int l = a.tile_list[t];
+  if (l < 0 || l >= a.nlist) return;
+  const int pb = a.lstart[l], pe = a.lstart[l + 1];
+  if (pb >= pe) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int tl = (int)(t - a.tile_off[l]);
+  const int cnt = min(kTile, a.list_len[l] - tl * kTile);
+  const unsigned char *tp = reinterpret_cast<const unsigned char *>(a.base) + t * a.nblocks * BLOCK_BYTES;
+  if (tid < kTile) s_yn[tid] = xnorm[t * kTile + tid];
+  for (int c0 = pb; c0 < pe; c0 += kTile) {
+    const int n = min(kTile, pe - c0);
+    __syncthreads();
+    if (tid < kTile) {
+      int64_t q = 0, dst = 0;
+      float qn = 0.f;
+      if (tid < n) {
+        const int pidx = a.lpair[c0 + tid];
+        q = pidx / a.p_stride;
+        dst = a.qoff[q] + a.poff[pidx] + (int64_t)tl * kTile;
+        qn = qnorm[q];
+      }
+      s_q[tid] = q;
+      s_dst[tid] = dst;
+      s_qn[tid] = qn;
+    }
+    __syncthreads();
+    lm_floatx4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[i][j] = lm_floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int b = 0; b < a.nblocks; ++b) {
+      // stage the tile's dim block b (as FP32) and the chunk's query slices
+#pragma unroll
+      for (int it = 0; it < YLOADS; ++it) {
+        const int e = (tid + it * 256) * EPL;          // element of the 64 x 32 block
+        const int r = e / kBlockDims, c = e % kBlockDims;
+        const uint4 v = *reinterpret_cast<const uint4 *>(tp + b * BLOCK_BYTES + (int64_t)e * S::kBytes);
+        float f[EPL];
+        S::unpack(v, f);
+#pragma unroll
+        for (int u = 0; u < EPL; u += 4)
+          *reinterpret_cast<float4 *>(&Ys[r * kLmLd + c + u]) = make_float4(f[u], f[u + 1], f[u + 2], f[u + 3]);
+      }
+#pragma unroll
+      for (int it = 0; it < 2; ++it) {
+        const int e = (tid + it * 256) * 4;
+        const int r = e / kBlockDims, c = e % kBlockDims;
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (r < n) v = *reinterpret_cast<const float4 *>(a.qrot + s_q[r] * a.q_stride + b * kBlockDims + c);
+        *reinterpret_cast<float4 *>(&Qs[r * kLmLd + c]) = v;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int kk = 0; kk < kBlockDims; kk += 4) {
+        float af[2], bf[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) af[i] = Qs[(wr * 32 + i * 16 + (lane & 15)) * kLmLd + kk + (lane >> 4)];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) bf[j] = Ys[(wc * 32 + j * 16 + (lane & 15)) * kLmLd + kk + (lane >> 4)];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i], bf[j], acc[i][j], 0, 0, 0);
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int col = wc * 32 + j * 16 + (lane & 15);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = wr * 32 + i * 16 + 4 * (lane >> 4) + r;
+          if (row < n && col < cnt) {
+            const float d = fmaxf(s_qn[row] + s_yn[col] - 2.f * acc[i][j][r], 0.f);
+            const int64_t o = s_dst[row] + col;
+            if (o < a.e1_cap) a.e1[o] = d;
+          }
+        }
+      }
+  }
+}
+
+void launch_full_lists(const Stage1Args &a, const float *xnorm, float *qnorm, int store, hipStream_t s) {
+  if (a.nq <= 0 || a.total_tiles <= 0) return;
+  launch_pair_groups(a, s);
+  hipLaunchKernelGGL(qnorm_kernel, dim3((unsigned)((a.nq + 3) / 4)), dim3(256), 0, s, a.qrot, a.q_stride,
+                     a.nblocks * kBlockDims, a.nq, qnorm);
+  const dim3 grid((unsigned)a.total_tiles), blk(256);
+  switch (store) {
+    case ST_F32: hipLaunchKernelGGL(full_lists_kernel<ST_F32>, grid, blk, 0, s, a, xnorm, qnorm); break;
+    case ST_F16: hipLaunchKernelGGL(full_lists_kernel<ST_F16>, grid, blk, 0, s, a, xnorm, qnorm); break;
+    default: hipLaunchKernelGGL(full_lists_kernel<ST_BF16>, grid, blk, 0, s, a, xnorm, qnorm); break;
+  }
+}
+
+void launch_stage1_lists(const Stage1Args &a, int store, hipStream_t s) {
+  if (a.nq <= 0 || a.total_tiles <= 0) return;
+  launch_pair_groups(a, s);
   const dim3 grid((unsigned)a.total_tiles), blk(kS1Threads);
   if (a.pre) {   // the FP8 codes do not depend on the storage type
     hipLaunchKernelGGL((stage1_lists_kernel<ST_F32, true>), grid, blk, 0, s, a);
@@ -1419,21 +1603,21 @@ size_t scan_lds_request(const ScanArgs &a, int W) {
 }
 
 template <int ST, bool P, bool LK, int W, bool PRE = false, bool RES = false, bool EST = false,
-          bool PQ = false, bool LG = false>
+          bool PQ = false, bool LG = false, bool LM = false>
 static void launch_variant(const ScanArgs &a, hipStream_t s) {
   const size_t smem = scan_lds_bytes(a.nblocks * kBlockDims, a.k_max, a.block_b, W, RES,
                                      PQ ? a.pq_m * 256 + a.nblocks * kBlockDims : 0, a.p_stride,
                                      LG ? a.lag : 0);
   if (smem > kMaxLds) throw std::runtime_error("scan: LDS request exceeds 160 KiB");
   const int qpw = 4 / W;
-  const void *kern = reinterpret_cast<const void *>(&scan_kernel<ST, P, LK, W, PRE, RES, EST, PQ, LG>);
+  const void *kern = reinterpret_cast<const void *>(&scan_kernel<ST, P, LK, W, PRE, RES, EST, PQ, LG, LM>);
   int64_t grid = (a.nq + qpw - 1) / qpw;
   if (a.queue) {
     // W = 1: each wave takes its own slots, so the grid covers ceil(nq / 4) workgroups at most
     grid = std::min<int64_t>(grid, resident_workgroups(kern, smem));
     hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(64), 0, s, a.queue, (int64_t)1, 0);
   }
-  hipLaunchKernelGGL((scan_kernel<ST, P, LK, W, PRE, RES, EST, PQ, LG>), dim3((unsigned)grid),
+  hipLaunchKernelGGL((scan_kernel<ST, P, LK, W, PRE, RES, EST, PQ, LG, LM>), dim3((unsigned)grid),
                      dim3(kScanThreads), smem, s, a);
 }
 
@@ -1474,6 +1658,10 @@ template <int ST> static void launch_store(const ScanArgs &a, hipStream_t s) {
   if (a.est_nb > 0) {
     if (w4) launch_variant<ST, false, false, 4, false, false, true>(a, s);
     else launch_variant<ST, false, false, 1, false, false, true>(a, s);
+  } else if (!a.prune && a.e1) {
+    // the list-major full-D scan's merge: a kernel without the base-reading paths
+    if (w4) launch_variant<ST, false, false, 4, false, false, false, false, false, true>(a, s);
+    else launch_variant<ST, false, false, 1, false, false, false, false, false, true>(a, s);
   } else if (!a.prune) {
     if (w4) launch_variant<ST, false, false, 4>(a, s); else launch_variant<ST, false, false, 1>(a, s);
   } else if (a.lag > 0) {

@@ -35,7 +35,7 @@ def _both(g, Q, k, nprobe, alpha, mode, stream):
     for fn in (g.search_device, g.search_device_noalloc):
         ids = torch.full((Q.shape[0], k), -7, dtype=torch.int64, device="cuda")
         d = torch.full((Q.shape[0], k), -7.0, dtype=torch.float32, device="cuda")
-        ctr = torch.zeros(70, dtype=torch.int64, device="cuda")
+        ctr = torch.zeros(71, dtype=torch.int64, device="cuda")
         torch.cuda.synchronize()
         fn(q.data_ptr(), Q.shape[0], k, nprobe, alpha, mode, ids.data_ptr(), d.data_ptr(),
            d_counters=ctr.data_ptr(), stream=stream.cuda_stream)
