@@ -352,12 +352,18 @@ def run_workload(wl, args, headline):
 
     t0 = time.time()
     nlist = cfg["nlist"]
+    fitp = dict(cfg.get("fit", {}))
+    if headline and args.block_b:
+        fitp["block_b"] = args.block_b
     ix = Index.fit(w["base"], w["calib"], nlist=nlist, seed=spec["cfg"], storage=cfg["storage"],
-                   rotation=cfg["rotation"], fp8_lead_dims=cfg.get("fp8", 0), **cfg.get("fit", {}))
+                   rotation=cfg["rotation"], fp8_lead_dims=cfg.get("fp8", 0), **fitp)
     torch.cuda.synchronize()
     fit_s = time.time() - t0
     info = ix.info()
     log(f"[bench] GPU fit {fit_s:.1f}s: {info}")
+    if args.launch:
+        wv, la, pe, t2 = (int(x) for x in args.launch.split(","))
+        ix.set_launch(waves_per_query=wv, lookahead=la, persistent=pe, two_phase=t2)
 
     t0 = time.time()
     base_t = torch.from_numpy(w["base"]).to(dev, torch.float64)
@@ -561,7 +567,7 @@ def run_workload(wl, args, headline):
 
     # host copies included: queries from pinned host memory, results back to pinned memory
     e2e = None
-    if not uneven:
+    if not uneven and not args.profile:
         qh = torch.from_numpy(w["queries"]).pin_memory()
         ih = torch.empty((nq * k,), dtype=torch.int64).pin_memory()
         dh = torch.empty((nq * k,), dtype=torch.float32).pin_memory()
@@ -584,7 +590,7 @@ def run_workload(wl, args, headline):
     # every launch shape of the scan at the operating point (results are bit-identical)
     chosen = ix.scan_variant(bsz, k, int(nps.max())) if uneven else ix.scan_variant(nq, k, nprobe)
     variants = {}
-    if headline:
+    if headline and not args.profile:
         shapes = [(w_, l_, p_, t_) for t_ in (0, 1) for p_ in (0, 1) for w_ in (1, 4) for l_ in (0, 1)]
         for wv, la, pe, t2 in shapes:
             ix.set_launch(waves_per_query=wv, lookahead=la, persistent=pe, two_phase=t2)
@@ -823,6 +829,14 @@ def main():
                          "(PCA, residual, random projection) and report recall@100")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (HBM counter calibration)")
+    ap.add_argument("--profile", action="store_true",
+                    help="short run for a profiler: the timed steps and both full-D layouts at the "
+                         "operating point only (no launch-shape sweep, no host-copy timing)")
+    ap.add_argument("--block-b", type=int, default=0,
+                    help="threshold refresh block B of the fitted index (default: the workload's)")
+    ap.add_argument("--launch", default="",
+                    help="force the scan's launch shape: waves,lookahead,persistent,two_phase "
+                         "(e.g. 1,1,0,1), instead of tuning it")
     ap.add_argument("--cpu-oracle-child", default="", help=argparse.SUPPRESS)
     args = ap.parse_args()
     if args.cpu_oracle_child:

@@ -1004,11 +1004,53 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
         ns = s_cnt[par];
         mt = qt; mstep = 64 * W;
       }
+      // many survivors (a query's first blocks, where no test prunes): sort them first with a
+      // bitonic network in LDS, so every element's rank is two binary searches instead of a
+      // count over all survivors (one wave; the padding sorts last)
+      int np2 = 64;
+      while (np2 < ns) np2 <<= 1;
+      const bool sorted = W == 1 && ns > 64 && np2 <= B;
+      if (sorted) {
+        for (int i = ns + lane; i < np2; i += 64) { s_sd[i] = INFINITY; s_si[i] = 0x7FFFFFFF; }
+        __builtin_amdgcn_wave_barrier();
+        for (int kk = 2; kk <= np2; kk <<= 1) {
+          for (int jj = kk >> 1; jj > 0; jj >>= 1) {
+            for (int t = lane; t < (np2 >> 1); t += 64) {
+              const int i0 = ((t & ~(jj - 1)) << 1) | (t & (jj - 1));
+              const int i1 = i0 + jj;
+              const float d0 = s_sd[i0], d1 = s_sd[i1];
+              const int32_t x0 = s_si[i0], x1 = s_si[i1];
+              const bool up = (i0 & kk) == 0;
+              if (up ? lex_less(d1, x1, d0, x0) : lex_less(d0, x0, d1, x1)) {
+                s_sd[i0] = d1; s_sd[i1] = d0; s_si[i0] = x1; s_si[i1] = x0;
+              }
+            }
+            __builtin_amdgcn_wave_barrier();
+          }
+        }
+      }
       if (ns > 0) {
         const float *td = s_td + tin * KM;
         const int32_t *ti = s_ti + tin * KM;
         float *od = s_td + (tin ^ 1) * KM;
         int32_t *oi = s_ti + (tin ^ 1) * KM;
+        if (sorted) {
+          // rank = place in its own sorted list + elements of the other list before it
+          for (int i = mt; i < tn + ns && i < tn + K; i += mstep) {
+            const bool inq = i < tn;
+            const int own = inq ? i : i - tn;
+            const float d = inq ? td[i] : s_sd[own];
+            const int32_t id = inq ? ti[i] : s_si[own];
+            int lo = 0, hi = inq ? ns : tn;
+            while (lo < hi) {
+              const int mid = (lo + hi) >> 1;
+              const bool lt_ = inq ? lex_less(s_sd[mid], s_si[mid], d, id) : lex_less(td[mid], ti[mid], d, id);
+              if (lt_) lo = mid + 1; else hi = mid;
+            }
+            const int rank = own + lo;
+            if (rank < K) { od[rank] = d; oi[rank] = id; }
+          }
+        } else
         for (int i = mt; i < tn + ns; i += mstep) {
           float d;
           int32_t id;
@@ -1295,29 +1337,36 @@ __global__ __launch_bounds__(256) void pair_scatter_kernel(const int32_t *probes
   if (l >= 0 && l < nlist) lpair[lstart[l] + rank[pidx]] = (int32_t)pidx;
 }
 
-// One workgroup per stored tile.  The tile's 64 vectors stay in registers (dim block 0, or with
-// PRE the FP8 codes of the leading 64 dims) while the workgroup takes the (query, list) pairs of
-// its list in chunks: first every pair's destination and query slice are staged in LDS (all
-// loads independent), then the four waves take the chunk's pairs in turn.  Each query's sums are
-// formed exactly as the scan forms them (per-lane FMA chain, then the transposed group
-// reduction), so the scan's tests on them take the same decisions bit for bit.
-//   block 0: lane (sub, g) holds dims [g EPL, g EPL + EPL) of vectors c CPW + sub (c < MAXCH)
-//            and ends with vector g CPW + sub's sum;
-//   PRE:     lane (sub8, g8) holds codes [16 g8, 16 g8 + 16) of vectors 16 c + sub8 (c < 4)
-//            and ends with vector 16 g8 + sub8's sum, decoded with the tile's scale.
+// In-lane copies of the scan's sums.  The scan spreads a vector's 32-dim slice over G lanes
+// (lane j holding dims [j EPL, j EPL + EPL); with the FP8 pre-stage G = 4 lanes of 16 codes) and
+// adds the G lane partials with the transposed reduction, whose tree pairs lanes differing in
+// bit 2 (G = 8), then in bit 1, then in bit 0: for every vector the sum is
+// ((P0 + P4) + (P2 + P6)) + ((P1 + P5) + (P3 + P7)) for G = 8 and (P0 + P2) + (P1 + P3) for
+// G = 4 (each addition commutes).  A lane holding the whole slice forms the same partials (the
+// same FMA chains in the same order) and adds them in the same tree, so its sum equals the
+// scan's bit for bit.
+template <int G> __device__ inline float tree_sum(const float (&P)[G]) {
+  if constexpr (G == 8) return ((P[0] + P[4]) + (P[2] + P[6])) + ((P[1] + P[5]) + (P[3] + P[7]));
+  else return (P[0] + P[2]) + (P[1] + P[3]);
+}
+
+// One workgroup per stored tile; lane = stored vector, which stays in registers (dim block 0, or
+// with PRE the FP8 codes of the leading 64 dims) while the workgroup takes the (query, list)
+// pairs of its list in chunks: first every pair's destination and query slice are staged in LDS
+// (independent loads), then the four waves take the chunk's pairs in turn, reading the query
+// slice as LDS broadcasts and adding each vector's partials in the scan's tree (no cross-lane
+// reduction).
 constexpr int kS1Threads = 256;
 template <int ST, bool PRE>
 __global__ __launch_bounds__(kS1Threads) void stage1_lists_kernel(Stage1Args a) {
   using S = Store<ST>;
   constexpr int EPL = 16 / S::kBytes;
-  constexpr int G = PRE ? 4 : kBlockDims / EPL;
-  constexpr int CPW = 64 / G;
-  constexpr int MAXCH = 64 / CPW;
-  constexpr int NV = PRE ? 16 : EPL;                        // values per lane per vector slot
+  constexpr int G = PRE ? 4 : kBlockDims / EPL;             // the scan's lanes per slice
+  constexpr int NP = PRE ? 16 : EPL;                        // values per lane partial
   constexpr int SLICE = kBlockDims * S::kBytes;
   constexpr int64_t BLOCK_BYTES = (int64_t)kTile * SLICE;
   constexpr int QD = PRE ? kFp8Lead : kBlockDims;           // query dims per pair
-  constexpr int CHUNK = PRE ? 128 : 256;                    // pairs staged at once
+  constexpr int CHUNK = PRE ? 32 : 64;                      // pairs staged at once (8 KiB of LDS)
   __shared__ __align__(16) float s_qv[CHUNK * QD];
   __shared__ int64_t s_dst[CHUNK];
   const int64_t t = blockIdx.x;
@@ -1327,34 +1376,29 @@ __global__ __launch_bounds__(kS1Threads) void stage1_lists_kernel(Stage1Args a) 
   const int pb = a.lstart[l], pe = a.lstart[l + 1];
   if (pb >= pe) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int g = lane % G, sub = lane / G;
   const int tl = (int)(t - a.tile_off[l]);                 // tile within its list
   const int cnt = min(kTile, a.list_len[l] - tl * kTile);  // stored vectors in this tile
-  float f[MAXCH][NV];
+  float f[G][NP];
   float sc = 1.f;
   if constexpr (PRE) {
     sc = a.scale8[t];
-    const unsigned char *p8 = a.base8 + t * (kTile * kFp8Lead) + g * 16;
+    const uint4 *p8 = reinterpret_cast<const uint4 *>(a.base8 + t * (kTile * kFp8Lead) + lane * kFp8Lead);
 #pragma unroll
-    for (int c = 0; c < MAXCH; ++c) {
-      const uint4 v = *reinterpret_cast<const uint4 *>(p8 + (c * CPW + sub) * kFp8Lead);
+    for (int k = 0; k < G; ++k) {
+      const uint4 v = p8[k];
       const uint32_t w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
-      for (int i = 0; i < 4; ++i) e4m3x4_to_f32(w[i], &f[c][4 * i]);
+      for (int i = 0; i < 4; ++i) e4m3x4_to_f32(w[i], &f[k][4 * i]);
     }
   } else {
-    const unsigned char *tp = reinterpret_cast<const unsigned char *>(a.base) + t * a.nblocks * BLOCK_BYTES + g * 16;
+    const uint4 *tp = reinterpret_cast<const uint4 *>(reinterpret_cast<const unsigned char *>(a.base) +
+                                                      t * a.nblocks * BLOCK_BYTES + lane * SLICE);
 #pragma unroll
-    for (int c = 0; c < MAXCH; ++c) {
-      const uint4 v = *reinterpret_cast<const uint4 *>(tp + (c * CPW + sub) * SLICE);
-      S::unpack(v, f[c]);
-    }
+    for (int k = 0; k < G; ++k) S::unpack(tp[k], f[k]);
   }
-  const int mine = g * CPW + sub;   // the vector this lane's sum belongs to
   for (int c0 = pb; c0 < pe; c0 += CHUNK) {
     const int n = min(CHUNK, pe - c0);
     __syncthreads();                 // the previous chunk's slices are no longer read
-    // stage: destinations, then the query slices (QD / 4 float4 per pair)
     for (int j = tid; j < n; j += kS1Threads) {
       const int pidx = a.lpair[c0 + j];
       const int64_t q = pidx / a.p_stride;
@@ -1368,42 +1412,26 @@ __global__ __launch_bounds__(kS1Threads) void stage1_lists_kernel(Stage1Args a) 
     __syncthreads();
     for (int j = wave; j < n; j += kS1Threads / 64) {
       const float *qs = s_qv + j * QD;
-      float part[MAXCH];
-      if constexpr (PRE) {
-        float q8[16];
+      float P[G];
 #pragma unroll
-        for (int e = 0; e < 16; ++e) q8[e] = qs[g * 16 + e];
+      for (int k = 0; k < G; ++k) {
+        float qk[NP];
 #pragma unroll
-        for (int c = 0; c < MAXCH; ++c) {
-          float acc = 0.f;
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-              const float d = f[c][4 * i + e] * sc - q8[4 * i + e];
-              acc = fmaf(d, d, acc);
-            }
-          }
-          part[c] = acc;
+        for (int e4 = 0; e4 < NP / 4; ++e4) {
+          const float4 x = *reinterpret_cast<const float4 *>(qs + k * NP + 4 * e4);
+          qk[4 * e4] = x.x; qk[4 * e4 + 1] = x.y; qk[4 * e4 + 2] = x.z; qk[4 * e4 + 3] = x.w;
         }
-      } else {
-        float qv[EPL];
+        float acc = 0.f;
 #pragma unroll
-        for (int e = 0; e < EPL; ++e) qv[e] = qs[g * EPL + e];
-#pragma unroll
-        for (int c = 0; c < MAXCH; ++c) {
-          float acc = 0.f;
-#pragma unroll
-          for (int e = 0; e < EPL; ++e) {
-            const float d = f[c][e] - qv[e];
-            acc = fmaf(d, d, acc);
-          }
-          part[c] = acc;
+        for (int e = 0; e < NP; ++e) {
+          const float d = PRE ? f[k][e] * sc - qk[e] : f[k][e] - qk[e];
+          acc = fmaf(d, d, acc);
         }
+        P[k] = acc;
       }
-      const float tot = transpose_sum<G>(part, g);
-      const int64_t o = s_dst[j] + mine;
-      if (mine < cnt && o < a.e1_cap) a.e1[o] = tot;
+      const float tot = tree_sum<G>(P);
+      const int64_t o = s_dst[j] + lane;
+      if (lane < cnt && o < a.e1_cap) a.e1[o] = tot;
     }
   }
 }
