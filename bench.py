@@ -59,8 +59,7 @@ CONFIGS = {
     # 1M x 128 integer descriptors, FP32, IVF 4096, 10,000 queries, K = 10 and 100 (the headline);
     # correction tables at K_c = 10 and 100
     "sift1m": dict(data="sift1m", nlist=4096, storage="f32", rotation="f32", k=10, nprobes=NPROBES,
-                   k100_nprobes=[48, 64, 96, 128], fit=dict(calib_k_extra=(100,)),
-                   serve=("frac", [0.25, 0.5])),
+                   k100_nprobes=[48, 64, 96, 128], fit=dict(calib_k_extra=(100,)), serve=None),
     # the same data and index with the FP8 E4M3 pre-stage over the leading 64 rotated dims
     # (64 B per candidate instead of the 128 B FP32 first stage; FP32 stages after it)
     "sift1m-fp8": dict(data="sift1m", nlist=4096, storage="f32", rotation="f32", fp8=64, k=10,
@@ -815,7 +814,7 @@ def main():
     ap.add_argument("--serve-rates", default="",
                     help="offered loads of the serving phase (override; fractions of the peak QPS "
                          "or absolute queries/s, as the workload defines)")
-    ap.add_argument("--serve-seconds", type=float, default=4.0)
+    ap.add_argument("--serve-seconds", type=float, default=8.0)
     ap.add_argument("--no-rp", action="store_true",
                     help="skip the PCA-vs-random-projection comparison on the headline workload")
     ap.add_argument("--ablation", action="store_true",

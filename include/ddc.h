@@ -331,6 +331,17 @@ ddc_status ddc_search_estimate(const ddc_index *ix, const float *queries, int64_
 ddc_status ddc_debug_intermediates(const ddc_index *ix, const float *queries, int64_t nq,
                                    int32_t nprobe, float *q_rot, int32_t *probes);
 
+/* Allocation failure injection, for tests of the error paths: spec "alloc:<n>" makes the n-th
+ * device or pinned-host allocation the library makes from now on (any thread, any call) fail
+ * before the runtime is asked, so that call returns DDC_ENOMEM having released what it had
+ * allocated (a failed fit / import / load leaves *out = NULL; a failed search leaves the index
+ * as it was); "alloc:0" turns it off.  The environment variable DDC_FAULT=alloc:<n>, read once
+ * when the library first allocates, has the same effect.  EINVAL for another spec. */
+ddc_status ddc_set_fault(const char *spec);
+/* Device and pinned-host allocations the library holds right now (count; bytes = the device
+ * ones), for leak checks after failed calls.  EINVAL on a NULL argument. */
+ddc_status ddc_live_allocations(int64_t *count, int64_t *bytes);
+
 /* Per-kernel timing of the search pipeline with HIP events recorded on the launch stream
  * around every kernel of every later search on this index (enable = 1) or none (0).
  * Kernels: 0 query rotation (A1), 1 coarse centroid distances (A2), 2 probe selection (A2),

@@ -27,7 +27,7 @@ SYMBOLS = ["ddc_fit_params_default", "ddc_fit", "ddc_import", "ddc_export", "ddc
            "ddc_server_get_stats", "ddc_server_destroy", "ddc_set_launch", "ddc_get_launch",
            "ddc_scan_variant", "ddc_save", "ddc_load", "ddc_set_ads_epsilon", "ddc_set_bsar_multiplier",
            "ddc_search_estimate", "ddc_correction_pq", "ddc_search_device_noalloc",
-           "ddc_search_device_noalloc_bytes"]
+           "ddc_search_device_noalloc_bytes", "ddc_set_fault", "ddc_live_allocations"]
 
 
 class FitParams(C.Structure):
@@ -132,6 +132,8 @@ def load_library():
                                           vp, vp, vp, vp]
         lib.ddc_search_device_noalloc.argtypes = lib.ddc_search_device.argtypes
         lib.ddc_search_device_noalloc_bytes.argtypes = []
+        lib.ddc_set_fault.argtypes = [C.c_char_p]
+        lib.ddc_live_allocations.argtypes = [C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         lib.ddc_debug_intermediates.argtypes = [vp, vp, i64, i32, vp, vp]
         lib.ddc_search_estimate.argtypes = [vp, vp, i64, i32, i32, i32, C.c_int, vp, vp]
         lib.ddc_correction_pq.argtypes = [vp, i32, f64, vp, vp, vp]
@@ -161,6 +163,19 @@ def load_library():
         lib.ddc_search_device_noalloc_bytes.restype = C.c_size_t
         _LIB = lib
         return lib
+
+
+def set_fault(spec: str):
+    """Inject an allocation failure ("alloc:<n>": the n-th allocation from now fails; "alloc:0"
+    turns it off) -- for tests of the error paths."""
+    _check(load_library().ddc_set_fault(spec.encode()))
+
+
+def live_allocations() -> tuple:
+    """(count, device bytes) of the allocations the library holds now."""
+    n, b = C.c_int64(), C.c_int64()
+    _check(load_library().ddc_live_allocations(C.byref(n), C.byref(b)))
+    return n.value, b.value
 
 
 def _check(rc):

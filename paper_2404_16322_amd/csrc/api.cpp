@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <atomic>
 #include <cstdlib>
 #include <cstring>
 #include <functional>
@@ -186,6 +187,45 @@ static double normal_quantile(double p) {
 }
 
 static thread_local std::string g_err;
+
+// ---- allocation fault injection -------------------------------------------------------
+namespace {
+std::atomic<int64_t> g_fault_at{0};     // the allocation that fails (1-based), 0 = none
+std::atomic<int64_t> g_fault_seen{0};   // allocations checked since it was set
+std::once_flag g_fault_env;
+
+bool parse_fault(const char *spec, int64_t *n) {
+  if (!spec) return false;
+  if (std::strncmp(spec, "alloc:", 6) != 0) return false;
+  char *end = nullptr;
+  const long long v = std::strtoll(spec + 6, &end, 10);
+  if (end == spec + 6 || *end != '\0' || v < 0) return false;
+  *n = v;
+  return true;
+}
+}  // namespace
+
+std::atomic<int64_t> g_live_count{0}, g_live_bytes{0};
+
+// the environment's setting, read once (before the first check or the first ddc_set_fault)
+void fault_env_once() {
+  std::call_once(g_fault_env, [] {
+    int64_t n = 0;
+    if (parse_fault(std::getenv("DDC_FAULT"), &n)) { g_fault_seen = 0; g_fault_at = n; }
+  });
+}
+
+void ddc::alloc_track(int64_t count, int64_t bytes) {
+  g_live_count += count;
+  g_live_bytes += bytes;
+}
+
+void ddc::fault_check_alloc() {
+  fault_env_once();
+  const int64_t at = g_fault_at.load();
+  if (at > 0 && ++g_fault_seen == at)
+    throw DdcError(DDC_ENOMEM, "allocation failed (injected fault: allocation " + std::to_string(at) + ")");
+}
 
 ddc_status ddc::set_err(ddc_status st, const char *fmt, ...) {
   char buf[512];
@@ -1658,6 +1698,23 @@ ddc_status ddc_debug_intermediates(const ddc_index *ixc, const float *queries, i
   HIPC(hipStreamSynchronize(sh.s));
   return DDC_OK;
   GUARD_END
+}
+
+ddc_status ddc_live_allocations(int64_t *count, int64_t *bytes) {
+  if (!count || !bytes) return set_err(DDC_EINVAL, "NULL argument");
+  *count = g_live_count.load();
+  *bytes = g_live_bytes.load();
+  return DDC_OK;
+}
+
+ddc_status ddc_set_fault(const char *spec) {
+  int64_t n = 0;
+  if (!parse_fault(spec, &n)) return set_err(DDC_EINVAL, "fault spec must be \"alloc:<n>\" with n >= 0");
+  fault_env_once();
+  g_fault_at = 0;
+  g_fault_seen = 0;
+  g_fault_at = n;
+  return DDC_OK;
 }
 
 ddc_status ddc_set_kernel_timing(ddc_index *ix, int enable) {

@@ -25,6 +25,15 @@ constexpr size_t kMaxLds = 160 * 1024;  // LDS per workgroup on gfx950
 
 enum StoreType : int { ST_F32 = 0, ST_F16 = 1, ST_BF16 = 2 };
 
+// Allocation fault injection (tests): DDC_FAULT=alloc:<n> in the environment, or
+// ddc_set_fault("alloc:<n>"), makes the n-th device or pinned-host allocation from then on fail
+// as out of memory before the runtime is called (0 / unset: never).  Called before every such
+// allocation; throws the library's out-of-memory error on the injected one.
+void fault_check_alloc();
+// Live device / pinned-host allocations of the library (count, bytes): every successful
+// allocation adds, every release subtracts (tests check that failed calls leave nothing behind).
+void alloc_track(int64_t count, int64_t bytes);
+
 // Arguments of the pruned scan (A3) + top-K merge (A4) + finalize (A5) kernel.
 struct ScanArgs {
   const float *qrot;       // [nq x q_stride] rotated queries, zero beyond D

@@ -93,13 +93,16 @@ void launch_pq_encode(const void *base, int store, int32_t nblocks, int64_t tota
   if (dsub < 1 || dsub > kMaxDsub || M < 1 || M > 65535) throw std::invalid_argument("pq: bad M / dsub");
   const int64_t nslots = total_tiles * kTile;
   float *dmin = nullptr;
+  fault_check_alloc();
   if (hipMallocAsync(reinterpret_cast<void **>(&dmin), (size_t)nslots * M * 4, s) != hipSuccess)
     throw std::runtime_error("pq: scratch allocation failed");
+  alloc_track(1, (int64_t)nslots * M * 4);
   hipLaunchKernelGGL(pq_encode_kernel, dim3((unsigned)total_tiles, (unsigned)M), dim3(kTile), 0, s, base,
                      store, nblocks, perm, books, M, dsub, codes, dmin);
   hipLaunchKernelGGL(pq_err_kernel, dim3((unsigned)((nslots + 255) / 256)), dim3(256), 0, s, dmin, nslots, M,
                      err);
   (void)hipFreeAsync(dmin, s);
+  alloc_track(-1, -(int64_t)nslots * M * 4);
 }
 
 __global__ void pq_features64_kernel(const double *qrot, int32_t D, const void *base, int store,

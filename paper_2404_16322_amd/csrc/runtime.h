@@ -61,11 +61,18 @@ struct DevBuf {
   DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
   void alloc(size_t b) {
     release();
-    if (b) HIPC(hipMalloc(&p, b));
+    if (b) {
+      fault_check_alloc();
+      HIPC(hipMalloc(&p, b));
+      alloc_track(1, (int64_t)b);
+    }
     bytes = b;
   }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) {
+      (void)hipFree(p);
+      alloc_track(-1, -(int64_t)bytes);
+    }
     p = nullptr;
     bytes = 0;
   }
@@ -107,20 +114,32 @@ inline void set_pool_retain(int dev) {
 struct AsyncBuf {
   void *p = nullptr;
   hipStream_t s = nullptr;
+  size_t n = 0;
   AsyncBuf(size_t bytes, hipStream_t st) : s(st) {
-    if (bytes) HIPC(hipMallocAsync(&p, bytes, st));
+    if (bytes) {
+      fault_check_alloc();
+      HIPC(hipMallocAsync(&p, bytes, st));
+      n = bytes;
+      alloc_track(1, (int64_t)n);
+    }
   }
   AsyncBuf(const AsyncBuf &) = delete;
   AsyncBuf &operator=(AsyncBuf &&o) noexcept {
     if (this != &o) {
-      if (p) (void)hipFreeAsync(p, s);
-      p = o.p; s = o.s; o.p = nullptr;
+      drop();
+      p = o.p; s = o.s; n = o.n; o.p = nullptr; o.n = 0;
     }
     return *this;
   }
-  AsyncBuf(AsyncBuf &&o) noexcept : p(o.p), s(o.s) { o.p = nullptr; }
-  ~AsyncBuf() {
-    if (p) (void)hipFreeAsync(p, s);
+  AsyncBuf(AsyncBuf &&o) noexcept : p(o.p), s(o.s), n(o.n) { o.p = nullptr; o.n = 0; }
+  ~AsyncBuf() { drop(); }
+  void drop() {
+    if (p) {
+      (void)hipFreeAsync(p, s);
+      alloc_track(-1, -(int64_t)n);
+    }
+    p = nullptr;
+    n = 0;
   }
   template <class T> T *as() const { return reinterpret_cast<T *>(p); }
 };

@@ -83,13 +83,26 @@ struct ddc_server {
   }
 };
 
+// pinned host buffer of n bytes (counted like the device allocations)
+template <class T> static void host_alloc(T **p, size_t n) {
+  fault_check_alloc();
+  HIPC(hipHostMalloc((void **)p, n, 0));
+  alloc_track(1, 0);   // counted, not in the device bytes
+}
+template <class T> static void host_free(T *&p) {
+  if (!p) return;
+  (void)hipHostFree(p);
+  alloc_track(-1, 0);
+  p = nullptr;
+}
+
 static void release_slot(Slot &sl) {
-  if (sl.h_q) (void)hipHostFree(sl.h_q);
-  if (sl.h_k) (void)hipHostFree(sl.h_k);
-  if (sl.h_np) (void)hipHostFree(sl.h_np);
-  if (sl.h_off) (void)hipHostFree(sl.h_off);
-  if (sl.h_ids) (void)hipHostFree(sl.h_ids);
-  if (sl.h_d) (void)hipHostFree(sl.h_d);
+  host_free(sl.h_q);
+  host_free(sl.h_k);
+  host_free(sl.h_np);
+  host_free(sl.h_off);
+  host_free(sl.h_ids);
+  host_free(sl.h_d);
   if (sl.done) (void)hipEventDestroy(sl.done);
   if (sl.stream) (void)hipStreamDestroy(sl.stream);
   sl.d_q.release(); sl.d_k.release(); sl.d_np.release();
@@ -256,12 +269,12 @@ ddc_status ddc_server_create(const ddc_index *ixc, const ddc_server_params *p, d
       sl.d_off.alloc((mb + 1) * 8);
       sl.d_ids.alloc(mb * kMaxK * 8);
       sl.d_d.alloc(mb * kMaxK * 4);
-      HIPC(hipHostMalloc((void **)&sl.h_q, mb * ix->D * 4, 0));
-      HIPC(hipHostMalloc((void **)&sl.h_k, mb * 4, 0));
-      HIPC(hipHostMalloc((void **)&sl.h_np, mb * 4, 0));
-      HIPC(hipHostMalloc((void **)&sl.h_off, (mb + 1) * 8, 0));
-      HIPC(hipHostMalloc((void **)&sl.h_ids, mb * kMaxK * 8, 0));
-      HIPC(hipHostMalloc((void **)&sl.h_d, mb * kMaxK * 4, 0));
+      host_alloc(&sl.h_q, mb * ix->D * 4);
+      host_alloc(&sl.h_k, mb * 4);
+      host_alloc(&sl.h_np, mb * 4);
+      host_alloc(&sl.h_off, (mb + 1) * 8);
+      host_alloc(&sl.h_ids, mb * kMaxK * 8);
+      host_alloc(&sl.h_d, mb * kMaxK * 4);
     }
     {
       // grow the stream-ordered pool once for n_streams batches of max_batch queries (it keeps
@@ -272,9 +285,33 @@ ddc_status ddc_server_create(const ddc_index *ixc, const ddc_server_params *p, d
       for (auto &sl : s->slots) HIPC(hipStreamSynchronize(sl.stream));
     }
     for (auto &sl : s->slots) HIPC(hipStreamSynchronize(sl.stream));
+    // one small search per stream with the server's significance and test, so the first
+    // requests find the correction rows uploaded, the kernels they launch loaded and the pool
+    // grown for a batch of that shape (zero queries: finite, valid input)
+    {
+      const int wq = (int)std::min<int64_t>(mb, 256);
+      const int wnp = std::min(ix->nlist, 16), wk = 10;
+      for (auto &sl : s->slots) {
+        HIPC(hipMemsetAsync(sl.d_q.p, 0, (size_t)wq * ix->D * 4, sl.stream));
+        std::vector<int32_t> hk(wq, wk), hn(wq, wnp);
+        std::vector<int64_t> ho(wq + 1);
+        for (int i = 0; i <= wq; ++i) ho[i] = (int64_t)i * wk;
+        HIPC(hipMemcpyAsync(sl.d_k.p, hk.data(), (size_t)wq * 4, hipMemcpyHostToDevice, sl.stream));
+        HIPC(hipMemcpyAsync(sl.d_np.p, hn.data(), (size_t)wq * 4, hipMemcpyHostToDevice, sl.stream));
+        HIPC(hipMemcpyAsync(sl.d_off.p, ho.data(), (size_t)(wq + 1) * 8, hipMemcpyHostToDevice, sl.stream));
+        for (int nq : {wq, 1})
+          search_device(ix, sl.d_q.as<float>(), nq, sl.d_k.as<int32_t>(), 0, wk, sl.d_np.as<int32_t>(), 0,
+                        wnp, p->significance, p->mode, sl.d_off.as<int64_t>(), sl.d_ids.as<int64_t>(),
+                        sl.d_d.as<float>(), nullptr, sl.stream, nullptr, nullptr, /*may_tune=*/false);
+        HIPC(hipStreamSynchronize(sl.stream));   // the pageable staging above stays alive until here
+      }
+    }
   } catch (const DdcError &e) {
     for (auto &sl : s->slots) release_slot(sl);
     return set_err(e.st, "%s", e.what());
+  } catch (const std::exception &e) {
+    for (auto &sl : s->slots) release_slot(sl);
+    return set_err(DDC_EDEVICE, "%s", e.what());
   }
   s->th = std::thread(run_loop, s.get());
   *out = s.release();

@@ -226,3 +226,16 @@ def test_oracle_and_product_share_no_code():
             code = "\n".join(l for l in txt.splitlines() if not l.lstrip().startswith("#"))
             code = re.sub(r'"""(?:.|\n)*?"""', "", code)
             assert not use_pkg.search(code), f
+
+
+def test_fault_injection_spec_and_live_counts_without_device(lib):
+    """ddc_set_fault accepts only "alloc:<n>" (n >= 0) and the live-allocation count starts empty
+    (no device is touched by either)."""
+    for bad in (b"", b"alloc", b"alloc:", b"alloc:-1", b"alloc:3x", b"free:1", None):
+        assert lib.ddc_set_fault(bad) == -1
+    assert lib.ddc_set_fault(b"alloc:7") == 0
+    assert lib.ddc_set_fault(b"alloc:0") == 0
+    n, b = C.c_int64(-1), C.c_int64(-1)
+    assert lib.ddc_live_allocations(C.byref(n), C.byref(b)) == 0
+    assert (n.value, b.value) == (0, 0)
+    assert lib.ddc_live_allocations(None, None) == -1
