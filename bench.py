@@ -354,6 +354,8 @@ def run_workload(wl, args, headline):
     fitp = dict(cfg.get("fit", {}))
     if headline and args.block_b:
         fitp["block_b"] = args.block_b
+    if headline and args.lag >= 0:
+        fitp["lag_l"] = args.lag
     ix = Index.fit(w["base"], w["calib"], nlist=nlist, seed=spec["cfg"], storage=cfg["storage"],
                    rotation=cfg["rotation"], fp8_lead_dims=cfg.get("fp8", 0), **fitp)
     torch.cuda.synchronize()
@@ -833,6 +835,8 @@ def main():
                          "operating point only (no launch-shape sweep, no host-copy timing)")
     ap.add_argument("--block-b", type=int, default=0,
                     help="threshold refresh block B of the fitted index (default: the workload's)")
+    ap.add_argument("--lag", type=int, default=-1,
+                    help="threshold lag L of the fitted index in blocks (default: the workload's)")
     ap.add_argument("--launch", default="",
                     help="force the scan's launch shape: waves,lookahead,persistent,two_phase "
                          "(e.g. 1,1,0,1), instead of tuning it")

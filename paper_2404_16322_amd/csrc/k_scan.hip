@@ -144,8 +144,9 @@ __host__ __device__ inline size_t align16(size_t b) { return (b + 15) & ~(size_t
 // res: the alive lists also carry each survivor's running sum of squared coordinates;
 // lut_floats: the query's quantization lookup table (BSA-O), 0 when unused
 // lag: the wave keeps the taus after its query's last lag + 1 blocks (lag > 0)
+// lp: lag-parallel (each of the W waves scans a whole block; one survivor list per wave)
 __host__ __device__ inline Lds lds_layout(int Dp, int kmax, int block_b, int W, bool res,
-                                          int lut_floats, int p_stride, int lag) {
+                                          int lut_floats, int p_stride, int lag, bool lp = false) {
   Lds l;
   size_t o = 0;
   l.q = o; o += align16((size_t)Dp * 4);
@@ -153,11 +154,12 @@ __host__ __device__ inline Lds lds_layout(int Dp, int kmax, int block_b, int W, 
   l.meta = o; o += p_stride <= kMetaCap ? align16((size_t)3 * p_stride * 4) : 0;
   l.td = o; o += align16((size_t)2 * kmax * 4);
   l.ti = o; o += align16((size_t)2 * kmax * 4);
-  l.sd = o; o += align16((size_t)block_b * 4);
-  l.si = o; o += align16((size_t)block_b * 4);
-  l.cnt = o; o += 16;
+  const int lists = lp ? W : 1;
+  l.sd = o; o += align16((size_t)lists * block_b * 4);
+  l.si = o; o += align16((size_t)lists * block_b * 4);
+  l.cnt = o; o += lp ? 32 : 16;   // lp: the four waves' survivor counts after the first four
   l.query_bytes = o;
-  const int seg = W == 1 ? block_b : kTile;   // candidates one wave scans per segment
+  const int seg = (W == 1 || lp) ? block_b : kTile;   // candidates one wave scans per segment
   o = 0;
   l.ac = o; o += align16((size_t)2 * seg * 2);
   l.ae = o; o += align16((size_t)2 * seg * 4);
@@ -169,8 +171,9 @@ __host__ __device__ inline Lds lds_layout(int Dp, int kmax, int block_b, int W, 
   return l;
 }
 __host__ __device__ inline size_t scan_lds_bytes(int Dp, int kmax, int block_b, int W, bool res,
-                                                  int lut_floats, int p_stride, int lag) {
-  const Lds l = lds_layout(Dp, kmax, block_b, W, res, lut_floats, p_stride, lag);
+                                                  int lut_floats, int p_stride, int lag,
+                                                  bool lp = false) {
+  const Lds l = lds_layout(Dp, kmax, block_b, W, res, lut_floats, p_stride, lag, lp);
   return (size_t)(4 / W) * l.query_bytes + 4 * l.wave_bytes;
 }
 
@@ -184,8 +187,13 @@ __host__ __device__ inline size_t scan_lds_bytes(int Dp, int kmax, int block_b, 
 // e_d + ||x_r||^2 + ||q'_r||^2 (C1 - C2).  PQ: the quantization test of BSA-O (asymmetric
 // distance from the query's lookup table in LDS and the candidate's codes, with its
 // quantization error as second feature) before the stages, whose tests are then lossless.
+// LP (lag-parallel, W = 4 with LAG and lag >= 3): the blocks of a query go to its four waves in
+// turn, each wave scanning a whole block (every block of a group of four consecutive blocks is
+// tested against a tau from before the group, which the lag provides); the group's survivor
+// lists are then merged into the queue in block order, recording every block's tau, so the
+// results are those of the one-wave lagged scan bit for bit.
 template <int ST, bool PRUNE, bool LOOK, int W, bool PRE, bool RES, bool EST = false, bool PQ = false,
-          bool LAG = false, bool LM = false>
+          bool LAG = false, bool LM = false, bool LP = false>
 __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4, 8))) void scan_kernel(ScanArgs a) {
   using S = Store<ST>;
   constexpr int EPL = 16 / S::kBytes;          // elements per lane load
@@ -214,8 +222,10 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
   const int Dp = nb * kBlockDims;
   const int B = a.block_b;
   const int KM = a.k_max;
-  const int SEG = W == 1 ? B : kTile;
-  const Lds L = lds_layout(Dp, KM, B, W, RES, PQ ? a.pq_m * 256 + Dp : 0, a.p_stride, LAG ? a.lag : 0);
+  static_assert(!LP || (W == 4 && LAG), "lag-parallel scans need four waves and a lag");
+  constexpr bool WHOLE = W == 1 || LP;       // a wave scans whole blocks
+  const int SEG = WHOLE ? B : kTile;
+  const Lds L = lds_layout(Dp, KM, B, W, RES, PQ ? a.pq_m * 256 + Dp : 0, a.p_stride, LAG ? a.lag : 0, LP);
   unsigned char *ql = smem + (size_t)qs * L.query_bytes;
   unsigned char *wl = smem + (size_t)QPW * L.query_bytes + (size_t)wave * L.wave_bytes;
   float *s_q = reinterpret_cast<float *>(ql + L.q);
@@ -371,7 +381,10 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
   int32_t tau_id = 0x7FFFFFFF;
   int bidx = 0;   // blocks of this query done (the lagged tau's index)
   const unsigned long long lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-  int ns = 0;   // W = 1: survivors of the current block (wave-uniform)
+  int ns = 0;   // W = 1 and LP: the wave's survivors of the current block (wave-uniform)
+  // LP: each wave's survivors go to a list of its own
+  float *sdw = LP ? s_sd + wsub * B : s_sd;
+  int32_t *siw = LP ? s_si + wsub * B : s_si;
 
   // append the lanes with `take` to the block's survivor list
   auto append = [&](bool take, float ev, int32_t id) {
@@ -379,7 +392,7 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
     const int cnt = __popcll(bal);
     if (cnt == 0) return;
     int base;
-    if (W == 1) {
+    if (WHOLE) {
       base = ns;
       ns += cnt;
     } else {
@@ -389,9 +402,56 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
     }
     if (take) {
       const int pos = base + __popcll(bal & lt);
-      s_sd[pos] = ev;
-      s_si[pos] = id;
+      sdw[pos] = ev;
+      siw[pos] = id;
     }
+  };
+
+  // LP: merge the survivor lists of the group's n blocks (wave j scanned block g0 + j) into
+  // the queue in block order, recording the tau after each block in the ring; a candidate's
+  // rank is its place in the queue plus the survivors before it by (dis, id)
+  auto lp_merge = [&](int n) {
+    __syncthreads();                         // every wave's list and count are in LDS
+    const int g0 = (bidx - 1) & ~3;          // the group's first block
+    for (int j = 0; j < n; ++j) {
+      const int nsj = __builtin_amdgcn_readfirstlane(s_cnt[4 + j]);
+      if (nsj > 0) {
+        const float *sd = s_sd + j * B;
+        const int32_t *si = s_si + j * B;
+        const float *td = s_td + tin * KM;
+        const int32_t *ti = s_ti + tin * KM;
+        float *od = s_td + (tin ^ 1) * KM;
+        int32_t *oi = s_ti + (tin ^ 1) * KM;
+        for (int i = qt; i < tn + nsj; i += 64 * W) {
+          float d;
+          int32_t id;
+          int rank;
+          if (i < tn) {
+            d = td[i]; id = ti[i]; rank = i;
+          } else {
+            d = sd[i - tn]; id = si[i - tn];
+            int lo = 0, hi = tn;
+            while (lo < hi) {
+              const int mid = (lo + hi) >> 1;
+              if (lex_less(td[mid], ti[mid], d, id)) lo = mid + 1; else hi = mid;
+            }
+            rank = lo;
+          }
+          for (int k2 = 0; k2 < nsj; ++k2) rank += lex_less(sd[k2], si[k2], d, id) ? 1 : 0;
+          if (rank < K) { od[rank] = d; oi[rank] = id; }
+        }
+        __syncthreads();
+        tin ^= 1;
+        tn = min(K, tn + nsj);
+        if (tn == K) {
+          tau = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(s_td[tin * KM + K - 1])));
+          tau_id = __builtin_amdgcn_readfirstlane(s_ti[tin * KM + K - 1]);
+        }
+      }
+      if (lane == 0) s_th[(g0 + j) % (a.lag + 1)] = tn == K ? tau : INFINITY;
+    }
+    __builtin_amdgcn_wave_barrier();
+    __syncthreads();                         // the lists are free for the next group
   };
 
   // two-phase scan: the first e1 entry of the current list (its candidates follow in order)
@@ -425,8 +485,10 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
         tau_t = j >= 0 ? s_th[j % (a.lag + 1)] : INFINITY;
         tau_t = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, tau_t)));
       }
-      for (int s0 = (W == 1 ? 0 : wsub * kTile); s0 < blen; s0 += (W == 1 ? blen : W * kTile)) {
-      const int slen = W == 1 ? blen : min(kTile, blen - s0);
+      // LP: the block belongs to wave bidx % 4; the other waves skip it
+      const bool mine = !LP || (bidx & 3) == wsub;
+      for (int s0 = (WHOLE ? (mine ? 0 : blen) : wsub * kTile); s0 < blen; s0 += (WHOLE ? blen : W * kTile)) {
+      const int slen = WHOLE ? blen : min(kTile, blen - s0);
       const unsigned char *bbase = lbase + (int64_t)((bs + s0) / kTile) * nb * BLOCK_BYTES;
       const int32_t *bids = lids + bs + s0;
       const float *xnorm_seg = (RES || EST) ? a.xnorm + (int64_t)toff * kTile + bs + s0 : nullptr;
@@ -994,6 +1056,13 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
         }
       }
       }  // segments
+      if constexpr (LP) {
+        // the block's survivor count for the group merge, which follows the group's last block
+        if (mine && lane == 0) s_cnt[4 + wsub] = ns;
+        ++bidx;
+        if ((bidx & 3) == 0) lp_merge(4);
+        continue;
+      }
       // ---- merge: queue (sorted, tn) + survivors (ns) -> K smallest by (dis, id) ----
       int mt, mstep;
       if (W == 1) {
@@ -1093,6 +1162,7 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
       }
     }
   }
+  if (LP && (bidx & 3) != 0) lp_merge(bidx & 3);   // a last, incomplete group
 
   // ---- finalize: ascending (dis, id), original ids, padding ----
   const int64_t off = a.out_off ? a.out_off[q] : (int64_t)q * a.k_all;
@@ -1627,57 +1697,63 @@ static int resident_workgroups(const void *kern, size_t smem) {
 
 size_t scan_lds_request(const ScanArgs &a, int W) {
   return scan_lds_bytes(a.nblocks * kBlockDims, a.k_max, a.block_b, W, a.res != 0,
-                        a.pq_m > 0 ? a.pq_m * 256 + a.nblocks * kBlockDims : 0, a.p_stride, a.lag);
+                        a.pq_m > 0 ? a.pq_m * 256 + a.nblocks * kBlockDims : 0, a.p_stride, a.lag,
+                        lag_parallel(a, W));
 }
 
 template <int ST, bool P, bool LK, int W, bool PRE = false, bool RES = false, bool EST = false,
-          bool PQ = false, bool LG = false, bool LM = false>
+          bool PQ = false, bool LG = false, bool LM = false, bool LP = false>
 static void launch_variant(const ScanArgs &a, hipStream_t s) {
   const size_t smem = scan_lds_bytes(a.nblocks * kBlockDims, a.k_max, a.block_b, W, RES,
                                      PQ ? a.pq_m * 256 + a.nblocks * kBlockDims : 0, a.p_stride,
-                                     LG ? a.lag : 0);
+                                     LG ? a.lag : 0, LP);
   if (smem > kMaxLds) throw std::runtime_error("scan: LDS request exceeds 160 KiB");
   const int qpw = 4 / W;
-  const void *kern = reinterpret_cast<const void *>(&scan_kernel<ST, P, LK, W, PRE, RES, EST, PQ, LG, LM>);
+  const void *kern = reinterpret_cast<const void *>(&scan_kernel<ST, P, LK, W, PRE, RES, EST, PQ, LG, LM, LP>);
   int64_t grid = (a.nq + qpw - 1) / qpw;
   if (a.queue) {
     // W = 1: each wave takes its own slots, so the grid covers ceil(nq / 4) workgroups at most
     grid = std::min<int64_t>(grid, resident_workgroups(kern, smem));
     hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(64), 0, s, a.queue, (int64_t)1, 0);
   }
-  hipLaunchKernelGGL((scan_kernel<ST, P, LK, W, PRE, RES, EST, PQ, LG, LM>), dim3((unsigned)grid),
+  hipLaunchKernelGGL((scan_kernel<ST, P, LK, W, PRE, RES, EST, PQ, LG, LM, LP>), dim3((unsigned)grid),
                      dim3(kScanThreads), smem, s, a);
+}
+
+// one pruned kernel; with a lag of at least 3, four waves per query scan consecutive blocks in
+// parallel (lag-parallel) instead of splitting each block's tiles
+template <int ST, bool LK, int W, bool PRE, bool RES, bool PQ, bool LG>
+static void launch_pruned_w(const ScanArgs &a, hipStream_t s) {
+  if constexpr (LG && W == 4) {
+    if (a.lag >= kLagParallelMin) {
+      launch_variant<ST, true, LK, 4, PRE, RES, false, PQ, true, false, true>(a, s);
+      return;
+    }
+  }
+  launch_variant<ST, true, LK, W, PRE, RES, false, PQ, LG>(a, s);
+}
+
+template <int ST, bool LK, bool PRE, bool RES, bool PQ, bool LG>
+static void launch_pruned_lk(const ScanArgs &a, hipStream_t s) {
+  if (a.waves_per_query == 4) launch_pruned_w<ST, LK, 4, PRE, RES, PQ, LG>(a, s);
+  else launch_pruned_w<ST, LK, 1, PRE, RES, PQ, LG>(a, s);
 }
 
 // LG: the pruned kernels with a lagged threshold (lag > 0), a separate instantiation so that
 // the lag-free kernels carry none of its bookkeeping
 template <int ST, bool LG> static void launch_pruned(const ScanArgs &a, hipStream_t s) {
-  const bool w4 = a.waves_per_query == 4;
   if (a.pq_m > 0) {
-    if (a.lookahead) {
-      if (w4) launch_variant<ST, true, true, 4, false, false, false, true, LG>(a, s);
-      else launch_variant<ST, true, true, 1, false, false, false, true, LG>(a, s);
-    } else {
-      if (w4) launch_variant<ST, true, false, 4, false, false, false, true, LG>(a, s);
-      else launch_variant<ST, true, false, 1, false, false, false, true, LG>(a, s);
-    }
+    if (a.lookahead) launch_pruned_lk<ST, true, false, false, true, LG>(a, s);
+    else launch_pruned_lk<ST, false, false, false, true, LG>(a, s);
   } else if (a.res) {
-    if (w4) launch_variant<ST, true, false, 4, false, true, false, false, LG>(a, s);
-    else launch_variant<ST, true, false, 1, false, true, false, false, LG>(a, s);
+    launch_pruned_lk<ST, false, false, true, false, LG>(a, s);
   } else if (a.pre) {
-    if (a.lookahead) {
-      if (w4) launch_variant<ST, true, true, 4, true, false, false, false, LG>(a, s);
-      else launch_variant<ST, true, true, 1, true, false, false, false, LG>(a, s);
-    } else {
-      if (w4) launch_variant<ST, true, false, 4, true, false, false, false, LG>(a, s);
-      else launch_variant<ST, true, false, 1, true, false, false, false, LG>(a, s);
-    }
+    if (a.lookahead) launch_pruned_lk<ST, true, true, false, false, LG>(a, s);
+    else launch_pruned_lk<ST, false, true, false, false, LG>(a, s);
   } else if (a.lookahead) {
-    if (w4) launch_variant<ST, true, true, 4, false, false, false, false, LG>(a, s);
-    else launch_variant<ST, true, true, 1, false, false, false, false, LG>(a, s);
+    launch_pruned_lk<ST, true, false, false, false, LG>(a, s);
   } else {
-    if (w4) launch_variant<ST, true, false, 4, false, false, false, false, LG>(a, s);
-    else launch_variant<ST, true, false, 1, false, false, false, false, LG>(a, s);
+    launch_pruned_lk<ST, false, false, false, false, LG>(a, s);
   }
 }
 
