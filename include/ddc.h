@@ -361,12 +361,14 @@ ddc_status ddc_set_bsar_multiplier(ddc_index *ix, double m);
 /* Launch shape of the pruned scan (A3-A5).  None of these changes any result bit (every
  * candidate's partial distances are summed in the same order in every variant); they only
  * trade occupancy, latency and bytes read.  waves_per_query: 1 (one wavefront runs a query's
- * whole scan, four queries per workgroup) or 4 (a workgroup per query, the tiles of every
+ * whole scan, four queries per workgroup), 4 (a workgroup per query, the tiles of every
  * candidate block split over its four wavefronts; on an index with lag_l >= 3 instead the
- * lag-parallel scan: wavefront j scans the blocks b with b mod 4 = j, four blocks at once, each
- * tested against the lagged tau that is already known when its group of four starts, and the
- * group's survivors are merged in block order, so results and counters equal those of
- * waves_per_query = 1), 0 = tuned.  lookahead: 0 (one dim block
+ * lag-parallel scan below) or 2 (the lag-parallel scan with two wavefronts, on an index with
+ * lag_l >= 1; elsewhere, and in unpruned searches, as 1), 0 = tuned.  Lag-parallel scan with W
+ * wavefronts: wavefront j scans the blocks b with b mod W = j, W blocks at once, each tested
+ * against the lagged tau that is already known when its group of W starts, and the group's
+ * survivors are merged in block order, so results and counters equal those of
+ * waves_per_query = 1.  lookahead: 0 (one dim block
  * per dependent load), 1 (when few candidates are alive, one load covers up to 8 consecutive
  * dim blocks of each), -1 = tuned.  query_order: group queries with the same first list;
  * xcd_swizzle: give each XCD a contiguous query range (0 or 1 each).  Tuned values are picked

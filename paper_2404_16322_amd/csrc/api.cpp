@@ -67,6 +67,8 @@ static Variant fixed_variant(const ddc_index *ix, int64_t nq, int prune, int np_
 
 static Variant forced_or(const ddc_index *ix, Variant v, int kind, bool two_ok) {
   if (ix->waves_per_query) v[0] = ix->waves_per_query;
+  // two waves per query only as the lag-parallel scan (a pruned search on an index with L >= 1)
+  if (v[0] == 2 && !((kind & 1) && ix->L >= 1)) v[0] = 1;
   if (ix->lookahead >= 0) v[1] = ix->lookahead;
   if (ix->persistent >= 0) v[2] = ix->persistent;
   if (ix->two_phase >= 0) v[3] = ix->two_phase;
@@ -134,7 +136,7 @@ static void choose_variant(ddc_index *ix, ScanArgs &a, int np_max, hipStream_t s
         std::vector<Variant> cand;   // simplest shapes first; shapes whose LDS does not fit skipped
         for (int t2 : {0, 1})
           for (int p : {0, 1})
-            for (int w : {1, 4})
+            for (int w : {1, 2, 4})
               for (int l : {0, 1}) {
                 auto c = forced_or(ix, {w, l, p, t2}, kind, two_ok);
                 if (scan_lds_request(a, c[0]) > kMaxLds) continue;
@@ -1762,8 +1764,9 @@ ddc_status ddc_set_ads_epsilon(ddc_index *ix, double eps0) {
 
 ddc_status ddc_set_launch(ddc_index *ix, const ddc_launch_params *p) {
   if (!ix || !p) return set_err(DDC_EINVAL, "NULL argument");
-  if (p->waves_per_query != 0 && p->waves_per_query != 1 && p->waves_per_query != 4)
-    return set_err(DDC_EINVAL, "waves_per_query must be 0, 1 or 4");
+  if (p->waves_per_query != 0 && p->waves_per_query != 1 && p->waves_per_query != 2 &&
+      p->waves_per_query != 4)
+    return set_err(DDC_EINVAL, "waves_per_query must be 0, 1, 2 or 4");
   if (p->lookahead < -1 || p->lookahead > 1) return set_err(DDC_EINVAL, "lookahead must be -1, 0 or 1");
   if ((p->query_order != 0 && p->query_order != 1) || (p->xcd_swizzle != 0 && p->xcd_swizzle != 1))
     return set_err(DDC_EINVAL, "query_order and xcd_swizzle must be 0 or 1");

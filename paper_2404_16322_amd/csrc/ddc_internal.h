@@ -128,13 +128,12 @@ void launch_stage1_lists(const Stage1Args &a, int store, hipStream_t s);
 // norms ||y||^2 of the stored values from xnorm, ||q'||^2 in FP32), clamped at 0, written to
 // e1 in the layout of launch_stage1_lists.  qnorm: [nq] scratch.
 void launch_full_lists(const Stage1Args &a, const float *xnorm, float *qnorm, int store, hipStream_t s);
-// Lag-parallel scan: with a lag of at least this many blocks, every block of a group of four
-// consecutive blocks is tested against a tau known before the group starts, so with four waves
-// per query each wave scans one block of the group at once and the group's survivors are merged
-// in block order afterwards (results and counters equal the one-wave lagged scan's).
-constexpr int kLagParallelMin = 3;
+// Lag-parallel scan: with a lag of at least W - 1 blocks, every block of a group of W
+// consecutive blocks is tested against a tau known before the group starts, so with W = 2 or 4
+// waves per query each wave scans one block of the group at once and the group's survivors are
+// merged in block order afterwards (results and counters equal the one-wave lagged scan's).
 inline bool lag_parallel(const ScanArgs &a, int W) {
-  return W == 4 && a.prune && a.lag >= kLagParallelMin;
+  return a.prune && ((W == 4 && a.lag >= 3) || (W == 2 && a.lag >= 1));
 }
 // LDS bytes one workgroup of the scan needs with W waves per query (> kMaxLds: not launchable).
 size_t scan_lds_request(const ScanArgs &a, int W);

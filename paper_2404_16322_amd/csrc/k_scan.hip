@@ -174,7 +174,8 @@ __host__ __device__ inline size_t scan_lds_bytes(int Dp, int kmax, int block_b, 
                                                   int lut_floats, int p_stride, int lag,
                                                   bool lp = false) {
   const Lds l = lds_layout(Dp, kmax, block_b, W, res, lut_floats, p_stride, lag, lp);
-  return (size_t)(4 / W) * l.query_bytes + 4 * l.wave_bytes;
+  // lp: a workgroup of W waves for one query; otherwise four waves for 4 / W queries
+  return lp ? l.query_bytes + (size_t)W * l.wave_bytes : (size_t)(4 / W) * l.query_bytes + 4 * l.wave_bytes;
 }
 
 // W waves per query (W = 1: four queries per workgroup, no workgroup barrier at all; W = 4:
@@ -187,11 +188,12 @@ __host__ __device__ inline size_t scan_lds_bytes(int Dp, int kmax, int block_b, 
 // e_d + ||x_r||^2 + ||q'_r||^2 (C1 - C2).  PQ: the quantization test of BSA-O (asymmetric
 // distance from the query's lookup table in LDS and the candidate's codes, with its
 // quantization error as second feature) before the stages, whose tests are then lossless.
-// LP (lag-parallel, W = 4 with LAG and lag >= 3): the blocks of a query go to its four waves in
-// turn, each wave scanning a whole block (every block of a group of four consecutive blocks is
-// tested against a tau from before the group, which the lag provides); the group's survivor
-// lists are then merged into the queue in block order, recording every block's tau, so the
-// results are those of the one-wave lagged scan bit for bit.
+// LP (lag-parallel, W = 2 or 4 with LAG and lag >= W - 1; a workgroup of W waves runs one
+// query): the blocks of a query go to its W waves in turn, each wave scanning a whole block
+// (every block of a group of W consecutive blocks is tested against a tau from before the group,
+// which the lag provides); the group's survivor lists are then merged into the queue in block
+// order, recording every block's tau, so the results are those of the one-wave lagged scan bit
+// for bit.
 template <int ST, bool PRUNE, bool LOOK, int W, bool PRE, bool RES, bool EST = false, bool PQ = false,
           bool LAG = false, bool LM = false, bool LP = false>
 __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4, 8))) void scan_kernel(ScanArgs a) {
@@ -203,7 +205,7 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
   constexpr int GROUP = CPW * MAXCH;           // candidates per load group (64)
   constexpr int SLICE = kBlockDims * S::kBytes;            // bytes per vector slice
   constexpr int64_t BLOCK_BYTES = (int64_t)kTile * SLICE;  // bytes per tile dim-block
-  constexpr int QPW = 4 / W;                   // queries per workgroup
+  constexpr int QPW = LP ? 1 : 4 / W;          // queries per workgroup (LP: W waves, one query)
 
   extern __shared__ __align__(16) unsigned char smem[];
   const int lane = threadIdx.x & 63;
@@ -222,7 +224,8 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
   const int Dp = nb * kBlockDims;
   const int B = a.block_b;
   const int KM = a.k_max;
-  static_assert(!LP || (W == 4 && LAG), "lag-parallel scans need four waves and a lag");
+  static_assert(!LP || ((W == 2 || W == 4) && LAG), "lag-parallel scans need two or four waves and a lag");
+  constexpr int GM = W - 1;                  // LP: block index mod the group size
   constexpr bool WHOLE = W == 1 || LP;       // a wave scans whole blocks
   const int SEG = WHOLE ? B : kTile;
   const Lds L = lds_layout(Dp, KM, B, W, RES, PQ ? a.pq_m * 256 + Dp : 0, a.p_stride, LAG ? a.lag : 0, LP);
@@ -412,7 +415,7 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
   // rank is its place in the queue plus the survivors before it by (dis, id)
   auto lp_merge = [&](int n) {
     __syncthreads();                         // every wave's list and count are in LDS
-    const int g0 = (bidx - 1) & ~3;          // the group's first block
+    const int g0 = (bidx - 1) & ~GM;         // the group's first block
     for (int j = 0; j < n; ++j) {
       const int nsj = __builtin_amdgcn_readfirstlane(s_cnt[4 + j]);
       if (nsj > 0) {
@@ -486,7 +489,7 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
         tau_t = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, tau_t)));
       }
       // LP: the block belongs to wave bidx % 4; the other waves skip it
-      const bool mine = !LP || (bidx & 3) == wsub;
+      const bool mine = !LP || (bidx & GM) == wsub;
       for (int s0 = (WHOLE ? (mine ? 0 : blen) : wsub * kTile); s0 < blen; s0 += (WHOLE ? blen : W * kTile)) {
       const int slen = WHOLE ? blen : min(kTile, blen - s0);
       const unsigned char *bbase = lbase + (int64_t)((bs + s0) / kTile) * nb * BLOCK_BYTES;
@@ -1060,7 +1063,7 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
         // the block's survivor count for the group merge, which follows the group's last block
         if (mine && lane == 0) s_cnt[4 + wsub] = ns;
         ++bidx;
-        if ((bidx & 3) == 0) lp_merge(4);
+        if ((bidx & GM) == 0) lp_merge(W);
         continue;
       }
       // ---- merge: queue (sorted, tn) + survivors (ns) -> K smallest by (dis, id) ----
@@ -1162,7 +1165,7 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
       }
     }
   }
-  if (LP && (bidx & 3) != 0) lp_merge(bidx & 3);   // a last, incomplete group
+  if (LP && (bidx & GM) != 0) lp_merge(bidx & GM);   // a last, incomplete group
 
   // ---- finalize: ascending (dis, id), original ids, padding ----
   const int64_t off = a.out_off ? a.out_off[q] : (int64_t)q * a.k_all;
@@ -1677,7 +1680,7 @@ void launch_stage1_lists(const Stage1Args &a, int store, hipStream_t s) {
 }
 
 // Workgroups of this kernel that fit on the device at once (occupancy x compute units).
-static int resident_workgroups(const void *kern, size_t smem) {
+static int resident_workgroups(const void *kern, size_t smem, int threads = kScanThreads) {
   static std::mutex mtx;
   static std::map<std::tuple<const void *, size_t, int>, int> cache;
   int dev = 0;
@@ -1687,7 +1690,7 @@ static int resident_workgroups(const void *kern, size_t smem) {
   auto it = cache.find(key);
   if (it != cache.end()) return it->second;
   int per_cu = 0, cus = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kScanThreads, smem) != hipSuccess ||
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, smem) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     throw std::runtime_error("scan: occupancy query failed");
   const int r = std::max(1, per_cu) * std::max(1, cus);
@@ -1708,34 +1711,41 @@ static void launch_variant(const ScanArgs &a, hipStream_t s) {
                                      PQ ? a.pq_m * 256 + a.nblocks * kBlockDims : 0, a.p_stride,
                                      LG ? a.lag : 0, LP);
   if (smem > kMaxLds) throw std::runtime_error("scan: LDS request exceeds 160 KiB");
-  const int qpw = 4 / W;
+  const int qpw = LP ? 1 : 4 / W;
+  const int threads = LP ? 64 * W : kScanThreads;   // LP: the query's W waves alone
   const void *kern = reinterpret_cast<const void *>(&scan_kernel<ST, P, LK, W, PRE, RES, EST, PQ, LG, LM, LP>);
   int64_t grid = (a.nq + qpw - 1) / qpw;
   if (a.queue) {
     // W = 1: each wave takes its own slots, so the grid covers ceil(nq / 4) workgroups at most
-    grid = std::min<int64_t>(grid, resident_workgroups(kern, smem));
+    grid = std::min<int64_t>(grid, resident_workgroups(kern, smem, threads));
     hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(64), 0, s, a.queue, (int64_t)1, 0);
   }
   hipLaunchKernelGGL((scan_kernel<ST, P, LK, W, PRE, RES, EST, PQ, LG, LM, LP>), dim3((unsigned)grid),
-                     dim3(kScanThreads), smem, s, a);
+                     dim3(threads), smem, s, a);
 }
 
-// one pruned kernel; with a lag of at least 3, four waves per query scan consecutive blocks in
-// parallel (lag-parallel) instead of splitting each block's tiles
+// one pruned kernel; with a lag of at least W - 1 blocks, W = 2 or 4 waves per query scan
+// consecutive blocks in parallel (lag-parallel); W = 4 with a shorter lag splits each block's
+// tiles instead
 template <int ST, bool LK, int W, bool PRE, bool RES, bool PQ, bool LG>
 static void launch_pruned_w(const ScanArgs &a, hipStream_t s) {
-  if constexpr (LG && W == 4) {
-    if (a.lag >= kLagParallelMin) {
-      launch_variant<ST, true, LK, 4, PRE, RES, false, PQ, true, false, true>(a, s);
+  if constexpr (LG && W > 1) {
+    if (lag_parallel(a, W)) {
+      launch_variant<ST, true, LK, W, PRE, RES, false, PQ, true, false, true>(a, s);
       return;
     }
   }
-  launch_variant<ST, true, LK, W, PRE, RES, false, PQ, LG>(a, s);
+  if constexpr (W == 2) {
+    throw std::runtime_error("scan: two waves per query need a lagged threshold");
+  } else {
+    launch_variant<ST, true, LK, W, PRE, RES, false, PQ, LG>(a, s);
+  }
 }
 
 template <int ST, bool LK, bool PRE, bool RES, bool PQ, bool LG>
 static void launch_pruned_lk(const ScanArgs &a, hipStream_t s) {
   if (a.waves_per_query == 4) launch_pruned_w<ST, LK, 4, PRE, RES, PQ, LG>(a, s);
+  else if (LG && a.waves_per_query == 2) launch_pruned_w<ST, LK, 2, PRE, RES, PQ, LG>(a, s);
   else launch_pruned_w<ST, LK, 1, PRE, RES, PQ, LG>(a, s);
 }
 

@@ -12,7 +12,7 @@ from parity_util import artifacts, check_search, oracle_index, workload
 
 pytestmark = pytest.mark.gpu
 
-VARIANTS = [(w, la, p, t) for t in (0, 1) for p in (0, 1) for w in (1, 4) for la in (0, 1)]
+VARIANTS = [(w, la, p, t) for t in (0, 1) for p in (0, 1) for w in (1, 2, 4) for la in (0, 1)]
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -114,7 +114,7 @@ def test_lagged_residual_test_matches_oracle():
     g.set_bsar_multiplier(3.0)
     Q = w["queries"]
     res = []
-    for wv in (1, 4):
+    for wv in (1, 2, 4):
         for p in (0, 1):
             g.set_launch(waves_per_query=wv, lookahead=0, persistent=p)
             res.append(g.search(Q, 10, 8, 0.0, mode="bsar"))

@@ -1,9 +1,10 @@
-"""Lag-parallel scan on the GPU.  With a threshold lag L >= 3 (candidates of block b tested
-against the tau after block b - 1 - L), every block of a group of four consecutive blocks sees
-a tau that is known before the group starts.  Four wavefronts of a workgroup then scan the
-four blocks of a group at once and merge their survivors into the queue in block order; the
-merge is exact, so results and every work counter must equal those of the one-wavefront
-lagged scan bit for bit, and both match the oracle run with the same B and L."""
+"""Lag-parallel scan on the GPU.  With a threshold lag L (candidates of block b tested against
+the tau after block b - 1 - L) of at least W - 1 blocks, every block of a group of W consecutive
+blocks sees a tau that is known before the group starts.  W = 2 (L >= 1) or 4 (L >= 3)
+wavefronts of a workgroup then scan the W blocks of a group at once and merge their survivors
+into the queue in block order; the merge is exact, so results and every work counter must equal
+those of the one-wavefront lagged scan bit for bit, and both match the oracle run with the same
+B and L."""
 import numpy as np
 import pytest
 
@@ -13,7 +14,9 @@ from parity_util import artifacts, check_search, oracle_index, workload
 pytestmark = pytest.mark.gpu
 
 ONE_WAVE = [(1, la, p, t) for t in (0, 1) for p in (0, 1) for la in (0, 1)]
-LAG_PARALLEL = [(4, la, p, t) for t in (0, 1) for p in (0, 1) for la in (0, 1)]
+# two waves per query: lag-parallel from L = 1; four: lag-parallel from L = 3 (below that the
+# four waves split each block's tiles, which equals the one-wave scan as well)
+LAG_PARALLEL = [(w, la, p, t) for w in (2, 4) for t in (0, 1) for p in (0, 1) for la in (0, 1)]
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -47,7 +50,7 @@ def _assert_same(ref, other):
                 assert a[key] == b[key], key
 
 
-@pytest.mark.parametrize("L", [3, 4, 7])
+@pytest.mark.parametrize("L", [1, 2, 3, 4, 7])
 @pytest.mark.parametrize("storage,mode,alpha", [("f32", "learned", 0.1), ("bf16", "learned", 0.1),
                                                 ("f32", "lossless", 0.0)])
 def test_lag_parallel_equals_one_wave_scan(L, storage, mode, alpha):
@@ -67,7 +70,7 @@ def test_lag_parallel_equals_one_wave_scan(L, storage, mode, alpha):
         _assert_same(ref[0], r)
     for i in range(len(lp)):
         # same two-phase choice: the two-phase counters agree too
-        assert lp[i][3]["two_phase_sums"] == ref[i][3]["two_phase_sums"]
+        assert lp[i][3]["two_phase_sums"] == ref[i % len(ref)][3]["two_phase_sums"]
     ids, d, off, st = lp[0]
     for qi in range(0, Q.shape[0], 8):   # every 8th query against the oracle, one at a time
         ora = O.search(ix, Q[qi:qi + 1], int(ks[qi]), int(nps[qi]), alpha, mode=mode)
@@ -75,18 +78,18 @@ def test_lag_parallel_equals_one_wave_scan(L, storage, mode, alpha):
         assert not r["bad"], (qi, r["bad"])
 
 
-@pytest.mark.parametrize("L", [3, 5])
-def test_lag_parallel_matches_oracle_d128(L):
+@pytest.mark.parametrize("L,W", [(1, 2), (2, 2), (3, 4), (5, 4), (5, 2)])
+def test_lag_parallel_matches_oracle_d128(L, W):
     ix = oracle_index(B=64, L=L, n_calib=300)
     w = workload("gauss128")
     g = _index(ix)
     Q = w["queries"]
-    g.set_launch(waves_per_query=4, lookahead=1, persistent=0, two_phase=0)
+    g.set_launch(waves_per_query=W, lookahead=1, persistent=0, two_phase=0)
     ids, d, st = g.search(Q, 10, 8, 0.1)
     g.set_launch(waves_per_query=0, lookahead=-1, persistent=-1, two_phase=-1)
     ora = O.search(ix, Q, 10, 8, 0.1)
     r = check_search(ids, d, ora, ix)
-    print(f"L={L}: {r['same']}/{r['nq']} identical, {r['excused']} excused")
+    print(f"L={L} W={W}: {r['same']}/{r['nq']} identical, {r['excused']} excused")
     assert not r["bad"], r["bad"][:5]
     assert r["excused"] <= 0.05 * r["nq"] + 1
     assert st["candidates"] == int(ora["stops"].sum())
@@ -129,7 +132,7 @@ def test_lag_parallel_residual_and_quantization_tests():
     Q = w["queries"]
     run = lambda: g.search(Q, 10, 8, 0.1, mode="bsao")
     ref = _run(g, [(1, 0, 0, 0), (1, 1, 1, 0)], run)
-    lp = _run(g, [(4, 0, 0, 0), (4, 1, 1, 0)], run)
+    lp = _run(g, [(4, 0, 0, 0), (4, 1, 1, 0), (2, 0, 0, 0), (2, 1, 1, 0)], run)
     for r in ref[1:] + lp:
         _assert_same(ref[0], r)
     ora = O.search(ix, Q, 10, 8, 0.1, mode="bsao")
@@ -138,12 +141,33 @@ def test_lag_parallel_residual_and_quantization_tests():
     g.set_bsar_multiplier(3.0)
     run = lambda: g.search(Q, 10, 8, 0.0, mode="bsar")
     ref = _run(g, [(1, 0, 0, 0), (1, 0, 1, 0)], run)
-    lp = _run(g, [(4, 0, 0, 0), (4, 0, 1, 0)], run)
+    lp = _run(g, [(4, 0, 0, 0), (4, 0, 1, 0), (2, 0, 0, 0), (2, 0, 1, 0)], run)
     for r in ref[1:] + lp:
         _assert_same(ref[0], r)
     ora = O.search(dict(ix, bsar_m=3.0), Q, 10, 8, 0.0, mode="bsar")
     r = check_search(lp[0][0], lp[0][1], ora, ix)
     assert not r["bad"], r["bad"][:5]
+
+
+def test_two_waves_without_lag_run_as_one():
+    """waves_per_query = 2 on an index without lag, or in an unpruned search, is the one-wave
+    scan (the tuner's and scan_variant's answer say so)."""
+    ix = oracle_index(B=64, L=0, n_calib=300)
+    w = workload("gauss128")
+    g = _index(ix)
+    Q = w["queries"]
+    g.set_launch(waves_per_query=2, lookahead=0, persistent=0, two_phase=0)
+    assert g.scan_variant(Q.shape[0], 10, 8)[0] == 1
+    a = g.search(Q, 10, 8, 0.1)
+    g.set_launch(waves_per_query=1)
+    b = g.search(Q, 10, 8, 0.1)
+    _assert_same(a, b)
+    g.set_launch(waves_per_query=0, lookahead=-1, persistent=-1, two_phase=-1)
+    ix3 = oracle_index(B=64, L=3, n_calib=300)
+    g3 = _index(ix3)
+    g3.set_launch(waves_per_query=2)
+    assert g3.scan_variant(Q.shape[0], 10, 8)[0] == 2
+    assert g3.scan_variant(Q.shape[0], 10, 8, mode="none")[0] == 1
 
 
 def test_lag_parallel_persistent_grid_smaller_than_batch():
@@ -157,6 +181,6 @@ def test_lag_parallel_persistent_grid_smaller_than_batch():
     ks = np.tile(rng.integers(1, 64, 100), 60).astype(np.int32)
     nps = np.tile(rng.integers(1, 33, 100), 60).astype(np.int32)
     run = lambda: g.search_var(Q, ks, nps, 0.1)
-    res = _run(g, [(1, 0, 0, 0), (4, 0, 1, 0), (4, 0, 0, 1), (4, 0, 1, 1)], run)
+    res = _run(g, [(1, 0, 0, 0), (4, 0, 1, 0), (4, 0, 0, 1), (4, 0, 1, 1), (2, 0, 1, 0), (2, 0, 1, 1)], run)
     for r in res[1:]:
         _assert_same(res[0], r)
