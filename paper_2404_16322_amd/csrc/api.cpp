@@ -763,12 +763,14 @@ static void *stream_workspace(ddc_index *ix, hipStream_t s, size_t bytes) {
 // persistent launch's slot counter; with two_phase (or the list-major full-D scan) the first
 // phase's list counts and starts, pair ranks, pairs by list, pair offsets, query counts and
 // offsets, its sums (a bound on the batch's candidates: cmax times the summed lengths of the
-// np_max longest lists) and the queries' squared norms; each piece 256-byte aligned.
+// np_max longest lists, each padded to whole 128-byte lines) and the queries' squared norms;
+// each piece 256-byte aligned.
 constexpr int64_t kChunk = 32768;
 constexpr int kParts = 20;
 static int64_t e1_bound(const ddc_index *ix, int64_t cmax, int np_max) {
+  // every (query, list) segment is padded to a multiple of 32 sums
   const int np = std::min<int>(std::max(np_max, 0), (int)ix->len_desc_prefix.size() - 1);
-  return np > 0 ? cmax * ix->len_desc_prefix[np] : 0;
+  return np > 0 ? cmax * (ix->len_desc_prefix[np] + 31 * (int64_t)np) : 0;
 }
 static void scratch_sizes(const ddc_index *ix, int64_t cmax, int np_max, bool two_phase,
                           size_t (&sizes)[kParts]) {

@@ -91,8 +91,8 @@ struct ScanArgs {
   // Two-phase scan: when e1 is set, the partial distance after dim block 0 (with pre: the FP8
   // pre-stage's) of every candidate of every probed list was computed beforehand list by list
   // (launch_stage1_lists): query q's candidates start at e1[e1_qoff[q]], its lists' in probe
-  // order, each list's in stored order.  The first test then reads these instead of the base
-  // (bit-identical sums).
+  // order, each list's in stored order and its segment padded to e1_padded(length) entries.
+  // The first test then reads these instead of the base (bit-identical sums).
   const float *e1;
   const int64_t *e1_qoff;
   int64_t e1_cap;          // entries of e1 (no read at or past it)
@@ -128,6 +128,9 @@ void launch_stage1_lists(const Stage1Args &a, int store, hipStream_t s);
 // norms ||y||^2 of the stored values from xnorm, ||q'||^2 in FP32), clamped at 0, written to
 // e1 in the layout of launch_stage1_lists.  qnorm: [nq] scratch.
 void launch_full_lists(const Stage1Args &a, const float *xnorm, float *qnorm, int store, hipStream_t s);
+// e1 (the list-major phases' per-candidate sums): every (query, list) segment starts at a
+// multiple of this many floats (128 B), so the first phase's 64-sum rows are whole cache lines
+__host__ __device__ inline int64_t e1_padded(int64_t len) { return (len + 31) & ~(int64_t)31; }
 // Lag-parallel scan: with a lag of at least W - 1 blocks, every block of a group of W
 // consecutive blocks is tested against a tau known before the group starts, so with W = 2 or 4
 // waves per query each wave scans one block of the group at once and the group's survivors are

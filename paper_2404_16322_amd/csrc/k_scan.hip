@@ -471,7 +471,7 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
       toff = (lst >= 0 && lst < a.nlist) ? a.tile_off[lst] : 0;
     }
     const int64_t e1_list = e1_at;
-    e1_at += (lst >= 0 && lst < a.nlist) ? len : 0;
+    e1_at += (lst >= 0 && lst < a.nlist) ? e1_padded(len) : 0;
     if (lst < 0 || lst >= a.nlist) continue;  // never follow an invalid list id
     const unsigned char *lbase = reinterpret_cast<const unsigned char *>(a.base) +
                                  (int64_t)toff * nb * BLOCK_BYTES;  // wave-uniform
@@ -1366,10 +1366,10 @@ __global__ __launch_bounds__(256) void pair_offsets_kernel(const int32_t *probes
   int64_t carry = 0;
   for (int p0 = 0; p0 < np; p0 += 64) {
     const int p = p0 + lane;
-    int64_t len = 0;
+    int64_t len = 0;   // the pair's e1 segment: the list's length, padded to whole cache lines
     if (p < np) {
       const int l = probes[q * p_stride + p];
-      len = (l >= 0 && l < nlist) ? list_len[l] : 0;
+      len = (l >= 0 && l < nlist) ? e1_padded(list_len[l]) : 0;
     }
     int64_t inc = len;
 #pragma unroll
