@@ -131,7 +131,11 @@ def serve_phase(ix, w, gt, offered_qps, seconds, alpha, nlist, seed=0, n_streams
     Poisson process at `offered_qps` queries/s; every query has its own K ~ U{10..100} and
     nprobe ~ U{16..128}.  Latency = completion seen on the host - scheduled arrival, so a
     producer running late never hides queueing delay.  recall@10 of every served query is
-    taken against FP64 exact KNN (`gt`, rows of the query set)."""
+    taken against FP64 exact KNN (`gt`, rows of the query set).  The producer sleeps until
+    shortly before each arrival and spins the rest; the interpreter's thread switch interval is
+    cut to 50 us and its garbage collector paused for the phase, so neither Python thread holds
+    the other off (the default 5 ms switch interval let a spinning thread delay submissions by
+    milliseconds)."""
     import threading
     from paper_2404_16322_amd import Server
     rng = np.random.default_rng(1000 + seed)
@@ -157,10 +161,17 @@ def serve_phase(ix, w, gt, offered_qps, seconds, alpha, nlist, seed=0, n_streams
         for i, (q, k, npb) in enumerate(reqs):
             t = start + int(sched[i] * 1e9)
             t_sched[i] = t
+            ahead = t - time.monotonic_ns() - 300_000
+            if ahead > 0:
+                time.sleep(ahead * 1e-9)
             while time.monotonic_ns() < t:
                 pass
             tickets[i] = srv.submit(q, k, npb)
 
+    switch = sys.getswitchinterval()
+    gc_on = gc.isenabled()
+    sys.setswitchinterval(5e-5)
+    gc.disable()
     th = threading.Thread(target=producer)
     th.start()
     lat = []
@@ -179,6 +190,9 @@ def serve_phase(ix, w, gt, offered_qps, seconds, alpha, nlist, seed=0, n_streams
         i += 1
     th.join()
     end = time.monotonic_ns()
+    sys.setswitchinterval(switch)
+    if gc_on:
+        gc.enable()
     hits = 0
     served_rows = set()
     for (ids_r, off_r), rows in zip(results, req_rows):
@@ -195,6 +209,7 @@ def serve_phase(ix, w, gt, offered_qps, seconds, alpha, nlist, seed=0, n_streams
                 p99_ms=round(float(np.percentile(lat, 99)), 3), max_ms=round(float(lat[-1]), 3),
                 recall_at_10=round(hits / (10 * total_q), 4), distinct_queries=len(served_rows),
                 server_p50_ms=round(st["p50_ms"], 3), server_p99_ms=round(st["p99_ms"], 3),
+                server_max_ms=round(st["max_ms"], 3),
                 max_concurrent_batches=st["max_concurrent"], budget_peak_bytes=st["budget_peak_bytes"],
                 n_streams=n_streams, max_batch=max_batch, hbm_budget_bytes=budget)
 

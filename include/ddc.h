@@ -412,7 +412,8 @@ ddc_status ddc_scan_variant(ddc_index *ix, int64_t nq, int32_t k_max, int32_t np
  * hbm_budget_bytes; batches on different streams overlap on the GPU and a request arriving
  * while others run starts as soon as a stream and budget are free.  Every query keeps its own
  * K and N_probe; its result is the same as searching it alone (ddc_search_var).  The index
- * must outlive the server.  Slot buffers for max_batch queries are allocated at creation. */
+ * must outlive the server.  Slot buffers for max_batch queries, each stream's search scratch
+ * included, are allocated at creation: serving itself allocates no device memory. */
 typedef struct ddc_server ddc_server;
 typedef struct {
   int32_t n_streams;        /* concurrent micro-batches, 1..16 */

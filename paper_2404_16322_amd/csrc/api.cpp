@@ -829,9 +829,10 @@ void ddc::search_device(ddc_index *ix, const float *d_q, int64_t nq, const int32
   // LOSSLESS tests e_s > tau with the stored values only: the FP8 estimate is no lower bound;
   // ADS is a fixed table on the stored values too
   const bool lossless = (mode == DDC_CORR_LOSSLESS || mode == DDC_CORR_ADS) && ix->St > 0;
+  const bool copy_tables = fixed_ws && !ws_ext->cached_tables;
   if (mode == DDC_CORR_BSAO) {
     a.prune = 1;
-    if (fixed_ws) {
+    if (copy_tables) {
       std::shared_ptr<const std::vector<float>> h;
       {
         std::lock_guard<std::mutex> lk(ix->beta_mtx);
@@ -860,7 +861,7 @@ void ddc::search_device(ddc_index *ix, const float *d_q, int64_t nq, const int32
     for (int j = 0; j < ix->St; ++j) a.test_after[((j + 1) * ix->delta_d) / kBlockDims - 1] = 1;
   } else if (learned || lossless) {
     a.prune = 1;
-    if (fixed_ws) {
+    if (copy_tables) {
       std::shared_ptr<const std::vector<float>> h;
       {
         std::lock_guard<std::mutex> lk(ix->beta_mtx);

@@ -239,6 +239,11 @@ struct EstimateSpec {
 struct Workspace {
   void *p;
   size_t bytes;
+  // the correction rows from the index's device cache (made on first use, then reused) instead
+  // of a copy from their host rows into the workspace on every call: for callers that may
+  // allocate once but not per call (the server), since a copy from pageable host memory can
+  // stall the device
+  bool cached_tables = false;
   static constexpr size_t kTableBytes = 16384;
 };
 
@@ -246,8 +251,10 @@ struct Workspace {
 // est (nullable): rank by that estimate instead (mode and alpha are then ignored).
 // stream_scratch: take the scratch from s's grow-only workspace in the index (callers whose
 // streams live on; calls on one stream must not overlap), else from the stream-ordered pool.
-// ws (nullable): take tables and scratch from this workspace instead, allocate nothing, time
-// nothing and never tune (the caller has checked that it is large enough).
+// ws (nullable): take tables and scratch from this workspace instead, allocate nothing (with
+// ws->cached_tables the tables come from the index's device cache, which allocates on the first
+// use of a (significance, test) pair), time nothing and never tune (the caller has checked that
+// the workspace is large enough).
 void search_device(ddc_index *ix, const float *d_q, int64_t nq, const int32_t *d_k, int k_all,
                    int k_max, const int32_t *d_np, int np_all, int np_max, double alpha,
                    ddc_corr mode, const int64_t *d_off, int64_t *d_ids, float *d_d,

@@ -10,6 +10,7 @@
 // search is computed per query (per-query rotation row, probe list, threshold schedule).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <cmath>
@@ -44,14 +45,30 @@ struct Request {
   int state = 0;                     // 0 queued, 1 running, 2 done, 3 failed
 };
 
+// A batch's inputs (queries, K, nprobe, result offsets) and outputs (ids, distances) each travel
+// as one packed block, so a batch costs one host-to-device and one device-to-host copy: with
+// four copies per batch, one of them now and then waited milliseconds for other streams' work.
+struct InLayout {
+  size_t k, np, off, bytes;   // byte offsets of K, nprobe and the offsets; total (queries at 0)
+};
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+static InLayout in_layout(int64_t nq, int D) {
+  InLayout l;
+  l.k = align256((size_t)nq * D * 4);
+  l.np = l.k + align256((size_t)nq * 4);
+  l.off = l.np + align256((size_t)nq * 4);
+  l.bytes = l.off + (size_t)(nq + 1) * 8;
+  return l;
+}
+static size_t out_d_offset(int64_t nres) { return align256((size_t)nres * 8); }   // ids at 0
+
 struct Slot {
   hipStream_t stream = nullptr;
   hipEvent_t done = nullptr;
-  DevBuf d_q, d_k, d_np, d_off, d_ids, d_d;
-  float *h_q = nullptr;
-  int32_t *h_k = nullptr, *h_np = nullptr;
-  int64_t *h_off = nullptr, *h_ids = nullptr;
-  float *h_d = nullptr;
+  DevBuf d_in, d_out;
+  DevBuf ws;   // the batch's correction rows and search scratch (sized for max_batch at creation)
+  char *h_in = nullptr, *h_out = nullptr;
+  size_t out_d = 0;                  // the current batch's distances in h_out / d_out
   std::vector<std::shared_ptr<Request>> reqs;
   std::vector<int64_t> res_off;      // first result of every request in the batch
   int64_t bytes = 0;
@@ -84,10 +101,32 @@ struct ddc_server {
 };
 
 // pinned host buffer of n bytes (counted like the device allocations)
-template <class T> static void host_alloc(T **p, size_t n) {
+template <class T> static void host_alloc(T **p, size_t n, unsigned flags = 0) {
   fault_check_alloc();
-  HIPC(hipHostMalloc((void **)p, n, 0));
+  HIPC(hipHostMalloc((void **)p, n, flags));
   alloc_track(1, 0);   // counted, not in the device bytes
+}
+
+// A batch's packed inputs and outputs are moved by this kernel on the batch's stream, reading
+// or writing the pinned host block (coherent, so never cached stale on the device) over PCIe:
+// the runtime's copy commands now and then blocked the submitting thread for milliseconds while
+// other streams ran.  A write to the host ends with a system-scope fence, so the host sees the
+// results once the batch's completion event has fired.  n16: 16-byte words (the blocks are
+// sized in whole words).
+template <bool TO_HOST>
+__global__ __launch_bounds__(256) void stage_kernel(const uint4 *__restrict__ src, uint4 *__restrict__ dst,
+                                                    int64_t n16) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n16; i += (int64_t)gridDim.x * 256)
+    dst[i] = src[i];
+  if (TO_HOST) __threadfence_system();
+}
+template <bool TO_HOST> static void stage(const char *src, char *dst, size_t bytes, hipStream_t st) {
+  const int64_t n16 = (int64_t)((bytes + 15) / 16);
+  if (n16 == 0) return;
+  const unsigned grid = (unsigned)std::min<int64_t>((n16 + 255) / 256, 1024);
+  hipLaunchKernelGGL(stage_kernel<TO_HOST>, dim3(grid), dim3(256), 0, st,
+                     reinterpret_cast<const uint4 *>(src), reinterpret_cast<uint4 *>(dst), n16);
+  HIPC(hipGetLastError());
 }
 template <class T> static void host_free(T *&p) {
   if (!p) return;
@@ -97,17 +136,12 @@ template <class T> static void host_free(T *&p) {
 }
 
 static void release_slot(Slot &sl) {
-  host_free(sl.h_q);
-  host_free(sl.h_k);
-  host_free(sl.h_np);
-  host_free(sl.h_off);
-  host_free(sl.h_ids);
-  host_free(sl.h_d);
+  host_free(sl.h_in);
+  host_free(sl.h_out);
   if (sl.done) (void)hipEventDestroy(sl.done);
   if (sl.stream) (void)hipStreamDestroy(sl.stream);
-  sl.d_q.release(); sl.d_k.release(); sl.d_np.release();
-  sl.d_off.release(); sl.d_ids.release(); sl.d_d.release();
-  sl.h_q = nullptr; sl.h_k = sl.h_np = nullptr; sl.h_off = sl.h_ids = nullptr; sl.h_d = nullptr;
+  sl.d_in.release(); sl.d_out.release(); sl.ws.release();
+  sl.h_in = sl.h_out = nullptr;
   sl.done = nullptr; sl.stream = nullptr;
 }
 
@@ -123,8 +157,10 @@ static bool reap(ddc_server *s) {
     for (size_t r = 0; r < sl.reqs.size(); ++r) {
       Request &rq = *sl.reqs[r];
       if (e == hipSuccess) {
-        rq.ids.assign(sl.h_ids + sl.res_off[r], sl.h_ids + sl.res_off[r] + rq.nres);
-        rq.d.assign(sl.h_d + sl.res_off[r], sl.h_d + sl.res_off[r] + rq.nres);
+        const int64_t *h_ids = reinterpret_cast<const int64_t *>(sl.h_out);
+        const float *h_d = reinterpret_cast<const float *>(sl.h_out + sl.out_d);
+        rq.ids.assign(h_ids + sl.res_off[r], h_ids + sl.res_off[r] + rq.nres);
+        rq.d.assign(h_d + sl.res_off[r], h_d + sl.res_off[r] + rq.nres);
         rq.state = 2;
         rq.t_done = t;
         s->lat_ms.push_back((double)(t - rq.t_submit) * 1e-6);
@@ -172,16 +208,21 @@ static bool admit(ddc_server *s, Slot &sl) {
     s->max_running = std::max(s->max_running, s->running);
   }
   const int D = s->ix->D;
+  const InLayout L = in_layout(nq, D);
+  float *h_q = reinterpret_cast<float *>(sl.h_in);
+  int32_t *h_k = reinterpret_cast<int32_t *>(sl.h_in + L.k);
+  int32_t *h_np = reinterpret_cast<int32_t *>(sl.h_in + L.np);
+  int64_t *h_off = reinterpret_cast<int64_t *>(sl.h_in + L.off);
   int64_t qo = 0, ro = 0;
   sl.res_off.clear();
-  sl.h_off[0] = 0;
+  h_off[0] = 0;
   for (auto &r : take) {
-    std::memcpy(sl.h_q + qo * D, r->q.data(), (size_t)r->nq * D * 4);
+    std::memcpy(h_q + qo * D, r->q.data(), (size_t)r->nq * D * 4);
     sl.res_off.push_back(ro);
     for (int i = 0; i < r->nq; ++i) {
-      sl.h_k[qo + i] = r->k[i];
-      sl.h_np[qo + i] = r->np[i];
-      sl.h_off[qo + i + 1] = sl.h_off[qo + i] + r->k[i];
+      h_k[qo + i] = r->k[i];
+      h_np[qo + i] = r->np[i];
+      h_off[qo + i + 1] = h_off[qo + i] + r->k[i];
     }
     qo += r->nq;
     ro += r->nres;
@@ -190,16 +231,17 @@ static bool admit(ddc_server *s, Slot &sl) {
   sl.bytes = bytes;
   sl.busy = true;
   hipStream_t st = sl.stream;
-  HIPC(hipMemcpyAsync(sl.d_q.p, sl.h_q, (size_t)nq * D * 4, hipMemcpyHostToDevice, st));
-  HIPC(hipMemcpyAsync(sl.d_k.p, sl.h_k, (size_t)nq * 4, hipMemcpyHostToDevice, st));
-  HIPC(hipMemcpyAsync(sl.d_np.p, sl.h_np, (size_t)nq * 4, hipMemcpyHostToDevice, st));
-  HIPC(hipMemcpyAsync(sl.d_off.p, sl.h_off, (size_t)(nq + 1) * 8, hipMemcpyHostToDevice, st));
-  search_device(s->ix, sl.d_q.as<float>(), nq, sl.d_k.as<int32_t>(), 0, k_max, sl.d_np.as<int32_t>(),
-                0, np_max, s->p.significance, s->p.mode, sl.d_off.as<int64_t>(),
-                sl.d_ids.as<int64_t>(), sl.d_d.as<float>(), nullptr, st, nullptr, nullptr,
-                /*may_tune=*/false);
-  HIPC(hipMemcpyAsync(sl.h_ids, sl.d_ids.p, (size_t)nres * 8, hipMemcpyDeviceToHost, st));
-  HIPC(hipMemcpyAsync(sl.h_d, sl.d_d.p, (size_t)nres * 4, hipMemcpyDeviceToHost, st));
+  char *d_in = sl.d_in.as<char>();
+  stage<false>(sl.h_in, d_in, L.bytes, st);
+  sl.out_d = out_d_offset(nres);
+  char *d_out = sl.d_out.as<char>();
+  const Workspace w{sl.ws.p, sl.ws.bytes, /*cached_tables=*/true};
+  search_device(s->ix, reinterpret_cast<const float *>(d_in), nq, reinterpret_cast<const int32_t *>(d_in + L.k),
+                0, k_max, reinterpret_cast<const int32_t *>(d_in + L.np), 0, np_max, s->p.significance,
+                s->p.mode, reinterpret_cast<const int64_t *>(d_in + L.off), reinterpret_cast<int64_t *>(d_out),
+                reinterpret_cast<float *>(d_out + sl.out_d), nullptr, st, nullptr, nullptr,
+                /*may_tune=*/false, nullptr, false, &w);
+  stage<true>(d_out, sl.h_out, sl.out_d + (size_t)nres * 4, st);
   HIPC(hipEventRecord(sl.done, st));
   return true;
 }
@@ -221,7 +263,9 @@ static void run_loop(ddc_server *s) {
           lk.unlock();
           std::this_thread::sleep_for(std::chrono::microseconds(20));
         } else {
-          s->cv.wait_for(lk, std::chrono::milliseconds(20));
+          // the queue is checked under the lock before sleeping: a request submitted after
+          // admit() saw the queue empty (its notify found no waiter) is not left waiting
+          s->cv.wait_for(lk, std::chrono::milliseconds(20), [s] { return !s->queue.empty() || s->stop; });
         }
       }
     }
@@ -263,47 +307,46 @@ ddc_status ddc_server_create(const ddc_index *ixc, const ddc_server_params *p, d
     for (auto &sl : s->slots) {
       HIPC(hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking));
       HIPC(hipEventCreateWithFlags(&sl.done, hipEventDisableTiming));
-      sl.d_q.alloc(mb * ix->D * 4);
-      sl.d_k.alloc(mb * 4);
-      sl.d_np.alloc(mb * 4);
-      sl.d_off.alloc((mb + 1) * 8);
-      sl.d_ids.alloc(mb * kMaxK * 8);
-      sl.d_d.alloc(mb * kMaxK * 4);
-      host_alloc(&sl.h_q, mb * ix->D * 4);
-      host_alloc(&sl.h_k, mb * 4);
-      host_alloc(&sl.h_np, mb * 4);
-      host_alloc(&sl.h_off, (mb + 1) * 8);
-      host_alloc(&sl.h_ids, mb * kMaxK * 8);
-      host_alloc(&sl.h_d, mb * kMaxK * 4);
-    }
-    {
-      // grow the stream-ordered pool once for n_streams batches of max_batch queries (it keeps
-      // what it reserved), so the first requests do not pay for mapping new memory
-      std::vector<AsyncBuf> warm;
-      for (auto &sl : s->slots)
-        warm.emplace_back(search_scratch_bytes(ix, mb, std::min(ix->nlist, 4096)), sl.stream);
-      for (auto &sl : s->slots) HIPC(hipStreamSynchronize(sl.stream));
+      const size_t in_b = (in_layout(mb, ix->D).bytes + 15) & ~(size_t)15;   // whole 16-byte words
+      const size_t out_b = (out_d_offset(mb * kMaxK) + (size_t)mb * kMaxK * 4 + 15) & ~(size_t)15;
+      sl.d_in.alloc(in_b);
+      sl.d_out.alloc(out_b);
+      host_alloc(&sl.h_in, in_b, hipHostMallocCoherent);
+      host_alloc(&sl.h_out, out_b, hipHostMallocCoherent);
+      // every batch's scratch comes from this one buffer, so serving maps no device memory:
+      // an allocation the stream-ordered pool cannot serve from a freed block maps new memory,
+      // which stalled every stream of the device for several milliseconds
+      sl.ws.alloc(Workspace::kTableBytes + search_scratch_bytes(ix, mb, std::min(ix->nlist, 4096)));
     }
     for (auto &sl : s->slots) HIPC(hipStreamSynchronize(sl.stream));
     // one small search per stream with the server's significance and test, so the first
-    // requests find the correction rows uploaded, the kernels they launch loaded and the pool
-    // grown for a batch of that shape (zero queries: finite, valid input)
+    // requests find the correction rows computed and the kernels they launch loaded (zero
+    // queries: finite, valid input)
     {
       const int wq = (int)std::min<int64_t>(mb, 256);
       const int wnp = std::min(ix->nlist, 16), wk = 10;
       for (auto &sl : s->slots) {
-        HIPC(hipMemsetAsync(sl.d_q.p, 0, (size_t)wq * ix->D * 4, sl.stream));
-        std::vector<int32_t> hk(wq, wk), hn(wq, wnp);
-        std::vector<int64_t> ho(wq + 1);
-        for (int i = 0; i <= wq; ++i) ho[i] = (int64_t)i * wk;
-        HIPC(hipMemcpyAsync(sl.d_k.p, hk.data(), (size_t)wq * 4, hipMemcpyHostToDevice, sl.stream));
-        HIPC(hipMemcpyAsync(sl.d_np.p, hn.data(), (size_t)wq * 4, hipMemcpyHostToDevice, sl.stream));
-        HIPC(hipMemcpyAsync(sl.d_off.p, ho.data(), (size_t)(wq + 1) * 8, hipMemcpyHostToDevice, sl.stream));
-        for (int nq : {wq, 1})
-          search_device(ix, sl.d_q.as<float>(), nq, sl.d_k.as<int32_t>(), 0, wk, sl.d_np.as<int32_t>(), 0,
-                        wnp, p->significance, p->mode, sl.d_off.as<int64_t>(), sl.d_ids.as<int64_t>(),
-                        sl.d_d.as<float>(), nullptr, sl.stream, nullptr, nullptr, /*may_tune=*/false);
-        HIPC(hipStreamSynchronize(sl.stream));   // the pageable staging above stays alive until here
+        const Workspace w{sl.ws.p, sl.ws.bytes, /*cached_tables=*/true};
+        for (int nq : {wq, 1}) {
+          // the batch path as admit() runs it: one packed input copy, the search, one output copy
+          const InLayout L = in_layout(nq, ix->D);
+          std::memset(sl.h_in, 0, (size_t)nq * ix->D * 4);
+          int32_t *h_k = reinterpret_cast<int32_t *>(sl.h_in + L.k);
+          int32_t *h_np = reinterpret_cast<int32_t *>(sl.h_in + L.np);
+          int64_t *h_off = reinterpret_cast<int64_t *>(sl.h_in + L.off);
+          for (int i = 0; i < nq; ++i) { h_k[i] = wk; h_np[i] = wnp; }
+          for (int i = 0; i <= nq; ++i) h_off[i] = (int64_t)i * wk;
+          char *d_in = sl.d_in.as<char>(), *d_out = sl.d_out.as<char>();
+          const size_t od = out_d_offset((int64_t)nq * wk);
+          stage<false>(sl.h_in, d_in, L.bytes, sl.stream);
+          search_device(ix, reinterpret_cast<const float *>(d_in), nq, reinterpret_cast<const int32_t *>(d_in + L.k),
+                        0, wk, reinterpret_cast<const int32_t *>(d_in + L.np), 0, wnp, p->significance,
+                        p->mode, reinterpret_cast<const int64_t *>(d_in + L.off), reinterpret_cast<int64_t *>(d_out),
+                        reinterpret_cast<float *>(d_out + od), nullptr, sl.stream, nullptr, nullptr,
+                        /*may_tune=*/false, nullptr, false, &w);
+          stage<true>(d_out, sl.h_out, od + (size_t)nq * wk * 4, sl.stream);
+          HIPC(hipStreamSynchronize(sl.stream));   // h_in is rewritten for the next shape
+        }
       }
     }
   } catch (const DdcError &e) {
