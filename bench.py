@@ -676,10 +676,19 @@ def run_workload(wl, args, headline):
         for _ in range(args.warmup):
             run(kb[0], kb[1], "learned", kk=100)
         ms100 = timed(kb[0], kb[1], "learned", steps, kk=100)
-        msf100 = timed(kf[0], 0.0, "none", steps, kk=100)
+        # the full-D baseline at K = 100 in both layouts (the faster one is the baseline)
+        msf_q = timed(kf[0], 0.0, "none", steps, kk=100)
+        ix.set_launch(full_d_matrix=1)
+        run(kf[0], 0.0, "none", kk=100)
+        msf_l = timed(kf[0], 0.0, "none", steps, kk=100)
+        ix.set_launch(full_d_matrix=0)
+        msf100 = min(msf_q, msf_l)
         k100 = dict(k=100, qps=round(nq / ms100 * 1e3, 1), nprobe=kb[0], significance=kb[1],
                     recall_at_10=round(kb[3], 4), ms_per_step=round(ms100, 4),
                     full_d_qps=round(nq / msf100 * 1e3, 1), full_d_nprobe=kf[0],
+                    full_d_layout="list_major" if msf_l <= msf_q else "query_major",
+                    full_d_qps_by_layout=dict(query_major=round(nq / msf_q * 1e3, 1),
+                                              list_major=round(nq / msf_l * 1e3, 1)),
                     full_d_recall_at_10=round(kf[3], 4), speedup_vs_full_d=round(msf100 / ms100, 3))
         log(f"[bench] K=100: {k100}")
 
