@@ -420,7 +420,9 @@ typedef struct {
   int32_t max_batch;        /* queries per micro-batch and per request, 1..65536 */
   int64_t hbm_budget_bytes; /* device bytes all in-flight batches may use */
   double significance;      /* alpha of every request, [0, 1) */
-  ddc_corr mode;
+  ddc_corr mode;            /* the test of every request, any of ddc_search's under its conditions
+                               (DDC_CORR_BSAO: an index with pq_m > 0 and its tables; DDC_CORR_BSAR:
+                               the rotation's eigenvalues); EINVAL at creation otherwise */
 } ddc_server_params;
 typedef struct {
   int64_t requests_done, queries_done, rejected;

@@ -290,8 +290,12 @@ ddc_status ddc_server_create(const ddc_index *ixc, const ddc_server_params *p, d
   if (p->max_batch < 1 || p->max_batch > 65536) return set_err(DDC_EINVAL, "max_batch must be in [1, 65536]");
   if (!(p->significance >= 0.0 && p->significance < 1.0)) return set_err(DDC_EINVAL, "significance must be in [0, 1)");
   if (p->mode != DDC_CORR_LEARNED && p->mode != DDC_CORR_LOSSLESS && p->mode != DDC_CORR_NONE &&
-      p->mode != DDC_CORR_ADS && p->mode != DDC_CORR_BSAR)
+      p->mode != DDC_CORR_ADS && p->mode != DDC_CORR_BSAR && p->mode != DDC_CORR_BSAO)
     return set_err(DDC_EINVAL, "unknown correction mode");
+  if (p->mode == DDC_CORR_BSAO && !ixc->pq_tables())
+    return set_err(DDC_EINVAL, "the BSA-O test needs an index with pq_m > 0 and its calibrated tables");
+  if (p->mode == DDC_CORR_BSAR && (int)ixc->lam.size() != ixc->D)
+    return set_err(DDC_EINVAL, "the residual test needs the rotation's eigenvalues (lam)");
   if (p->mode == DDC_CORR_LEARNED && p->significance > 0 && ixc->Tt() > 0 && ixc->tables.empty())
     return set_err(DDC_EINVAL, "index has no calibrated correction table");
   ddc_index *ix = const_cast<ddc_index *>(ixc);

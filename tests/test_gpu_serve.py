@@ -109,3 +109,20 @@ def test_poisson_arrivals_report_latency(index):
     srv.close()
     assert st["requests_done"] == len(reqs)
     assert 0 < st["p50_ms"] <= st["p99_ms"] <= st["max_ms"]
+
+
+def test_quantization_test_served_like_searched_alone():
+    """BSA-O's quantization test (Sec. V-B) through the server: every request's results equal
+    searching its queries alone with the same test and significance."""
+    from paper_2404_16322_amd import Index, Server
+    ix = Index.from_artifacts(artifacts(oracle_index(pq_m=32, n_calib=400)))
+    reqs = _requests(3, 24)
+    srv = Server(ix, n_streams=3, max_batch=96, hbm_budget_bytes=1 << 30, alpha=0.1, mode="bsao")
+    tickets = [srv.submit(q, k, npb) for q, k, npb in reqs]
+    res = _collect(srv, tickets)
+    srv.close()
+    for (q, k, npb), (ids, d, off, _) in zip(reqs, res):
+        a_ids, a_d, a_off, _ = ix.search_var(q, k, npb, 0.1, mode="bsao")
+        np.testing.assert_array_equal(off, a_off)
+        np.testing.assert_array_equal(ids, a_ids)
+        np.testing.assert_array_equal(d, a_d)
