@@ -119,6 +119,17 @@ __device__ inline void e4m3x4_to_f32(uint32_t w, float *f) {
   f[0] = lo[0]; f[1] = lo[1]; f[2] = hi[0]; f[3] = hi[1];
 }
 
+// One term of the FP8 pre-stage: the decoded value is the code's value times the tile's scale
+// rounded to FP32, and its difference to the query coordinate is rounded again.  Contraction
+// into one fused multiply-add is off here, so every kernel forms the same sum (a fused form in
+// one kernel and a separately rounded product in another once decided 1 pre-stage test of
+// 3e8 differently).
+__device__ inline float fp8_term(float code_value, float scale, float q) {
+#pragma clang fp contract(off)
+  const float decoded = code_value * scale;
+  return decoded - q;
+}
+
 __device__ inline bool lex_less(float d, int32_t id, float td, int32_t tid) {
   return d < td || (d == td && id < tid);
 }
@@ -701,7 +712,7 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
                   e4m3x4_to_f32(w[i], f);
 #pragma unroll
                   for (int e = 0; e < 4; ++e) {
-                    const float d = f[e] * sc[u] - q8[4 * i + e];
+                    const float d = fp8_term(f[e], sc[u], q8[4 * i + e]);
                     acc = fmaf(d, d, acc);
                   }
                 }
@@ -1497,7 +1508,7 @@ __global__ __launch_bounds__(kS1Threads) void stage1_lists_kernel(Stage1Args a) 
         float acc = 0.f;
 #pragma unroll
         for (int e = 0; e < NP; ++e) {
-          const float d = PRE ? f[k][e] * sc - qk[e] : f[k][e] - qk[e];
+          const float d = PRE ? fp8_term(f[k][e], sc, qk[e]) : f[k][e] - qk[e];
           acc = fmaf(d, d, acc);
         }
         P[k] = acc;
