@@ -392,10 +392,17 @@ ddc_status ddc_set_bsar_multiplier(ddc_index *ix, double m);
  * on the matrix cores (FP32 products; each tile read once for all those queries), clamped at 0,
  * and the per-query scan merges these distances.  The result is the exact full-D search up to
  * FP32 rounding of that expanded form (its ids and distances can differ from the default scan's
- * in the last bits and at near ties).  Defaults: 0, -1, 1, 1, -1, -1, 0. */
+ * in the last bits and at near ties).  stage1_matrix (not result-invariant, never tuned; 0 or
+ * 1): with 1, the first phase of a two-phase scan whose first test follows dim block 0 (not the
+ * FP8 pre-stage) forms each candidate's stage-1 distance as ||q'_1||^2 + ||y_1||^2 -
+ * 2 <q'_1, y_1> over that block on the matrix cores (FP32 products, each stored tile's block 0
+ * read once and kept in registers for all the queries probing its list), clamped at 0; the
+ * scan tests and extends those sums as usual.  Results then equal the one-phase scan's up to
+ * FP32 rounding of the first block's partial distance (ids can differ at near-threshold
+ * decisions and near ties).  Defaults: 0, -1, 1, 1, -1, -1, 0, 0. */
 typedef struct {
   int32_t waves_per_query, lookahead, query_order, xcd_swizzle, persistent, two_phase;
-  int32_t full_d_matrix;
+  int32_t full_d_matrix, stage1_matrix;
 } ddc_launch_params;
 ddc_status ddc_set_launch(ddc_index *ix, const ddc_launch_params *p);
 ddc_status ddc_get_launch(const ddc_index *ix, ddc_launch_params *p);

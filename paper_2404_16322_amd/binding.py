@@ -92,7 +92,7 @@ class ServerStats(C.Structure):
 class LaunchParams(C.Structure):
     _fields_ = [("waves_per_query", C.c_int32), ("lookahead", C.c_int32),
                 ("query_order", C.c_int32), ("xcd_swizzle", C.c_int32), ("persistent", C.c_int32),
-                ("two_phase", C.c_int32), ("full_d_matrix", C.c_int32)]
+                ("two_phase", C.c_int32), ("full_d_matrix", C.c_int32), ("stage1_matrix", C.c_int32)]
 
 
 class DdcError(RuntimeError):
@@ -438,16 +438,17 @@ class Index:
     def set_launch(self, waves_per_query: int | None = None, lookahead: int | None = None,
                    query_order: int | None = None, xcd_swizzle: int | None = None,
                    persistent: int | None = None, two_phase: int | None = None,
-                   full_d_matrix: int | None = None):
-        """Result-invariant launch shape of the scan; None keeps the current value
-        (waves_per_query 0, lookahead -1, persistent -1 and two_phase -1 mean tuned per size
-        class)."""
+                   full_d_matrix: int | None = None, stage1_matrix: int | None = None):
+        """Launch shape of the scan; None keeps the current value (waves_per_query 0,
+        lookahead -1, persistent -1 and two_phase -1 mean tuned per size class).  Every knob
+        but full_d_matrix and stage1_matrix is result-invariant; those two form distances on
+        the matrix cores in the expanded form (results equal up to FP32 rounding)."""
         cur = self.launch()
         lp = LaunchParams(*(cur[k] if v is None else int(v) for k, v in
                             (("waves_per_query", waves_per_query), ("lookahead", lookahead),
                              ("query_order", query_order), ("xcd_swizzle", xcd_swizzle),
                              ("persistent", persistent), ("two_phase", two_phase),
-                             ("full_d_matrix", full_d_matrix))))
+                             ("full_d_matrix", full_d_matrix), ("stage1_matrix", stage1_matrix))))
         _check(load_library().ddc_set_launch(self._h, C.byref(lp)))
 
     def launch(self) -> dict:

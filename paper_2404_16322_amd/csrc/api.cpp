@@ -87,6 +87,10 @@ struct LaunchOrders {
   std::function<std::pair<const int32_t *, int32_t *>(bool rebuild)> longest_first;
   std::function<std::pair<const float *, const int64_t *>(bool rebuild)> stage1;
   int64_t e1_cap = 0;
+  // the list-major full-D scan: its distances, computed before the launch shape is chosen, so
+  // the tuner times the merge scan that reads them
+  const float *lm_e1 = nullptr;
+  const int64_t *lm_qoff = nullptr;
 };
 
 static void apply_variant(ScanArgs &a, const Variant &v, LaunchOrders &o) {
@@ -105,6 +109,10 @@ static void apply_variant(ScanArgs &a, const Variant &v, LaunchOrders &o) {
     a.e1 = e.first;
     a.e1_qoff = e.second;
     a.e1_cap = o.e1_cap;
+  } else if (o.lm_e1) {
+    a.e1 = o.lm_e1;
+    a.e1_qoff = o.lm_qoff;
+    a.e1_cap = o.e1_cap;
   } else {
     a.e1 = nullptr;
     a.e1_qoff = nullptr;
@@ -119,7 +127,7 @@ static void choose_variant(ddc_index *ix, ScanArgs &a, int np_max, hipStream_t s
                            LaunchOrders &orders) {
   const int kind = scan_kind(a);
   const bool two_ok = static_cast<bool>(orders.stage1);
-  const auto key = tune_class(a.nq, np_max, a.k_max, kind + (two_ok ? 32 : 0));
+  const auto key = tune_class(a.nq, np_max, a.k_max, kind + (two_ok ? 32 : 0) + (orders.lm_e1 ? 64 : 0));
   Variant v = fixed_variant(ix, a.nq, a.prune, np_max, two_ok);
   if (scan_lds_request(a, v[0]) > kMaxLds) v[0] = 4;   // e.g. four lookup tables of BSA-O
   const bool need_w = ix->waves_per_query == 0, need_l = a.prune && !a.res && ix->lookahead < 0;
@@ -998,7 +1006,8 @@ void ddc::search_device(ddc_index *ix, const float *d_q, int64_t nq, const int32
         s1_made = true;
         if (first || rebuild) {
           const Stage1Args s1 = stage1_args();
-          timed(ix, 4, s, [&] { launch_stage1_lists(s1, ix->store(), s); }, fixed_ws);
+          timed(ix, 4, s, [&] { launch_stage1_lists(s1, ix->store(), s, ix->stage1_matrix == 1 && !s1.pre); },
+                fixed_ws);
         }
         return {s1_e1.as<float>(), s1_qoff.as<int64_t>()};
       };
@@ -1006,16 +1015,16 @@ void ddc::search_device(ddc_index *ix, const float *d_q, int64_t nq, const int32
     a.xcd_swizzle = ix->xcd_swizzle;
     a.nq = (int32_t)nqc; a.nblocks = ix->NB; a.block_b = ix->B; a.nlist = ix->nlist;
     a.k_max = k_max; a.lag = ix->L;
-    choose_variant(ix, a, np_max, s, may_tune, orders);
     if (lm_full) {
       const Stage1Args s1 = stage1_args();
       timed(ix, 4, s, [&] {
         launch_full_lists(s1, ix->d_xnorm.as<float>(), s1_qnorm.as<float>(), ix->store(), s);
       }, fixed_ws);
-      a.e1 = s1_e1.as<float>();
-      a.e1_qoff = s1_qoff.as<int64_t>();
-      a.e1_cap = e1_cap;
+      orders.lm_e1 = s1_e1.as<float>();
+      orders.lm_qoff = s1_qoff.as<int64_t>();
+      orders.e1_cap = e1_cap;
     }
+    choose_variant(ix, a, np_max, s, may_tune, orders);
     timed(ix, 3, s, [&] { launch_scan(a, ix->store(), s); }, fixed_ws);
   }
   HIPC(hipGetLastError());
@@ -1776,6 +1785,7 @@ ddc_status ddc_set_launch(ddc_index *ix, const ddc_launch_params *p) {
   if (p->persistent < -1 || p->persistent > 1) return set_err(DDC_EINVAL, "persistent must be -1, 0 or 1");
   if (p->two_phase < -1 || p->two_phase > 1) return set_err(DDC_EINVAL, "two_phase must be -1, 0 or 1");
   if (p->full_d_matrix != 0 && p->full_d_matrix != 1) return set_err(DDC_EINVAL, "full_d_matrix must be 0 or 1");
+  if (p->stage1_matrix != 0 && p->stage1_matrix != 1) return set_err(DDC_EINVAL, "stage1_matrix must be 0 or 1");
   std::lock_guard<std::mutex> lk(ix->tune_mtx);
   ix->tuned.clear();   // a choice tuned under other forced knobs may not be the best now
   ix->waves_per_query = p->waves_per_query;
@@ -1785,6 +1795,7 @@ ddc_status ddc_set_launch(ddc_index *ix, const ddc_launch_params *p) {
   ix->persistent = p->persistent;
   ix->two_phase = p->two_phase;
   ix->full_d_matrix = p->full_d_matrix;
+  ix->stage1_matrix = p->stage1_matrix;
   return DDC_OK;
 }
 
@@ -1797,6 +1808,7 @@ ddc_status ddc_get_launch(const ddc_index *ix, ddc_launch_params *p) {
   p->persistent = ix->persistent;
   p->two_phase = ix->two_phase;
   p->full_d_matrix = ix->full_d_matrix;
+  p->stage1_matrix = ix->stage1_matrix;
   return DDC_OK;
 }
 
@@ -1821,7 +1833,8 @@ ddc_status ddc_scan_variant(ddc_index *ix, int64_t nq, int32_t k_max, int32_t np
   if (scan_lds_request(la, v[0]) > kMaxLds) v[0] = 4;
   {
     std::lock_guard<std::mutex> lk(ix->tune_mtx);
-    auto it = ix->tuned.find(tune_class(nqc, nprobe_max, k_max, kind + (two_ok ? 32 : 0)));
+    const bool lm = !prune && ix->full_d_matrix == 1 && ix->d_tile_list.p != nullptr;
+    auto it = ix->tuned.find(tune_class(nqc, nprobe_max, k_max, kind + (two_ok ? 32 : 0) + (lm ? 64 : 0)));
     if (it != ix->tuned.end()) v = it->second;
   }
   v = forced_or(ix, v, kind, two_ok);

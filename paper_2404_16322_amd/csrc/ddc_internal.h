@@ -120,7 +120,10 @@ struct Stage1Args {
   int64_t *poff, *qcnt, *qoff;
   float *e1; int64_t e1_cap;
 };
-void launch_stage1_lists(const Stage1Args &a, int store, hipStream_t s);
+// matrix (stored values only, not with pre): the sums are formed instead as
+// ||q'_1||^2 + ||y_1||^2 - 2 <q'_1, y_1> on the matrix cores (FP32 products), clamped at 0 (the
+// stage-1 distance up to FP32 rounding of that form, not the scan's bits).
+void launch_stage1_lists(const Stage1Args &a, int store, hipStream_t s, bool matrix = false);
 
 // Full-dimension distances list by list on the matrix cores (the list-major full-D scan):
 // the pair grouping of launch_stage1_lists, then for every stored tile and every query that

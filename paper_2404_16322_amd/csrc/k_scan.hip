@@ -1675,12 +1675,141 @@ void launch_full_lists(const Stage1Args &a, const float *xnorm, float *qnorm, in
   }
 }
 
-void launch_stage1_lists(const Stage1Args &a, int store, hipStream_t s) {
+// Stage-1 sums on the matrix cores (opt-in, not bit-identical to the scan's own first test):
+// one workgroup per stored tile.  The tile's dim block 0 is staged once through LDS with each
+// vector's ||y_1||^2 and every wave keeps the MFMA B operand of all 64 vectors in registers;
+// the waves then take the list's (query, list) pairs 16 at a time each, with no workgroup
+// barrier: a 16 x 64 block of inner products from 4 v_mfma_f32_16x16x4_f32 blocks over 8 K
+// steps, and e1 = max(||q'_1||^2 + ||y_1||^2 - 2 <q'_1, y_1>, 0) per pair and vector.  The K
+// order is permuted so each lane reads 8 contiguous dims: at step s the lane of K slot k4
+// holds dim 8 k4 + s of its row (A: query, B: vector), which leaves every sum unchanged in
+// content (A[i][k] at lane i + 16 k, B[k][j] at lane j + 16 k; result lane l, register r holds
+// C[4 (l / 16) + r][l % 16]).
+template <int ST>
+__global__ __launch_bounds__(256) void stage1_matrix_kernel(Stage1Args a) {
+  using S = Store<ST>;
+  constexpr int EPL = 16 / S::kBytes;
+  constexpr int YLOADS = (kTile * kBlockDims / EPL) / 256;
+  constexpr int SLICE = kBlockDims * S::kBytes;
+  constexpr int RW = 16;                          // pairs per wave per round
+  __shared__ __align__(16) float Ys[kTile * kLmLd];
+  __shared__ float s_yn[kTile];
+  __shared__ int64_t s_dst[4][RW];
+  __shared__ float s_qn[4][RW];
+  const int64_t t = blockIdx.x;
+  if (t >= a.total_tiles) return;
+  const int l = a.tile_list[t];
+  if (l < 0 || l >= a.nlist) return;
+  const int pb = a.lstart[l], pe = a.lstart[l + 1];
+  if (pb >= pe) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r16 = lane & 15, k4 = lane >> 4;
+  const int tl = (int)(t - a.tile_off[l]);
+  const int cnt = min(kTile, a.list_len[l] - tl * kTile);
+  const unsigned char *tp = reinterpret_cast<const unsigned char *>(a.base) +
+                            t * a.nblocks * ((int64_t)kTile * SLICE);   // dim block 0 of the tile
+#pragma unroll
+  for (int it = 0; it < YLOADS; ++it) {
+    const int e = (tid + it * 256) * EPL;
+    const int r = e / kBlockDims, c = e % kBlockDims;
+    const uint4 v = *reinterpret_cast<const uint4 *>(tp + (int64_t)e * S::kBytes);
+    float f[EPL];
+    S::unpack(v, f);
+#pragma unroll
+    for (int u = 0; u < EPL; u += 4)
+      *reinterpret_cast<float4 *>(&Ys[r * kLmLd + c + u]) = make_float4(f[u], f[u + 1], f[u + 2], f[u + 3]);
+  }
+  __syncthreads();
+  if (tid < kTile) {
+    float sq = 0.f;
+    for (int k = 0; k < kBlockDims; ++k) sq = fmaf(Ys[tid * kLmLd + k], Ys[tid * kLmLd + k], sq);
+    s_yn[tid] = sq;
+  }
+  float bf[8][4];   // B operand: vector 16 j + r16, dims 8 k4 .. 8 k4 + 7
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int s8 = 0; s8 < 8; ++s8) bf[s8][j] = Ys[(16 * j + r16) * kLmLd + 8 * k4 + s8];
+  __syncthreads();
+  float yn[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) yn[j] = s_yn[16 * j + r16];
+  int64_t *wdst = s_dst[wave];
+  float *wqn = s_qn[wave];
+  for (int r0 = pb + RW * wave; r0 < pe; r0 += 4 * RW) {
+    const int n = min(RW, pe - r0);
+    float af[RW / 16][8];
+#pragma unroll
+    for (int i = 0; i < RW / 16; ++i) {
+      const int row = 16 * i + r16;
+      float4 x0 = make_float4(0.f, 0.f, 0.f, 0.f), x1 = x0;
+      int pidx = 0;
+      int64_t q = 0;
+      if (row < n) {
+        pidx = a.lpair[r0 + row];
+        q = pidx / a.p_stride;
+        const float4 *qp = reinterpret_cast<const float4 *>(a.qrot + q * a.q_stride + 8 * k4);
+        x0 = qp[0];
+        x1 = qp[1];
+      }
+      af[i][0] = x0.x; af[i][1] = x0.y; af[i][2] = x0.z; af[i][3] = x0.w;
+      af[i][4] = x1.x; af[i][5] = x1.y; af[i][6] = x1.z; af[i][7] = x1.w;
+      float sq = 0.f;
+#pragma unroll
+      for (int s8 = 0; s8 < 8; ++s8) sq = fmaf(af[i][s8], af[i][s8], sq);
+      sq += __shfl_xor(sq, 16);
+      sq += __shfl_xor(sq, 32);
+      if (k4 == 0 && row < n) {
+        wqn[row] = sq;
+        wdst[row] = a.qoff[q] + a.poff[pidx] + (int64_t)tl * kTile;
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+    lm_floatx4 acc[RW / 16][4];
+#pragma unroll
+    for (int i = 0; i < RW / 16; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = lm_floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s8 = 0; s8 < 8; ++s8)
+#pragma unroll
+      for (int i = 0; i < RW / 16; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i][s8], bf[s8][j], acc[i][j], 0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < RW / 16; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * i + 4 * k4 + r;
+        if (row < n) {
+          const float qn = wqn[row];
+          const int64_t o0 = wdst[row];
+          const int lim = (int)min<int64_t>(cnt, a.e1_cap - o0);   // vectors of the row to write
+          float *rp = a.e1 + o0 + r16;
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            if (16 * j + r16 < lim) rp[16 * j] = fmaxf(qn + yn[j] - 2.f * acc[i][j][r], 0.f);
+        }
+      }
+    __builtin_amdgcn_wave_barrier();   // this round's rows are read before the next round's writes
+  }
+}
+
+void launch_stage1_lists(const Stage1Args &a, int store, hipStream_t s, bool matrix) {
   if (a.nq <= 0 || a.total_tiles <= 0) return;
   launch_pair_groups(a, s);
   const dim3 grid((unsigned)a.total_tiles), blk(kS1Threads);
   if (a.pre) {   // the FP8 codes do not depend on the storage type
     hipLaunchKernelGGL((stage1_lists_kernel<ST_F32, true>), grid, blk, 0, s, a);
+    return;
+  }
+  if (matrix) {
+    switch (store) {
+      case ST_F32: hipLaunchKernelGGL(stage1_matrix_kernel<ST_F32>, grid, blk, 0, s, a); break;
+      case ST_F16: hipLaunchKernelGGL(stage1_matrix_kernel<ST_F16>, grid, blk, 0, s, a); break;
+      default: hipLaunchKernelGGL(stage1_matrix_kernel<ST_BF16>, grid, blk, 0, s, a); break;
+    }
     return;
   }
   switch (store) {

@@ -215,6 +215,7 @@ struct ddc_index {
   int waves_per_query = 0, lookahead = -1, query_order = 1, xcd_swizzle = 1, persistent = -1;
   int two_phase = -1;
   int full_d_matrix = 0;            // NONE-mode scans: distances list by list on the matrix cores
+  int stage1_matrix = 0;            // two-phase first phase (stored values) on the matrix cores
   std::mutex tune_mtx;
   // class -> (waves per query, look-ahead, persistent, two-phase)
   std::map<std::array<int, 4>, std::array<int, 4>> tuned;

@@ -36,13 +36,19 @@ def full():
     return w, ix, g
 
 
-def test_full_size_sampled_queries_match_oracle(full):
+@pytest.fixture(scope="module")
+def sampled(full):
+    w, ix, _ = full
+    sample = np.random.default_rng(7).choice(w["queries"].shape[0], 64, replace=False)
+    return sample, O.search(ix, w["queries"][sample], 10, 48, 0.05)
+
+
+def test_full_size_sampled_queries_match_oracle(full, sampled):
     w, ix, g = full
     Q = w["queries"]
     assert Q.shape == (10_000, 128)
     ids, d, st = g.search(Q, 10, 48, 0.05)
-    sample = np.random.default_rng(7).choice(Q.shape[0], 64, replace=False)
-    ora = O.search(ix, Q[sample], 10, 48, 0.05)
+    sample, ora = sampled
     res = check_search(ids[sample], d[sample], ora, ix)
     print(f"full size: {res['same']}/{res['nq']} identical, {res['excused']} excused")
     assert not res["bad"], res["bad"][:5]
@@ -72,3 +78,32 @@ def test_full_size_properties_on_every_query(full):
     for qi in range(500):
         ex = O.sq_dist_direct(ix["Y"][ids[qi]], qr[qi])
         np.testing.assert_allclose(d[qi], ex, rtol=1e-4)
+
+
+def test_full_size_stage1_matrix_first_phase(full, sampled):
+    """The two-phase scan with its stage-1 sums formed on the matrix cores (expanded form), in
+    the benchmark's launch configuration: sampled queries match the oracle to the same bar, the
+    results equal the default search's up to FP32 rounding, and every stage-1 sum came from
+    the first phase."""
+    w, ix, g = full
+    Q = w["queries"]
+    base_ids, base_d, _ = g.search(Q, 10, 48, 0.05)
+    g.set_launch(two_phase=1, stage1_matrix=1)
+    try:
+        ids, d, st = g.search(Q, 10, 48, 0.05)
+        print(f"[fullsize] stage1_matrix launch shape {g.scan_variant(Q.shape[0], 10, 48)}", flush=True)
+    finally:
+        g.set_launch(two_phase=-1, stage1_matrix=0)
+    assert 0 < st["two_phase_sums"] <= st["candidates"]   # a query's first block runs untested
+    sample, ora = sampled
+    res = check_search(ids[sample], d[sample], ora, ix)
+    print(f"full size, matrix first phase: {res['same']}/{res['nq']} identical, {res['excused']} excused")
+    assert not res["bad"], res["bad"][:5]
+    assert res["excused"] <= 4
+    same = (ids == base_ids).all(axis=1)
+    assert same.mean() > 0.99
+    np.testing.assert_allclose(d[same], base_d[same], rtol=1e-4)
+    assert np.all(np.diff(d, axis=1) >= 0)
+    qr = O.rotate(Q[:500], ix["mu"], ix["R"])
+    for qi in range(500):
+        np.testing.assert_allclose(d[qi], O.sq_dist_direct(ix["Y"][ids[qi]], qr[qi]), rtol=1e-4)
