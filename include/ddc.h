@@ -392,14 +392,20 @@ ddc_status ddc_set_bsar_multiplier(ddc_index *ix, double m);
  * on the matrix cores (FP32 products; each tile read once for all those queries), clamped at 0,
  * and the per-query scan merges these distances.  The result is the exact full-D search up to
  * FP32 rounding of that expanded form (its ids and distances can differ from the default scan's
- * in the last bits and at near ties).  stage1_matrix (not result-invariant, never tuned; 0 or
- * 1): with 1, the first phase of a two-phase scan whose first test follows dim block 0 (not the
- * FP8 pre-stage) forms each candidate's stage-1 distance as ||q'_1||^2 + ||y_1||^2 -
- * 2 <q'_1, y_1> over that block on the matrix cores (FP32 products, each stored tile's block 0
- * read once and kept in registers for all the queries probing its list), clamped at 0; the
- * scan tests and extends those sums as usual.  Results then equal the one-phase scan's up to
- * FP32 rounding of the first block's partial distance (ids can differ at near-threshold
- * decisions and near ties).  Defaults: 0, -1, 1, 1, -1, -1, 0, 0. */
+ * in the last bits and at near ties).  stage1_matrix (0, 1 or 2; 0 and 1 result-invariant): with
+ * 1, the first phase of a two-phase scan whose first test follows dim block 0 (not the FP8
+ * pre-stage) forms
+ * each candidate's stage-1 distance as ||q'_1||^2 + ||y_1||^2 - 2 <q'_1, y_1> over that block on
+ * the matrix cores (FP32 products, each stored tile's block 0 read once and kept in registers for
+ * all the queries probing its list), clamped at 0.  The scan prunes on such a sum only where the
+ * first test prunes every value within its proven FP32 error bound (2^-12 (3 ||q'_1||^2 + 2 e1),
+ * about 48 times the worst case); every other candidate re-reads dim block 0 and takes the test
+ * on the sum in the scan's own arithmetic, so ids, distances and counters equal the one-phase
+ * scan's bit for bit.  With 2 (not result-invariant) the scan takes the expanded-form sums as
+ * they are: its results equal the one-phase scan's up to FP32 rounding of the first block's
+ * partial distance (ids can differ at near-threshold decisions and near ties), and no candidate
+ * re-reads dim block 0.  0 keeps the first phase in the scan's own arithmetic.  Defaults: 0,
+ * -1, 1, 1, -1, -1, 0, 0. */
 typedef struct {
   int32_t waves_per_query, lookahead, query_order, xcd_swizzle, persistent, two_phase;
   int32_t full_d_matrix, stage1_matrix;

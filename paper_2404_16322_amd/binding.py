@@ -441,8 +441,9 @@ class Index:
                    full_d_matrix: int | None = None, stage1_matrix: int | None = None):
         """Launch shape of the scan; None keeps the current value (waves_per_query 0,
         lookahead -1, persistent -1 and two_phase -1 mean tuned per size class).  Every knob
-        but full_d_matrix and stage1_matrix is result-invariant; those two form distances on
-        the matrix cores in the expanded form (results equal up to FP32 rounding)."""
+        but full_d_matrix and stage1_matrix=2 is result-invariant; those two take distances
+        formed on the matrix cores in the expanded form as they are (results equal up to FP32
+        rounding)."""
         cur = self.launch()
         lp = LaunchParams(*(cur[k] if v is None else int(v) for k, v in
                             (("waves_per_query", waves_per_query), ("lookahead", lookahead),

@@ -87,6 +87,7 @@ struct LaunchOrders {
   std::function<std::pair<const int32_t *, int32_t *>(bool rebuild)> longest_first;
   std::function<std::pair<const float *, const int64_t *>(bool rebuild)> stage1;
   int64_t e1_cap = 0;
+  float e1_tol = 0.f;   // stage1's sums in the expanded form: their error bound (ScanArgs::e1_tol)
   // the list-major full-D scan: its distances, computed before the launch shape is chosen, so
   // the tuner times the merge scan that reads them
   const float *lm_e1 = nullptr;
@@ -109,14 +110,17 @@ static void apply_variant(ScanArgs &a, const Variant &v, LaunchOrders &o) {
     a.e1 = e.first;
     a.e1_qoff = e.second;
     a.e1_cap = o.e1_cap;
+    a.e1_tol = o.e1_tol;
   } else if (o.lm_e1) {
     a.e1 = o.lm_e1;
     a.e1_qoff = o.lm_qoff;
     a.e1_cap = o.e1_cap;
+    a.e1_tol = 0.f;
   } else {
     a.e1 = nullptr;
     a.e1_qoff = nullptr;
     a.e1_cap = 0;
+    a.e1_tol = 0.f;
   }
 }
 
@@ -774,6 +778,11 @@ static void *stream_workspace(ddc_index *ix, hipStream_t s, size_t bytes) {
 // np_max longest lists, each padded to whole 128-byte lines) and the queries' squared norms;
 // each piece 256-byte aligned.
 constexpr int64_t kChunk = 32768;
+// Error bound of the expanded-form stage-1 sums against the scan's own, relative to
+// 3 ||q'_1||^2 + 2 |e1|: about 85 units in the last place cover the norms' and inner product's
+// FP32 sums over 32 terms, the final two roundings and the direct sum's rounding (||y_1||^2 <=
+// 2 ||q'_1||^2 + 2 e1); 2^-12 leaves a factor of about 48 on top.
+constexpr float kE1Tol = 1.0f / 4096.0f;
 constexpr int kParts = 20;
 static int64_t e1_bound(const ddc_index *ix, int64_t cmax, int np_max) {
   // every (query, list) segment is padded to a multiple of 32 sums
@@ -1001,13 +1010,15 @@ void ddc::search_device(ddc_index *ix, const float *d_q, int64_t nq, const int32
     };
     if (two_ok) {
       orders.e1_cap = e1_cap;
-      orders.stage1 = [&](bool rebuild) -> std::pair<const float *, const int64_t *> {
+      // stage1_matrix 1: expanded-form sums behind their error bound; 2: taken as they are
+      const bool matrix = ix->stage1_matrix >= 1 && !a.pre;
+      orders.e1_tol = matrix && ix->stage1_matrix == 1 ? kE1Tol : 0.f;
+      orders.stage1 = [&, matrix](bool rebuild) -> std::pair<const float *, const int64_t *> {
         const bool first = !s1_made;
         s1_made = true;
         if (first || rebuild) {
           const Stage1Args s1 = stage1_args();
-          timed(ix, 4, s, [&] { launch_stage1_lists(s1, ix->store(), s, ix->stage1_matrix == 1 && !s1.pre); },
-                fixed_ws);
+          timed(ix, 4, s, [&] { launch_stage1_lists(s1, ix->store(), s, matrix); }, fixed_ws);
         }
         return {s1_e1.as<float>(), s1_qoff.as<int64_t>()};
       };
@@ -1785,7 +1796,7 @@ ddc_status ddc_set_launch(ddc_index *ix, const ddc_launch_params *p) {
   if (p->persistent < -1 || p->persistent > 1) return set_err(DDC_EINVAL, "persistent must be -1, 0 or 1");
   if (p->two_phase < -1 || p->two_phase > 1) return set_err(DDC_EINVAL, "two_phase must be -1, 0 or 1");
   if (p->full_d_matrix != 0 && p->full_d_matrix != 1) return set_err(DDC_EINVAL, "full_d_matrix must be 0 or 1");
-  if (p->stage1_matrix != 0 && p->stage1_matrix != 1) return set_err(DDC_EINVAL, "stage1_matrix must be 0 or 1");
+  if (p->stage1_matrix < 0 || p->stage1_matrix > 2) return set_err(DDC_EINVAL, "stage1_matrix must be 0, 1 or 2");
   std::lock_guard<std::mutex> lk(ix->tune_mtx);
   ix->tuned.clear();   // a choice tuned under other forced knobs may not be the best now
   ix->waves_per_query = p->waves_per_query;

@@ -96,6 +96,11 @@ struct ScanArgs {
   const float *e1;
   const int64_t *e1_qoff;
   int64_t e1_cap;          // entries of e1 (no read at or past it)
+  // e1_tol > 0: e1 holds stage-1 sums in the expanded form (launch_stage1_lists with matrix),
+  // each within e1_tol (3 ||q'_1||^2 + 2 |e1|) of the scan's own sum; the scan prunes on them
+  // only where the bound decides its own test, and the candidates left re-read dim block 0 and
+  // take the first test in the scan's own arithmetic (results and counters as with exact sums)
+  float e1_tol;
   // (prune = 0 with e1 set: e1 holds every candidate's full distance, from launch_full_lists)
 };
 
@@ -121,8 +126,8 @@ struct Stage1Args {
   float *e1; int64_t e1_cap;
 };
 // matrix (stored values only, not with pre): the sums are formed instead as
-// ||q'_1||^2 + ||y_1||^2 - 2 <q'_1, y_1> on the matrix cores (FP32 products), clamped at 0 (the
-// stage-1 distance up to FP32 rounding of that form, not the scan's bits).
+// ||q'_1||^2 + ||y_1||^2 - 2 <q'_1, y_1> on the matrix cores (FP32 products), clamped at 0: the
+// scan's own sums up to the bound ScanArgs::e1_tol describes, not their bits.
 void launch_stage1_lists(const Stage1Args &a, int store, hipStream_t s, bool matrix = false);
 
 // Full-dimension distances list by list on the matrix cores (the list-major full-D scan):

@@ -357,6 +357,14 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
     }
     if (W > 1) __syncthreads(); else __builtin_amdgcn_wave_barrier();
   }
+  // ||q'_1||^2 over dim block 0 (the expanded-form sums' error bound; any order will do)
+  float qn1 = 0.f;
+  if (!PQ && !PRE && !RES && PRUNE && a.e1_tol > 0.f) {
+    const float v = lane < kBlockDims ? s_q[lane] : 0.f;
+    qn1 = v * v;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) qn1 += __shfl_xor(qn1, o);
+  }
   const int nbe = EST ? a.est_nb : nb;           // dim blocks the no-test path reads
   float qres = 0.f;                              // EST: ||q'_r||^2 beyond the leading blocks
   if (EST) {
@@ -742,9 +750,15 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
         if (!PQ && !PRE && !RES && a.e1) {
           // ---- two-phase scan: the stage-1 sums of the segment come from e1 (one 4-byte load
           // per candidate instead of its dim block 0); the test after block 0 as the one-stage
-          // path takes it; survivors go to the alive list and the stages continue at block 1 ----
+          // path takes it; survivors go to the alive list and the stages continue at block 1.
+          // Expanded-form sums (e1_tol > 0): a candidate is pruned here only if the test prunes
+          // every value within the sum's error bound (the test is monotone in the sum); the
+          // others restart at block 0 and are tested on the sum of the scan's own arithmetic ----
           const float mb = s_mb[0], bb = s_mb[1];
           const int64_t e0 = e1_list + bs + s0;
+          const bool bounded = a.e1_tol > 0.f;
+          const float tq = a.e1_tol * 3.f * qn1;
+          const float t2 = a.e1_tol * 2.f;
           int nn = 0, pruned = 0;
           for (int c0 = 0; c0 < slen; c0 += 256) {
             float evs[4];   // four loads in flight, then the tests
@@ -757,27 +771,34 @@ __global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4,
             for (int u = 0; u < 4; ++u) {
               const int idx = c0 + u * 64 + lane;
               const bool valid = idx < slen && e0 + idx < a.e1_cap;
-              const float ev = evs[u];
+              float ev = evs[u];
+              if (bounded) {
+                // the end of the bound interval where the test value is smallest
+                const float w = fmaf(t2, fabsf(ev), tq) + 1e-30f;
+                ev = mb >= 0.f ? ev - w : ev + w;
+              }
               const bool prune = valid && fmaf(mb, ev, bb) > tau_t;
               const bool keep = valid && !prune;
               const unsigned long long bal = __ballot(keep);
               if (keep) {
                 const int pos = nn + __popcll(bal & lt);
                 s_ac[pos] = (uint16_t)idx;
-                s_ae[pos] = ev;
+                s_ae[pos] = bounded ? 0.f : ev;
               }
               nn += __popcll(bal);
               pruned += __popcll(__ballot(prune));
             }
           }
-          st_slices += slen;
+          // slices: block 0 of every candidate once (the re-read of the rechecked ones is
+          // counted by the stages below, so they are taken off here)
+          st_slices += bounded ? slen - nn : slen;
           st_e1 += slen;
-          st_e1_sl += slen;
+          st_e1_sl += bounded ? slen - nn : slen;
           if (ctr) stop_add(0, (uint32_t)pruned);
           __builtin_amdgcn_wave_barrier();
           nalive = nn;
           listed = true;
-          b = 1;
+          b = bounded ? 0 : 1;
         }
         while (b < nb && nalive > 0) {
           if (LOOK && nalive <= 8 && 64 / (nalive <= 1 ? 1 : nalive <= 2 ? 2 : nalive <= 4 ? 4 : 8) > G &&
@@ -1675,8 +1696,8 @@ void launch_full_lists(const Stage1Args &a, const float *xnorm, float *qnorm, in
   }
 }
 
-// Stage-1 sums on the matrix cores (opt-in, not bit-identical to the scan's own first test):
-// one workgroup per stored tile.  The tile's dim block 0 is staged once through LDS with each
+// Stage-1 sums on the matrix cores, in the expanded form (the scan prunes on them only where their
+// error bound decides its own test, ScanArgs::e1_tol): one workgroup per stored tile.  The tile's dim block 0 is staged once through LDS with each
 // vector's ||y_1||^2 and every wave keeps the MFMA B operand of all 64 vectors in registers;
 // the waves then take the list's (query, list) pairs 16 at a time each, with no workgroup
 // barrier: a 16 x 64 block of inner products from 4 v_mfma_f32_16x16x4_f32 blocks over 8 K

@@ -101,7 +101,7 @@ def test_tuner_picks_a_variant_and_caches_it():
     w = workload("gauss128")
     g = _index(ix)
     assert g.launch() == dict(waves_per_query=0, lookahead=-1, query_order=1, xcd_swizzle=1,
-                              persistent=-1, two_phase=-1, full_d_matrix=0)
+                              persistent=-1, two_phase=-1, full_d_matrix=0, stage1_matrix=0)
     ids0, d0, _ = g.search(w["queries"], 10, 8, 0.1)
     v = g.scan_variant(w["queries"].shape[0], 10, 8)
     assert v in VARIANTS
