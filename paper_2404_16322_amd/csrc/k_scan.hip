@@ -1415,6 +1415,15 @@ __global__ __launch_bounds__(256) void pair_offsets_kernel(const int32_t *probes
   if (lane == 0) qcnt[q] = carry;
 }
 
+// Tile of a list-major workgroup: consecutive workgroups go to the eight XCDs in turn, so XCD x
+// takes the x-th contiguous eighth of the tiles; a list's tiles then share one XCD's L2, which
+// fetches the slices of the queries probing the list once for all of them.
+__device__ inline int64_t xcd_tile() {
+  const int64_t n = gridDim.x, wg = blockIdx.x, x = wg % 8, r = wg / 8;
+  const int64_t per = n / 8, rem = n % 8;
+  return x * per + min(x, rem) + r;
+}
+
 // Probed (query, list) pairs grouped by list: count, then scatter after the prefix sum.
 __global__ __launch_bounds__(256) void pair_count_kernel(const int32_t *probes, int32_t p_stride,
                                                          const int32_t *nprobe, int32_t nprobe_all,
@@ -1474,7 +1483,7 @@ __global__ __launch_bounds__(kS1Threads) void stage1_lists_kernel(Stage1Args a) 
   constexpr int CHUNK = PRE ? 32 : 64;                      // pairs staged at once (8 KiB of LDS)
   __shared__ __align__(16) float s_qv[CHUNK * QD];
   __shared__ int64_t s_dst[CHUNK];
-  const int64_t t = blockIdx.x;
+  const int64_t t = xcd_tile();
   if (t >= a.total_tiles) return;
   const int l = a.tile_list[t];
   if (l < 0 || l >= a.nlist) return;
@@ -1594,7 +1603,7 @@ __global__ __launch_bounds__(256) void full_lists_kernel(Stage1Args a, const flo
   __shared__ int64_t s_dst[kTile];
   __shared__ int64_t s_q[kTile];
   __shared__ float s_qn[kTile], s_yn[kTile];
-  const int64_t t = blockIdx.x;
+  const int64_t t = xcd_tile();
   if (t >= a.total_tiles) return;
   const int l = a.tile_list[t];
   if (l < 0 || l >= a.nlist) return;
@@ -1717,7 +1726,7 @@ __global__ __launch_bounds__(256) void stage1_matrix_kernel(Stage1Args a) {
   __shared__ float s_yn[kTile];
   __shared__ int64_t s_dst[4][RW];
   __shared__ float s_qn[4][RW];
-  const int64_t t = blockIdx.x;
+  const int64_t t = xcd_tile();
   if (t >= a.total_tiles) return;
   const int l = a.tile_list[t];
   if (l < 0 || l >= a.nlist) return;
