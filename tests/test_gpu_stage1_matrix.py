@@ -143,6 +143,27 @@ def test_stage1_expanded_sums_match_oracle(storage, mode, alpha, k, nprobe):
     assert not r["bad"], r["bad"][:5]
 
 
+@pytest.mark.parametrize("L", [1, 3])
+def test_stage1_matrix_lagged_and_lag_parallel(L):
+    """A lagged index (blocks of 64, lag 1 and 3): the bounded matrix first phase with one wave
+    per query and in the lag-parallel shapes (two waves from L = 1, four from L = 3) equals the
+    direct first phase and the one-phase scan bit for bit, counters included."""
+    ix = oracle_index(B=64, L=L, n_calib=300)
+    w = workload("gauss128")
+    g = _index(ix)
+    Q = w["queries"]
+    run = lambda: g.search(Q, 10, 8, 0.1)
+    g.set_launch(waves_per_query=1, lookahead=1, persistent=0, two_phase=0, stage1_matrix=0)
+    ref = run()
+    for wv in (1, 2, 4):
+        for p in (0, 1):
+            for m in (0, 1):
+                g.set_launch(waves_per_query=wv, lookahead=1, persistent=p, two_phase=1, stage1_matrix=m)
+                _same(ref, run())
+    g.set_launch(waves_per_query=0, lookahead=-1, persistent=-1, two_phase=-1, stage1_matrix=0)
+    assert 0 < ref[2]["candidates"]
+
+
 def test_stage1_matrix_knob_validation_and_default():
     ix = oracle_index(storage="f32", n_calib=300)
     g = _index(ix)
