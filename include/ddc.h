@@ -383,9 +383,10 @@ ddc_status ddc_set_bsar_multiplier(ddc_index *ix, double m);
  * (for the learned and fixed-table tests whose first test follows dim block 0 with Delta_d = 32,
  * or is the FP8 pre-stage: first that test's partial distance of every candidate of every
  * probed list is computed list by list, each stored tile read once for all the queries that
- * probe its list, in the scan's own arithmetic; the scan then tests those sums and reads the
- * survivors' remaining dims only; its scratch holds one float per candidate of the batch), -1 =
- * tuned (fixed rule: on once a list is probed by four or more queries on average).
+ * probe its list, in the scan's own arithmetic (or on the matrix cores: stage1_matrix below);
+ * the scan then tests those sums and reads the survivors' remaining dims only; its scratch
+ * holds one float per candidate of the batch), -1 = tuned (fixed rule: on once a list is
+ * probed by four or more queries on average).
  * full_d_matrix (not result-invariant, never tuned; 0 or 1): with 1, scans without a test
  * (DDC_CORR_NONE, or significance 0 in the learned mode) run list by list: for every stored
  * tile and every query probing its list the distance ||q'||^2 + ||y||^2 - 2 <q', y> is formed
