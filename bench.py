@@ -77,10 +77,11 @@ CONFIGS = {
     # 2M x 768 unit-normalised FP16 with the FP8 E4M3 pre-stage over the leading 64 dims;
     # a step is 4 launches of 4,096 queries, each query with its own nprobe ~ U{8..256} and
     # K ~ U{10, 50, 100}
+    # (the pre-stage's sums of the two-phase first phase on the matrix cores, taken as they are)
     "embed768": dict(data="embed768", nlist=4096, storage="f16", rotation="bf16", fp8=64,
                      uneven=dict(batches=4, batch=4096, nprobe=(8, 256), k=(10, 50, 100)),
                      fit=dict(kmeans_train_per_list=64, kmeans_iters=10, calib_k_extra=(50, 100)),
-                     serve=None),
+                     serve=None, first_phase="expanded"),
     # 5M x 256 unit-normalised FP16, IVF 16384: serving at absolute Poisson rates
     "embed256": dict(data="embed256", nlist=16384, storage="f16", rotation="f32", k=10,
                      nprobes=[16, 32, 48, 64, 96, 128],

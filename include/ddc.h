@@ -405,7 +405,9 @@ ddc_status ddc_set_bsar_multiplier(ddc_index *ix, double m);
  * scan's bit for bit.  With 2 (not result-invariant) the scan takes the expanded-form sums as
  * they are: its results equal the one-phase scan's up to FP32 rounding of the first block's
  * partial distance (ids can differ at near-threshold decisions and near ties), and no candidate
- * re-reads dim block 0.  0 keeps the first phase in the scan's own arithmetic.  Defaults: 0,
+ * re-reads dim block 0; with the FP8 pre-stage, mode 2 also forms the pre-stage's sums over the
+ * leading 64 dims this way (from the decoded codes; the pre-stage's decisions then hold up to
+ * FP32 rounding, and its survivors' distances are exact as ever).  0 keeps the first phase in the scan's own arithmetic.  Defaults: 0,
  * -1, 1, 1, -1, -1, 0, 0. */
 typedef struct {
   int32_t waves_per_query, lookahead, query_order, xcd_swizzle, persistent, two_phase;

@@ -1010,9 +1010,10 @@ void ddc::search_device(ddc_index *ix, const float *d_q, int64_t nq, const int32
     };
     if (two_ok) {
       orders.e1_cap = e1_cap;
-      // stage1_matrix 1: expanded-form sums behind their error bound; 2: taken as they are
-      const bool matrix = ix->stage1_matrix >= 1 && !a.pre;
-      orders.e1_tol = matrix && ix->stage1_matrix == 1 ? kE1Tol : 0.f;
+      // stage1_matrix 1: expanded-form sums behind their error bound (dim block 0 only; the FP8
+      // pre-stage keeps the scan's arithmetic); 2: taken as they are (also the pre-stage's)
+      const bool matrix = ix->stage1_matrix == 2 || (ix->stage1_matrix == 1 && !a.pre);
+      orders.e1_tol = ix->stage1_matrix == 1 && !a.pre ? kE1Tol : 0.f;
       orders.stage1 = [&, matrix](bool rebuild) -> std::pair<const float *, const int64_t *> {
         const bool first = !s1_made;
         s1_made = true;

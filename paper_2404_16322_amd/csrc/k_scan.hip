@@ -1715,14 +1715,19 @@ void launch_full_lists(const Stage1Args &a, const float *xnorm, float *qnorm, in
 // holds dim 8 k4 + s of its row (A: query, B: vector), which leaves every sum unchanged in
 // content (A[i][k] at lane i + 16 k, B[k][j] at lane j + 16 k; result lane l, register r holds
 // C[4 (l / 16) + r][l % 16]).
-template <int ST>
+// PRE: the FP8 pre-stage's sums over the leading 64 dims instead, from the tile's codes decoded
+// as the scan decodes them (code value times the tile's scale, rounded to FP32), 16 K steps.
+template <int ST, bool PRE>
 __global__ __launch_bounds__(256) void stage1_matrix_kernel(Stage1Args a) {
   using S = Store<ST>;
   constexpr int EPL = 16 / S::kBytes;
   constexpr int YLOADS = (kTile * kBlockDims / EPL) / 256;
   constexpr int SLICE = kBlockDims * S::kBytes;
   constexpr int RW = 16;                          // pairs per wave per round
-  __shared__ __align__(16) float Ys[kTile * kLmLd];
+  constexpr int KD = PRE ? kFp8Lead : kBlockDims; // dims of the first test
+  constexpr int KS = KD / 4;                      // K steps; a lane holds KS contiguous dims
+  constexpr int LD = PRE ? KD + 4 : kLmLd;        // padded LDS row (floats)
+  __shared__ __align__(16) float Ys[kTile * LD];
   __shared__ float s_yn[kTile];
   __shared__ int64_t s_dst[4][RW];
   __shared__ float s_qn[4][RW];
@@ -1736,30 +1741,44 @@ __global__ __launch_bounds__(256) void stage1_matrix_kernel(Stage1Args a) {
   const int r16 = lane & 15, k4 = lane >> 4;
   const int tl = (int)(t - a.tile_off[l]);
   const int cnt = min(kTile, a.list_len[l] - tl * kTile);
-  const unsigned char *tp = reinterpret_cast<const unsigned char *>(a.base) +
-                            t * a.nblocks * ((int64_t)kTile * SLICE);   // dim block 0 of the tile
+  if constexpr (PRE) {
+    // thread tid decodes codes 16 (tid % 4) .. + 15 of vector tid / 4
+    const float sc = a.scale8[t];
+    const uint4 v = *reinterpret_cast<const uint4 *>(a.base8 + t * (kTile * kFp8Lead) + tid * 16);
+    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+    const int r = tid >> 2, c = 16 * (tid & 3);
 #pragma unroll
-  for (int it = 0; it < YLOADS; ++it) {
-    const int e = (tid + it * 256) * EPL;
-    const int r = e / kBlockDims, c = e % kBlockDims;
-    const uint4 v = *reinterpret_cast<const uint4 *>(tp + (int64_t)e * S::kBytes);
-    float f[EPL];
-    S::unpack(v, f);
+    for (int i = 0; i < 4; ++i) {
+      float f[4];
+      e4m3x4_to_f32(w[i], f);
+      *reinterpret_cast<float4 *>(&Ys[r * LD + c + 4 * i]) = make_float4(f[0] * sc, f[1] * sc, f[2] * sc, f[3] * sc);
+    }
+  } else {
+    const unsigned char *tp = reinterpret_cast<const unsigned char *>(a.base) +
+                              t * a.nblocks * ((int64_t)kTile * SLICE);   // dim block 0 of the tile
 #pragma unroll
-    for (int u = 0; u < EPL; u += 4)
-      *reinterpret_cast<float4 *>(&Ys[r * kLmLd + c + u]) = make_float4(f[u], f[u + 1], f[u + 2], f[u + 3]);
+    for (int it = 0; it < YLOADS; ++it) {
+      const int e = (tid + it * 256) * EPL;
+      const int r = e / kBlockDims, c = e % kBlockDims;
+      const uint4 v = *reinterpret_cast<const uint4 *>(tp + (int64_t)e * S::kBytes);
+      float f[EPL];
+      S::unpack(v, f);
+#pragma unroll
+      for (int u = 0; u < EPL; u += 4)
+        *reinterpret_cast<float4 *>(&Ys[r * LD + c + u]) = make_float4(f[u], f[u + 1], f[u + 2], f[u + 3]);
+    }
   }
   __syncthreads();
   if (tid < kTile) {
     float sq = 0.f;
-    for (int k = 0; k < kBlockDims; ++k) sq = fmaf(Ys[tid * kLmLd + k], Ys[tid * kLmLd + k], sq);
+    for (int k = 0; k < KD; ++k) sq = fmaf(Ys[tid * LD + k], Ys[tid * LD + k], sq);
     s_yn[tid] = sq;
   }
-  float bf[8][4];   // B operand: vector 16 j + r16, dims 8 k4 .. 8 k4 + 7
+  float bf[KS][4];   // B operand: vector 16 j + r16, dims KS k4 .. KS k4 + KS - 1
 #pragma unroll
   for (int j = 0; j < 4; ++j)
 #pragma unroll
-    for (int s8 = 0; s8 < 8; ++s8) bf[s8][j] = Ys[(16 * j + r16) * kLmLd + 8 * k4 + s8];
+    for (int s8 = 0; s8 < KS; ++s8) bf[s8][j] = Ys[(16 * j + r16) * LD + KS * k4 + s8];
   __syncthreads();
   float yn[4];
 #pragma unroll
@@ -1768,25 +1787,25 @@ __global__ __launch_bounds__(256) void stage1_matrix_kernel(Stage1Args a) {
   float *wqn = s_qn[wave];
   for (int r0 = pb + RW * wave; r0 < pe; r0 += 4 * RW) {
     const int n = min(RW, pe - r0);
-    float af[RW / 16][8];
+    float af[RW / 16][KS];
 #pragma unroll
     for (int i = 0; i < RW / 16; ++i) {
       const int row = 16 * i + r16;
-      float4 x0 = make_float4(0.f, 0.f, 0.f, 0.f), x1 = x0;
       int pidx = 0;
       int64_t q = 0;
       if (row < n) {
         pidx = a.lpair[r0 + row];
         q = pidx / a.p_stride;
-        const float4 *qp = reinterpret_cast<const float4 *>(a.qrot + q * a.q_stride + 8 * k4);
-        x0 = qp[0];
-        x1 = qp[1];
       }
-      af[i][0] = x0.x; af[i][1] = x0.y; af[i][2] = x0.z; af[i][3] = x0.w;
-      af[i][4] = x1.x; af[i][5] = x1.y; af[i][6] = x1.z; af[i][7] = x1.w;
+      const float4 *qp = reinterpret_cast<const float4 *>(a.qrot + q * a.q_stride + KS * k4);
+#pragma unroll
+      for (int v4 = 0; v4 < KS / 4; ++v4) {
+        const float4 x = row < n ? qp[v4] : make_float4(0.f, 0.f, 0.f, 0.f);
+        af[i][4 * v4] = x.x; af[i][4 * v4 + 1] = x.y; af[i][4 * v4 + 2] = x.z; af[i][4 * v4 + 3] = x.w;
+      }
       float sq = 0.f;
 #pragma unroll
-      for (int s8 = 0; s8 < 8; ++s8) sq = fmaf(af[i][s8], af[i][s8], sq);
+      for (int s8 = 0; s8 < KS; ++s8) sq = fmaf(af[i][s8], af[i][s8], sq);
       sq += __shfl_xor(sq, 16);
       sq += __shfl_xor(sq, 32);
       if (k4 == 0 && row < n) {
@@ -1801,7 +1820,7 @@ __global__ __launch_bounds__(256) void stage1_matrix_kernel(Stage1Args a) {
 #pragma unroll
       for (int j = 0; j < 4; ++j) acc[i][j] = lm_floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int s8 = 0; s8 < 8; ++s8)
+    for (int s8 = 0; s8 < KS; ++s8)
 #pragma unroll
       for (int i = 0; i < RW / 16; ++i)
 #pragma unroll
@@ -1831,14 +1850,17 @@ void launch_stage1_lists(const Stage1Args &a, int store, hipStream_t s, bool mat
   launch_pair_groups(a, s);
   const dim3 grid((unsigned)a.total_tiles), blk(kS1Threads);
   if (a.pre) {   // the FP8 codes do not depend on the storage type
-    hipLaunchKernelGGL((stage1_lists_kernel<ST_F32, true>), grid, blk, 0, s, a);
+    if (matrix)
+      hipLaunchKernelGGL((stage1_matrix_kernel<ST_F32, true>), grid, blk, 0, s, a);
+    else
+      hipLaunchKernelGGL((stage1_lists_kernel<ST_F32, true>), grid, blk, 0, s, a);
     return;
   }
   if (matrix) {
     switch (store) {
-      case ST_F32: hipLaunchKernelGGL(stage1_matrix_kernel<ST_F32>, grid, blk, 0, s, a); break;
-      case ST_F16: hipLaunchKernelGGL(stage1_matrix_kernel<ST_F16>, grid, blk, 0, s, a); break;
-      default: hipLaunchKernelGGL(stage1_matrix_kernel<ST_BF16>, grid, blk, 0, s, a); break;
+      case ST_F32: hipLaunchKernelGGL((stage1_matrix_kernel<ST_F32, false>), grid, blk, 0, s, a); break;
+      case ST_F16: hipLaunchKernelGGL((stage1_matrix_kernel<ST_F16, false>), grid, blk, 0, s, a); break;
+      default: hipLaunchKernelGGL((stage1_matrix_kernel<ST_BF16, false>), grid, blk, 0, s, a); break;
     }
     return;
   }

@@ -143,6 +143,44 @@ def test_stage1_expanded_sums_match_oracle(storage, mode, alpha, k, nprobe):
     assert not r["bad"], r["bad"][:5]
 
 
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+@pytest.mark.parametrize("k,nprobe,alpha", [(10, 8, 0.1), (100, 20, 0.3)])
+def test_stage1_expanded_fp8_prestage_sums_match_oracle(storage, k, nprobe, alpha):
+    """stage1_matrix = 2 on an index with the FP8 pre-stage: the pre-stage's sums over the
+    leading 64 dims from the matrix cores (codes decoded with the tile scale as the scan decodes
+    them), taken as they are.  The survivors restart at dim 0, so every returned distance is the
+    one the default scan returns for that id; ids equal except near pre-stage decisions; the
+    oracle's bar holds; the mode-1 setting keeps the pre-stage in the scan's arithmetic (bit
+    for bit the default)."""
+    ix = oracle_index(storage=storage, n_calib=300, fp8_lead=64)
+    w = workload("gauss128")
+    g = _index(ix)
+    Q = np.concatenate([w["queries"], w["val"][:200]])
+    run = lambda: g.search(Q, k, nprobe, alpha)
+    g.set_launch(waves_per_query=1, lookahead=1, persistent=0, two_phase=0, stage1_matrix=0)
+    ref = run()
+    g.set_launch(two_phase=1, stage1_matrix=1)
+    _same(ref, run())
+    out = None
+    for wv, la, p in SHAPES:
+        g.set_launch(waves_per_query=wv, lookahead=la, persistent=p, two_phase=1, stage1_matrix=2)
+        r = run()
+        if out is None:
+            out = r
+        else:
+            _same(out, r)
+    g.set_launch(waves_per_query=0, lookahead=-1, persistent=-1, two_phase=-1, stage1_matrix=0)
+    ids, d, st = out
+    assert st["two_phase_sums"] == st["prestage_reads"] > 0
+    same = (ids == ref[0]).all(1)
+    assert same.mean() >= 0.95
+    np.testing.assert_array_equal(d[same], ref[1][same])
+    ora = O.search(ix, Q, k, nprobe, alpha)
+    r = check_search(ids, d, ora, ix)
+    print(f"expanded FP8 pre-stage {storage} k={k}: {r['same']}/{r['nq']} identical, {r['excused']} excused")
+    assert not r["bad"], r["bad"][:5]
+
+
 @pytest.mark.parametrize("L", [1, 3])
 def test_stage1_matrix_lagged_and_lag_parallel(L):
     """A lagged index (blocks of 64, lag 1 and 3): the bounded matrix first phase with one wave
