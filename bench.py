@@ -385,8 +385,9 @@ def run_workload(wl, args, headline):
     form = cfg.get("first_phase", "direct") if args.first_phase == "config" else args.first_phase
     ix.set_launch(stage1_matrix=FORMS[form])
     if args.launch:
-        wv, la, pe, t2 = (int(x) for x in args.launch.split(","))
-        ix.set_launch(waves_per_query=wv, lookahead=la, persistent=pe, two_phase=t2)
+        lv = [int(x) for x in args.launch.split(",")]
+        ix.set_launch(waves_per_query=lv[0], lookahead=lv[1], persistent=lv[2], two_phase=lv[3],
+                      waves_per_simd=lv[4] if len(lv) > 4 else 0)
 
     t0 = time.time()
     base_t = torch.from_numpy(w["base"]).to(dev, torch.float64)
@@ -611,7 +612,8 @@ def run_workload(wl, args, headline):
         log(f"[bench] end to end: {e2e}")
 
     # every launch shape of the scan at the operating point (results are bit-identical)
-    chosen = ix.scan_variant(bsz, k, int(nps.max())) if uneven else ix.scan_variant(nq, k, nprobe)
+    chosen = (ix.scan_variant(bsz, k, int(nps.max()), with_budget=True) if uneven
+              else ix.scan_variant(nq, k, nprobe, with_budget=True))
     variants = {}
     if headline and not args.profile:
         shapes = [(w_, l_, p_, t_) for t_ in (0, 1) for p_ in (0, 1) for w_ in (1, 4) for l_ in (0, 1)]
@@ -648,7 +650,8 @@ def run_workload(wl, args, headline):
             stream.synchronize()
             ix.set_kernel_timing(False)
             akms, akn = ix.kernel_timing(reset=True)
-            alt_chosen = ix.scan_variant(bsz, k, int(nps.max())) if uneven else ix.scan_variant(nq, k, nprobe)
+            alt_chosen = (ix.scan_variant(bsz, k, int(nps.max()), with_budget=True) if uneven
+                          else ix.scan_variant(nq, k, nprobe, with_budget=True))
             other_form.append(dict(form=alt, qps=round(nq / ms_alt * 1e3, 1), ms_per_step=round(ms_alt, 4),
                                    recall_at_10=round(r_alt, 4), scan_variant_tuned=list(alt_chosen),
                                    first_phase_ms=round(akms[4] / max(1, akn[3]), 4),
@@ -771,7 +774,7 @@ def run_workload(wl, args, headline):
                     frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
                     kernel=f"scan_kernel<{cfg['storage']}, pruned, lookahead={chosen[1]}, "
                            f"waves={chosen[0]}>{' persistent' if chosen[2] else ''}"
-                           f"{' two-phase' if chosen[3] else ''}",
+                           f"{' two-phase' if chosen[3] else ''}, built for {chosen[4]} waves per SIMD",
                     bytes_per_launch=int(scan_bytes), kernel_ms=round(scan_ms, 4))
     two_phase = None
     if chosen[3]:
@@ -826,7 +829,8 @@ def run_workload(wl, args, headline):
         "without_fp8_prestage": no_pre,
         "scan_variant_ms": variants or None,
         "scan_variant_tuned": {"waves_per_query": chosen[0], "lookahead": chosen[1],
-                               "persistent": chosen[2], "two_phase": chosen[3]},
+                               "persistent": chosen[2], "two_phase": chosen[3],
+                               "waves_per_simd": chosen[4]},
         "kernel_ms_per_step": {"rotation": round(kstep[0], 4), "coarse": round(kstep[1], 4),
                                "select": round(kstep[2], 4), "scan": round(kstep[3], 4),
                                "first_phase": round(kstep[4], 4)},
@@ -909,8 +913,8 @@ def main():
                          "the matrix cores behind their error bound (matrix; bit-identical results) or "
                          "taken as they are (expanded)")
     ap.add_argument("--launch", default="",
-                    help="force the scan's launch shape: waves,lookahead,persistent,two_phase "
-                         "(e.g. 1,1,0,1), instead of tuning it")
+                    help="force the scan's launch shape: waves,lookahead,persistent,two_phase"
+                         "[,waves_per_simd] (e.g. 1,1,0,1,5), instead of tuning it")
     ap.add_argument("--cpu-oracle-child", default="", help=argparse.SUPPRESS)
     args = ap.parse_args()
     if args.cpu_oracle_child:

@@ -407,20 +407,24 @@ ddc_status ddc_set_bsar_multiplier(ddc_index *ix, double m);
  * partial distance (ids can differ at near-threshold decisions and near ties), and no candidate
  * re-reads dim block 0; with the FP8 pre-stage, mode 2 also forms the pre-stage's sums over the
  * leading 64 dims this way (from the decoded codes; the pre-stage's decisions then hold up to
- * FP32 rounding, and its survivors' distances are exact as ever).  0 keeps the first phase in the scan's own arithmetic.  Defaults: 0,
- * -1, 1, 1, -1, -1, 0, 0. */
+ * FP32 rounding, and its survivors' distances are exact as ever).  0 keeps the first phase in
+ * the scan's own arithmetic.  waves_per_simd (result-invariant; 0 = tuned, 4 or 5): the
+ * register budget of the one-wave kernel of the lag-free learned and fixed-table tests without
+ * the FP8 pre-stage (a second build for five waves per SIMD spills a few registers to trade
+ * them for occupancy); other kernels ignore it.  Defaults: 0, -1, 1, 1, -1, -1, 0, 0, 0. */
 typedef struct {
   int32_t waves_per_query, lookahead, query_order, xcd_swizzle, persistent, two_phase;
-  int32_t full_d_matrix, stage1_matrix;
+  int32_t full_d_matrix, stage1_matrix, waves_per_simd;
 } ddc_launch_params;
 ddc_status ddc_set_launch(ddc_index *ix, const ddc_launch_params *p);
 ddc_status ddc_get_launch(const ddc_index *ix, ddc_launch_params *p);
 /* The scan variant a search of nq queries with this K, N_probe and mode runs: waves (1 or 4),
- * lookahead (0 or 1), persistent (0 or 1; nullable) and two_phase (0 or 1; nullable).  A size
- * class not tuned yet reports the fixed rule's choice. */
+ * lookahead (0 or 1), persistent (0 or 1; nullable), two_phase (0 or 1; nullable) and
+ * waves_per_simd (4 or 5, the register budget of the kernel; nullable).  A size class not tuned
+ * yet reports the fixed rule's choice. */
 ddc_status ddc_scan_variant(ddc_index *ix, int64_t nq, int32_t k_max, int32_t nprobe_max,
                             ddc_corr mode, int32_t *waves, int32_t *lookahead, int32_t *persistent,
-                            int32_t *two_phase);
+                            int32_t *two_phase, int32_t *waves_per_simd);
 
 /* ---- continuous-batching server --------------------------------------------------------
  * A scheduler thread admits queued requests into micro-batches on n_streams HIP streams while

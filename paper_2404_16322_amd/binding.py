@@ -92,7 +92,8 @@ class ServerStats(C.Structure):
 class LaunchParams(C.Structure):
     _fields_ = [("waves_per_query", C.c_int32), ("lookahead", C.c_int32),
                 ("query_order", C.c_int32), ("xcd_swizzle", C.c_int32), ("persistent", C.c_int32),
-                ("two_phase", C.c_int32), ("full_d_matrix", C.c_int32), ("stage1_matrix", C.c_int32)]
+                ("two_phase", C.c_int32), ("full_d_matrix", C.c_int32), ("stage1_matrix", C.c_int32),
+                ("waves_per_simd", C.c_int32)]
 
 
 class DdcError(RuntimeError):
@@ -147,7 +148,7 @@ def load_library():
         lib.ddc_get_launch.argtypes = [vp, C.POINTER(LaunchParams)]
         lib.ddc_scan_variant.argtypes = [vp, i64, i32, i32, C.c_int, C.POINTER(C.c_int32),
                                          C.POINTER(C.c_int32), C.POINTER(C.c_int32),
-                                         C.POINTER(C.c_int32)]
+                                         C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
         lib.ddc_server_create.argtypes = [vp, C.POINTER(ServerParams), C.POINTER(vp)]
         lib.ddc_server_submit.argtypes = [vp, vp, i32, vp, vp, C.POINTER(C.c_uint64)]
         lib.ddc_server_poll.argtypes = [vp, C.c_uint64, vp, vp, C.POINTER(C.c_int), C.POINTER(C.c_uint64)]
@@ -438,9 +439,10 @@ class Index:
     def set_launch(self, waves_per_query: int | None = None, lookahead: int | None = None,
                    query_order: int | None = None, xcd_swizzle: int | None = None,
                    persistent: int | None = None, two_phase: int | None = None,
-                   full_d_matrix: int | None = None, stage1_matrix: int | None = None):
+                   full_d_matrix: int | None = None, stage1_matrix: int | None = None,
+                   waves_per_simd: int | None = None):
         """Launch shape of the scan; None keeps the current value (waves_per_query 0,
-        lookahead -1, persistent -1 and two_phase -1 mean tuned per size class).  Every knob
+        lookahead -1, persistent -1, two_phase -1 and waves_per_simd 0 mean tuned per size class).  Every knob
         but full_d_matrix and stage1_matrix=2 is result-invariant; those two take distances
         formed on the matrix cores in the expanded form as they are (results equal up to FP32
         rounding)."""
@@ -449,7 +451,8 @@ class Index:
                             (("waves_per_query", waves_per_query), ("lookahead", lookahead),
                              ("query_order", query_order), ("xcd_swizzle", xcd_swizzle),
                              ("persistent", persistent), ("two_phase", two_phase),
-                             ("full_d_matrix", full_d_matrix), ("stage1_matrix", stage1_matrix))))
+                             ("full_d_matrix", full_d_matrix), ("stage1_matrix", stage1_matrix),
+                             ("waves_per_simd", waves_per_simd))))
         _check(load_library().ddc_set_launch(self._h, C.byref(lp)))
 
     def launch(self) -> dict:
@@ -457,13 +460,15 @@ class Index:
         _check(load_library().ddc_get_launch(self._h, C.byref(lp)))
         return {k: getattr(lp, k) for k, _ in LaunchParams._fields_}
 
-    def scan_variant(self, nq: int, k: int, nprobe: int, mode: str = "learned") -> tuple:
+    def scan_variant(self, nq: int, k: int, nprobe: int, mode: str = "learned",
+                     with_budget: bool = False) -> tuple:
         """(waves per query, lookahead, persistent, two-phase) a search of this shape runs
-        (tuned or fixed rule)."""
-        w, la, pe, tp = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+        (tuned or fixed rule); with_budget adds the kernel's waves per SIMD (4 or 5)."""
+        w, la, pe, tp, ws = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
         _check(load_library().ddc_scan_variant(self._h, nq, k, nprobe, CORR[mode], C.byref(w),
-                                               C.byref(la), C.byref(pe), C.byref(tp)))
-        return w.value, la.value, pe.value, tp.value
+                                               C.byref(la), C.byref(pe), C.byref(tp), C.byref(ws)))
+        v = (w.value, la.value, pe.value, tp.value)
+        return v + (ws.value,) if with_budget else v
 
     def set_kernel_timing(self, enable: bool):
         _check(load_library().ddc_set_kernel_timing(self._h, int(enable)))

@@ -54,15 +54,16 @@ static int scan_kind(const ScanArgs &a) {
 }
 
 // Launch shape of the scan: waves per query (1 or 4), look-ahead (0 or 1), persistent (0 or 1),
-// two-phase (0 or 1: stage-1 sums computed list by list first).
-using Variant = std::array<int, 4>;
+// two-phase (0 or 1: stage-1 sums computed list by list first), and the register budget of the
+// one-wave lag-free kernel of the plain stage tests (0: four waves per SIMD, 1: five).
+using Variant = std::array<int, 5>;
 
 // Without measurements: a workgroup per query while the batch leaves the chip's wave slots
 // mostly empty, multi-block loads once vectors span eight or more dim blocks, one pass, and the
 // two-phase scan once a list is probed by four or more queries on average.
 static Variant fixed_variant(const ddc_index *ix, int64_t nq, int prune, int np_max, bool two_ok) {
   const bool reuse = two_ok && (double)nq * np_max >= 4.0 * ix->nlist;
-  return {nq < 4096 ? 4 : 1, prune && ix->NB >= 8 ? 1 : 0, 0, reuse ? 1 : 0};
+  return {nq < 4096 ? 4 : 1, prune && ix->NB >= 8 ? 1 : 0, 0, reuse ? 1 : 0, 0};
 }
 
 static Variant forced_or(const ddc_index *ix, Variant v, int kind, bool two_ok) {
@@ -74,6 +75,8 @@ static Variant forced_or(const ddc_index *ix, Variant v, int kind, bool two_ok) 
   if (ix->two_phase >= 0) v[3] = ix->two_phase;
   if (!(kind & 1) || (kind & 4)) v[1] = 0;   // look-ahead only for the learned/fixed-table tests
   if (!two_ok) v[3] = 0;
+  if (ix->waves_per_simd) v[4] = ix->waves_per_simd == 5 ? 1 : 0;
+  if (!(kind == 1 && ix->L == 0 && v[0] == 1)) v[4] = 0;   // the five-wave build exists only there
   return v;
 }
 
@@ -97,6 +100,7 @@ struct LaunchOrders {
 static void apply_variant(ScanArgs &a, const Variant &v, LaunchOrders &o) {
   a.waves_per_query = v[0];
   a.lookahead = v[1];
+  a.occ5 = v[4];
   if (v[2]) {
     const auto pq = o.longest_first(false);
     a.order = pq.first;
@@ -149,11 +153,12 @@ static void choose_variant(ddc_index *ix, ScanArgs &a, int np_max, hipStream_t s
         for (int t2 : {0, 1})
           for (int p : {0, 1})
             for (int w : {1, 2, 4})
-              for (int l : {0, 1}) {
-                auto c = forced_or(ix, {w, l, p, t2}, kind, two_ok);
-                if (scan_lds_request(a, c[0]) > kMaxLds) continue;
-                if (std::find(cand.begin(), cand.end(), c) == cand.end()) cand.push_back(c);
-              }
+              for (int l : {0, 1})
+                for (int o : {0, 1}) {
+                  auto c = forced_or(ix, {w, l, p, t2, o}, kind, two_ok);
+                  if (scan_lds_request(a, c[0]) > kMaxLds) continue;
+                  if (std::find(cand.begin(), cand.end(), c) == cand.end()) cand.push_back(c);
+                }
         if (cand.empty()) cand.push_back(v);
         hipEvent_t e0, e1;
         HIPC(hipEventCreate(&e0));
@@ -1798,6 +1803,8 @@ ddc_status ddc_set_launch(ddc_index *ix, const ddc_launch_params *p) {
   if (p->two_phase < -1 || p->two_phase > 1) return set_err(DDC_EINVAL, "two_phase must be -1, 0 or 1");
   if (p->full_d_matrix != 0 && p->full_d_matrix != 1) return set_err(DDC_EINVAL, "full_d_matrix must be 0 or 1");
   if (p->stage1_matrix < 0 || p->stage1_matrix > 2) return set_err(DDC_EINVAL, "stage1_matrix must be 0, 1 or 2");
+  if (p->waves_per_simd != 0 && p->waves_per_simd != 4 && p->waves_per_simd != 5)
+    return set_err(DDC_EINVAL, "waves_per_simd must be 0, 4 or 5");
   std::lock_guard<std::mutex> lk(ix->tune_mtx);
   ix->tuned.clear();   // a choice tuned under other forced knobs may not be the best now
   ix->waves_per_query = p->waves_per_query;
@@ -1808,6 +1815,7 @@ ddc_status ddc_set_launch(ddc_index *ix, const ddc_launch_params *p) {
   ix->two_phase = p->two_phase;
   ix->full_d_matrix = p->full_d_matrix;
   ix->stage1_matrix = p->stage1_matrix;
+  ix->waves_per_simd = p->waves_per_simd;
   return DDC_OK;
 }
 
@@ -1821,12 +1829,13 @@ ddc_status ddc_get_launch(const ddc_index *ix, ddc_launch_params *p) {
   p->two_phase = ix->two_phase;
   p->full_d_matrix = ix->full_d_matrix;
   p->stage1_matrix = ix->stage1_matrix;
+  p->waves_per_simd = ix->waves_per_simd;
   return DDC_OK;
 }
 
 ddc_status ddc_scan_variant(ddc_index *ix, int64_t nq, int32_t k_max, int32_t nprobe_max,
                             ddc_corr mode, int32_t *waves, int32_t *lookahead, int32_t *persistent,
-                            int32_t *two_phase) {
+                            int32_t *two_phase, int32_t *waves_per_simd) {
   if (!ix || !waves || !lookahead) return set_err(DDC_EINVAL, "NULL argument");
   if (nq < 1 || k_max < 1 || nprobe_max < 1) return set_err(DDC_EINVAL, "sizes must be >= 1");
   // the kernel family a search in this mode launches (significance > 0 assumed for LEARNED)
@@ -1854,6 +1863,7 @@ ddc_status ddc_scan_variant(ddc_index *ix, int64_t nq, int32_t k_max, int32_t np
   *lookahead = v[1];
   if (persistent) *persistent = v[2];
   if (two_phase) *two_phase = v[3];
+  if (waves_per_simd) *waves_per_simd = v[4] ? 5 : 4;
   return DDC_OK;
 }
 

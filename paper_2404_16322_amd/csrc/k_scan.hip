@@ -205,9 +205,11 @@ __host__ __device__ inline size_t scan_lds_bytes(int Dp, int kmax, int block_b, 
 // which the lag provides); the group's survivor lists are then merged into the queue in block
 // order, recording every block's tau, so the results are those of the one-wave lagged scan bit
 // for bit.
+// OCC: the register budget, in waves per SIMD (4; 5 for the one-wave lag-free kernels' second
+// build, a launch shape the tuner may pick: same code and results, fewer registers)
 template <int ST, bool PRUNE, bool LOOK, int W, bool PRE, bool RES, bool EST = false, bool PQ = false,
-          bool LAG = false, bool LM = false, bool LP = false>
-__global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(4, 8))) void scan_kernel(ScanArgs a) {
+          bool LAG = false, bool LM = false, bool LP = false, int OCC = 4>
+__global__ __launch_bounds__(kScanThreads) __attribute__((amdgpu_waves_per_eu(OCC, 8))) void scan_kernel(ScanArgs a) {
   using S = Store<ST>;
   constexpr int EPL = 16 / S::kBytes;          // elements per lane load
   constexpr int G = kBlockDims / EPL;          // lanes per vector slice
@@ -1897,7 +1899,7 @@ size_t scan_lds_request(const ScanArgs &a, int W) {
 }
 
 template <int ST, bool P, bool LK, int W, bool PRE = false, bool RES = false, bool EST = false,
-          bool PQ = false, bool LG = false, bool LM = false, bool LP = false>
+          bool PQ = false, bool LG = false, bool LM = false, bool LP = false, int OCC = 4>
 static void launch_variant(const ScanArgs &a, hipStream_t s) {
   const size_t smem = scan_lds_bytes(a.nblocks * kBlockDims, a.k_max, a.block_b, W, RES,
                                      PQ ? a.pq_m * 256 + a.nblocks * kBlockDims : 0, a.p_stride,
@@ -1905,14 +1907,14 @@ static void launch_variant(const ScanArgs &a, hipStream_t s) {
   if (smem > kMaxLds) throw std::runtime_error("scan: LDS request exceeds 160 KiB");
   const int qpw = LP ? 1 : 4 / W;
   const int threads = LP ? 64 * W : kScanThreads;   // LP: the query's W waves alone
-  const void *kern = reinterpret_cast<const void *>(&scan_kernel<ST, P, LK, W, PRE, RES, EST, PQ, LG, LM, LP>);
+  const void *kern = reinterpret_cast<const void *>(&scan_kernel<ST, P, LK, W, PRE, RES, EST, PQ, LG, LM, LP, OCC>);
   int64_t grid = (a.nq + qpw - 1) / qpw;
   if (a.queue) {
     // W = 1: each wave takes its own slots, so the grid covers ceil(nq / 4) workgroups at most
     grid = std::min<int64_t>(grid, resident_workgroups(kern, smem, threads));
     hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(64), 0, s, a.queue, (int64_t)1, 0);
   }
-  hipLaunchKernelGGL((scan_kernel<ST, P, LK, W, PRE, RES, EST, PQ, LG, LM, LP>), dim3((unsigned)grid),
+  hipLaunchKernelGGL((scan_kernel<ST, P, LK, W, PRE, RES, EST, PQ, LG, LM, LP, OCC>), dim3((unsigned)grid),
                      dim3(threads), smem, s, a);
 }
 
@@ -1929,6 +1931,9 @@ static void launch_pruned_w(const ScanArgs &a, hipStream_t s) {
   }
   if constexpr (W == 2) {
     throw std::runtime_error("scan: two waves per query need a lagged threshold");
+  } else if constexpr (W == 1 && !PRE && !RES && !PQ && !LG) {
+    if (a.occ5) launch_variant<ST, true, LK, 1, false, false, false, false, false, false, false, 5>(a, s);
+    else launch_variant<ST, true, LK, 1, false, false, false, false, false>(a, s);
   } else {
     launch_variant<ST, true, LK, W, PRE, RES, false, PQ, LG>(a, s);
   }

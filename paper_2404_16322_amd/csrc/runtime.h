@@ -216,9 +216,10 @@ struct ddc_index {
   int two_phase = -1;
   int full_d_matrix = 0;            // NONE-mode scans: distances list by list on the matrix cores
   int stage1_matrix = 0;            // two-phase first phase (stored values) on the matrix cores
+  int waves_per_simd = 0;           // register budget of the one-wave pruned kernel (0 = tuned)
   std::mutex tune_mtx;
   // class -> (waves per query, look-ahead, persistent, two-phase)
-  std::map<std::array<int, 4>, std::array<int, 4>> tuned;
+  std::map<std::array<int, 4>, std::array<int, 5>> tuned;   // size class -> launch shape
   int store() const {
     return storage == DDC_F32 ? ddc::ST_F32 : storage == DDC_F16 ? ddc::ST_F16 : ddc::ST_BF16;
   }

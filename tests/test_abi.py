@@ -90,10 +90,10 @@ def test_search_rejects_bad_arguments_without_device(lib):
     assert lib.ddc_search_device_noalloc_bytes() == 64 << 20
     rc = lib.ddc_search_estimate(None, q.ctypes.data, 1, 10, 1, 32, 0, ids.ctypes.data, d.ctypes.data)
     assert rc == -1 and b"NULL" in lib.ddc_last_error()
-    lp = B.LaunchParams(0, -1, 1, 1, -1, -1, 0, 0)
+    lp = B.LaunchParams(0, -1, 1, 1, -1, -1, 0, 0, 0)
     assert lib.ddc_set_launch(None, C.byref(lp)) == -1
     w = C.c_int32()
-    assert lib.ddc_scan_variant(None, 1, 1, 1, 0, C.byref(w), C.byref(w), None, None) == -1
+    assert lib.ddc_scan_variant(None, 1, 1, 1, 0, C.byref(w), C.byref(w), None, None, None) == -1
 
 
 def test_fit_rejects_bad_parameters_without_device(lib):

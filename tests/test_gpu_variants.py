@@ -96,12 +96,45 @@ def test_variants_per_query_k_nprobe_and_counters():
             assert r[3][key] == res[0][3][key], key
 
 
+@pytest.mark.parametrize("storage", ["f32", "bf16", "f16"])
+def test_five_wave_build_bitwise_identical(storage):
+    """The one-wave kernel's second build for five waves per SIMD (waves_per_simd = 5; it
+    spills a few registers) returns the four-wave build's ids, distances and counters in every
+    one-wave shape, one- and two-phase; kernels without that build ignore the knob."""
+    ix = oracle_index(storage=storage, n_calib=300)
+    w = workload("gauss128")
+    g = _index(ix)
+    Q = np.concatenate([w["queries"], w["val"][:200]])
+    for mode, alpha, k in (("learned", 0.1, 10), ("learned", 0.3, 100), ("lossless", 0.0, 10)):
+        ref = None
+        for la in (0, 1):
+            for p in (0, 1):
+                for t in (0, 1):
+                    for ws in (4, 5):
+                        g.set_launch(waves_per_query=1, lookahead=la, persistent=p, two_phase=t,
+                                     waves_per_simd=ws)
+                        r = g.search(Q, k, 8, alpha, mode=mode)
+                        if ref is None:
+                            ref = r
+                            continue
+                        for a, b in zip(ref, r):
+                            if isinstance(a, np.ndarray):
+                                np.testing.assert_array_equal(a, b)
+                            else:
+                                for key in ("candidates", "refined", "stage_slices"):
+                                    assert a[key] == b[key], key
+    g.set_launch(waves_per_query=0, lookahead=-1, persistent=-1, two_phase=-1, waves_per_simd=0)
+    with pytest.raises(Exception):
+        g.set_launch(waves_per_simd=6)
+
+
 def test_tuner_picks_a_variant_and_caches_it():
     ix = oracle_index()
     w = workload("gauss128")
     g = _index(ix)
     assert g.launch() == dict(waves_per_query=0, lookahead=-1, query_order=1, xcd_swizzle=1,
-                              persistent=-1, two_phase=-1, full_d_matrix=0, stage1_matrix=0)
+                              persistent=-1, two_phase=-1, full_d_matrix=0, stage1_matrix=0,
+                              waves_per_simd=0)
     ids0, d0, _ = g.search(w["queries"], 10, 8, 0.1)
     v = g.scan_variant(w["queries"].shape[0], 10, 8)
     assert v in VARIANTS
