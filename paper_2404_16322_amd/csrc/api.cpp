@@ -1042,6 +1042,9 @@ void ddc::search_device(ddc_index *ix, const float *d_q, int64_t nq, const int32
       orders.e1_cap = e1_cap;
     }
     choose_variant(ix, a, np_max, s, may_tune, orders);
+    // callers with a fixed workspace (the allocation-free entry point, the server) keep the
+    // four-wave build: the five-wave one spills to a private segment the runtime provides
+    if (fixed_ws) a.occ5 = 0;
     timed(ix, 3, s, [&] { launch_scan(a, ix->store(), s); }, fixed_ws);
   }
   HIPC(hipGetLastError());
