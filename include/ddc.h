@@ -409,11 +409,11 @@ ddc_status ddc_set_bsar_multiplier(ddc_index *ix, double m);
  * leading 64 dims this way (from the decoded codes; the pre-stage's decisions then hold up to
  * FP32 rounding, and its survivors' distances are exact as ever).  0 keeps the first phase in
  * the scan's own arithmetic.  waves_per_simd (result-invariant; 0 = tuned, 4 or 5): the
- * register budget of the one-wave kernel of the lag-free learned and fixed-table tests without
- * the FP8 pre-stage (a second build for five waves per SIMD spills a few registers to a
- * private segment the HIP runtime provides, to trade them for occupancy; searches with a fixed
- * workspace, ddc_search_device_noalloc and the server, always use the four-wave build); other
- * kernels ignore it.  Defaults: 0, -1, 1, 1, -1, -1, 0, 0, 0. */
+ * register budget of the one-wave kernel of the lag-free learned and fixed-table tests (a
+ * second build for five waves per SIMD spills a few registers to a private segment the HIP
+ * runtime provides, to trade them for occupancy; searches with a fixed workspace,
+ * ddc_search_device_noalloc and the server, always use the four-wave build); other kernels
+ * ignore it.  Defaults: 0, -1, 1, 1, -1, -1, 0, 0, 0. */
 typedef struct {
   int32_t waves_per_query, lookahead, query_order, xcd_swizzle, persistent, two_phase;
   int32_t full_d_matrix, stage1_matrix, waves_per_simd;

@@ -76,7 +76,8 @@ static Variant forced_or(const ddc_index *ix, Variant v, int kind, bool two_ok) 
   if (!(kind & 1) || (kind & 4)) v[1] = 0;   // look-ahead only for the learned/fixed-table tests
   if (!two_ok) v[3] = 0;
   if (ix->waves_per_simd) v[4] = ix->waves_per_simd == 5 ? 1 : 0;
-  if (!(kind == 1 && ix->L == 0 && v[0] == 1)) v[4] = 0;   // the five-wave build exists only there
+  // the five-wave build exists only there: the plain stage tests, with or without the pre-stage
+  if (!((kind == 1 || kind == 3) && ix->L == 0 && v[0] == 1)) v[4] = 0;
   return v;
 }
 

@@ -80,7 +80,7 @@ struct ScanArgs {
   int32_t waves_per_query; // 1 or 4 (result-invariant)
   int32_t lookahead;       // 0 or 1: multi-stage loads when few candidates survive (result-invariant)
   int32_t occ5;            // 1: the one-wave lag-free pruned kernel built for five waves per SIMD
-                           // (no FP8 pre-stage, residual or quantization test; result-invariant)
+                           // (no residual or quantization test; result-invariant)
   int32_t nq, nblocks, block_b, prune, nlist, k_max;
   int32_t lag;           // tau lag L in blocks: block b is tested against the tau after block b - 1 - L
   // Correction tables [ntab][nblocks + 1][2] = (m, beta) of the test after dim block b

@@ -1931,9 +1931,9 @@ static void launch_pruned_w(const ScanArgs &a, hipStream_t s) {
   }
   if constexpr (W == 2) {
     throw std::runtime_error("scan: two waves per query need a lagged threshold");
-  } else if constexpr (W == 1 && !PRE && !RES && !PQ && !LG) {
-    if (a.occ5) launch_variant<ST, true, LK, 1, false, false, false, false, false, false, false, 5>(a, s);
-    else launch_variant<ST, true, LK, 1, false, false, false, false, false>(a, s);
+  } else if constexpr (W == 1 && !RES && !PQ && !LG) {
+    if (a.occ5) launch_variant<ST, true, LK, 1, PRE, false, false, false, false, false, false, 5>(a, s);
+    else launch_variant<ST, true, LK, 1, PRE, false, false, false, false>(a, s);
   } else {
     launch_variant<ST, true, LK, W, PRE, RES, false, PQ, LG>(a, s);
   }

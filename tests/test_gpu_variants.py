@@ -96,12 +96,13 @@ def test_variants_per_query_k_nprobe_and_counters():
             assert r[3][key] == res[0][3][key], key
 
 
-@pytest.mark.parametrize("storage", ["f32", "bf16", "f16"])
-def test_five_wave_build_bitwise_identical(storage):
+@pytest.mark.parametrize("storage,fp8", [("f32", 0), ("bf16", 0), ("f16", 0), ("f16", 64), ("f32", 64)])
+def test_five_wave_build_bitwise_identical(storage, fp8):
     """The one-wave kernel's second build for five waves per SIMD (waves_per_simd = 5; it
     spills a few registers) returns the four-wave build's ids, distances and counters in every
-    one-wave shape, one- and two-phase; kernels without that build ignore the knob."""
-    ix = oracle_index(storage=storage, n_calib=300)
+    one-wave shape, one- and two-phase, with and without the FP8 pre-stage; kernels without
+    that build ignore the knob."""
+    ix = oracle_index(storage=storage, n_calib=300, fp8_lead=fp8)
     w = workload("gauss128")
     g = _index(ix)
     Q = np.concatenate([w["queries"], w["val"][:200]])
